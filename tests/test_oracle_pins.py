@@ -1,0 +1,465 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these checks re-types the oracle's own formulas: the nonlinear term is
+rebuilt here from the discrete Hessian matrix H (H_ii = second difference,
+H_ij = four-point cross difference), via N_h = (tr H)^2 - tr(H^2) and
+Sigma_0 = |H - tr(H)/3 I|_F^2, and the root is taken in the cancellation-free
+form 2q/(1+sqrt(1+8 alpha q/3)) rather than the paper's split form that the
+oracle implements.  Linear solves use the FFT with exact discrete eigenvalues.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1303_0008_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# independent helpers (test side)
+# ---------------------------------------------------------------------------
+def sh(u, dx, dy, dz):
+    """u(i+dx, j+dy, k+dz) on a periodic (n2, n1, n0) array."""
+    return np.roll(u, (-dz, -dy, -dx), axis=(0, 1, 2))
+
+
+def hessian_periodic(u, h):
+    """Discrete Hessian components (xx, yy, zz, xy, xz, yz)."""
+    hxx = (sh(u, 1, 0, 0) + sh(u, -1, 0, 0) - 2 * u) / h**2
+    hyy = (sh(u, 0, 1, 0) + sh(u, 0, -1, 0) - 2 * u) / h**2
+    hzz = (sh(u, 0, 0, 1) + sh(u, 0, 0, -1) - 2 * u) / h**2
+    hxy = (sh(u, 1, 1, 0) + sh(u, -1, -1, 0) - sh(u, 1, -1, 0) - sh(u, -1, 1, 0)) / (4 * h**2)
+    hxz = (sh(u, 1, 0, 1) + sh(u, -1, 0, -1) - sh(u, 1, 0, -1) - sh(u, -1, 0, 1)) / (4 * h**2)
+    hyz = (sh(u, 0, 1, 1) + sh(u, 0, -1, -1) - sh(u, 0, 1, -1) - sh(u, 0, -1, 1)) / (4 * h**2)
+    return hxx, hyy, hzz, hxy, hxz, hyz
+
+
+def hessian_padded(P, h):
+    """Same on the interior of a padded (n2+2, n1+2, n0+2) array (ghost shell)."""
+    n2, n1, n0 = (s - 2 for s in P.shape)
+
+    def s(dx, dy, dz):
+        return P[1 + dz:1 + dz + n2, 1 + dy:1 + dy + n1, 1 + dx:1 + dx + n0]
+
+    u = s(0, 0, 0)
+    hxx = (s(1, 0, 0) + s(-1, 0, 0) - 2 * u) / h**2
+    hyy = (s(0, 1, 0) + s(0, -1, 0) - 2 * u) / h**2
+    hzz = (s(0, 0, 1) + s(0, 0, -1) - 2 * u) / h**2
+    hxy = (s(1, 1, 0) + s(-1, -1, 0) - s(1, -1, 0) - s(-1, 1, 0)) / (4 * h**2)
+    hxz = (s(1, 0, 1) + s(-1, 0, -1) - s(1, 0, -1) - s(-1, 0, 1)) / (4 * h**2)
+    hyz = (s(0, 1, 1) + s(0, -1, -1) - s(0, 1, -1) - s(0, -1, 1)) / (4 * h**2)
+    return hxx, hyy, hzz, hxy, hxz, hyz
+
+
+def n_term(H):
+    """(tr H)^2 - tr(H^2) for symmetric H."""
+    hxx, hyy, hzz, hxy, hxz, hyz = H
+    tr = hxx + hyy + hzz
+    tr_h2 = hxx**2 + hyy**2 + hzz**2 + 2 * (hxy**2 + hxz**2 + hyz**2)
+    return tr**2 - tr_h2
+
+
+def sigma0(H):
+    """Frobenius norm^2 of the traceless part of H."""
+    hxx, hyy, hzz, hxy, hxz, hyz = H
+    t = (hxx + hyy + hzz) / 3
+    return (hxx - t)**2 + (hyy - t)**2 + (hzz - t)**2 + 2 * (hxy**2 + hxz**2 + hyz**2)
+
+
+def q_root(s0, delta, alpha, kappa):
+    q = alpha * s0 + kappa * delta
+    return 2 * q / (1 + np.sqrt(1 + 8 * alpha * q / 3))
+
+
+def fft_poisson(rhs, h):
+    """Solve Lap_h u = rhs - mean(rhs) (7-point, periodic), mean(u) = 0."""
+    n2, n1, n0 = rhs.shape
+    mz = np.fft.fftfreq(n2) * n2
+    my = np.fft.fftfreq(n1) * n1
+    mx = np.fft.fftfreq(n0) * n0
+    lam = -(4 / h**2) * (np.sin(np.pi * mz / n2)[:, None, None] ** 2
+                         + np.sin(np.pi * my / n1)[None, :, None] ** 2
+                         + np.sin(np.pi * mx / n0)[None, None, :] ** 2)
+    rk = np.fft.fftn(rhs)
+    lam[0, 0, 0] = 1.0
+    uk = rk / lam
+    uk[0, 0, 0] = 0.0
+    return np.real(np.fft.ifftn(uk))
+
+
+def pack_ghosts(P):
+    """Compact ghost order from a padded array: faces x-,x+ (j,k), y-,y+ (i,k),
+    z-,z+ (i,j); edges along x (y-z-, y+z-, y-z+, y+z+), along y, along z."""
+    n2, n1, n0 = (s - 2 for s in P.shape)
+    out = []
+    for s in (0, n0 + 1):
+        out.append(P[1:-1, 1:-1, s].ravel())
+    for s in (0, n1 + 1):
+        out.append(P[1:-1, s, 1:-1].ravel())
+    for s in (0, n2 + 1):
+        out.append(P[s, 1:-1, 1:-1].ravel())
+    for e in range(4):
+        out.append(P[(n2 + 1) if e & 2 else 0, (n1 + 1) if e & 1 else 0, 1:-1].ravel())
+    for e in range(4):
+        out.append(P[(n2 + 1) if e & 2 else 0, 1:-1, (n0 + 1) if e & 1 else 0].ravel())
+    for e in range(4):
+        out.append(P[1:-1, (n1 + 1) if e & 2 else 0, (n0 + 1) if e & 1 else 0].ravel())
+    return np.concatenate(out)
+
+
+def gauge(u):
+    return u - u.mean()
+
+
+def relerr(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# Sec. IV.B golden: 1D sine
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("alpha", [0.05, -0.05, 0.2])
+def test_sine_1d_golden(oracle_mod, axis, alpha):
+    g = json.load(open(os.path.join(GOLDEN, "sine_1d.json")))
+    K = g["K_over_pi2"] * np.pi**2
+    kappa = 1.5
+    n = 32
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h
+    shape = [1, 1, 1]
+    shape[2 - axis] = n
+    prof = np.sin(2 * np.pi * x).reshape(shape)
+    delta = np.broadcast_to(-K / kappa * prof, (n, n, n)).copy()
+    phi, info = oracle_mod.solve(delta, alpha, kappa)
+    # exact discrete solution: the nonlinear term vanishes for 1D fields
+    amp_discrete = K * h**2 / (4 * np.sin(np.pi * h) ** 2)
+    exact = np.broadcast_to(amp_discrete * prof, (n, n, n))
+    assert relerr(phi, exact) < 1e-12
+    assert abs(info["cbar"]) < 1e-12
+    # paper's continuum amplitude, to the O(h^2) discretisation error
+    assert abs(amp_discrete - g["amplitude"]) / g["amplitude"] < 0.34 * (np.pi * h) ** 2
+    assert abs(np.abs(phi).max() - g["amplitude"]) / g["amplitude"] < 0.34 * (np.pi * h) ** 2 + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Sec. IV.B golden: 1D Gaussian with the corrected density
+# ---------------------------------------------------------------------------
+def test_gaussian_1d_golden(oracle_mod):
+    g = json.load(open(os.path.join(GOLDEN, "gaussian_1d.json")))
+    n = 64
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h
+    prof = g["J"] * (1 - g["a"] * np.exp(-((x - 0.5) ** 2) / g["w"] ** 2))
+    phi_ex = np.broadcast_to(prof[None, :, None], (n, n, n)).copy()     # varies along y
+    lap = (sh(phi_ex, 0, 1, 0) + sh(phi_ex, 0, -1, 0) - 2 * phi_ex) / h**2
+    kappa = 1.5
+    phi, info = oracle_mod.solve(lap / kappa, 0.1, kappa)
+    assert relerr(phi, gauge(phi_ex)) < 1e-11
+    # the printed density has (1 - u^2/w^2); the Laplacian has (1 - 2u^2/w^2)
+    u = x - 0.5
+    w = g["w"]
+    cont = 2 * g["J"] * g["a"] / w**2 * (1 - 2 * u**2 / w**2) * np.exp(-u**2 / w**2)
+    assert np.abs(lap[0, :, 0] - cont).max() / np.abs(cont).max() < 5 * (np.pi * h / w) ** 2
+
+
+# ---------------------------------------------------------------------------
+# alpha = 0: linear (Poisson) limit against the FFT
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(16, 16, 16), (16, 8, 32)])
+def test_alpha0_vs_fft(oracle_mod, shape):
+    n0, n1, n2 = shape
+    h = 1.0 / n0
+    delta = I.lognormal((n0, n1, n2), 11, sigma=1.0)
+    kappa = 1.5
+    phi, info = oracle_mod.solve(delta, 0.0, kappa, h=h)
+    ref = fft_poisson(kappa * delta, h)
+    assert relerr(phi, ref) < 1e-12
+    assert info["rms"] < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# Sec. IV.A: uniform density, random initial guess -> constant field
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("alpha", [0.1, -0.1])
+def test_uniform_density(oracle_mod, alpha):
+    n = 16
+    delta = np.zeros((n, n, n))
+    phi0 = I.uniform_guess(n, 5)
+    phi, info = oracle_mod.solve(delta, alpha, 1.5, phi0=phi0, tol=1e-10)
+    assert info["rms"] < 1e-10
+    assert np.abs(phi).max() < 1e-11
+    # the physical branch gives Lap(phi) = 0 for a uniform field (Sec. III.A, after Eq. one_branch)
+    L, dL, sig, root = oracle_mod.cell_operator(delta, np.zeros_like(delta), alpha, 1.5, (3, 4, 5))
+    assert root == 0.0 and sig == 0.0
+
+
+# ---------------------------------------------------------------------------
+# first-order perturbation theory in alpha
+# ---------------------------------------------------------------------------
+def test_first_order_in_alpha(oracle_mod):
+    n = 16
+    h = 1.0 / n
+    kappa = 1.5
+    delta = I.lognormal(n, 21, sigma=0.5)
+    phi0 = fft_poisson(kappa * delta, h)
+    nh = n_term(hessian_periodic(phi0, h))
+    phi1 = fft_poisson(-nh, h)
+    errs = []
+    for a in (1e-3, 2e-3, 4e-3):
+        phi, _ = oracle_mod.solve(delta, a, kappa)
+        errs.append(np.abs(phi - phi0 - a * phi1).max())
+    r1, r2 = errs[1] / errs[0], errs[2] / errs[1]
+    assert abs(np.log2(r1) - 2) < 0.05 and abs(np.log2(r2) - 2) < 0.05, errs
+    # and the first-order term is really there (the Poisson solution alone is off at O(alpha))
+    phi, _ = oracle_mod.solve(delta, 4e-3, kappa)
+    assert np.abs(phi - phi0).max() > 20 * errs[2]
+
+
+# ---------------------------------------------------------------------------
+# dense bordered Newton on 8^3 periodic (unknowns phi and cbar)
+# ---------------------------------------------------------------------------
+def _newton(F, x0, iters=30):
+    x = x0.astype(np.float64).copy()
+    m = x.size
+    eps = 1e-30
+    prev = np.inf
+    for _ in range(iters):
+        f = F(x.astype(np.complex128)).real
+        cur = np.abs(f).max()
+        if cur == 0.0 or (cur < 1e-12 and cur >= 0.5 * prev):   # at the rounding floor
+            break
+        prev = cur
+        J = np.empty((m, m))
+        for c in range(m):
+            xc = x.astype(np.complex128)
+            xc[c] += 1j * eps
+            J[:, c] = F(xc).imag / eps
+        x = x - np.linalg.solve(J, f)
+    return x, np.abs(F(x.astype(np.complex128)).real).max()
+
+
+@pytest.mark.parametrize("alpha,sigma", [(0.2, 1.0), (-0.05, 0.5)])
+def test_dense_newton_periodic_8(oracle_mod, alpha, sigma):
+    n = 8
+    h = 1.0 / n
+    kappa = 1.5
+    delta = I.lognormal(n, 31, sigma=sigma)
+    assert (1 + 8 * alpha * kappa * delta / 3).min() > 0.1    # no cell near the guard
+
+    def F(x):
+        phi = x[:-1].reshape(n, n, n)
+        H = hessian_periodic(phi, h)
+        lap = H[0] + H[1] + H[2]
+        r = lap - q_root(sigma0(H), delta, alpha, kappa) + x[-1]
+        return np.concatenate([r.ravel() * h**2, [phi.sum() / n**3]])
+
+    x, res = _newton(F, np.zeros(n**3 + 1))
+    assert res < 1e-12
+    phi_ref = x[:-1].reshape(n, n, n)
+    phi, info = oracle_mod.solve(delta, alpha, kappa)
+    assert relerr(phi, phi_ref) < 1e-11
+    assert abs(info["cbar"] - x[-1]) < 1e-11 * max(1.0, abs(x[-1]))
+    assert abs(x[-1]) > 1e-6      # the compatibility constant is genuinely non-zero
+
+
+# ---------------------------------------------------------------------------
+# dense Newton on small Dirichlet patches, raw form Lap + alpha N = kappa delta
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [4, 5, 6])
+def test_dense_newton_dirichlet(oracle_mod, n):
+    h = 1.0 / 64
+    alpha, kappa = 0.1, 1.5
+    delta = I.lognormal(n, 41 + n, sigma=0.5)
+    rng = np.random.Generator(np.random.PCG64(7 + n))
+    P = np.zeros((n + 2,) * 3)
+    P[...] = 2e-4 * rng.standard_normal(P.shape)
+    ghost = pack_ghosts(P)
+
+    def F(x):
+        Q = P.astype(np.complex128)
+        Q[1:-1, 1:-1, 1:-1] = x.reshape(n, n, n)
+        H = hessian_padded(Q, h)
+        return ((H[0] + H[1] + H[2]) + alpha * n_term(H) - kappa * delta).ravel() * h**2
+
+    x, res = _newton(F, np.zeros(n**3))
+    assert res < 1e-14
+    phi_ref = x.reshape(n, n, n)
+    Pr = P.copy()
+    Pr[1:-1, 1:-1, 1:-1] = phi_ref
+    Hr = hessian_padded(Pr, h)
+    assert (1 + 4 * alpha * (Hr[0] + Hr[1] + Hr[2]) / 3).min() > 0   # physical branch everywhere
+    phi, info = oracle_mod.solve(delta, alpha, kappa, h=h, ghost=ghost)
+    assert info["rms"] < 1e-9
+    assert relerr(phi, phi_ref) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# splitting constant w: the discrete solution does not depend on it (Dirichlet, f = 0)
+# ---------------------------------------------------------------------------
+def test_w_independence(oracle_mod):
+    n = 8
+    h = 1.0 / 64
+    delta = I.lognormal(n, 51, sigma=0.8)
+    rng = np.random.Generator(np.random.PCG64(3))
+    ghost = 1e-3 * rng.standard_normal(oracle_mod.ghost_count((n, n, n)))
+    a, _ = oracle_mod.solve(delta, 0.1, 1.5, h=h, ghost=ghost, w=1.0 / 3.0)
+    b, _ = oracle_mod.solve(delta, 0.1, 1.5, h=h, ghost=ghost, w=0.25, max_cycles=400)
+    assert relerr(b, a) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# dL/dphi of Sec. III.B against central finite differences
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("w", [0.25, 1.0 / 3.0])
+def test_dLdphi_finite_difference(oracle_mod, w):
+    n = 8
+    delta = I.lognormal(n, 61, sigma=1.0)
+    rng = np.random.Generator(np.random.PCG64(9))
+    phi = 0.01 * rng.standard_normal((n, n, n))
+    c = (2, 5, 3)
+    L, dL, _, _ = oracle_mod.cell_operator(delta, phi, 0.2, 1.5, c, w=w)
+    eps = 1e-6
+    p1, p2 = phi.copy(), phi.copy()
+    p1[c[2], c[1], c[0]] += eps
+    p2[c[2], c[1], c[0]] -= eps
+    Lp = oracle_mod.cell_operator(delta, p1, 0.2, 1.5, c, w=w)[0]
+    Lm = oracle_mod.cell_operator(delta, p2, 0.2, 1.5, c, w=w)[0]
+    fd = (Lp - Lm) / (2 * eps)
+    assert abs(fd - dL) / abs(dL) < 1e-6
+    if w == 1.0 / 3.0:
+        assert abs(dL + 6 * n**2) / (6 * n**2) < 1e-12     # exactly -6/h^2 at w = 1/3
+    else:
+        assert abs(dL + 6 * n**2) / (6 * n**2) > 1e-4
+
+
+# ---------------------------------------------------------------------------
+# symmetries of the stencil: 48 cube symmetries and translations
+# ---------------------------------------------------------------------------
+def _cube_symmetries():
+    for perm in itertools.permutations(range(3)):
+        for flips in itertools.product((False, True), repeat=3):
+            yield perm, flips
+
+
+def _apply(u, perm, flips):
+    v = np.transpose(u, perm)
+    for ax, f in enumerate(flips):
+        if f:
+            v = np.flip(v, axis=ax)
+    return np.ascontiguousarray(v)
+
+
+def _invert(u, perm, flips):
+    v = u
+    for ax, f in enumerate(flips):
+        if f:
+            v = np.flip(v, axis=ax)
+    return np.ascontiguousarray(np.transpose(v, np.argsort(perm)))
+
+
+def test_cube_symmetries(oracle_mod):
+    n = 8
+    delta = I.lognormal(n, 71, sigma=1.0)
+    ref, _ = oracle_mod.solve(delta, 0.2, 1.5)
+    for perm, flips in _cube_symmetries():
+        phi, _ = oracle_mod.solve(_apply(delta, perm, flips), 0.2, 1.5)
+        assert relerr(_invert(phi, perm, flips), ref) < 1e-12, (perm, flips)
+
+
+def test_translation_and_shift(oracle_mod):
+    n = 16
+    delta = I.lognormal(n, 72, sigma=1.0)
+    ref, _ = oracle_mod.solve(delta, 0.2, 1.5)
+    phi, _ = oracle_mod.solve(np.roll(delta, (3, 5, 7), axis=(0, 1, 2)), 0.2, 1.5)
+    assert relerr(np.roll(phi, (-3, -5, -7), axis=(0, 1, 2)), ref) < 1e-12
+    # phi -> phi + const leaves the residual unchanged
+    d1, i1 = oracle_mod.residual(delta, ref, 0.2, 1.5)
+    d2, i2 = oracle_mod.residual(delta, ref + 0.37, 0.2, 1.5)
+    assert np.abs(d1 - d2).max() < 1e-10 * np.abs(ref).max() * n**2
+
+
+# ---------------------------------------------------------------------------
+# Dirichlet path reproduces a periodic solution on a cut-out (Sec. IV.D)
+# ---------------------------------------------------------------------------
+def test_cutout_reproduces_periodic(oracle_mod):
+    n, m = 32, 16
+    off = (5, 9, 3)               # (x, y, z) cell offset of the cut-out
+    delta = I.lognormal(n, 81, sigma=1.0)
+    phi_p, info = oracle_mod.solve(delta, 0.2, 1.5)
+    big = np.roll(phi_p, (-(off[2] - 1), -(off[1] - 1), -(off[0] - 1)), axis=(0, 1, 2))[:m + 2, :m + 2, :m + 2]
+    ghost = pack_ghosts(big)
+    sub_delta = np.roll(delta, (-off[2], -off[1], -off[0]), axis=(0, 1, 2))[:m, :m, :m]
+    src = np.full((m, m, m), -info["cbar"])
+    phi_d, dinfo = oracle_mod.solve(sub_delta, 0.2, 1.5, h=1.0 / n, ghost=ghost, source=src)
+    assert relerr(phi_d, big[1:-1, 1:-1, 1:-1]) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# refinement boundary values: trilinear interpolation is exact for linear fields
+# ---------------------------------------------------------------------------
+def test_ghost_fill_exact_for_linear(oracle_mod):
+    npar = 16
+    H = 1.0 / npar
+    x, y, z = I.cell_centres(npar)
+    parent = (0.3 * x[None, None, :] - 0.7 * y[None, :, None] + 1.1 * z[:, None, None])
+    n, h, origin = 8, 1.0 / 64, (12, 20, 17)   # patch well inside: no wrap involved
+    g = oracle_mod.fill_ghosts(parent, n, h, origin)
+    P = np.zeros((n + 2,) * 3)
+    c = lambda o: (o + np.arange(-1, n + 1) + 0.5) * h
+    P[...] = (0.3 * c(origin[0])[None, None, :] - 0.7 * c(origin[1])[None, :, None]
+              + 1.1 * c(origin[2])[:, None, None])
+    assert np.abs(g - pack_ghosts(P)).max() < 1e-14
+
+
+def test_ghost_fill_periodic_wrap(oracle_mod):
+    npar = 32
+    H = 1.0 / npar
+    x, y, z = I.cell_centres(npar)
+    f = lambda X, Y, Z: np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y) + np.sin(4 * np.pi * Z)
+    parent = f(x[None, None, :], y[None, :, None], z[:, None, None])
+    n, h, origin = 8, 1.0 / 128, (124, 3, 60)     # crosses x = 1 -> wraps
+    g = oracle_mod.fill_ghosts(parent, n, h, origin)
+    c = lambda o: np.mod((o + np.arange(-1, n + 1) + 0.5) * h, 1.0)
+    P = f(c(origin[0])[None, None, :], c(origin[1])[None, :, None], c(origin[2])[:, None, None])
+    assert np.abs(g - pack_ghosts(P)).max() < 2 * (2 * np.pi * 2) ** 2 * H**2 / 8 * 3
+
+
+# ---------------------------------------------------------------------------
+# Sec. II.B / IV.C physics: top-hat against the closed-form radial solution
+# ---------------------------------------------------------------------------
+def _radial_potential(r_eval, R, d0, dbar, alpha, kappa):
+    rr = np.linspace(1e-9, r_eval.max(), 20001)
+    m = (d0 * np.minimum(rr, R) ** 3 - dbar * rr**3) / 3.0
+    if alpha == 0.0:
+        g = kappa * m / rr**2
+    else:
+        g = 2 * kappa * m / rr**2 / (1 + np.sqrt(1 + 8 * alpha * kappa * m / rr**3))
+    Phi = np.concatenate([[0.0], np.cumsum(0.5 * (g[1:] + g[:-1]) * np.diff(rr))])
+    return np.interp(r_eval, rr, Phi)
+
+
+@pytest.mark.slow
+def test_tophat_closed_form(oracle_mod):
+    n, R, d0 = 64, 0.1, 50.0
+    alpha, kappa = 0.05, 1.5
+    delta = I.tophat(n, radius=R, amplitude=d0)
+    dbar = -delta.min()
+    x, y, z = I.cell_centres(n)
+    r = np.sqrt((x[None, None, :] - .5) ** 2 + (y[None, :, None] - .5) ** 2 + (z[:, None, None] - .5) ** 2)
+    sel = r < 1.6 * R
+
+    def mismatch(phi, a):
+        ref = _radial_potential(r[sel], R, d0, dbar, a, kappa)
+        diff = phi[sel] - ref
+        return np.abs(diff - diff.mean()).max() / (ref.max() - ref.min())
+
+    phi, info = oracle_mod.solve(delta, alpha, kappa, tol=1e-11)
+    err_nl = mismatch(phi, alpha)
+    err_wrong = mismatch(phi, 0.0)          # the linear (unscreened) profile must not fit
+    assert err_nl < 0.05, err_nl
+    assert err_wrong > 4 * err_nl, (err_nl, err_wrong)
