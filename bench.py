@@ -1,0 +1,187 @@
+"""Benchmark of the gfx950 Vainshtein multigrid solver (one GPU).
+
+Workload (the configuration the headline metric is quoted on): periodic 256^3
+unit box, density contrast from a CIC deposit of 256^3 lattice particles
+displaced by a seeded Zel'dovich field (P(k) ~ k^-1.5, cut at k_Nyquist/4),
+alpha = 0.2, kappa = 1.5, solved from phi = 0 to RMS residual 1e-8.
+
+One step = one complete solve (all V-cycles, every level, norms and host
+checks) with the inputs already resident in HBM.  ``value`` is smoother cell
+updates (all levels, all sweeps) per second of wall time over the timed
+steps; ``ms_per_step`` is the time to tolerance.
+
+``roofline`` describes the dominant kernel, the finest-level fused red-black
+sweep: algorithmic bytes per launch (24 B per cell: read phi, read delta,
+write phi) divided by its average duration, timed here with HIP events around
+back-to-back launches on the plan's stream.
+
+``cpu_baseline`` times the CPU oracle (plain FP64 C, one thread) on a bounded
+sample of the same workload: one lexicographic Newton-Gauss-Seidel sweep over
+the full 256^3 grid.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "zeldovich256"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip",):
+        p = os.path.join(ROOT, "paper_1303_0008_amd", "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; otherwise None."""
+    p = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def time_solves(torch, V, delta, w, prec, steps, warmup, flags, stream):
+    n = w["n"]
+    params = V.make_params(w["alpha"], w["kappa"], w["tol"], 100, prec, flags=flags)
+    plan = V.Plan([V.make_grid(n)], params, stream=stream)
+    phis = [torch.zeros_like(delta) for _ in range(steps + warmup)]
+    infos = []
+    with torch.cuda.stream(stream):
+        for i in range(warmup):
+            plan.solve(delta, phis[i])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        updates = 0
+        for i in range(steps):
+            infos.append(plan.solve(delta, phis[warmup + i])[0])
+            updates += plan.stats()["cell_updates"]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    return plan, infos, updates, (t1 - t0), phis[-1]
+
+
+def time_smoother(torch, plan, stream, launches):
+    """Average duration of the finest-level smoother, from HIP events on the plan's stream."""
+    plan.smooth(2)                      # warm
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    plan.smooth(launches)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / launches
+
+
+def cpu_baseline(delta, w):
+    from oracle import oracle as O
+    import numpy as np
+    phi = np.zeros_like(delta)
+    t0 = time.perf_counter()
+    O.relax(delta, phi, w["alpha"], w["kappa"], 1)
+    dt = time.perf_counter() - t0
+    cells = delta.size
+    return {"value": cells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one lexicographic Newton-Gauss-Seidel sweep of the FP64 oracle over the full "
+                      f"{w['n']}^3 workload ({cells} cell updates, {dt:.1f} s, single thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--smooth-launches", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the solver is a single-GPU build).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1303_0008_amd import inputs as I
+    from paper_1303_0008_amd import vmg as V
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    V.load()
+    w = dict(I.WORKLOADS[WORKLOAD])
+    t = time.perf_counter()
+    delta_np = I.workload_delta(WORKLOAD)
+    log(f"workload {WORKLOAD}: generated in {time.perf_counter() - t:.1f} s, max delta {delta_np.max():.1f}")
+    delta = torch.from_numpy(delta_np).to("cuda")
+    stream = torch.cuda.Stream()        # default priority
+    torch.cuda.synchronize()
+
+    results = {}
+    plan64, infos, updates, dt, phi_last = time_solves(torch, V, delta, w, V.FP64, args.steps, args.warmup,
+                                                       V.GRAPH, stream)
+    ms = 1e3 * dt / args.steps
+    log(f"fp64: {ms:.3f} ms/solve, cycles {infos[-1]['cycles']}, rms {infos[-1]['rms']:.3e}")
+    results["fp64"] = {"time_to_tol_ms": ms, "cycles": infos[-1]["cycles"], "rms": infos[-1]["rms"],
+                       "cell_updates_per_s": updates / dt}
+    smooth_ms = time_smoother(torch, plan64, stream, args.smooth_launches)
+    n3 = w["n"] ** 3
+    bytes_per_launch = 24 * n3
+    achieved = bytes_per_launch / (smooth_ms * 1e-3) / 1e9
+    log(f"smoother: {smooth_ms * 1e3:.1f} us/launch, {achieved:.0f} GB/s, {n3 / (smooth_ms * 1e-3) / 1e9:.1f} G cell-updates/s")
+    traffic = load_traffic("smooth_fp64_zeldovich256_traffic.json")
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_smooth<8,0> (finest-level fused red-black sweep, FP64)",
+            "bytes_per_launch": bytes_per_launch, "us_per_launch": smooth_ms * 1e3}
+    plan64.close()
+
+    line = {
+        "metric": "cell-updates/s (smoother, all levels) over the solve to RMS residual 1e-8 at 256^3",
+        "value": results["fp64"]["cell_updates_per_s"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": results["fp64"]["time_to_tol_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "zeldovich256: periodic 256^3, Zel'dovich+CIC delta (P~k^-1.5, "
+                               "cut k_Nyq/4), alpha=0.2, kappa=1.5, tol 1e-8, phi0=0",
+                   "n": w["n"], "alpha": w["alpha"], "kappa": w["kappa"], "tol": w["tol"],
+                   "precision": "fp64", "schedule": "V(2,2) fused red-black, hipGraph"},
+        "roofline": roof,
+        "results": results,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(delta_np, w)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

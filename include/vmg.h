@@ -1,0 +1,186 @@
+/*
+ * vmg.h -- C ABI of the MI355X (gfx950) nonlinear multigrid solver for the
+ * Vainshtein-screened scalar field of DGP/Galileon gravity.
+ *
+ * Problem (Li, Zhao & Koyama, Sec. III.A, Eq. code_eqn, in code units):
+ *
+ *     Lap(phi) + alpha [ (Lap phi)^2 - (d_i d_j phi)^2 ] = kappa * delta
+ *
+ * Here alpha is the coefficient of the nonlinear term (the reciprocal of the
+ * paper's alpha = 3 beta a^4 / R_c^2) and kappa the source coefficient
+ * (Omega_m a / beta).  Discretisation (Sec. III.B): cell-centred cubic cells
+ * of size h, 7-point Laplacian, 3-point second and 4-point cross differences,
+ * operator splitting with w = 1/3 (Eq. two_branch) and the physical root
+ * (Eq. one_branch).  At w = 1/3 the per-cell root does not depend on the
+ * cell's own value, so the nonlinear Gauss-Seidel update is closed form:
+ *
+ *     Sigma0 = [ ((a_x-a_y)^2 + (a_x-a_z)^2 + (a_y-a_z)^2)/3
+ *               + (B_xy^2 + B_xz^2 + B_yz^2)/8 ] / h^4
+ *     q = alpha*Sigma0 + kappa*delta,   D = 1 + (8 alpha / 3) q
+ *     Q = 2q / (1 + sqrt(D))   (D >= 0),   Q = -3/(4 alpha)   (D < 0, guard)
+ *     operator  L(phi) = Lap_h phi - Q
+ *
+ * a_x etc. are the 3-point second differences times h^2, B_xy etc. the
+ * 4-point cross differences times 4h^2 (Sec. III.B, discrete Sigma_ijk).
+ *
+ * Equations solved (Sec. III.C, Eq. fine_grid_eqn, with f the optional source):
+ *   periodic grid : L(phi) + cbar = f, with the constant cbar = mean(f) - mean(L(phi))
+ *                   that makes the periodic problem solvable, and mean(phi) = 0;
+ *   Dirichlet grid: L(phi) = f on the n0*n1*n2 cells, neighbours outside the grid
+ *                   taken from a given one-cell ghost shell (refinement boundary,
+ *                   Sec. III.C and IV.D).
+ * Residual d = L(phi) (+ cbar) - f; reported norm = sqrt(mean(d^2)) in FP64.
+ *
+ * Method: full-approximation-scheme V-cycles (Sec. III.C): fused red-black
+ * nonlinear Gauss-Seidel sweeps, residual with 8-child-average restriction,
+ * coarse right-hand side f^H = L^H(R phi^h) - R d^h, cell-centred trilinear
+ * prolongation of phi^H - R phi^h, direct relaxation on the coarsest level.
+ *
+ * Memory conventions.  Every array pointer is a DEVICE pointer (hipMalloc /
+ * torch.cuda memory) to FP64 data, x fastest: cell (i,j,k) of a grid is
+ * element offset + (k*n1 + j)*n0 + i.  The caller owns every array passed in;
+ * the plan owns all its workspaces.  No entry point throws; failures return a
+ * status and vmg_last_error() describes the last one (per thread).
+ */
+#ifndef VMG_H
+#define VMG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VMG_OK = 0,
+    VMG_EINVAL = 1,       /* invalid argument: sizes, spacing, tolerance, null pointer ... */
+    VMG_ENOMEM = 2,       /* device or host allocation failed */
+    VMG_EHIP = 3,         /* a HIP runtime call failed */
+    VMG_ENOCONV = 4,      /* max_cycles reached before the tolerance; results are filled */
+    VMG_ENONFINITE = 5    /* non-finite input or residual, or the residual diverged */
+} vmg_status;
+
+typedef enum { VMG_FP64 = 0, VMG_MIXED = 1 } vmg_precision;
+typedef enum { VMG_PERIODIC = 0, VMG_DIRICHLET = 1 } vmg_bc;
+
+/* flags */
+#define VMG_GRAPH 1u          /* replay the V-cycle as a captured hipGraph */
+#define VMG_AUTOTUNE 2u       /* time tile/schedule choices at plan creation */
+#define VMG_QUIET_NOCONV 4u   /* reserved */
+
+/* One grid.  A plan holds either exactly one periodic grid or one or more
+ * Dirichlet grids (refinement patches, solved as one batch). */
+typedef struct {
+    int32_t n[3];          /* cells along x, y, z; periodic: even, >= 4; Dirichlet: >= 2 */
+    int32_t bc;            /* vmg_bc */
+    double h;              /* cell size (> 0) */
+    int64_t offset;        /* element offset of this grid's cells in delta / phi / source */
+    int64_t ghost_offset;  /* Dirichlet: element offset of its ghost values in `ghost` */
+} vmg_grid;
+
+/* Compact ghost order of a Dirichlet grid (2(n1 n2 + n0 n2 + n0 n1) + 4(n0+n1+n2) values):
+ *   faces  x-, x+ : cells (-1, j, k), (n0, j, k)   j fastest, then k
+ *   faces  y-, y+ : cells (i, -1, k), (i, n1, k)   i fastest, then k
+ *   faces  z-, z+ : cells (i, j, -1), (i, j, n2)   i fastest, then j
+ *   edges along x : (i,-1,-1), (i,n1,-1), (i,-1,n2), (i,n1,n2)   i fastest
+ *   edges along y : (-1,j,-1), (n0,j,-1), (-1,j,n2), (n0,j,n2)   j fastest
+ *   edges along z : (-1,-1,k), (n0,-1,k), (-1,n1,k), (n0,n1,k)   k fastest
+ * Corner cells are not part of the 19-point stencil and are not stored. */
+
+typedef struct {
+    double alpha;          /* coefficient of the nonlinear term (0 = linear Poisson limit) */
+    double kappa;          /* source coefficient */
+    double tol;            /* stop when the RMS residual of every grid is <= tol (> 0) */
+    int32_t max_cycles;    /* V-cycles (FP64) or outer iterations (mixed); >= 1 */
+    int32_t prec;          /* vmg_precision */
+    int32_t nu1, nu2;      /* pre/post smoothing sweeps; 0,0 selects the defaults (2,2) */
+    uint32_t flags;        /* VMG_GRAPH | VMG_AUTOTUNE */
+    int32_t reserved;
+} vmg_params;
+
+typedef struct {
+    double rms0;           /* RMS residual of the initial guess */
+    double rms;            /* RMS residual of the returned phi */
+    double compat_c;       /* cbar (periodic), 0 for Dirichlet */
+    int32_t cycles;        /* V-cycles run (FP64) or outer iterations (mixed) */
+    int32_t inner_cycles;  /* FP32 inner V-cycles (mixed), 0 otherwise */
+    int64_t n_guarded;     /* cells where D < 0 at the returned phi */
+} vmg_result;
+
+typedef struct vmg_plan vmg_plan;
+
+/* Create a solver plan for `n_grids` grids (Sec. III.C: the domain grid, or a
+ * set of refinement patches).  Allocates every workspace on the current
+ * device, may run the autotuner (VMG_AUTOTUNE) and records the V-cycle graph
+ * (VMG_GRAPH).  All later work is issued on `stream` (0 = null stream).
+ * Errors: VMG_EINVAL (sizes, h <= 0, tol <= 0, max_cycles < 1, mixed BC kinds,
+ * a periodic grid that does not coarsen to <= 8 cells per side, a Dirichlet
+ * grid whose coarsest level exceeds 8 cells per side), VMG_ENOMEM, VMG_EHIP. */
+vmg_status vmg_plan_create(vmg_plan **plan, const vmg_grid *grids, int32_t n_grids,
+                           const vmg_params *p, hipStream_t stream);
+
+/* Solve (Sec. III.C: V-cycles until |d| < tol).  delta: density contrast of
+ * every grid; ghost: Dirichlet ghost values (may be NULL for a periodic plan);
+ * source: optional additive right-hand side f (NULL = 0; not supported with
+ * VMG_MIXED); phi: initial guess in, solution out (periodic: mean removed).
+ * out: host array of n_grids results.  Never allocates device memory; runs on
+ * the plan's stream and returns after it has finished.
+ * Errors: VMG_EINVAL (null pointers), VMG_ENONFINITE (non-finite delta or
+ * residual, divergence; phi holds the last iterate), VMG_ENOCONV (max_cycles
+ * reached; phi and out are filled), VMG_EHIP. */
+vmg_status vmg_solve(vmg_plan *plan, const double *delta, const double *ghost,
+                     const double *source, double *phi, vmg_result *out);
+
+/* Release every resource of the plan (NULL is accepted). */
+vmg_status vmg_plan_destroy(vmg_plan *plan);
+
+/* Thread-local message describing the last non-OK status ("" if none). */
+const char *vmg_last_error(void);
+
+/* Convenience: one periodic n^3 grid of the unit box (h = 1/n), one call.
+ * precision: vmg_precision.  rms and cycles are host pointers (may be NULL).
+ * Creates and destroys a plan internally (so it allocates). */
+vmg_status vmg_solve_periodic(const double *delta, int32_t n, double alpha, double kappa,
+                              double tol, int32_t precision, double *phi, double *rms,
+                              int32_t *cycles, hipStream_t stream);
+
+/* Residual of a given phi on grid `g` of a plan (Sec. III.C: d^h = L^h(phi^h) - f^h,
+ * with cbar on periodic grids): writes d (device, same layout as phi; may be
+ * NULL) and *res (host).  Pointers index the whole batch as in vmg_solve.
+ * Errors: VMG_EINVAL, VMG_EHIP. */
+vmg_status vmg_residual(vmg_plan *plan, int32_t g, const double *delta, const double *ghost,
+                        const double *source, const double *phi, double *d, vmg_result *res);
+
+/* Refinement boundary values (Sec. III.C, IV.D: "interpolated from coarser
+ * levels"): trilinear interpolation of a cell-centred periodic parent field
+ * (np[0] x np[1] x np[2] cells of size parent_h, device pointer, x fastest) at
+ * the centres of the ghost cells of each Dirichlet grid.  origins: host array of
+ * 3*n_grids integers, the position of cell (0,0,0) of grid i in units of that
+ * grid's h.  Writes ghost (device) at each grid's ghost_offset, compact order.
+ * Errors: VMG_EINVAL, VMG_EHIP. */
+vmg_status vmg_fill_ghosts(const double *parent, const int32_t np[3], double parent_h,
+                           const vmg_grid *grids, const int32_t *origins, int32_t n_grids,
+                           double *ghost, hipStream_t stream);
+
+/* Number of ghost values of a Dirichlet grid with n cells per axis. */
+int64_t vmg_ghost_count(const int32_t n[3]);
+
+/* Measurement hook: run `sweeps` finest-level smoother sweeps (the kernel the
+ * plan's precision uses on its finest level) on the plan's internal copy of
+ * that level as the last vmg_solve left it, enqueued on the plan's stream
+ * without host synchronisation.  Does not touch caller memory.
+ * Errors: VMG_EINVAL (no solve yet, sweeps < 0), VMG_EHIP. */
+vmg_status vmg_smooth(vmg_plan *plan, int32_t sweeps);
+
+/* Counters of the last vmg_solve (host pointers, each may be NULL):
+ * cell_updates  = smoother cell updates over all levels and sweeps,
+ * finest_sweeps = finest-level smoother sweeps (launches of that kernel),
+ * finest_cells  = cells of the finest level(s) per sweep. */
+vmg_status vmg_plan_stats(const vmg_plan *plan, int64_t *cell_updates, int64_t *finest_sweeps,
+                          int64_t *finest_cells);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VMG_H */

@@ -1,0 +1,149 @@
+// Device helpers shared by the FP64 and mixed-precision kernel files.
+#pragma once
+#include "vmg_internal.h"
+
+namespace vmg {
+
+constexpr int NT = 256;          // threads per block for every kernel here
+constexpr int MAX_RED_BLOCKS = 2048;
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+
+// 18 stencil neighbours of a cell (the centre is not needed by the root).
+template <typename T>
+struct NbT {
+    T xm, xp, ym, yp, zm, zp;
+    T xpyp, xmym, xpym, xmyp;
+    T xpzp, xmzm, xpzm, xmzp;
+    T ypzp, ymzm, ypzm, ymzp;
+};
+using Nb = NbT<double>;
+
+// Reciprocal and square root from the hardware approximations (v_rcp_f64,
+// v_rsq_f64) refined by two Newton steps each: ~1 ulp, a third of the IEEE
+// division / square-root sequences.
+__device__ __forceinline__ double rcp_nr(double u) {
+    double r = __builtin_amdgcn_rcp(u);
+    double e = fma(-u, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-u, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double sqrt_nr(double D) {   // D > 0
+    const double y = __builtin_amdgcn_rsq(D);
+    const double hy = 0.5 * y;
+    double s = D * y;
+    s = fma(hy, fma(-s, s, D), s);
+    return fma(hy, fma(-s, s, D), s);
+}
+
+// Physical root Q of the per-cell quadratic (Sec. III.A, Eq. one_branch at w = 1/3)
+// from the 18 neighbours; also returns the neighbour sum S and the guard flag.
+__device__ __forceinline__ double nl_root(const Nb& v, double dl, const Coef& c, double inv_h4,
+                                          double& S, bool& guard) {
+    const double sx = v.xp + v.xm, sy = v.yp + v.ym, sz = v.zp + v.zm;
+    S = sx + sy + sz;
+    const double dxy = sx - sy, dxz = sx - sz, dyz = sy - sz;
+    const double bxy = (v.xpyp + v.xmym) - (v.xpym + v.xmyp);
+    const double bxz = (v.xpzp + v.xmzm) - (v.xpzm + v.xmzp);
+    const double byz = (v.ypzp + v.ymzm) - (v.ypzm + v.ymzp);
+    const double s0 = ((dxy * dxy + dxz * dxz + dyz * dyz) * (1.0 / 3.0)
+                     + (bxy * bxy + bxz * bxz + byz * byz) * 0.125) * inv_h4;
+    const double q = c.alpha * s0 + c.kappa * dl;
+    const double D = 1.0 + c.c8 * q;
+    guard = !(D > 0.0);
+    // D == 0 gives 2q = vertex, so the guard branch is continuous there
+    return guard ? c.vertex : 2.0 * q * rcp_nr(1.0 + sqrt_nr(D));
+}
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous range of tiles so that shared halos stay in one L2.
+    if ((nb & 7) != 0) return b;
+    return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ void decode(const Geom& g, int64_t e, int& i, int& j, int& k) {
+    i = (int)(e % g.n0);
+    const int64_t r = e / g.n0;
+    j = (int)(r % g.n1);
+    k = (int)(r / g.n1);
+}
+
+__device__ __forceinline__ int64_t cell_index(const Geom& g, int i, int j, int k) {
+    return g.off0 + i + (int64_t)j * g.sy + (int64_t)k * g.sz;
+}
+
+// 18 neighbours of cell (i,j,k) read through global memory (periodic wrap or ghost shell)
+template <int DIR, typename T, typename NB>
+__device__ __forceinline__ T gather_nb(const Geom& g, const T* __restrict__ u, int i, int j, int k, NB& v) {
+    int im, ip, jm, jp, km, kp;
+    if (DIR) {
+        im = i - 1; ip = i + 1; jm = j - 1; jp = j + 1; km = k - 1; kp = k + 1;
+    } else {
+        im = i == 0 ? g.n0 - 1 : i - 1; ip = i == g.n0 - 1 ? 0 : i + 1;
+        jm = j == 0 ? g.n1 - 1 : j - 1; jp = j == g.n1 - 1 ? 0 : j + 1;
+        km = k == 0 ? g.n2 - 1 : k - 1; kp = k == g.n2 - 1 ? 0 : k + 1;
+    }
+    const int64_t sy = g.sy, sz = g.sz, o = g.off0;
+    auto at = [&](int x, int y, int z) { return u[o + x + y * sy + z * sz]; };
+    v.xm = at(im, j, k); v.xp = at(ip, j, k);
+    v.ym = at(i, jm, k); v.yp = at(i, jp, k);
+    v.zm = at(i, j, km); v.zp = at(i, j, kp);
+    v.xpyp = at(ip, jp, k); v.xmym = at(im, jm, k); v.xpym = at(ip, jm, k); v.xmyp = at(im, jp, k);
+    v.xpzp = at(ip, j, kp); v.xmzm = at(im, j, km); v.xpzm = at(ip, j, km); v.xmzp = at(im, j, kp);
+    v.ypzp = at(i, jp, kp); v.ymzm = at(i, jm, km); v.ypzm = at(i, jp, km); v.ymzp = at(i, jm, kp);
+    return at(i, j, k);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum R_NSLOT per-thread accumulators over the block (fixed order) and store
+// them in partials[blockIdx.x * R_NSLOT + k].
+__device__ __forceinline__ void block_store_partials(double (&acc)[R_NSLOT], double* partials) {
+    __shared__ double red[NT / 64][R_NSLOT];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < R_NSLOT; ++k) {
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) red[w][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < R_NSLOT) {
+        double s = 0.0;
+        for (int q = 0; q < NT / 64; ++q) s += red[q][threadIdx.x];
+        partials[(int64_t)blockIdx.x * R_NSLOT + threadIdx.x] = s;
+    }
+}
+
+// residual d = L(phi) + cbar - f at one cell; also returns Q and the guard flag
+template <int DIR>
+__device__ __forceinline__ double cell_residual(const Geom& g, const Coef& c, const double* phi,
+                                                const double* delta, const double* f, double cb,
+                                                int i, int j, int k, double inv_h2, double inv_h4,
+                                                double& Q, bool& gd, double& pc, double& fv) {
+    Nb v;
+    pc = gather_nb<DIR>(g, phi, i, j, k, v);
+    const int64_t gi = cell_index(g, i, j, k);
+    double S;
+    Q = nl_root(v, delta[gi], c, inv_h4, S, gd);
+    fv = f ? f[gi] : 0.0;
+    return (S - 6.0 * pc) * inv_h2 - Q - fv + cb;
+}
+
+static inline int grid_for(int64_t n, int cap = 65536) {
+    int64_t b = (n + NT - 1) / NT;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+}  // namespace vmg

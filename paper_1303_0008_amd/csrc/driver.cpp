@@ -1,0 +1,571 @@
+// Host side of the gfx950 multigrid library: plans, level hierarchies, the
+// FAS V-cycle (Li, Zhao & Koyama, Sec. III.C), the convergence loop, hipGraph
+// replay of a cycle, and the extern "C" entry points declared in vmg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vmg.h"
+#include "vmg_internal.h"
+#include "vmg_plan.h"
+
+namespace vmg {
+
+thread_local std::string g_err;
+
+vmg_status fail(vmg_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define CKH(expr)                                                                        \
+    do {                                                                                 \
+        hipError_t _e = (expr);                                                          \
+        if (_e != hipSuccess)                                                            \
+            return fail(VMG_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));    \
+    } while (0)
+
+static Geom make_geom(int n0, int n1, int n2, bool dirichlet, double h) {
+    Geom g;
+    g.n0 = n0; g.n1 = n1; g.n2 = n2;
+    g.dir = dirichlet ? 1 : 0;
+    g.h = h;
+    g.base = 0;
+    g.ncell = (int64_t)n0 * n1 * n2;
+    if (dirichlet) {
+        g.sy = n0 + 2;
+        g.sz = g.sy * (n1 + 2);
+        g.off0 = 1 + g.sy + g.sz;
+        g.nstore = g.sz * (n2 + 2);
+    } else {
+        g.sy = n0;
+        g.sz = (int64_t)n0 * n1;
+        g.off0 = 0;
+        g.nstore = g.ncell;
+    }
+    return g;
+}
+
+static bool can_coarsen(const Geom& g) {
+    const int minc = g.dir ? 2 : 4;
+    const int n[3] = {g.n0, g.n1, g.n2};
+    for (int d = 0; d < 3; ++d)
+        if ((n[d] & 1) || n[d] / 2 < minc) return false;
+    return true;
+}
+
+Coef make_coef(double alpha, double kappa) {
+    Coef c;
+    c.alpha = alpha;
+    c.kappa = kappa;
+    c.c8 = 8.0 * alpha / 3.0;
+    c.vertex = alpha != 0.0 ? -3.0 / (4.0 * alpha) : 0.0;
+    return c;
+}
+
+static vmg_status dalloc(Plan* P, void** p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) return fail(VMG_ENOMEM, "hipMalloc failed");
+    P->allocs.push_back(*p);
+    return VMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+vmg_status build_plan(Plan* P, const vmg_grid* grids, int n_grids, const vmg_params* p,
+                      hipStream_t stream) {
+    if (!stream) {
+        // stream capture is not possible on the legacy null stream: use a blocking
+        // stream of our own (default priority; it synchronises with the null stream)
+        CKH(hipStreamCreate(&P->own_stream));
+        stream = P->own_stream;
+    }
+    P->stream = stream;
+    P->params = *p;
+    P->coef = make_coef(p->alpha, p->kappa);
+    P->nu1 = p->nu1;
+    P->nu2 = p->nu2;
+    if (P->nu1 == 0 && P->nu2 == 0) { P->nu1 = 2; P->nu2 = 2; }
+    P->ncoarse = 40;
+    P->cfg.ty = 8;
+    P->cfg.zc = 16;
+    P->periodic = grids[0].bc == VMG_PERIODIC;
+    int64_t max_cells = 1;
+    for (int gi = 0; gi < n_grids; ++gi) {
+        const vmg_grid& d = grids[gi];
+        GridState G;
+        G.desc = d;
+        Geom g = make_geom(d.n[0], d.n[1], d.n[2], d.bc == VMG_DIRICHLET, d.h);
+        for (;;) {
+            LevelBuf L;
+            L.g = g;
+            G.lev.push_back(L);
+            if (!can_coarsen(g) || G.lev.size() >= 24) break;
+            g = make_geom(g.n0 / 2, g.n1 / 2, g.n2 / 2, g.dir == 1, g.h * 2.0);
+        }
+        const Geom& gc = G.lev.back().g;
+        if (gc.n0 > 8 || gc.n1 > 8 || gc.n2 > 8)
+            return fail(VMG_EINVAL, "grid " + std::to_string(gi) + " does not coarsen to <= 8 cells per side");
+        max_cells = std::max<int64_t>(max_cells, G.lev[0].g.ncell);
+        P->grids.push_back(G);
+    }
+    // allocations
+    for (auto& G : P->grids) {
+        for (size_t l = 0; l < G.lev.size(); ++l) {
+            LevelBuf& L = G.lev[l];
+            const size_t bytes = sizeof(double) * (size_t)L.g.nstore;
+            vmg_status st;
+            if ((st = dalloc(P, (void**)&L.phi[0], bytes)) != VMG_OK) return st;
+            if ((st = dalloc(P, (void**)&L.phi[1], bytes)) != VMG_OK) return st;
+            if ((st = dalloc(P, (void**)&L.delta, bytes)) != VMG_OK) return st;
+            if ((st = dalloc(P, (void**)&L.f, bytes)) != VMG_OK) return st;
+            if (l > 0) {
+                if ((st = dalloc(P, (void**)&L.phiold, bytes)) != VMG_OK) return st;
+                if ((st = dalloc(P, (void**)&L.rd, bytes)) != VMG_OK) return st;
+            }
+            if ((st = dalloc(P, (void**)&L.sc, sizeof(LevelScalars))) != VMG_OK) return st;
+            CKH(launch_fill(L.phi[0], L.g.nstore, 0.0, stream));
+            CKH(launch_fill(L.phi[1], L.g.nstore, 0.0, stream));
+            CKH(launch_fill(L.f, L.g.nstore, 0.0, stream));
+            CKH(launch_fill(L.delta, L.g.nstore, 0.0, stream));
+            if (l > 0) {
+                CKH(launch_fill(L.phiold, L.g.nstore, 0.0, stream));
+                CKH(launch_fill(L.rd, L.g.nstore, 0.0, stream));
+            }
+            CKH(launch_fill((double*)L.sc, sizeof(LevelScalars) / sizeof(double), 0.0, stream));
+        }
+        vmg_status st;
+        if ((st = dalloc(P, (void**)&G.norm_dev, sizeof(NormOut))) != VMG_OK) return st;
+    }
+    const int nb = partial_blocks_for(max_cells);
+    vmg_status st;
+    P->mixed = p->prec == VMG_MIXED;
+    if (P->mixed && (st = alloc_mixed(P)) != VMG_OK) return st;
+    if ((st = dalloc(P, (void**)&P->partials, sizeof(double) * R_NSLOT * (size_t)nb)) != VMG_OK) return st;
+    if (hipHostMalloc((void**)&P->host_norm, sizeof(NormOut) * P->grids.size(), hipHostMallocDefault) !=
+        hipSuccess)
+        return fail(VMG_ENOMEM, "hipHostMalloc failed");
+    CKH(hipStreamSynchronize(stream));
+    return VMG_OK;
+}
+
+void destroy_plan(Plan* P) {
+    for (int q = 0; q < 2; ++q)
+        if (P->graph_ok[q]) (void)hipGraphExecDestroy(P->graph[q]);
+    for (void* a : P->allocs) (void)hipFree(a);
+    if (P->host_norm) (void)hipHostFree(P->host_norm);
+    if (P->own_stream) (void)hipStreamDestroy(P->own_stream);
+}
+
+// ---------------------------------------------------------------------------
+// one V-cycle on one grid
+// ---------------------------------------------------------------------------
+static const double* level_f(const Plan* P, const GridState& G, int l) {
+    if (l > 0) return G.lev[l].f;
+    return P->has_source ? G.lev[0].f : nullptr;
+}
+
+static hipError_t smooth_level(Plan* P, GridState& G, int l) {
+    LevelBuf& L = G.lev[l];
+    hipError_t e = launch_smooth(L.g, P->coef, L.phi[L.cur], L.phi[L.cur ^ 1], L.delta,
+                                 level_f(P, G, l), L.sc, P->cfg, P->stream);
+    L.cur ^= 1;
+    P->cell_updates += L.g.ncell;
+    if (l == 0) P->finest_sweeps += 1;
+    return e;
+}
+
+static hipError_t vcycle(Plan* P, GridState& G, int l) {
+    LevelBuf& L = G.lev[l];
+    const int last = (int)G.lev.size() - 1;
+    hipError_t e;
+    if (l == last) {
+        e = launch_coarse_solve(L.g, P->coef, L.phi[L.cur], L.delta, level_f(P, G, l), L.sc,
+                                P->ncoarse, P->stream);
+        P->cell_updates += (int64_t)P->ncoarse * L.g.ncell;
+        return e;
+    }
+    for (int s = 0; s < P->nu1; ++s)
+        if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
+    LevelBuf& C = G.lev[l + 1];
+    C.cur = 0;
+    int nb = 0;
+    const int periodic = L.g.dir ? 0 : 1;
+    if ((e = launch_residual_restrict(L.g, C.g, P->coef, L.phi[L.cur], L.delta, level_f(P, G, l), L.sc,
+                                      C.phi[0], C.phiold, C.rd, P->partials, &nb, P->stream)) != hipSuccess)
+        return e;
+    if ((e = launch_finalize(P->partials, nb, L.g.ncell, periodic, 0, L.sc, nullptr, P->stream)) != hipSuccess)
+        return e;
+    if ((e = launch_fas_rhs(C.g, P->coef, C.phi[0], C.delta, C.rd, C.f, P->partials, &nb, P->stream)) !=
+        hipSuccess)
+        return e;
+    if ((e = launch_finalize(P->partials, nb, C.g.ncell, periodic, 1, C.sc, nullptr, P->stream)) != hipSuccess)
+        return e;
+    if ((e = vcycle(P, G, l + 1)) != hipSuccess) return e;
+    if ((e = launch_prolong(L.g, C.g, L.phi[L.cur], C.phi[C.cur], C.phiold, P->stream)) != hipSuccess)
+        return e;
+    for (int s = 0; s < P->nu2; ++s)
+        if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+static hipError_t norm_pass(Plan* P, GridState& G) {
+    LevelBuf& L = G.lev[0];
+    int nb = 0;
+    hipError_t e = launch_residual_norm(L.g, P->coef, L.phi[L.cur], L.delta, level_f(P, G, 0), L.sc,
+                                        nullptr, P->partials, &nb, P->stream);
+    if (e != hipSuccess) return e;
+    return launch_finalize(P->partials, nb, L.g.ncell, L.g.dir ? 0 : 1, 0, L.sc, G.norm_dev, P->stream);
+}
+
+// Enqueue one full cycle for every grid + norms + the copy of the norms to the host.
+static hipError_t enqueue_cycle(Plan* P) {
+    hipError_t e;
+    for (auto& G : P->grids) {
+        if ((e = vcycle(P, G, 0)) != hipSuccess) return e;
+        if ((e = norm_pass(P, G)) != hipSuccess) return e;
+    }
+    for (size_t gi = 0; gi < P->grids.size(); ++gi) {
+        e = hipMemcpyAsync(&P->host_norm[gi], P->grids[gi].norm_dev, sizeof(NormOut),
+                           hipMemcpyDeviceToHost, P->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static hipError_t enqueue_iteration(Plan* P) { return P->mixed ? enqueue_outer(P) : enqueue_cycle(P); }
+
+static vmg_status run_cycle(Plan* P) {
+    const bool use_graph = (P->params.flags & VMG_GRAPH) != 0;
+    const int parity = P->grids[0].lev[0].cur;
+    if (!use_graph) {
+        CKH(enqueue_iteration(P));
+        CKH(hipStreamSynchronize(P->stream));
+        return VMG_OK;
+    }
+    if (!P->graph_ok[parity]) {
+        // capture the cycle once for this ping-pong parity of the finest level
+        std::vector<int> saved;
+        for (auto& G : P->grids) saved.push_back(G.lev[0].cur);
+        const int64_t cu = P->cell_updates, fs = P->finest_sweeps;
+        hipGraph_t graph;
+        CKH(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_iteration(P);
+        hipError_t e2 = hipStreamEndCapture(P->stream, &graph);
+        if (e != hipSuccess) return fail(VMG_EHIP, std::string("capture: ") + hipGetErrorString(e));
+        CKH(e2);
+        CKH(hipGraphInstantiate(&P->graph[parity], graph, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(graph);
+        P->graph_ok[parity] = true;
+        P->cycle_updates = P->cell_updates - cu;
+        P->cycle_finest = P->finest_sweeps - fs;
+        for (size_t gi = 0; gi < P->grids.size(); ++gi) P->grids[gi].lev[0].cur = saved[gi];
+        P->cell_updates = cu;
+        P->finest_sweeps = fs;
+    }
+    CKH(hipGraphLaunch(P->graph[parity], P->stream));
+    CKH(hipStreamSynchronize(P->stream));
+    // the captured cycle flips the finest level exactly as the eager one would
+    P->cell_updates += P->cycle_updates;
+    P->finest_sweeps += P->cycle_finest;
+    if (!P->mixed)   // the mixed path updates phi in place
+        for (auto& G : P->grids)
+            if ((P->nu1 + P->nu2) & 1) G.lev[0].cur ^= 1;
+    return VMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+vmg_status solve(Plan* P, const double* delta, const double* ghost, const double* source, double* phi,
+                 vmg_result* out) {
+    hipStream_t s = P->stream;
+    P->has_source = source != nullptr;
+    P->cell_updates = 0;
+    P->finest_sweeps = 0;
+    // ---- inputs -> plan buffers ------------------------------------------
+    int nb = 0;
+    for (auto& G : P->grids) {
+        LevelBuf& L0 = G.lev[0];
+        const double* d_in = delta + G.desc.offset;
+        CKH(launch_check_finite(d_in, L0.g.ncell, P->partials, &nb, s));
+        CKH(launch_finalize(P->partials, nb, L0.g.ncell, 0, 0, L0.sc, G.norm_dev, s));
+        CKH(hipMemcpyAsync(&P->host_norm[&G - &P->grids[0]], G.norm_dev, sizeof(NormOut),
+                           hipMemcpyDeviceToHost, s));
+    }
+    CKH(hipStreamSynchronize(s));
+    for (size_t gi = 0; gi < P->grids.size(); ++gi)
+        if (P->host_norm[gi].n_nonfinite > 0)
+            return fail(VMG_ENONFINITE, "non-finite values in delta of grid " + std::to_string(gi));
+    for (auto& G : P->grids) {
+        LevelBuf& L0 = G.lev[0];
+        L0.cur = 0;
+        CKH(launch_copy_in(L0.g, delta + G.desc.offset, L0.delta, s));
+        CKH(launch_copy_in(L0.g, phi + G.desc.offset, L0.phi[0], s));
+        if (source) CKH(launch_copy_in(L0.g, source + G.desc.offset, L0.f, s));
+        if (L0.g.dir) {
+            CKH(launch_ghost_in(L0.g, ghost + G.desc.ghost_offset, L0.phi[0], s));
+            CKH(launch_ghost_in(L0.g, ghost + G.desc.ghost_offset, L0.phi[1], s));
+        }
+        for (size_t l = 1; l < G.lev.size(); ++l) {
+            LevelBuf& F = G.lev[l - 1];
+            LevelBuf& C = G.lev[l];
+            CKH(launch_restrict_plain(F.g, C.g, F.delta, C.delta, s));
+            if (C.g.dir) {
+                CKH(launch_restrict_ghosts(F.g, C.g, F.phi[0], C.phi[0], s));
+                CKH(launch_restrict_ghosts(F.g, C.g, F.phi[0], C.phi[1], s));
+                CKH(launch_restrict_ghosts(F.g, C.g, F.phi[0], C.phiold, s));
+            }
+        }
+        for (auto& L : G.lev) CKH(launch_fill((double*)L.sc, sizeof(LevelScalars) / sizeof(double), 0.0, s));
+        if (!P->mixed) CKH(norm_pass(P, G));
+    }
+    if (P->mixed) {
+        CKH(mixed_prepare(P));
+        CKH(mixed_initial_pass(P));
+    } else {
+        for (size_t gi = 0; gi < P->grids.size(); ++gi)
+            CKH(hipMemcpyAsync(&P->host_norm[gi], P->grids[gi].norm_dev, sizeof(NormOut),
+                               hipMemcpyDeviceToHost, s));
+    }
+    CKH(hipStreamSynchronize(s));
+    const int ng = (int)P->grids.size();
+    std::vector<double> rms0(ng), best(ng);
+    for (int gi = 0; gi < ng; ++gi) {
+        rms0[gi] = P->host_norm[gi].rms;
+        best[gi] = rms0[gi];
+        if (!(P->host_norm[gi].n_nonfinite == 0) || !std::isfinite(rms0[gi]))
+            return fail(VMG_ENONFINITE, "non-finite initial residual in grid " + std::to_string(gi));
+    }
+    // ---- cycles ------------------------------------------------------------
+    int cycles = 0;
+    vmg_status status = VMG_OK;
+    auto converged = [&]() {
+        for (int gi = 0; gi < ng; ++gi)
+            if (!(P->host_norm[gi].rms <= P->params.tol)) return false;
+        return true;
+    };
+    while (!converged()) {
+        if (cycles >= P->params.max_cycles) {
+            status = VMG_ENOCONV;
+            break;
+        }
+        vmg_status st = run_cycle(P);
+        if (st != VMG_OK) return st;
+        ++cycles;
+        bool bad = false;
+        for (int gi = 0; gi < ng; ++gi) {
+            const NormOut& no = P->host_norm[gi];
+            if (no.n_nonfinite > 0 || !std::isfinite(no.rms) || no.rms > 1e6 * std::max(best[gi], 1e-300))
+                bad = true;
+            best[gi] = std::min(best[gi], no.rms);
+        }
+        if (bad) {
+            status = VMG_ENONFINITE;
+            g_err = "residual became non-finite or diverged";
+            break;
+        }
+    }
+    // ---- outputs -------------------------------------------------------------
+    for (int gi = 0; gi < ng; ++gi) {
+        GridState& G = P->grids[gi];
+        LevelBuf& L0 = G.lev[0];
+        if (!L0.g.dir) CKH(launch_gauge(L0.g, L0.phi[L0.cur], G.norm_dev, s));
+        CKH(launch_copy_out(L0.g, L0.phi[L0.cur], phi + G.desc.offset, s));
+        if (out) {
+            out[gi].rms0 = rms0[gi];
+            out[gi].rms = P->host_norm[gi].rms;
+            out[gi].compat_c = P->host_norm[gi].cbar;
+            out[gi].cycles = cycles;
+            out[gi].inner_cycles = P->mixed ? cycles : 0;
+            out[gi].n_guarded = (int64_t)P->host_norm[gi].n_guard;
+        }
+    }
+    CKH(hipStreamSynchronize(s));
+    P->solved = true;
+    if (status == VMG_ENOCONV) g_err = "max_cycles reached before the tolerance";
+    return status;
+}
+
+}  // namespace vmg
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace vmg;
+
+extern "C" {
+
+const char* vmg_last_error(void) { return g_err.c_str(); }
+
+int64_t vmg_ghost_count(const int32_t n[3]) {
+    if (!n) return 0;
+    return ghost_count(n[0], n[1], n[2]);
+}
+
+vmg_status vmg_plan_create(vmg_plan** plan, const vmg_grid* grids, int32_t n_grids, const vmg_params* p,
+                           hipStream_t stream) {
+    g_err.clear();
+    if (!plan || !grids || !p || n_grids < 1) return fail(VMG_EINVAL, "null argument or n_grids < 1");
+    *plan = nullptr;
+    if (!(p->tol > 0.0) || p->max_cycles < 1 || (p->prec != VMG_FP64 && p->prec != VMG_MIXED) ||
+        p->nu1 < 0 || p->nu2 < 0 || !std::isfinite(p->alpha) || !std::isfinite(p->kappa))
+        return fail(VMG_EINVAL, "invalid parameters (tol > 0, max_cycles >= 1, prec, nu1/nu2 >= 0, finite alpha/kappa)");
+    const int bc0 = grids[0].bc;
+    for (int i = 0; i < n_grids; ++i) {
+        const vmg_grid& g = grids[i];
+        if (g.bc != VMG_PERIODIC && g.bc != VMG_DIRICHLET) return fail(VMG_EINVAL, "unknown bc");
+        if (g.bc != bc0) return fail(VMG_EINVAL, "a plan holds one periodic grid or Dirichlet grids only");
+        const int minn = g.bc == VMG_PERIODIC ? 4 : 2;
+        if (g.n[0] < minn || g.n[1] < minn || g.n[2] < minn)
+            return fail(VMG_EINVAL, "grid too small (periodic >= 4, Dirichlet >= 2 cells per side)");
+        if (!(g.h > 0.0) || !std::isfinite(g.h)) return fail(VMG_EINVAL, "h must be > 0");
+        if (g.offset < 0 || g.ghost_offset < 0) return fail(VMG_EINVAL, "negative offset");
+    }
+    if (bc0 == VMG_PERIODIC && n_grids != 1) return fail(VMG_EINVAL, "a periodic plan holds exactly one grid");
+    Plan* P = new (std::nothrow) Plan();
+    if (!P) return fail(VMG_ENOMEM, "host allocation failed");
+    vmg_status st = build_plan(P, grids, n_grids, p, stream);
+    if (st != VMG_OK) {
+        std::string msg = g_err;
+        destroy_plan(P);
+        delete P;
+        g_err = msg;
+        return st;
+    }
+    *plan = reinterpret_cast<vmg_plan*>(P);
+    return VMG_OK;
+}
+
+vmg_status vmg_plan_destroy(vmg_plan* plan) {
+    if (!plan) return VMG_OK;
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    (void)hipStreamSynchronize(P->stream);
+    destroy_plan(P);
+    delete P;
+    return VMG_OK;
+}
+
+vmg_status vmg_solve(vmg_plan* plan, const double* delta, const double* ghost, const double* source,
+                     double* phi, vmg_result* out) {
+    g_err.clear();
+    if (!plan || !delta || !phi) return fail(VMG_EINVAL, "null plan, delta or phi");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    if (!P->periodic && !ghost) return fail(VMG_EINVAL, "Dirichlet grids need ghost values");
+    return solve(P, delta, ghost, source, phi, out);
+}
+
+vmg_status vmg_solve_periodic(const double* delta, int32_t n, double alpha, double kappa, double tol,
+                              int32_t precision, double* phi, double* rms, int32_t* cycles,
+                              hipStream_t stream) {
+    vmg_grid g;
+    std::memset(&g, 0, sizeof(g));
+    g.n[0] = g.n[1] = g.n[2] = n;
+    g.bc = VMG_PERIODIC;
+    g.h = n > 0 ? 1.0 / n : 0.0;
+    vmg_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.alpha = alpha;
+    p.kappa = kappa;
+    p.tol = tol;
+    p.max_cycles = 200;
+    p.prec = precision;
+    vmg_plan* plan = nullptr;
+    vmg_status st = vmg_plan_create(&plan, &g, 1, &p, stream);
+    if (st != VMG_OK) return st;
+    vmg_result r;
+    std::memset(&r, 0, sizeof(r));
+    st = vmg_solve(plan, delta, nullptr, nullptr, phi, &r);
+    std::string msg = g_err;
+    vmg_plan_destroy(plan);
+    g_err = msg;
+    if (rms) *rms = r.rms;
+    if (cycles) *cycles = r.cycles;
+    return st;
+}
+
+vmg_status vmg_residual(vmg_plan* plan, int32_t gi, const double* delta, const double* ghost,
+                        const double* source, const double* phi, double* d, vmg_result* res) {
+    g_err.clear();
+    if (!plan || !delta || !phi) return fail(VMG_EINVAL, "null plan, delta or phi");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    if (gi < 0 || gi >= (int)P->grids.size()) return fail(VMG_EINVAL, "grid index out of range");
+    GridState& G = P->grids[gi];
+    LevelBuf& L0 = G.lev[0];
+    if (L0.g.dir && !ghost) return fail(VMG_EINVAL, "Dirichlet grids need ghost values");
+    hipStream_t s = P->stream;
+    const bool had = P->has_source;
+    P->has_source = source != nullptr;
+    L0.cur = 0;
+    CKH(launch_copy_in(L0.g, delta + G.desc.offset, L0.delta, s));
+    CKH(launch_copy_in(L0.g, phi + G.desc.offset, L0.phi[0], s));
+    if (source) CKH(launch_copy_in(L0.g, source + G.desc.offset, L0.f, s));
+    if (L0.g.dir) CKH(launch_ghost_in(L0.g, ghost + G.desc.ghost_offset, L0.phi[0], s));
+    CKH(launch_fill((double*)L0.sc, sizeof(LevelScalars) / sizeof(double), 0.0, s));
+    int nb = 0;
+    const double* f = P->has_source ? L0.f : nullptr;
+    // first pass sets cbar, second evaluates d with it
+    CKH(launch_residual_norm(L0.g, P->coef, L0.phi[0], L0.delta, f, L0.sc, nullptr, P->partials, &nb, s));
+    CKH(launch_finalize(P->partials, nb, L0.g.ncell, L0.g.dir ? 0 : 1, 0, L0.sc, G.norm_dev, s));
+    CKH(launch_residual_norm(L0.g, P->coef, L0.phi[0], L0.delta, f, L0.sc, d ? d + G.desc.offset : nullptr,
+                             P->partials, &nb, s));
+    CKH(launch_finalize(P->partials, nb, L0.g.ncell, L0.g.dir ? 0 : 1, 0, L0.sc, G.norm_dev, s));
+    NormOut no;
+    CKH(hipMemcpyAsync(&no, G.norm_dev, sizeof(NormOut), hipMemcpyDeviceToHost, s));
+    CKH(hipStreamSynchronize(s));
+    P->has_source = had;
+    P->solved = false;   // the finest-level buffers no longer hold a solve's state
+    if (res) {
+        res->rms0 = no.rms;
+        res->rms = no.rms;
+        res->compat_c = no.cbar;
+        res->cycles = 0;
+        res->inner_cycles = 0;
+        res->n_guarded = (int64_t)no.n_guard;
+    }
+    return VMG_OK;
+}
+
+vmg_status vmg_fill_ghosts(const double* parent, const int32_t np[3], double parent_h, const vmg_grid* grids,
+                           const int32_t* origins, int32_t n_grids, double* ghost, hipStream_t stream) {
+    g_err.clear();
+    if (!parent || !np || !grids || !origins || !ghost || n_grids < 1)
+        return fail(VMG_EINVAL, "null argument");
+    if (np[0] < 1 || np[1] < 1 || np[2] < 1 || !(parent_h > 0.0)) return fail(VMG_EINVAL, "bad parent grid");
+    for (int i = 0; i < n_grids; ++i) {
+        const vmg_grid& g = grids[i];
+        if (g.bc != VMG_DIRICHLET || g.n[0] < 1 || g.n[1] < 1 || g.n[2] < 1 || !(g.h > 0.0))
+            return fail(VMG_EINVAL, "ghost fill needs Dirichlet grids with n >= 1 and h > 0");
+        CKH(launch_ghost_fill(parent, np[0], np[1], np[2], parent_h, g.n[0], g.n[1], g.n[2], g.h,
+                              origins[3 * i], origins[3 * i + 1], origins[3 * i + 2], ghost + g.ghost_offset,
+                              stream));
+    }
+    return VMG_OK;
+}
+
+vmg_status vmg_smooth(vmg_plan* plan, int32_t sweeps) {
+    g_err.clear();
+    if (!plan || sweeps < 0) return fail(VMG_EINVAL, "null plan or sweeps < 0");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    if (!P->solved) return fail(VMG_EINVAL, "vmg_smooth needs a previous vmg_solve");
+    for (int s = 0; s < sweeps; ++s)
+        for (auto& G : P->grids) CKH(P->mixed ? smooth_corr_level(P, G, 0) : smooth_level(P, G, 0));
+    return VMG_OK;
+}
+
+vmg_status vmg_plan_stats(const vmg_plan* plan, int64_t* cell_updates, int64_t* finest_sweeps,
+                          int64_t* finest_cells) {
+    if (!plan) return fail(VMG_EINVAL, "null plan");
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (cell_updates) *cell_updates = P->cell_updates;
+    if (finest_sweeps) *finest_sweeps = P->finest_sweeps;
+    if (finest_cells) {
+        int64_t c = 0;
+        for (const auto& G : P->grids) c += G.lev[0].g.ncell;
+        *finest_cells = c;
+    }
+    return VMG_OK;
+}
+
+}  // extern "C"

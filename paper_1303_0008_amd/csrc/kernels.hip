@@ -1,0 +1,1215 @@
+// gfx950 kernels of the FP64 nonlinear multigrid path.
+//
+// Discrete operator (Li, Zhao & Koyama, Sec. III.B with w = 1/3, Eq. one_branch):
+//   s_x = phi(i+1)+phi(i-1) (likewise y, z), S = s_x+s_y+s_z
+//   B_xy = phi(+,+)+phi(-,-)-phi(+,-)-phi(-,+) (likewise xz, yz)
+//   Sigma0 h^4 = ((s_x-s_y)^2+(s_x-s_z)^2+(s_y-s_z)^2)/3 + (B_xy^2+B_xz^2+B_yz^2)/8
+//   q = alpha*Sigma0 + kappa*delta, D = 1 + (8 alpha/3) q
+//   Q = 2q/(1+sqrt D) if D >= 0 else -3/(4 alpha)
+//   L(phi) = (S - 6 phi_c)/h^2 - Q
+// Sigma0 does not involve phi_c, so the Newton-Gauss-Seidel step of Sec. III.B is
+// the exact per-cell root: phi_c <- (S - h^2 (Q + f - cbar)) / 6.
+#include <algorithm>
+#include <cstring>
+
+#include "device_common.h"
+
+namespace vmg {
+
+// ---------------------------------------------------------------------------
+// Fused red-black sweep.  Colour of cell (i,j,k) = (i+j+k) & 1 (0 = red).
+// Red phase reads only phi^0 (old values, so same-colour edge neighbours are
+// taken from the snapshot); black phase reads phi^1 = phi^0 with the red cells
+// updated.  One block owns a TX x TY x zc brick and marches up z:
+//   * phi^0 is staged in LDS on a two-cell ring around the tile (3 planes),
+//   * the red phase runs on a one-cell ring (recomputing what neighbouring
+//     blocks own, so no block reads another block's output) and stores the
+//     full phi^1 plane (red computed, black copied) in LDS (3 planes),
+//   * the black phase runs on the tile and writes phi^2 once,
+//   * the next plane of phi^0 and delta (and f) is loaded into registers while
+//     the current planes are computed (software pipelining).
+// A sweep therefore reads phi^0 and delta (and f) once and writes phi^2 once.
+// ---------------------------------------------------------------------------
+struct SmoothArgs {
+    Geom g;
+    Coef c;
+    const double* pin;
+    double* pout;
+    const double* delta;
+    const double* f;      // may be null
+    const LevelScalars* sc;
+    int zc, tiles_x, tiles_y;
+};
+
+template <int TY, int DIR, bool HAS_F>
+__device__ __forceinline__ void smooth_brick(const SmoothArgs& a, const int x0, const int y0, const int z0,
+                                             const int z1) {
+    constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+    constexpr int NP2 = W2 * H2, NP1 = W1 * H1;
+    constexpr int NL2 = (NP2 + NT - 1) / NT, NL1 = (NP1 + NT - 1) / NT;
+    constexpr int RH = W1 / 2;        // red/black pairs per ring-1 row
+    constexpr int BH = TX / 2;        // black cells per interior row
+    __shared__ double P0[3][H2][W2];  // phi^0, ring 2, slot = z mod 3
+    __shared__ double P1[3][H1][W1];  // phi^1, ring 1
+    __shared__ double DL[3][H1][W1];  // delta, ring 1
+    __shared__ double FF[HAS_F ? 3 : 1][HAS_F ? H1 : 1][HAS_F ? W1 : 1];
+
+    const Geom& g = a.g;
+    const int tid = threadIdx.x;
+
+    const double h2 = g.h * g.h, inv_h4 = 1.0 / (h2 * h2);
+    const double cb = DIR ? 0.0 : a.sc->cbar;
+
+    // per-thread in-plane offsets of the ring-2 (phi) and ring-1 (delta, f) slots
+    int off2[NL2], off1[NL1];
+    bool ok2[NL2], ok1[NL1];
+#pragma unroll
+    for (int s = 0; s < NL2; ++s) {
+        const int e = tid + s * NT;
+        ok2[s] = false;
+        off2[s] = 0;
+        if (e < NP2) {
+            int gx = x0 - 2 + e % W2, gy = y0 - 2 + e / W2;
+            if (DIR) {
+                ok2[s] = gx >= -1 && gx <= g.n0 && gy >= -1 && gy <= g.n1;
+            } else {
+                gx = wrapi(gx, g.n0);
+                gy = wrapi(gy, g.n1);
+                ok2[s] = true;
+            }
+            off2[s] = (int)(g.off0 + gx + (int64_t)gy * g.sy);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NL1; ++s) {
+        const int e = tid + s * NT;
+        ok1[s] = false;
+        off1[s] = 0;
+        if (e < NP1) {
+            int gx = x0 - 1 + e % W1, gy = y0 - 1 + e / W1;
+            if (DIR) {
+                ok1[s] = gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1;
+            } else {
+                gx = wrapi(gx, g.n0);
+                gy = wrapi(gy, g.n1);
+                ok1[s] = true;
+            }
+            off1[s] = (int)(g.off0 + gx + (int64_t)gy * g.sy);
+        }
+    }
+    auto plane_z = [&](int t, bool& zok) -> int64_t {
+        int gz;
+        if (DIR) { gz = t; zok = t >= -1 && t <= g.n2; }
+        else { gz = wrapi(t, g.n2); zok = true; }
+        return (int64_t)gz * g.sz;
+    };
+    auto load_phi = [&](int t, double (&r)[NL2]) {
+        bool zok;
+        const int64_t zo = plane_z(t, zok);
+#pragma unroll
+        for (int s = 0; s < NL2; ++s) r[s] = (ok2[s] && zok && tid + s * NT < NP2) ? a.pin[zo + off2[s]] : 0.0;
+    };
+    auto load_r1 = [&](const double* src, int t, double (&r)[NL1]) {
+        bool zok;
+        const int64_t zo = plane_z(t, zok);
+        if (DIR) zok = t >= 0 && t < g.n2;
+#pragma unroll
+        for (int s = 0; s < NL1; ++s) r[s] = (ok1[s] && zok && tid + s * NT < NP1) ? src[zo + off1[s]] : 0.0;
+    };
+    auto store2 = [&](double* dst, const double (&r)[NL2]) {
+#pragma unroll
+        for (int s = 0; s < NL2; ++s)
+            if (tid + s * NT < NP2) dst[tid + s * NT] = r[s];
+    };
+    auto store1 = [&](double* dst, const double (&r)[NL1]) {
+#pragma unroll
+        for (int s = 0; s < NL1; ++s)
+            if (tid + s * NT < NP1) dst[tid + s * NT] = r[s];
+    };
+    auto slot = [](int z) { return (z + 3) % 3; };   // z >= -2
+
+    // prologue: phi^0 planes z0-2 .. z0, delta (and f) plane z0-1
+    {
+        double r2[NL2], r1[NL1];
+        for (int t = z0 - 2; t <= z0; ++t) {
+            load_phi(t, r2);
+            store2(&P0[slot(t)][0][0], r2);
+        }
+        load_r1(a.delta, z0 - 1, r1);
+        store1(&DL[slot(z0 - 1)][0][0], r1);
+        if (HAS_F) {
+            load_r1(a.f, z0 - 1, r1);
+            store1(&FF[slot(z0 - 1)][0][0], r1);
+        }
+    }
+    __syncthreads();
+
+    for (int t = z0; t <= z1 + 1; ++t) {
+        // ---- prefetch phi^0 plane t+1 and delta (f) plane t into registers ----
+        double nphi[NL2], ndl[NL1], nf[NL1];
+        const bool pf_phi = t + 1 <= z1 + 1, pf_dl = t <= z1;
+        if (pf_phi) load_phi(t + 1, nphi);
+        if (pf_dl) {
+            load_r1(a.delta, t, ndl);
+            if (HAS_F) load_r1(a.f, t, nf);
+        }
+        // ---- red phase on plane p = t-1, ring 1: P0 -> P1 ----------------------
+        {
+            const int p = t - 1;
+            const double(*Pm)[W2] = P0[slot(p - 1)];
+            const double(*Pc)[W2] = P0[slot(p)];
+            const double(*Pp)[W2] = P0[slot(p + 1)];
+            const double(*Dc)[W1] = DL[slot(p)];
+            double(*Q1)[W1] = P1[slot(p)];
+            const bool pzok = DIR ? (p >= 0 && p < g.n2) : true;
+            for (int e = tid; e < RH * H1; e += NT) {
+                const int r = e / RH, m = e - r * RH;
+                const int gy = y0 - 1 + r;
+                const int odd = (gy + p + 1) & 1;
+                const int lx = 2 * m + odd;            // red ring-1 column
+                const int lb = 2 * m + 1 - odd;        // black ring-1 column (copied)
+                const int gx = x0 - 1 + lx;
+                const int X = lx + 1, Y = r + 1;       // ring-2 coordinates
+                bool interior = true;
+                if (DIR) interior = pzok && gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1;
+                double val = Pc[Y][X];
+                if (interior) {
+                    Nb v;
+                    v.xm = Pc[Y][X - 1]; v.xp = Pc[Y][X + 1];
+                    v.ym = Pc[Y - 1][X]; v.yp = Pc[Y + 1][X];
+                    v.zm = Pm[Y][X];     v.zp = Pp[Y][X];
+                    v.xpyp = Pc[Y + 1][X + 1]; v.xmym = Pc[Y - 1][X - 1];
+                    v.xpym = Pc[Y - 1][X + 1]; v.xmyp = Pc[Y + 1][X - 1];
+                    v.xpzp = Pp[Y][X + 1]; v.xmzm = Pm[Y][X - 1];
+                    v.xpzm = Pm[Y][X + 1]; v.xmzp = Pp[Y][X - 1];
+                    v.ypzp = Pp[Y + 1][X]; v.ymzm = Pm[Y - 1][X];
+                    v.ypzm = Pm[Y + 1][X]; v.ymzp = Pp[Y - 1][X];
+                    double S;
+                    bool gd;
+                    const double Q = nl_root(v, Dc[r][lx], a.c, inv_h4, S, gd);
+                    const double fv = HAS_F ? FF[slot(p)][r][lx] : 0.0;
+                    val = (S - h2 * (Q + fv - cb)) * (1.0 / 6.0);
+                }
+                Q1[r][lx] = val;
+                Q1[r][lb] = Pc[Y][lb + 1];
+            }
+        }
+        __syncthreads();
+        // ---- black phase on plane p2 = t-2, tile interior: P1 -> phi^2 ----------
+        const int p2 = t - 2;
+        if (p2 >= z0) {
+            const double(*Rm)[W1] = P1[slot(p2 - 1)];
+            const double(*Rc)[W1] = P1[slot(p2)];
+            const double(*Rp)[W1] = P1[slot(p2 + 1)];
+            const double(*Dc)[W1] = DL[slot(p2)];
+            for (int e = tid; e < BH * TY; e += NT) {
+                const int r = e / BH, m = e - r * BH;
+                const int gy = y0 + r;
+                if (gy >= g.n1) continue;
+                const int xb = 2 * m + ((gy + p2 + 1) & 1);
+                const int xr = 2 * m + ((gy + p2) & 1);
+                const int64_t rowoff = g.off0 + (int64_t)gy * g.sy + (int64_t)p2 * g.sz + x0;
+                const int X = xb + 1, Y = r + 1;       // ring-1 coordinates
+                if (x0 + xb < g.n0) {
+                    Nb v;
+                    v.xm = Rc[Y][X - 1]; v.xp = Rc[Y][X + 1];
+                    v.ym = Rc[Y - 1][X]; v.yp = Rc[Y + 1][X];
+                    v.zm = Rm[Y][X];     v.zp = Rp[Y][X];
+                    v.xpyp = Rc[Y + 1][X + 1]; v.xmym = Rc[Y - 1][X - 1];
+                    v.xpym = Rc[Y - 1][X + 1]; v.xmyp = Rc[Y + 1][X - 1];
+                    v.xpzp = Rp[Y][X + 1]; v.xmzm = Rm[Y][X - 1];
+                    v.xpzm = Rm[Y][X + 1]; v.xmzp = Rp[Y][X - 1];
+                    v.ypzp = Rp[Y + 1][X]; v.ymzm = Rm[Y - 1][X];
+                    v.ypzm = Rm[Y + 1][X]; v.ymzp = Rp[Y - 1][X];
+                    double S;
+                    bool gd;
+                    const double Q = nl_root(v, Dc[Y][X], a.c, inv_h4, S, gd);
+                    const double fv = HAS_F ? FF[slot(p2)][Y][X] : 0.0;
+                    a.pout[rowoff + xb] = (S - h2 * (Q + fv - cb)) * (1.0 / 6.0);
+                }
+                if (x0 + xr < g.n0) a.pout[rowoff + xr] = Rc[Y][xr + 1];
+            }
+        }
+        // ---- commit the prefetched planes (slots not read in this iteration) ----
+        if (pf_phi) store2(&P0[slot(t + 1)][0][0], nphi);
+        if (pf_dl) {
+            store1(&DL[slot(t)][0][0], ndl);
+            if (HAS_F) store1(&FF[slot(t)][0][0], nf);
+        }
+        __syncthreads();
+    }
+}
+
+template <int TY, int DIR, bool HAS_F>
+__global__ void __launch_bounds__(NT) k_smooth(SmoothArgs a) {
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = b % a.tiles_x;
+    b /= a.tiles_x;
+    const int ty = b % a.tiles_y;
+    const int ch = b / a.tiles_y;
+    const int z0 = ch * a.zc;
+    if (z0 >= a.g.n2) return;
+    smooth_brick<TY, DIR, HAS_F>(a, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
+}
+
+// Persistent sweep over a (grid, tile x, tile y, z chunk) work list: every
+// Dirichlet grid of a batch at one level in one launch.  `proto` carries the
+// pooled level buffers and coefficients; geoms[w.x] locates grid w.x in them.
+template <int TY, bool HAS_F>
+__global__ void __launch_bounds__(NT) k_smooth_batch(SmoothArgs proto, const Geom* __restrict__ geoms,
+                                                     const int4* __restrict__ items, int nitems) {
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int4 w = items[it];
+        SmoothArgs a = proto;
+        a.g = geoms[w.x];
+        const int z0 = w.w * a.zc;
+        smooth_brick<TY, 1, HAS_F>(a, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
+    }
+}
+
+// residual d = L(phi) + cbar - f at one cell; also returns Q and the guard flag
+// ---------------------------------------------------------------------------
+// residual + restriction (8-child average of phi and d) in one pass
+// ---------------------------------------------------------------------------
+template <int DIR>
+__global__ void __launch_bounds__(NT) k_residual_restrict(Geom gf, Geom gc, Coef c,
+                                                          const double* __restrict__ phi,
+                                                          const double* __restrict__ delta,
+                                                          const double* __restrict__ f,
+                                                          const LevelScalars* sc, double* phic,
+                                                          double* phiold_c, double* rd_c,
+                                                          double* partials) {
+    double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
+    const double cb = DIR ? 0.0 : sc->cbar;
+    const double inv_h2 = 1.0 / (gf.h * gf.h), inv_h4 = inv_h2 * inv_h2;
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < gc.ncell;
+         e += (int64_t)gridDim.x * NT) {
+        int I, J, K;
+        decode(gc, e, I, J, K);
+        double sphi = 0.0, sd = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < 8; ++ch) {
+            const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
+            double Q, pc, fv;
+            bool gd;
+            const double d = cell_residual<DIR>(gf, c, phi, delta, f, cb, i, j, k, inv_h2, inv_h4,
+                                                Q, gd, pc, fv);
+            acc[R_D2] += d * d;
+            acc[R_D1] += d;
+            acc[R_Q] += Q;
+            acc[R_F] += fv;
+            acc[R_PHI] += pc;
+            acc[R_GUARD] += gd ? 1.0 : 0.0;
+            acc[R_NONFIN] += isfinite(d) ? 0.0 : 1.0;
+            sphi += pc;
+            sd += d;
+        }
+        const int64_t co = cell_index(gc, I, J, K);
+        phic[co] = 0.125 * sphi;
+        phiold_c[co] = 0.125 * sphi;
+        rd_c[co] = 0.125 * sd;
+    }
+    block_store_partials(acc, partials);
+}
+
+template <int DIR>
+__global__ void __launch_bounds__(NT) k_residual_norm(Geom g, Coef c, const double* __restrict__ phi,
+                                                      const double* __restrict__ delta,
+                                                      const double* __restrict__ f,
+                                                      const LevelScalars* sc, double* d_out,
+                                                      double* partials) {
+    double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
+    const double cb = DIR ? 0.0 : sc->cbar;
+    const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < g.ncell;
+         e += (int64_t)gridDim.x * NT) {
+        int i, j, k;
+        decode(g, e, i, j, k);
+        double Q, pc, fv;
+        bool gd;
+        const double d = cell_residual<DIR>(g, c, phi, delta, f, cb, i, j, k, inv_h2, inv_h4, Q, gd,
+                                            pc, fv);
+        acc[R_D2] += d * d;
+        acc[R_D1] += d;
+        acc[R_Q] += Q;
+        acc[R_F] += fv;
+        acc[R_PHI] += pc;
+        acc[R_GUARD] += gd ? 1.0 : 0.0;
+        acc[R_NONFIN] += isfinite(d) ? 0.0 : 1.0;
+        if (d_out) d_out[e] = d;   // caller layout: unpadded, x fastest
+    }
+    block_store_partials(acc, partials);
+}
+
+// f^H = L^H(R phi) - R d   (coarse FAS right-hand side, Sec. III.C)
+template <int DIR>
+__global__ void __launch_bounds__(NT) k_fas_rhs(Geom g, Coef c, const double* __restrict__ phi,
+                                                const double* __restrict__ delta,
+                                                const double* __restrict__ rd, double* f,
+                                                double* partials) {
+    double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
+    const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < g.ncell;
+         e += (int64_t)gridDim.x * NT) {
+        int i, j, k;
+        decode(g, e, i, j, k);
+        double Q, pc, fv;
+        bool gd;
+        const double L = cell_residual<DIR>(g, c, phi, delta, nullptr, 0.0, i, j, k, inv_h2, inv_h4,
+                                            Q, gd, pc, fv);
+        const int64_t gi = cell_index(g, i, j, k);
+        const double fh = L - rd[gi];
+        f[gi] = fh;
+        acc[R_Q] += Q;
+        acc[R_F] += fh;
+    }
+    block_store_partials(acc, partials);
+}
+
+__global__ void __launch_bounds__(NT) k_finalize(const double* __restrict__ partials, int nblocks,
+                                                 int64_t ncell, int periodic, int mode,
+                                                 LevelScalars* sc, NormOut* out, LevelScalars* inner) {
+    __shared__ double red[NT / 64][R_NSLOT];
+    double acc[R_NSLOT];
+#pragma unroll
+    for (int k = 0; k < R_NSLOT; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += NT) {
+#pragma unroll
+        for (int k = 0; k < R_NSLOT; ++k) acc[k] += partials[(int64_t)b * R_NSLOT + k];
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < R_NSLOT; ++k) {
+        const double s = wave_sum(acc[k]);
+        if (lane == 0) red[w][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double tot[R_NSLOT];
+    for (int k = 0; k < R_NSLOT; ++k) {
+        tot[k] = 0.0;
+        for (int q = 0; q < NT / 64; ++q) tot[k] += red[q][k];
+    }
+    const double N = (double)ncell;
+    if (mode == 1) {
+        if (periodic) sc->cbar = (tot[R_F] + tot[R_Q]) / N;
+        return;
+    }
+    double d2 = tot[R_D2];
+    double cb = 0.0;
+    if (periodic) {
+        const double old = sc->cbar;
+        cb = (tot[R_F] + tot[R_Q]) / N;
+        const double del = cb - old;
+        d2 = tot[R_D2] + 2.0 * del * tot[R_D1] + N * del * del;
+        sc->cbar = cb;
+    }
+    if (mode == 2 && inner) inner->cbar = periodic ? -tot[R_D1] / N : 0.0;
+    if (out) {
+        out->rms = sqrt(fmax(d2, 0.0) / N);
+        out->cbar = cb;
+        out->mean_phi = tot[R_PHI] / N;
+        out->n_guard = tot[R_GUARD];
+        out->n_nonfinite = tot[R_NONFIN];
+        out->sum_q = tot[R_Q];
+    }
+}
+
+// phi^h += P(phi^H - phiold^H): cell-centred trilinear, weights 3/4 and 1/4 per axis
+template <int DIR>
+__global__ void __launch_bounds__(NT) k_prolong(Geom gf, Geom gc, double* __restrict__ phif,
+                                                const double* __restrict__ phic,
+                                                const double* __restrict__ oldc) {
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < gf.ncell;
+         e += (int64_t)gridDim.x * NT) {
+        int i, j, k;
+        decode(gf, e, i, j, k);
+        const int I = i >> 1, J = j >> 1, K = k >> 1;
+        const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            int ii = I + ((q & 1) ? si : 0), jj = J + ((q & 2) ? sj : 0), kk = K + ((q & 4) ? sk : 0);
+            const double w = ((q & 1) ? 0.25 : 0.75) * ((q & 2) ? 0.25 : 0.75) * ((q & 4) ? 0.25 : 0.75);
+            double corr;
+            if (DIR) {
+                if (ii < 0 || ii >= gc.n0 || jj < 0 || jj >= gc.n1 || kk < 0 || kk >= gc.n2) {
+                    corr = 0.0;
+                } else {
+                    const int64_t ci = cell_index(gc, ii, jj, kk);
+                    corr = phic[ci] - oldc[ci];
+                }
+            } else {
+                ii = ii < 0 ? ii + gc.n0 : (ii >= gc.n0 ? ii - gc.n0 : ii);
+                jj = jj < 0 ? jj + gc.n1 : (jj >= gc.n1 ? jj - gc.n1 : jj);
+                kk = kk < 0 ? kk + gc.n2 : (kk >= gc.n2 ? kk - gc.n2 : kk);
+                const int64_t ci = cell_index(gc, ii, jj, kk);
+                corr = phic[ci] - oldc[ci];
+            }
+            acc += w * corr;
+        }
+        phif[cell_index(gf, i, j, k)] += acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarsest level: whole grid in LDS, red-black sweeps (same snapshot schedule)
+// ---------------------------------------------------------------------------
+constexpr int CMAX = 10 * 10 * 10;   // storage of a padded 8^3 grid
+
+// phi (and, if given, phi_also) receive the result; storage starts at g.base.
+template <int DIR>
+__device__ __forceinline__ void coarse_solve_body(Geom g, const Coef& c, double* phi, double* phi_also,
+                                                  const double* delta, const double* f, int sweeps) {
+    __shared__ double sphi[CMAX], sdel[CMAX], sf[CMAX];
+    __shared__ double red[NT / 64];
+    const int tid = threadIdx.x;
+    phi += g.base;
+    delta += g.base;
+    if (f) f += g.base;
+    if (phi_also) phi_also += g.base;
+    for (int64_t e = tid; e < g.nstore; e += NT) {
+        sphi[e] = phi[e];
+        sdel[e] = delta[e];
+        sf[e] = f ? f[e] : 0.0;
+    }
+    __syncthreads();
+    Geom lg = g;   // same indexing on the LDS copy
+    lg.off0 -= g.base;
+    lg.base = 0;
+    const double h2 = g.h * g.h, inv_h4 = 1.0 / (h2 * h2);
+    double sumf = 0.0;
+    if (!DIR) {
+        double a = 0.0;
+        for (int64_t e = tid; e < g.ncell; e += NT) {
+            int i, j, k;
+            decode(g, e, i, j, k);
+            a += sf[cell_index(lg, i, j, k)];
+        }
+        a = wave_sum(a);
+        if ((tid & 63) == 0) red[tid >> 6] = a;
+        __syncthreads();
+        for (int q = 0; q < NT / 64; ++q) sumf += red[q];
+        __syncthreads();
+    }
+    const int per = (int)((g.ncell + NT - 1) / NT);   // <= 2 for 8^3
+    for (int s = 0; s < sweeps; ++s) {
+        double cb = 0.0;
+        if (!DIR) {
+            double a = 0.0;
+            for (int64_t e = tid; e < g.ncell; e += NT) {
+                int i, j, k;
+                decode(g, e, i, j, k);
+                Nb v;
+                gather_nb<DIR>(lg, sphi, i, j, k, v);
+                double S;
+                bool gd;
+                a += nl_root(v, sdel[cell_index(lg, i, j, k)], c, inv_h4, S, gd);
+            }
+            a = wave_sum(a);
+            if ((tid & 63) == 0) red[tid >> 6] = a;
+            __syncthreads();
+            double sq = 0.0;
+            for (int q = 0; q < NT / 64; ++q) sq += red[q];
+            cb = (sumf + sq) / (double)g.ncell;
+            __syncthreads();
+        }
+        for (int colour = 0; colour < 2; ++colour) {
+            double nv[2];
+            int64_t ni[2];
+            for (int q = 0; q < per && q < 2; ++q) {
+                ni[q] = -1;
+                const int64_t e = tid + (int64_t)q * NT;
+                if (e >= g.ncell) continue;
+                int i, j, k;
+                decode(g, e, i, j, k);
+                if (((i + j + k) & 1) != colour) continue;
+                Nb v;
+                gather_nb<DIR>(lg, sphi, i, j, k, v);
+                const int64_t li = cell_index(lg, i, j, k);
+                double S;
+                bool gd;
+                const double Q = nl_root(v, sdel[li], c, inv_h4, S, gd);
+                nv[q] = (S - h2 * (Q + sf[li] - cb)) * (1.0 / 6.0);
+                ni[q] = li;
+            }
+            __syncthreads();
+            for (int q = 0; q < per && q < 2; ++q)
+                if (tid + (int64_t)q * NT < g.ncell && ni[q] >= 0) sphi[ni[q]] = nv[q];
+            __syncthreads();
+        }
+    }
+    for (int64_t e = tid; e < g.ncell; e += NT) {
+        int i, j, k;
+        decode(g, e, i, j, k);
+        const int64_t li = cell_index(lg, i, j, k);
+        phi[li] = sphi[li];
+        if (phi_also) phi_also[li] = sphi[li];
+    }
+    __syncthreads();
+}
+
+template <int DIR>
+__global__ void __launch_bounds__(NT) k_coarse_solve(Geom g, Coef c, double* phi, const double* delta,
+                                                     const double* f, int sweeps) {
+    coarse_solve_body<DIR>(g, c, phi, nullptr, delta, f, sweeps);
+}
+
+// ---------------------------------------------------------------------------
+// utilities
+// ---------------------------------------------------------------------------
+__global__ void k_restrict_plain(Geom gf, Geom gc, const double* uf, double* uc) {
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < gc.ncell;
+         e += (int64_t)gridDim.x * NT) {
+        int I, J, K;
+        decode(gc, e, I, J, K);
+        double s = 0.0;
+        for (int ch = 0; ch < 8; ++ch)
+            s += uf[cell_index(gf, 2 * I + (ch & 1), 2 * J + ((ch >> 1) & 1), 2 * K + (ch >> 2))];
+        uc[cell_index(gc, I, J, K)] = 0.125 * s;
+    }
+}
+
+// coarse Dirichlet ghosts: mean of the fine ghost cells inside each coarse ghost cell
+__global__ void k_restrict_ghosts(Geom gf, Geom gc, const double* uf, double* uc) {
+    const int64_t tot = (int64_t)(gc.n0 + 2) * (gc.n1 + 2) * (gc.n2 + 2);
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < tot; e += (int64_t)gridDim.x * NT) {
+        const int I = (int)(e % (gc.n0 + 2)) - 1;
+        const int J = (int)((e / (gc.n0 + 2)) % (gc.n1 + 2)) - 1;
+        const int K = (int)(e / ((int64_t)(gc.n0 + 2) * (gc.n1 + 2))) - 1;
+        const int out = (I < 0 || I >= gc.n0) + (J < 0 || J >= gc.n1) + (K < 0 || K >= gc.n2);
+        if (out == 0 || out == 3) continue;
+        double s = 0.0;
+        int cnt = 0;
+        for (int ch = 0; ch < 8; ++ch) {
+            const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
+            if (i < -1 || i > gf.n0 || j < -1 || j > gf.n1 || k < -1 || k > gf.n2) continue;
+            const int o = (i < 0 || i >= gf.n0) + (j < 0 || j >= gf.n1) + (k < 0 || k >= gf.n2);
+            if (o == 0 || o == 3) continue;
+            s += uf[cell_index(gf, i, j, k)];
+            ++cnt;
+        }
+        uc[cell_index(gc, I, J, K)] = cnt ? s / cnt : 0.0;
+    }
+}
+
+__global__ void k_copy_in(Geom g, const double* src, double* dst) {
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < g.ncell; e += (int64_t)gridDim.x * NT) {
+        int i, j, k;
+        decode(g, e, i, j, k);
+        dst[cell_index(g, i, j, k)] = src[e];
+    }
+}
+
+__global__ void k_copy_out(Geom g, const double* src, double* dst) {
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < g.ncell; e += (int64_t)gridDim.x * NT) {
+        int i, j, k;
+        decode(g, e, i, j, k);
+        dst[e] = src[cell_index(g, i, j, k)];
+    }
+}
+
+__device__ __forceinline__ int64_t ghost_count_dev(int n0, int n1, int n2) {
+    return 2 * ((int64_t)n1 * n2 + (int64_t)n0 * n2 + (int64_t)n0 * n1) + 4 * ((int64_t)n0 + n1 + n2);
+}
+
+// Decode a compact ghost index into cell coordinates (i, j, k) in [-1, n].
+__device__ void ghost_coords(int n0, int n1, int n2, int64_t q, int& i, int& j, int& k) {
+    const int64_t fx = (int64_t)n1 * n2, fy = (int64_t)n0 * n2, fz = (int64_t)n0 * n1;
+    if (q < 2 * fx) { const int s = (int)(q / fx); const int64_t r = q % fx;
+        i = s ? n0 : -1; j = (int)(r % n1); k = (int)(r / n1); return; }
+    q -= 2 * fx;
+    if (q < 2 * fy) { const int s = (int)(q / fy); const int64_t r = q % fy;
+        j = s ? n1 : -1; i = (int)(r % n0); k = (int)(r / n0); return; }
+    q -= 2 * fy;
+    if (q < 2 * fz) { const int s = (int)(q / fz); const int64_t r = q % fz;
+        k = s ? n2 : -1; i = (int)(r % n0); j = (int)(r / n0); return; }
+    q -= 2 * fz;
+    if (q < 4 * (int64_t)n0) { const int e = (int)(q / n0);
+        i = (int)(q % n0); j = (e & 1) ? n1 : -1; k = (e & 2) ? n2 : -1; return; }
+    q -= 4 * (int64_t)n0;
+    if (q < 4 * (int64_t)n1) { const int e = (int)(q / n1);
+        j = (int)(q % n1); i = (e & 1) ? n0 : -1; k = (e & 2) ? n2 : -1; return; }
+    q -= 4 * (int64_t)n1;
+    const int e = (int)(q / n2);
+    k = (int)(q % n2); i = (e & 1) ? n0 : -1; j = (e & 2) ? n1 : -1;
+}
+
+__global__ void k_ghost_in(Geom g, const double* ghost, double* dst, int64_t count) {
+    for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < count; q += (int64_t)gridDim.x * NT) {
+        int i, j, k;
+        ghost_coords(g.n0, g.n1, g.n2, q, i, j, k);
+        dst[cell_index(g, i, j, k)] = ghost[q];
+    }
+}
+
+__global__ void k_ghost_fill(const double* parent, int np0, int np1, int np2, double H, int n0,
+                             int n1, int n2, double h, int o0, int o1, int o2, double* ghost,
+                             int64_t count) {
+    for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < count; q += (int64_t)gridDim.x * NT) {
+        int c[3];
+        ghost_coords(n0, n1, n2, q, c[0], c[1], c[2]);
+        const int o[3] = {o0, o1, o2}, np[3] = {np0, np1, np2};
+        int base[3];
+        double t[3];
+        for (int d = 0; d < 3; ++d) {
+            const double u = (o[d] + c[d] + 0.5) * h / H - 0.5;   // parent index space
+            const double fl = floor(u);
+            base[d] = (int)fl;
+            t[d] = u - fl;
+        }
+        double v = 0.0;
+        for (int m = 0; m < 8; ++m) {
+            const int dx = m & 1, dy = (m >> 1) & 1, dz = m >> 2;
+            const double w = (dx ? t[0] : 1.0 - t[0]) * (dy ? t[1] : 1.0 - t[1]) * (dz ? t[2] : 1.0 - t[2]);
+            const int I = ((base[0] + dx) % np[0] + np[0]) % np[0];
+            const int J = ((base[1] + dy) % np[1] + np[1]) % np[1];
+            const int K = ((base[2] + dz) % np[2] + np[2]) % np[2];
+            v += w * parent[((int64_t)K * np1 + J) * np0 + I];
+        }
+        ghost[q] = v;
+    }
+}
+
+__global__ void k_gauge(Geom g, double* phi, const NormOut* no) {
+    const double m = no->mean_phi;
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < g.ncell; e += (int64_t)gridDim.x * NT) {
+        int i, j, k;
+        decode(g, e, i, j, k);
+        phi[cell_index(g, i, j, k)] -= m;
+    }
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) p[e] = v;
+}
+
+__global__ void __launch_bounds__(NT) k_check_finite(const double* p, int64_t n, double* partials) {
+    double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT)
+        acc[R_NONFIN] += isfinite(p[e]) ? 0.0 : 1.0;
+    block_store_partials(acc, partials);
+}
+
+// ---------------------------------------------------------------------------
+// Batched Dirichlet kernels: one launch covers every grid of a level.  The
+// grids of a level share pooled buffers; geoms[k] locates grid k in them and
+// each block handles items[blockIdx.x] = (k, first cell) = 256 cells of grid k.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_rr_batch(const Geom* __restrict__ gfs, const Geom* __restrict__ gcs,
+                                                 const int2* __restrict__ items, Coef c,
+                                                 const double* __restrict__ phi, const double* __restrict__ delta,
+                                                 const double* __restrict__ f, double* phic, double* phiold_c,
+                                                 double* rd_c) {
+    const int2 w = items[blockIdx.x];
+    const Geom gf = gfs[w.x], gc = gcs[w.x];
+    const int64_t e = (int64_t)w.y + threadIdx.x;
+    if (e >= gc.ncell) return;
+    const double inv_h2 = 1.0 / (gf.h * gf.h), inv_h4 = inv_h2 * inv_h2;
+    int I, J, K;
+    decode(gc, e, I, J, K);
+    double sphi = 0.0, sd = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) {
+        const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
+        double Q, pc, fv;
+        bool gd;
+        sd += cell_residual<1>(gf, c, phi, delta, f, 0.0, i, j, k, inv_h2, inv_h4, Q, gd, pc, fv);
+        sphi += pc;
+    }
+    const int64_t co = cell_index(gc, I, J, K);
+    phic[co] = 0.125 * sphi;
+    phiold_c[co] = 0.125 * sphi;
+    rd_c[co] = 0.125 * sd;
+}
+
+__global__ void __launch_bounds__(NT) k_fas_batch(const Geom* __restrict__ gs, const int2* __restrict__ items,
+                                                  Coef c, const double* __restrict__ phi,
+                                                  const double* __restrict__ delta, const double* __restrict__ rd,
+                                                  double* f) {
+    const int2 w = items[blockIdx.x];
+    const Geom g = gs[w.x];
+    const int64_t e = (int64_t)w.y + threadIdx.x;
+    if (e >= g.ncell) return;
+    const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+    int i, j, k;
+    decode(g, e, i, j, k);
+    double Q, pc, fv;
+    bool gd;
+    const double L = cell_residual<1>(g, c, phi, delta, nullptr, 0.0, i, j, k, inv_h2, inv_h4, Q, gd, pc, fv);
+    const int64_t gi = cell_index(g, i, j, k);
+    f[gi] = L - rd[gi];
+}
+
+__global__ void __launch_bounds__(NT) k_prolong_batch(const Geom* __restrict__ gfs, const Geom* __restrict__ gcs,
+                                                      const int2* __restrict__ items, double* __restrict__ phif,
+                                                      const double* __restrict__ phic,
+                                                      const double* __restrict__ oldc) {
+    const int2 w = items[blockIdx.x];
+    const Geom gf = gfs[w.x], gc = gcs[w.x];
+    const int64_t e = (int64_t)w.y + threadIdx.x;
+    if (e >= gf.ncell) return;
+    int i, j, k;
+    decode(gf, e, i, j, k);
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int ii = I + ((q & 1) ? si : 0), jj = J + ((q & 2) ? sj : 0), kk = K + ((q & 4) ? sk : 0);
+        const double wq = ((q & 1) ? 0.25 : 0.75) * ((q & 2) ? 0.25 : 0.75) * ((q & 4) ? 0.25 : 0.75);
+        if (ii < 0 || ii >= gc.n0 || jj < 0 || jj >= gc.n1 || kk < 0 || kk >= gc.n2) continue;
+        const int64_t ci = cell_index(gc, ii, jj, kk);
+        acc += wq * (phic[ci] - oldc[ci]);
+    }
+    phif[cell_index(gf, i, j, k)] += acc;
+}
+
+// residual norm partials per block (grid k's blocks are contiguous)
+__global__ void __launch_bounds__(NT) k_norm_batch(const Geom* __restrict__ gs, const int2* __restrict__ items,
+                                                   Coef c, const double* __restrict__ phi,
+                                                   const double* __restrict__ delta, const double* __restrict__ f,
+                                                   double* partials) {
+    double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
+    const int2 w = items[blockIdx.x];
+    const Geom g = gs[w.x];
+    const int64_t e = (int64_t)w.y + threadIdx.x;
+    if (e < g.ncell) {
+        const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+        int i, j, k;
+        decode(g, e, i, j, k);
+        double Q, pc, fv;
+        bool gd;
+        const double d = cell_residual<1>(g, c, phi, delta, f, 0.0, i, j, k, inv_h2, inv_h4, Q, gd, pc, fv);
+        acc[R_D2] = d * d;
+        acc[R_D1] = d;
+        acc[R_Q] = Q;
+        acc[R_F] = fv;
+        acc[R_PHI] = pc;
+        acc[R_GUARD] = gd ? 1.0 : 0.0;
+        acc[R_NONFIN] = isfinite(d) ? 0.0 : 1.0;
+    }
+    block_store_partials(acc, partials);
+}
+
+// one block per grid: sum its blocks' partials [first[k], first[k+1]) in a fixed order
+__global__ void __launch_bounds__(NT) k_finalize_batch(const double* __restrict__ partials,
+                                                       const int* __restrict__ first,
+                                                       const Geom* __restrict__ gs, NormOut* out) {
+    __shared__ double red[NT / 64][R_NSLOT];
+    const int k = blockIdx.x;
+    double acc[R_NSLOT];
+#pragma unroll
+    for (int q = 0; q < R_NSLOT; ++q) acc[q] = 0.0;
+    for (int b = first[k] + threadIdx.x; b < first[k + 1]; b += NT)
+#pragma unroll
+        for (int q = 0; q < R_NSLOT; ++q) acc[q] += partials[(int64_t)b * R_NSLOT + q];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < R_NSLOT; ++q) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0) red[wv][q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double tot[R_NSLOT];
+    for (int q = 0; q < R_NSLOT; ++q) {
+        tot[q] = 0.0;
+        for (int m = 0; m < NT / 64; ++m) tot[q] += red[m][q];
+    }
+    const double N = (double)gs[k].ncell;
+    out[k].rms = sqrt(fmax(tot[R_D2], 0.0) / N);
+    out[k].cbar = 0.0;
+    out[k].mean_phi = tot[R_PHI] / N;
+    out[k].n_guard = tot[R_GUARD];
+    out[k].n_nonfinite = tot[R_NONFIN];
+    out[k].sum_q = tot[R_Q];
+}
+
+// coarsest levels of several grids, one block per grid; the result goes to both
+// ping-pong buffers so that either parity reads it
+__global__ void __launch_bounds__(NT) k_coarse_batch(const Geom* __restrict__ gs, Coef c, double* phi0,
+                                                     double* phi1, const double* delta, const double* f,
+                                                     int sweeps) {
+    coarse_solve_body<1>(gs[blockIdx.x], c, phi0, phi1, delta, f, sweeps);
+}
+
+__global__ void k_copy_in_batch(const Geom* __restrict__ gs, const int64_t* __restrict__ uoff,
+                                const int2* __restrict__ items, const double* __restrict__ src, double* dst0,
+                                double* dst1) {
+    const int2 w = items[blockIdx.x];
+    const Geom g = gs[w.x];
+    const int64_t e = (int64_t)w.y + threadIdx.x;
+    if (e >= g.ncell) return;
+    int i, j, k;
+    decode(g, e, i, j, k);
+    const double v = src[uoff[w.x] + e];
+    const int64_t gi = cell_index(g, i, j, k);
+    dst0[gi] = v;
+    if (dst1) dst1[gi] = v;
+}
+
+__global__ void k_copy_out_batch(const Geom* __restrict__ gs, const int64_t* __restrict__ uoff,
+                                 const int2* __restrict__ items, const double* __restrict__ src, double* dst) {
+    const int2 w = items[blockIdx.x];
+    const Geom g = gs[w.x];
+    const int64_t e = (int64_t)w.y + threadIdx.x;
+    if (e >= g.ncell) return;
+    int i, j, k;
+    decode(g, e, i, j, k);
+    dst[uoff[w.x] + e] = src[cell_index(g, i, j, k)];
+}
+
+// items here run over each grid's ghost values (compact order)
+__global__ void k_ghost_in_batch(const Geom* __restrict__ gs, const int64_t* __restrict__ goff,
+                                 const int2* __restrict__ items, const double* __restrict__ ghost, double* dst0,
+                                 double* dst1) {
+    const int2 w = items[blockIdx.x];
+    const Geom g = gs[w.x];
+    const int64_t q = (int64_t)w.y + threadIdx.x;
+    if (q >= ghost_count_dev(g.n0, g.n1, g.n2)) return;
+    int i, j, k;
+    ghost_coords(g.n0, g.n1, g.n2, q, i, j, k);
+    const double v = ghost[goff[w.x] + q];
+    const int64_t gi = cell_index(g, i, j, k);
+    dst0[gi] = v;
+    dst1[gi] = v;
+}
+
+__global__ void k_restrict_plain_batch(const Geom* __restrict__ gfs, const Geom* __restrict__ gcs,
+                                       const int2* __restrict__ items, const double* __restrict__ uf, double* uc) {
+    const int2 w = items[blockIdx.x];
+    const Geom gf = gfs[w.x], gc = gcs[w.x];
+    const int64_t e = (int64_t)w.y + threadIdx.x;
+    if (e >= gc.ncell) return;
+    int I, J, K;
+    decode(gc, e, I, J, K);
+    double s = 0.0;
+    for (int ch = 0; ch < 8; ++ch)
+        s += uf[cell_index(gf, 2 * I + (ch & 1), 2 * J + ((ch >> 1) & 1), 2 * K + (ch >> 2))];
+    uc[cell_index(gc, I, J, K)] = 0.125 * s;
+}
+
+// items run over each coarse grid's padded storage; writes the coarse ghost shell
+__global__ void k_restrict_ghosts_batch(const Geom* __restrict__ gfs, const Geom* __restrict__ gcs,
+                                        const int2* __restrict__ items, const double* __restrict__ uf,
+                                        double* uc0, double* uc1, double* uc2) {
+    const int2 w = items[blockIdx.x];
+    const Geom gf = gfs[w.x], gc = gcs[w.x];
+    const int64_t e = (int64_t)w.y + threadIdx.x;
+    if (e >= gc.nstore) return;
+    const int I = (int)(e % (gc.n0 + 2)) - 1;
+    const int J = (int)((e / (gc.n0 + 2)) % (gc.n1 + 2)) - 1;
+    const int K = (int)(e / ((int64_t)(gc.n0 + 2) * (gc.n1 + 2))) - 1;
+    const int out = (I < 0 || I >= gc.n0) + (J < 0 || J >= gc.n1) + (K < 0 || K >= gc.n2);
+    if (out == 0 || out == 3) return;
+    double s = 0.0;
+    int cnt = 0;
+    for (int ch = 0; ch < 8; ++ch) {
+        const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
+        if (i < -1 || i > gf.n0 || j < -1 || j > gf.n1 || k < -1 || k > gf.n2) continue;
+        const int o = (i < 0 || i >= gf.n0) + (j < 0 || j >= gf.n1) + (k < 0 || k >= gf.n2);
+        if (o == 0 || o == 3) continue;
+        s += uf[cell_index(gf, i, j, k)];
+        ++cnt;
+    }
+    const double v = cnt ? s / cnt : 0.0;
+    const int64_t ci = cell_index(gc, I, J, K);
+    uc0[ci] = v;
+    uc1[ci] = v;
+    uc2[ci] = v;
+}
+
+__global__ void __launch_bounds__(NT) k_check_finite_batch(const Geom* __restrict__ gs,
+                                                           const int64_t* __restrict__ uoff,
+                                                           const int2* __restrict__ items,
+                                                           const double* __restrict__ src, double* partials) {
+    double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
+    const int2 w = items[blockIdx.x];
+    const Geom g = gs[w.x];
+    const int64_t e = (int64_t)w.y + threadIdx.x;
+    if (e < g.ncell) acc[R_NONFIN] = isfinite(src[uoff[w.x] + e]) ? 0.0 : 1.0;
+    block_store_partials(acc, partials);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int partial_blocks_for(int64_t ncell) { return grid_for(ncell, MAX_RED_BLOCKS); }
+
+int64_t ghost_count(int n0, int n1, int n2) {
+    return 2 * ((int64_t)n1 * n2 + (int64_t)n0 * n2 + (int64_t)n0 * n1) + 4 * ((int64_t)n0 + n1 + n2);
+}
+
+template <int TY, int DIR>
+static hipError_t smooth_launch(const SmoothArgs& a, hipStream_t s) {
+    const int chunks = (a.g.n2 + a.zc - 1) / a.zc;
+    const int nb = a.tiles_x * a.tiles_y * chunks;
+    if (a.f)
+        hipLaunchKernelGGL((k_smooth<TY, DIR, true>), dim3(nb), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_smooth<TY, DIR, false>), dim3(nb), dim3(NT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth(const Geom& g, const Coef& c, const double* pin, double* pout,
+                         const double* delta, const double* f, const LevelScalars* sc,
+                         SmoothCfg cfg, hipStream_t s) {
+    SmoothArgs a;
+    a.g = g; a.c = c; a.pin = pin; a.pout = pout; a.delta = delta; a.f = f; a.sc = sc;
+    a.zc = cfg.zc > 0 ? cfg.zc : 16;
+    a.tiles_x = (g.n0 + TX - 1) / TX;
+    const int ty = cfg.ty;
+    a.tiles_y = (g.n1 + ty - 1) / ty;
+    if (g.dir) {
+        if (ty == 4) return smooth_launch<4, 1>(a, s);
+        if (ty == 16) return smooth_launch<16, 1>(a, s);
+        return smooth_launch<8, 1>(a, s);
+    }
+    if (ty == 4) return smooth_launch<4, 0>(a, s);
+    if (ty == 16) return smooth_launch<16, 0>(a, s);
+    return smooth_launch<8, 0>(a, s);
+}
+
+hipError_t launch_residual_restrict(const Geom& gf, const Geom& gc, const Coef& c,
+                                    const double* phi, const double* delta, const double* f,
+                                    const LevelScalars* sc, double* phic, double* phiold_c,
+                                    double* rd_c, double* partials, int* nblocks_out, hipStream_t s) {
+    const int nb = grid_for(gc.ncell, MAX_RED_BLOCKS);
+    if (gf.dir)
+        hipLaunchKernelGGL(k_residual_restrict<1>, dim3(nb), dim3(NT), 0, s, gf, gc, c, phi, delta, f,
+                           sc, phic, phiold_c, rd_c, partials);
+    else
+        hipLaunchKernelGGL(k_residual_restrict<0>, dim3(nb), dim3(NT), 0, s, gf, gc, c, phi, delta, f,
+                           sc, phic, phiold_c, rd_c, partials);
+    *nblocks_out = nb;
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_norm(const Geom& g, const Coef& c, const double* phi,
+                                const double* delta, const double* f, const LevelScalars* sc,
+                                double* d_out, double* partials, int* nblocks_out, hipStream_t s) {
+    const int nb = grid_for(g.ncell, MAX_RED_BLOCKS);
+    if (g.dir)
+        hipLaunchKernelGGL(k_residual_norm<1>, dim3(nb), dim3(NT), 0, s, g, c, phi, delta, f, sc, d_out,
+                           partials);
+    else
+        hipLaunchKernelGGL(k_residual_norm<0>, dim3(nb), dim3(NT), 0, s, g, c, phi, delta, f, sc, d_out,
+                           partials);
+    *nblocks_out = nb;
+    return hipGetLastError();
+}
+
+hipError_t launch_fas_rhs(const Geom& g, const Coef& c, const double* phi, const double* delta,
+                          const double* rd, double* f, double* partials, int* nblocks_out,
+                          hipStream_t s) {
+    const int nb = grid_for(g.ncell, MAX_RED_BLOCKS);
+    if (g.dir)
+        hipLaunchKernelGGL(k_fas_rhs<1>, dim3(nb), dim3(NT), 0, s, g, c, phi, delta, rd, f, partials);
+    else
+        hipLaunchKernelGGL(k_fas_rhs<0>, dim3(nb), dim3(NT), 0, s, g, c, phi, delta, rd, f, partials);
+    *nblocks_out = nb;
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* partials, int nblocks, int64_t ncell, int periodic,
+                           int mode, LevelScalars* sc, NormOut* out, hipStream_t s, LevelScalars* inner) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NT), 0, s, partials, nblocks, ncell, periodic, mode,
+                       sc, out, inner);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(const Geom& gf, const Geom& gc, double* phif, const double* phic,
+                          const double* phiold_c, hipStream_t s) {
+    const int nb = grid_for(gf.ncell);
+    if (gf.dir)
+        hipLaunchKernelGGL(k_prolong<1>, dim3(nb), dim3(NT), 0, s, gf, gc, phif, phic, phiold_c);
+    else
+        hipLaunchKernelGGL(k_prolong<0>, dim3(nb), dim3(NT), 0, s, gf, gc, phif, phic, phiold_c);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_solve(const Geom& g, const Coef& c, double* phi, const double* delta,
+                               const double* f, LevelScalars* sc, int sweeps, hipStream_t s) {
+    if (g.nstore > CMAX || g.ncell > 2 * NT) return hipErrorInvalidValue;
+    (void)sc;
+    if (g.dir)
+        hipLaunchKernelGGL(k_coarse_solve<1>, dim3(1), dim3(NT), 0, s, g, c, phi, delta, f, sweeps);
+    else
+        hipLaunchKernelGGL(k_coarse_solve<0>, dim3(1), dim3(NT), 0, s, g, c, phi, delta, f, sweeps);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict_plain(const Geom& gf, const Geom& gc, const double* uf, double* uc,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_restrict_plain, dim3(grid_for(gc.ncell)), dim3(NT), 0, s, gf, gc, uf, uc);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict_ghosts(const Geom& gf, const Geom& gc, const double* uf, double* uc,
+                                  hipStream_t s) {
+    const int64_t tot = (int64_t)(gc.n0 + 2) * (gc.n1 + 2) * (gc.n2 + 2);
+    hipLaunchKernelGGL(k_restrict_ghosts, dim3(grid_for(tot)), dim3(NT), 0, s, gf, gc, uf, uc);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_in(const Geom& g, const double* src, double* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_in, dim3(grid_for(g.ncell)), dim3(NT), 0, s, g, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_out(const Geom& g, const double* src, double* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_out, dim3(grid_for(g.ncell)), dim3(NT), 0, s, g, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost_in(const Geom& g, const double* ghost, double* dst, hipStream_t s) {
+    const int64_t cnt = ghost_count(g.n0, g.n1, g.n2);
+    hipLaunchKernelGGL(k_ghost_in, dim3(grid_for(cnt)), dim3(NT), 0, s, g, ghost, dst, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost_fill(const double* parent, int np0, int np1, int np2, double H, int n0,
+                             int n1, int n2, double h, int o0, int o1, int o2, double* ghost,
+                             hipStream_t s) {
+    const int64_t cnt = ghost_count(n0, n1, n2);
+    hipLaunchKernelGGL(k_ghost_fill, dim3(grid_for(cnt)), dim3(NT), 0, s, parent, np0, np1, np2, H,
+                       n0, n1, n2, h, o0, o1, o2, ghost, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge(const Geom& g, double* phi, const NormOut* no, hipStream_t s) {
+    hipLaunchKernelGGL(k_gauge, dim3(grid_for(g.ncell)), dim3(NT), 0, s, g, phi, no);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(NT), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double* p, int64_t n, double* partials, int* nblocks_out,
+                               hipStream_t s) {
+    const int nb = grid_for(n, MAX_RED_BLOCKS);
+    hipLaunchKernelGGL(k_check_finite, dim3(nb), dim3(NT), 0, s, p, n, partials);
+    *nblocks_out = nb;
+    return hipGetLastError();
+}
+
+// ---- batched launchers --------------------------------------------------------
+hipError_t launch_smooth_batch(const SmoothArgs& proto, const Geom* geoms, const int4* items, int nitems,
+                               int ty, int max_blocks, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const int nb = std::min(nitems, max_blocks);
+    const bool f = proto.f != nullptr;
+    if (ty == 4) {
+        if (f) hipLaunchKernelGGL((k_smooth_batch<4, true>), dim3(nb), dim3(NT), 0, s, proto, geoms, items, nitems);
+        else hipLaunchKernelGGL((k_smooth_batch<4, false>), dim3(nb), dim3(NT), 0, s, proto, geoms, items, nitems);
+    } else if (ty == 16) {
+        if (f) hipLaunchKernelGGL((k_smooth_batch<16, true>), dim3(nb), dim3(NT), 0, s, proto, geoms, items, nitems);
+        else hipLaunchKernelGGL((k_smooth_batch<16, false>), dim3(nb), dim3(NT), 0, s, proto, geoms, items, nitems);
+    } else {
+        if (f) hipLaunchKernelGGL((k_smooth_batch<8, true>), dim3(nb), dim3(NT), 0, s, proto, geoms, items, nitems);
+        else hipLaunchKernelGGL((k_smooth_batch<8, false>), dim3(nb), dim3(NT), 0, s, proto, geoms, items, nitems);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth_batch_args(const Coef& c, const double* pin, double* pout, const double* delta,
+                                    const double* f, SmoothCfg cfg, const Geom* geoms, const int4* items,
+                                    int nitems, int max_blocks, hipStream_t s) {
+    SmoothArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.c = c; a.pin = pin; a.pout = pout; a.delta = delta; a.f = f; a.sc = nullptr;
+    a.zc = cfg.zc > 0 ? cfg.zc : 16;
+    return launch_smooth_batch(a, geoms, items, nitems, cfg.ty, max_blocks, s);
+}
+
+hipError_t launch_rr_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, const Coef& c,
+                           const double* phi, const double* delta, const double* f, double* phic,
+                           double* phiold_c, double* rd_c, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rr_batch, dim3(nitems), dim3(NT), 0, s, gfs, gcs, items, c, phi, delta, f, phic, phiold_c,
+                       rd_c);
+    return hipGetLastError();
+}
+
+hipError_t launch_fas_batch(const Geom* gs, const int2* items, int nitems, const Coef& c, const double* phi,
+                            const double* delta, const double* rd, double* f, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fas_batch, dim3(nitems), dim3(NT), 0, s, gs, items, c, phi, delta, rd, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, double* phif,
+                                const double* phic, const double* oldc, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prolong_batch, dim3(nitems), dim3(NT), 0, s, gfs, gcs, items, phif, phic, oldc);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_batch(const Geom* gs, const int2* items, int nitems, const Coef& c, const double* phi,
+                             const double* delta, const double* f, double* partials, const int* first, int ngrids,
+                             NormOut* out, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_norm_batch, dim3(nitems), dim3(NT), 0, s, gs, items, c, phi, delta, f, partials);
+    hipLaunchKernelGGL(k_finalize_batch, dim3(ngrids), dim3(NT), 0, s, partials, first, gs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const double* partials, const int* first, const Geom* gs, int ngrids,
+                                 NormOut* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_batch, dim3(ngrids), dim3(NT), 0, s, partials, first, gs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_batch(const Geom* gs, int ngrids, const Coef& c, double* phi0, double* phi1,
+                               const double* delta, const double* f, int sweeps, hipStream_t s) {
+    if (ngrids <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coarse_batch, dim3(ngrids), dim3(NT), 0, s, gs, c, phi0, phi1, delta, f, sweeps);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_in_batch(const Geom* gs, const int64_t* uoff, const int2* items, int nitems,
+                                const double* src, double* dst0, double* dst1, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_in_batch, dim3(nitems), dim3(NT), 0, s, gs, uoff, items, src, dst0, dst1);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_out_batch(const Geom* gs, const int64_t* uoff, const int2* items, int nitems,
+                                 const double* src, double* dst, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_out_batch, dim3(nitems), dim3(NT), 0, s, gs, uoff, items, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost_in_batch(const Geom* gs, const int64_t* goff, const int2* items, int nitems,
+                                 const double* ghost, double* dst0, double* dst1, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ghost_in_batch, dim3(nitems), dim3(NT), 0, s, gs, goff, items, ghost, dst0, dst1);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict_plain_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems,
+                                       const double* uf, double* uc, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restrict_plain_batch, dim3(nitems), dim3(NT), 0, s, gfs, gcs, items, uf, uc);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict_ghosts_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems,
+                                        const double* uf, double* uc0, double* uc1, double* uc2, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restrict_ghosts_batch, dim3(nitems), dim3(NT), 0, s, gfs, gcs, items, uf, uc0, uc1, uc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite_batch(const Geom* gs, const int64_t* uoff, const int2* items, int nitems,
+                                     const double* src, double* partials, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_finite_batch, dim3(nitems), dim3(NT), 0, s, gs, uoff, items, src, partials);
+    return hipGetLastError();
+}
+
+}  // namespace vmg

@@ -1,0 +1,152 @@
+// Host side of the mixed-precision path: FP32 correction V-cycle inside an
+// FP64 defect-correction loop (residual, root near a vanishing discriminant
+// and norms stay FP64; smoothing, restriction and prolongation are FP32).
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "vmg_internal.h"
+#include "vmg_plan.h"
+
+namespace vmg {
+
+CoefF make_coef_f(const Coef& c, double h) {
+    CoefF f;
+    f.alpha = (float)c.alpha;
+    f.c8 = (float)c.c8;
+    f.a34 = c.alpha != 0.0 ? (float)(3.0 / (4.0 * c.alpha)) : 0.0f;
+    f.a_ih4 = (float)(c.alpha / (h * h * h * h));
+    f.h2 = (float)(h * h);
+    return f;
+}
+
+vmg_status alloc_mixed(Plan* P) {
+    hipStream_t s = P->stream;
+    for (auto& G : P->grids) {
+        for (size_t l = 0; l < G.lev.size(); ++l) {
+            LevelBuf& L = G.lev[l];
+            const size_t n = (size_t)L.g.nstore;
+            float** bufs[] = {&L.e[0], &L.e[1], &L.r, &L.pt, &L.t0, &L.eold, &L.rdf};
+            const int nb = l > 0 ? 7 : 5;
+            for (int b = 0; b < nb; ++b) {
+                if (hipMalloc((void**)bufs[b], sizeof(float) * n) != hipSuccess)
+                    return fail(VMG_ENOMEM, "hipMalloc failed (mixed buffers)");
+                P->allocs.push_back(*bufs[b]);
+                if (launch_fill_f(*bufs[b], (int64_t)n, 0.0f, s) != hipSuccess)
+                    return fail(VMG_EHIP, "fill failed");
+            }
+            if (hipMalloc((void**)&L.scf, sizeof(LevelScalars)) != hipSuccess)
+                return fail(VMG_ENOMEM, "hipMalloc failed (mixed scalars)");
+            P->allocs.push_back(L.scf);
+            if (launch_fill((double*)L.scf, sizeof(LevelScalars) / sizeof(double), 0.0, s) != hipSuccess)
+                return fail(VMG_EHIP, "fill failed");
+        }
+    }
+    return VMG_OK;
+}
+
+// FP32 ghost shells of the base state (Dirichlet): cast the FP64 level arrays
+// once per solve; interiors are rewritten every outer iteration.
+hipError_t mixed_prepare(Plan* P) {
+    hipError_t e;
+    for (auto& G : P->grids)
+        for (auto& L : G.lev)
+            if (L.g.dir && (e = launch_cast_all(L.phi[0], L.pt, L.g.nstore, P->stream)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+hipError_t smooth_corr_level(Plan* P, GridState& G, int l) {
+    LevelBuf& L = G.lev[l];
+    const CoefF cf = make_coef_f(P->coef, L.g.h);
+    hipError_t e = launch_smooth_corr(L.g, cf, L.e[L.ecur], L.e[L.ecur ^ 1], L.pt, L.t0, L.r, L.scf, P->cfg,
+                                      P->stream);
+    L.ecur ^= 1;
+    P->cell_updates += L.g.ncell;
+    if (l == 0) P->finest_sweeps += 1;
+    return e;
+}
+
+static hipError_t inner_vcycle(Plan* P, GridState& G, int l) {
+    LevelBuf& L = G.lev[l];
+    const int last = (int)G.lev.size() - 1;
+    const CoefF cf = make_coef_f(P->coef, L.g.h);
+    hipError_t e;
+    if (l == last) {
+        e = launch_coarse_corr(L.g, cf, L.e[L.ecur], L.pt, L.t0, L.r, P->ncoarse, P->stream);
+        P->cell_updates += (int64_t)P->ncoarse * L.g.ncell;
+        return e;
+    }
+    for (int s = 0; s < P->nu1; ++s)
+        if ((e = smooth_corr_level(P, G, l)) != hipSuccess) return e;
+    LevelBuf& C = G.lev[l + 1];
+    const CoefF cc = make_coef_f(P->coef, C.g.h);
+    C.ecur = 0;
+    int nb = 0;
+    const int periodic = L.g.dir ? 0 : 1;
+    if ((e = launch_rr_corr(L.g, C.g, cf, L.e[L.ecur], L.pt, L.t0, L.r, L.scf, C.e[0], C.eold, C.rdf,
+                            P->partials, &nb, P->stream)) != hipSuccess)
+        return e;
+    if ((e = launch_finalize(P->partials, nb, L.g.ncell, periodic, 0, L.scf, nullptr, P->stream)) != hipSuccess)
+        return e;
+    if ((e = launch_fas_corr(C.g, cc, C.e[0], C.pt, C.t0, C.rdf, C.r, P->partials, &nb, P->stream)) != hipSuccess)
+        return e;
+    if ((e = launch_finalize(P->partials, nb, C.g.ncell, periodic, 1, C.scf, nullptr, P->stream)) != hipSuccess)
+        return e;
+    if ((e = inner_vcycle(P, G, l + 1)) != hipSuccess) return e;
+    if ((e = launch_prolong_corr(L.g, C.g, L.e[L.ecur], C.e[C.ecur], C.eold, P->stream)) != hipSuccess) return e;
+    for (int s = 0; s < P->nu2; ++s)
+        if ((e = smooth_corr_level(P, G, l)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+static const double* level0_f(const Plan* P, const GridState& G) {
+    return P->has_source ? G.lev[0].f : nullptr;
+}
+
+// FP64 residual of the current phi + FP32 inputs of the inner problem + norm
+static hipError_t cast_pass(Plan* P, GridState& G) {
+    LevelBuf& L = G.lev[0];
+    int nb = 0;
+    hipError_t e = launch_cast(L.g, P->coef, L.phi[0], L.delta, level0_f(P, G), L.sc, L.pt, L.t0, L.r,
+                               P->partials, &nb, P->stream);
+    if (e != hipSuccess) return e;
+    return launch_finalize(P->partials, nb, L.g.ncell, L.g.dir ? 0 : 1, 2, L.sc, G.norm_dev, P->stream, L.scf);
+}
+
+static hipError_t norms_to_host(Plan* P) {
+    for (size_t gi = 0; gi < P->grids.size(); ++gi) {
+        hipError_t e = hipMemcpyAsync(&P->host_norm[gi], P->grids[gi].norm_dev, sizeof(NormOut),
+                                      hipMemcpyDeviceToHost, P->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t mixed_initial_pass(Plan* P) {
+    hipError_t e;
+    for (auto& G : P->grids)
+        if ((e = cast_pass(P, G)) != hipSuccess) return e;
+    return norms_to_host(P);
+}
+
+hipError_t enqueue_outer(Plan* P) {
+    hipError_t e;
+    for (auto& G : P->grids) {
+        // coarse base states of the inner problem
+        for (size_t l = 1; l < G.lev.size(); ++l) {
+            LevelBuf& F = G.lev[l - 1];
+            LevelBuf& C = G.lev[l];
+            if ((e = launch_base_restrict(F.g, C.g, F.pt, C.pt, P->stream)) != hipSuccess) return e;
+            if ((e = launch_base_t0(C.g, P->coef, C.pt, C.delta, C.t0, P->stream)) != hipSuccess) return e;
+        }
+        LevelBuf& L0 = G.lev[0];
+        L0.ecur = 0;
+        if ((e = launch_fill_f(L0.e[0], L0.g.nstore, 0.0f, P->stream)) != hipSuccess) return e;
+        if ((e = inner_vcycle(P, G, 0)) != hipSuccess) return e;
+        if ((e = launch_update(L0.g, L0.phi[0], L0.e[L0.ecur], P->stream)) != hipSuccess) return e;
+        if ((e = cast_pass(P, G)) != hipSuccess) return e;
+    }
+    return norms_to_host(P);
+}
+
+}  // namespace vmg

@@ -1,0 +1,132 @@
+// Internal declarations of the gfx950 multigrid library (kernels <-> driver).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace vmg {
+
+// One level of one grid as the kernels see it.  Periodic levels are stored
+// unpadded (n0*n1*n2, x fastest) and wrap their indices; Dirichlet levels are
+// stored with a one-cell shell ((n0+2)*(n1+2)*(n2+2)) that holds the ghosts.
+struct Geom {
+    int n0, n1, n2;
+    int dir;          // 1: Dirichlet (padded), 0: periodic
+    int64_t sy, sz;   // element strides of y and z (x stride is 1)
+    int64_t off0;     // element offset of interior cell (0,0,0)
+    int64_t ncell;    // n0*n1*n2
+    int64_t nstore;   // elements of storage
+    double h;
+    int64_t base;     // element offset where this grid's storage starts (pooled batches)
+};
+
+// Coefficients of the discrete operator (Sec. III.A/B with w = 1/3):
+//   q = alpha*Sigma0 + kappa*delta, D = 1 + c8*q, Q = 2q/(1+sqrt D) or vertex.
+struct Coef {
+    double alpha, kappa;
+    double c8;        // 8*alpha/3
+    double vertex;    // -3/(4 alpha) (unused when alpha == 0: then D == 1)
+};
+
+// FP32 coefficients of the inner (correction) operator of the mixed path.
+struct CoefF {
+    float alpha;
+    float c8;        // 8*alpha/3
+    float a34;       // 3/(4 alpha) (unused when alpha == 0)
+    float a_ih4;     // alpha / h^4
+    float h2;        // h^2
+};
+
+// Reduction slots written per block and summed by k_finalize.
+enum { R_D2 = 0, R_D1, R_Q, R_F, R_PHI, R_GUARD, R_NONFIN, R_NSLOT };
+
+// Device-resident per-level scalars.
+struct LevelScalars {
+    double cbar;      // compatibility constant in use (periodic), 0 otherwise
+    double pad[7];
+};
+
+// Host-visible result of a norm pass.
+struct NormOut {
+    double rms;       // sqrt(mean d^2) with the updated cbar
+    double cbar;      // updated cbar
+    double mean_phi;
+    double n_guard;
+    double n_nonfinite;
+    double sum_q;
+    double pad[2];
+};
+
+// Fused red-black sweep tile configuration.
+constexpr int TX = 64;
+
+struct SmoothCfg {
+    int ty;      // 4, 8 or 16
+    int zc;      // z planes per block
+};
+
+// ---- launchers (kernels.hip) --------------------------------------------
+hipError_t launch_smooth(const Geom& g, const Coef& c, const double* pin, double* pout,
+                         const double* delta, const double* f, const LevelScalars* sc,
+                         SmoothCfg cfg, hipStream_t s);
+hipError_t launch_residual_restrict(const Geom& gf, const Geom& gc, const Coef& c,
+                                    const double* phi, const double* delta, const double* f,
+                                    const LevelScalars* sc, double* phic, double* phiold_c,
+                                    double* rd_c, double* partials, int* nblocks_out, hipStream_t s);
+hipError_t launch_residual_norm(const Geom& g, const Coef& c, const double* phi,
+                                const double* delta, const double* f, const LevelScalars* sc,
+                                double* d_out, double* partials, int* nblocks_out, hipStream_t s);
+hipError_t launch_fas_rhs(const Geom& g, const Coef& c, const double* phi, const double* delta,
+                          const double* rd, double* f, double* partials, int* nblocks_out,
+                          hipStream_t s);
+// mode 0: residual pass (updates cbar from sum Q + sum f, corrects the lagged sums, writes NormOut)
+// mode 1: FAS rhs pass (cbar = mean f + mean Q)
+// mode 2: as mode 0, and also sets inner->cbar = -mean(d) (mean of the inner right-hand side)
+hipError_t launch_finalize(const double* partials, int nblocks, int64_t ncell, int periodic,
+                           int mode, LevelScalars* sc, NormOut* out, hipStream_t s,
+                           LevelScalars* inner = nullptr);
+hipError_t launch_prolong(const Geom& gf, const Geom& gc, double* phif, const double* phic,
+                          const double* phiold_c, hipStream_t s);
+hipError_t launch_coarse_solve(const Geom& g, const Coef& c, double* phi, const double* delta,
+                               const double* f, LevelScalars* sc, int sweeps, hipStream_t s);
+hipError_t launch_restrict_plain(const Geom& gf, const Geom& gc, const double* uf, double* uc,
+                                 hipStream_t s);
+hipError_t launch_copy_in(const Geom& g, const double* src, double* dst, hipStream_t s);
+hipError_t launch_copy_out(const Geom& g, const double* src, double* dst, hipStream_t s);
+hipError_t launch_ghost_in(const Geom& g, const double* ghost, double* dst, hipStream_t s);
+hipError_t launch_restrict_ghosts(const Geom& gf, const Geom& gc, const double* uf, double* uc,
+                                  hipStream_t s);
+hipError_t launch_gauge(const Geom& g, double* phi, const NormOut* no, hipStream_t s);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_check_finite(const double* p, int64_t n, double* partials, int* nblocks_out,
+                               hipStream_t s);
+hipError_t launch_ghost_fill(const double* parent, int np0, int np1, int np2, double H,
+                             int n0, int n1, int n2, double h, int o0, int o1, int o2,
+                             double* ghost, hipStream_t s);
+
+// ---- mixed path (kernels_mixed.hip) ---------------------------------------
+hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, float* eout,
+                              const float* pt, const float* t0, const float* r, const LevelScalars* sc,
+                              SmoothCfg cfg, hipStream_t s);
+hipError_t launch_rr_corr(const Geom& gf, const Geom& gc, const CoefF& c, const float* e, const float* pt,
+                          const float* t0, const float* r, const LevelScalars* sc, float* ec, float* eold_c,
+                          float* rd_c, double* partials, int* nblocks_out, hipStream_t s);
+hipError_t launch_fas_corr(const Geom& g, const CoefF& c, const float* e, const float* pt, const float* t0,
+                           const float* rd, float* r, double* partials, int* nblocks_out, hipStream_t s);
+hipError_t launch_prolong_corr(const Geom& gf, const Geom& gc, float* ef, const float* ec, const float* eold_c,
+                               hipStream_t s);
+hipError_t launch_coarse_corr(const Geom& g, const CoefF& c, float* e, const float* pt, const float* t0,
+                              const float* r, int sweeps, hipStream_t s);
+hipError_t launch_cast(const Geom& g, const Coef& c, const double* phi, const double* delta, const double* f,
+                       const LevelScalars* sc, float* pt, float* t0, float* r, double* partials,
+                       int* nblocks_out, hipStream_t s);
+hipError_t launch_base_restrict(const Geom& gf, const Geom& gc, const float* pf, float* pc, hipStream_t s);
+hipError_t launch_base_t0(const Geom& g, const Coef& c, const float* pt, const double* delta, float* t0,
+                          hipStream_t s);
+hipError_t launch_update(const Geom& g, double* phi, const float* e, hipStream_t s);
+hipError_t launch_fill_f(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_cast_all(const double* src, float* dst, int64_t n, hipStream_t s);
+
+int64_t ghost_count(int n0, int n1, int n2);
+int partial_blocks_for(int64_t ncell);   // upper bound of blocks used by reduction kernels
+
+}  // namespace vmg

@@ -1,0 +1,256 @@
+"""ctypes binding of libvmg.so (the gfx950 nonlinear multigrid library).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch supplies device memory (``Tensor.data_ptr()``) and the
+current HIP stream.  The functions mirror the C ABI in ``include/vmg.h``:
+``plan_create``, ``solve``, ``plan_destroy``, ``last_error``,
+``solve_periodic``, ``residual``, ``fill_ghosts``, ``ghost_count``,
+``smooth``, ``plan_stats``; ``Plan`` wraps a plan handle.
+
+There is no fallback: if the library is missing or no GPU is present the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvmg.so")
+
+VMG_OK, VMG_EINVAL, VMG_ENOMEM, VMG_EHIP, VMG_ENOCONV, VMG_ENONFINITE = range(6)
+STATUS_NAMES = {0: "VMG_OK", 1: "VMG_EINVAL", 2: "VMG_ENOMEM", 3: "VMG_EHIP", 4: "VMG_ENOCONV",
+                5: "VMG_ENONFINITE"}
+FP64, MIXED = 0, 1
+PERIODIC, DIRICHLET = 0, 1
+GRAPH, AUTOTUNE = 1, 2
+
+
+class VmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("bc", ctypes.c_int32), ("h", ctypes.c_double),
+                ("offset", ctypes.c_int64), ("ghost_offset", ctypes.c_int64)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("kappa", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_cycles", ctypes.c_int32), ("prec", ctypes.c_int32), ("nu1", ctypes.c_int32),
+                ("nu2", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("rms0", ctypes.c_double), ("rms", ctypes.c_double), ("compat_c", ctypes.c_double),
+                ("cycles", ctypes.c_int32), ("inner_cycles", ctypes.c_int32),
+                ("n_guarded", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# Every symbol declared in include/vmg.h (checked by the CPU test-suite).
+EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
+           "vmg_solve_periodic", "vmg_residual", "vmg_fill_ghosts", "vmg_ghost_count",
+           "vmg_smooth", "vmg_plan_stats"]
+
+_lib = None
+
+
+def load():
+    """Load libvmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1303_0008_amd.build` "
+                          "(or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, P = ctypes.c_void_p, ctypes.POINTER
+    L.vmg_plan_create.argtypes = [P(vp), P(Grid), ctypes.c_int32, P(Params), vp]
+    L.vmg_solve.argtypes = [vp, vp, vp, vp, vp, P(Result)]
+    L.vmg_plan_destroy.argtypes = [vp]
+    L.vmg_last_error.restype = ctypes.c_char_p
+    L.vmg_solve_periodic.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int32, vp, P(ctypes.c_double),
+                                     P(ctypes.c_int32), vp]
+    L.vmg_residual.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, P(Result)]
+    L.vmg_fill_ghosts.argtypes = [vp, P(ctypes.c_int32), ctypes.c_double, P(Grid), P(ctypes.c_int32),
+                                  ctypes.c_int32, vp, vp]
+    L.vmg_ghost_count.argtypes = [P(ctypes.c_int32)]
+    L.vmg_ghost_count.restype = ctypes.c_int64
+    L.vmg_smooth.argtypes = [vp, ctypes.c_int32]
+    L.vmg_plan_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
+    for name in EXPORTS:
+        if name != "vmg_last_error" and name != "vmg_ghost_count":
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def last_error():
+    return load().vmg_last_error().decode()
+
+
+def _check(st, allow=()):
+    if st != VMG_OK and st not in allow:
+        raise VmgError(st, last_error())
+    return st
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("arrays must be contiguous float64 tensors on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def ghost_count(n):
+    n = (n,) * 3 if isinstance(n, int) else tuple(n)
+    return int(load().vmg_ghost_count((ctypes.c_int32 * 3)(*n)))
+
+
+def make_grid(n, h=None, bc=PERIODIC, offset=0, ghost_offset=0):
+    n = (n,) * 3 if isinstance(n, int) else tuple(int(v) for v in n)
+    g = Grid()
+    g.n[:] = n
+    g.bc = bc
+    g.h = (1.0 / n[0]) if h is None else h
+    g.offset = offset
+    g.ghost_offset = ghost_offset
+    return g
+
+
+def make_params(alpha, kappa, tol, max_cycles=100, prec=FP64, nu1=0, nu2=0, flags=0):
+    p = Params()
+    p.alpha, p.kappa, p.tol = alpha, kappa, tol
+    p.max_cycles, p.prec, p.nu1, p.nu2, p.flags = max_cycles, prec, nu1, nu2, flags
+    return p
+
+
+def plan_create(grids, params, stream=None):
+    """vmg_plan_create: returns an opaque handle (int)."""
+    arr = (Grid * len(grids))(*grids)
+    h = ctypes.c_void_p()
+    _check(load().vmg_plan_create(ctypes.byref(h), arr, len(grids), ctypes.byref(params),
+                                  _stream(stream)))
+    return h.value
+
+
+def plan_destroy(handle):
+    _check(load().vmg_plan_destroy(ctypes.c_void_p(handle)))
+
+
+def solve(handle, delta, phi, ghost=None, source=None, n_grids=1, allow_noconv=False):
+    """vmg_solve: phi (in: guess, out: solution).  Returns a list of result dicts."""
+    res = (Result * n_grids)()
+    st = load().vmg_solve(ctypes.c_void_p(handle), _ptr(delta), _ptr(ghost), _ptr(source), _ptr(phi),
+                          res)
+    _check(st, allow=(VMG_ENOCONV,) if allow_noconv else ())
+    out = [r.as_dict() for r in res]
+    for r in out:
+        r["status"] = st
+    return out
+
+
+def residual(handle, g, delta, phi, d=None, ghost=None, source=None):
+    """vmg_residual: residual field (into d, optional) and its RMS for grid g."""
+    r = Result()
+    _check(load().vmg_residual(ctypes.c_void_p(handle), g, _ptr(delta), _ptr(ghost), _ptr(source),
+                               _ptr(phi), _ptr(d), ctypes.byref(r)))
+    return r.as_dict()
+
+
+def solve_periodic(delta, alpha, kappa, tol, phi, precision=FP64, stream=None):
+    """vmg_solve_periodic on an n^3 unit box; returns (rms, cycles)."""
+    n = delta.shape[-1]
+    rms = ctypes.c_double()
+    cyc = ctypes.c_int32()
+    _check(load().vmg_solve_periodic(_ptr(delta), n, alpha, kappa, tol, precision, _ptr(phi),
+                                     ctypes.byref(rms), ctypes.byref(cyc), _stream(stream)))
+    return rms.value, cyc.value
+
+
+def fill_ghosts(parent, parent_h, grids, origins, ghost, stream=None):
+    """vmg_fill_ghosts: trilinear refinement boundary values from a periodic parent."""
+    n2, n1, n0 = parent.shape
+    npar = (ctypes.c_int32 * 3)(n0, n1, n2)
+    arr = (Grid * len(grids))(*grids)
+    flat = [int(v) for o in origins for v in o]
+    org = (ctypes.c_int32 * len(flat))(*flat)
+    _check(load().vmg_fill_ghosts(_ptr(parent), npar, parent_h, arr, org, len(grids), _ptr(ghost),
+                                  _stream(stream)))
+
+
+def smooth(handle, sweeps):
+    """vmg_smooth: finest-level smoother sweeps on the plan's state (measurement hook)."""
+    _check(load().vmg_smooth(ctypes.c_void_p(handle), sweeps))
+
+
+def plan_stats(handle):
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().vmg_plan_stats(ctypes.c_void_p(handle), ctypes.byref(a), ctypes.byref(b),
+                                 ctypes.byref(c)))
+    return dict(cell_updates=a.value, finest_sweeps=b.value, finest_cells=c.value)
+
+
+class Plan:
+    """Owning wrapper of a plan handle."""
+
+    def __init__(self, grids, params, stream=None):
+        self.grids = list(grids)
+        self.handle = plan_create(self.grids, params, stream)
+
+    def solve(self, delta, phi, ghost=None, source=None, allow_noconv=False):
+        return solve(self.handle, delta, phi, ghost, source, len(self.grids), allow_noconv)
+
+    def residual(self, g, delta, phi, d=None, ghost=None, source=None):
+        return residual(self.handle, g, delta, phi, d, ghost, source)
+
+    def smooth(self, sweeps):
+        smooth(self.handle, sweeps)
+
+    def stats(self):
+        return plan_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            plan_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_field(delta, alpha, kappa, tol=1e-10, precision=FP64, max_cycles=100, phi0=None, flags=0,
+                nu1=0, nu2=0):
+    """Convenience: solve one periodic grid given a (n2, n1, n0) float64 CUDA tensor."""
+    import torch
+    n2, n1, n0 = delta.shape
+    phi = torch.zeros_like(delta) if phi0 is None else phi0.clone()
+    with Plan([make_grid((n0, n1, n2))], make_params(alpha, kappa, tol, max_cycles, precision, nu1, nu2,
+                                                     flags)) as p:
+        info = p.solve(delta.contiguous(), phi)[0]
+    return phi, info

@@ -1,0 +1,52 @@
+"""CPU checks of the C ABI: the library loads and exports every declared symbol."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "vmg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vmg_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for must in ("vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
+                 "vmg_solve_periodic"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1303_0008_amd import vmg
+    lib = vmg.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(vmg.EXPORTS) == declared_functions()
+
+
+def test_ghost_count_matches_oracle(oracle_mod):
+    from paper_1303_0008_amd import vmg
+    for n in [(2, 2, 2), (16, 16, 16), (5, 7, 9)]:
+        assert vmg.ghost_count(n) == oracle_mod.ghost_count(n)
+
+
+def test_plan_create_rejects_bad_arguments():
+    """Argument validation happens before any device call."""
+    from paper_1303_0008_amd import vmg
+    lib = vmg.load()
+    h = ctypes.c_void_p()
+    g = vmg.make_grid(32)
+    p = vmg.make_params(0.1, 1.5, tol=-1.0)
+    assert lib.vmg_plan_create(ctypes.byref(h), ctypes.byref(g), 1, ctypes.byref(p), None) == vmg.VMG_EINVAL
+    assert "tol" in vmg.last_error()
+    p = vmg.make_params(0.1, 1.5, tol=1e-8)
+    g2 = vmg.make_grid(2)
+    assert lib.vmg_plan_create(ctypes.byref(h), ctypes.byref(g2), 1, ctypes.byref(p), None) == vmg.VMG_EINVAL
+    arr = (vmg.Grid * 2)(vmg.make_grid(32), vmg.make_grid(32))
+    assert lib.vmg_plan_create(ctypes.byref(h), arr, 2, ctypes.byref(p), None) == vmg.VMG_EINVAL
+    assert lib.vmg_solve(None, None, None, None, None, None) == vmg.VMG_EINVAL

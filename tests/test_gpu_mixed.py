@@ -1,0 +1,133 @@
+"""GPU parity of the mixed-precision path (FP32 correction V-cycle inside an
+FP64 defect-correction loop) against the FP64 CPU oracle.
+
+The outer residual is FP64, so the mixed path can be driven to the FP64
+floor; the bar is |phi_mixed - phi_oracle|_inf / |phi_oracle|_inf <= 1e-8.
+"""
+import numpy as np
+import pytest
+
+from paper_1303_0008_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def V():
+    from paper_1303_0008_amd import vmg
+    vmg.load()
+    return vmg
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def relerr(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("shape,alpha,seed,sigma", [((32, 32, 32), 0.1, 601, 1.0),
+                                                     ((32, 32, 32), -0.2, 602, 1.5),
+                                                     ((48, 32, 40), 0.2, 603, 1.5),
+                                                     ((64, 64, 64), 0.2, 604, 1.5)])
+def test_mixed_parity_periodic(torch_cuda, V, oracle_mod, shape, alpha, seed, sigma):
+    torch = torch_cuda
+    say("mixed periodic", shape, alpha)
+    n0, n1, n2 = shape
+    delta = I.lognormal(shape, seed, sigma=sigma)
+    ref, rinfo = oracle_mod.solve(delta, alpha, 1.5, h=1.0 / n0)
+    d_t = dev(torch, delta)
+    phi = torch.zeros_like(d_t)
+    with V.Plan([V.make_grid(shape)], V.make_params(alpha, 1.5, 1e-12, 80, V.MIXED)) as p:
+        info = p.solve(d_t, phi, allow_noconv=True)[0]
+    say("  mixed", info, "oracle", rinfo)
+    assert info["rms"] <= 1e-11
+    assert info["inner_cycles"] == info["cycles"]
+    assert relerr(phi.cpu().numpy(), ref) <= 1e-8
+    if alpha < 0:
+        assert info["n_guarded"] > 0
+
+
+def test_mixed_tophat32(torch_cuda, V, oracle_mod):
+    torch = torch_cuda
+    say("mixed tophat32")
+    delta = I.tophat(32)
+    ref, _ = oracle_mod.solve(delta, 0.05, 1.5)
+    d_t = dev(torch, delta)
+    phi = torch.zeros_like(d_t)
+    with V.Plan([V.make_grid(32)], V.make_params(0.05, 1.5, 1e-12, 80, V.MIXED)) as p:
+        info = p.solve(d_t, phi)[0]
+    say("  mixed", info)
+    assert relerr(phi.cpu().numpy(), ref) <= 1e-8
+
+
+def test_mixed_matches_fp64_cycles(torch_cuda, V):
+    """The FP32 inner cycle reduces the FP64 residual about as fast as an FP64 cycle."""
+    torch = torch_cuda
+    say("mixed vs fp64 cycles")
+    d_t = dev(torch, I.lognormal(64, 605, sigma=1.0))
+    cyc = {}
+    for prec in (V.FP64, V.MIXED):
+        phi = torch.zeros_like(d_t)
+        with V.Plan([V.make_grid(64)], V.make_params(0.1, 1.5, 1e-8, 60, prec)) as p:
+            cyc[prec] = p.solve(d_t, phi)[0]["cycles"]
+    say("  cycles", cyc)
+    assert cyc[V.MIXED] <= cyc[V.FP64] + 2
+
+
+def test_mixed_graph_matches_eager(torch_cuda, V):
+    torch = torch_cuda
+    say("mixed graph")
+    d_t = dev(torch, I.lognormal(32, 606, sigma=1.0))
+    out = []
+    for flags in (0, V.GRAPH):
+        phi = torch.zeros_like(d_t)
+        with V.Plan([V.make_grid(32)], V.make_params(0.1, 1.5, 1e-11, 60, V.MIXED, flags=flags)) as p:
+            p.solve(d_t, phi)
+        out.append(phi.cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+
+
+def test_mixed_dirichlet_patches(torch_cuda, V, oracle_mod):
+    torch = torch_cuda
+    say("mixed dirichlet")
+    sizes = [(16, 16, 16), (24, 24, 24)]
+    h = 1.0 / 512
+    rng = np.random.Generator(np.random.PCG64(12))
+    grids, deltas, ghosts, refs = [], [], [], []
+    off = goff = 0
+    for i, n in enumerate(sizes):
+        d = I.lognormal(n, 700 + i, sigma=1.5)
+        g = 2e-5 * rng.standard_normal(oracle_mod.ghost_count(n))
+        ref, _ = oracle_mod.solve(d, 0.1, 1.5, h=h, ghost=g)
+        grids.append(V.make_grid(n, h, V.DIRICHLET, off, goff))
+        deltas.append(d.ravel())
+        ghosts.append(g)
+        refs.append(ref)
+        off += d.size
+        goff += g.size
+    dt = dev(torch, np.concatenate(deltas))
+    gt = dev(torch, np.concatenate(ghosts))
+    phi = torch.zeros_like(dt)
+    with V.Plan(grids, V.make_params(0.1, 1.5, 1e-12, 80, V.MIXED)) as p:
+        res = p.solve(dt, phi, ghost=gt, allow_noconv=True)
+    out = phi.cpu().numpy()
+    off = 0
+    for i, n in enumerate(sizes):
+        m = n[0] * n[1] * n[2]
+        say("  patch", n, res[i])
+        assert relerr(out[off:off + m].reshape(n[2], n[1], n[0]), refs[i]) <= 1e-8
+        off += m
