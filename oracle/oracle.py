@@ -54,6 +54,7 @@ def lib():
                                        ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, dp]
         L.or_fill_ghosts.argtypes = [ip, ctypes.c_double, dp, ip, ctypes.c_double, ip, dp]
+        L.or_fill_interior.argtypes = [ip, ctypes.c_double, dp, ip, ctypes.c_double, ip, dp]
         L.or_ghost_count.argtypes = [ip]
         L.or_ghost_count.restype = ctypes.c_long
         _lib = L
@@ -131,6 +132,20 @@ def cell_operator(delta, phi, alpha, kappa, ijk, h=None, ghost=None, w=W_PAPER):
     lib().or_cell_operator(_ivec(n), 1 if ghost is None else 0, h, alpha, kappa, w, _dp(delta),
                            _dp(ghost), _dp(phi), int(ijk[0]), int(ijk[1]), int(ijk[2]), _dp(out))
     return tuple(out)
+
+
+def fill_interior(parent, n, h, origin):
+    """Initial guess on a patch (n cells of size h, cell (0,0,0) at origin*h):
+    trilinear interpolation of the periodic cell-centred ``parent`` at every
+    cell centre, shaped (n2, n1, n0)."""
+    parent = _f64(parent)
+    npar = _dims(parent)
+    H = 1.0 / npar[0]
+    nn = (n,) * 3 if np.isscalar(n) else tuple(n)
+    out = np.zeros(nn[::-1])
+    rc = lib().or_fill_interior(_ivec(npar), H, _dp(parent), _ivec(nn), h, _ivec(origin), _dp(out))
+    assert rc == 0
+    return out
 
 
 def fill_ghosts(parent, n, h, origin):

@@ -37,6 +37,14 @@
  *     coarse density = R(delta) ("by interpolation", Sec. III.C);
  *   - refinement boundary (Sec. III.C, IV.D): a one-cell ghost shell (faces and
  *     edges, no corners) around the n0*n1*n2 unknowns, values given;
+ *   - coarse levels of a refinement (Sec. III.C only says they need suitable
+ *     boundary conditions): the ghosts of a coarse level hold the restricted
+ *     boundary values plus the odd reflection of the adjacent interior
+ *     correction, so the coarse correction vanishes on the refinement's faces
+ *     (the boundary values are fixed there); prolongation uses the same
+ *     reflection.  A zero correction at the coarse ghost centres instead puts
+ *     the boundary half a coarse cell too far out, and the V-cycle then slows
+ *     down with every extra level;
  *   - Gauss-Seidel order (unspecified): lexicographic, x fastest.
  *
  * Array layout: every field handed in or out is x-fastest, unpadded
@@ -333,7 +341,38 @@ static void restrict_ghosts(const OGrid *fg, const double *uf, const OGrid *cg, 
             }
 }
 
-/* fine += P(coarse correction); correction outside a Dirichlet grid is zero */
+/* Reflect an index one cell outside [0, n) back inside, flipping *sign. */
+static int reflect(int i, int n, int *sign) {
+    if (i < 0) { *sign = -*sign; return 0; }
+    if (i >= n) { *sign = -*sign; return n - 1; }
+    return i;
+}
+
+/* Correction phi - phiold at (i,j,k) of a Dirichlet level, ghosts included:
+ * outside the grid it is minus (per crossed face) the value at the mirror cell. */
+static double dir_corr(const OLevel *C, int i, int j, int k) {
+    int sg = 1;
+    const int a = reflect(i, C->g.n[0], &sg), b = reflect(j, C->g.n[1], &sg), e = reflect(k, C->g.n[2], &sg);
+    const long p = pidx(&C->g, a, b, e);
+    return sg * (C->phi[p] - C->phiold[p]);
+}
+
+/* Coarse Dirichlet level: ghosts = restricted boundary values (kept in the
+ * ghosts of phiold) + reflected interior correction. */
+static void refresh_ghosts(OLevel *C) {
+    const OGrid *g = &C->g;
+    for (int k = -1; k <= g->n[2]; ++k)
+        for (int j = -1; j <= g->n[1]; ++j)
+            for (int i = -1; i <= g->n[0]; ++i) {
+                const int o = (i < 0 || i >= g->n[0]) + (j < 0 || j >= g->n[1]) + (k < 0 || k >= g->n[2]);
+                if (o == 0 || o == 3) continue;
+                const long p = pidx(g, i, j, k);
+                C->phi[p] = C->phiold[p] + dir_corr(C, i, j, k);
+            }
+}
+
+/* fine += P(coarse correction); on a Dirichlet grid the correction outside is
+ * the reflection of the interior one */
 static void prolong_add(const OLevel *C, OLevel *F) {
     const OGrid *cg = &C->g, *fg = &F->g;
     for (int k = 0; k < fg->n[2]; ++k)
@@ -348,13 +387,10 @@ static void prolong_add(const OLevel *C, OLevel *F) {
                             const double wgt = (a ? 0.25 : 0.75) * (b ? 0.25 : 0.75) * (e ? 0.25 : 0.75);
                             int ii = I + a * si, jj = J + b * sj, kk = K + e * sk;
                             double corr;
-                            if (cg->periodic) {
+                            if (cg->periodic)
                                 corr = at(cg, C->phi, ii, jj, kk) - at(cg, C->phiold, ii, jj, kk);
-                            } else if (ii < 0 || ii >= cg->n[0] || jj < 0 || jj >= cg->n[1] || kk < 0 || kk >= cg->n[2]) {
-                                corr = 0.0;
-                            } else {
-                                corr = C->phi[pidx(cg, ii, jj, kk)] - C->phiold[pidx(cg, ii, jj, kk)];
-                            }
+                            else
+                                corr = dir_corr(C, ii, jj, kk);
                             acc += wgt * corr;
                         }
                 F->phi[pidx(fg, i, j, k)] += acc;
@@ -392,18 +428,36 @@ static void hier_free(OHier *H) {
     for (int l = 0; l < H->nlev; ++l) level_free(&H->lev[l]);
 }
 
+/* Sweeps on level l; a coarse Dirichlet level refreshes its ghosts after each. */
+static void relax_level(OHier *H, int l, int sweeps) {
+    OLevel *F = &H->lev[l];
+    const int refresh = l > 0 && !F->g.periodic;
+    for (int s = 0; s < sweeps; ++s) {
+        relax(F, &H->c, 1);
+        if (refresh) refresh_ghosts(F);
+    }
+}
+
 static void vcycle(OHier *H, int l) {
     OLevel *F = &H->lev[l];
     if (l == H->nlev - 1) {
-        relax(F, &H->c, H->ncoarse);
+        relax_level(H, l, H->ncoarse);
         return;
     }
     OLevel *C = &H->lev[l + 1];
-    relax(F, &H->c, H->nu1);
+    relax_level(H, l, H->nu1);
     const double cbar = compat_const(F, &H->c);
     residual(F, &H->c, cbar, NULL, NULL);
     restrict_field(&F->g, F->phi, &C->g, C->phi);
-    memcpy(C->phiold, C->phi, sizeof(double) * npad(&C->g));
+    if (C->g.periodic) {
+        memcpy(C->phiold, C->phi, sizeof(double) * npad(&C->g));
+    } else {
+        /* interior only: the ghosts of phiold keep the restricted boundary values */
+        for (int K = 0; K < C->g.n[2]; ++K)
+            for (int J = 0; J < C->g.n[1]; ++J)
+                for (int I = 0; I < C->g.n[0]; ++I) C->phiold[pidx(&C->g, I, J, K)] = C->phi[pidx(&C->g, I, J, K)];
+        refresh_ghosts(C);
+    }
     /* f^H = L^H(R phi^h) - R d^h (the coarse periodic constant drops out: only
      * f^H - mean(f^H) matters to the projected coarse equation) */
     restrict_field(&F->g, F->d, &C->g, C->d);
@@ -415,7 +469,7 @@ static void vcycle(OHier *H, int l) {
             }
     vcycle(H, l + 1);
     prolong_add(C, F);
-    relax(F, &H->c, H->nu2);
+    relax_level(H, l, H->nu2);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -469,17 +523,22 @@ int or_solve(const int n[3], int periodic, double h, double alpha, double kappa,
     if (!periodic && ghost) ghosts_to_pad(&g, ghost, F->phi);
     for (int l = 1; l < H.nlev; ++l) {
         restrict_field(&H.lev[l - 1].g, H.lev[l - 1].delta, &H.lev[l].g, H.lev[l].delta);
-        if (!periodic) restrict_ghosts(&H.lev[l - 1].g, H.lev[l - 1].phi, &H.lev[l].g, H.lev[l].phi);
+        if (!periodic) {
+            restrict_ghosts(&H.lev[l - 1].g, H.lev[l - 1].phi, &H.lev[l].g, H.lev[l].phi);
+            memcpy(H.lev[l].phiold, H.lev[l].phi, sizeof(double) * npad(&H.lev[l].g));
+        }
     }
-    double rms = 0.0, best = 1e300, hist[4] = {1e300, 1e300, 1e300, 1e300};
+    double rms = 0.0, best = 1e300, hist[8] = {1e300, 1e300, 1e300, 1e300, 1e300, 1e300, 1e300, 1e300};
     int cyc = 0;
     for (;;) {
         const double cbar = compat_const(F, &H.c);
         rms = sqrt(residual(F, &H.c, cbar, NULL, NULL) / (double)ncells(&g));
         if (!(rms == rms)) break;
         if (rms <= tol || cyc >= max_cycles) break;
-        if (cyc >= 4 && rms > 0.5 * hist[cyc % 4]) break;  /* stagnated at the rounding floor */
-        hist[cyc % 4] = rms;
+        /* stagnated at the rounding floor: less than 10% gained over 8 cycles (a
+         * slow nonlinear start phase still gains more than that) */
+        if (cyc >= 8 && rms > 0.9 * hist[cyc % 8]) break;
+        hist[cyc % 8] = rms;
         if (rms < best) best = rms;
         vcycle(&H, 0);
         ++cyc;
@@ -544,10 +603,46 @@ int or_cell_operator(const int n[3], int periodic, double h, double alpha, doubl
     return 0;
 }
 
-/* Refinement boundary values (Sec. III.C, IV.D): trilinear interpolation of a
- * cell-centred periodic parent field (np0,np1,np2 cells of size H) at the
- * centres of a patch's ghost cells.  The patch has n cells of size h; its cell
- * (0,0,0) starts at origin*h.  Output in the compact ghost order. */
+/* Trilinear interpolation of a cell-centred periodic parent field (np0,np1,np2
+ * cells of size H) at the centre of patch cell (i,j,k); the patch has cells of
+ * size h and its cell (0,0,0) starts at origin*h (Sec. III.C, IV.D: values on a
+ * refinement are interpolated from the coarser level). */
+static double parent_trilinear(const int np_[3], double H, const double *parent, double h, const int origin[3],
+                               int i, int j, int k) {
+    const int ii[3] = {i, j, k};
+    int base[3];
+    double t[3];
+    for (int d = 0; d < 3; ++d) {
+        const double x = (origin[d] + ii[d] + 0.5) * h;        /* box coordinate */
+        const double u = x / H - 0.5;                            /* parent index space */
+        const double fl = floor(u);
+        base[d] = (int)fl;
+        t[d] = u - fl;
+    }
+    double v = 0.0;
+    for (int c2 = 0; c2 < 2; ++c2)
+        for (int c1 = 0; c1 < 2; ++c1)
+            for (int c0 = 0; c0 < 2; ++c0) {
+                const double wgt = (c0 ? t[0] : 1 - t[0]) * (c1 ? t[1] : 1 - t[1]) * (c2 ? t[2] : 1 - t[2]);
+                const int I = wrap(base[0] + c0, np_[0]), J = wrap(base[1] + c1, np_[1]), K = wrap(base[2] + c2, np_[2]);
+                v += wgt * parent[((long)K * np_[1] + J) * np_[0] + I];
+            }
+    return v;
+}
+
+/* Initial guess on a refinement: the parent interpolated at every patch cell
+ * centre; output x-fastest n0*n1*n2. */
+int or_fill_interior(const int np_[3], double H, const double *parent, const int n[3], double h,
+                     const int origin[3], double *phi) {
+    long q = 0;
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) phi[q++] = parent_trilinear(np_, H, parent, h, origin, i, j, k);
+    return 0;
+}
+
+/* Refinement boundary values: the same interpolation at the centres of a
+ * patch's ghost cells, output in the compact ghost order. */
 int or_fill_ghosts(const int np_[3], double H, const double *parent, const int n[3], double h,
                    const int origin[3], double *ghost) {
     OGrid g = {{n[0], n[1], n[2]}, 0, h};
@@ -557,26 +652,7 @@ int or_fill_ghosts(const int np_[3], double H, const double *parent, const int n
             for (int i = -1; i <= n[0]; ++i) {
                 const int o = (i < 0 || i >= n[0]) + (j < 0 || j >= n[1]) + (k < 0 || k >= n[2]);
                 if (o == 0 || o == 3) continue;
-                const int ii[3] = {i, j, k};
-                int base[3];
-                double t[3];
-                for (int d = 0; d < 3; ++d) {
-                    const double x = (origin[d] + ii[d] + 0.5) * h;        /* box coordinate */
-                    const double u = x / H - 0.5;                            /* parent index space */
-                    const double fl = floor(u);
-                    base[d] = (int)fl;
-                    t[d] = u - fl;
-                }
-                double v = 0.0;
-                for (int c2 = 0; c2 < 2; ++c2)
-                    for (int c1 = 0; c1 < 2; ++c1)
-                        for (int c0 = 0; c0 < 2; ++c0) {
-                            const double wgt = (c0 ? t[0] : 1 - t[0]) * (c1 ? t[1] : 1 - t[1]) * (c2 ? t[2] : 1 - t[2]);
-                            const int I = wrap(base[0] + c0, np_[0]), J = wrap(base[1] + c1, np_[1]),
-                                      K = wrap(base[2] + c2, np_[2]);
-                            v += wgt * parent[((long)K * np_[1] + J) * np_[0] + I];
-                        }
-                pad[pidx(&g, i, j, k)] = v;
+                pad[pidx(&g, i, j, k)] = parent_trilinear(np_, H, parent, h, origin, i, j, k);
             }
     /* pad -> compact */
     const int n0 = n[0], n1 = n[1], n2 = n[2];

@@ -399,6 +399,21 @@ def test_cutout_reproduces_periodic(oracle_mod):
     assert relerr(phi_d, big[1:-1, 1:-1, 1:-1]) < 1e-11
 
 
+def test_dirichlet_vcycle_rate_independent_of_depth(oracle_mod):
+    """Coarse levels of a refinement carry the reflected correction, so the
+    V-cycle keeps its rate as levels are added: 16^3 (4 levels) and 32^3
+    (5 levels) reach the same residual reduction in the same number of cycles."""
+    cyc = {}
+    for n in (16, 32):
+        d = I.lognormal(n, 555, sigma=1.5)
+        rng = np.random.Generator(np.random.PCG64(1))
+        g = 2e-5 * rng.standard_normal(oracle_mod.ghost_count((n, n, n)))
+        _, info = oracle_mod.solve(d, 0.1, 1.5, h=1 / 512, ghost=g, tol=1e-10, max_cycles=40, nu1=1, nu2=1)
+        assert info["rms"] <= 1e-10
+        cyc[n] = info["cycles"]
+    assert abs(cyc[32] - cyc[16]) <= 3 and cyc[32] <= 25
+
+
 # ---------------------------------------------------------------------------
 # refinement boundary values: trilinear interpolation is exact for linear fields
 # ---------------------------------------------------------------------------
@@ -414,6 +429,30 @@ def test_ghost_fill_exact_for_linear(oracle_mod):
     P[...] = (0.3 * c(origin[0])[None, None, :] - 0.7 * c(origin[1])[None, :, None]
               + 1.1 * c(origin[2])[:, None, None])
     assert np.abs(g - pack_ghosts(P)).max() < 1e-14
+
+
+def test_interior_fill_exact_for_linear(oracle_mod):
+    npar = 16
+    x, y, z = I.cell_centres(npar)
+    parent = (0.3 * x[None, None, :] - 0.7 * y[None, :, None] + 1.1 * z[:, None, None])
+    n, h, origin = (8, 6, 5), 1.0 / 64, (12, 20, 17)
+    got = oracle_mod.fill_interior(parent, n, h, origin)
+    c = lambda o, m: (o + np.arange(m) + 0.5) * h
+    want = (0.3 * c(origin[0], n[0])[None, None, :] - 0.7 * c(origin[1], n[1])[None, :, None]
+            + 1.1 * c(origin[2], n[2])[:, None, None])
+    assert got.shape == (5, 6, 8)
+    assert np.abs(got - want).max() < 1e-14
+
+
+def test_interior_fill_same_spacing_is_a_copy(oracle_mod):
+    # a patch with the parent's own cell size samples the parent at its own
+    # cell centres (all interpolation weights 0 or 1), wrapping periodically
+    rng = np.random.Generator(np.random.PCG64(3))
+    parent = rng.standard_normal((12, 10, 8))
+    n, origin = (5, 6, 7), (6, 7, 9)
+    got = oracle_mod.fill_interior(parent, n, 1.0 / 8, origin)
+    want = np.roll(parent, (-origin[2], -origin[1], -origin[0]), axis=(0, 1, 2))[:7, :6, :5]
+    assert np.array_equal(got, want)
 
 
 def test_ghost_fill_periodic_wrap(oracle_mod):
