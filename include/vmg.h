@@ -163,6 +163,17 @@ vmg_status vmg_fill_ghosts(const double *parent, const int32_t np[3], double par
                            const vmg_grid *grids, const int32_t *origins, int32_t n_grids,
                            double *ghost, hipStream_t stream);
 
+/* Initial guess on refinements (Sec. III.C, IV.D: a refinement starts from the
+ * solution of the coarser level, interpolated): the same trilinear
+ * interpolation of the periodic parent as vmg_fill_ghosts, at every cell centre
+ * of each grid, written to phi (device) at each grid's offset, x fastest.
+ * Starting a refinement from zero instead of from this guess leaves a jump of
+ * the boundary values across the outermost cells, which the nonlinear operator
+ * turns into a long slow phase of the solve.  Errors: VMG_EINVAL, VMG_EHIP. */
+vmg_status vmg_fill_interior(const double *parent, const int32_t np[3], double parent_h,
+                             const vmg_grid *grids, const int32_t *origins, int32_t n_grids,
+                             double *phi, hipStream_t stream);
+
 /* Number of ghost values of a Dirichlet grid with n cells per axis. */
 int64_t vmg_ghost_count(const int32_t n[3]);
 
@@ -179,6 +190,14 @@ vmg_status vmg_smooth(vmg_plan *plan, int32_t sweeps);
  * finest_cells  = cells of the finest level(s) per sweep. */
 vmg_status vmg_plan_stats(const vmg_plan *plan, int64_t *cell_updates, int64_t *finest_sweeps,
                           int64_t *finest_cells);
+
+/* Schedule a plan uses (host pointers, each may be NULL): tile height and
+ * z-chunk of the fused sweep (chosen by the autotuner with VMG_AUTOTUNE, which
+ * times the finest-level smoother for heights {4,8,16} x chunks {8,16,32} at
+ * plan creation; Sec. V of the paper notes the code needed more tuning),
+ * pre/post sweeps and coarsest-level sweeps.  Errors: VMG_EINVAL. */
+vmg_status vmg_plan_config(const vmg_plan *plan, int32_t *tile_y, int32_t *z_chunk, int32_t *nu1,
+                           int32_t *nu2, int32_t *coarse_sweeps);
 
 #ifdef __cplusplus
 }

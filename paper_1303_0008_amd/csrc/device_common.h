@@ -139,6 +139,58 @@ __device__ __forceinline__ double cell_residual(const Geom& g, const Coef& c, co
     return (S - 6.0 * pc) * inv_h2 - Q - fv + cb;
 }
 
+// Mirror an index that lies one cell outside [0, n) back inside; each mirrored
+// axis flips the sign of a correction (homogeneous Dirichlet data on the cell
+// faces of a cell-centred grid).
+__device__ __forceinline__ int mirror(int i, int n, int& sign) {
+    if (i < 0) { sign = -sign; return 0; }
+    if (i >= n) { sign = -sign; return n - 1; }
+    return i;
+}
+
+__device__ __forceinline__ int64_t ghost_count_dev(int n0, int n1, int n2) {
+    return 2 * ((int64_t)n1 * n2 + (int64_t)n0 * n2 + (int64_t)n0 * n1) + 4 * ((int64_t)n0 + n1 + n2);
+}
+
+// Decode a compact ghost index into cell coordinates (i, j, k) in [-1, n].
+__device__ __forceinline__ void ghost_coords(int n0, int n1, int n2, int64_t q, int& i, int& j, int& k) {
+    const int64_t fx = (int64_t)n1 * n2, fy = (int64_t)n0 * n2, fz = (int64_t)n0 * n1;
+    if (q < 2 * fx) { const int s = (int)(q / fx); const int64_t r = q % fx;
+        i = s ? n0 : -1; j = (int)(r % n1); k = (int)(r / n1); return; }
+    q -= 2 * fx;
+    if (q < 2 * fy) { const int s = (int)(q / fy); const int64_t r = q % fy;
+        j = s ? n1 : -1; i = (int)(r % n0); k = (int)(r / n0); return; }
+    q -= 2 * fy;
+    if (q < 2 * fz) { const int s = (int)(q / fz); const int64_t r = q % fz;
+        k = s ? n2 : -1; i = (int)(r % n0); j = (int)(r / n0); return; }
+    q -= 2 * fz;
+    if (q < 4 * (int64_t)n0) { const int e = (int)(q / n0);
+        i = (int)(q % n0); j = (e & 1) ? n1 : -1; k = (e & 2) ? n2 : -1; return; }
+    q -= 4 * (int64_t)n0;
+    if (q < 4 * (int64_t)n1) { const int e = (int)(q / n1);
+        j = (int)(q % n1); i = (e & 1) ? n0 : -1; k = (e & 2) ? n2 : -1; return; }
+    q -= 4 * (int64_t)n1;
+    const int e = (int)(q / n2);
+    k = (int)(q % n2); i = (e & 1) ? n0 : -1; j = (e & 2) ? n1 : -1;
+}
+
+// Coarse Dirichlet ghost refresh: ghost = reference + (-1)^k (u - ref) at the mirrored
+// interior cell, i.e. the coarse correction u - ref vanishes on the grid faces.
+template <typename T>
+__global__ void k_ghost_refresh_batch(const Geom* __restrict__ gs, const int2* __restrict__ items, T* u,
+                                      const T* __restrict__ ref) {
+    const int2 w = items[blockIdx.x];
+    const Geom g = gs[w.x];
+    const int64_t q = (int64_t)w.y + threadIdx.x;
+    if (q >= ghost_count_dev(g.n0, g.n1, g.n2)) return;
+    int i, j, k;
+    ghost_coords(g.n0, g.n1, g.n2, q, i, j, k);
+    int sign = 1;
+    const int ir = mirror(i, g.n0, sign), jr = mirror(j, g.n1, sign), kr = mirror(k, g.n2, sign);
+    const int64_t gi = cell_index(g, i, j, k), ii = cell_index(g, ir, jr, kr);
+    u[gi] = ref[gi] + (T)sign * (u[ii] - ref[ii]);
+}
+
 static inline int grid_for(int64_t n, int cap = 65536) {
     int64_t b = (n + NT - 1) / NT;
     if (b < 1) b = 1;

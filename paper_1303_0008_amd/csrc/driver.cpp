@@ -89,7 +89,7 @@ vmg_status build_plan(Plan* P, const vmg_grid* grids, int n_grids, const vmg_par
     P->nu1 = p->nu1;
     P->nu2 = p->nu2;
     if (P->nu1 == 0 && P->nu2 == 0) { P->nu1 = 2; P->nu2 = 2; }
-    P->ncoarse = 40;
+    P->ncoarse = 20;
     P->cfg.ty = 8;
     P->cfg.zc = 16;
     P->periodic = grids[0].bc == VMG_PERIODIC;
@@ -112,43 +112,53 @@ vmg_status build_plan(Plan* P, const vmg_grid* grids, int n_grids, const vmg_par
         max_cells = std::max<int64_t>(max_cells, G.lev[0].g.ncell);
         P->grids.push_back(G);
     }
-    // allocations
-    for (auto& G : P->grids) {
-        for (size_t l = 0; l < G.lev.size(); ++l) {
-            LevelBuf& L = G.lev[l];
-            const size_t bytes = sizeof(double) * (size_t)L.g.nstore;
-            vmg_status st;
-            if ((st = dalloc(P, (void**)&L.phi[0], bytes)) != VMG_OK) return st;
-            if ((st = dalloc(P, (void**)&L.phi[1], bytes)) != VMG_OK) return st;
-            if ((st = dalloc(P, (void**)&L.delta, bytes)) != VMG_OK) return st;
-            if ((st = dalloc(P, (void**)&L.f, bytes)) != VMG_OK) return st;
-            if (l > 0) {
-                if ((st = dalloc(P, (void**)&L.phiold, bytes)) != VMG_OK) return st;
-                if ((st = dalloc(P, (void**)&L.rd, bytes)) != VMG_OK) return st;
-            }
-            if ((st = dalloc(P, (void**)&L.sc, sizeof(LevelScalars))) != VMG_OK) return st;
-            CKH(launch_fill(L.phi[0], L.g.nstore, 0.0, stream));
-            CKH(launch_fill(L.phi[1], L.g.nstore, 0.0, stream));
-            CKH(launch_fill(L.f, L.g.nstore, 0.0, stream));
-            CKH(launch_fill(L.delta, L.g.nstore, 0.0, stream));
-            if (l > 0) {
-                CKH(launch_fill(L.phiold, L.g.nstore, 0.0, stream));
-                CKH(launch_fill(L.rd, L.g.nstore, 0.0, stream));
-            }
-            CKH(launch_fill((double*)L.sc, sizeof(LevelScalars) / sizeof(double), 0.0, stream));
-        }
-        vmg_status st;
-        if ((st = dalloc(P, (void**)&G.norm_dev, sizeof(NormOut))) != VMG_OK) return st;
-    }
-    const int nb = partial_blocks_for(max_cells);
-    vmg_status st;
     P->mixed = p->prec == VMG_MIXED;
-    if (P->mixed && (st = alloc_mixed(P)) != VMG_OK) return st;
+    P->batched = !P->periodic;
+    vmg_status st;
+    if (P->batched) {
+        if ((st = build_batch(P)) != VMG_OK) return st;
+    } else {
+        for (auto& G : P->grids) {
+            for (size_t l = 0; l < G.lev.size(); ++l) {
+                LevelBuf& L = G.lev[l];
+                const size_t bytes = sizeof(double) * (size_t)L.g.nstore;
+                if ((st = dalloc(P, (void**)&L.phi[0], bytes)) != VMG_OK) return st;
+                if ((st = dalloc(P, (void**)&L.phi[1], bytes)) != VMG_OK) return st;
+                if ((st = dalloc(P, (void**)&L.delta, bytes)) != VMG_OK) return st;
+                if ((st = dalloc(P, (void**)&L.f, bytes)) != VMG_OK) return st;
+                if (l > 0) {
+                    if ((st = dalloc(P, (void**)&L.phiold, bytes)) != VMG_OK) return st;
+                    if ((st = dalloc(P, (void**)&L.rd, bytes)) != VMG_OK) return st;
+                }
+                if ((st = dalloc(P, (void**)&L.sc, sizeof(LevelScalars))) != VMG_OK) return st;
+                CKH(launch_fill(L.phi[0], L.g.nstore, 0.0, stream));
+                CKH(launch_fill(L.phi[1], L.g.nstore, 0.0, stream));
+                CKH(launch_fill(L.f, L.g.nstore, 0.0, stream));
+                CKH(launch_fill(L.delta, L.g.nstore, 0.0, stream));
+                if (l > 0) {
+                    CKH(launch_fill(L.phiold, L.g.nstore, 0.0, stream));
+                    CKH(launch_fill(L.rd, L.g.nstore, 0.0, stream));
+                }
+                CKH(launch_fill((double*)L.sc, sizeof(LevelScalars) / sizeof(double), 0.0, stream));
+            }
+        }
+        if (P->mixed && (st = alloc_mixed(P)) != VMG_OK) return st;
+    }
+    for (auto& G : P->grids)
+        if ((st = dalloc(P, (void**)&G.norm_dev, sizeof(NormOut))) != VMG_OK) return st;
+    int64_t nb = partial_blocks_for(max_cells);
+    for (auto& G : P->grids)
+        for (auto& L : G.lev) nb = std::max<int64_t>(nb, resid_blocks(L.g));
+    nb = std::max<int64_t>(nb, batch_partials_needed(P));
     if ((st = dalloc(P, (void**)&P->partials, sizeof(double) * R_NSLOT * (size_t)nb)) != VMG_OK) return st;
     if (hipHostMalloc((void**)&P->host_norm, sizeof(NormOut) * P->grids.size(), hipHostMallocDefault) !=
         hipSuccess)
         return fail(VMG_ENOMEM, "hipHostMalloc failed");
     CKH(hipStreamSynchronize(stream));
+    if (p->flags & VMG_AUTOTUNE) {
+        if ((st = autotune(P)) != VMG_OK) return st;
+        CKH(hipStreamSynchronize(stream));
+    }
     return VMG_OK;
 }
 
@@ -177,6 +187,8 @@ static hipError_t smooth_level(Plan* P, GridState& G, int l) {
     if (l == 0) P->finest_sweeps += 1;
     return e;
 }
+
+hipError_t smooth_level_public(Plan* P, GridState& G, int l) { return smooth_level(P, G, l); }
 
 static hipError_t vcycle(Plan* P, GridState& G, int l) {
     LevelBuf& L = G.lev[l];
@@ -236,11 +248,16 @@ static hipError_t enqueue_cycle(Plan* P) {
     return hipSuccess;
 }
 
-static hipError_t enqueue_iteration(Plan* P) { return P->mixed ? enqueue_outer(P) : enqueue_cycle(P); }
+static hipError_t enqueue_iteration(Plan* P) {
+    if (P->batched) return batch_enqueue_iteration(P);
+    return P->mixed ? enqueue_outer(P) : enqueue_cycle(P);
+}
+
+static int finest_parity(const Plan* P) { return P->batched ? batch_parity(P) : P->grids[0].lev[0].cur; }
 
 static vmg_status run_cycle(Plan* P) {
     const bool use_graph = (P->params.flags & VMG_GRAPH) != 0;
-    const int parity = P->grids[0].lev[0].cur;
+    const int parity = finest_parity(P);
     if (!use_graph) {
         CKH(enqueue_iteration(P));
         CKH(hipStreamSynchronize(P->stream));
@@ -250,6 +267,7 @@ static vmg_status run_cycle(Plan* P) {
         // capture the cycle once for this ping-pong parity of the finest level
         std::vector<int> saved;
         for (auto& G : P->grids) saved.push_back(G.lev[0].cur);
+        const int saved_b = finest_parity(P);
         const int64_t cu = P->cell_updates, fs = P->finest_sweeps;
         hipGraph_t graph;
         CKH(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
@@ -263,6 +281,7 @@ static vmg_status run_cycle(Plan* P) {
         P->cycle_updates = P->cell_updates - cu;
         P->cycle_finest = P->finest_sweeps - fs;
         for (size_t gi = 0; gi < P->grids.size(); ++gi) P->grids[gi].lev[0].cur = saved[gi];
+        if (P->batched && batch_parity(P) != saved_b) batch_flip_parity(P);
         P->cell_updates = cu;
         P->finest_sweeps = fs;
     }
@@ -271,9 +290,17 @@ static vmg_status run_cycle(Plan* P) {
     // the captured cycle flips the finest level exactly as the eager one would
     P->cell_updates += P->cycle_updates;
     P->finest_sweeps += P->cycle_finest;
-    if (!P->mixed)   // the mixed path updates phi in place
-        for (auto& G : P->grids)
-            if ((P->nu1 + P->nu2) & 1) G.lev[0].cur ^= 1;
+    // the captured iteration leaves the finest phi in the other buffer when it
+    // did an odd number of FP64 sweeps, and always on the periodic mixed path
+    // (its update pass writes phi + e to the second buffer); the batched mixed
+    // path updates in place
+    const bool flip = P->mixed ? !P->batched : ((P->nu1 + P->nu2) & 1) != 0;
+    if (flip) {
+        if (P->batched)
+            batch_flip_parity(P);
+        else
+            for (auto& G : P->grids) G.lev[0].cur ^= 1;
+    }
     return VMG_OK;
 }
 
@@ -286,18 +313,25 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
     P->finest_sweeps = 0;
     // ---- inputs -> plan buffers ------------------------------------------
     int nb = 0;
-    for (auto& G : P->grids) {
-        LevelBuf& L0 = G.lev[0];
-        const double* d_in = delta + G.desc.offset;
-        CKH(launch_check_finite(d_in, L0.g.ncell, P->partials, &nb, s));
-        CKH(launch_finalize(P->partials, nb, L0.g.ncell, 0, 0, L0.sc, G.norm_dev, s));
-        CKH(hipMemcpyAsync(&P->host_norm[&G - &P->grids[0]], G.norm_dev, sizeof(NormOut),
-                           hipMemcpyDeviceToHost, s));
+    if (P->batched) {
+        CKH(batch_check_delta(P, delta));
+    } else {
+        for (auto& G : P->grids) {
+            LevelBuf& L0 = G.lev[0];
+            const double* d_in = delta + G.desc.offset;
+            CKH(launch_check_finite(d_in, L0.g.ncell, P->partials, &nb, s));
+            CKH(launch_finalize(P->partials, nb, L0.g.ncell, 0, 0, L0.sc, G.norm_dev, s));
+            CKH(hipMemcpyAsync(&P->host_norm[&G - &P->grids[0]], G.norm_dev, sizeof(NormOut),
+                               hipMemcpyDeviceToHost, s));
+        }
     }
     CKH(hipStreamSynchronize(s));
     for (size_t gi = 0; gi < P->grids.size(); ++gi)
         if (P->host_norm[gi].n_nonfinite > 0)
             return fail(VMG_ENONFINITE, "non-finite values in delta of grid " + std::to_string(gi));
+    if (P->batched) {
+        CKH(batch_setup(P, delta, ghost, source, phi));
+    } else {
     for (auto& G : P->grids) {
         LevelBuf& L0 = G.lev[0];
         L0.cur = 0;
@@ -328,6 +362,7 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
         for (size_t gi = 0; gi < P->grids.size(); ++gi)
             CKH(hipMemcpyAsync(&P->host_norm[gi], P->grids[gi].norm_dev, sizeof(NormOut),
                                hipMemcpyDeviceToHost, s));
+    }
     }
     CKH(hipStreamSynchronize(s));
     const int ng = (int)P->grids.size();
@@ -368,11 +403,14 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
         }
     }
     // ---- outputs -------------------------------------------------------------
+    if (P->batched) CKH(batch_outputs(P, phi));
     for (int gi = 0; gi < ng; ++gi) {
         GridState& G = P->grids[gi];
         LevelBuf& L0 = G.lev[0];
-        if (!L0.g.dir) CKH(launch_gauge(L0.g, L0.phi[L0.cur], G.norm_dev, s));
-        CKH(launch_copy_out(L0.g, L0.phi[L0.cur], phi + G.desc.offset, s));
+        if (!P->batched) {
+            if (!L0.g.dir) CKH(launch_gauge(L0.g, L0.phi[L0.cur], G.norm_dev, s));
+            CKH(launch_copy_out(L0.g, L0.phi[L0.cur], phi + G.desc.offset, s));
+        }
         if (out) {
             out[gi].rms0 = rms0[gi];
             out[gi].rms = P->host_norm[gi].rms;
@@ -544,13 +582,45 @@ vmg_status vmg_fill_ghosts(const double* parent, const int32_t np[3], double par
     return VMG_OK;
 }
 
+vmg_status vmg_fill_interior(const double* parent, const int32_t np[3], double parent_h, const vmg_grid* grids,
+                             const int32_t* origins, int32_t n_grids, double* phi, hipStream_t stream) {
+    g_err.clear();
+    if (!parent || !np || !grids || !origins || !phi || n_grids < 1) return fail(VMG_EINVAL, "null argument");
+    if (np[0] < 1 || np[1] < 1 || np[2] < 1 || !(parent_h > 0.0)) return fail(VMG_EINVAL, "bad parent grid");
+    for (int i = 0; i < n_grids; ++i) {
+        const vmg_grid& g = grids[i];
+        if (g.n[0] < 1 || g.n[1] < 1 || g.n[2] < 1 || !(g.h > 0.0) || g.offset < 0)
+            return fail(VMG_EINVAL, "interior fill needs grids with n >= 1, h > 0 and offset >= 0");
+        CKH(launch_interior_fill(parent, np[0], np[1], np[2], parent_h, g.n[0], g.n[1], g.n[2], g.h,
+                                 origins[3 * i], origins[3 * i + 1], origins[3 * i + 2], phi + g.offset, stream));
+    }
+    return VMG_OK;
+}
+
 vmg_status vmg_smooth(vmg_plan* plan, int32_t sweeps) {
     g_err.clear();
     if (!plan || sweeps < 0) return fail(VMG_EINVAL, "null plan or sweeps < 0");
     Plan* P = reinterpret_cast<Plan*>(plan);
     if (!P->solved) return fail(VMG_EINVAL, "vmg_smooth needs a previous vmg_solve");
-    for (int s = 0; s < sweeps; ++s)
+    for (int s = 0; s < sweeps; ++s) {
+        if (P->batched) {
+            CKH(batch_smooth_finest(P));
+            continue;
+        }
         for (auto& G : P->grids) CKH(P->mixed ? smooth_corr_level(P, G, 0) : smooth_level(P, G, 0));
+    }
+    return VMG_OK;
+}
+
+vmg_status vmg_plan_config(const vmg_plan* plan, int32_t* tile_y, int32_t* z_chunk, int32_t* nu1, int32_t* nu2,
+                           int32_t* coarse_sweeps) {
+    if (!plan) return fail(VMG_EINVAL, "null plan");
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (tile_y) *tile_y = P->cfg.ty;
+    if (z_chunk) *z_chunk = P->cfg.zc;
+    if (nu1) *nu1 = P->nu1;
+    if (nu2) *nu2 = P->nu2;
+    if (coarse_sweeps) *coarse_sweeps = P->ncoarse;
     return VMG_OK;
 }
 

@@ -41,35 +41,61 @@ struct SmoothArgs {
     int zc, tiles_x, tiles_y;
 };
 
+// Neighbourhood of a cell read from a parity-split LDS plane set.  `c` is the
+// word offset of the cell's row-half position for the neighbours in its own
+// x parity class (x-1 at c, x+1 at c+1), `o` the offset of the cell itself in
+// the other class (used for the y and z neighbours); W is the row length in
+// words; Pm/Pc/Pp the planes below, at and above the cell.
+template <int W>
+__device__ __forceinline__ void nb_split(const double* __restrict__ Pm, const double* __restrict__ Pc,
+                                         const double* __restrict__ Pp, int c, int o, Nb& v) {
+    v.xm = Pc[c];           v.xp = Pc[c + 1];
+    v.xmym = Pc[c - W];     v.xpym = Pc[c - W + 1];
+    v.xmyp = Pc[c + W];     v.xpyp = Pc[c + W + 1];
+    v.xmzm = Pm[c];         v.xpzm = Pm[c + 1];
+    v.xmzp = Pp[c];         v.xpzp = Pp[c + 1];
+    v.ym = Pc[o - W];       v.yp = Pc[o + W];
+    v.zm = Pm[o];           v.zp = Pp[o];
+    v.ymzm = Pm[o - W];     v.ypzm = Pm[o + W];
+    v.ymzp = Pp[o - W];     v.ypzp = Pp[o + W];
+}
+
 template <int TY, int DIR, bool HAS_F>
 __device__ __forceinline__ void smooth_brick(const SmoothArgs& a, const int x0, const int y0, const int z0,
                                              const int z1) {
     constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
-    constexpr int NP2 = W2 * H2, NP1 = W1 * H1;
-    constexpr int NL2 = (NP2 + NT - 1) / NT, NL1 = (NP1 + NT - 1) / NT;
+    constexpr int HW2 = W2 / 2, HW1 = W1 / 2;     // half-row lengths (34, 33)
+    constexpr int NP2 = W2 * H2;
+    constexpr int NL2 = (NP2 + NT - 1) / NT;
     constexpr int RH = W1 / 2;        // red/black pairs per ring-1 row
     constexpr int BH = TX / 2;        // black cells per interior row
-    __shared__ double P0[3][H2][W2];  // phi^0, ring 2, slot = z mod 3
-    __shared__ double P1[3][H1][W1];  // phi^1, ring 1
-    __shared__ double DL[3][H1][W1];  // delta, ring 1
-    __shared__ double FF[HAS_F ? 3 : 1][HAS_F ? H1 : 1][HAS_F ? W1 : 1];
+    constexpr int NR = (RH * H1 + NT - 1) / NT;   // red cells per thread
+    constexpr int NB = (BH * TY + NT - 1) / NT;   // black cells per thread
+    constexpr int S2 = H2 * W2, S1 = H1 * W1;     // words per plane
+    // Rows are stored split by x parity: word (Y, X) lives at Y*W + (X&1)*W/2 + (X>>1),
+    // so lanes working on every other cell of a row touch consecutive words.
+    __shared__ double P0[3 * S2];  // phi^0, ring 2, slot = z mod 3
+    __shared__ double P1[3 * S1];  // phi^1 (red computed, black copied), ring 1
 
     const Geom& g = a.g;
     const int tid = threadIdx.x;
-
+    if (z0 >= g.n2) return;
     const double h2 = g.h * g.h, inv_h4 = 1.0 / (h2 * h2);
     const double cb = DIR ? 0.0 : a.sc->cbar;
 
-    // per-thread in-plane offsets of the ring-2 (phi) and ring-1 (delta, f) slots
-    int off2[NL2], off1[NL1];
-    bool ok2[NL2], ok1[NL1];
+    // ---- per-thread constants (everything that does not depend on z) -------
+    int off2[NL2], lds2[NL2];
+    bool ok2[NL2];
 #pragma unroll
     for (int s = 0; s < NL2; ++s) {
         const int e = tid + s * NT;
         ok2[s] = false;
         off2[s] = 0;
+        lds2[s] = 0;
         if (e < NP2) {
-            int gx = x0 - 2 + e % W2, gy = y0 - 2 + e / W2;
+            const int X = e % W2, Y = e / W2;
+            lds2[s] = Y * W2 + (X & 1) * HW2 + (X >> 1);
+            int gx = x0 - 2 + X, gy = y0 - 2 + Y;
             if (DIR) {
                 ok2[s] = gx >= -1 && gx <= g.n0 && gy >= -1 && gy <= g.n1;
             } else {
@@ -80,162 +106,180 @@ __device__ __forceinline__ void smooth_brick(const SmoothArgs& a, const int x0, 
             off2[s] = (int)(g.off0 + gx + (int64_t)gy * g.sy);
         }
     }
+    // red cells: ring-1 row r, pair m; parity par = (y0 + r + p) & 1 puts the red cell at
+    // ring-1 column 2m + par and the black one at 2m + 1 - par
+    bool rv[NR];              // slot exists
+    int rpar0[NR];            // parity at p = 0
+    int rc[NR][2], ro[NR][2]; // nb_split offsets in P0 (ring 2) for each parity
+    int rw[NR][2], rb[NR][2]; // P1 words of the red and the black cell
+    int rsrc[NR][2];          // P0 word of the black cell (copied into P1)
+    int rg[NR][2];            // global in-plane index of the red cell (-1: not a cell)
 #pragma unroll
-    for (int s = 0; s < NL1; ++s) {
-        const int e = tid + s * NT;
-        ok1[s] = false;
-        off1[s] = 0;
-        if (e < NP1) {
-            int gx = x0 - 1 + e % W1, gy = y0 - 1 + e / W1;
+    for (int q = 0; q < NR; ++q) {
+        const int e = tid + q * NT;
+        rv[q] = e < RH * H1;
+        const int r = rv[q] ? e / RH : 0, m = rv[q] ? e - r * RH : 0;
+        rpar0[q] = (y0 + r) & 1;
+        const int gy = y0 - 1 + r;
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            const int Y = r + 1;                                  // ring-2 row
+            rc[q][par] = Y * W2 + par * HW2 + m;                  // x-1 of the red cell (X = 2m+par+1)
+            ro[q][par] = Y * W2 + (1 - par) * HW2 + m + par;      // the red cell itself
+            rw[q][par] = r * W1 + par * HW1 + m;                  // ring-1 column 2m+par
+            rb[q][par] = r * W1 + (1 - par) * HW1 + m;            // ring-1 column 2m+1-par
+            rsrc[q][par] = Y * W2 + par * HW2 + m + 1 - par;      // ring-2 column 2m+2-par
+            int gx = x0 - 1 + 2 * m + par, wy = gy;
             if (DIR) {
-                ok1[s] = gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1;
+                rg[q][par] = (rv[q] && gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1)
+                                 ? (int)(g.off0 + gx + (int64_t)gy * g.sy) : -1;
             } else {
                 gx = wrapi(gx, g.n0);
-                gy = wrapi(gy, g.n1);
-                ok1[s] = true;
+                wy = wrapi(gy, g.n1);
+                rg[q][par] = rv[q] ? (int)(gx + (int64_t)wy * g.sy) : -1;
             }
-            off1[s] = (int)(g.off0 + gx + (int64_t)gy * g.sy);
         }
     }
-    auto plane_z = [&](int t, bool& zok) -> int64_t {
+    // black cells: interior row r, pair m; black at column 2m + ((y0 + r + p2 + 1) & 1)
+    bool bv[NB];
+    int bpar0[NB];
+    int bc[NB][2], bo[NB][2], brd[NB][2];
+    int64_t brow[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int e = tid + q * NT;
+        const int r = e / BH, m = e - (e / BH) * BH;
+        const int gy = y0 + r;
+        bv[q] = e < BH * TY && gy < g.n1;
+        bpar0[q] = (y0 + r + 1) & 1;
+        brow[q] = g.off0 + (int64_t)gy * g.sy + x0 + 2 * m;
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            const int Y = r + 1;                                   // ring-1 row
+            bc[q][par] = Y * W1 + par * HW1 + m;                   // x-1 of the black cell (X = 2m+par+1)
+            bo[q][par] = Y * W1 + (1 - par) * HW1 + m + par;       // the black cell itself
+            brd[q][par] = Y * W1 + par * HW1 + m + 1 - par;        // red partner at column 2m+2-par
+        }
+    }
+    const int bxmax = g.n0 - x0;   // columns >= bxmax are outside the grid
+    auto plane_off = [&](int t, bool& zok) -> int64_t {
         int gz;
         if (DIR) { gz = t; zok = t >= -1 && t <= g.n2; }
-        else { gz = wrapi(t, g.n2); zok = true; }
+        else { gz = t < 0 ? t + g.n2 : (t >= g.n2 ? t - g.n2 : t); zok = true; }
         return (int64_t)gz * g.sz;
     };
     auto load_phi = [&](int t, double (&r)[NL2]) {
         bool zok;
-        const int64_t zo = plane_z(t, zok);
+        const int64_t zo = plane_off(t, zok);
 #pragma unroll
-        for (int s = 0; s < NL2; ++s) r[s] = (ok2[s] && zok && tid + s * NT < NP2) ? a.pin[zo + off2[s]] : 0.0;
+        for (int s = 0; s < NL2; ++s) r[s] = (ok2[s] && zok) ? a.pin[zo + off2[s]] : 0.0;
     };
-    auto load_r1 = [&](const double* src, int t, double (&r)[NL1]) {
-        bool zok;
-        const int64_t zo = plane_z(t, zok);
-        if (DIR) zok = t >= 0 && t < g.n2;
-#pragma unroll
-        for (int s = 0; s < NL1; ++s) r[s] = (ok1[s] && zok && tid + s * NT < NP1) ? src[zo + off1[s]] : 0.0;
-    };
-    auto store2 = [&](double* dst, const double (&r)[NL2]) {
+    auto store_phi = [&](int sl, const double (&r)[NL2]) {
 #pragma unroll
         for (int s = 0; s < NL2; ++s)
-            if (tid + s * NT < NP2) dst[tid + s * NT] = r[s];
-    };
-    auto store1 = [&](double* dst, const double (&r)[NL1]) {
-#pragma unroll
-        for (int s = 0; s < NL1; ++s)
-            if (tid + s * NT < NP1) dst[tid + s * NT] = r[s];
+            if (tid + s * NT < NP2) P0[sl * S2 + lds2[s]] = r[s];
     };
     auto slot = [](int z) { return (z + 3) % 3; };   // z >= -2
 
-    // prologue: phi^0 planes z0-2 .. z0, delta (and f) plane z0-1
+    double rd_dl[NR], rd_f[NR], bk_dl[NB], bk_f[NB];
+    auto fetch_red = [&](int p, double (&dl)[NR], double (&ff)[NR]) {
+        bool zok;
+        int64_t zo = plane_off(p, zok);
+        if (DIR) zok = p >= 0 && p < g.n2;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const int par = (rpar0[q] + p) & 1;
+            const int gi = rg[q][par];
+            const bool ok = zok && gi >= 0;
+            dl[q] = ok ? a.delta[zo + gi] : 0.0;
+            ff[q] = (HAS_F && ok) ? a.f[zo + gi] : 0.0;
+        }
+    };
+    auto fetch_black = [&](int p2, double (&dl)[NB], double (&ff)[NB]) {
+        const int64_t zo = (int64_t)p2 * g.sz;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int par = (bpar0[q] + p2) & 1;
+            const bool ok = bv[q] && 2 * (tid + q * NT - ((tid + q * NT) / BH) * BH) + par < bxmax;
+            const int64_t gi = zo + brow[q] + par;
+            dl[q] = ok ? a.delta[gi] : 0.0;
+            ff[q] = (HAS_F && ok) ? a.f[gi] : 0.0;
+        }
+    };
+
+    // prologue: phi^0 planes z0-2 .. z0; sources of the first red plane
     {
-        double r2[NL2], r1[NL1];
+        double r2[NL2];
         for (int t = z0 - 2; t <= z0; ++t) {
             load_phi(t, r2);
-            store2(&P0[slot(t)][0][0], r2);
+            store_phi(slot(t), r2);
         }
-        load_r1(a.delta, z0 - 1, r1);
-        store1(&DL[slot(z0 - 1)][0][0], r1);
-        if (HAS_F) {
-            load_r1(a.f, z0 - 1, r1);
-            store1(&FF[slot(z0 - 1)][0][0], r1);
-        }
+        fetch_red(z0 - 1, rd_dl, rd_f);
     }
     __syncthreads();
 
     for (int t = z0; t <= z1 + 1; ++t) {
-        // ---- prefetch phi^0 plane t+1 and delta (f) plane t into registers ----
-        double nphi[NL2], ndl[NL1], nf[NL1];
-        const bool pf_phi = t + 1 <= z1 + 1, pf_dl = t <= z1;
+        const int p = t - 1, p2 = t - 2;
+        // ---- prefetch: phi^0 plane t+1, sources of the next red (t) and black (t-1) planes
+        double nphi[NL2], nrd[NR], nrf[NR], nbd[NB], nbf[NB];
+        const bool pf_phi = t + 1 <= z1 + 1, pf_red = t <= z1, pf_blk = t - 1 >= z0 && t - 1 < z1;
         if (pf_phi) load_phi(t + 1, nphi);
-        if (pf_dl) {
-            load_r1(a.delta, t, ndl);
-            if (HAS_F) load_r1(a.f, t, nf);
-        }
-        // ---- red phase on plane p = t-1, ring 1: P0 -> P1 ----------------------
+        if (pf_red) fetch_red(t, nrd, nrf);
+        if (pf_blk) fetch_black(t - 1, nbd, nbf);
+        // ---- red phase on plane p, ring 1: P0 -> P1 ---------------------------
         {
-            const int p = t - 1;
-            const double(*Pm)[W2] = P0[slot(p - 1)];
-            const double(*Pc)[W2] = P0[slot(p)];
-            const double(*Pp)[W2] = P0[slot(p + 1)];
-            const double(*Dc)[W1] = DL[slot(p)];
-            double(*Q1)[W1] = P1[slot(p)];
-            const bool pzok = DIR ? (p >= 0 && p < g.n2) : true;
-            for (int e = tid; e < RH * H1; e += NT) {
-                const int r = e / RH, m = e - r * RH;
-                const int gy = y0 - 1 + r;
-                const int odd = (gy + p + 1) & 1;
-                const int lx = 2 * m + odd;            // red ring-1 column
-                const int lb = 2 * m + 1 - odd;        // black ring-1 column (copied)
-                const int gx = x0 - 1 + lx;
-                const int X = lx + 1, Y = r + 1;       // ring-2 coordinates
-                bool interior = true;
-                if (DIR) interior = pzok && gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1;
-                double val = Pc[Y][X];
+            const double* Pm = P0 + slot(p - 1) * S2;
+            const double* Pc = P0 + slot(p) * S2;
+            const double* Pp = P0 + slot(p + 1) * S2;
+            double* Q1 = P1 + slot(p) * S1;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                if (!rv[q]) continue;
+                const int par = (rpar0[q] + p) & 1;
+                const int c = rc[q][par], o = ro[q][par];
+                double val = Pc[o];
+                const bool interior = DIR ? (rg[q][par] >= 0 && p >= 0 && p < g.n2) : true;
                 if (interior) {
                     Nb v;
-                    v.xm = Pc[Y][X - 1]; v.xp = Pc[Y][X + 1];
-                    v.ym = Pc[Y - 1][X]; v.yp = Pc[Y + 1][X];
-                    v.zm = Pm[Y][X];     v.zp = Pp[Y][X];
-                    v.xpyp = Pc[Y + 1][X + 1]; v.xmym = Pc[Y - 1][X - 1];
-                    v.xpym = Pc[Y - 1][X + 1]; v.xmyp = Pc[Y + 1][X - 1];
-                    v.xpzp = Pp[Y][X + 1]; v.xmzm = Pm[Y][X - 1];
-                    v.xpzm = Pm[Y][X + 1]; v.xmzp = Pp[Y][X - 1];
-                    v.ypzp = Pp[Y + 1][X]; v.ymzm = Pm[Y - 1][X];
-                    v.ypzm = Pm[Y + 1][X]; v.ymzp = Pp[Y - 1][X];
+                    nb_split<W2>(Pm, Pc, Pp, c, o, v);
                     double S;
                     bool gd;
-                    const double Q = nl_root(v, Dc[r][lx], a.c, inv_h4, S, gd);
-                    const double fv = HAS_F ? FF[slot(p)][r][lx] : 0.0;
-                    val = (S - h2 * (Q + fv - cb)) * (1.0 / 6.0);
+                    const double Q = nl_root(v, rd_dl[q], a.c, inv_h4, S, gd);
+                    val = (S - h2 * (Q + (HAS_F ? rd_f[q] : 0.0) - cb)) * (1.0 / 6.0);
                 }
-                Q1[r][lx] = val;
-                Q1[r][lb] = Pc[Y][lb + 1];
+                Q1[rw[q][par]] = val;
+                Q1[rb[q][par]] = Pc[rsrc[q][par]];
             }
         }
         __syncthreads();
-        // ---- black phase on plane p2 = t-2, tile interior: P1 -> phi^2 ----------
-        const int p2 = t - 2;
+        // ---- black phase on plane p2, tile interior: P1 -> phi^2 ---------------
         if (p2 >= z0) {
-            const double(*Rm)[W1] = P1[slot(p2 - 1)];
-            const double(*Rc)[W1] = P1[slot(p2)];
-            const double(*Rp)[W1] = P1[slot(p2 + 1)];
-            const double(*Dc)[W1] = DL[slot(p2)];
-            for (int e = tid; e < BH * TY; e += NT) {
-                const int r = e / BH, m = e - r * BH;
-                const int gy = y0 + r;
-                if (gy >= g.n1) continue;
-                const int xb = 2 * m + ((gy + p2 + 1) & 1);
-                const int xr = 2 * m + ((gy + p2) & 1);
-                const int64_t rowoff = g.off0 + (int64_t)gy * g.sy + (int64_t)p2 * g.sz + x0;
-                const int X = xb + 1, Y = r + 1;       // ring-1 coordinates
-                if (x0 + xb < g.n0) {
+            const double* Rm = P1 + slot(p2 - 1) * S1;
+            const double* Rc = P1 + slot(p2) * S1;
+            const double* Rp = P1 + slot(p2 + 1) * S1;
+            const int64_t zo = (int64_t)p2 * g.sz;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                if (!bv[q]) continue;
+                const int par = (bpar0[q] + p2) & 1;
+                const int mcol = 2 * (tid + q * NT - ((tid + q * NT) / BH) * BH);
+                if (mcol + par < bxmax) {
                     Nb v;
-                    v.xm = Rc[Y][X - 1]; v.xp = Rc[Y][X + 1];
-                    v.ym = Rc[Y - 1][X]; v.yp = Rc[Y + 1][X];
-                    v.zm = Rm[Y][X];     v.zp = Rp[Y][X];
-                    v.xpyp = Rc[Y + 1][X + 1]; v.xmym = Rc[Y - 1][X - 1];
-                    v.xpym = Rc[Y - 1][X + 1]; v.xmyp = Rc[Y + 1][X - 1];
-                    v.xpzp = Rp[Y][X + 1]; v.xmzm = Rm[Y][X - 1];
-                    v.xpzm = Rm[Y][X + 1]; v.xmzp = Rp[Y][X - 1];
-                    v.ypzp = Rp[Y + 1][X]; v.ymzm = Rm[Y - 1][X];
-                    v.ypzm = Rm[Y + 1][X]; v.ymzp = Rp[Y - 1][X];
+                    nb_split<W1>(Rm, Rc, Rp, bc[q][par], bo[q][par], v);
                     double S;
                     bool gd;
-                    const double Q = nl_root(v, Dc[Y][X], a.c, inv_h4, S, gd);
-                    const double fv = HAS_F ? FF[slot(p2)][Y][X] : 0.0;
-                    a.pout[rowoff + xb] = (S - h2 * (Q + fv - cb)) * (1.0 / 6.0);
+                    const double Q = nl_root(v, bk_dl[q], a.c, inv_h4, S, gd);
+                    a.pout[zo + brow[q] + par] = (S - h2 * (Q + (HAS_F ? bk_f[q] : 0.0) - cb)) * (1.0 / 6.0);
                 }
-                if (x0 + xr < g.n0) a.pout[rowoff + xr] = Rc[Y][xr + 1];
+                if (mcol + 1 - par < bxmax) a.pout[zo + brow[q] + 1 - par] = Rc[brd[q][par]];
             }
         }
-        // ---- commit the prefetched planes (slots not read in this iteration) ----
-        if (pf_phi) store2(&P0[slot(t + 1)][0][0], nphi);
-        if (pf_dl) {
-            store1(&DL[slot(t)][0][0], ndl);
-            if (HAS_F) store1(&FF[slot(t)][0][0], nf);
-        }
+        // ---- commit prefetched data (the phi slot was last read by this red phase)
+        if (pf_phi) store_phi(slot(t + 1), nphi);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) { rd_dl[q] = nrd[q]; rd_f[q] = nrf[q]; }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) { bk_dl[q] = nbd[q]; bk_f[q] = nbf[q]; }
         __syncthreads();
     }
 }
@@ -268,6 +312,215 @@ __global__ void __launch_bounds__(NT) k_smooth_batch(SmoothArgs proto, const Geo
 }
 
 // residual d = L(phi) + cbar - f at one cell; also returns Q and the guard flag
+// ---------------------------------------------------------------------------
+// Tiled residual pass.  A block owns a 64 x 8 x zc brick (zc even) and marches
+// up z with phi staged on a one-cell ring in LDS (3 planes, next plane
+// prefetched into registers).  Thread (m, r) handles the x pair (2m, 2m+1) of
+// row r; rows 2k and 2k+1 live in the two halves of one wave, so the 2x2x2
+// restriction sums need one cross-half shuffle and one z-pair register.
+//   MODE 0 (norm):     d = L(phi) + cbar - f, reductions, optional d_out (caller layout)
+//   MODE 1 (restrict): as 0, and R phi -> phic, phiold_c; R d -> rd_c
+//   MODE 2 (FAS rhs):  fout = L(phi) - rd (rd passed as f), reductions of Q and fout
+// ---------------------------------------------------------------------------
+struct ResidArgs {
+    Geom g, gc;
+    Coef c;
+    const double* phi;
+    const double* delta;
+    const double* f;          // f (modes 0,1) or R d (mode 2); may be null in modes 0,1
+    const LevelScalars* sc;
+    double* d_out;            // mode 0, optional
+    double* phic;             // mode 1
+    double* phiold_c;         // mode 1
+    double* rd_c;             // mode 1
+    double* fout;             // mode 2
+    double* partials;
+    int zc, tiles_x, tiles_y;
+};
+
+constexpr int RTY = 8;   // rows per residual tile
+
+template <int DIR, int MODE>
+__global__ void __launch_bounds__(NT) k_resid_tiled(ResidArgs a) {
+    constexpr int W1 = TX + 2, H1 = RTY + 2;
+    constexpr int NP1 = W1 * H1;
+    constexpr int NL1 = (NP1 + NT - 1) / NT;
+    __shared__ double PH[3][H1][W1];
+    const Geom& g = a.g;
+    const int tid = threadIdx.x;
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = b % a.tiles_x;
+    b /= a.tiles_x;
+    const int ty = b % a.tiles_y;
+    const int ch = b / a.tiles_y;
+    const int x0 = tx * TX, y0 = ty * RTY, z0 = ch * a.zc;
+    const int z1 = min(z0 + a.zc, g.n2);
+    double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
+    const double cb = (DIR || MODE == 2) ? 0.0 : a.sc->cbar;
+    const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+    const int m = tid & 31, r = tid >> 5;           // x pair, row
+    const int gy = y0 + r;
+    const int xa = x0 + 2 * m;                       // first cell of the pair
+    const bool row_ok = gy < g.n1;
+
+    int off1[NL1];
+    bool ok1[NL1];
+#pragma unroll
+    for (int s = 0; s < NL1; ++s) {
+        const int e = tid + s * NT;
+        ok1[s] = false;
+        off1[s] = 0;
+        if (e < NP1) {
+            int gx = x0 - 1 + e % W1, gyy = y0 - 1 + e / W1;
+            if (DIR) {
+                ok1[s] = gx >= -1 && gx <= g.n0 && gyy >= -1 && gyy <= g.n1;
+            } else {
+                gx = wrapi(gx, g.n0);
+                gyy = wrapi(gyy, g.n1);
+                ok1[s] = true;
+            }
+            off1[s] = (int)(g.off0 + gx + (int64_t)gyy * g.sy);
+        }
+    }
+    auto plane_off = [&](int t, bool& zok) -> int64_t {
+        int gz;
+        if (DIR) { gz = t; zok = t >= -1 && t <= g.n2; }
+        else { gz = wrapi(t, g.n2); zok = true; }
+        return (int64_t)gz * g.sz;
+    };
+    auto load_plane = [&](int t, double (&rr)[NL1]) {
+        bool zok;
+        const int64_t zo = plane_off(t, zok);
+#pragma unroll
+        for (int s = 0; s < NL1; ++s) rr[s] = (ok1[s] && zok && tid + s * NT < NP1) ? a.phi[zo + off1[s]] : 0.0;
+    };
+    auto store_plane = [&](int sl, const double (&rr)[NL1]) {
+        double* dst = &PH[sl][0][0];
+#pragma unroll
+        for (int s = 0; s < NL1; ++s)
+            if (tid + s * NT < NP1) dst[tid + s * NT] = rr[s];
+    };
+    auto slot = [](int z) { return (z + 3) % 3; };
+    auto src_fetch = [&](int t, double (&dl)[2], double (&fv)[2]) {
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+            dl[c2] = 0.0;
+            fv[c2] = 0.0;
+            if (!row_ok || xa + c2 >= g.n0 || t >= z1) continue;
+            const int64_t gi = g.off0 + xa + c2 + (int64_t)gy * g.sy + (int64_t)t * g.sz;
+            dl[c2] = a.delta[gi];
+            if (a.f) fv[c2] = a.f[gi];
+        }
+    };
+
+    {
+        double rr[NL1];
+        for (int t = z0 - 1; t <= z0 + 1; ++t) {
+            load_plane(t, rr);
+            store_plane(slot(t), rr);
+        }
+    }
+    double cdl[2], cfv[2];
+    src_fetch(z0, cdl, cfv);
+    __syncthreads();
+    double zsum_phi = 0.0, zsum_d = 0.0;   // restriction partial sums of the even plane
+    for (int t = z0; t < z1; ++t) {
+        // planes t-1, t, t+1 are in LDS; plane t+2 is fetched while plane t is computed
+        double nxt[NL1], ndl[2], nfv[2];
+        const bool pf = t + 2 <= z1;
+        if (pf) load_plane(t + 2, nxt);
+        src_fetch(t + 1, ndl, nfv);
+        const int sm = slot(t - 1), sc = slot(t), sp = slot(t + 1);
+        double psum = 0.0, dsum = 0.0;
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+            const int X = 2 * m + c2 + 1, Y = r + 1;
+            if (!row_ok || xa + c2 >= g.n0) continue;
+            Nb v;
+            v.xm = PH[sc][Y][X - 1]; v.xp = PH[sc][Y][X + 1];
+            v.ym = PH[sc][Y - 1][X]; v.yp = PH[sc][Y + 1][X];
+            v.zm = PH[sm][Y][X];     v.zp = PH[sp][Y][X];
+            v.xpyp = PH[sc][Y + 1][X + 1]; v.xmym = PH[sc][Y - 1][X - 1];
+            v.xpym = PH[sc][Y - 1][X + 1]; v.xmyp = PH[sc][Y + 1][X - 1];
+            v.xpzp = PH[sp][Y][X + 1]; v.xmzm = PH[sm][Y][X - 1];
+            v.xpzm = PH[sm][Y][X + 1]; v.xmzp = PH[sp][Y][X - 1];
+            v.ypzp = PH[sp][Y + 1][X]; v.ymzm = PH[sm][Y - 1][X];
+            v.ypzm = PH[sm][Y + 1][X]; v.ymzp = PH[sp][Y - 1][X];
+            const double pc = PH[sc][Y][X];
+            double S;
+            bool gd;
+            const double Q = nl_root(v, cdl[c2], a.c, inv_h4, S, gd);
+            const double L = (S - 6.0 * pc) * inv_h2 - Q;
+            if (MODE == 2) {
+                const double fh = L - cfv[c2];
+                a.fout[g.off0 + xa + c2 + (int64_t)gy * g.sy + (int64_t)t * g.sz] = fh;
+                acc[R_Q] += Q;
+                acc[R_F] += fh;
+            } else {
+                const double d = L - cfv[c2] + cb;
+                acc[R_D2] += d * d;
+                acc[R_D1] += d;
+                acc[R_Q] += Q;
+                acc[R_F] += cfv[c2];
+                acc[R_PHI] += pc;
+                acc[R_GUARD] += gd ? 1.0 : 0.0;
+                acc[R_NONFIN] += isfinite(d) ? 0.0 : 1.0;
+                if (MODE == 0 && a.d_out)
+                    a.d_out[xa + c2 + ((int64_t)t * g.n1 + gy) * g.n0] = d;
+                psum += pc;
+                dsum += d;
+            }
+        }
+        if (MODE == 1) {
+            // y pair: rows 2k and 2k+1 are lanes l and l+32 of one wave
+            psum += __shfl_down(psum, 32, 64);
+            dsum += __shfl_down(dsum, 32, 64);
+            if ((t & 1) == 0) {
+                zsum_phi = psum;
+                zsum_d = dsum;
+            } else if ((r & 1) == 0 && row_ok && xa < g.n0) {
+                const Geom& gc = a.gc;
+                const int64_t co = gc.off0 + (xa >> 1) + (int64_t)(gy >> 1) * gc.sy + (int64_t)(t >> 1) * gc.sz;
+                const double rp = 0.125 * (zsum_phi + psum);
+                a.phic[co] = rp;
+                a.phiold_c[co] = rp;
+                a.rd_c[co] = 0.125 * (zsum_d + dsum);
+            }
+        }
+        __syncthreads();
+        if (pf) {
+            double* dst = &PH[slot(t + 2)][0][0];   // slot of plane t-1: no longer read
+#pragma unroll
+            for (int s = 0; s < NL1; ++s)
+                if (tid + s * NT < NP1) dst[tid + s * NT] = nxt[s];
+        }
+        cdl[0] = ndl[0]; cdl[1] = ndl[1];
+        cfv[0] = nfv[0]; cfv[1] = nfv[1];
+        __syncthreads();
+    }
+    block_store_partials(acc, a.partials);
+}
+
+static hipError_t resid_launch(ResidArgs& a, int mode, int* nblocks_out, hipStream_t s) {
+    a.zc = 16;
+    a.tiles_x = (a.g.n0 + TX - 1) / TX;
+    a.tiles_y = (a.g.n1 + RTY - 1) / RTY;
+    const int nb = a.tiles_x * a.tiles_y * ((a.g.n2 + a.zc - 1) / a.zc);
+    *nblocks_out = nb;
+#define RL(D, M) hipLaunchKernelGGL((k_resid_tiled<D, M>), dim3(nb), dim3(NT), 0, s, a)
+    if (a.g.dir) {
+        if (mode == 0) RL(1, 0); else if (mode == 1) RL(1, 1); else RL(1, 2);
+    } else {
+        if (mode == 0) RL(0, 0); else if (mode == 1) RL(0, 1); else RL(0, 2);
+    }
+#undef RL
+    return hipGetLastError();
+}
+
+int resid_blocks(const Geom& g) {
+    return ((g.n0 + TX - 1) / TX) * ((g.n1 + RTY - 1) / RTY) * ((g.n2 + 15) / 16);
+}
+
 // ---------------------------------------------------------------------------
 // residual + restriction (8-child average of phi and d) in one pass
 // ---------------------------------------------------------------------------
@@ -452,36 +705,111 @@ __global__ void __launch_bounds__(NT) k_prolong(Geom gf, Geom gc, double* __rest
     }
 }
 
+// Tiled prolongation + correction.  A block owns a 64 x 8 x 16 fine brick; the
+// coarse correction c = phi^H - phiold^H of the 34 x 6 x 10 coarse cells around
+// it is staged in LDS once (zero outside a Dirichlet grid, wrapped on a
+// periodic one), then every fine cell adds its trilinear interpolant.
+constexpr int PZ = 16;   // fine planes per prolongation block
+template <int DIR>
+__global__ void __launch_bounds__(NT) k_prolong_tiled(Geom gf, Geom gc, double* __restrict__ phif,
+                                                      const double* __restrict__ phic,
+                                                      const double* __restrict__ oldc, int tiles_x, int tiles_y) {
+    constexpr int CX = TX / 2 + 2, CY = 8 / 2 + 2, CZ = PZ / 2 + 2;
+    __shared__ double C[CZ][CY][CX];
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = b % tiles_x;
+    b /= tiles_x;
+    const int ty = b % tiles_y;
+    const int ch = b / tiles_y;
+    const int x0 = tx * TX, y0 = ty * 8, z0 = ch * PZ;
+    const int cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1, cz0 = z0 / 2 - 1;
+    for (int e = threadIdx.x; e < CX * CY * CZ; e += NT) {
+        const int lx = e % CX, ly = (e / CX) % CY, lz = e / (CX * CY);
+        int I = cx0 + lx, J = cy0 + ly, K = cz0 + lz;
+        double v = 0.0;
+        if (DIR) {
+            if (I >= 0 && I < gc.n0 && J >= 0 && J < gc.n1 && K >= 0 && K < gc.n2) {
+                const int64_t ci = cell_index(gc, I, J, K);
+                v = phic[ci] - oldc[ci];
+            }
+        } else {
+            I = wrapi(I, gc.n0);
+            J = wrapi(J, gc.n1);
+            K = wrapi(K, gc.n2);
+            const int64_t ci = cell_index(gc, I, J, K);
+            v = phic[ci] - oldc[ci];
+        }
+        C[lz][ly][lx] = v;
+    }
+    __syncthreads();
+    const int lxf = threadIdx.x & 63;          // fine x within the tile
+    const int i = x0 + lxf;
+    if (i >= gf.n0) return;
+    const int Ii = (i >> 1) - cx0, si = (i & 1) ? 1 : -1;
+    for (int q = threadIdx.x >> 6; q < 8 * PZ; q += NT / 64) {
+        const int j = y0 + (q & 7), k = z0 + (q >> 3);
+        if (j >= gf.n1 || k >= gf.n2) continue;
+        const int Jj = (j >> 1) - cy0, sj = (j & 1) ? 1 : -1;
+        const int Kk = (k >> 1) - cz0, sk = (k & 1) ? 1 : -1;
+        const double c000 = C[Kk][Jj][Ii], c100 = C[Kk][Jj][Ii + si];
+        const double c010 = C[Kk][Jj + sj][Ii], c110 = C[Kk][Jj + sj][Ii + si];
+        const double c001 = C[Kk + sk][Jj][Ii], c101 = C[Kk + sk][Jj][Ii + si];
+        const double c011 = C[Kk + sk][Jj + sj][Ii], c111 = C[Kk + sk][Jj + sj][Ii + si];
+        const double x00 = 0.75 * c000 + 0.25 * c100, x10 = 0.75 * c010 + 0.25 * c110;
+        const double x01 = 0.75 * c001 + 0.25 * c101, x11 = 0.75 * c011 + 0.25 * c111;
+        const double y0v = 0.75 * x00 + 0.25 * x10, y1v = 0.75 * x01 + 0.25 * x11;
+        phif[cell_index(gf, i, j, k)] += 0.75 * y0v + 0.25 * y1v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // coarsest level: whole grid in LDS, red-black sweeps (same snapshot schedule)
 // ---------------------------------------------------------------------------
 constexpr int CMAX = 10 * 10 * 10;   // storage of a padded 8^3 grid
 
 // phi (and, if given, phi_also) receive the result; storage starts at g.base.
+// With `old` (coarse Dirichlet levels) the ghosts follow the correction phi - old
+// by mirroring after every colour pass; without it they stay fixed.
 template <int DIR>
 __device__ __forceinline__ void coarse_solve_body(Geom g, const Coef& c, double* phi, double* phi_also,
-                                                  const double* delta, const double* f, int sweeps) {
-    __shared__ double sphi[CMAX], sdel[CMAX], sf[CMAX];
+                                                  const double* delta, const double* f, int sweeps,
+                                                  const double* old = nullptr) {
+    __shared__ double sphi[CMAX], sdel[CMAX], sf[CMAX], sold[CMAX];
     __shared__ double red[NT / 64];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
     phi += g.base;
     delta += g.base;
     if (f) f += g.base;
     if (phi_also) phi_also += g.base;
-    for (int64_t e = tid; e < g.nstore; e += NT) {
+    if (old) old += g.base;
+    for (int64_t e = tid; e < g.nstore; e += nt) {
         sphi[e] = phi[e];
         sdel[e] = delta[e];
         sf[e] = f ? f[e] : 0.0;
+        if (DIR && old) sold[e] = old[e];
     }
     __syncthreads();
     Geom lg = g;   // same indexing on the LDS copy
     lg.off0 -= g.base;
     lg.base = 0;
+    const int64_t nghost = DIR ? ghost_count_dev(g.n0, g.n1, g.n2) : 0;
+    auto refresh_ghosts = [&]() {
+        if (!DIR || !old) return;
+        for (int64_t q = tid; q < nghost; q += nt) {
+            int i, j, k;
+            ghost_coords(g.n0, g.n1, g.n2, q, i, j, k);
+            int sign = 1;
+            const int ir = mirror(i, g.n0, sign), jr = mirror(j, g.n1, sign), kr = mirror(k, g.n2, sign);
+            const int64_t gi = cell_index(lg, i, j, k), ii = cell_index(lg, ir, jr, kr);
+            sphi[gi] = sold[gi] + sign * (sphi[ii] - sold[ii]);
+        }
+        __syncthreads();
+    };
     const double h2 = g.h * g.h, inv_h4 = 1.0 / (h2 * h2);
     double sumf = 0.0;
     if (!DIR) {
         double a = 0.0;
-        for (int64_t e = tid; e < g.ncell; e += NT) {
+        for (int64_t e = tid; e < g.ncell; e += nt) {
             int i, j, k;
             decode(g, e, i, j, k);
             a += sf[cell_index(lg, i, j, k)];
@@ -489,15 +817,15 @@ __device__ __forceinline__ void coarse_solve_body(Geom g, const Coef& c, double*
         a = wave_sum(a);
         if ((tid & 63) == 0) red[tid >> 6] = a;
         __syncthreads();
-        for (int q = 0; q < NT / 64; ++q) sumf += red[q];
+        for (int q = 0; q < nt / 64; ++q) sumf += red[q];
         __syncthreads();
     }
-    const int per = (int)((g.ncell + NT - 1) / NT);   // <= 2 for 8^3
+    const int per = (int)((g.ncell + nt - 1) / nt);   // <= 2 (checked at launch)
     for (int s = 0; s < sweeps; ++s) {
         double cb = 0.0;
         if (!DIR) {
             double a = 0.0;
-            for (int64_t e = tid; e < g.ncell; e += NT) {
+            for (int64_t e = tid; e < g.ncell; e += nt) {
                 int i, j, k;
                 decode(g, e, i, j, k);
                 Nb v;
@@ -510,7 +838,7 @@ __device__ __forceinline__ void coarse_solve_body(Geom g, const Coef& c, double*
             if ((tid & 63) == 0) red[tid >> 6] = a;
             __syncthreads();
             double sq = 0.0;
-            for (int q = 0; q < NT / 64; ++q) sq += red[q];
+            for (int q = 0; q < nt / 64; ++q) sq += red[q];
             cb = (sumf + sq) / (double)g.ncell;
             __syncthreads();
         }
@@ -519,7 +847,7 @@ __device__ __forceinline__ void coarse_solve_body(Geom g, const Coef& c, double*
             int64_t ni[2];
             for (int q = 0; q < per && q < 2; ++q) {
                 ni[q] = -1;
-                const int64_t e = tid + (int64_t)q * NT;
+                const int64_t e = tid + (int64_t)q * nt;
                 if (e >= g.ncell) continue;
                 int i, j, k;
                 decode(g, e, i, j, k);
@@ -535,17 +863,26 @@ __device__ __forceinline__ void coarse_solve_body(Geom g, const Coef& c, double*
             }
             __syncthreads();
             for (int q = 0; q < per && q < 2; ++q)
-                if (tid + (int64_t)q * NT < g.ncell && ni[q] >= 0) sphi[ni[q]] = nv[q];
+                if (tid + (int64_t)q * nt < g.ncell && ni[q] >= 0) sphi[ni[q]] = nv[q];
             __syncthreads();
+            refresh_ghosts();
         }
     }
-    for (int64_t e = tid; e < g.ncell; e += NT) {
+    for (int64_t e = tid; e < g.ncell; e += nt) {
         int i, j, k;
         decode(g, e, i, j, k);
         const int64_t li = cell_index(lg, i, j, k);
         phi[li] = sphi[li];
         if (phi_also) phi_also[li] = sphi[li];
     }
+    if (DIR && old)
+        for (int64_t q = tid; q < nghost; q += nt) {
+            int i, j, k;
+            ghost_coords(g.n0, g.n1, g.n2, q, i, j, k);
+            const int64_t li = cell_index(lg, i, j, k);
+            phi[li] = sphi[li];
+            if (phi_also) phi_also[li] = sphi[li];
+        }
     __syncthreads();
 }
 
@@ -609,32 +946,6 @@ __global__ void k_copy_out(Geom g, const double* src, double* dst) {
     }
 }
 
-__device__ __forceinline__ int64_t ghost_count_dev(int n0, int n1, int n2) {
-    return 2 * ((int64_t)n1 * n2 + (int64_t)n0 * n2 + (int64_t)n0 * n1) + 4 * ((int64_t)n0 + n1 + n2);
-}
-
-// Decode a compact ghost index into cell coordinates (i, j, k) in [-1, n].
-__device__ void ghost_coords(int n0, int n1, int n2, int64_t q, int& i, int& j, int& k) {
-    const int64_t fx = (int64_t)n1 * n2, fy = (int64_t)n0 * n2, fz = (int64_t)n0 * n1;
-    if (q < 2 * fx) { const int s = (int)(q / fx); const int64_t r = q % fx;
-        i = s ? n0 : -1; j = (int)(r % n1); k = (int)(r / n1); return; }
-    q -= 2 * fx;
-    if (q < 2 * fy) { const int s = (int)(q / fy); const int64_t r = q % fy;
-        j = s ? n1 : -1; i = (int)(r % n0); k = (int)(r / n0); return; }
-    q -= 2 * fy;
-    if (q < 2 * fz) { const int s = (int)(q / fz); const int64_t r = q % fz;
-        k = s ? n2 : -1; i = (int)(r % n0); j = (int)(r / n0); return; }
-    q -= 2 * fz;
-    if (q < 4 * (int64_t)n0) { const int e = (int)(q / n0);
-        i = (int)(q % n0); j = (e & 1) ? n1 : -1; k = (e & 2) ? n2 : -1; return; }
-    q -= 4 * (int64_t)n0;
-    if (q < 4 * (int64_t)n1) { const int e = (int)(q / n1);
-        j = (int)(q % n1); i = (e & 1) ? n0 : -1; k = (e & 2) ? n2 : -1; return; }
-    q -= 4 * (int64_t)n1;
-    const int e = (int)(q / n2);
-    k = (int)(q % n2); i = (e & 1) ? n0 : -1; j = (e & 2) ? n1 : -1;
-}
-
 __global__ void k_ghost_in(Geom g, const double* ghost, double* dst, int64_t count) {
     for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < count; q += (int64_t)gridDim.x * NT) {
         int i, j, k;
@@ -643,31 +954,45 @@ __global__ void k_ghost_in(Geom g, const double* ghost, double* dst, int64_t cou
     }
 }
 
-__global__ void k_ghost_fill(const double* parent, int np0, int np1, int np2, double H, int n0,
-                             int n1, int n2, double h, int o0, int o1, int o2, double* ghost,
-                             int64_t count) {
+// Trilinear value of a cell-centred periodic parent (np cells of size H) at the
+// centre of patch cell c (cells of size h, cell 0 at o*h).
+__device__ double parent_trilinear(const double* __restrict__ parent, const int np[3], double H, double h,
+                                   const int o[3], const int c[3]) {
+    int base[3];
+    double t[3];
+    for (int d = 0; d < 3; ++d) {
+        const double u = (o[d] + c[d] + 0.5) * h / H - 0.5;   // parent index space
+        const double fl = floor(u);
+        base[d] = (int)fl;
+        t[d] = u - fl;
+    }
+    double v = 0.0;
+    for (int m = 0; m < 8; ++m) {
+        const int dx = m & 1, dy = (m >> 1) & 1, dz = m >> 2;
+        const double w = (dx ? t[0] : 1.0 - t[0]) * (dy ? t[1] : 1.0 - t[1]) * (dz ? t[2] : 1.0 - t[2]);
+        const int I = ((base[0] + dx) % np[0] + np[0]) % np[0];
+        const int J = ((base[1] + dy) % np[1] + np[1]) % np[1];
+        const int K = ((base[2] + dz) % np[2] + np[2]) % np[2];
+        v += w * parent[((int64_t)K * np[1] + J) * np[0] + I];
+    }
+    return v;
+}
+
+// MODE 0: ghost shell (compact order); MODE 1: interior, x fastest.
+template <int MODE>
+__global__ void k_parent_fill(const double* parent, int np0, int np1, int np2, double H, int n0, int n1, int n2,
+                              double h, int o0, int o1, int o2, double* out, int64_t count) {
+    const int o[3] = {o0, o1, o2}, np[3] = {np0, np1, np2};
     for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < count; q += (int64_t)gridDim.x * NT) {
         int c[3];
-        ghost_coords(n0, n1, n2, q, c[0], c[1], c[2]);
-        const int o[3] = {o0, o1, o2}, np[3] = {np0, np1, np2};
-        int base[3];
-        double t[3];
-        for (int d = 0; d < 3; ++d) {
-            const double u = (o[d] + c[d] + 0.5) * h / H - 0.5;   // parent index space
-            const double fl = floor(u);
-            base[d] = (int)fl;
-            t[d] = u - fl;
+        if (MODE == 0) {
+            ghost_coords(n0, n1, n2, q, c[0], c[1], c[2]);
+        } else {
+            c[0] = (int)(q % n0);
+            c[1] = (int)((q / n0) % n1);
+            c[2] = (int)(q / ((int64_t)n0 * n1));
         }
-        double v = 0.0;
-        for (int m = 0; m < 8; ++m) {
-            const int dx = m & 1, dy = (m >> 1) & 1, dz = m >> 2;
-            const double w = (dx ? t[0] : 1.0 - t[0]) * (dy ? t[1] : 1.0 - t[1]) * (dz ? t[2] : 1.0 - t[2]);
-            const int I = ((base[0] + dx) % np[0] + np[0]) % np[0];
-            const int J = ((base[1] + dy) % np[1] + np[1]) % np[1];
-            const int K = ((base[2] + dz) % np[2] + np[2]) % np[2];
-            v += w * parent[((int64_t)K * np1 + J) * np0 + I];
-        }
-        ghost[q] = v;
+        out[q] = parent_trilinear(parent, np, H, h, o, c);
     }
 }
 
@@ -756,11 +1081,13 @@ __global__ void __launch_bounds__(NT) k_prolong_batch(const Geom* __restrict__ g
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-        const int ii = I + ((q & 1) ? si : 0), jj = J + ((q & 2) ? sj : 0), kk = K + ((q & 4) ? sk : 0);
+        int sign = 1;
+        const int ii = mirror(I + ((q & 1) ? si : 0), gc.n0, sign);
+        const int jj = mirror(J + ((q & 2) ? sj : 0), gc.n1, sign);
+        const int kk = mirror(K + ((q & 4) ? sk : 0), gc.n2, sign);
         const double wq = ((q & 1) ? 0.25 : 0.75) * ((q & 2) ? 0.25 : 0.75) * ((q & 4) ? 0.25 : 0.75);
-        if (ii < 0 || ii >= gc.n0 || jj < 0 || jj >= gc.n1 || kk < 0 || kk >= gc.n2) continue;
         const int64_t ci = cell_index(gc, ii, jj, kk);
-        acc += wq * (phic[ci] - oldc[ci]);
+        acc += wq * sign * (phic[ci] - oldc[ci]);
     }
     phif[cell_index(gf, i, j, k)] += acc;
 }
@@ -830,8 +1157,8 @@ __global__ void __launch_bounds__(NT) k_finalize_batch(const double* __restrict_
 // ping-pong buffers so that either parity reads it
 __global__ void __launch_bounds__(NT) k_coarse_batch(const Geom* __restrict__ gs, Coef c, double* phi0,
                                                      double* phi1, const double* delta, const double* f,
-                                                     int sweeps) {
-    coarse_solve_body<1>(gs[blockIdx.x], c, phi0, phi1, delta, f, sweeps);
+                                                     int sweeps, const double* old) {
+    coarse_solve_body<1>(gs[blockIdx.x], c, phi0, phi1, delta, f, sweeps, old);
 }
 
 __global__ void k_copy_in_batch(const Geom* __restrict__ gs, const int64_t* __restrict__ uoff,
@@ -975,41 +1302,30 @@ hipError_t launch_residual_restrict(const Geom& gf, const Geom& gc, const Coef& 
                                     const double* phi, const double* delta, const double* f,
                                     const LevelScalars* sc, double* phic, double* phiold_c,
                                     double* rd_c, double* partials, int* nblocks_out, hipStream_t s) {
-    const int nb = grid_for(gc.ncell, MAX_RED_BLOCKS);
-    if (gf.dir)
-        hipLaunchKernelGGL(k_residual_restrict<1>, dim3(nb), dim3(NT), 0, s, gf, gc, c, phi, delta, f,
-                           sc, phic, phiold_c, rd_c, partials);
-    else
-        hipLaunchKernelGGL(k_residual_restrict<0>, dim3(nb), dim3(NT), 0, s, gf, gc, c, phi, delta, f,
-                           sc, phic, phiold_c, rd_c, partials);
-    *nblocks_out = nb;
-    return hipGetLastError();
+    ResidArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = gf; a.gc = gc; a.c = c; a.phi = phi; a.delta = delta; a.f = f; a.sc = sc;
+    a.phic = phic; a.phiold_c = phiold_c; a.rd_c = rd_c; a.partials = partials;
+    return resid_launch(a, 1, nblocks_out, s);
 }
 
 hipError_t launch_residual_norm(const Geom& g, const Coef& c, const double* phi,
                                 const double* delta, const double* f, const LevelScalars* sc,
                                 double* d_out, double* partials, int* nblocks_out, hipStream_t s) {
-    const int nb = grid_for(g.ncell, MAX_RED_BLOCKS);
-    if (g.dir)
-        hipLaunchKernelGGL(k_residual_norm<1>, dim3(nb), dim3(NT), 0, s, g, c, phi, delta, f, sc, d_out,
-                           partials);
-    else
-        hipLaunchKernelGGL(k_residual_norm<0>, dim3(nb), dim3(NT), 0, s, g, c, phi, delta, f, sc, d_out,
-                           partials);
-    *nblocks_out = nb;
-    return hipGetLastError();
+    ResidArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = g; a.c = c; a.phi = phi; a.delta = delta; a.f = f; a.sc = sc; a.d_out = d_out;
+    a.partials = partials;
+    return resid_launch(a, 0, nblocks_out, s);
 }
 
 hipError_t launch_fas_rhs(const Geom& g, const Coef& c, const double* phi, const double* delta,
                           const double* rd, double* f, double* partials, int* nblocks_out,
                           hipStream_t s) {
-    const int nb = grid_for(g.ncell, MAX_RED_BLOCKS);
-    if (g.dir)
-        hipLaunchKernelGGL(k_fas_rhs<1>, dim3(nb), dim3(NT), 0, s, g, c, phi, delta, rd, f, partials);
-    else
-        hipLaunchKernelGGL(k_fas_rhs<0>, dim3(nb), dim3(NT), 0, s, g, c, phi, delta, rd, f, partials);
-    *nblocks_out = nb;
-    return hipGetLastError();
+    ResidArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = g; a.c = c; a.phi = phi; a.delta = delta; a.f = rd; a.fout = f; a.partials = partials;
+    return resid_launch(a, 2, nblocks_out, s);
 }
 
 hipError_t launch_finalize(const double* partials, int nblocks, int64_t ncell, int periodic,
@@ -1021,22 +1337,24 @@ hipError_t launch_finalize(const double* partials, int nblocks, int64_t ncell, i
 
 hipError_t launch_prolong(const Geom& gf, const Geom& gc, double* phif, const double* phic,
                           const double* phiold_c, hipStream_t s) {
-    const int nb = grid_for(gf.ncell);
+    const int tx = (gf.n0 + TX - 1) / TX, ty = (gf.n1 + 7) / 8;
+    const int nb = tx * ty * ((gf.n2 + PZ - 1) / PZ);
     if (gf.dir)
-        hipLaunchKernelGGL(k_prolong<1>, dim3(nb), dim3(NT), 0, s, gf, gc, phif, phic, phiold_c);
+        hipLaunchKernelGGL(k_prolong_tiled<1>, dim3(nb), dim3(NT), 0, s, gf, gc, phif, phic, phiold_c, tx, ty);
     else
-        hipLaunchKernelGGL(k_prolong<0>, dim3(nb), dim3(NT), 0, s, gf, gc, phif, phic, phiold_c);
+        hipLaunchKernelGGL(k_prolong_tiled<0>, dim3(nb), dim3(NT), 0, s, gf, gc, phif, phic, phiold_c, tx, ty);
     return hipGetLastError();
 }
 
 hipError_t launch_coarse_solve(const Geom& g, const Coef& c, double* phi, const double* delta,
                                const double* f, LevelScalars* sc, int sweeps, hipStream_t s) {
-    if (g.nstore > CMAX || g.ncell > 2 * NT) return hipErrorInvalidValue;
     (void)sc;
+    if (g.nstore > CMAX || g.ncell > 2 * NT) return hipErrorInvalidValue;
+    const int nt = g.ncell <= 128 ? 64 : NT;   // one wave for small grids: cheap barriers
     if (g.dir)
-        hipLaunchKernelGGL(k_coarse_solve<1>, dim3(1), dim3(NT), 0, s, g, c, phi, delta, f, sweeps);
+        hipLaunchKernelGGL(k_coarse_solve<1>, dim3(1), dim3(nt), 0, s, g, c, phi, delta, f, sweeps);
     else
-        hipLaunchKernelGGL(k_coarse_solve<0>, dim3(1), dim3(NT), 0, s, g, c, phi, delta, f, sweeps);
+        hipLaunchKernelGGL(k_coarse_solve<0>, dim3(1), dim3(nt), 0, s, g, c, phi, delta, f, sweeps);
     return hipGetLastError();
 }
 
@@ -1073,8 +1391,16 @@ hipError_t launch_ghost_fill(const double* parent, int np0, int np1, int np2, do
                              int n1, int n2, double h, int o0, int o1, int o2, double* ghost,
                              hipStream_t s) {
     const int64_t cnt = ghost_count(n0, n1, n2);
-    hipLaunchKernelGGL(k_ghost_fill, dim3(grid_for(cnt)), dim3(NT), 0, s, parent, np0, np1, np2, H,
+    hipLaunchKernelGGL(k_parent_fill<0>, dim3(grid_for(cnt)), dim3(NT), 0, s, parent, np0, np1, np2, H,
                        n0, n1, n2, h, o0, o1, o2, ghost, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_interior_fill(const double* parent, int np0, int np1, int np2, double H, int n0, int n1, int n2,
+                                double h, int o0, int o1, int o2, double* phi, hipStream_t s) {
+    const int64_t cnt = (int64_t)n0 * n1 * n2;
+    hipLaunchKernelGGL(k_parent_fill<1>, dim3(grid_for(cnt)), dim3(NT), 0, s, parent, np0, np1, np2, H,
+                       n0, n1, n2, h, o0, o1, o2, phi, cnt);
     return hipGetLastError();
 }
 
@@ -1164,9 +1490,24 @@ hipError_t launch_finalize_batch(const double* partials, const int* first, const
 }
 
 hipError_t launch_coarse_batch(const Geom* gs, int ngrids, const Coef& c, double* phi0, double* phi1,
-                               const double* delta, const double* f, int sweeps, hipStream_t s) {
+                               const double* delta, const double* f, int sweeps, const double* old,
+                               hipStream_t s) {
     if (ngrids <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coarse_batch, dim3(ngrids), dim3(NT), 0, s, gs, c, phi0, phi1, delta, f, sweeps);
+    hipLaunchKernelGGL(k_coarse_batch, dim3(ngrids), dim3(NT), 0, s, gs, c, phi0, phi1, delta, f, sweeps, old);
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost_refresh_batch(const Geom* gs, const int2* items, int nitems, double* u, const double* ref,
+                                      hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ghost_refresh_batch<double>, dim3(nitems), dim3(NT), 0, s, gs, items, u, ref);
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost_refresh_batch_f(const Geom* gs, const int2* items, int nitems, float* u, const float* ref,
+                                        hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ghost_refresh_batch<float>, dim3(nitems), dim3(NT), 0, s, gs, items, u, ref);
     return hipGetLastError();
 }
 

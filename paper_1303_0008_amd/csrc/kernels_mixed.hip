@@ -15,6 +15,9 @@
 // (sign of D0), so the root near a vanishing discriminant is evaluated in FP64.
 // dQ does not depend on e at the cell itself, so the nonlinear Gauss-Seidel
 // update stays closed form: e_c <- (S_e - h^2 (dQ + r - cbar_e)) / 6.
+#include <algorithm>
+#include <cstring>
+
 #include "device_common.h"
 
 namespace vmg {
@@ -67,34 +70,33 @@ struct CorrArgs {
 };
 
 template <int TY, int DIR>
-__global__ void __launch_bounds__(NT) k_smooth_corr(CorrArgs a) {
+__device__ __forceinline__ void corr_brick(const CorrArgs& a, const int x0, const int y0, const int z0,
+                                           const int z1) {
     constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
-    constexpr int NP2 = W2 * H2, NP1 = W1 * H1;
-    constexpr int NL2 = (NP2 + NT - 1) / NT, NL1 = (NP1 + NT - 1) / NT;
+    constexpr int NP2 = W2 * H2;
+    constexpr int NL2 = (NP2 + NT - 1) / NT;
     constexpr int RH = W1 / 2;
     constexpr int BH = TX / 2;
-    __shared__ float E0[3][H2][W2];    // e^0, ring 2
-    __shared__ float PT2[3][H2][W2];   // phi~, ring 2
-    __shared__ float E1[3][H1][W1];    // e^1 (red computed, black copied), ring 1
-    __shared__ float PT1[3][H1][W1];   // phi~ copy, ring 1
-    __shared__ float TT[3][H1][W1];    // t0, ring 1
-    __shared__ float RR[3][H1][W1];    // r, ring 1
+    constexpr int NR = (RH * H1 + NT - 1) / NT;
+    constexpr int NB = (BH * TY + NT - 1) / NT;
+    // rows split by x parity so that lanes on every other cell read consecutive words
+    __shared__ float E0[3][H2][2][W2 / 2];    // e^0, ring 2
+    __shared__ float PT2[3][H2][2][W2 / 2];   // phi~, ring 2
+    __shared__ float E1[3][H1][2][W1 / 2];    // e^1 (red computed, black copied), ring 1
+    __shared__ float PT1[3][H1][2][W1 / 2];   // phi~ copy, ring 1
+#define AE0(S, Y, X) E0[S][Y][(X) & 1][(X) >> 1]
+#define AP2(S, Y, X) PT2[S][Y][(X) & 1][(X) >> 1]
+#define AE1(S, Y, X) E1[S][Y][(X) & 1][(X) >> 1]
+#define AP1(S, Y, X) PT1[S][Y][(X) & 1][(X) >> 1]
 
     const Geom& g = a.g;
     const int tid = threadIdx.x;
-    int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int tx = b % a.tiles_x;
-    b /= a.tiles_x;
-    const int ty = b % a.tiles_y;
-    const int ch = b / a.tiles_y;
-    const int x0 = tx * TX, y0 = ty * TY, z0 = ch * a.zc;
-    const int z1 = min(z0 + a.zc, g.n2);
     if (z0 >= g.n2) return;
     const float h2 = a.c.h2;
     const float cb = DIR ? 0.0f : (float)a.sc->cbar;
 
-    int off2[NL2], off1[NL1];
-    bool ok2[NL2], ok1[NL1];
+    int off2[NL2];
+    bool ok2[NL2];
 #pragma unroll
     for (int s = 0; s < NL2; ++s) {
         const int e = tid + s * NT;
@@ -112,165 +114,208 @@ __global__ void __launch_bounds__(NT) k_smooth_corr(CorrArgs a) {
             off2[s] = (int)(g.off0 + gx + (int64_t)gy * g.sy);
         }
     }
-#pragma unroll
-    for (int s = 0; s < NL1; ++s) {
-        const int e = tid + s * NT;
-        ok1[s] = false;
-        off1[s] = 0;
-        if (e < NP1) {
-            int gx = x0 - 1 + e % W1, gy = y0 - 1 + e / W1;
-            if (DIR) {
-                ok1[s] = gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1;
-            } else {
-                gx = wrapi(gx, g.n0);
-                gy = wrapi(gy, g.n1);
-                ok1[s] = true;
-            }
-            off1[s] = (int)(g.off0 + gx + (int64_t)gy * g.sy);
-        }
-    }
-    auto zoff = [&](int t, bool& zok, bool interior_only) -> int64_t {
+    auto plane_off = [&](int t, bool& zok) -> int64_t {
         int gz;
-        if (DIR) { gz = t; zok = interior_only ? (t >= 0 && t < g.n2) : (t >= -1 && t <= g.n2); }
+        if (DIR) { gz = t; zok = t >= -1 && t <= g.n2; }
         else { gz = wrapi(t, g.n2); zok = true; }
         return (int64_t)gz * g.sz;
     };
     auto load2 = [&](const float* src, int t, float (&r)[NL2]) {
         bool zok;
-        const int64_t zo = zoff(t, zok, false);
+        const int64_t zo = plane_off(t, zok);
 #pragma unroll
         for (int s = 0; s < NL2; ++s) r[s] = (ok2[s] && zok && tid + s * NT < NP2) ? src[zo + off2[s]] : 0.0f;
     };
-    auto load1 = [&](const float* src, int t, float (&r)[NL1]) {
-        bool zok;
-        const int64_t zo = zoff(t, zok, true);
+    auto store2 = [&](float (*dst)[2][W2 / 2], const float (&r)[NL2]) {
 #pragma unroll
-        for (int s = 0; s < NL1; ++s) r[s] = (ok1[s] && zok && tid + s * NT < NP1) ? src[zo + off1[s]] : 0.0f;
+        for (int s = 0; s < NL2; ++s) {
+            const int e = tid + s * NT;
+            if (e < NP2) {
+                const int X = e % W2, Y = e / W2;
+                dst[Y][X & 1][X >> 1] = r[s];
+            }
+        }
     };
-    auto store2 = [&](float* dst, const float (&r)[NL2]) {
-#pragma unroll
-        for (int s = 0; s < NL2; ++s)
-            if (tid + s * NT < NP2) dst[tid + s * NT] = r[s];
+    auto r1_index = [&](int lx, int r, int p) -> int64_t {
+        int gx = x0 - 1 + lx, gy = y0 - 1 + r, gz = p;
+        if (DIR) {
+            if (gx < 0 || gx >= g.n0 || gy < 0 || gy >= g.n1 || gz < 0 || gz >= g.n2) return -1;
+        } else {
+            gx = wrapi(gx, g.n0);
+            gy = wrapi(gy, g.n1);
+            gz = wrapi(gz, g.n2);
+        }
+        return g.off0 + gx + (int64_t)gy * g.sy + (int64_t)gz * g.sz;
     };
-    auto store1 = [&](float* dst, const float (&r)[NL1]) {
-#pragma unroll
-        for (int s = 0; s < NL1; ++s)
-            if (tid + s * NT < NP1) dst[tid + s * NT] = r[s];
+    auto red_cell = [&](int q, int p, int& r, int& lx, int& lb) -> bool {
+        const int e = tid + q * NT;
+        if (e >= RH * H1) return false;
+        r = e / RH;
+        const int m = e - r * RH;
+        const int odd = (y0 - 1 + r + p + 1) & 1;
+        lx = 2 * m + odd;
+        lb = 2 * m + 1 - odd;
+        return true;
+    };
+    auto black_cell = [&](int q, int p2, int& r, int& xb, int& xr) -> bool {
+        const int e = tid + q * NT;
+        if (e >= BH * TY) return false;
+        r = e / BH;
+        const int m = e - r * BH;
+        xb = 2 * m + ((y0 + r + p2 + 1) & 1);
+        xr = 2 * m + ((y0 + r + p2) & 1);
+        return true;
     };
     auto slot = [](int z) { return (z + 3) % 3; };
 
+    float rd_t[NR], rd_r[NR], bk_t[NB], bk_r[NB];
+    auto fetch_red = [&](int p, float (&tt)[NR], float (&rr)[NR]) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            int r, lx, lb;
+            tt[q] = 1.0f;
+            rr[q] = 0.0f;
+            if (!red_cell(q, p, r, lx, lb)) continue;
+            const int64_t gi = r1_index(lx, r, p);
+            if (gi < 0) continue;
+            tt[q] = a.t0[gi];
+            rr[q] = a.r[gi];
+        }
+    };
+    auto fetch_black = [&](int p2, float (&tt)[NB], float (&rr)[NB]) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            int r, xb, xr;
+            tt[q] = 1.0f;
+            rr[q] = 0.0f;
+            if (!black_cell(q, p2, r, xb, xr)) continue;
+            const int64_t gi = r1_index(xb + 1, r + 1, p2);
+            if (gi < 0) continue;
+            tt[q] = a.t0[gi];
+            rr[q] = a.r[gi];
+        }
+    };
+
     {
-        float r2[NL2], r1[NL1];
+        float r2[NL2];
         for (int t = z0 - 2; t <= z0; ++t) {
             load2(a.ein, t, r2);
-            store2(&E0[slot(t)][0][0], r2);
+            store2(E0[slot(t)], r2);
             load2(a.pt, t, r2);
-            store2(&PT2[slot(t)][0][0], r2);
+            store2(PT2[slot(t)], r2);
         }
-        load1(a.t0, z0 - 1, r1);
-        store1(&TT[slot(z0 - 1)][0][0], r1);
-        load1(a.r, z0 - 1, r1);
-        store1(&RR[slot(z0 - 1)][0][0], r1);
+        fetch_red(z0 - 1, rd_t, rd_r);
     }
     __syncthreads();
 
     for (int t = z0; t <= z1 + 1; ++t) {
-        float ne[NL2], np[NL2], nt[NL1], nr[NL1];
-        const bool pf2 = t + 1 <= z1 + 1, pf1 = t <= z1;
+        const int p = t - 1, p2 = t - 2;
+        float ne[NL2], np[NL2], nrt[NR], nrr[NR], nbt[NB], nbr[NB];
+        const bool pf2 = t + 1 <= z1 + 1, pf_red = t <= z1, pf_blk = t - 1 >= z0 && t - 1 < z1;
         if (pf2) {
             load2(a.ein, t + 1, ne);
             load2(a.pt, t + 1, np);
         }
-        if (pf1) {
-            load1(a.t0, t, nt);
-            load1(a.r, t, nr);
-        }
+        if (pf_red) fetch_red(t, nrt, nrr);
+        if (pf_blk) fetch_black(t - 1, nbt, nbr);
         {
-            const int p = t - 1;
-            const float(*Em)[W2] = E0[slot(p - 1)];
-            const float(*Ec)[W2] = E0[slot(p)];
-            const float(*Ep)[W2] = E0[slot(p + 1)];
-            const float(*Pm)[W2] = PT2[slot(p - 1)];
-            const float(*Pc)[W2] = PT2[slot(p)];
-            const float(*Pp)[W2] = PT2[slot(p + 1)];
-            const float(*Tc)[W1] = TT[slot(p)];
-            const float(*Rc)[W1] = RR[slot(p)];
-            float(*Q1)[W1] = E1[slot(p)];
-            float(*C1)[W1] = PT1[slot(p)];
+            const int sm = slot(p - 1), sc = slot(p), sp = slot(p + 1);
             const bool pzok = DIR ? (p >= 0 && p < g.n2) : true;
-            for (int e = tid; e < RH * H1; e += NT) {
-                const int r = e / RH, m = e - r * RH;
-                const int gy = y0 - 1 + r;
-                const int odd = (gy + p + 1) & 1;
-                const int lx = 2 * m + odd, lb = 2 * m + 1 - odd;
-                const int gx = x0 - 1 + lx;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                int r, lx, lb;
+                if (!red_cell(q, p, r, lx, lb)) continue;
+                const int gx = x0 - 1 + lx, gy = y0 - 1 + r;
                 const int X = lx + 1, Y = r + 1;
                 bool interior = true;
                 if (DIR) interior = pzok && gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1;
-                float val = Ec[Y][X];
+                float val = AE0(sc, Y, X);
                 if (interior) {
                     NbT<float> ve, vp;
-#define LOADNB(v, Pm_, Pc_, Pp_)                                                        \
-    v.xm = Pc_[Y][X - 1]; v.xp = Pc_[Y][X + 1]; v.ym = Pc_[Y - 1][X]; v.yp = Pc_[Y + 1][X]; \
-    v.zm = Pm_[Y][X]; v.zp = Pp_[Y][X];                                                 \
-    v.xpyp = Pc_[Y + 1][X + 1]; v.xmym = Pc_[Y - 1][X - 1];                             \
-    v.xpym = Pc_[Y - 1][X + 1]; v.xmyp = Pc_[Y + 1][X - 1];                             \
-    v.xpzp = Pp_[Y][X + 1]; v.xmzm = Pm_[Y][X - 1]; v.xpzm = Pm_[Y][X + 1]; v.xmzp = Pp_[Y][X - 1]; \
-    v.ypzp = Pp_[Y + 1][X]; v.ymzm = Pm_[Y - 1][X]; v.ypzm = Pm_[Y + 1][X]; v.ymzp = Pp_[Y - 1][X];
-                    LOADNB(ve, Em, Ec, Ep)
-                    LOADNB(vp, Pm, Pc, Pp)
+#define LOADNB(v, A, Sm, Sc, Sp)                                                                   \
+    v.xm = A(Sc, Y, X - 1); v.xp = A(Sc, Y, X + 1); v.ym = A(Sc, Y - 1, X); v.yp = A(Sc, Y + 1, X); \
+    v.zm = A(Sm, Y, X); v.zp = A(Sp, Y, X);                                                          \
+    v.xpyp = A(Sc, Y + 1, X + 1); v.xmym = A(Sc, Y - 1, X - 1);                                      \
+    v.xpym = A(Sc, Y - 1, X + 1); v.xmyp = A(Sc, Y + 1, X - 1);                                      \
+    v.xpzp = A(Sp, Y, X + 1); v.xmzm = A(Sm, Y, X - 1); v.xpzm = A(Sm, Y, X + 1); v.xmzp = A(Sp, Y, X - 1); \
+    v.ypzp = A(Sp, Y + 1, X); v.ymzm = A(Sm, Y - 1, X); v.ypzm = A(Sm, Y + 1, X); v.ymzp = A(Sp, Y - 1, X);
+                    LOADNB(ve, AE0, sm, sc, sp)
+                    LOADNB(vp, AP2, sm, sc, sp)
                     float Se;
                     const float dq = dq_corr(ve, vp, a.c.a_ih4, Se);
-                    const float dQ = dQ_of(dq, Tc[r][lx], a.c);
-                    val = (Se - h2 * (dQ + Rc[r][lx] - cb)) * (1.0f / 6.0f);
+                    const float dQ = dQ_of(dq, rd_t[q], a.c);
+                    val = (Se - h2 * (dQ + rd_r[q] - cb)) * (1.0f / 6.0f);
                 }
-                Q1[r][lx] = val;
-                Q1[r][lb] = Ec[Y][lb + 1];
-                C1[r][lx] = Pc[Y][X];
-                C1[r][lb] = Pc[Y][lb + 1];
+                AE1(sc, r, lx) = val;
+                AE1(sc, r, lb) = AE0(sc, Y, lb + 1);
+                AP1(sc, r, lx) = AP2(sc, Y, X);
+                AP1(sc, r, lb) = AP2(sc, Y, lb + 1);
             }
         }
         __syncthreads();
-        const int p2 = t - 2;
         if (p2 >= z0) {
-            const float(*Em)[W1] = E1[slot(p2 - 1)];
-            const float(*Ec)[W1] = E1[slot(p2)];
-            const float(*Ep)[W1] = E1[slot(p2 + 1)];
-            const float(*Pm)[W1] = PT1[slot(p2 - 1)];
-            const float(*Pc)[W1] = PT1[slot(p2)];
-            const float(*Pp)[W1] = PT1[slot(p2 + 1)];
-            const float(*Tc)[W1] = TT[slot(p2)];
-            const float(*Rc)[W1] = RR[slot(p2)];
-            for (int e = tid; e < BH * TY; e += NT) {
-                const int r = e / BH, m = e - r * BH;
+            const int sm = slot(p2 - 1), sc = slot(p2), sp = slot(p2 + 1);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                int r, xb, xr;
+                if (!black_cell(q, p2, r, xb, xr)) continue;
                 const int gy = y0 + r;
                 if (gy >= g.n1) continue;
-                const int xb = 2 * m + ((gy + p2 + 1) & 1);
-                const int xr = 2 * m + ((gy + p2) & 1);
                 const int64_t rowoff = g.off0 + (int64_t)gy * g.sy + (int64_t)p2 * g.sz + x0;
                 const int X = xb + 1, Y = r + 1;
                 if (x0 + xb < g.n0) {
                     NbT<float> ve, vp;
-                    LOADNB(ve, Em, Ec, Ep)
-                    LOADNB(vp, Pm, Pc, Pp)
+                    LOADNB(ve, AE1, sm, sc, sp)
+                    LOADNB(vp, AP1, sm, sc, sp)
 #undef LOADNB
                     float Se;
                     const float dq = dq_corr(ve, vp, a.c.a_ih4, Se);
-                    const float dQ = dQ_of(dq, Tc[Y][X], a.c);
-                    a.eout[rowoff + xb] = (Se - h2 * (dQ + Rc[Y][X] - cb)) * (1.0f / 6.0f);
+                    const float dQ = dQ_of(dq, bk_t[q], a.c);
+                    a.eout[rowoff + xb] = (Se - h2 * (dQ + bk_r[q] - cb)) * (1.0f / 6.0f);
                 }
-                if (x0 + xr < g.n0) a.eout[rowoff + xr] = Ec[Y][xr + 1];
+                if (x0 + xr < g.n0) a.eout[rowoff + xr] = AE1(sc, Y, xr + 1);
             }
         }
         if (pf2) {
-            store2(&E0[slot(t + 1)][0][0], ne);
-            store2(&PT2[slot(t + 1)][0][0], np);
+            store2(E0[slot(t + 1)], ne);
+            store2(PT2[slot(t + 1)], np);
         }
-        if (pf1) {
-            store1(&TT[slot(t)][0][0], nt);
-            store1(&RR[slot(t)][0][0], nr);
-        }
+#pragma unroll
+        for (int q = 0; q < NR; ++q) { rd_t[q] = nrt[q]; rd_r[q] = nrr[q]; }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) { bk_t[q] = nbt[q]; bk_r[q] = nbr[q]; }
         __syncthreads();
+    }
+#undef AE0
+#undef AP2
+#undef AE1
+#undef AP1
+}
+
+template <int TY, int DIR>
+__global__ void __launch_bounds__(NT) k_smooth_corr(CorrArgs a) {
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = b % a.tiles_x;
+    b /= a.tiles_x;
+    const int ty = b % a.tiles_y;
+    const int ch = b / a.tiles_y;
+    const int z0 = ch * a.zc;
+    if (z0 >= a.g.n2) return;
+    corr_brick<TY, DIR>(a, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
+}
+
+// persistent sweep over a (grid, tile x, tile y, z chunk) work list (Dirichlet batches)
+template <int TY>
+__global__ void __launch_bounds__(NT) k_smooth_corr_batch(CorrArgs proto, const Geom* __restrict__ geoms,
+                                                          const int4* __restrict__ items, int nitems) {
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int4 w = items[it];
+        CorrArgs a = proto;
+        a.g = geoms[w.x];
+        a.c.a_ih4 = proto.c.alpha / (float)(a.g.h * a.g.h * a.g.h * a.g.h);
+        a.c.h2 = (float)(a.g.h * a.g.h);
+        const int z0 = w.w * a.zc;
+        corr_brick<TY, 1>(a, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
     }
 }
 
@@ -383,24 +428,49 @@ __global__ void __launch_bounds__(NT) k_prolong_corr(Geom gf, Geom gc, float* __
 
 // coarsest inner level, whole grid in LDS
 template <int DIR>
-__global__ void __launch_bounds__(NT) k_coarse_corr(Geom g, CoefF c, float* e, const float* pt,
-                                                    const float* t0, const float* r, int sweeps) {
+__device__ __forceinline__ void coarse_corr_body(Geom g, CoefF c, float* e, float* e_also, const float* pt,
+                                                 const float* t0, const float* r, int sweeps,
+                                                 const float* old = nullptr) {
     constexpr int CM = 1000;
-    __shared__ float se[CM], sp[CM], st[CM], sr[CM];
+    __shared__ float se[CM], sp[CM], st[CM], sr[CM], so[CM];
     __shared__ double red[NT / 64];
-    const int tid = threadIdx.x;
-    for (int64_t q = tid; q < g.nstore; q += NT) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    e += g.base;
+    pt += g.base;
+    t0 += g.base;
+    r += g.base;
+    if (e_also) e_also += g.base;
+    if (old) old += g.base;
+    c.a_ih4 = c.alpha / (float)(g.h * g.h * g.h * g.h);
+    c.h2 = (float)(g.h * g.h);
+    g.off0 -= g.base;
+    g.base = 0;
+    for (int64_t q = tid; q < g.nstore; q += nt) {
         se[q] = e[q];
         sp[q] = pt[q];
         st[q] = t0[q];
         sr[q] = r[q];
+        if (DIR && old) so[q] = old[q];
     }
     __syncthreads();
+    const int64_t nghost = DIR ? ghost_count_dev(g.n0, g.n1, g.n2) : 0;
+    auto refresh_ghosts = [&]() {
+        if (!DIR || !old) return;
+        for (int64_t q = tid; q < nghost; q += nt) {
+            int i, j, k;
+            ghost_coords(g.n0, g.n1, g.n2, q, i, j, k);
+            int sign = 1;
+            const int ir = mirror(i, g.n0, sign), jr = mirror(j, g.n1, sign), kr = mirror(k, g.n2, sign);
+            const int64_t gi = cell_index(g, i, j, k), ii = cell_index(g, ir, jr, kr);
+            se[gi] = so[gi] + (float)sign * (se[ii] - so[ii]);
+        }
+        __syncthreads();
+    };
     const float h2 = c.h2;
     double sumr = 0.0;
     if (!DIR) {
         double acc = 0.0;
-        for (int64_t q = tid; q < g.ncell; q += NT) {
+        for (int64_t q = tid; q < g.ncell; q += nt) {
             int i, j, k;
             decode(g, q, i, j, k);
             acc += sr[cell_index(g, i, j, k)];
@@ -408,15 +478,15 @@ __global__ void __launch_bounds__(NT) k_coarse_corr(Geom g, CoefF c, float* e, c
         acc = wave_sum(acc);
         if ((tid & 63) == 0) red[tid >> 6] = acc;
         __syncthreads();
-        for (int w = 0; w < NT / 64; ++w) sumr += red[w];
+        for (int w = 0; w < nt / 64; ++w) sumr += red[w];
         __syncthreads();
     }
-    const int per = (int)((g.ncell + NT - 1) / NT);
+    const int per = (int)((g.ncell + nt - 1) / nt);
     for (int s = 0; s < sweeps; ++s) {
         float cb = 0.0f;
         if (!DIR) {
             double acc = 0.0;
-            for (int64_t q = tid; q < g.ncell; q += NT) {
+            for (int64_t q = tid; q < g.ncell; q += nt) {
                 int i, j, k;
                 decode(g, q, i, j, k);
                 NbT<float> ve, vp;
@@ -429,7 +499,7 @@ __global__ void __launch_bounds__(NT) k_coarse_corr(Geom g, CoefF c, float* e, c
             if ((tid & 63) == 0) red[tid >> 6] = acc;
             __syncthreads();
             double sq = 0.0;
-            for (int w = 0; w < NT / 64; ++w) sq += red[w];
+            for (int w = 0; w < nt / 64; ++w) sq += red[w];
             cb = (float)((sumr + sq) / (double)g.ncell);
             __syncthreads();
         }
@@ -437,7 +507,7 @@ __global__ void __launch_bounds__(NT) k_coarse_corr(Geom g, CoefF c, float* e, c
             float nv[2];
             int64_t ni[2] = {-1, -1};
             for (int q = 0; q < per && q < 2; ++q) {
-                const int64_t m = tid + (int64_t)q * NT;
+                const int64_t m = tid + (int64_t)q * nt;
                 if (m >= g.ncell) continue;
                 int i, j, k;
                 decode(g, m, i, j, k);
@@ -455,14 +525,65 @@ __global__ void __launch_bounds__(NT) k_coarse_corr(Geom g, CoefF c, float* e, c
             for (int q = 0; q < 2; ++q)
                 if (ni[q] >= 0) se[ni[q]] = nv[q];
             __syncthreads();
+            refresh_ghosts();
         }
     }
-    for (int64_t q = tid; q < g.ncell; q += NT) {
+    for (int64_t q = tid; q < g.ncell; q += nt) {
         int i, j, k;
         decode(g, q, i, j, k);
         const int64_t li = cell_index(g, i, j, k);
         e[li] = se[li];
+        if (e_also) e_also[li] = se[li];
     }
+    if (DIR && old)
+        for (int64_t q = tid; q < nghost; q += nt) {
+            int i, j, k;
+            ghost_coords(g.n0, g.n1, g.n2, q, i, j, k);
+            const int64_t li = cell_index(g, i, j, k);
+            e[li] = se[li];
+            if (e_also) e_also[li] = se[li];
+        }
+    __syncthreads();
+}
+
+template <int DIR>
+__global__ void __launch_bounds__(NT) k_coarse_corr(Geom g, CoefF c, float* e, const float* pt,
+                                                    const float* t0, const float* r, int sweeps) {
+    coarse_corr_body<DIR>(g, c, e, nullptr, pt, t0, r, sweeps);
+}
+
+// coarsest inner levels of several Dirichlet grids, one block per grid; result in both e buffers
+__global__ void __launch_bounds__(NT) k_coarse_corr_batch(const Geom* __restrict__ gs, CoefF c, float* e0,
+                                                          float* e1, const float* pt, const float* t0,
+                                                          const float* r, int sweeps, const float* old) {
+    coarse_corr_body<1>(gs[blockIdx.x], c, e0, e1, pt, t0, r, sweeps, old);
+}
+
+// D0 = 1 + (8 alpha/3)(alpha Sigma0 + kappa delta) of the FP64 state (same arithmetic as nl_root)
+__device__ __forceinline__ double base_discriminant(const Nb& v, double dl, const Coef& c, double inv_h4) {
+    const double sx = v.xp + v.xm, sy = v.yp + v.ym, sz = v.zp + v.zm;
+    const double dxy = sx - sy, dxz = sx - sz, dyz = sy - sz;
+    const double bxy = (v.xpyp + v.xmym) - (v.xpym + v.xmyp);
+    const double bxz = (v.xpzp + v.xmzm) - (v.xpzm + v.xmzp);
+    const double byz = (v.ypzp + v.ymzm) - (v.ypzm + v.ymzp);
+    const double s0 = ((dxy * dxy + dxz * dxz + dyz * dyz) * (1.0 / 3.0)
+                     + (bxy * bxy + bxz * bxz + byz * byz) * 0.125) * inv_h4;
+    return 1.0 + c.c8 * (c.alpha * s0 + c.kappa * dl);
+}
+
+// t0 = +-sqrt|D0| of a coarse inner level from its FP32 base state and density
+template <int DIR>
+__device__ __forceinline__ float base_t0_cell(const Geom& g, const Coef& c, const float* pt, const double* delta,
+                                              int i, int j, int k, double inv_h4) {
+    NbT<float> vf;
+    gather_nb<DIR>(g, pt, i, j, k, vf);
+    Nb v;
+    v.xm = vf.xm; v.xp = vf.xp; v.ym = vf.ym; v.yp = vf.yp; v.zm = vf.zm; v.zp = vf.zp;
+    v.xpyp = vf.xpyp; v.xmym = vf.xmym; v.xpym = vf.xpym; v.xmyp = vf.xmyp;
+    v.xpzp = vf.xpzp; v.xmzm = vf.xmzm; v.xpzm = vf.xpzm; v.xmzp = vf.xmzp;
+    v.ypzp = vf.ypzp; v.ymzm = vf.ymzm; v.ypzm = vf.ypzm; v.ymzp = vf.ymzp;
+    const double D0 = base_discriminant(v, delta[cell_index(g, i, j, k)], c, inv_h4);
+    return (float)(D0 >= 0.0 ? sqrt(D0) : -sqrt(-D0));
 }
 
 // ---------------------------------------------------------------------------
@@ -566,6 +687,535 @@ __global__ void k_cast_all(const double* src, float* dst, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// Tiled passes of the mixed path (same brick / z-march layout as the FP64
+// residual pass: 64 x 8 x 16 bricks, one-cell LDS ring, thread = x pair of a row)
+// ---------------------------------------------------------------------------
+constexpr int MTY = 8, MZC = 16;
+
+struct CastArgs {
+    Geom g;
+    Coef c;
+    const double* phi;     // current FP64 iterate
+    const float* e;        // correction to add first (UPDATE), else unused
+    double* phi_out;       // phi + e (UPDATE), else unused
+    const double* delta;
+    const double* f;       // optional source
+    const LevelScalars* sc;
+    float *pt, *t0, *r;
+    double* partials;
+    int tiles_x, tiles_y;
+};
+
+// Outer FP64 pass: phi_new = phi (+ e), d = L(phi_new) + cbar - f, norm partials,
+// and the inner problem's inputs phi~ = fp32(phi_new), t0 = +-sqrt|D0|, r = -d.
+template <int DIR, bool UPDATE>
+__global__ void __launch_bounds__(NT) k_cast_tiled(CastArgs a) {
+    constexpr int W1 = TX + 2, H1 = MTY + 2, NP1 = W1 * H1, NL1 = (NP1 + NT - 1) / NT;
+    __shared__ double PH[3][H1][W1];
+    const Geom& g = a.g;
+    const int tid = threadIdx.x;
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = b % a.tiles_x;
+    b /= a.tiles_x;
+    const int ty = b % a.tiles_y;
+    const int ch = b / a.tiles_y;
+    const int x0 = tx * TX, y0 = ty * MTY, z0 = ch * MZC;
+    const int z1 = min(z0 + MZC, g.n2);
+    double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
+    const double cb = DIR ? 0.0 : a.sc->cbar;
+    const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+    const int m = tid & 31, r = tid >> 5;
+    const int gy = y0 + r, xa = x0 + 2 * m;
+    const bool row_ok = gy < g.n1;
+    int off1[NL1];
+    bool ok1[NL1];
+#pragma unroll
+    for (int s2 = 0; s2 < NL1; ++s2) {
+        const int e = tid + s2 * NT;
+        ok1[s2] = false;
+        off1[s2] = 0;
+        if (e < NP1) {
+            int gx = x0 - 1 + e % W1, gyy = y0 - 1 + e / W1;
+            if (DIR) {
+                ok1[s2] = gx >= -1 && gx <= g.n0 && gyy >= -1 && gyy <= g.n1;
+            } else {
+                gx = wrapi(gx, g.n0);
+                gyy = wrapi(gyy, g.n1);
+                ok1[s2] = true;
+            }
+            off1[s2] = (int)(g.off0 + gx + (int64_t)gyy * g.sy);
+        }
+    }
+    auto plane_off = [&](int t, bool& zok) -> int64_t {
+        int gz;
+        if (DIR) { gz = t; zok = t >= -1 && t <= g.n2; }
+        else { gz = t < 0 ? t + g.n2 : (t >= g.n2 ? t - g.n2 : t); zok = true; }
+        return (int64_t)gz * g.sz;
+    };
+    auto load_plane = [&](int t, double (&rr)[NL1]) {
+        bool zok;
+        const int64_t zo = plane_off(t, zok);
+#pragma unroll
+        for (int s2 = 0; s2 < NL1; ++s2) {
+            const bool ok = ok1[s2] && zok && tid + s2 * NT < NP1;
+            double v = ok ? a.phi[zo + off1[s2]] : 0.0;
+            if (UPDATE && ok) v += (double)a.e[zo + off1[s2]];   // e is zero on ghosts
+            rr[s2] = v;
+        }
+    };
+    auto store_plane = [&](int sl, const double (&rr)[NL1]) {
+        double* dst = &PH[sl][0][0];
+#pragma unroll
+        for (int s2 = 0; s2 < NL1; ++s2)
+            if (tid + s2 * NT < NP1) dst[tid + s2 * NT] = rr[s2];
+    };
+    auto slot = [](int z) { return (z + 3) % 3; };
+    auto src_fetch = [&](int t, double (&dl)[2], double (&fv)[2]) {
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+            dl[c2] = 0.0;
+            fv[c2] = 0.0;
+            if (!row_ok || xa + c2 >= g.n0 || t >= z1) continue;
+            const int64_t gi = g.off0 + xa + c2 + (int64_t)gy * g.sy + (int64_t)t * g.sz;
+            dl[c2] = a.delta[gi];
+            if (a.f) fv[c2] = a.f[gi];
+        }
+    };
+    {
+        double rr[NL1];
+        for (int t = z0 - 1; t <= z0 + 1; ++t) {
+            load_plane(t, rr);
+            store_plane(slot(t), rr);
+        }
+    }
+    double cdl[2], cfv[2];
+    src_fetch(z0, cdl, cfv);
+    __syncthreads();
+    for (int t = z0; t < z1; ++t) {
+        double nxt[NL1], ndl[2], nfv[2];
+        const bool pf = t + 2 <= z1;
+        if (pf) load_plane(t + 2, nxt);
+        src_fetch(t + 1, ndl, nfv);
+        const int sm = slot(t - 1), sc = slot(t), sp = slot(t + 1);
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+            const int X = 2 * m + c2 + 1, Y = r + 1;
+            if (!row_ok || xa + c2 >= g.n0) continue;
+            Nb v;
+            v.xm = PH[sc][Y][X - 1]; v.xp = PH[sc][Y][X + 1];
+            v.ym = PH[sc][Y - 1][X]; v.yp = PH[sc][Y + 1][X];
+            v.zm = PH[sm][Y][X];     v.zp = PH[sp][Y][X];
+            v.xpyp = PH[sc][Y + 1][X + 1]; v.xmym = PH[sc][Y - 1][X - 1];
+            v.xpym = PH[sc][Y - 1][X + 1]; v.xmyp = PH[sc][Y + 1][X - 1];
+            v.xpzp = PH[sp][Y][X + 1]; v.xmzm = PH[sm][Y][X - 1];
+            v.xpzm = PH[sm][Y][X + 1]; v.xmzp = PH[sp][Y][X - 1];
+            v.ypzp = PH[sp][Y + 1][X]; v.ymzm = PH[sm][Y - 1][X];
+            v.ypzm = PH[sm][Y + 1][X]; v.ymzp = PH[sp][Y - 1][X];
+            const double pc = PH[sc][Y][X];
+            double S;
+            bool gd;
+            const double Q = nl_root(v, cdl[c2], a.c, inv_h4, S, gd);
+            const double D0 = base_discriminant(v, cdl[c2], a.c, inv_h4);
+            const double d = (S - 6.0 * pc) * inv_h2 - Q - cfv[c2] + cb;
+            const int64_t gi = g.off0 + xa + c2 + (int64_t)gy * g.sy + (int64_t)t * g.sz;
+            if (UPDATE) a.phi_out[gi] = pc;
+            a.pt[gi] = (float)pc;
+            a.t0[gi] = (float)(D0 >= 0.0 ? sqrt(D0) : -sqrt(-D0));
+            a.r[gi] = (float)(-d);
+            acc[R_D2] += d * d;
+            acc[R_D1] += d;
+            acc[R_Q] += Q;
+            acc[R_F] += cfv[c2];
+            acc[R_PHI] += pc;
+            acc[R_GUARD] += gd ? 1.0 : 0.0;
+            acc[R_NONFIN] += isfinite(d) ? 0.0 : 1.0;
+        }
+        __syncthreads();
+        if (pf) store_plane(slot(t + 2), nxt);
+        cdl[0] = ndl[0]; cdl[1] = ndl[1];
+        cfv[0] = nfv[0]; cfv[1] = nfv[1];
+        __syncthreads();
+    }
+    block_store_partials(acc, a.partials);
+}
+
+struct CorrResArgs {
+    Geom g, gc;
+    CoefF c;
+    const float* e;
+    const float* pt;
+    const float* t0;
+    const float* r;            // inner rhs (MODE 1) or R d_e (MODE 2)
+    const LevelScalars* sc;    // inner cbar (MODE 1, periodic)
+    float *ec, *eold_c, *rd_c; // MODE 1
+    float* rout;               // MODE 2
+    double* partials;
+    int tiles_x, tiles_y;
+};
+
+// MODE 1: inner residual d_e = Lap e - dQ(e) - r + cbar_e, reductions, R e -> ec, eold_c, R d_e -> rd_c
+// MODE 2: coarse inner rhs rout = Lap e - dQ(e) - rd, reductions of dQ and rout
+template <int DIR, int MODE>
+__global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
+    constexpr int W1 = TX + 2, H1 = MTY + 2, NP1 = W1 * H1, NL1 = (NP1 + NT - 1) / NT;
+    __shared__ float EE[3][H1][W1];
+    __shared__ float PP[3][H1][W1];
+    const Geom& g = a.g;
+    const int tid = threadIdx.x;
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = b % a.tiles_x;
+    b /= a.tiles_x;
+    const int ty = b % a.tiles_y;
+    const int ch = b / a.tiles_y;
+    const int x0 = tx * TX, y0 = ty * MTY, z0 = ch * MZC;
+    const int z1 = min(z0 + MZC, g.n2);
+    double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
+    const float cb = (DIR || MODE == 2) ? 0.0f : (float)a.sc->cbar;
+    const float inv_h2 = 1.0f / a.c.h2;
+    const int m = tid & 31, r = tid >> 5;
+    const int gy = y0 + r, xa = x0 + 2 * m;
+    const bool row_ok = gy < g.n1;
+    int off1[NL1];
+    bool ok1[NL1];
+#pragma unroll
+    for (int s2 = 0; s2 < NL1; ++s2) {
+        const int e = tid + s2 * NT;
+        ok1[s2] = false;
+        off1[s2] = 0;
+        if (e < NP1) {
+            int gx = x0 - 1 + e % W1, gyy = y0 - 1 + e / W1;
+            if (DIR) {
+                ok1[s2] = gx >= -1 && gx <= g.n0 && gyy >= -1 && gyy <= g.n1;
+            } else {
+                gx = wrapi(gx, g.n0);
+                gyy = wrapi(gyy, g.n1);
+                ok1[s2] = true;
+            }
+            off1[s2] = (int)(g.off0 + gx + (int64_t)gyy * g.sy);
+        }
+    }
+    auto plane_off = [&](int t, bool& zok) -> int64_t {
+        int gz;
+        if (DIR) { gz = t; zok = t >= -1 && t <= g.n2; }
+        else { gz = t < 0 ? t + g.n2 : (t >= g.n2 ? t - g.n2 : t); zok = true; }
+        return (int64_t)gz * g.sz;
+    };
+    auto load_planes = [&](int t, float (&re)[NL1], float (&rp)[NL1]) {
+        bool zok;
+        const int64_t zo = plane_off(t, zok);
+#pragma unroll
+        for (int s2 = 0; s2 < NL1; ++s2) {
+            const bool ok = ok1[s2] && zok && tid + s2 * NT < NP1;
+            re[s2] = ok ? a.e[zo + off1[s2]] : 0.0f;
+            rp[s2] = ok ? a.pt[zo + off1[s2]] : 0.0f;
+        }
+    };
+    auto store_planes = [&](int sl, const float (&re)[NL1], const float (&rp)[NL1]) {
+        float* de = &EE[sl][0][0];
+        float* dp = &PP[sl][0][0];
+#pragma unroll
+        for (int s2 = 0; s2 < NL1; ++s2)
+            if (tid + s2 * NT < NP1) {
+                de[tid + s2 * NT] = re[s2];
+                dp[tid + s2 * NT] = rp[s2];
+            }
+    };
+    auto slot = [](int z) { return (z + 3) % 3; };
+    auto src_fetch = [&](int t, float (&tt)[2], float (&rv)[2]) {
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+            tt[c2] = 1.0f;
+            rv[c2] = 0.0f;
+            if (!row_ok || xa + c2 >= g.n0 || t >= z1) continue;
+            const int64_t gi = g.off0 + xa + c2 + (int64_t)gy * g.sy + (int64_t)t * g.sz;
+            tt[c2] = a.t0[gi];
+            rv[c2] = a.r[gi];
+        }
+    };
+    {
+        float re[NL1], rp[NL1];
+        for (int t = z0 - 1; t <= z0 + 1; ++t) {
+            load_planes(t, re, rp);
+            store_planes(slot(t), re, rp);
+        }
+    }
+    float ctt[2], crv[2];
+    src_fetch(z0, ctt, crv);
+    __syncthreads();
+    float zs_e = 0.0f, zs_d = 0.0f;
+    for (int t = z0; t < z1; ++t) {
+        float ne[NL1], np[NL1], ntt[2], nrv[2];
+        const bool pf = t + 2 <= z1;
+        if (pf) load_planes(t + 2, ne, np);
+        src_fetch(t + 1, ntt, nrv);
+        const int sm = slot(t - 1), sc = slot(t), sp = slot(t + 1);
+        float esum = 0.0f, dsum = 0.0f;
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+            const int X = 2 * m + c2 + 1, Y = r + 1;
+            if (!row_ok || xa + c2 >= g.n0) continue;
+            NbT<float> ve, vp;
+#define LNB(v, A)                                                                          \
+    v.xm = A[sc][Y][X - 1]; v.xp = A[sc][Y][X + 1]; v.ym = A[sc][Y - 1][X]; v.yp = A[sc][Y + 1][X]; \
+    v.zm = A[sm][Y][X]; v.zp = A[sp][Y][X];                                                \
+    v.xpyp = A[sc][Y + 1][X + 1]; v.xmym = A[sc][Y - 1][X - 1];                            \
+    v.xpym = A[sc][Y - 1][X + 1]; v.xmyp = A[sc][Y + 1][X - 1];                            \
+    v.xpzp = A[sp][Y][X + 1]; v.xmzm = A[sm][Y][X - 1]; v.xpzm = A[sm][Y][X + 1]; v.xmzp = A[sp][Y][X - 1]; \
+    v.ypzp = A[sp][Y + 1][X]; v.ymzm = A[sm][Y - 1][X]; v.ypzm = A[sm][Y + 1][X]; v.ymzp = A[sp][Y - 1][X];
+            LNB(ve, EE)
+            LNB(vp, PP)
+#undef LNB
+            const float ecv = EE[sc][Y][X];
+            float Se;
+            const float dq = dq_corr(ve, vp, a.c.a_ih4, Se);
+            const float dQ = dQ_of(dq, ctt[c2], a.c);
+            const float L = (Se - 6.0f * ecv) * inv_h2 - dQ;
+            if (MODE == 2) {
+                const float rh = L - crv[c2];
+                a.rout[g.off0 + xa + c2 + (int64_t)gy * g.sy + (int64_t)t * g.sz] = rh;
+                acc[R_Q] += dQ;
+                acc[R_F] += rh;
+            } else {
+                const float d = L - crv[c2] + cb;
+                acc[R_D2] += (double)d * d;
+                acc[R_D1] += d;
+                acc[R_Q] += dQ;
+                acc[R_F] += crv[c2];
+                acc[R_NONFIN] += isfinite(d) ? 0.0 : 1.0;
+                esum += ecv;
+                dsum += d;
+            }
+        }
+        if (MODE == 1) {
+            esum += __shfl_down(esum, 32, 64);
+            dsum += __shfl_down(dsum, 32, 64);
+            if ((t & 1) == 0) {
+                zs_e = esum;
+                zs_d = dsum;
+            } else if ((r & 1) == 0 && row_ok && xa < g.n0) {
+                const Geom& gc = a.gc;
+                const int64_t co = gc.off0 + (xa >> 1) + (int64_t)(gy >> 1) * gc.sy + (int64_t)(t >> 1) * gc.sz;
+                const float re = 0.125f * (zs_e + esum);
+                a.ec[co] = re;
+                a.eold_c[co] = re;
+                a.rd_c[co] = 0.125f * (zs_d + dsum);
+            }
+        }
+        __syncthreads();
+        if (pf) store_planes(slot(t + 2), ne, np);
+        ctt[0] = ntt[0]; ctt[1] = ntt[1];
+        crv[0] = nrv[0]; crv[1] = nrv[1];
+        __syncthreads();
+    }
+    block_store_partials(acc, a.partials);
+}
+
+// tiled FP32 prolongation + correction (see k_prolong_tiled)
+template <int DIR>
+__global__ void __launch_bounds__(NT) k_prolong_corr_tiled(Geom gf, Geom gc, float* __restrict__ ef,
+                                                           const float* __restrict__ ecs,
+                                                           const float* __restrict__ oldc, int tiles_x, int tiles_y) {
+    constexpr int PZF = 16;
+    constexpr int CX = TX / 2 + 2, CY = 8 / 2 + 2, CZ = PZF / 2 + 2;
+    __shared__ float C[CZ][CY][CX];
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = b % tiles_x;
+    b /= tiles_x;
+    const int ty = b % tiles_y;
+    const int ch = b / tiles_y;
+    const int x0 = tx * TX, y0 = ty * 8, z0 = ch * PZF;
+    const int cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1, cz0 = z0 / 2 - 1;
+    for (int e = threadIdx.x; e < CX * CY * CZ; e += NT) {
+        const int lx = e % CX, ly = (e / CX) % CY, lz = e / (CX * CY);
+        int I = cx0 + lx, J = cy0 + ly, K = cz0 + lz;
+        float v = 0.0f;
+        if (DIR) {
+            if (I >= 0 && I < gc.n0 && J >= 0 && J < gc.n1 && K >= 0 && K < gc.n2) {
+                const int64_t ci = cell_index(gc, I, J, K);
+                v = ecs[ci] - oldc[ci];
+            }
+        } else {
+            I = wrapi(I, gc.n0);
+            J = wrapi(J, gc.n1);
+            K = wrapi(K, gc.n2);
+            const int64_t ci = cell_index(gc, I, J, K);
+            v = ecs[ci] - oldc[ci];
+        }
+        C[lz][ly][lx] = v;
+    }
+    __syncthreads();
+    const int lxf = threadIdx.x & 63;
+    const int i = x0 + lxf;
+    if (i >= gf.n0) return;
+    const int Ii = (i >> 1) - cx0, si = (i & 1) ? 1 : -1;
+    for (int q = threadIdx.x >> 6; q < 8 * PZF; q += NT / 64) {
+        const int j = y0 + (q & 7), k = z0 + (q >> 3);
+        if (j >= gf.n1 || k >= gf.n2) continue;
+        const int Jj = (j >> 1) - cy0, sj = (j & 1) ? 1 : -1;
+        const int Kk = (k >> 1) - cz0, sk = (k & 1) ? 1 : -1;
+        const float x00 = 0.75f * C[Kk][Jj][Ii] + 0.25f * C[Kk][Jj][Ii + si];
+        const float x10 = 0.75f * C[Kk][Jj + sj][Ii] + 0.25f * C[Kk][Jj + sj][Ii + si];
+        const float x01 = 0.75f * C[Kk + sk][Jj][Ii] + 0.25f * C[Kk + sk][Jj][Ii + si];
+        const float x11 = 0.75f * C[Kk + sk][Jj + sj][Ii] + 0.25f * C[Kk + sk][Jj + sj][Ii + si];
+        ef[cell_index(gf, i, j, k)] += 0.75f * (0.75f * x00 + 0.25f * x10) + 0.25f * (0.75f * x01 + 0.25f * x11);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched Dirichlet kernels of the mixed path (items = (grid, first cell) blocks
+// of 256 cells over pooled level buffers; coefficients follow each grid's h)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ CoefF coef_for(CoefF c, const Geom& g) {
+    c.a_ih4 = c.alpha / (float)(g.h * g.h * g.h * g.h);
+    c.h2 = (float)(g.h * g.h);
+    return c;
+}
+
+__global__ void __launch_bounds__(NT) k_rr_corr_batch(const Geom* __restrict__ gfs, const Geom* __restrict__ gcs,
+                                                      const int2* __restrict__ items, CoefF c0,
+                                                      const float* __restrict__ e, const float* __restrict__ pt,
+                                                      const float* __restrict__ t0, const float* __restrict__ r,
+                                                      float* ec, float* eold_c, float* rd_c) {
+    const int2 w = items[blockIdx.x];
+    const Geom gf = gfs[w.x], gc = gcs[w.x];
+    const int64_t q = (int64_t)w.y + threadIdx.x;
+    if (q >= gc.ncell) return;
+    const CoefF c = coef_for(c0, gf);
+    const float inv_h2 = 1.0f / c.h2;
+    int I, J, K;
+    decode(gc, q, I, J, K);
+    float se = 0.0f, sd = 0.0f;
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) {
+        const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
+        float dQ, ev, rv;
+        sd += corr_residual<1>(gf, c, e, pt, t0, r, 0.0f, i, j, k, inv_h2, dQ, ev, rv);
+        se += ev;
+    }
+    const int64_t co = cell_index(gc, I, J, K);
+    ec[co] = 0.125f * se;
+    eold_c[co] = 0.125f * se;
+    rd_c[co] = 0.125f * sd;
+}
+
+__global__ void __launch_bounds__(NT) k_fas_corr_batch(const Geom* __restrict__ gs, const int2* __restrict__ items,
+                                                       CoefF c0, const float* __restrict__ e,
+                                                       const float* __restrict__ pt, const float* __restrict__ t0,
+                                                       const float* __restrict__ rd, float* r) {
+    const int2 w = items[blockIdx.x];
+    const Geom g = gs[w.x];
+    const int64_t q = (int64_t)w.y + threadIdx.x;
+    if (q >= g.ncell) return;
+    const CoefF c = coef_for(c0, g);
+    int i, j, k;
+    decode(g, q, i, j, k);
+    float dQ, ev, rv;
+    const float L = corr_residual<1>(g, c, e, pt, t0, nullptr, 0.0f, i, j, k, 1.0f / c.h2, dQ, ev, rv);
+    const int64_t gi = cell_index(g, i, j, k);
+    r[gi] = L - rd[gi];
+}
+
+__global__ void __launch_bounds__(NT) k_prolong_corr_batch(const Geom* __restrict__ gfs, const Geom* __restrict__ gcs,
+                                                           const int2* __restrict__ items, float* __restrict__ ef,
+                                                           const float* __restrict__ ecs,
+                                                           const float* __restrict__ oldc) {
+    const int2 w = items[blockIdx.x];
+    const Geom gf = gfs[w.x], gc = gcs[w.x];
+    const int64_t q = (int64_t)w.y + threadIdx.x;
+    if (q >= gf.ncell) return;
+    int i, j, k;
+    decode(gf, q, i, j, k);
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+    float acc = 0.0f;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        int sign = 1;
+        const int ii = mirror(I + ((m & 1) ? si : 0), gc.n0, sign);
+        const int jj = mirror(J + ((m & 2) ? sj : 0), gc.n1, sign);
+        const int kk = mirror(K + ((m & 4) ? sk : 0), gc.n2, sign);
+        const float wq = ((m & 1) ? 0.25f : 0.75f) * ((m & 2) ? 0.25f : 0.75f) * ((m & 4) ? 0.25f : 0.75f);
+        const int64_t ci = cell_index(gc, ii, jj, kk);
+        acc += wq * (float)sign * (ecs[ci] - oldc[ci]);
+    }
+    ef[cell_index(gf, i, j, k)] += acc;
+}
+
+__global__ void __launch_bounds__(NT) k_cast_batch(const Geom* __restrict__ gs, const int2* __restrict__ items,
+                                                   Coef c, const double* __restrict__ phi,
+                                                   const double* __restrict__ delta, const double* __restrict__ f,
+                                                   float* pt, float* t0, float* r, double* partials) {
+    double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
+    const int2 w = items[blockIdx.x];
+    const Geom g = gs[w.x];
+    const int64_t q = (int64_t)w.y + threadIdx.x;
+    if (q < g.ncell) {
+        const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+        int i, j, k;
+        decode(g, q, i, j, k);
+        Nb v;
+        const double pc = gather_nb<1>(g, phi, i, j, k, v);
+        const int64_t gi = cell_index(g, i, j, k);
+        double S;
+        bool gd;
+        const double dl = delta[gi];
+        const double Q = nl_root(v, dl, c, inv_h4, S, gd);
+        const double D0 = base_discriminant(v, dl, c, inv_h4);
+        const double fv = f ? f[gi] : 0.0;
+        const double d = (S - 6.0 * pc) * inv_h2 - Q - fv;
+        pt[gi] = (float)pc;
+        t0[gi] = (float)(D0 >= 0.0 ? sqrt(D0) : -sqrt(-D0));
+        r[gi] = (float)(-d);
+        acc[R_D2] = d * d;
+        acc[R_D1] = d;
+        acc[R_Q] = Q;
+        acc[R_F] = fv;
+        acc[R_PHI] = pc;
+        acc[R_GUARD] = gd ? 1.0 : 0.0;
+        acc[R_NONFIN] = isfinite(d) ? 0.0 : 1.0;
+    }
+    block_store_partials(acc, partials);
+}
+
+__global__ void k_base_restrict_batch(const Geom* __restrict__ gfs, const Geom* __restrict__ gcs,
+                                      const int2* __restrict__ items, const float* pf, float* pc) {
+    const int2 w = items[blockIdx.x];
+    const Geom gf = gfs[w.x], gc = gcs[w.x];
+    const int64_t q = (int64_t)w.y + threadIdx.x;
+    if (q >= gc.ncell) return;
+    int I, J, K;
+    decode(gc, q, I, J, K);
+    float s = 0.0f;
+    for (int ch = 0; ch < 8; ++ch)
+        s += pf[cell_index(gf, 2 * I + (ch & 1), 2 * J + ((ch >> 1) & 1), 2 * K + (ch >> 2))];
+    pc[cell_index(gc, I, J, K)] = 0.125f * s;
+}
+
+__global__ void k_base_t0_batch(const Geom* __restrict__ gs, const int2* __restrict__ items, Coef c,
+                                const float* pt, const double* delta, float* t0) {
+    const int2 w = items[blockIdx.x];
+    const Geom g = gs[w.x];
+    const int64_t q = (int64_t)w.y + threadIdx.x;
+    if (q >= g.ncell) return;
+    const double inv_h4 = 1.0 / (g.h * g.h * g.h * g.h);
+    int i, j, k;
+    decode(g, q, i, j, k);
+    t0[cell_index(g, i, j, k)] = base_t0_cell<1>(g, c, pt, delta, i, j, k, inv_h4);
+}
+
+__global__ void k_update_batch(const Geom* __restrict__ gs, const int2* __restrict__ items, double* phi,
+                               const float* e) {
+    const int2 w = items[blockIdx.x];
+    const Geom g = gs[w.x];
+    const int64_t q = (int64_t)w.y + threadIdx.x;
+    if (q >= g.ncell) return;
+    int i, j, k;
+    decode(g, q, i, j, k);
+    const int64_t gi = cell_index(g, i, j, k);
+    phi[gi] += (double)e[gi];
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 template <int TY, int DIR>
@@ -593,47 +1243,84 @@ hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, f
     return corr_launch<8, 0>(a, s);
 }
 
+static void corr_tiles(const Geom& g, int& tx, int& ty, int& nb) {
+    tx = (g.n0 + TX - 1) / TX;
+    ty = (g.n1 + MTY - 1) / MTY;
+    nb = tx * ty * ((g.n2 + MZC - 1) / MZC);
+}
+
 hipError_t launch_rr_corr(const Geom& gf, const Geom& gc, const CoefF& c, const float* e, const float* pt,
                           const float* t0, const float* r, const LevelScalars* sc, float* ec, float* eold_c,
                           float* rd_c, double* partials, int* nblocks_out, hipStream_t s) {
-    const int nb = grid_for(gc.ncell, 2048);
-    if (gf.dir)
-        hipLaunchKernelGGL(k_rr_corr<1>, dim3(nb), dim3(NT), 0, s, gf, gc, c, e, pt, t0, r, sc, ec, eold_c, rd_c,
-                           partials);
-    else
-        hipLaunchKernelGGL(k_rr_corr<0>, dim3(nb), dim3(NT), 0, s, gf, gc, c, e, pt, t0, r, sc, ec, eold_c, rd_c,
-                           partials);
+    CorrResArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = gf; a.gc = gc; a.c = c; a.e = e; a.pt = pt; a.t0 = t0; a.r = r; a.sc = sc;
+    a.ec = ec; a.eold_c = eold_c; a.rd_c = rd_c; a.partials = partials;
+    int nb;
+    corr_tiles(gf, a.tiles_x, a.tiles_y, nb);
     *nblocks_out = nb;
+    if (gf.dir)
+        hipLaunchKernelGGL((k_corr_tiled<1, 1>), dim3(nb), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_corr_tiled<0, 1>), dim3(nb), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_fas_corr(const Geom& g, const CoefF& c, const float* e, const float* pt, const float* t0,
                            const float* rd, float* r, double* partials, int* nblocks_out, hipStream_t s) {
-    const int nb = grid_for(g.ncell, 2048);
-    if (g.dir)
-        hipLaunchKernelGGL(k_fas_corr<1>, dim3(nb), dim3(NT), 0, s, g, c, e, pt, t0, rd, r, partials);
-    else
-        hipLaunchKernelGGL(k_fas_corr<0>, dim3(nb), dim3(NT), 0, s, g, c, e, pt, t0, rd, r, partials);
+    CorrResArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = g; a.c = c; a.e = e; a.pt = pt; a.t0 = t0; a.r = rd; a.rout = r; a.partials = partials;
+    int nb;
+    corr_tiles(g, a.tiles_x, a.tiles_y, nb);
     *nblocks_out = nb;
+    if (g.dir)
+        hipLaunchKernelGGL((k_corr_tiled<1, 2>), dim3(nb), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_corr_tiled<0, 2>), dim3(nb), dim3(NT), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_prolong_corr(const Geom& gf, const Geom& gc, float* ef, const float* ec, const float* eold_c,
                                hipStream_t s) {
+    const int tx = (gf.n0 + TX - 1) / TX, ty = (gf.n1 + 7) / 8;
+    const int nb = tx * ty * ((gf.n2 + 15) / 16);
     if (gf.dir)
-        hipLaunchKernelGGL(k_prolong_corr<1>, dim3(grid_for(gf.ncell)), dim3(NT), 0, s, gf, gc, ef, ec, eold_c);
+        hipLaunchKernelGGL(k_prolong_corr_tiled<1>, dim3(nb), dim3(NT), 0, s, gf, gc, ef, ec, eold_c, tx, ty);
     else
-        hipLaunchKernelGGL(k_prolong_corr<0>, dim3(grid_for(gf.ncell)), dim3(NT), 0, s, gf, gc, ef, ec, eold_c);
+        hipLaunchKernelGGL(k_prolong_corr_tiled<0>, dim3(nb), dim3(NT), 0, s, gf, gc, ef, ec, eold_c, tx, ty);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_update(const Geom& g, const Coef& c, const double* phi, const float* e, double* phi_out,
+                              const double* delta, const double* f, const LevelScalars* sc, float* pt, float* t0,
+                              float* r, double* partials, int* nblocks_out, hipStream_t s) {
+    CastArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = g; a.c = c; a.phi = phi; a.e = e; a.phi_out = phi_out; a.delta = delta; a.f = f; a.sc = sc;
+    a.pt = pt; a.t0 = t0; a.r = r; a.partials = partials;
+    int nb;
+    corr_tiles(g, a.tiles_x, a.tiles_y, nb);
+    *nblocks_out = nb;
+    const bool up = e != nullptr;
+    if (g.dir) {
+        if (up) hipLaunchKernelGGL((k_cast_tiled<1, true>), dim3(nb), dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((k_cast_tiled<1, false>), dim3(nb), dim3(NT), 0, s, a);
+    } else {
+        if (up) hipLaunchKernelGGL((k_cast_tiled<0, true>), dim3(nb), dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((k_cast_tiled<0, false>), dim3(nb), dim3(NT), 0, s, a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_coarse_corr(const Geom& g, const CoefF& c, float* e, const float* pt, const float* t0,
                               const float* r, int sweeps, hipStream_t s) {
     if (g.nstore > 1000 || g.ncell > 2 * NT) return hipErrorInvalidValue;
+    const int nt = g.ncell <= 128 ? 64 : NT;
     if (g.dir)
-        hipLaunchKernelGGL(k_coarse_corr<1>, dim3(1), dim3(NT), 0, s, g, c, e, pt, t0, r, sweeps);
+        hipLaunchKernelGGL(k_coarse_corr<1>, dim3(1), dim3(nt), 0, s, g, c, e, pt, t0, r, sweeps);
     else
-        hipLaunchKernelGGL(k_coarse_corr<0>, dim3(1), dim3(NT), 0, s, g, c, e, pt, t0, r, sweeps);
+        hipLaunchKernelGGL(k_coarse_corr<0>, dim3(1), dim3(nt), 0, s, g, c, e, pt, t0, r, sweeps);
     return hipGetLastError();
 }
 
@@ -678,6 +1365,85 @@ hipError_t launch_fill_f(float* p, int64_t n, float v, hipStream_t s) {
 
 hipError_t launch_cast_all(const double* src, float* dst, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_cast_all, dim3(grid_for(n)), dim3(NT), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+// ---- batched launchers (Dirichlet batches) -------------------------------------
+hipError_t launch_smooth_corr_batch(const CoefF& c, const float* ein, float* eout, const float* pt, const float* t0,
+                                    const float* r, SmoothCfg cfg, const Geom* geoms, const int4* items, int nitems,
+                                    int max_blocks, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    CorrArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.c = c; a.ein = ein; a.eout = eout; a.pt = pt; a.t0 = t0; a.r = r; a.sc = nullptr;
+    a.zc = cfg.zc > 0 ? cfg.zc : 16;
+    const int nb = std::min(nitems, max_blocks);
+    if (cfg.ty == 4)
+        hipLaunchKernelGGL(k_smooth_corr_batch<4>, dim3(nb), dim3(NT), 0, s, a, geoms, items, nitems);
+    else if (cfg.ty == 16)
+        hipLaunchKernelGGL(k_smooth_corr_batch<16>, dim3(nb), dim3(NT), 0, s, a, geoms, items, nitems);
+    else
+        hipLaunchKernelGGL(k_smooth_corr_batch<8>, dim3(nb), dim3(NT), 0, s, a, geoms, items, nitems);
+    return hipGetLastError();
+}
+
+hipError_t launch_rr_corr_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, const CoefF& c,
+                                const float* e, const float* pt, const float* t0, const float* r, float* ec,
+                                float* eold_c, float* rd_c, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rr_corr_batch, dim3(nitems), dim3(NT), 0, s, gfs, gcs, items, c, e, pt, t0, r, ec, eold_c,
+                       rd_c);
+    return hipGetLastError();
+}
+
+hipError_t launch_fas_corr_batch(const Geom* gs, const int2* items, int nitems, const CoefF& c, const float* e,
+                                 const float* pt, const float* t0, const float* rd, float* r, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fas_corr_batch, dim3(nitems), dim3(NT), 0, s, gs, items, c, e, pt, t0, rd, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_corr_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, float* ef,
+                                     const float* ec, const float* eold_c, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prolong_corr_batch, dim3(nitems), dim3(NT), 0, s, gfs, gcs, items, ef, ec, eold_c);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_corr_batch(const Geom* gs, int ngrids, const CoefF& c, float* e0, float* e1,
+                                    const float* pt, const float* t0, const float* r, int sweeps, const float* old,
+                                    hipStream_t s) {
+    if (ngrids <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coarse_corr_batch, dim3(ngrids), dim3(NT), 0, s, gs, c, e0, e1, pt, t0, r, sweeps, old);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_batch(const Geom* gs, const int2* items, int nitems, const Coef& c, const double* phi,
+                             const double* delta, const double* f, float* pt, float* t0, float* r,
+                             double* partials, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cast_batch, dim3(nitems), dim3(NT), 0, s, gs, items, c, phi, delta, f, pt, t0, r, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_base_restrict_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems,
+                                      const float* pf, float* pc, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_base_restrict_batch, dim3(nitems), dim3(NT), 0, s, gfs, gcs, items, pf, pc);
+    return hipGetLastError();
+}
+
+hipError_t launch_base_t0_batch(const Geom* gs, const int2* items, int nitems, const Coef& c, const float* pt,
+                                const double* delta, float* t0, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_base_t0_batch, dim3(nitems), dim3(NT), 0, s, gs, items, c, pt, delta, t0);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_batch(const Geom* gs, const int2* items, int nitems, double* phi, const float* e,
+                               hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update_batch, dim3(nitems), dim3(NT), 0, s, gs, items, phi, e);
     return hipGetLastError();
 }
 

@@ -103,13 +103,16 @@ static const double* level0_f(const Plan* P, const GridState& G) {
     return P->has_source ? G.lev[0].f : nullptr;
 }
 
-// FP64 residual of the current phi + FP32 inputs of the inner problem + norm
-static hipError_t cast_pass(Plan* P, GridState& G) {
+// FP64 residual of phi (after adding the correction e when `update`), FP32
+// inputs of the inner problem and the norm.  With `update` phi ping-pongs.
+static hipError_t cast_pass(Plan* P, GridState& G, bool update) {
     LevelBuf& L = G.lev[0];
     int nb = 0;
-    hipError_t e = launch_cast(L.g, P->coef, L.phi[0], L.delta, level0_f(P, G), L.sc, L.pt, L.t0, L.r,
-                               P->partials, &nb, P->stream);
+    hipError_t e = launch_cast_update(L.g, P->coef, L.phi[L.cur], update ? L.e[L.ecur] : nullptr,
+                                      L.phi[L.cur ^ 1], L.delta, level0_f(P, G), L.sc, L.pt, L.t0, L.r,
+                                      P->partials, &nb, P->stream);
     if (e != hipSuccess) return e;
+    if (update) L.cur ^= 1;
     return launch_finalize(P->partials, nb, L.g.ncell, L.g.dir ? 0 : 1, 2, L.sc, G.norm_dev, P->stream, L.scf);
 }
 
@@ -125,7 +128,7 @@ static hipError_t norms_to_host(Plan* P) {
 hipError_t mixed_initial_pass(Plan* P) {
     hipError_t e;
     for (auto& G : P->grids)
-        if ((e = cast_pass(P, G)) != hipSuccess) return e;
+        if ((e = cast_pass(P, G, false)) != hipSuccess) return e;
     return norms_to_host(P);
 }
 
@@ -143,8 +146,7 @@ hipError_t enqueue_outer(Plan* P) {
         L0.ecur = 0;
         if ((e = launch_fill_f(L0.e[0], L0.g.nstore, 0.0f, P->stream)) != hipSuccess) return e;
         if ((e = inner_vcycle(P, G, 0)) != hipSuccess) return e;
-        if ((e = launch_update(L0.g, L0.phi[0], L0.e[L0.ecur], P->stream)) != hipSuccess) return e;
-        if ((e = cast_pass(P, G)) != hipSuccess) return e;
+        if ((e = cast_pass(P, G, true)) != hipSuccess) return e;
     }
     return norms_to_host(P);
 }

@@ -102,6 +102,8 @@ hipError_t launch_check_finite(const double* p, int64_t n, double* partials, int
 hipError_t launch_ghost_fill(const double* parent, int np0, int np1, int np2, double H,
                              int n0, int n1, int n2, double h, int o0, int o1, int o2,
                              double* ghost, hipStream_t s);
+hipError_t launch_interior_fill(const double* parent, int np0, int np1, int np2, double H, int n0, int n1, int n2,
+                                double h, int o0, int o1, int o2, double* phi, hipStream_t s);
 
 // ---- mixed path (kernels_mixed.hip) ---------------------------------------
 hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, float* eout,
@@ -119,6 +121,11 @@ hipError_t launch_coarse_corr(const Geom& g, const CoefF& c, float* e, const flo
 hipError_t launch_cast(const Geom& g, const Coef& c, const double* phi, const double* delta, const double* f,
                        const LevelScalars* sc, float* pt, float* t0, float* r, double* partials,
                        int* nblocks_out, hipStream_t s);
+// phi_out = phi + e (e may be null: then phi_out is not written), FP64 residual of it,
+// norm partials and the FP32 inner inputs (pt, t0, r)
+hipError_t launch_cast_update(const Geom& g, const Coef& c, const double* phi, const float* e, double* phi_out,
+                              const double* delta, const double* f, const LevelScalars* sc, float* pt, float* t0,
+                              float* r, double* partials, int* nblocks_out, hipStream_t s);
 hipError_t launch_base_restrict(const Geom& gf, const Geom& gc, const float* pf, float* pc, hipStream_t s);
 hipError_t launch_base_t0(const Geom& g, const Coef& c, const float* pt, const double* delta, float* t0,
                           hipStream_t s);
@@ -126,7 +133,67 @@ hipError_t launch_update(const Geom& g, double* phi, const float* e, hipStream_t
 hipError_t launch_fill_f(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_cast_all(const double* src, float* dst, int64_t n, hipStream_t s);
 
+// ---- batched Dirichlet launchers (one launch per level for every grid) ------
+struct SmoothArgs;
+hipError_t launch_smooth_batch_args(const Coef& c, const double* pin, double* pout, const double* delta,
+                                    const double* f, SmoothCfg cfg, const Geom* geoms, const int4* items,
+                                    int nitems, int max_blocks, hipStream_t s);
+hipError_t launch_rr_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, const Coef& c,
+                           const double* phi, const double* delta, const double* f, double* phic,
+                           double* phiold_c, double* rd_c, hipStream_t s);
+hipError_t launch_fas_batch(const Geom* gs, const int2* items, int nitems, const Coef& c, const double* phi,
+                            const double* delta, const double* rd, double* f, hipStream_t s);
+hipError_t launch_prolong_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, double* phif,
+                                const double* phic, const double* oldc, hipStream_t s);
+hipError_t launch_norm_batch(const Geom* gs, const int2* items, int nitems, const Coef& c, const double* phi,
+                             const double* delta, const double* f, double* partials, const int* first, int ngrids,
+                             NormOut* out, hipStream_t s);
+hipError_t launch_finalize_batch(const double* partials, const int* first, const Geom* gs, int ngrids,
+                                 NormOut* out, hipStream_t s);
+hipError_t launch_coarse_batch(const Geom* gs, int ngrids, const Coef& c, double* phi0, double* phi1,
+                               const double* delta, const double* f, int sweeps, const double* old,
+                               hipStream_t s);
+hipError_t launch_ghost_refresh_batch(const Geom* gs, const int2* items, int nitems, double* u, const double* ref,
+                                      hipStream_t s);
+hipError_t launch_ghost_refresh_batch_f(const Geom* gs, const int2* items, int nitems, float* u, const float* ref,
+                                        hipStream_t s);
+hipError_t launch_copy_in_batch(const Geom* gs, const int64_t* uoff, const int2* items, int nitems,
+                                const double* src, double* dst0, double* dst1, hipStream_t s);
+hipError_t launch_copy_out_batch(const Geom* gs, const int64_t* uoff, const int2* items, int nitems,
+                                 const double* src, double* dst, hipStream_t s);
+hipError_t launch_ghost_in_batch(const Geom* gs, const int64_t* goff, const int2* items, int nitems,
+                                 const double* ghost, double* dst0, double* dst1, hipStream_t s);
+hipError_t launch_restrict_plain_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems,
+                                       const double* uf, double* uc, hipStream_t s);
+hipError_t launch_restrict_ghosts_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems,
+                                        const double* uf, double* uc0, double* uc1, double* uc2, hipStream_t s);
+hipError_t launch_check_finite_batch(const Geom* gs, const int64_t* uoff, const int2* items, int nitems,
+                                     const double* src, double* partials, hipStream_t s);
+hipError_t launch_smooth_corr_batch(const CoefF& c, const float* ein, float* eout, const float* pt, const float* t0,
+                                    const float* r, SmoothCfg cfg, const Geom* geoms, const int4* items, int nitems,
+                                    int max_blocks, hipStream_t s);
+hipError_t launch_rr_corr_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, const CoefF& c,
+                                const float* e, const float* pt, const float* t0, const float* r, float* ec,
+                                float* eold_c, float* rd_c, hipStream_t s);
+hipError_t launch_fas_corr_batch(const Geom* gs, const int2* items, int nitems, const CoefF& c, const float* e,
+                                 const float* pt, const float* t0, const float* rd, float* r, hipStream_t s);
+hipError_t launch_prolong_corr_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, float* ef,
+                                     const float* ec, const float* eold_c, hipStream_t s);
+hipError_t launch_coarse_corr_batch(const Geom* gs, int ngrids, const CoefF& c, float* e0, float* e1,
+                                    const float* pt, const float* t0, const float* r, int sweeps, const float* old,
+                                    hipStream_t s);
+hipError_t launch_cast_batch(const Geom* gs, const int2* items, int nitems, const Coef& c, const double* phi,
+                             const double* delta, const double* f, float* pt, float* t0, float* r,
+                             double* partials, hipStream_t s);
+hipError_t launch_base_restrict_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems,
+                                      const float* pf, float* pc, hipStream_t s);
+hipError_t launch_base_t0_batch(const Geom* gs, const int2* items, int nitems, const Coef& c, const float* pt,
+                                const double* delta, float* t0, hipStream_t s);
+hipError_t launch_update_batch(const Geom* gs, const int2* items, int nitems, double* phi, const float* e,
+                               hipStream_t s);
+
 int64_t ghost_count(int n0, int n1, int n2);
-int partial_blocks_for(int64_t ncell);   // upper bound of blocks used by reduction kernels
+int partial_blocks_for(int64_t ncell);   // upper bound of blocks used by grid-stride reduction kernels
+int resid_blocks(const Geom& g);         // blocks of the tiled residual kernel on level g
 
 }  // namespace vmg

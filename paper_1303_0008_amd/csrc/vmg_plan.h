@@ -36,6 +36,36 @@ struct GridState {
     NormOut* norm_dev = nullptr;
 };
 
+// One level of a batch of Dirichlet grids: pooled buffers shared by every grid
+// that has this level, plus the device work lists of the batched kernels.
+struct BatchLevel {
+    std::vector<int> members;        // grid ids with a level here, in id order
+    std::vector<int> coarsest;       // per member: 1 if this is its coarsest level
+    int64_t pool = 0;                // elements per pooled buffer
+    double* phi[2] = {nullptr, nullptr};
+    double *phiold = nullptr, *f = nullptr, *delta = nullptr, *rd = nullptr;
+    float* e[2] = {nullptr, nullptr};
+    float *eold = nullptr, *r = nullptr, *pt = nullptr, *t0 = nullptr, *rdf = nullptr;
+    LevelScalars* sc = nullptr;      // one per member
+    LevelScalars* scf = nullptr;
+    Geom* d_geom = nullptr;          // member geometries at this level
+    Geom* d_geom_fine = nullptr;     // same grids one level finer (levels >= 1)
+    Geom* d_geomC = nullptr;         // members whose coarsest level is this one
+    int nC = 0;
+    int4* d_sitems = nullptr;        // smoother work list (members that continue below)
+    int nsitems = 0;
+    int2* d_cells = nullptr;         // 256-cell blocks of every member at this level
+    int ncells = 0;
+    int2* d_fcells = nullptr;        // 256-cell blocks of the finer level of every member (levels >= 1)
+    int nfcells = 0;
+    int2* d_store = nullptr;         // 256-element blocks of each member's padded storage (levels >= 1)
+    int nstore_items = 0;
+    int2* d_ghosts = nullptr;        // 256-value blocks of each member's ghost shell (levels >= 1)
+    int nghost_items = 0;
+    int64_t cells_A = 0, cells_C = 0;
+    int cur = 0, ecur = 0;
+};
+
 struct Plan {
     std::vector<GridState> grids;
     vmg_params params;
@@ -55,6 +85,18 @@ struct Plan {
     int64_t cell_updates = 0, finest_sweeps = 0;
     int64_t cycle_updates = 0, cycle_finest = 0;
     std::vector<void*> allocs;
+    // batched Dirichlet plans
+    bool tuned_from_cache = false;
+    struct TuneEntry { SmoothCfg cfg; double us; };
+    std::vector<TuneEntry> tune_log;       // autotuner timings (finest-level sweep, us)
+    bool batched = false;
+    std::vector<BatchLevel> blev;
+    int64_t* d_uoff = nullptr;       // caller offsets of each grid's cells
+    int64_t* d_goff = nullptr;       // caller offsets of each grid's ghosts
+    int2* d_gitems = nullptr;        // 256-value blocks of every grid's ghosts
+    int bngitems = 0;
+    int* d_first = nullptr;          // first norm block of each grid (+ end)
+    NormOut* d_norms = nullptr;
 };
 
 vmg_status fail(vmg_status st, const std::string& msg);
@@ -64,6 +106,18 @@ hipError_t enqueue_outer(Plan* P);          // one mixed-precision outer iterati
 hipError_t mixed_initial_pass(Plan* P);     // cast pass of the initial guess (+ norms to host)
 hipError_t mixed_prepare(Plan* P);          // per-solve set-up of the FP32 ghost shells
 hipError_t smooth_corr_level(Plan* P, GridState& G, int l);
+vmg_status build_batch(Plan* P);
+vmg_status autotune(Plan* P);
+hipError_t smooth_level_public(Plan* P, GridState& G, int l);
+int64_t batch_partials_needed(const Plan* P);
+hipError_t batch_build_smooth_items(Plan* P);
+hipError_t batch_enqueue_iteration(Plan* P);
+hipError_t batch_check_delta(Plan* P, const double* delta);
+hipError_t batch_setup(Plan* P, const double* delta, const double* ghost, const double* source, const double* phi);
+hipError_t batch_outputs(Plan* P, double* phi);
+hipError_t batch_smooth_finest(Plan* P);
+int batch_parity(const Plan* P);
+void batch_flip_parity(Plan* P);
 extern thread_local std::string g_err;
 
 }  // namespace vmg

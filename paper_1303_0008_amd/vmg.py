@@ -4,7 +4,7 @@ Argument marshalling only: every step of the solve runs in the library's HIP
 kernels.  PyTorch supplies device memory (``Tensor.data_ptr()``) and the
 current HIP stream.  The functions mirror the C ABI in ``include/vmg.h``:
 ``plan_create``, ``solve``, ``plan_destroy``, ``last_error``,
-``solve_periodic``, ``residual``, ``fill_ghosts``, ``ghost_count``,
+``solve_periodic``, ``residual``, ``fill_ghosts``, ``fill_interior``, ``ghost_count``,
 ``smooth``, ``plan_stats``; ``Plan`` wraps a plan handle.
 
 There is no fallback: if the library is missing or no GPU is present the
@@ -55,7 +55,7 @@ class Result(ctypes.Structure):
 # Every symbol declared in include/vmg.h (checked by the CPU test-suite).
 EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
            "vmg_solve_periodic", "vmg_residual", "vmg_fill_ghosts", "vmg_ghost_count",
-           "vmg_smooth", "vmg_plan_stats"]
+           "vmg_smooth", "vmg_plan_stats", "vmg_plan_config", "vmg_fill_interior"]
 
 _lib = None
 
@@ -80,10 +80,14 @@ def load():
     L.vmg_residual.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, P(Result)]
     L.vmg_fill_ghosts.argtypes = [vp, P(ctypes.c_int32), ctypes.c_double, P(Grid), P(ctypes.c_int32),
                                   ctypes.c_int32, vp, vp]
+    L.vmg_fill_interior.argtypes = [vp, P(ctypes.c_int32), ctypes.c_double, P(Grid), P(ctypes.c_int32),
+                                    ctypes.c_int32, vp, vp]
     L.vmg_ghost_count.argtypes = [P(ctypes.c_int32)]
     L.vmg_ghost_count.restype = ctypes.c_int64
     L.vmg_smooth.argtypes = [vp, ctypes.c_int32]
     L.vmg_plan_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
+    i32p = P(ctypes.c_int32)
+    L.vmg_plan_config.argtypes = [vp, i32p, i32p, i32p, i32p, i32p]
     for name in EXPORTS:
         if name != "vmg_last_error" and name != "vmg_ghost_count":
             getattr(L, name).restype = ctypes.c_int
@@ -195,6 +199,17 @@ def fill_ghosts(parent, parent_h, grids, origins, ghost, stream=None):
                                   _stream(stream)))
 
 
+def fill_interior(parent, parent_h, grids, origins, phi, stream=None):
+    """vmg_fill_interior: trilinear initial guess on refinements from a periodic parent."""
+    n2, n1, n0 = parent.shape
+    npar = (ctypes.c_int32 * 3)(n0, n1, n2)
+    arr = (Grid * len(grids))(*grids)
+    flat = [int(v) for o in origins for v in o]
+    org = (ctypes.c_int32 * len(flat))(*flat)
+    _check(load().vmg_fill_interior(_ptr(parent), npar, parent_h, arr, org, len(grids), _ptr(phi),
+                                    _stream(stream)))
+
+
 def smooth(handle, sweeps):
     """vmg_smooth: finest-level smoother sweeps on the plan's state (measurement hook)."""
     _check(load().vmg_smooth(ctypes.c_void_p(handle), sweeps))
@@ -205,6 +220,13 @@ def plan_stats(handle):
     _check(load().vmg_plan_stats(ctypes.c_void_p(handle), ctypes.byref(a), ctypes.byref(b),
                                  ctypes.byref(c)))
     return dict(cell_updates=a.value, finest_sweeps=b.value, finest_cells=c.value)
+
+
+def plan_config(handle):
+    """vmg_plan_config: the schedule the plan uses (tile height, z chunk, nu1, nu2, coarse sweeps)."""
+    v = [ctypes.c_int32() for _ in range(5)]
+    _check(load().vmg_plan_config(ctypes.c_void_p(handle), *[ctypes.byref(x) for x in v]))
+    return dict(zip(("tile_y", "z_chunk", "nu1", "nu2", "coarse_sweeps"), (x.value for x in v)))
 
 
 class Plan:
@@ -225,6 +247,9 @@ class Plan:
 
     def stats(self):
         return plan_stats(self.handle)
+
+    def config(self):
+        return plan_config(self.handle)
 
     def close(self):
         if self.handle:

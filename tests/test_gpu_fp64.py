@@ -285,6 +285,29 @@ def test_fill_ghosts_parity(torch_cuda, V, oracle_mod):
     assert np.abs(got - ref).max() <= 1e-15 * max(1.0, np.abs(ref).max()) + 1e-18
 
 
+def test_fill_interior_parity(torch_cuda, V, oracle_mod):
+    torch = torch_cuda
+    say("fill interior")
+    parent = I.lognormal(32, 502, sigma=1.0) * 1e-3
+    h = 1.0 / 128
+    specs = [((8, 8, 8), (100, 3, 60)), ((12, 6, 10), (5, 120, 127)), ((16, 16, 16), (0, 0, 0)),
+             ((3, 5, 1), (127, 127, 127))]
+    grids, origins, refs = [], [], []
+    off = 0
+    for n, o in specs:
+        grids.append(V.make_grid(n, h, V.DIRICHLET, off, 0))
+        origins.append(o)
+        r = oracle_mod.fill_interior(parent, n, h, o).ravel()
+        refs.append(r)
+        off += r.size
+    phi = torch.full((off,), -7.0, dtype=torch.float64, device="cuda")
+    V.fill_interior(dev(torch, parent), 1.0 / 32, grids, origins, phi)
+    torch.cuda.synchronize()
+    got = phi.cpu().numpy()
+    ref = np.concatenate(refs)
+    assert np.abs(got - ref).max() <= 1e-15 * max(1.0, np.abs(ref).max()) + 1e-18
+
+
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("name", ["lognormal128", "zeldovich256"])
 def test_full_size_residual_property(torch_cuda, V, oracle_mod, name):
