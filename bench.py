@@ -41,7 +41,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip",):
+    for f in ("device_common.h", "kernels.hip", "kernels_mixed.hip"):
         p = os.path.join(ROOT, "paper_1303_0008_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
@@ -95,6 +95,84 @@ def time_smoother(torch, plan, stream, launches):
     return e0.elapsed_time(e1) / launches
 
 
+COPY_BYTES = 256 << 20       # calibration copy: 256 MiB read + 256 MiB written
+FINEST = {"fp64": ("k_smooth<8, 0, false>", 24), "mixed": ("k_smooth_corr<8, 0>", 20)}
+
+
+def traffic_probe(torch, V, delta, w, launches=10):
+    """Kernels for the HBM counter runs: finest-level sweeps of both precisions on
+    a solved state, then a plain device copy of COPY_BYTES (calibration)."""
+    stream = torch.cuda.Stream()
+    for prec in (V.FP64, V.MIXED):
+        plan = V.Plan([V.make_grid(w["n"])], V.make_params(w["alpha"], w["kappa"], w["tol"], 100, prec),
+                      stream=stream)
+        phi = torch.zeros_like(delta)
+        with torch.cuda.stream(stream):
+            plan.solve(delta, phi)
+            plan.smooth(launches)
+        torch.cuda.synchronize()
+        plan.close()
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"traffic probe done: {launches} sweeps per precision, 3 copies of {COPY_BYTES >> 20} MiB")
+
+
+def _counter_rows(path):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {path}")
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def traffic_from(fetch_dir, write_dir, n):
+    """Per-launch HBM bytes of the finest sweeps from a FETCH_SIZE run and a
+    WRITE_SIZE run of --traffic-probe, each scaled so that the calibration copy
+    reads / writes exactly COPY_BYTES; writes the JSON files the roofline reads."""
+    import statistics
+    ncell = n ** 3
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _counter_rows(path) if r.get("Counter_Name") == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        tail = rows[-3:]      # the probe ends with the three calibration copies
+        if len(tail) < 3 or not all("copy" in r["Kernel_Name"].lower() for r in tail):
+            raise SystemExit(f"{counter}: calibration copies not found at the end of the run")
+        copies = [float(r["Counter_Value"]) for r in tail]
+        # counter KiB -> bytes, times the factor that makes the copy read/write COPY_BYTES
+        scale = COPY_BYTES / (1024.0 * statistics.median(copies))
+        for name, (kern, _) in FINEST.items():
+            vals = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"].startswith("void vmg::" + kern)
+                    and int(r["Grid_Size"]) >= 2048 * 256]
+            if not vals:
+                raise SystemExit(f"{counter}: no {kern} launches")
+            per.setdefault(name, {})[counter] = {"kib_per_launch_median": statistics.median(vals),
+                                                  "launches": len(vals), "copy_kib": statistics.median(copies),
+                                                  "calibration_factor": scale,
+                                                  "bytes_per_launch": statistics.median(vals) * 1024.0 * scale}
+    for name, (kern, bpc) in FINEST.items():
+        d = per[name]
+        out = {"kernel": kern, "workload": f"{WORKLOAD} ({n}^3)", "kernel_source_hash": kernel_source_hash(),
+               "algorithmic_bytes_per_launch": bpc * ncell,
+               "fetch": d["FETCH_SIZE"], "write": d["WRITE_SIZE"],
+               "bytes_per_launch": d["FETCH_SIZE"]["bytes_per_launch"] + d["WRITE_SIZE"]["bytes_per_launch"]}
+        out["ratio_to_algorithmic"] = out["bytes_per_launch"] / out["algorithmic_bytes_per_launch"]
+        p = os.path.join(ROOT, "profiles", f"smooth_{name}_{WORKLOAD}_traffic.json")
+        with open(p, "w") as fh:
+            json.dump(out, fh, indent=1)
+        log(f"{name}: {out['bytes_per_launch'] / 1e6:.1f} MB per launch "
+            f"({out['ratio_to_algorithmic']:.2f} x algorithmic) -> {p}")
+
+
 def cpu_baseline(delta, w):
     from oracle import oracle as O
     import numpy as np
@@ -115,7 +193,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--smooth-launches", type=int, default=50)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run only the kernels of the HBM counter runs (under rocprofv3 --pmc)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc csv outputs of --traffic-probe into profiles/*_traffic.json")
     args = ap.parse_args()
+    if args.traffic_from:
+        from paper_1303_0008_amd import inputs as I
+        traffic_from(args.traffic_from[0], args.traffic_from[1], I.WORKLOADS[WORKLOAD]["n"])
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the solver is a single-GPU build).", file=sys.stderr)
@@ -133,6 +219,9 @@ def main():
     delta_np = I.workload_delta(WORKLOAD)
     log(f"workload {WORKLOAD}: generated in {time.perf_counter() - t:.1f} s, max delta {delta_np.max():.1f}")
     delta = torch.from_numpy(delta_np).to("cuda")
+    if args.traffic_probe:
+        traffic_probe(torch, V, delta, w)
+        return
     stream = torch.cuda.Stream()        # default priority
     torch.cuda.synchronize()
 

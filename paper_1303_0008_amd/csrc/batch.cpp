@@ -33,16 +33,34 @@ static void cell_items(std::vector<int2>& out, int k, int64_t n) {
     for (int64_t s = 0; s < n; s += 256) out.push_back(make_int2(k, (int)s));
 }
 
-// Work list of the persistent smoother for the grids of `lv` that continue below it.
+// Work list of the persistent smoother for the grids of each level that continue
+// below it.  The finest level uses the plan's (tuned) schedule; coarser levels
+// shorten the z chunk, then the tile height, until the level has at least
+// MIN_TILED_BLOCKS items (or the shortest schedule).
 hipError_t batch_build_smooth_items(Plan* P) {
     for (size_t l = 0; l < P->blev.size(); ++l) {
         BatchLevel& B = P->blev[l];
+        auto count = [&](const SmoothCfg& c) {
+            int64_t n = 0;
+            for (size_t k = 0; k < B.members.size(); ++k) {
+                if (B.coarsest[k]) continue;
+                const Geom& g = P->grids[B.members[k]].lev[l].g;
+                n += (int64_t)((g.n0 + TX - 1) / TX) * ((g.n1 + c.ty - 1) / c.ty) * ((g.n2 + c.zc - 1) / c.zc);
+            }
+            return n;
+        };
+        SmoothCfg cfg = P->cfg;
+        if (l > 0) {
+            while (cfg.zc > 2 && count(cfg) < MIN_TILED_BLOCKS) cfg.zc >>= 1;
+            if (count(cfg) < MIN_TILED_BLOCKS && cfg.ty > 4) cfg.ty = 4;
+        }
+        B.cfg = cfg;
         std::vector<int4> items;
         for (size_t k = 0; k < B.members.size(); ++k) {
             if (B.coarsest[k]) continue;
             const Geom& g = P->grids[B.members[k]].lev[l].g;
-            const int tx = (g.n0 + TX - 1) / TX, ty = (g.n1 + P->cfg.ty - 1) / P->cfg.ty;
-            const int tz = (g.n2 + P->cfg.zc - 1) / P->cfg.zc;
+            const int tx = (g.n0 + TX - 1) / TX, ty = (g.n1 + cfg.ty - 1) / cfg.ty;
+            const int tz = (g.n2 + cfg.zc - 1) / cfg.zc;
             for (int c = 0; c < tz; ++c)
                 for (int y = 0; y < ty; ++y)
                     for (int x = 0; x < tx; ++x) items.push_back(make_int4((int)k, x, y, c));
@@ -190,7 +208,7 @@ static const double* bf(const Plan* P, int l) {
 // ---------------------------------------------------------------------------
 static hipError_t bsmooth(Plan* P, int l) {
     BatchLevel& B = P->blev[l];
-    CKE(launch_smooth_batch_args(P->coef, B.phi[B.cur], B.phi[B.cur ^ 1], B.delta, bf(P, l), P->cfg, B.d_geom,
+    CKE(launch_smooth_batch_args(P->coef, B.phi[B.cur], B.phi[B.cur ^ 1], B.delta, bf(P, l), B.cfg, B.d_geom,
                                  B.d_sitems, B.nsitems, max_resident_blocks(), P->stream));
     B.cur ^= 1;
     P->cell_updates += B.cells_A;
@@ -237,7 +255,7 @@ static hipError_t bnorms(Plan* P) {
 static hipError_t bsmooth_corr(Plan* P, int l) {
     BatchLevel& B = P->blev[l];
     const CoefF cf = make_coef_f(P->coef, 1.0);   // per-grid h is applied inside the kernels
-    CKE(launch_smooth_corr_batch(cf, B.e[B.ecur], B.e[B.ecur ^ 1], B.pt, B.t0, B.r, P->cfg, B.d_geom, B.d_sitems,
+    CKE(launch_smooth_corr_batch(cf, B.e[B.ecur], B.e[B.ecur ^ 1], B.pt, B.t0, B.r, B.cfg, B.d_geom, B.d_sitems,
                                  B.nsitems, max_resident_blocks(), P->stream));
     B.ecur ^= 1;
     P->cell_updates += B.cells_A;

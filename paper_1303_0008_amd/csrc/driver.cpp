@@ -180,8 +180,10 @@ static const double* level_f(const Plan* P, const GridState& G, int l) {
 
 static hipError_t smooth_level(Plan* P, GridState& G, int l) {
     LevelBuf& L = G.lev[l];
+    // the finest level runs the plan's (tuned) schedule, coarser ones a shortened one
+    const SmoothCfg cfg = l == 0 ? P->cfg : level_cfg(L.g.n0, L.g.n1, L.g.n2, P->cfg);
     hipError_t e = launch_smooth(L.g, P->coef, L.phi[L.cur], L.phi[L.cur ^ 1], L.delta,
-                                 level_f(P, G, l), L.sc, P->cfg, P->stream);
+                                 level_f(P, G, l), L.sc, cfg, P->stream);
     L.cur ^= 1;
     P->cell_updates += L.g.ncell;
     if (l == 0) P->finest_sweeps += 1;

@@ -11,6 +11,7 @@
 // the exact per-cell root: phi_c <- (S - h^2 (Q + f - cbar)) / 6.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "device_common.h"
 
@@ -60,17 +61,17 @@ __device__ __forceinline__ void nb_split(const double* __restrict__ Pm, const do
     v.ymzp = Pp[o - W];     v.ypzp = Pp[o + W];
 }
 
-template <int TY, int DIR, bool HAS_F>
+template <int TY, int DIR, bool HAS_F, int NTH>
 __device__ __forceinline__ void smooth_brick(const SmoothArgs& a, const int x0, const int y0, const int z0,
                                              const int z1) {
     constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
     constexpr int HW2 = W2 / 2, HW1 = W1 / 2;     // half-row lengths (34, 33)
     constexpr int NP2 = W2 * H2;
-    constexpr int NL2 = (NP2 + NT - 1) / NT;
+    constexpr int NL2 = (NP2 + NTH - 1) / NTH;
     constexpr int RH = W1 / 2;        // red/black pairs per ring-1 row
     constexpr int BH = TX / 2;        // black cells per interior row
-    constexpr int NR = (RH * H1 + NT - 1) / NT;   // red cells per thread
-    constexpr int NB = (BH * TY + NT - 1) / NT;   // black cells per thread
+    constexpr int NR = (RH * H1 + NTH - 1) / NTH;   // red cells per thread
+    constexpr int NB = (BH * TY + NTH - 1) / NTH;   // black cells per thread
     constexpr int S2 = H2 * W2, S1 = H1 * W1;     // words per plane
     // Rows are stored split by x parity: word (Y, X) lives at Y*W + (X&1)*W/2 + (X>>1),
     // so lanes working on every other cell of a row touch consecutive words.
@@ -88,7 +89,7 @@ __device__ __forceinline__ void smooth_brick(const SmoothArgs& a, const int x0, 
     bool ok2[NL2];
 #pragma unroll
     for (int s = 0; s < NL2; ++s) {
-        const int e = tid + s * NT;
+        const int e = tid + s * NTH;
         ok2[s] = false;
         off2[s] = 0;
         lds2[s] = 0;
@@ -116,7 +117,7 @@ __device__ __forceinline__ void smooth_brick(const SmoothArgs& a, const int x0, 
     int rg[NR][2];            // global in-plane index of the red cell (-1: not a cell)
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-        const int e = tid + q * NT;
+        const int e = tid + q * NTH;
         rv[q] = e < RH * H1;
         const int r = rv[q] ? e / RH : 0, m = rv[q] ? e - r * RH : 0;
         rpar0[q] = (y0 + r) & 1;
@@ -141,16 +142,20 @@ __device__ __forceinline__ void smooth_brick(const SmoothArgs& a, const int x0, 
         }
     }
     // black cells: interior row r, pair m; black at column 2m + ((y0 + r + p2 + 1) & 1)
+    // With more threads than black cells, the black cells go to the highest
+    // waves so that red and black work land on different waves.
+    constexpr int BOFF = NTH > BH * TY ? ((NTH - BH * TY) / 64) * 64 : 0;
+    const int tb = tid - BOFF;
     bool bv[NB];
     int bpar0[NB];
     int bc[NB][2], bo[NB][2], brd[NB][2];
     int64_t brow[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-        const int e = tid + q * NT;
-        const int r = e / BH, m = e - (e / BH) * BH;
+        const int e = tb + q * NTH;
+        const int r = e >= 0 ? e / BH : 0, m = e >= 0 ? e - r * BH : 0;
         const int gy = y0 + r;
-        bv[q] = e < BH * TY && gy < g.n1;
+        bv[q] = e >= 0 && e < BH * TY && gy < g.n1;
         bpar0[q] = (y0 + r + 1) & 1;
         brow[q] = g.off0 + (int64_t)gy * g.sy + x0 + 2 * m;
 #pragma unroll
@@ -177,11 +182,10 @@ __device__ __forceinline__ void smooth_brick(const SmoothArgs& a, const int x0, 
     auto store_phi = [&](int sl, const double (&r)[NL2]) {
 #pragma unroll
         for (int s = 0; s < NL2; ++s)
-            if (tid + s * NT < NP2) P0[sl * S2 + lds2[s]] = r[s];
+            if (tid + s * NTH < NP2) P0[sl * S2 + lds2[s]] = r[s];
     };
     auto slot = [](int z) { return (z + 3) % 3; };   // z >= -2
 
-    double rd_dl[NR], rd_f[NR], bk_dl[NB], bk_f[NB];
     auto fetch_red = [&](int p, double (&dl)[NR], double (&ff)[NR]) {
         bool zok;
         int64_t zo = plane_off(p, zok);
@@ -200,32 +204,40 @@ __device__ __forceinline__ void smooth_brick(const SmoothArgs& a, const int x0, 
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int par = (bpar0[q] + p2) & 1;
-            const bool ok = bv[q] && 2 * (tid + q * NT - ((tid + q * NT) / BH) * BH) + par < bxmax;
+            const bool ok = bv[q] && 2 * (tb + q * NTH - ((tb + q * NTH) / BH) * BH) + par < bxmax;
             const int64_t gi = zo + brow[q] + par;
             dl[q] = ok ? a.delta[gi] : 0.0;
             ff[q] = (HAS_F && ok) ? a.f[gi] : 0.0;
         }
     };
 
-    // prologue: phi^0 planes z0-2 .. z0; sources of the first red plane
+    // Software pipeline over z.  Step t computes red on plane t-1 (phi^0 planes
+    // t-2..t in LDS) and black on plane t-2 (phi^1 planes t-3..t-1 in LDS).
+    // Loads run two steps ahead of their use: the phi^0 plane t+2 is issued at
+    // the start of step t and committed to LDS at the end of step t+1; the
+    // delta/f values of a red (black) plane are issued right after the red
+    // (black) phase that consumed their register buffer, two steps before use.
+    // Buffers alternate with the step's parity b, so the loop body is unrolled
+    // twice and every buffer index is a compile-time constant.
+    double pq[2][NL2];                       // phi^0 planes in flight
+    double rq_dl[2][NR], rq_f[2][NR];        // red sources: plane t-1 in [b] at step t
+    double bq_dl[2][NB], bq_f[2][NB];        // black sources: plane t-2 in [b] at step t
     {
         double r2[NL2];
         for (int t = z0 - 2; t <= z0; ++t) {
             load_phi(t, r2);
             store_phi(slot(t), r2);
         }
-        fetch_red(z0 - 1, rd_dl, rd_f);
+        if (z0 + 1 <= z1 + 1) load_phi(z0 + 1, pq[1]);
+        fetch_red(z0 - 1, rq_dl[0], rq_f[0]);
+        if (z0 <= z1) fetch_red(z0, rq_dl[1], rq_f[1]);
     }
     __syncthreads();
 
-    for (int t = z0; t <= z1 + 1; ++t) {
+    auto step = [&](const int t, auto parity_tag) {
+        constexpr int b = decltype(parity_tag)::value;
         const int p = t - 1, p2 = t - 2;
-        // ---- prefetch: phi^0 plane t+1, sources of the next red (t) and black (t-1) planes
-        double nphi[NL2], nrd[NR], nrf[NR], nbd[NB], nbf[NB];
-        const bool pf_phi = t + 1 <= z1 + 1, pf_red = t <= z1, pf_blk = t - 1 >= z0 && t - 1 < z1;
-        if (pf_phi) load_phi(t + 1, nphi);
-        if (pf_red) fetch_red(t, nrd, nrf);
-        if (pf_blk) fetch_black(t - 1, nbd, nbf);
+        if (t + 2 <= z1 + 1) load_phi(t + 2, pq[b]);
         // ---- red phase on plane p, ring 1: P0 -> P1 ---------------------------
         {
             const double* Pm = P0 + slot(p - 1) * S2;
@@ -244,13 +256,14 @@ __device__ __forceinline__ void smooth_brick(const SmoothArgs& a, const int x0, 
                     nb_split<W2>(Pm, Pc, Pp, c, o, v);
                     double S;
                     bool gd;
-                    const double Q = nl_root(v, rd_dl[q], a.c, inv_h4, S, gd);
-                    val = (S - h2 * (Q + (HAS_F ? rd_f[q] : 0.0) - cb)) * (1.0 / 6.0);
+                    const double Q = nl_root(v, rq_dl[b][q], a.c, inv_h4, S, gd);
+                    val = (S - h2 * (Q + (HAS_F ? rq_f[b][q] : 0.0) - cb)) * (1.0 / 6.0);
                 }
                 Q1[rw[q][par]] = val;
                 Q1[rb[q][par]] = Pc[rsrc[q][par]];
             }
         }
+        if (t + 1 <= z1) fetch_red(t + 1, rq_dl[b], rq_f[b]);
         __syncthreads();
         // ---- black phase on plane p2, tile interior: P1 -> phi^2 ---------------
         if (p2 >= z0) {
@@ -262,30 +275,39 @@ __device__ __forceinline__ void smooth_brick(const SmoothArgs& a, const int x0, 
             for (int q = 0; q < NB; ++q) {
                 if (!bv[q]) continue;
                 const int par = (bpar0[q] + p2) & 1;
-                const int mcol = 2 * (tid + q * NT - ((tid + q * NT) / BH) * BH);
+                const int mcol = 2 * (tb + q * NTH - ((tb + q * NTH) / BH) * BH);
                 if (mcol + par < bxmax) {
                     Nb v;
                     nb_split<W1>(Rm, Rc, Rp, bc[q][par], bo[q][par], v);
                     double S;
                     bool gd;
-                    const double Q = nl_root(v, bk_dl[q], a.c, inv_h4, S, gd);
-                    a.pout[zo + brow[q] + par] = (S - h2 * (Q + (HAS_F ? bk_f[q] : 0.0) - cb)) * (1.0 / 6.0);
+                    const double Q = nl_root(v, bq_dl[b][q], a.c, inv_h4, S, gd);
+                    a.pout[zo + brow[q] + par] = (S - h2 * (Q + (HAS_F ? bq_f[b][q] : 0.0) - cb)) * (1.0 / 6.0);
                 }
                 if (mcol + 1 - par < bxmax) a.pout[zo + brow[q] + 1 - par] = Rc[brd[q][par]];
             }
         }
-        // ---- commit prefetched data (the phi slot was last read by this red phase)
-        if (pf_phi) store_phi(slot(t + 1), nphi);
-#pragma unroll
-        for (int q = 0; q < NR; ++q) { rd_dl[q] = nrd[q]; rd_f[q] = nrf[q]; }
-#pragma unroll
-        for (int q = 0; q < NB; ++q) { bk_dl[q] = nbd[q]; bk_f[q] = nbf[q]; }
+        if (t >= z0 && t < z1) fetch_black(t, bq_dl[b], bq_f[b]);
+        // ---- commit phi^0 plane t+1 (its slot held plane t-2, last read by this red phase)
+        if (t + 1 <= z1 + 1) store_phi(slot(t + 1), pq[b ^ 1]);
         __syncthreads();
+    };
+    int t = z0;
+    for (; t + 1 <= z1 + 1; t += 2) {
+        step(t, std::integral_constant<int, 0>());
+        step(t + 1, std::integral_constant<int, 1>());
     }
+    if (t <= z1 + 1) step(t, std::integral_constant<int, 0>());
 }
 
+// Threads per block of the fused sweep and the waves per SIMD it is built for
+// (4 blocks of 4 waves per CU: at most 128 VGPRs, 4 x 35 KB of LDS).  Wider
+// blocks measured slower: each plane step ends in two block-wide barriers.
+constexpr int SNT = 256;
+constexpr int SNT_WAVES_PER_SIMD = 4;
+
 template <int TY, int DIR, bool HAS_F>
-__global__ void __launch_bounds__(NT) k_smooth(SmoothArgs a) {
+__global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth(SmoothArgs a) {
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % a.tiles_x;
     b /= a.tiles_x;
@@ -293,21 +315,21 @@ __global__ void __launch_bounds__(NT) k_smooth(SmoothArgs a) {
     const int ch = b / a.tiles_y;
     const int z0 = ch * a.zc;
     if (z0 >= a.g.n2) return;
-    smooth_brick<TY, DIR, HAS_F>(a, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
+    smooth_brick<TY, DIR, HAS_F, SNT>(a, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
 }
 
 // Persistent sweep over a (grid, tile x, tile y, z chunk) work list: every
 // Dirichlet grid of a batch at one level in one launch.  `proto` carries the
 // pooled level buffers and coefficients; geoms[w.x] locates grid w.x in them.
 template <int TY, bool HAS_F>
-__global__ void __launch_bounds__(NT) k_smooth_batch(SmoothArgs proto, const Geom* __restrict__ geoms,
+__global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth_batch(SmoothArgs proto, const Geom* __restrict__ geoms,
                                                      const int4* __restrict__ items, int nitems) {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int4 w = items[it];
         SmoothArgs a = proto;
         a.g = geoms[w.x];
         const int z0 = w.w * a.zc;
-        smooth_brick<TY, 1, HAS_F>(a, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
+        smooth_brick<TY, 1, HAS_F, SNT>(a, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
     }
 }
 
@@ -502,9 +524,9 @@ __global__ void __launch_bounds__(NT) k_resid_tiled(ResidArgs a) {
 }
 
 static hipError_t resid_launch(ResidArgs& a, int mode, int* nblocks_out, hipStream_t s) {
-    a.zc = 16;
     a.tiles_x = (a.g.n0 + TX - 1) / TX;
     a.tiles_y = (a.g.n1 + RTY - 1) / RTY;
+    a.zc = level_zc((int64_t)a.tiles_x * a.tiles_y, a.g.n2);
     const int nb = a.tiles_x * a.tiles_y * ((a.g.n2 + a.zc - 1) / a.zc);
     *nblocks_out = nb;
 #define RL(D, M) hipLaunchKernelGGL((k_resid_tiled<D, M>), dim3(nb), dim3(NT), 0, s, a)
@@ -518,7 +540,9 @@ static hipError_t resid_launch(ResidArgs& a, int mode, int* nblocks_out, hipStre
 }
 
 int resid_blocks(const Geom& g) {
-    return ((g.n0 + TX - 1) / TX) * ((g.n1 + RTY - 1) / RTY) * ((g.n2 + 15) / 16);
+    const int xy = ((g.n0 + TX - 1) / TX) * ((g.n1 + RTY - 1) / RTY);
+    const int zc = level_zc(xy, g.n2);
+    return xy * ((g.n2 + zc - 1) / zc);
 }
 
 // ---------------------------------------------------------------------------
@@ -705,23 +729,26 @@ __global__ void __launch_bounds__(NT) k_prolong(Geom gf, Geom gc, double* __rest
     }
 }
 
-// Tiled prolongation + correction.  A block owns a 64 x 8 x 16 fine brick; the
-// coarse correction c = phi^H - phiold^H of the 34 x 6 x 10 coarse cells around
-// it is staged in LDS once (zero outside a Dirichlet grid, wrapped on a
-// periodic one), then every fine cell adds its trilinear interpolant.
-constexpr int PZ = 16;   // fine planes per prolongation block
+// Tiled prolongation + correction.  A block owns a 64 x 8 x pz fine brick
+// (pz <= 16, even); the coarse correction c = phi^H - phiold^H of the
+// 34 x 6 x (pz/2+2) coarse cells around it is staged in LDS once (zero outside
+// a Dirichlet grid, wrapped on a periodic one), then every fine cell adds its
+// trilinear interpolant.
+constexpr int PZ = 16;   // largest number of fine planes per prolongation block
 template <int DIR>
 __global__ void __launch_bounds__(NT) k_prolong_tiled(Geom gf, Geom gc, double* __restrict__ phif,
                                                       const double* __restrict__ phic,
-                                                      const double* __restrict__ oldc, int tiles_x, int tiles_y) {
-    constexpr int CX = TX / 2 + 2, CY = 8 / 2 + 2, CZ = PZ / 2 + 2;
-    __shared__ double C[CZ][CY][CX];
+                                                      const double* __restrict__ oldc, int tiles_x, int tiles_y,
+                                                      int pz) {
+    constexpr int CX = TX / 2 + 2, CY = 8 / 2 + 2, CZM = PZ / 2 + 2;
+    __shared__ double C[CZM][CY][CX];
+    const int CZ = pz / 2 + 2;
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % tiles_x;
     b /= tiles_x;
     const int ty = b % tiles_y;
     const int ch = b / tiles_y;
-    const int x0 = tx * TX, y0 = ty * 8, z0 = ch * PZ;
+    const int x0 = tx * TX, y0 = ty * 8, z0 = ch * pz;
     const int cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1, cz0 = z0 / 2 - 1;
     for (int e = threadIdx.x; e < CX * CY * CZ; e += NT) {
         const int lx = e % CX, ly = (e / CX) % CY, lz = e / (CX * CY);
@@ -746,7 +773,7 @@ __global__ void __launch_bounds__(NT) k_prolong_tiled(Geom gf, Geom gc, double* 
     const int i = x0 + lxf;
     if (i >= gf.n0) return;
     const int Ii = (i >> 1) - cx0, si = (i & 1) ? 1 : -1;
-    for (int q = threadIdx.x >> 6; q < 8 * PZ; q += NT / 64) {
+    for (int q = threadIdx.x >> 6; q < 8 * pz; q += NT / 64) {
         const int j = y0 + (q & 7), k = z0 + (q >> 3);
         if (j >= gf.n1 || k >= gf.n2) continue;
         const int Jj = (j >> 1) - cy0, sj = (j & 1) ? 1 : -1;
@@ -1273,9 +1300,9 @@ static hipError_t smooth_launch(const SmoothArgs& a, hipStream_t s) {
     const int chunks = (a.g.n2 + a.zc - 1) / a.zc;
     const int nb = a.tiles_x * a.tiles_y * chunks;
     if (a.f)
-        hipLaunchKernelGGL((k_smooth<TY, DIR, true>), dim3(nb), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_smooth<TY, DIR, true>), dim3(nb), dim3(SNT), 0, s, a);
     else
-        hipLaunchKernelGGL((k_smooth<TY, DIR, false>), dim3(nb), dim3(NT), 0, s, a);
+        hipLaunchKernelGGL((k_smooth<TY, DIR, false>), dim3(nb), dim3(SNT), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1338,11 +1365,12 @@ hipError_t launch_finalize(const double* partials, int nblocks, int64_t ncell, i
 hipError_t launch_prolong(const Geom& gf, const Geom& gc, double* phif, const double* phic,
                           const double* phiold_c, hipStream_t s) {
     const int tx = (gf.n0 + TX - 1) / TX, ty = (gf.n1 + 7) / 8;
-    const int nb = tx * ty * ((gf.n2 + PZ - 1) / PZ);
+    const int pz = level_zc((int64_t)tx * ty, gf.n2, PZ);
+    const int nb = tx * ty * ((gf.n2 + pz - 1) / pz);
     if (gf.dir)
-        hipLaunchKernelGGL(k_prolong_tiled<1>, dim3(nb), dim3(NT), 0, s, gf, gc, phif, phic, phiold_c, tx, ty);
+        hipLaunchKernelGGL(k_prolong_tiled<1>, dim3(nb), dim3(NT), 0, s, gf, gc, phif, phic, phiold_c, tx, ty, pz);
     else
-        hipLaunchKernelGGL(k_prolong_tiled<0>, dim3(nb), dim3(NT), 0, s, gf, gc, phif, phic, phiold_c, tx, ty);
+        hipLaunchKernelGGL(k_prolong_tiled<0>, dim3(nb), dim3(NT), 0, s, gf, gc, phif, phic, phiold_c, tx, ty, pz);
     return hipGetLastError();
 }
 
@@ -1429,14 +1457,14 @@ hipError_t launch_smooth_batch(const SmoothArgs& proto, const Geom* geoms, const
     const int nb = std::min(nitems, max_blocks);
     const bool f = proto.f != nullptr;
     if (ty == 4) {
-        if (f) hipLaunchKernelGGL((k_smooth_batch<4, true>), dim3(nb), dim3(NT), 0, s, proto, geoms, items, nitems);
-        else hipLaunchKernelGGL((k_smooth_batch<4, false>), dim3(nb), dim3(NT), 0, s, proto, geoms, items, nitems);
+        if (f) hipLaunchKernelGGL((k_smooth_batch<4, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
+        else hipLaunchKernelGGL((k_smooth_batch<4, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
     } else if (ty == 16) {
-        if (f) hipLaunchKernelGGL((k_smooth_batch<16, true>), dim3(nb), dim3(NT), 0, s, proto, geoms, items, nitems);
-        else hipLaunchKernelGGL((k_smooth_batch<16, false>), dim3(nb), dim3(NT), 0, s, proto, geoms, items, nitems);
+        if (f) hipLaunchKernelGGL((k_smooth_batch<16, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
+        else hipLaunchKernelGGL((k_smooth_batch<16, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
     } else {
-        if (f) hipLaunchKernelGGL((k_smooth_batch<8, true>), dim3(nb), dim3(NT), 0, s, proto, geoms, items, nitems);
-        else hipLaunchKernelGGL((k_smooth_batch<8, false>), dim3(nb), dim3(NT), 0, s, proto, geoms, items, nitems);
+        if (f) hipLaunchKernelGGL((k_smooth_batch<8, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
+        else hipLaunchKernelGGL((k_smooth_batch<8, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
     }
     return hipGetLastError();
 }

@@ -703,7 +703,7 @@ struct CastArgs {
     const LevelScalars* sc;
     float *pt, *t0, *r;
     double* partials;
-    int tiles_x, tiles_y;
+    int tiles_x, tiles_y, zc;
 };
 
 // Outer FP64 pass: phi_new = phi (+ e), d = L(phi_new) + cbar - f, norm partials,
@@ -719,8 +719,8 @@ __global__ void __launch_bounds__(NT) k_cast_tiled(CastArgs a) {
     b /= a.tiles_x;
     const int ty = b % a.tiles_y;
     const int ch = b / a.tiles_y;
-    const int x0 = tx * TX, y0 = ty * MTY, z0 = ch * MZC;
-    const int z1 = min(z0 + MZC, g.n2);
+    const int x0 = tx * TX, y0 = ty * MTY, z0 = ch * a.zc;
+    const int z1 = min(z0 + a.zc, g.n2);
     double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
     const double cb = DIR ? 0.0 : a.sc->cbar;
     const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
@@ -850,7 +850,7 @@ struct CorrResArgs {
     float *ec, *eold_c, *rd_c; // MODE 1
     float* rout;               // MODE 2
     double* partials;
-    int tiles_x, tiles_y;
+    int tiles_x, tiles_y, zc;
 };
 
 // MODE 1: inner residual d_e = Lap e - dQ(e) - r + cbar_e, reductions, R e -> ec, eold_c, R d_e -> rd_c
@@ -867,8 +867,8 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
     b /= a.tiles_x;
     const int ty = b % a.tiles_y;
     const int ch = b / a.tiles_y;
-    const int x0 = tx * TX, y0 = ty * MTY, z0 = ch * MZC;
-    const int z1 = min(z0 + MZC, g.n2);
+    const int x0 = tx * TX, y0 = ty * MTY, z0 = ch * a.zc;
+    const int z1 = min(z0 + a.zc, g.n2);
     double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
     const float cb = (DIR || MODE == 2) ? 0.0f : (float)a.sc->cbar;
     const float inv_h2 = 1.0f / a.c.h2;
@@ -1014,16 +1014,17 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
 template <int DIR>
 __global__ void __launch_bounds__(NT) k_prolong_corr_tiled(Geom gf, Geom gc, float* __restrict__ ef,
                                                            const float* __restrict__ ecs,
-                                                           const float* __restrict__ oldc, int tiles_x, int tiles_y) {
-    constexpr int PZF = 16;
-    constexpr int CX = TX / 2 + 2, CY = 8 / 2 + 2, CZ = PZF / 2 + 2;
-    __shared__ float C[CZ][CY][CX];
+                                                           const float* __restrict__ oldc, int tiles_x, int tiles_y,
+                                                           int pzf) {
+    constexpr int CX = TX / 2 + 2, CY = 8 / 2 + 2, CZM = 16 / 2 + 2;
+    __shared__ float C[CZM][CY][CX];
+    const int CZ = pzf / 2 + 2;
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % tiles_x;
     b /= tiles_x;
     const int ty = b % tiles_y;
     const int ch = b / tiles_y;
-    const int x0 = tx * TX, y0 = ty * 8, z0 = ch * PZF;
+    const int x0 = tx * TX, y0 = ty * 8, z0 = ch * pzf;
     const int cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1, cz0 = z0 / 2 - 1;
     for (int e = threadIdx.x; e < CX * CY * CZ; e += NT) {
         const int lx = e % CX, ly = (e / CX) % CY, lz = e / (CX * CY);
@@ -1048,7 +1049,7 @@ __global__ void __launch_bounds__(NT) k_prolong_corr_tiled(Geom gf, Geom gc, flo
     const int i = x0 + lxf;
     if (i >= gf.n0) return;
     const int Ii = (i >> 1) - cx0, si = (i & 1) ? 1 : -1;
-    for (int q = threadIdx.x >> 6; q < 8 * PZF; q += NT / 64) {
+    for (int q = threadIdx.x >> 6; q < 8 * pzf; q += NT / 64) {
         const int j = y0 + (q & 7), k = z0 + (q >> 3);
         if (j >= gf.n1 || k >= gf.n2) continue;
         const int Jj = (j >> 1) - cy0, sj = (j & 1) ? 1 : -1;
@@ -1243,10 +1244,11 @@ hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, f
     return corr_launch<8, 0>(a, s);
 }
 
-static void corr_tiles(const Geom& g, int& tx, int& ty, int& nb) {
+static void corr_tiles(const Geom& g, int& tx, int& ty, int& zc, int& nb) {
     tx = (g.n0 + TX - 1) / TX;
     ty = (g.n1 + MTY - 1) / MTY;
-    nb = tx * ty * ((g.n2 + MZC - 1) / MZC);
+    zc = level_zc((int64_t)tx * ty, g.n2, MZC);
+    nb = tx * ty * ((g.n2 + zc - 1) / zc);
 }
 
 hipError_t launch_rr_corr(const Geom& gf, const Geom& gc, const CoefF& c, const float* e, const float* pt,
@@ -1257,7 +1259,7 @@ hipError_t launch_rr_corr(const Geom& gf, const Geom& gc, const CoefF& c, const 
     a.g = gf; a.gc = gc; a.c = c; a.e = e; a.pt = pt; a.t0 = t0; a.r = r; a.sc = sc;
     a.ec = ec; a.eold_c = eold_c; a.rd_c = rd_c; a.partials = partials;
     int nb;
-    corr_tiles(gf, a.tiles_x, a.tiles_y, nb);
+    corr_tiles(gf, a.tiles_x, a.tiles_y, a.zc, nb);
     *nblocks_out = nb;
     if (gf.dir)
         hipLaunchKernelGGL((k_corr_tiled<1, 1>), dim3(nb), dim3(NT), 0, s, a);
@@ -1272,7 +1274,7 @@ hipError_t launch_fas_corr(const Geom& g, const CoefF& c, const float* e, const 
     std::memset(&a, 0, sizeof(a));
     a.g = g; a.c = c; a.e = e; a.pt = pt; a.t0 = t0; a.r = rd; a.rout = r; a.partials = partials;
     int nb;
-    corr_tiles(g, a.tiles_x, a.tiles_y, nb);
+    corr_tiles(g, a.tiles_x, a.tiles_y, a.zc, nb);
     *nblocks_out = nb;
     if (g.dir)
         hipLaunchKernelGGL((k_corr_tiled<1, 2>), dim3(nb), dim3(NT), 0, s, a);
@@ -1284,11 +1286,12 @@ hipError_t launch_fas_corr(const Geom& g, const CoefF& c, const float* e, const 
 hipError_t launch_prolong_corr(const Geom& gf, const Geom& gc, float* ef, const float* ec, const float* eold_c,
                                hipStream_t s) {
     const int tx = (gf.n0 + TX - 1) / TX, ty = (gf.n1 + 7) / 8;
-    const int nb = tx * ty * ((gf.n2 + 15) / 16);
+    const int pz = level_zc((int64_t)tx * ty, gf.n2, 16);
+    const int nb = tx * ty * ((gf.n2 + pz - 1) / pz);
     if (gf.dir)
-        hipLaunchKernelGGL(k_prolong_corr_tiled<1>, dim3(nb), dim3(NT), 0, s, gf, gc, ef, ec, eold_c, tx, ty);
+        hipLaunchKernelGGL(k_prolong_corr_tiled<1>, dim3(nb), dim3(NT), 0, s, gf, gc, ef, ec, eold_c, tx, ty, pz);
     else
-        hipLaunchKernelGGL(k_prolong_corr_tiled<0>, dim3(nb), dim3(NT), 0, s, gf, gc, ef, ec, eold_c, tx, ty);
+        hipLaunchKernelGGL(k_prolong_corr_tiled<0>, dim3(nb), dim3(NT), 0, s, gf, gc, ef, ec, eold_c, tx, ty, pz);
     return hipGetLastError();
 }
 
@@ -1300,7 +1303,7 @@ hipError_t launch_cast_update(const Geom& g, const Coef& c, const double* phi, c
     a.g = g; a.c = c; a.phi = phi; a.e = e; a.phi_out = phi_out; a.delta = delta; a.f = f; a.sc = sc;
     a.pt = pt; a.t0 = t0; a.r = r; a.partials = partials;
     int nb;
-    corr_tiles(g, a.tiles_x, a.tiles_y, nb);
+    corr_tiles(g, a.tiles_x, a.tiles_y, a.zc, nb);
     *nblocks_out = nb;
     const bool up = e != nullptr;
     if (g.dir) {

@@ -58,7 +58,8 @@ hipError_t mixed_prepare(Plan* P) {
 hipError_t smooth_corr_level(Plan* P, GridState& G, int l) {
     LevelBuf& L = G.lev[l];
     const CoefF cf = make_coef_f(P->coef, L.g.h);
-    hipError_t e = launch_smooth_corr(L.g, cf, L.e[L.ecur], L.e[L.ecur ^ 1], L.pt, L.t0, L.r, L.scf, P->cfg,
+    const SmoothCfg cfg = l == 0 ? P->cfg : level_cfg(L.g.n0, L.g.n1, L.g.n2, P->cfg);
+    hipError_t e = launch_smooth_corr(L.g, cf, L.e[L.ecur], L.e[L.ecur ^ 1], L.pt, L.t0, L.r, L.scf, cfg,
                                       P->stream);
     L.ecur ^= 1;
     P->cell_updates += L.g.ncell;

@@ -64,6 +64,32 @@ struct SmoothCfg {
     int zc;      // z planes per block
 };
 
+// Blocks a tiled pass should at least launch: four per compute unit.
+constexpr int64_t MIN_TILED_BLOCKS = 1024;
+
+// z planes per block of a tiled pass over n2 planes with xy_tiles tiles per
+// plane: zc0, halved (down to 2, so restriction keeps its z pairs) while the
+// launch would have fewer than MIN_TILED_BLOCKS blocks.  Coarse levels then
+// spread over the chip instead of running long serial z-marches on a few CUs.
+inline int level_zc(int64_t xy_tiles, int n2, int zc0 = 16) {
+    int zc = zc0;
+    while (zc > 2 && xy_tiles * ((n2 + zc - 1) / zc) < MIN_TILED_BLOCKS) zc >>= 1;
+    return zc;
+}
+
+// Fused-sweep schedule of one level: the plan's (tuned) schedule, with the
+// z chunk shortened and then the tile height lowered to 4 on small grids.
+inline SmoothCfg level_cfg(int n0, int n1, int n2, SmoothCfg c) {
+    const int64_t tx = (n0 + 63) / 64;
+    auto blocks = [&](int ty, int zc) { return tx * ((n1 + ty - 1) / ty) * ((n2 + zc - 1) / zc); };
+    c.zc = level_zc(tx * ((n1 + c.ty - 1) / c.ty), n2, c.zc);
+    if (blocks(c.ty, c.zc) < MIN_TILED_BLOCKS && c.ty > 4) {
+        c.ty = 4;
+        c.zc = level_zc(tx * ((n1 + 3) / 4), n2, c.zc);
+    }
+    return c;
+}
+
 // ---- launchers (kernels.hip) --------------------------------------------
 hipError_t launch_smooth(const Geom& g, const Coef& c, const double* pin, double* pout,
                          const double* delta, const double* f, const LevelScalars* sc,

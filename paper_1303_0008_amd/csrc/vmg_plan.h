@@ -60,6 +60,7 @@ struct BatchLevel {
     int nfcells = 0;
     int2* d_store = nullptr;         // 256-element blocks of each member's padded storage (levels >= 1)
     int nstore_items = 0;
+    SmoothCfg cfg{8, 16};            // schedule of the persistent smoother on this level
     int2* d_ghosts = nullptr;        // 256-value blocks of each member's ghost shell (levels >= 1)
     int nghost_items = 0;
     int64_t cells_A = 0, cells_C = 0;
