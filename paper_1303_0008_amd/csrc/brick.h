@@ -1,0 +1,276 @@
+// Fused red-black Gauss-Seidel sweep over one TX x TY x (z1 - z0) brick,
+// shared by the FP64 smoother and the FP32 correction smoother.
+//
+// Colour of cell (i,j,k) = (i+j+k) & 1 (0 = red).  The red phase reads only the
+// old state u^0 (so same-colour edge neighbours come from the snapshot); the
+// black phase reads u^1 = u^0 with the red cells updated.  A block marches up z:
+//   * u^0 is staged in LDS on a two-cell ring around the tile (3 planes),
+//   * the red phase runs on a one-cell ring (recomputing what neighbouring
+//     blocks own, so no block reads another block's output) and stores the
+//     full u^1 plane (red computed, black copied) in LDS (3 planes),
+//   * the black phase runs on the tile and writes u^2 once.
+// Loads run two plane steps ahead of their use (see the pipeline below), so a
+// sweep reads u^0 and the per-cell sources once and writes u^2 once.
+//
+// The arithmetic lives in a policy K:
+//   K::Cell                 what a cell holds in LDS (double phi, or float2 (e, phi~))
+//   K::Src                  per-cell sources of the update (delta and f, or t0 and r)
+//   k.cell(i), k.src(i)     the input state / sources at storage index i
+//   k.zero_cell(), k.zero_src()
+//   k.template update<W>(Pm, Pc, Pp, c, o, src)   updated cell from its neighbourhood
+//   k.out(i, cell)          write the output state at storage index i
+#pragma once
+
+#include <type_traits>
+
+#include "device_common.h"
+
+namespace vmg {
+
+// Threads per block of the fused sweep and the waves per SIMD it is built for
+// (4 blocks of 4 waves per CU: at most 128 VGPRs, 4 x 35 KB of LDS).  Wider
+// blocks measured slower: each plane step ends in two block-wide barriers.
+constexpr int SNT = 256;
+constexpr int SNT_WAVES_PER_SIMD = 4;
+
+// Neighbourhood of a cell read from a parity-split LDS plane set.  `c` is the
+// word offset of the cell's row-half position for the neighbours in its own
+// x parity class (x-1 at c, x+1 at c+1), `o` the offset of the cell itself in
+// the other class (used for the y and z neighbours); W is the row length in
+// cells; Pm/Pc/Pp the planes below, at and above the cell.
+template <int W, typename T>
+__device__ __forceinline__ void nb_split(const T* __restrict__ Pm, const T* __restrict__ Pc,
+                                         const T* __restrict__ Pp, int c, int o, NbT<T>& v) {
+    v.xm = Pc[c];           v.xp = Pc[c + 1];
+    v.xmym = Pc[c - W];     v.xpym = Pc[c - W + 1];
+    v.xmyp = Pc[c + W];     v.xpyp = Pc[c + W + 1];
+    v.xmzm = Pm[c];         v.xpzm = Pm[c + 1];
+    v.xmzp = Pp[c];         v.xpzp = Pp[c + 1];
+    v.ym = Pc[o - W];       v.yp = Pc[o + W];
+    v.zm = Pm[o];           v.zp = Pp[o];
+    v.ymzm = Pm[o - W];     v.ypzm = Pm[o + W];
+    v.ymzp = Pp[o - W];     v.ypzp = Pp[o + W];
+}
+
+template <int TY, int DIR, int NTH, typename K>
+__device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int x0, const int y0, const int z0,
+                                            const int z1) {
+    using Cell = typename K::Cell;
+    using Src = typename K::Src;
+    constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+    constexpr int HW2 = W2 / 2, HW1 = W1 / 2;     // half-row lengths (34, 33)
+    constexpr int NP2 = W2 * H2;
+    constexpr int NL2 = (NP2 + NTH - 1) / NTH;
+    constexpr int RH = W1 / 2;        // red/black pairs per ring-1 row
+    constexpr int BH = TX / 2;        // black cells per interior row
+    constexpr int NR = (RH * H1 + NTH - 1) / NTH;   // red cells per thread
+    constexpr int NB = (BH * TY + NTH - 1) / NTH;   // black cells per thread
+    constexpr int S2 = H2 * W2, S1 = H1 * W1;     // cells per plane
+    // Rows are stored split by x parity: cell (Y, X) lives at Y*W + (X&1)*W/2 + (X>>1),
+    // so lanes working on every other cell of a row touch consecutive words.
+    __shared__ Cell P0[3 * S2];  // u^0, ring 2, slot = z mod 3
+    __shared__ Cell P1[3 * S1];  // u^1 (red computed, black copied), ring 1
+
+    const int tid = threadIdx.x;
+    if (z0 >= g.n2) return;
+
+    // ---- per-thread constants (everything that does not depend on z) -------
+    int off2[NL2], lds2[NL2];
+    bool ok2[NL2];
+#pragma unroll
+    for (int s = 0; s < NL2; ++s) {
+        const int e = tid + s * NTH;
+        ok2[s] = false;
+        off2[s] = 0;
+        lds2[s] = 0;
+        if (e < NP2) {
+            const int X = e % W2, Y = e / W2;
+            lds2[s] = Y * W2 + (X & 1) * HW2 + (X >> 1);
+            int gx = x0 - 2 + X, gy = y0 - 2 + Y;
+            if (DIR) {
+                ok2[s] = gx >= -1 && gx <= g.n0 && gy >= -1 && gy <= g.n1;
+            } else {
+                gx = wrapi(gx, g.n0);
+                gy = wrapi(gy, g.n1);
+                ok2[s] = true;
+            }
+            off2[s] = (int)(g.off0 + gx + (int64_t)gy * g.sy);
+        }
+    }
+    // red cells: ring-1 row r, pair m; parity par = (y0 + r + p) & 1 puts the red cell at
+    // ring-1 column 2m + par and the black one at 2m + 1 - par
+    bool rv[NR];              // slot exists
+    int rpar0[NR];            // parity at p = 0
+    int rc[NR][2], ro[NR][2]; // nb_split offsets in P0 (ring 2) for each parity
+    int rw[NR][2], rb[NR][2]; // P1 cells of the red and the black cell
+    int rsrc[NR][2];          // P0 cell of the black cell (copied into P1)
+    int rg[NR][2];            // global in-plane index of the red cell (-1: not a cell)
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const int e = tid + q * NTH;
+        rv[q] = e < RH * H1;
+        const int r = rv[q] ? e / RH : 0, m = rv[q] ? e - r * RH : 0;
+        rpar0[q] = (y0 + r) & 1;
+        const int gy = y0 - 1 + r;
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            const int Y = r + 1;                                  // ring-2 row
+            rc[q][par] = Y * W2 + par * HW2 + m;                  // x-1 of the red cell (X = 2m+par+1)
+            ro[q][par] = Y * W2 + (1 - par) * HW2 + m + par;      // the red cell itself
+            rw[q][par] = r * W1 + par * HW1 + m;                  // ring-1 column 2m+par
+            rb[q][par] = r * W1 + (1 - par) * HW1 + m;            // ring-1 column 2m+1-par
+            rsrc[q][par] = Y * W2 + par * HW2 + m + 1 - par;      // ring-2 column 2m+2-par
+            int gx = x0 - 1 + 2 * m + par, wy = gy;
+            if (DIR) {
+                rg[q][par] = (rv[q] && gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1)
+                                 ? (int)(g.off0 + gx + (int64_t)gy * g.sy) : -1;
+            } else {
+                gx = wrapi(gx, g.n0);
+                wy = wrapi(gy, g.n1);
+                rg[q][par] = rv[q] ? (int)(gx + (int64_t)wy * g.sy) : -1;
+            }
+        }
+    }
+    // black cells: interior row r, pair m; black at column 2m + ((y0 + r + p2 + 1) & 1).
+    // With more threads than black cells, the black cells go to the highest
+    // waves so that red and black work land on different waves.
+    constexpr int BOFF = NTH > BH * TY ? ((NTH - BH * TY) / 64) * 64 : 0;
+    const int tb = tid - BOFF;
+    bool bv[NB];
+    int bpar0[NB], bm2[NB];
+    int bc[NB][2], bo[NB][2], brd[NB][2];
+    int64_t brow[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int e = tb + q * NTH;
+        const int r = e >= 0 ? e / BH : 0, m = e >= 0 ? e - r * BH : 0;
+        const int gy = y0 + r;
+        bv[q] = e >= 0 && e < BH * TY && gy < g.n1;
+        bpar0[q] = (y0 + r + 1) & 1;
+        bm2[q] = 2 * m;
+        brow[q] = g.off0 + (int64_t)gy * g.sy + x0 + 2 * m;
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            const int Y = r + 1;                                   // ring-1 row
+            bc[q][par] = Y * W1 + par * HW1 + m;                   // x-1 of the black cell (X = 2m+par+1)
+            bo[q][par] = Y * W1 + (1 - par) * HW1 + m + par;       // the black cell itself
+            brd[q][par] = Y * W1 + par * HW1 + m + 1 - par;        // red partner at column 2m+2-par
+        }
+    }
+    const int bxmax = g.n0 - x0;   // columns >= bxmax are outside the grid
+    auto plane_off = [&](int t, bool& zok) -> int64_t {
+        int gz;
+        if (DIR) { gz = t; zok = t >= -1 && t <= g.n2; }
+        else { gz = t < 0 ? t + g.n2 : (t >= g.n2 ? t - g.n2 : t); zok = true; }
+        return (int64_t)gz * g.sz;
+    };
+    auto load_plane = [&](int t, Cell (&r)[NL2]) {
+        bool zok;
+        const int64_t zo = plane_off(t, zok);
+#pragma unroll
+        for (int s = 0; s < NL2; ++s) r[s] = (ok2[s] && zok) ? k.cell(zo + off2[s]) : k.zero_cell();
+    };
+    auto store_plane = [&](int sl, const Cell (&r)[NL2]) {
+#pragma unroll
+        for (int s = 0; s < NL2; ++s)
+            if (tid + s * NTH < NP2) P0[sl * S2 + lds2[s]] = r[s];
+    };
+    auto slot = [](int z) { return (z + 3) % 3; };   // z >= -2
+
+    auto fetch_red = [&](int p, Src (&sr)[NR]) {
+        bool zok;
+        int64_t zo = plane_off(p, zok);
+        if (DIR) zok = p >= 0 && p < g.n2;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const int par = (rpar0[q] + p) & 1;
+            const int gi = rg[q][par];
+            sr[q] = (zok && gi >= 0) ? k.src(zo + gi) : k.zero_src();
+        }
+    };
+    auto fetch_black = [&](int p2, Src (&sr)[NB]) {
+        const int64_t zo = (int64_t)p2 * g.sz;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int par = (bpar0[q] + p2) & 1;
+            const bool ok = bv[q] && bm2[q] + par < bxmax;
+            sr[q] = ok ? k.src(zo + brow[q] + par) : k.zero_src();
+        }
+    };
+
+    // Software pipeline over z.  Step t computes red on plane t-1 (u^0 planes
+    // t-2..t in LDS) and black on plane t-2 (u^1 planes t-3..t-1 in LDS).
+    // Loads run two steps ahead of their use: the u^0 plane t+2 is issued at
+    // the start of step t and committed to LDS at the end of step t+1; the
+    // sources of a red (black) plane are issued right after the red (black)
+    // phase that consumed their register buffer, two steps before use.
+    // Buffers alternate with the step's parity b, so the loop body is unrolled
+    // twice and every buffer index is a compile-time constant.
+    Cell pq[2][NL2];        // u^0 planes in flight
+    Src rq[2][NR];          // red sources: plane t-1 in [b] at step t
+    Src bq[2][NB];          // black sources: plane t-2 in [b] at step t
+    {
+        Cell r2[NL2];
+        for (int t = z0 - 2; t <= z0; ++t) {
+            load_plane(t, r2);
+            store_plane(slot(t), r2);
+        }
+        load_plane(z0 + 1, pq[1]);
+        fetch_red(z0 - 1, rq[0]);
+        fetch_red(z0, rq[1]);
+    }
+    __syncthreads();
+
+    auto step = [&](const int t, auto parity_tag) {
+        constexpr int b = decltype(parity_tag)::value;
+        const int p = t - 1, p2 = t - 2;
+        if (t + 2 <= z1 + 1) load_plane(t + 2, pq[b]);
+        // ---- red phase on plane p, ring 1: P0 -> P1 ---------------------------
+        {
+            const Cell* Pm = P0 + slot(p - 1) * S2;
+            const Cell* Pc = P0 + slot(p) * S2;
+            const Cell* Pp = P0 + slot(p + 1) * S2;
+            Cell* Q1 = P1 + slot(p) * S1;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                if (!rv[q]) continue;
+                const int par = (rpar0[q] + p) & 1;
+                const int c = rc[q][par], o = ro[q][par];
+                Cell val = Pc[o];
+                const bool interior = DIR ? (rg[q][par] >= 0 && p >= 0 && p < g.n2) : true;
+                if (interior) val = k.template update<W2>(Pm, Pc, Pp, c, o, rq[b][q]);
+                Q1[rw[q][par]] = val;
+                Q1[rb[q][par]] = Pc[rsrc[q][par]];
+            }
+        }
+        if (t + 1 <= z1) fetch_red(t + 1, rq[b]);
+        __syncthreads();
+        // ---- black phase on plane p2, tile interior: P1 -> u^2 -----------------
+        if (p2 >= z0) {
+            const Cell* Rm = P1 + slot(p2 - 1) * S1;
+            const Cell* Rc = P1 + slot(p2) * S1;
+            const Cell* Rp = P1 + slot(p2 + 1) * S1;
+            const int64_t zo = (int64_t)p2 * g.sz;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                if (!bv[q]) continue;
+                const int par = (bpar0[q] + p2) & 1;
+                if (bm2[q] + par < bxmax)
+                    k.out(zo + brow[q] + par, k.template update<W1>(Rm, Rc, Rp, bc[q][par], bo[q][par], bq[b][q]));
+                if (bm2[q] + 1 - par < bxmax) k.out(zo + brow[q] + 1 - par, Rc[brd[q][par]]);
+            }
+        }
+        if (t >= z0 && t < z1) fetch_black(t, bq[b]);
+        // ---- commit u^0 plane t+1 (its slot held plane t-2, last read by this red phase)
+        if (t + 1 <= z1 + 1) store_plane(slot(t + 1), pq[b ^ 1]);
+        __syncthreads();
+    };
+    int t = z0;
+    for (; t + 1 <= z1 + 1; t += 2) {
+        step(t, std::integral_constant<int, 0>());
+        step(t + 1, std::integral_constant<int, 1>());
+    }
+    if (t <= z1 + 1) step(t, std::integral_constant<int, 0>());
+}
+
+}  // namespace vmg

@@ -13,23 +13,12 @@
 #include <cstring>
 #include <type_traits>
 
-#include "device_common.h"
+#include "brick.h"
 
 namespace vmg {
 
 // ---------------------------------------------------------------------------
-// Fused red-black sweep.  Colour of cell (i,j,k) = (i+j+k) & 1 (0 = red).
-// Red phase reads only phi^0 (old values, so same-colour edge neighbours are
-// taken from the snapshot); black phase reads phi^1 = phi^0 with the red cells
-// updated.  One block owns a TX x TY x zc brick and marches up z:
-//   * phi^0 is staged in LDS on a two-cell ring around the tile (3 planes),
-//   * the red phase runs on a one-cell ring (recomputing what neighbouring
-//     blocks own, so no block reads another block's output) and stores the
-//     full phi^1 plane (red computed, black copied) in LDS (3 planes),
-//   * the black phase runs on the tile and writes phi^2 once,
-//   * the next plane of phi^0 and delta (and f) is loaded into registers while
-//     the current planes are computed (software pipelining).
-// A sweep therefore reads phi^0 and delta (and f) once and writes phi^2 once.
+// FP64 fused red-black sweep (the z-marching brick is in brick.h).
 // ---------------------------------------------------------------------------
 struct SmoothArgs {
     Geom g;
@@ -42,269 +31,49 @@ struct SmoothArgs {
     int zc, tiles_x, tiles_y;
 };
 
-// Neighbourhood of a cell read from a parity-split LDS plane set.  `c` is the
-// word offset of the cell's row-half position for the neighbours in its own
-// x parity class (x-1 at c, x+1 at c+1), `o` the offset of the cell itself in
-// the other class (used for the y and z neighbours); W is the row length in
-// words; Pm/Pc/Pp the planes below, at and above the cell.
-template <int W>
-__device__ __forceinline__ void nb_split(const double* __restrict__ Pm, const double* __restrict__ Pc,
-                                         const double* __restrict__ Pp, int c, int o, Nb& v) {
-    v.xm = Pc[c];           v.xp = Pc[c + 1];
-    v.xmym = Pc[c - W];     v.xpym = Pc[c - W + 1];
-    v.xmyp = Pc[c + W];     v.xpyp = Pc[c + W + 1];
-    v.xmzm = Pm[c];         v.xpzm = Pm[c + 1];
-    v.xmzp = Pp[c];         v.xpzp = Pp[c + 1];
-    v.ym = Pc[o - W];       v.yp = Pc[o + W];
-    v.zm = Pm[o];           v.zp = Pp[o];
-    v.ymzm = Pm[o - W];     v.ypzm = Pm[o + W];
-    v.ymzp = Pp[o - W];     v.ypzp = Pp[o + W];
-}
+// FP64 smoother policy of the fused sweep: cells hold phi, sources are delta
+// and (on coarse levels) the FAS right-hand side f.  Closed-form update of
+// Sec. III.B at w = 1/3: phi_c <- (S - h^2 (Q + f - cbar)) / 6.
+template <bool HAS_F>
+struct SmoothK {
+    using Cell = double;
+    struct Src {
+        double dl, f;
+    };
+    const double* __restrict__ pin;
+    double* __restrict__ pout;
+    const double* __restrict__ delta;
+    const double* __restrict__ f;
+    Coef c;
+    double h2, inv_h4, cb;
 
-template <int TY, int DIR, bool HAS_F, int NTH>
-__device__ __forceinline__ void smooth_brick(const SmoothArgs& a, const int x0, const int y0, const int z0,
-                                             const int z1) {
-    constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
-    constexpr int HW2 = W2 / 2, HW1 = W1 / 2;     // half-row lengths (34, 33)
-    constexpr int NP2 = W2 * H2;
-    constexpr int NL2 = (NP2 + NTH - 1) / NTH;
-    constexpr int RH = W1 / 2;        // red/black pairs per ring-1 row
-    constexpr int BH = TX / 2;        // black cells per interior row
-    constexpr int NR = (RH * H1 + NTH - 1) / NTH;   // red cells per thread
-    constexpr int NB = (BH * TY + NTH - 1) / NTH;   // black cells per thread
-    constexpr int S2 = H2 * W2, S1 = H1 * W1;     // words per plane
-    // Rows are stored split by x parity: word (Y, X) lives at Y*W + (X&1)*W/2 + (X>>1),
-    // so lanes working on every other cell of a row touch consecutive words.
-    __shared__ double P0[3 * S2];  // phi^0, ring 2, slot = z mod 3
-    __shared__ double P1[3 * S1];  // phi^1 (red computed, black copied), ring 1
-
-    const Geom& g = a.g;
-    const int tid = threadIdx.x;
-    if (z0 >= g.n2) return;
-    const double h2 = g.h * g.h, inv_h4 = 1.0 / (h2 * h2);
-    const double cb = DIR ? 0.0 : a.sc->cbar;
-
-    // ---- per-thread constants (everything that does not depend on z) -------
-    int off2[NL2], lds2[NL2];
-    bool ok2[NL2];
-#pragma unroll
-    for (int s = 0; s < NL2; ++s) {
-        const int e = tid + s * NTH;
-        ok2[s] = false;
-        off2[s] = 0;
-        lds2[s] = 0;
-        if (e < NP2) {
-            const int X = e % W2, Y = e / W2;
-            lds2[s] = Y * W2 + (X & 1) * HW2 + (X >> 1);
-            int gx = x0 - 2 + X, gy = y0 - 2 + Y;
-            if (DIR) {
-                ok2[s] = gx >= -1 && gx <= g.n0 && gy >= -1 && gy <= g.n1;
-            } else {
-                gx = wrapi(gx, g.n0);
-                gy = wrapi(gy, g.n1);
-                ok2[s] = true;
-            }
-            off2[s] = (int)(g.off0 + gx + (int64_t)gy * g.sy);
-        }
+    __device__ SmoothK(const SmoothArgs& a, const Geom& g, bool periodic)
+        : pin(a.pin), pout(a.pout), delta(a.delta), f(a.f), c(a.c) {
+        h2 = g.h * g.h;
+        inv_h4 = 1.0 / (h2 * h2);
+        cb = periodic ? a.sc->cbar : 0.0;
     }
-    // red cells: ring-1 row r, pair m; parity par = (y0 + r + p) & 1 puts the red cell at
-    // ring-1 column 2m + par and the black one at 2m + 1 - par
-    bool rv[NR];              // slot exists
-    int rpar0[NR];            // parity at p = 0
-    int rc[NR][2], ro[NR][2]; // nb_split offsets in P0 (ring 2) for each parity
-    int rw[NR][2], rb[NR][2]; // P1 words of the red and the black cell
-    int rsrc[NR][2];          // P0 word of the black cell (copied into P1)
-    int rg[NR][2];            // global in-plane index of the red cell (-1: not a cell)
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-        const int e = tid + q * NTH;
-        rv[q] = e < RH * H1;
-        const int r = rv[q] ? e / RH : 0, m = rv[q] ? e - r * RH : 0;
-        rpar0[q] = (y0 + r) & 1;
-        const int gy = y0 - 1 + r;
-#pragma unroll
-        for (int par = 0; par < 2; ++par) {
-            const int Y = r + 1;                                  // ring-2 row
-            rc[q][par] = Y * W2 + par * HW2 + m;                  // x-1 of the red cell (X = 2m+par+1)
-            ro[q][par] = Y * W2 + (1 - par) * HW2 + m + par;      // the red cell itself
-            rw[q][par] = r * W1 + par * HW1 + m;                  // ring-1 column 2m+par
-            rb[q][par] = r * W1 + (1 - par) * HW1 + m;            // ring-1 column 2m+1-par
-            rsrc[q][par] = Y * W2 + par * HW2 + m + 1 - par;      // ring-2 column 2m+2-par
-            int gx = x0 - 1 + 2 * m + par, wy = gy;
-            if (DIR) {
-                rg[q][par] = (rv[q] && gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1)
-                                 ? (int)(g.off0 + gx + (int64_t)gy * g.sy) : -1;
-            } else {
-                gx = wrapi(gx, g.n0);
-                wy = wrapi(gy, g.n1);
-                rg[q][par] = rv[q] ? (int)(gx + (int64_t)wy * g.sy) : -1;
-            }
-        }
+    __device__ double cell(int64_t i) const { return pin[i]; }
+    __device__ double zero_cell() const { return 0.0; }
+    __device__ Src src(int64_t i) const {
+        Src s;
+        s.dl = delta[i];
+        s.f = HAS_F ? f[i] : 0.0;
+        return s;
     }
-    // black cells: interior row r, pair m; black at column 2m + ((y0 + r + p2 + 1) & 1)
-    // With more threads than black cells, the black cells go to the highest
-    // waves so that red and black work land on different waves.
-    constexpr int BOFF = NTH > BH * TY ? ((NTH - BH * TY) / 64) * 64 : 0;
-    const int tb = tid - BOFF;
-    bool bv[NB];
-    int bpar0[NB];
-    int bc[NB][2], bo[NB][2], brd[NB][2];
-    int64_t brow[NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        const int e = tb + q * NTH;
-        const int r = e >= 0 ? e / BH : 0, m = e >= 0 ? e - r * BH : 0;
-        const int gy = y0 + r;
-        bv[q] = e >= 0 && e < BH * TY && gy < g.n1;
-        bpar0[q] = (y0 + r + 1) & 1;
-        brow[q] = g.off0 + (int64_t)gy * g.sy + x0 + 2 * m;
-#pragma unroll
-        for (int par = 0; par < 2; ++par) {
-            const int Y = r + 1;                                   // ring-1 row
-            bc[q][par] = Y * W1 + par * HW1 + m;                   // x-1 of the black cell (X = 2m+par+1)
-            bo[q][par] = Y * W1 + (1 - par) * HW1 + m + par;       // the black cell itself
-            brd[q][par] = Y * W1 + par * HW1 + m + 1 - par;        // red partner at column 2m+2-par
-        }
+    __device__ Src zero_src() const { return Src{0.0, 0.0}; }
+    template <int W>
+    __device__ double update(const double* Pm, const double* Pc, const double* Pp, int co, int o,
+                             const Src& s) const {
+        Nb v;
+        nb_split<W>(Pm, Pc, Pp, co, o, v);
+        double S;
+        bool gd;
+        const double Q = nl_root(v, s.dl, c, inv_h4, S, gd);
+        return (S - h2 * (Q + (HAS_F ? s.f : 0.0) - cb)) * (1.0 / 6.0);
     }
-    const int bxmax = g.n0 - x0;   // columns >= bxmax are outside the grid
-    auto plane_off = [&](int t, bool& zok) -> int64_t {
-        int gz;
-        if (DIR) { gz = t; zok = t >= -1 && t <= g.n2; }
-        else { gz = t < 0 ? t + g.n2 : (t >= g.n2 ? t - g.n2 : t); zok = true; }
-        return (int64_t)gz * g.sz;
-    };
-    auto load_phi = [&](int t, double (&r)[NL2]) {
-        bool zok;
-        const int64_t zo = plane_off(t, zok);
-#pragma unroll
-        for (int s = 0; s < NL2; ++s) r[s] = (ok2[s] && zok) ? a.pin[zo + off2[s]] : 0.0;
-    };
-    auto store_phi = [&](int sl, const double (&r)[NL2]) {
-#pragma unroll
-        for (int s = 0; s < NL2; ++s)
-            if (tid + s * NTH < NP2) P0[sl * S2 + lds2[s]] = r[s];
-    };
-    auto slot = [](int z) { return (z + 3) % 3; };   // z >= -2
-
-    auto fetch_red = [&](int p, double (&dl)[NR], double (&ff)[NR]) {
-        bool zok;
-        int64_t zo = plane_off(p, zok);
-        if (DIR) zok = p >= 0 && p < g.n2;
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            const int par = (rpar0[q] + p) & 1;
-            const int gi = rg[q][par];
-            const bool ok = zok && gi >= 0;
-            dl[q] = ok ? a.delta[zo + gi] : 0.0;
-            ff[q] = (HAS_F && ok) ? a.f[zo + gi] : 0.0;
-        }
-    };
-    auto fetch_black = [&](int p2, double (&dl)[NB], double (&ff)[NB]) {
-        const int64_t zo = (int64_t)p2 * g.sz;
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int par = (bpar0[q] + p2) & 1;
-            const bool ok = bv[q] && 2 * (tb + q * NTH - ((tb + q * NTH) / BH) * BH) + par < bxmax;
-            const int64_t gi = zo + brow[q] + par;
-            dl[q] = ok ? a.delta[gi] : 0.0;
-            ff[q] = (HAS_F && ok) ? a.f[gi] : 0.0;
-        }
-    };
-
-    // Software pipeline over z.  Step t computes red on plane t-1 (phi^0 planes
-    // t-2..t in LDS) and black on plane t-2 (phi^1 planes t-3..t-1 in LDS).
-    // Loads run two steps ahead of their use: the phi^0 plane t+2 is issued at
-    // the start of step t and committed to LDS at the end of step t+1; the
-    // delta/f values of a red (black) plane are issued right after the red
-    // (black) phase that consumed their register buffer, two steps before use.
-    // Buffers alternate with the step's parity b, so the loop body is unrolled
-    // twice and every buffer index is a compile-time constant.
-    double pq[2][NL2];                       // phi^0 planes in flight
-    double rq_dl[2][NR], rq_f[2][NR];        // red sources: plane t-1 in [b] at step t
-    double bq_dl[2][NB], bq_f[2][NB];        // black sources: plane t-2 in [b] at step t
-    {
-        double r2[NL2];
-        for (int t = z0 - 2; t <= z0; ++t) {
-            load_phi(t, r2);
-            store_phi(slot(t), r2);
-        }
-        if (z0 + 1 <= z1 + 1) load_phi(z0 + 1, pq[1]);
-        fetch_red(z0 - 1, rq_dl[0], rq_f[0]);
-        if (z0 <= z1) fetch_red(z0, rq_dl[1], rq_f[1]);
-    }
-    __syncthreads();
-
-    auto step = [&](const int t, auto parity_tag) {
-        constexpr int b = decltype(parity_tag)::value;
-        const int p = t - 1, p2 = t - 2;
-        if (t + 2 <= z1 + 1) load_phi(t + 2, pq[b]);
-        // ---- red phase on plane p, ring 1: P0 -> P1 ---------------------------
-        {
-            const double* Pm = P0 + slot(p - 1) * S2;
-            const double* Pc = P0 + slot(p) * S2;
-            const double* Pp = P0 + slot(p + 1) * S2;
-            double* Q1 = P1 + slot(p) * S1;
-#pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                if (!rv[q]) continue;
-                const int par = (rpar0[q] + p) & 1;
-                const int c = rc[q][par], o = ro[q][par];
-                double val = Pc[o];
-                const bool interior = DIR ? (rg[q][par] >= 0 && p >= 0 && p < g.n2) : true;
-                if (interior) {
-                    Nb v;
-                    nb_split<W2>(Pm, Pc, Pp, c, o, v);
-                    double S;
-                    bool gd;
-                    const double Q = nl_root(v, rq_dl[b][q], a.c, inv_h4, S, gd);
-                    val = (S - h2 * (Q + (HAS_F ? rq_f[b][q] : 0.0) - cb)) * (1.0 / 6.0);
-                }
-                Q1[rw[q][par]] = val;
-                Q1[rb[q][par]] = Pc[rsrc[q][par]];
-            }
-        }
-        if (t + 1 <= z1) fetch_red(t + 1, rq_dl[b], rq_f[b]);
-        __syncthreads();
-        // ---- black phase on plane p2, tile interior: P1 -> phi^2 ---------------
-        if (p2 >= z0) {
-            const double* Rm = P1 + slot(p2 - 1) * S1;
-            const double* Rc = P1 + slot(p2) * S1;
-            const double* Rp = P1 + slot(p2 + 1) * S1;
-            const int64_t zo = (int64_t)p2 * g.sz;
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                if (!bv[q]) continue;
-                const int par = (bpar0[q] + p2) & 1;
-                const int mcol = 2 * (tb + q * NTH - ((tb + q * NTH) / BH) * BH);
-                if (mcol + par < bxmax) {
-                    Nb v;
-                    nb_split<W1>(Rm, Rc, Rp, bc[q][par], bo[q][par], v);
-                    double S;
-                    bool gd;
-                    const double Q = nl_root(v, bq_dl[b][q], a.c, inv_h4, S, gd);
-                    a.pout[zo + brow[q] + par] = (S - h2 * (Q + (HAS_F ? bq_f[b][q] : 0.0) - cb)) * (1.0 / 6.0);
-                }
-                if (mcol + 1 - par < bxmax) a.pout[zo + brow[q] + 1 - par] = Rc[brd[q][par]];
-            }
-        }
-        if (t >= z0 && t < z1) fetch_black(t, bq_dl[b], bq_f[b]);
-        // ---- commit phi^0 plane t+1 (its slot held plane t-2, last read by this red phase)
-        if (t + 1 <= z1 + 1) store_phi(slot(t + 1), pq[b ^ 1]);
-        __syncthreads();
-    };
-    int t = z0;
-    for (; t + 1 <= z1 + 1; t += 2) {
-        step(t, std::integral_constant<int, 0>());
-        step(t + 1, std::integral_constant<int, 1>());
-    }
-    if (t <= z1 + 1) step(t, std::integral_constant<int, 0>());
-}
-
-// Threads per block of the fused sweep and the waves per SIMD it is built for
-// (4 blocks of 4 waves per CU: at most 128 VGPRs, 4 x 35 KB of LDS).  Wider
-// blocks measured slower: each plane step ends in two block-wide barriers.
-constexpr int SNT = 256;
-constexpr int SNT_WAVES_PER_SIMD = 4;
+    __device__ void out(int64_t i, double v) const { pout[i] = v; }
+};
 
 template <int TY, int DIR, bool HAS_F>
 __global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth(SmoothArgs a) {
@@ -315,7 +84,8 @@ __global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth(SmoothArgs a
     const int ch = b / a.tiles_y;
     const int z0 = ch * a.zc;
     if (z0 >= a.g.n2) return;
-    smooth_brick<TY, DIR, HAS_F, SNT>(a, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
+    const SmoothK<HAS_F> k(a, a.g, DIR == 0);
+    fused_sweep<TY, DIR, SNT>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
 }
 
 // Persistent sweep over a (grid, tile x, tile y, z chunk) work list: every
@@ -329,7 +99,8 @@ __global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth_batch(Smooth
         SmoothArgs a = proto;
         a.g = geoms[w.x];
         const int z0 = w.w * a.zc;
-        smooth_brick<TY, 1, HAS_F, SNT>(a, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
+        const SmoothK<HAS_F> k(a, a.g, false);
+        fused_sweep<TY, 1, SNT>(k, a.g, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
     }
 }
 

@@ -18,7 +18,7 @@
 #include <algorithm>
 #include <cstring>
 
-#include "device_common.h"
+#include "brick.h"
 
 namespace vmg {
 
@@ -69,231 +69,51 @@ struct CorrArgs {
     int zc, tiles_x, tiles_y;
 };
 
-template <int TY, int DIR>
-__device__ __forceinline__ void corr_brick(const CorrArgs& a, const int x0, const int y0, const int z0,
-                                           const int z1) {
-    constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
-    constexpr int NP2 = W2 * H2;
-    constexpr int NL2 = (NP2 + NT - 1) / NT;
-    constexpr int RH = W1 / 2;
-    constexpr int BH = TX / 2;
-    constexpr int NR = (RH * H1 + NT - 1) / NT;
-    constexpr int NB = (BH * TY + NT - 1) / NT;
-    // rows split by x parity so that lanes on every other cell read consecutive words
-    __shared__ float E0[3][H2][2][W2 / 2];    // e^0, ring 2
-    __shared__ float PT2[3][H2][2][W2 / 2];   // phi~, ring 2
-    __shared__ float E1[3][H1][2][W1 / 2];    // e^1 (red computed, black copied), ring 1
-    __shared__ float PT1[3][H1][2][W1 / 2];   // phi~ copy, ring 1
-#define AE0(S, Y, X) E0[S][Y][(X) & 1][(X) >> 1]
-#define AP2(S, Y, X) PT2[S][Y][(X) & 1][(X) >> 1]
-#define AE1(S, Y, X) E1[S][Y][(X) & 1][(X) >> 1]
-#define AP1(S, Y, X) PT1[S][Y][(X) & 1][(X) >> 1]
+// FP32 correction policy of the fused sweep (brick.h): a cell holds (e, phi~),
+// so one 8-byte LDS read gives both neighbourhoods; sources are t0 and r.
+struct CorrK {
+    using Cell = float2;   // (e, phi~)
+    struct Src {
+        float t0, r;
+    };
+    const float* __restrict__ ein;
+    float* __restrict__ eout;
+    const float* __restrict__ pt;
+    const float* __restrict__ t0;
+    const float* __restrict__ r;
+    CoefF c;
+    float cb;
 
-    const Geom& g = a.g;
-    const int tid = threadIdx.x;
-    if (z0 >= g.n2) return;
-    const float h2 = a.c.h2;
-    const float cb = DIR ? 0.0f : (float)a.sc->cbar;
-
-    int off2[NL2];
-    bool ok2[NL2];
-#pragma unroll
-    for (int s = 0; s < NL2; ++s) {
-        const int e = tid + s * NT;
-        ok2[s] = false;
-        off2[s] = 0;
-        if (e < NP2) {
-            int gx = x0 - 2 + e % W2, gy = y0 - 2 + e / W2;
-            if (DIR) {
-                ok2[s] = gx >= -1 && gx <= g.n0 && gy >= -1 && gy <= g.n1;
-            } else {
-                gx = wrapi(gx, g.n0);
-                gy = wrapi(gy, g.n1);
-                ok2[s] = true;
-            }
-            off2[s] = (int)(g.off0 + gx + (int64_t)gy * g.sy);
-        }
+    __device__ CorrK(const CorrArgs& a, bool periodic)
+        : ein(a.ein), eout(a.eout), pt(a.pt), t0(a.t0), r(a.r), c(a.c) {
+        cb = periodic ? (float)a.sc->cbar : 0.0f;
     }
-    auto plane_off = [&](int t, bool& zok) -> int64_t {
-        int gz;
-        if (DIR) { gz = t; zok = t >= -1 && t <= g.n2; }
-        else { gz = wrapi(t, g.n2); zok = true; }
-        return (int64_t)gz * g.sz;
-    };
-    auto load2 = [&](const float* src, int t, float (&r)[NL2]) {
-        bool zok;
-        const int64_t zo = plane_off(t, zok);
-#pragma unroll
-        for (int s = 0; s < NL2; ++s) r[s] = (ok2[s] && zok && tid + s * NT < NP2) ? src[zo + off2[s]] : 0.0f;
-    };
-    auto store2 = [&](float (*dst)[2][W2 / 2], const float (&r)[NL2]) {
-#pragma unroll
-        for (int s = 0; s < NL2; ++s) {
-            const int e = tid + s * NT;
-            if (e < NP2) {
-                const int X = e % W2, Y = e / W2;
-                dst[Y][X & 1][X >> 1] = r[s];
-            }
-        }
-    };
-    auto r1_index = [&](int lx, int r, int p) -> int64_t {
-        int gx = x0 - 1 + lx, gy = y0 - 1 + r, gz = p;
-        if (DIR) {
-            if (gx < 0 || gx >= g.n0 || gy < 0 || gy >= g.n1 || gz < 0 || gz >= g.n2) return -1;
-        } else {
-            gx = wrapi(gx, g.n0);
-            gy = wrapi(gy, g.n1);
-            gz = wrapi(gz, g.n2);
-        }
-        return g.off0 + gx + (int64_t)gy * g.sy + (int64_t)gz * g.sz;
-    };
-    auto red_cell = [&](int q, int p, int& r, int& lx, int& lb) -> bool {
-        const int e = tid + q * NT;
-        if (e >= RH * H1) return false;
-        r = e / RH;
-        const int m = e - r * RH;
-        const int odd = (y0 - 1 + r + p + 1) & 1;
-        lx = 2 * m + odd;
-        lb = 2 * m + 1 - odd;
-        return true;
-    };
-    auto black_cell = [&](int q, int p2, int& r, int& xb, int& xr) -> bool {
-        const int e = tid + q * NT;
-        if (e >= BH * TY) return false;
-        r = e / BH;
-        const int m = e - r * BH;
-        xb = 2 * m + ((y0 + r + p2 + 1) & 1);
-        xr = 2 * m + ((y0 + r + p2) & 1);
-        return true;
-    };
-    auto slot = [](int z) { return (z + 3) % 3; };
-
-    float rd_t[NR], rd_r[NR], bk_t[NB], bk_r[NB];
-    auto fetch_red = [&](int p, float (&tt)[NR], float (&rr)[NR]) {
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            int r, lx, lb;
-            tt[q] = 1.0f;
-            rr[q] = 0.0f;
-            if (!red_cell(q, p, r, lx, lb)) continue;
-            const int64_t gi = r1_index(lx, r, p);
-            if (gi < 0) continue;
-            tt[q] = a.t0[gi];
-            rr[q] = a.r[gi];
-        }
-    };
-    auto fetch_black = [&](int p2, float (&tt)[NB], float (&rr)[NB]) {
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            int r, xb, xr;
-            tt[q] = 1.0f;
-            rr[q] = 0.0f;
-            if (!black_cell(q, p2, r, xb, xr)) continue;
-            const int64_t gi = r1_index(xb + 1, r + 1, p2);
-            if (gi < 0) continue;
-            tt[q] = a.t0[gi];
-            rr[q] = a.r[gi];
-        }
-    };
-
-    {
-        float r2[NL2];
-        for (int t = z0 - 2; t <= z0; ++t) {
-            load2(a.ein, t, r2);
-            store2(E0[slot(t)], r2);
-            load2(a.pt, t, r2);
-            store2(PT2[slot(t)], r2);
-        }
-        fetch_red(z0 - 1, rd_t, rd_r);
+    __device__ float2 cell(int64_t i) const { return make_float2(ein[i], pt[i]); }
+    __device__ float2 zero_cell() const { return make_float2(0.0f, 0.0f); }
+    __device__ Src src(int64_t i) const { return Src{t0[i], r[i]}; }
+    __device__ Src zero_src() const { return Src{1.0f, 0.0f}; }
+    template <int W>
+    __device__ float2 update(const float2* Pm, const float2* Pc, const float2* Pp, int co, int o,
+                             const Src& s) const {
+        NbT<float2> v;
+        nb_split<W>(Pm, Pc, Pp, co, o, v);
+        NbT<float> ve, vp;
+#define VMG_SPLIT(m) ve.m = v.m.x; vp.m = v.m.y;
+        VMG_SPLIT(xm) VMG_SPLIT(xp) VMG_SPLIT(ym) VMG_SPLIT(yp) VMG_SPLIT(zm) VMG_SPLIT(zp)
+        VMG_SPLIT(xpyp) VMG_SPLIT(xmym) VMG_SPLIT(xpym) VMG_SPLIT(xmyp)
+        VMG_SPLIT(xpzp) VMG_SPLIT(xmzm) VMG_SPLIT(xpzm) VMG_SPLIT(xmzp)
+        VMG_SPLIT(ypzp) VMG_SPLIT(ymzm) VMG_SPLIT(ypzm) VMG_SPLIT(ymzp)
+#undef VMG_SPLIT
+        float Se;
+        const float dq = dq_corr(ve, vp, c.a_ih4, Se);
+        const float dQ = dQ_of(dq, s.t0, c);
+        return make_float2((Se - c.h2 * (dQ + s.r - cb)) * (1.0f / 6.0f), Pc[o].y);
     }
-    __syncthreads();
-
-    for (int t = z0; t <= z1 + 1; ++t) {
-        const int p = t - 1, p2 = t - 2;
-        float ne[NL2], np[NL2], nrt[NR], nrr[NR], nbt[NB], nbr[NB];
-        const bool pf2 = t + 1 <= z1 + 1, pf_red = t <= z1, pf_blk = t - 1 >= z0 && t - 1 < z1;
-        if (pf2) {
-            load2(a.ein, t + 1, ne);
-            load2(a.pt, t + 1, np);
-        }
-        if (pf_red) fetch_red(t, nrt, nrr);
-        if (pf_blk) fetch_black(t - 1, nbt, nbr);
-        {
-            const int sm = slot(p - 1), sc = slot(p), sp = slot(p + 1);
-            const bool pzok = DIR ? (p >= 0 && p < g.n2) : true;
-#pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                int r, lx, lb;
-                if (!red_cell(q, p, r, lx, lb)) continue;
-                const int gx = x0 - 1 + lx, gy = y0 - 1 + r;
-                const int X = lx + 1, Y = r + 1;
-                bool interior = true;
-                if (DIR) interior = pzok && gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1;
-                float val = AE0(sc, Y, X);
-                if (interior) {
-                    NbT<float> ve, vp;
-#define LOADNB(v, A, Sm, Sc, Sp)                                                                   \
-    v.xm = A(Sc, Y, X - 1); v.xp = A(Sc, Y, X + 1); v.ym = A(Sc, Y - 1, X); v.yp = A(Sc, Y + 1, X); \
-    v.zm = A(Sm, Y, X); v.zp = A(Sp, Y, X);                                                          \
-    v.xpyp = A(Sc, Y + 1, X + 1); v.xmym = A(Sc, Y - 1, X - 1);                                      \
-    v.xpym = A(Sc, Y - 1, X + 1); v.xmyp = A(Sc, Y + 1, X - 1);                                      \
-    v.xpzp = A(Sp, Y, X + 1); v.xmzm = A(Sm, Y, X - 1); v.xpzm = A(Sm, Y, X + 1); v.xmzp = A(Sp, Y, X - 1); \
-    v.ypzp = A(Sp, Y + 1, X); v.ymzm = A(Sm, Y - 1, X); v.ypzm = A(Sm, Y + 1, X); v.ymzp = A(Sp, Y - 1, X);
-                    LOADNB(ve, AE0, sm, sc, sp)
-                    LOADNB(vp, AP2, sm, sc, sp)
-                    float Se;
-                    const float dq = dq_corr(ve, vp, a.c.a_ih4, Se);
-                    const float dQ = dQ_of(dq, rd_t[q], a.c);
-                    val = (Se - h2 * (dQ + rd_r[q] - cb)) * (1.0f / 6.0f);
-                }
-                AE1(sc, r, lx) = val;
-                AE1(sc, r, lb) = AE0(sc, Y, lb + 1);
-                AP1(sc, r, lx) = AP2(sc, Y, X);
-                AP1(sc, r, lb) = AP2(sc, Y, lb + 1);
-            }
-        }
-        __syncthreads();
-        if (p2 >= z0) {
-            const int sm = slot(p2 - 1), sc = slot(p2), sp = slot(p2 + 1);
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                int r, xb, xr;
-                if (!black_cell(q, p2, r, xb, xr)) continue;
-                const int gy = y0 + r;
-                if (gy >= g.n1) continue;
-                const int64_t rowoff = g.off0 + (int64_t)gy * g.sy + (int64_t)p2 * g.sz + x0;
-                const int X = xb + 1, Y = r + 1;
-                if (x0 + xb < g.n0) {
-                    NbT<float> ve, vp;
-                    LOADNB(ve, AE1, sm, sc, sp)
-                    LOADNB(vp, AP1, sm, sc, sp)
-#undef LOADNB
-                    float Se;
-                    const float dq = dq_corr(ve, vp, a.c.a_ih4, Se);
-                    const float dQ = dQ_of(dq, bk_t[q], a.c);
-                    a.eout[rowoff + xb] = (Se - h2 * (dQ + bk_r[q] - cb)) * (1.0f / 6.0f);
-                }
-                if (x0 + xr < g.n0) a.eout[rowoff + xr] = AE1(sc, Y, xr + 1);
-            }
-        }
-        if (pf2) {
-            store2(E0[slot(t + 1)], ne);
-            store2(PT2[slot(t + 1)], np);
-        }
-#pragma unroll
-        for (int q = 0; q < NR; ++q) { rd_t[q] = nrt[q]; rd_r[q] = nrr[q]; }
-#pragma unroll
-        for (int q = 0; q < NB; ++q) { bk_t[q] = nbt[q]; bk_r[q] = nbr[q]; }
-        __syncthreads();
-    }
-#undef AE0
-#undef AP2
-#undef AE1
-#undef AP1
-}
+    __device__ void out(int64_t i, float2 v) const { eout[i] = v.x; }
+};
 
 template <int TY, int DIR>
-__global__ void __launch_bounds__(NT) k_smooth_corr(CorrArgs a) {
+__global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth_corr(CorrArgs a) {
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % a.tiles_x;
     b /= a.tiles_x;
@@ -301,12 +121,13 @@ __global__ void __launch_bounds__(NT) k_smooth_corr(CorrArgs a) {
     const int ch = b / a.tiles_y;
     const int z0 = ch * a.zc;
     if (z0 >= a.g.n2) return;
-    corr_brick<TY, DIR>(a, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
+    const CorrK k(a, DIR == 0);
+    fused_sweep<TY, DIR, SNT>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
 }
 
 // persistent sweep over a (grid, tile x, tile y, z chunk) work list (Dirichlet batches)
 template <int TY>
-__global__ void __launch_bounds__(NT) k_smooth_corr_batch(CorrArgs proto, const Geom* __restrict__ geoms,
+__global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth_corr_batch(CorrArgs proto, const Geom* __restrict__ geoms,
                                                           const int4* __restrict__ items, int nitems) {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int4 w = items[it];
@@ -315,7 +136,8 @@ __global__ void __launch_bounds__(NT) k_smooth_corr_batch(CorrArgs proto, const 
         a.c.a_ih4 = proto.c.alpha / (float)(a.g.h * a.g.h * a.g.h * a.g.h);
         a.c.h2 = (float)(a.g.h * a.g.h);
         const int z0 = w.w * a.zc;
-        corr_brick<TY, 1>(a, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
+        const CorrK k(a, false);
+        fused_sweep<TY, 1, SNT>(k, a.g, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
     }
 }
 
@@ -1222,7 +1044,7 @@ __global__ void k_update_batch(const Geom* __restrict__ gs, const int2* __restri
 template <int TY, int DIR>
 static hipError_t corr_launch(const CorrArgs& a, hipStream_t s) {
     const int chunks = (a.g.n2 + a.zc - 1) / a.zc;
-    hipLaunchKernelGGL((k_smooth_corr<TY, DIR>), dim3(a.tiles_x * a.tiles_y * chunks), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_smooth_corr<TY, DIR>), dim3(a.tiles_x * a.tiles_y * chunks), dim3(SNT), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1382,11 +1204,11 @@ hipError_t launch_smooth_corr_batch(const CoefF& c, const float* ein, float* eou
     a.zc = cfg.zc > 0 ? cfg.zc : 16;
     const int nb = std::min(nitems, max_blocks);
     if (cfg.ty == 4)
-        hipLaunchKernelGGL(k_smooth_corr_batch<4>, dim3(nb), dim3(NT), 0, s, a, geoms, items, nitems);
+        hipLaunchKernelGGL(k_smooth_corr_batch<4>, dim3(nb), dim3(SNT), 0, s, a, geoms, items, nitems);
     else if (cfg.ty == 16)
-        hipLaunchKernelGGL(k_smooth_corr_batch<16>, dim3(nb), dim3(NT), 0, s, a, geoms, items, nitems);
+        hipLaunchKernelGGL(k_smooth_corr_batch<16>, dim3(nb), dim3(SNT), 0, s, a, geoms, items, nitems);
     else
-        hipLaunchKernelGGL(k_smooth_corr_batch<8>, dim3(nb), dim3(NT), 0, s, a, geoms, items, nitems);
+        hipLaunchKernelGGL(k_smooth_corr_batch<8>, dim3(nb), dim3(SNT), 0, s, a, geoms, items, nitems);
     return hipGetLastError();
 }
 
