@@ -33,13 +33,31 @@ static void cell_items(std::vector<int2>& out, int k, int64_t n) {
     for (int64_t s = 0; s < n; s += 256) out.push_back(make_int2(k, (int)s));
 }
 
-// Work list of the persistent smoother for the grids of each level that continue
-// below it.  The finest level uses the plan's (tuned) schedule; coarser levels
+// Work list of the persistent smoother on level l for schedule cfg (the grids of
+// the level that continue below it).
+hipError_t batch_set_level_cfg(Plan* P, int l, SmoothCfg cfg) {
+    BatchLevel& B = P->blev[l];
+    B.cfg = cfg;
+    std::vector<int4> items;
+    for (size_t k = 0; k < B.members.size(); ++k) {
+        if (B.coarsest[k]) continue;
+        const Geom& g = P->grids[B.members[k]].lev[l].g;
+        const int tx = (g.n0 + TX - 1) / TX, ty = (g.n1 + cfg.ty - 1) / cfg.ty;
+        const int tz = (g.n2 + cfg.zc - 1) / cfg.zc;
+        for (int c = 0; c < tz; ++c)
+            for (int y = 0; y < ty; ++y)
+                for (int x = 0; x < tx; ++x) items.push_back(make_int4((int)k, x, y, c));
+    }
+    B.nsitems = (int)items.size();
+    return upload(P, &B.d_sitems, items);
+}
+
+// Default work lists: the finest level uses the plan's schedule; coarser levels
 // shorten the z chunk, then the tile height, until the level has at least
 // MIN_TILED_BLOCKS items (or the shortest schedule).
 hipError_t batch_build_smooth_items(Plan* P) {
     for (size_t l = 0; l < P->blev.size(); ++l) {
-        BatchLevel& B = P->blev[l];
+        const BatchLevel& B = P->blev[l];
         auto count = [&](const SmoothCfg& c) {
             int64_t n = 0;
             for (size_t k = 0; k < B.members.size(); ++k) {
@@ -54,19 +72,7 @@ hipError_t batch_build_smooth_items(Plan* P) {
             while (cfg.zc > 2 && count(cfg) < MIN_TILED_BLOCKS) cfg.zc >>= 1;
             if (count(cfg) < MIN_TILED_BLOCKS && cfg.ty > 4) cfg.ty = 4;
         }
-        B.cfg = cfg;
-        std::vector<int4> items;
-        for (size_t k = 0; k < B.members.size(); ++k) {
-            if (B.coarsest[k]) continue;
-            const Geom& g = P->grids[B.members[k]].lev[l].g;
-            const int tx = (g.n0 + TX - 1) / TX, ty = (g.n1 + cfg.ty - 1) / cfg.ty;
-            const int tz = (g.n2 + cfg.zc - 1) / cfg.zc;
-            for (int c = 0; c < tz; ++c)
-                for (int y = 0; y < ty; ++y)
-                    for (int x = 0; x < tx; ++x) items.push_back(make_int4((int)k, x, y, c));
-        }
-        B.nsitems = (int)items.size();
-        CKE(upload(P, &B.d_sitems, items));
+        CKE(batch_set_level_cfg(P, (int)l, cfg));
     }
     return hipSuccess;
 }
@@ -358,6 +364,8 @@ hipError_t batch_outputs(Plan* P, double* phi) {
 }
 
 hipError_t batch_smooth_finest(Plan* P) { return P->mixed ? bsmooth_corr(P, 0) : bsmooth(P, 0); }
+
+hipError_t batch_smooth_level(Plan* P, int l) { return P->mixed ? bsmooth_corr(P, l) : bsmooth(P, l); }
 
 int batch_parity(const Plan* P) { return P->blev.empty() ? 0 : P->blev[0].cur; }
 

@@ -180,8 +180,7 @@ static const double* level_f(const Plan* P, const GridState& G, int l) {
 
 static hipError_t smooth_level(Plan* P, GridState& G, int l) {
     LevelBuf& L = G.lev[l];
-    // the finest level runs the plan's (tuned) schedule, coarser ones a shortened one
-    const SmoothCfg cfg = l == 0 ? P->cfg : level_cfg(L.g.n0, L.g.n1, L.g.n2, P->cfg);
+    const SmoothCfg cfg = level_schedule(P, l, L.g);
     hipError_t e = launch_smooth(L.g, P->coef, L.phi[L.cur], L.phi[L.cur ^ 1], L.delta,
                                  level_f(P, G, l), L.sc, cfg, P->stream);
     L.cur ^= 1;
@@ -191,6 +190,14 @@ static hipError_t smooth_level(Plan* P, GridState& G, int l) {
 }
 
 hipError_t smooth_level_public(Plan* P, GridState& G, int l) { return smooth_level(P, G, l); }
+
+// The finest level runs the plan's schedule; a coarser level its tuned one, else
+// the plan's schedule shortened by level_cfg.
+SmoothCfg level_schedule(const Plan* P, int l, const Geom& g) {
+    if (l == 0) return P->cfg;
+    if ((int)P->lcfg.size() > l && P->lcfg[l].ty > 0) return P->lcfg[l];
+    return level_cfg(g.n0, g.n1, g.n2, P->cfg);
+}
 
 static hipError_t vcycle(Plan* P, GridState& G, int l) {
     LevelBuf& L = G.lev[l];

@@ -71,6 +71,8 @@ struct CorrArgs {
 
 // FP32 correction policy of the fused sweep (brick.h): a cell holds (e, phi~),
 // so one 8-byte LDS read gives both neighbourhoods; sources are t0 and r.
+// ZERO_E: the input correction is identically zero and is not read.
+template <bool ZERO_E>
 struct CorrK {
     using Cell = float2;   // (e, phi~)
     struct Src {
@@ -88,7 +90,7 @@ struct CorrK {
         : ein(a.ein), eout(a.eout), pt(a.pt), t0(a.t0), r(a.r), c(a.c) {
         cb = periodic ? (float)a.sc->cbar : 0.0f;
     }
-    __device__ float2 cell(int64_t i) const { return make_float2(ein[i], pt[i]); }
+    __device__ float2 cell(int64_t i) const { return make_float2(ZERO_E ? 0.0f : ein[i], pt[i]); }
     __device__ float2 zero_cell() const { return make_float2(0.0f, 0.0f); }
     __device__ Src src(int64_t i) const { return Src{t0[i], r[i]}; }
     __device__ Src zero_src() const { return Src{1.0f, 0.0f}; }
@@ -112,7 +114,7 @@ struct CorrK {
     __device__ void out(int64_t i, float2 v) const { eout[i] = v.x; }
 };
 
-template <int TY, int DIR>
+template <int TY, int DIR, bool ZERO_E>
 __global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth_corr(CorrArgs a) {
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % a.tiles_x;
@@ -121,7 +123,7 @@ __global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth_corr(CorrArg
     const int ch = b / a.tiles_y;
     const int z0 = ch * a.zc;
     if (z0 >= a.g.n2) return;
-    const CorrK k(a, DIR == 0);
+    const CorrK<ZERO_E> k(a, DIR == 0);
     fused_sweep<TY, DIR, SNT>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
 }
 
@@ -136,7 +138,7 @@ __global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth_corr_batch(C
         a.c.a_ih4 = proto.c.alpha / (float)(a.g.h * a.g.h * a.g.h * a.g.h);
         a.c.h2 = (float)(a.g.h * a.g.h);
         const int z0 = w.w * a.zc;
-        const CorrK k(a, false);
+        const CorrK<false> k(a, false);
         fused_sweep<TY, 1, SNT>(k, a.g, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
     }
 }
@@ -670,13 +672,19 @@ struct CorrResArgs {
     const float* r;            // inner rhs (MODE 1) or R d_e (MODE 2)
     const LevelScalars* sc;    // inner cbar (MODE 1, periodic)
     float *ec, *eold_c, *rd_c; // MODE 1
+    float* ptc;                // MODE 1: restricted base state (may be null)
     float* rout;               // MODE 2
+    Coef c64;                  // MODE 2: FP64 coefficients of the base discriminant
+    const double* delta;       // MODE 2: density of this level
+    float* t0out;              // MODE 2: t0 of this level, computed here from phi~ and delta
     double* partials;
     int tiles_x, tiles_y, zc;
 };
 
 // MODE 1: inner residual d_e = Lap e - dQ(e) - r + cbar_e, reductions, R e -> ec, eold_c, R d_e -> rd_c
-// MODE 2: coarse inner rhs rout = Lap e - dQ(e) - rd, reductions of dQ and rout
+// MODE 2: coarse inner rhs rout = Lap e - dQ(e) - rd, reductions of dQ and rout; the
+//         level's t0 = +-sqrt|D0| of the base state is computed here (FP64 discriminant
+//         of phi~ and delta) and written for the smoother of this level
 template <int DIR, int MODE>
 __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
     constexpr int W1 = TX + 2, H1 = MTY + 2, NP1 = W1 * H1, NL1 = (NP1 + NT - 1) / NT;
@@ -743,14 +751,17 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
             }
     };
     auto slot = [](int z) { return (z + 3) % 3; };
-    auto src_fetch = [&](int t, float (&tt)[2], float (&rv)[2]) {
+    const double inv_h4_64 = 1.0 / (g.h * g.h * g.h * g.h);
+    auto src_fetch = [&](int t, float (&tt)[2], double (&dl)[2], float (&rv)[2]) {
 #pragma unroll
         for (int c2 = 0; c2 < 2; ++c2) {
             tt[c2] = 1.0f;
+            dl[c2] = 0.0;
             rv[c2] = 0.0f;
             if (!row_ok || xa + c2 >= g.n0 || t >= z1) continue;
             const int64_t gi = g.off0 + xa + c2 + (int64_t)gy * g.sy + (int64_t)t * g.sz;
-            tt[c2] = a.t0[gi];
+            if (MODE == 2) dl[c2] = a.delta[gi];
+            else tt[c2] = a.t0[gi];
             rv[c2] = a.r[gi];
         }
     };
@@ -762,16 +773,18 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
         }
     }
     float ctt[2], crv[2];
-    src_fetch(z0, ctt, crv);
+    double cdl[2];
+    src_fetch(z0, ctt, cdl, crv);
     __syncthreads();
-    float zs_e = 0.0f, zs_d = 0.0f;
+    float zs_e = 0.0f, zs_d = 0.0f, zs_p = 0.0f;
     for (int t = z0; t < z1; ++t) {
         float ne[NL1], np[NL1], ntt[2], nrv[2];
+        double ndl[2];
         const bool pf = t + 2 <= z1;
         if (pf) load_planes(t + 2, ne, np);
-        src_fetch(t + 1, ntt, nrv);
+        src_fetch(t + 1, ntt, ndl, nrv);
         const int sm = slot(t - 1), sc = slot(t), sp = slot(t + 1);
-        float esum = 0.0f, dsum = 0.0f;
+        float esum = 0.0f, dsum = 0.0f, psum = 0.0f;
 #pragma unroll
         for (int c2 = 0; c2 < 2; ++c2) {
             const int X = 2 * m + c2 + 1, Y = r + 1;
@@ -788,9 +801,20 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
             LNB(vp, PP)
 #undef LNB
             const float ecv = EE[sc][Y][X];
+            float t0c = ctt[c2];
+            if (MODE == 2) {
+                Nb vb;
+                vb.xm = vp.xm; vb.xp = vp.xp; vb.ym = vp.ym; vb.yp = vp.yp; vb.zm = vp.zm; vb.zp = vp.zp;
+                vb.xpyp = vp.xpyp; vb.xmym = vp.xmym; vb.xpym = vp.xpym; vb.xmyp = vp.xmyp;
+                vb.xpzp = vp.xpzp; vb.xmzm = vp.xmzm; vb.xpzm = vp.xpzm; vb.xmzp = vp.xmzp;
+                vb.ypzp = vp.ypzp; vb.ymzm = vp.ymzm; vb.ypzm = vp.ypzm; vb.ymzp = vp.ymzp;
+                const double D0 = base_discriminant(vb, cdl[c2], a.c64, inv_h4_64);
+                t0c = (float)(D0 >= 0.0 ? sqrt(D0) : -sqrt(-D0));
+                a.t0out[g.off0 + xa + c2 + (int64_t)gy * g.sy + (int64_t)t * g.sz] = t0c;
+            }
             float Se;
             const float dq = dq_corr(ve, vp, a.c.a_ih4, Se);
-            const float dQ = dQ_of(dq, ctt[c2], a.c);
+            const float dQ = dQ_of(dq, t0c, a.c);
             const float L = (Se - 6.0f * ecv) * inv_h2 - dQ;
             if (MODE == 2) {
                 const float rh = L - crv[c2];
@@ -806,14 +830,17 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
                 acc[R_NONFIN] += isfinite(d) ? 0.0 : 1.0;
                 esum += ecv;
                 dsum += d;
+                psum += PP[sc][Y][X];
             }
         }
         if (MODE == 1) {
             esum += __shfl_down(esum, 32, 64);
             dsum += __shfl_down(dsum, 32, 64);
+            psum += __shfl_down(psum, 32, 64);
             if ((t & 1) == 0) {
                 zs_e = esum;
                 zs_d = dsum;
+                zs_p = psum;
             } else if ((r & 1) == 0 && row_ok && xa < g.n0) {
                 const Geom& gc = a.gc;
                 const int64_t co = gc.off0 + (xa >> 1) + (int64_t)(gy >> 1) * gc.sy + (int64_t)(t >> 1) * gc.sz;
@@ -821,11 +848,13 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
                 a.ec[co] = re;
                 a.eold_c[co] = re;
                 a.rd_c[co] = 0.125f * (zs_d + dsum);
+                if (a.ptc) a.ptc[co] = 0.125f * (zs_p + psum);
             }
         }
         __syncthreads();
         if (pf) store_planes(slot(t + 2), ne, np);
         ctt[0] = ntt[0]; ctt[1] = ntt[1];
+        cdl[0] = ndl[0]; cdl[1] = ndl[1];
         crv[0] = nrv[0]; crv[1] = nrv[1];
         __syncthreads();
     }
@@ -1042,28 +1071,31 @@ __global__ void k_update_batch(const Geom* __restrict__ gs, const int2* __restri
 // launchers
 // ---------------------------------------------------------------------------
 template <int TY, int DIR>
-static hipError_t corr_launch(const CorrArgs& a, hipStream_t s) {
+static hipError_t corr_launch(const CorrArgs& a, bool zero_in, hipStream_t s) {
     const int chunks = (a.g.n2 + a.zc - 1) / a.zc;
-    hipLaunchKernelGGL((k_smooth_corr<TY, DIR>), dim3(a.tiles_x * a.tiles_y * chunks), dim3(SNT), 0, s, a);
+    if (zero_in)
+        hipLaunchKernelGGL((k_smooth_corr<TY, DIR, true>), dim3(a.tiles_x * a.tiles_y * chunks), dim3(SNT), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_smooth_corr<TY, DIR, false>), dim3(a.tiles_x * a.tiles_y * chunks), dim3(SNT), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, float* eout,
                               const float* pt, const float* t0, const float* r, const LevelScalars* sc,
-                              SmoothCfg cfg, hipStream_t s) {
+                              SmoothCfg cfg, hipStream_t s, bool zero_in) {
     CorrArgs a;
     a.g = g; a.c = c; a.ein = ein; a.eout = eout; a.pt = pt; a.t0 = t0; a.r = r; a.sc = sc;
     a.zc = cfg.zc > 0 ? cfg.zc : 16;
     a.tiles_x = (g.n0 + TX - 1) / TX;
     a.tiles_y = (g.n1 + cfg.ty - 1) / cfg.ty;
     if (g.dir) {
-        if (cfg.ty == 4) return corr_launch<4, 1>(a, s);
-        if (cfg.ty == 16) return corr_launch<16, 1>(a, s);
-        return corr_launch<8, 1>(a, s);
+        if (cfg.ty == 4) return corr_launch<4, 1>(a, zero_in, s);
+        if (cfg.ty == 16) return corr_launch<16, 1>(a, zero_in, s);
+        return corr_launch<8, 1>(a, zero_in, s);
     }
-    if (cfg.ty == 4) return corr_launch<4, 0>(a, s);
-    if (cfg.ty == 16) return corr_launch<16, 0>(a, s);
-    return corr_launch<8, 0>(a, s);
+    if (cfg.ty == 4) return corr_launch<4, 0>(a, zero_in, s);
+    if (cfg.ty == 16) return corr_launch<16, 0>(a, zero_in, s);
+    return corr_launch<8, 0>(a, zero_in, s);
 }
 
 static void corr_tiles(const Geom& g, int& tx, int& ty, int& zc, int& nb) {
@@ -1075,11 +1107,11 @@ static void corr_tiles(const Geom& g, int& tx, int& ty, int& zc, int& nb) {
 
 hipError_t launch_rr_corr(const Geom& gf, const Geom& gc, const CoefF& c, const float* e, const float* pt,
                           const float* t0, const float* r, const LevelScalars* sc, float* ec, float* eold_c,
-                          float* rd_c, double* partials, int* nblocks_out, hipStream_t s) {
+                          float* rd_c, float* ptc, double* partials, int* nblocks_out, hipStream_t s) {
     CorrResArgs a;
     std::memset(&a, 0, sizeof(a));
     a.g = gf; a.gc = gc; a.c = c; a.e = e; a.pt = pt; a.t0 = t0; a.r = r; a.sc = sc;
-    a.ec = ec; a.eold_c = eold_c; a.rd_c = rd_c; a.partials = partials;
+    a.ec = ec; a.eold_c = eold_c; a.rd_c = rd_c; a.ptc = ptc; a.partials = partials;
     int nb;
     corr_tiles(gf, a.tiles_x, a.tiles_y, a.zc, nb);
     *nblocks_out = nb;
@@ -1090,11 +1122,13 @@ hipError_t launch_rr_corr(const Geom& gf, const Geom& gc, const CoefF& c, const 
     return hipGetLastError();
 }
 
-hipError_t launch_fas_corr(const Geom& g, const CoefF& c, const float* e, const float* pt, const float* t0,
-                           const float* rd, float* r, double* partials, int* nblocks_out, hipStream_t s) {
+hipError_t launch_fas_corr(const Geom& g, const CoefF& c, const Coef& c64, const double* delta, const float* e,
+                           const float* pt, float* t0, const float* rd, float* r, double* partials,
+                           int* nblocks_out, hipStream_t s) {
     CorrResArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.g = g; a.c = c; a.e = e; a.pt = pt; a.t0 = t0; a.r = rd; a.rout = r; a.partials = partials;
+    a.g = g; a.c = c; a.c64 = c64; a.delta = delta; a.e = e; a.pt = pt; a.t0out = t0; a.r = rd; a.rout = r;
+    a.partials = partials;
     int nb;
     corr_tiles(g, a.tiles_x, a.tiles_y, a.zc, nb);
     *nblocks_out = nb;

@@ -55,19 +55,21 @@ hipError_t mixed_prepare(Plan* P) {
     return hipSuccess;
 }
 
-hipError_t smooth_corr_level(Plan* P, GridState& G, int l) {
+hipError_t smooth_corr_level(Plan* P, GridState& G, int l, bool zero_in) {
     LevelBuf& L = G.lev[l];
     const CoefF cf = make_coef_f(P->coef, L.g.h);
-    const SmoothCfg cfg = l == 0 ? P->cfg : level_cfg(L.g.n0, L.g.n1, L.g.n2, P->cfg);
+    const SmoothCfg cfg = level_schedule(P, l, L.g);
     hipError_t e = launch_smooth_corr(L.g, cf, L.e[L.ecur], L.e[L.ecur ^ 1], L.pt, L.t0, L.r, L.scf, cfg,
-                                      P->stream);
+                                      P->stream, zero_in);
     L.ecur ^= 1;
     P->cell_updates += L.g.ncell;
     if (l == 0) P->finest_sweeps += 1;
     return e;
 }
 
-static hipError_t inner_vcycle(Plan* P, GridState& G, int l) {
+// zero_e: the level's correction is identically zero on entry (finest level,
+// first inner cycle of an outer iteration); the first sweep then reads no e.
+static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e) {
     LevelBuf& L = G.lev[l];
     const int last = (int)G.lev.size() - 1;
     const CoefF cf = make_coef_f(P->coef, L.g.h);
@@ -78,22 +80,25 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l) {
         return e;
     }
     for (int s = 0; s < P->nu1; ++s)
-        if ((e = smooth_corr_level(P, G, l)) != hipSuccess) return e;
+        if ((e = smooth_corr_level(P, G, l, zero_e && s == 0)) != hipSuccess) return e;
     LevelBuf& C = G.lev[l + 1];
     const CoefF cc = make_coef_f(P->coef, C.g.h);
     C.ecur = 0;
     int nb = 0;
     const int periodic = L.g.dir ? 0 : 1;
-    if ((e = launch_rr_corr(L.g, C.g, cf, L.e[L.ecur], L.pt, L.t0, L.r, L.scf, C.e[0], C.eold, C.rdf,
+    // restriction of e and d_e; the coarse base state phi~ is restricted in the same pass
+    if ((e = launch_rr_corr(L.g, C.g, cf, L.e[L.ecur], L.pt, L.t0, L.r, L.scf, C.e[0], C.eold, C.rdf, C.pt,
                             P->partials, &nb, P->stream)) != hipSuccess)
         return e;
     if ((e = launch_finalize(P->partials, nb, L.g.ncell, periodic, 0, L.scf, nullptr, P->stream)) != hipSuccess)
         return e;
-    if ((e = launch_fas_corr(C.g, cc, C.e[0], C.pt, C.t0, C.rdf, C.r, P->partials, &nb, P->stream)) != hipSuccess)
+    // coarse rhs; also the coarse t0 (FP64 discriminant of the restricted base state)
+    if ((e = launch_fas_corr(C.g, cc, P->coef, C.delta, C.e[0], C.pt, C.t0, C.rdf, C.r, P->partials, &nb,
+                             P->stream)) != hipSuccess)
         return e;
     if ((e = launch_finalize(P->partials, nb, C.g.ncell, periodic, 1, C.scf, nullptr, P->stream)) != hipSuccess)
         return e;
-    if ((e = inner_vcycle(P, G, l + 1)) != hipSuccess) return e;
+    if ((e = inner_vcycle(P, G, l + 1, false)) != hipSuccess) return e;
     if ((e = launch_prolong_corr(L.g, C.g, L.e[L.ecur], C.e[C.ecur], C.eold, P->stream)) != hipSuccess) return e;
     for (int s = 0; s < P->nu2; ++s)
         if ((e = smooth_corr_level(P, G, l)) != hipSuccess) return e;
@@ -136,17 +141,13 @@ hipError_t mixed_initial_pass(Plan* P) {
 hipError_t enqueue_outer(Plan* P) {
     hipError_t e;
     for (auto& G : P->grids) {
-        // coarse base states of the inner problem
-        for (size_t l = 1; l < G.lev.size(); ++l) {
-            LevelBuf& F = G.lev[l - 1];
-            LevelBuf& C = G.lev[l];
-            if ((e = launch_base_restrict(F.g, C.g, F.pt, C.pt, P->stream)) != hipSuccess) return e;
-            if ((e = launch_base_t0(C.g, P->coef, C.pt, C.delta, C.t0, P->stream)) != hipSuccess) return e;
-        }
+        // the coarse base states (phi~, t0) of the inner problem are produced by the
+        // restriction and coarse-rhs passes of the inner cycle's descent
         LevelBuf& L0 = G.lev[0];
         L0.ecur = 0;
-        if ((e = launch_fill_f(L0.e[0], L0.g.nstore, 0.0f, P->stream)) != hipSuccess) return e;
-        if ((e = inner_vcycle(P, G, 0)) != hipSuccess) return e;
+        const bool zero_e = P->nu1 > 0 && G.lev.size() > 1;
+        if (!zero_e && (e = launch_fill_f(L0.e[0], L0.g.nstore, 0.0f, P->stream)) != hipSuccess) return e;
+        if ((e = inner_vcycle(P, G, 0, zero_e)) != hipSuccess) return e;
         if ((e = cast_pass(P, G, true)) != hipSuccess) return e;
     }
     return norms_to_host(P);

@@ -132,14 +132,19 @@ hipError_t launch_interior_fill(const double* parent, int np0, int np1, int np2,
                                 double h, int o0, int o1, int o2, double* phi, hipStream_t s);
 
 // ---- mixed path (kernels_mixed.hip) ---------------------------------------
+// zero_in: the input correction is identically zero (first sweep of an inner
+// cycle); ein is then not read.
 hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, float* eout,
                               const float* pt, const float* t0, const float* r, const LevelScalars* sc,
-                              SmoothCfg cfg, hipStream_t s);
+                              SmoothCfg cfg, hipStream_t s, bool zero_in = false);
+// ptc (may be null): receives the restricted base state phi~ of the coarse level
 hipError_t launch_rr_corr(const Geom& gf, const Geom& gc, const CoefF& c, const float* e, const float* pt,
                           const float* t0, const float* r, const LevelScalars* sc, float* ec, float* eold_c,
-                          float* rd_c, double* partials, int* nblocks_out, hipStream_t s);
-hipError_t launch_fas_corr(const Geom& g, const CoefF& c, const float* e, const float* pt, const float* t0,
-                           const float* rd, float* r, double* partials, int* nblocks_out, hipStream_t s);
+                          float* rd_c, float* ptc, double* partials, int* nblocks_out, hipStream_t s);
+// also computes and writes the level's t0 from phi~ and delta (FP64 discriminant)
+hipError_t launch_fas_corr(const Geom& g, const CoefF& c, const Coef& c64, const double* delta, const float* e,
+                           const float* pt, float* t0, const float* rd, float* r, double* partials,
+                           int* nblocks_out, hipStream_t s);
 hipError_t launch_prolong_corr(const Geom& gf, const Geom& gc, float* ef, const float* ec, const float* eold_c,
                                hipStream_t s);
 hipError_t launch_coarse_corr(const Geom& g, const CoefF& c, float* e, const float* pt, const float* t0,

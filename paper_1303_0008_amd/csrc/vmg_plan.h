@@ -73,7 +73,8 @@ struct Plan {
     Coef coef;
     hipStream_t stream = nullptr;
     hipStream_t own_stream = nullptr;      // created when the caller passes stream 0
-    SmoothCfg cfg;
+    SmoothCfg cfg;                         // finest-level schedule of the fused sweep
+    std::vector<SmoothCfg> lcfg;           // tuned schedules of levels >= 1 (empty: level_cfg rule)
     int nu1 = 2, nu2 = 2, ncoarse = 40;
     bool periodic = true;
     bool mixed = false;
@@ -88,8 +89,8 @@ struct Plan {
     std::vector<void*> allocs;
     // batched Dirichlet plans
     bool tuned_from_cache = false;
-    struct TuneEntry { SmoothCfg cfg; double us; };
-    std::vector<TuneEntry> tune_log;       // autotuner timings (finest-level sweep, us)
+    struct TuneEntry { int level; SmoothCfg cfg; double us; };
+    std::vector<TuneEntry> tune_log;       // autotuner timings (one sweep of a level, us)
     bool batched = false;
     std::vector<BatchLevel> blev;
     int64_t* d_uoff = nullptr;       // caller offsets of each grid's cells
@@ -106,10 +107,16 @@ vmg_status alloc_mixed(Plan* P);
 hipError_t enqueue_outer(Plan* P);          // one mixed-precision outer iteration (+ norms to host)
 hipError_t mixed_initial_pass(Plan* P);     // cast pass of the initial guess (+ norms to host)
 hipError_t mixed_prepare(Plan* P);          // per-solve set-up of the FP32 ghost shells
-hipError_t smooth_corr_level(Plan* P, GridState& G, int l);
+hipError_t smooth_corr_level(Plan* P, GridState& G, int l, bool zero_in = false);
 vmg_status build_batch(Plan* P);
 vmg_status autotune(Plan* P);
 hipError_t smooth_level_public(Plan* P, GridState& G, int l);
+// schedule of the fused sweep on level l of a single-grid (periodic) plan
+SmoothCfg level_schedule(const Plan* P, int l, const Geom& g);
+// batched plans: rebuild the persistent smoother's work list of level l for cfg;
+// one sweep of every grid on level l
+hipError_t batch_set_level_cfg(Plan* P, int l, SmoothCfg cfg);
+hipError_t batch_smooth_level(Plan* P, int l);
 int64_t batch_partials_needed(const Plan* P);
 hipError_t batch_build_smooth_items(Plan* P);
 hipError_t batch_enqueue_iteration(Plan* P);
