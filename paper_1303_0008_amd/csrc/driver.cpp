@@ -89,7 +89,7 @@ vmg_status build_plan(Plan* P, const vmg_grid* grids, int n_grids, const vmg_par
     P->nu1 = p->nu1;
     P->nu2 = p->nu2;
     if (P->nu1 == 0 && P->nu2 == 0) { P->nu1 = 2; P->nu2 = 2; }
-    P->ncoarse = 20;
+    P->ncoarse = 8;
     P->cfg.ty = 8;
     P->cfg.zc = 16;
     P->periodic = grids[0].bc == VMG_PERIODIC;
@@ -199,10 +199,41 @@ SmoothCfg level_schedule(const Plan* P, int l, const Geom& g) {
     return level_cfg(g.n0, g.n1, g.n2, P->cfg);
 }
 
+// First level (below the finest) at which the periodic coarse tail takes over,
+// or -1 when the plan does not use it.
+int tail_level(const Plan* P, const GridState& G) {
+    if (!P->use_tail || G.lev.empty() || G.lev[0].g.dir) return -1;
+    const int last = (int)G.lev.size() - 1;
+    for (int l = 1; l <= last; ++l)
+        if (G.lev[l].g.ncell <= TAIL_CELLS) return last - l + 1 <= TAIL_LEVELS ? l : -1;
+    return -1;
+}
+
+static hipError_t tail_cycle(Plan* P, GridState& G, int l) {
+    const int last = (int)G.lev.size() - 1;
+    TailArgs a;
+    a.nlev = last - l + 1;
+    for (int q = 0; q < a.nlev; ++q) {
+        const LevelBuf& T = G.lev[l + q];
+        a.n[q][0] = T.g.n0; a.n[q][1] = T.g.n1; a.n[q][2] = T.g.n2;
+        a.h[q] = T.g.h;
+        a.delta[q] = T.delta;
+        P->cell_updates += (int64_t)(q == a.nlev - 1 ? P->ncoarse : P->nu1 + P->nu2) * T.g.ncell;
+    }
+    LevelBuf& L = G.lev[l];
+    a.phi = L.phi[L.cur];
+    a.f = level_f(P, G, l);
+    a.sc = L.sc;
+    a.c = P->coef;
+    a.nu1 = P->nu1; a.nu2 = P->nu2; a.ncoarse = P->ncoarse;
+    return launch_tail(a, P->stream);
+}
+
 static hipError_t vcycle(Plan* P, GridState& G, int l) {
     LevelBuf& L = G.lev[l];
     const int last = (int)G.lev.size() - 1;
     hipError_t e;
+    if (l > 0 && l == tail_level(P, G)) return tail_cycle(P, G, l);
     if (l == last) {
         e = launch_coarse_solve(L.g, P->coef, L.phi[L.cur], L.delta, level_f(P, G, l), L.sc,
                                 P->ncoarse, P->stream);

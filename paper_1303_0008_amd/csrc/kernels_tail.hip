@@ -1,0 +1,267 @@
+// Coarse tail of a periodic V-cycle (Sec. III.C): every level with at most
+// TAIL_CELLS cells, down to the coarsest, handled by one workgroup with all of
+// those levels' arrays in LDS.  On these grids a separate launch per step costs
+// more than the step itself; here the whole sub-cycle is one launch.
+//
+// The arithmetic is the multi-kernel V-cycle's, step for step:
+//   * fused red-black sweep with snapshot semantics (red from the old state,
+//     black from the red-updated one), in place: each colour is computed into
+//     registers, then written after a barrier;
+//   * residual d = L(phi) - f + cbar, 8-child averages of phi and d, then
+//     cbar <- (sum f + sum Q) / N for the level's later sweeps;
+//   * coarse rhs f^H = L^H(R phi) - R d and cbar^H = (sum f^H + sum Q^H) / N^H;
+//   * coarsest level: cbar from the current sum of Q before every sweep;
+//   * cell-centred trilinear prolongation of phi^H - R phi (periodic wrap).
+// Reductions run in a fixed order, so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace vmg {
+
+namespace {
+
+constexpr int TAIL_NT = 512;
+constexpr int TAIL_POOL = 3 * TAIL_CELLS + 4 * (TAIL_CELLS / 8 + TAIL_CELLS / 64 + TAIL_CELLS / 512 + 1);
+
+__device__ __forceinline__ int tw(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+struct TLev {
+    int n0, n1, n2, N;
+    double h2, inv_h2, inv_h4;
+    double *phi, *old, *f, *del;   // LDS, x fastest, unpadded
+};
+
+__device__ __forceinline__ void tail_decode(const TLev& L, int e, int& i, int& j, int& k) {
+    i = e % L.n0;
+    const int r = e / L.n0;
+    j = r % L.n1;
+    k = r / L.n1;
+}
+
+__device__ __forceinline__ int tail_idx(const TLev& L, int i, int j, int k) {
+    return (tw(k, L.n2) * L.n1 + tw(j, L.n1)) * L.n0 + tw(i, L.n0);
+}
+
+template <typename T>
+__device__ __forceinline__ void tail_gather(const TLev& L, const T* u, int i, int j, int k, NbT<T>& v) {
+    v.xm = u[tail_idx(L, i - 1, j, k)];         v.xp = u[tail_idx(L, i + 1, j, k)];
+    v.ym = u[tail_idx(L, i, j - 1, k)];         v.yp = u[tail_idx(L, i, j + 1, k)];
+    v.zm = u[tail_idx(L, i, j, k - 1)];         v.zp = u[tail_idx(L, i, j, k + 1)];
+    v.xpyp = u[tail_idx(L, i + 1, j + 1, k)];   v.xmym = u[tail_idx(L, i - 1, j - 1, k)];
+    v.xpym = u[tail_idx(L, i + 1, j - 1, k)];   v.xmyp = u[tail_idx(L, i - 1, j + 1, k)];
+    v.xpzp = u[tail_idx(L, i + 1, j, k + 1)];   v.xmzm = u[tail_idx(L, i - 1, j, k - 1)];
+    v.xpzm = u[tail_idx(L, i + 1, j, k - 1)];   v.xmzp = u[tail_idx(L, i - 1, j, k + 1)];
+    v.ypzp = u[tail_idx(L, i, j + 1, k + 1)];   v.ymzm = u[tail_idx(L, i, j - 1, k - 1)];
+    v.ypzm = u[tail_idx(L, i, j + 1, k - 1)];   v.ymzp = u[tail_idx(L, i, j - 1, k + 1)];
+}
+
+// Block-wide sums of two values in a fixed order; every thread gets the totals.
+__device__ __forceinline__ void tail_sum2(double a, double b, double& A, double& B, double (*red)[2]) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w][0] = a;
+        red[w][1] = b;
+    }
+    __syncthreads();
+    A = 0.0;
+    B = 0.0;
+    for (int q = 0; q < TAIL_NT / 64; ++q) {
+        A += red[q][0];
+        B += red[q][1];
+    }
+    __syncthreads();
+}
+
+// One red-black sweep of level L: each colour's new values go to the LDS
+// scratch plane tmp first and are copied into phi after a barrier, so every
+// cell of a colour is computed from the same state.
+__device__ void tail_sweep(const TLev& L, double* tmp, const Coef& c, double cb) {
+    const int tid = threadIdx.x;
+    for (int colour = 0; colour < 2; ++colour) {
+        for (int e = tid; e < L.N; e += TAIL_NT) {
+            int i, j, k;
+            tail_decode(L, e, i, j, k);
+            if (((i + j + k) & 1) != colour) continue;
+            Nb v;
+            tail_gather(L, L.phi, i, j, k, v);
+            double S;
+            bool gd;
+            const double Q = nl_root(v, L.del[e], c, L.inv_h4, S, gd);
+            tmp[e] = (S - L.h2 * (Q + L.f[e] - cb)) * (1.0 / 6.0);
+        }
+        __syncthreads();
+        for (int e = tid; e < L.N; e += TAIL_NT) {
+            int i, j, k;
+            tail_decode(L, e, i, j, k);
+            if (((i + j + k) & 1) == colour) L.phi[e] = tmp[e];
+        }
+        __syncthreads();
+    }
+}
+
+// Descriptor of tail level l: sizes from the arguments, arrays carved out of
+// the LDS pool in level order (phi, f, delta, and phiold below the top).  Built
+// on the fly so that nothing is indexed by a run-time level in private memory.
+__device__ __forceinline__ TLev tail_level(const TailArgs& a, double* pool, int l) {
+    int off = 0;
+    for (int q = 0; q < l; ++q) off += (q == 0 ? 3 : 4) * a.n[q][0] * a.n[q][1] * a.n[q][2];
+    TLev T;
+    T.n0 = a.n[l][0];
+    T.n1 = a.n[l][1];
+    T.n2 = a.n[l][2];
+    T.N = T.n0 * T.n1 * T.n2;
+    T.h2 = a.h[l] * a.h[l];
+    T.inv_h2 = 1.0 / T.h2;
+    T.inv_h4 = T.inv_h2 * T.inv_h2;
+    T.phi = pool + off;
+    T.f = T.phi + T.N;
+    T.del = T.f + T.N;
+    T.old = l > 0 ? T.del + T.N : nullptr;
+    return T;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(TAIL_NT) k_tail(TailArgs a) {
+    __shared__ double pool[TAIL_POOL];
+    __shared__ double tmp[TAIL_CELLS];
+    __shared__ double red[TAIL_NT / 64][2];
+    __shared__ double cbar[TAIL_LEVELS];
+    const int tid = threadIdx.x;
+    const int nl = a.nlev;
+    {
+        const TLev T = tail_level(a, pool, 0);
+        for (int e = tid; e < T.N; e += TAIL_NT) {
+            T.phi[e] = a.phi[e];
+            T.f[e] = a.f ? a.f[e] : 0.0;
+        }
+    }
+    for (int l = 0; l < nl; ++l) {
+        const TLev T = tail_level(a, pool, l);
+        for (int e = tid; e < T.N; e += TAIL_NT) T.del[e] = a.delta[l][e];
+    }
+    if (tid == 0) cbar[0] = a.sc->cbar;
+    __syncthreads();
+    const int last = nl - 1;
+    // ---- descent ------------------------------------------------------------
+    for (int l = 0; l < last; ++l) {
+        const TLev F = tail_level(a, pool, l);
+        const TLev C = tail_level(a, pool, l + 1);
+        for (int s = 0; s < a.nu1; ++s) tail_sweep(F, tmp, a.c, cbar[l]);
+        // residual, restriction of phi and d (R d is kept as -R d in f^H)
+        double sq = 0.0, sf = 0.0;
+        for (int e = tid; e < C.N; e += TAIL_NT) {
+            int I, J, K;
+            tail_decode(C, e, I, J, K);
+            double sp = 0.0, sd = 0.0;
+#pragma unroll 1
+            for (int m = 0; m < 8; ++m) {
+                const int i = 2 * I + (m & 1), j = 2 * J + ((m >> 1) & 1), k = 2 * K + (m >> 2);
+                const int fe = (k * F.n1 + j) * F.n0 + i;
+                Nb v;
+                tail_gather(F, F.phi, i, j, k, v);
+                double S;
+                bool gd;
+                const double Q = nl_root(v, F.del[fe], a.c, F.inv_h4, S, gd);
+                const double pc = F.phi[fe];
+                sd += (S - 6.0 * pc) * F.inv_h2 - Q - F.f[fe] + cbar[l];
+                sp += pc;
+                sq += Q;
+                sf += F.f[fe];
+            }
+            C.phi[e] = 0.125 * sp;
+            C.old[e] = 0.125 * sp;
+            C.f[e] = -0.125 * sd;
+        }
+        double SQ, SF;
+        tail_sum2(sq, sf, SQ, SF, red);   // also orders the restriction before the rhs
+        if (tid == 0) cbar[l] = (SF + SQ) / (double)F.N;
+        // coarse rhs f^H = L^H(R phi) - R d
+        sq = 0.0;
+        sf = 0.0;
+        for (int e = tid; e < C.N; e += TAIL_NT) {
+            int I, J, K;
+            tail_decode(C, e, I, J, K);
+            Nb v;
+            tail_gather(C, C.phi, I, J, K, v);
+            double S;
+            bool gd;
+            const double Q = nl_root(v, C.del[e], a.c, C.inv_h4, S, gd);
+            const double fh = (S - 6.0 * C.phi[e]) * C.inv_h2 - Q + C.f[e];
+            C.f[e] = fh;
+            sq += Q;
+            sf += fh;
+        }
+        tail_sum2(sq, sf, SQ, SF, red);
+        if (tid == 0) cbar[l + 1] = (SF + SQ) / (double)C.N;
+        __syncthreads();
+    }
+    // ---- coarsest level: cbar from the current sum of Q before every sweep ---
+    {
+        const TLev C = tail_level(a, pool, last);
+        double sf = 0.0, dummy = 0.0, SF, D;
+        for (int e = tid; e < C.N; e += TAIL_NT) sf += C.f[e];
+        tail_sum2(sf, dummy, SF, D, red);
+        for (int s = 0; s < a.ncoarse; ++s) {
+            double sq = 0.0, SQ;
+            for (int e = tid; e < C.N; e += TAIL_NT) {
+                int i, j, k;
+                tail_decode(C, e, i, j, k);
+                Nb v;
+                tail_gather(C, C.phi, i, j, k, v);
+                double S;
+                bool gd;
+                sq += nl_root(v, C.del[e], a.c, C.inv_h4, S, gd);
+            }
+            tail_sum2(sq, dummy, SQ, D, red);
+            tail_sweep(C, tmp, a.c, (SF + SQ) / (double)C.N);
+        }
+    }
+    // ---- ascent: prolongation of the correction, post-smoothing -------------
+    for (int l = last - 1; l >= 0; --l) {
+        const TLev F = tail_level(a, pool, l);
+        const TLev C = tail_level(a, pool, l + 1);
+        for (int e = tid; e < F.N; e += TAIL_NT) {
+            int i, j, k;
+            tail_decode(F, e, i, j, k);
+            const int I = i >> 1, J = j >> 1, K = k >> 1;
+            const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+            double acc = 0.0;
+            for (int m = 0; m < 8; ++m) {
+                const int ai = m & 1, aj = (m >> 1) & 1, ak = m >> 2;
+                const double w = (ai ? 0.25 : 0.75) * (aj ? 0.25 : 0.75) * (ak ? 0.25 : 0.75);
+                const int ci = tail_idx(C, I + ai * si, J + aj * sj, K + ak * sk);
+                acc += w * (C.phi[ci] - C.old[ci]);
+            }
+            F.phi[e] += acc;
+        }
+        __syncthreads();
+        for (int s = 0; s < a.nu2; ++s) tail_sweep(F, tmp, a.c, cbar[l]);
+    }
+    {
+        const TLev T = tail_level(a, pool, 0);
+        for (int e = tid; e < T.N; e += TAIL_NT) a.phi[e] = T.phi[e];
+    }
+    if (tid == 0) a.sc->cbar = cbar[0];
+}
+
+hipError_t launch_tail(const TailArgs& a, hipStream_t s) {
+    if (a.nlev < 1 || a.nlev > TAIL_LEVELS) return hipErrorInvalidValue;
+    int64_t need = 0;
+    for (int l = 0; l < a.nlev; ++l) {
+        const int64_t N = (int64_t)a.n[l][0] * a.n[l][1] * a.n[l][2];
+        if (N > TAIL_CELLS || a.n[l][0] < 1 || a.n[l][1] < 1 || a.n[l][2] < 1) return hipErrorInvalidValue;
+        if (l > 0)
+            for (int d = 0; d < 3; ++d)
+                if (2 * a.n[l][d] != a.n[l - 1][d]) return hipErrorInvalidValue;
+        need += (l == 0 ? 3 : 4) * N;
+    }
+    if (need > TAIL_POOL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tail, dim3(1), dim3(TAIL_NT), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace vmg

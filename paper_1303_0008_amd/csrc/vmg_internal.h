@@ -90,6 +90,24 @@ inline SmoothCfg level_cfg(int n0, int n1, int n2, SmoothCfg c) {
     return c;
 }
 
+// ---- coarse tail (kernels_tail.hip) ----------------------------------------
+// Periodic levels with at most TAIL_CELLS cells, down to the coarsest, in one
+// single-workgroup launch (all arrays in LDS).
+constexpr int TAIL_CELLS = 512;
+constexpr int TAIL_LEVELS = 6;
+struct TailArgs {
+    int nlev;                           // levels in the tail; [0] is its top level
+    int n[TAIL_LEVELS][3];
+    double h[TAIL_LEVELS];
+    const double* delta[TAIL_LEVELS];   // density of each level (device, x fastest)
+    double* phi;                        // top-level state (in/out)
+    const double* f;                    // top-level FAS rhs (may be null: zero)
+    LevelScalars* sc;                   // top-level cbar (in/out)
+    Coef c;
+    int nu1, nu2, ncoarse;
+};
+hipError_t launch_tail(const TailArgs& a, hipStream_t s);
+
 // ---- launchers (kernels.hip) --------------------------------------------
 hipError_t launch_smooth(const Geom& g, const Coef& c, const double* pin, double* pout,
                          const double* delta, const double* f, const LevelScalars* sc,

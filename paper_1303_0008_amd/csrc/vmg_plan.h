@@ -76,6 +76,7 @@ struct Plan {
     SmoothCfg cfg;                         // finest-level schedule of the fused sweep
     std::vector<SmoothCfg> lcfg;           // tuned schedules of levels >= 1 (empty: level_cfg rule)
     int nu1 = 2, nu2 = 2, ncoarse = 40;
+    bool use_tail = true;                  // periodic coarse levels <= TAIL_CELLS in one launch
     bool periodic = true;
     bool mixed = false;
     bool has_source = false;
