@@ -16,8 +16,8 @@ write phi) divided by its average duration, timed here with HIP events around
 back-to-back launches on the plan's stream.
 
 ``cpu_baseline`` times the CPU oracle (plain FP64 C, one thread) on a bounded
-sample of the same workload: one lexicographic Newton-Gauss-Seidel sweep over
-the full 256^3 grid.
+sample of the same workload: five lexicographic Newton-Gauss-Seidel sweeps
+over the full 256^3 grid.
 """
 from __future__ import annotations
 
@@ -33,6 +33,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "zeldovich256"
+# Schedules the autotuner chose on MI355X for this workload (tile height and z chunk
+# per level); the library re-tunes any plan whose key is missing from the file.
+TUNE_CACHE = os.path.join(ROOT, "paper_1303_0008_amd", "tune_gfx950.txt")
 
 
 def log(*a):
@@ -41,16 +44,16 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("device_common.h", "kernels.hip", "kernels_mixed.hip"):
+    for f in ("device_common.h", "brick.h", "kernels.hip", "kernels_mixed.hip"):
         p = os.path.join(ROOT, "paper_1303_0008_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(name):
+def load_traffic(name, kernel):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source; otherwise None."""
+    taken on the current kernel source and the same instantiation; otherwise None."""
     p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
@@ -58,7 +61,7 @@ def load_traffic(name):
         d = json.load(open(p))
     except Exception:
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != kernel:
         return None
     return d.get("bytes_per_launch")
 
@@ -96,16 +99,26 @@ def time_smoother(torch, plan, stream, launches):
 
 
 COPY_BYTES = 256 << 20       # calibration copy: 256 MiB read + 256 MiB written
-FINEST = {"fp64": ("k_smooth<8, 0, false>", 24), "mixed": ("k_smooth_corr<8, 0>", 20)}
+# finest-level sweep of each precision: kernel name prefix / suffix (the tile height
+# between them is the autotuner's choice) and algorithmic bytes per cell
+FINEST = {"fp64": ("k_smooth<", ", 0, false>", 24), "mixed": ("k_smooth_corr<", ", 0, false>", 20)}
 
 
-def traffic_probe(torch, V, delta, w, launches=10):
+def finest_kernel(name, tile_y):
+    pre, post, _ = FINEST[name]
+    return f"{pre}{tile_y}{post}"
+
+
+PROBE_SWEEPS = 10
+
+
+def traffic_probe(torch, V, delta, w, launches=PROBE_SWEEPS):
     """Kernels for the HBM counter runs: finest-level sweeps of both precisions on
     a solved state, then a plain device copy of COPY_BYTES (calibration)."""
     stream = torch.cuda.Stream()
     for prec in (V.FP64, V.MIXED):
-        plan = V.Plan([V.make_grid(w["n"])], V.make_params(w["alpha"], w["kappa"], w["tol"], 100, prec),
-                      stream=stream)
+        plan = V.Plan([V.make_grid(w["n"])],
+                      V.make_params(w["alpha"], w["kappa"], w["tol"], 100, prec, flags=V.AUTOTUNE), stream=stream)
         phi = torch.zeros_like(delta)
         with torch.cuda.stream(stream):
             plan.solve(delta, phi)
@@ -150,18 +163,23 @@ def traffic_from(fetch_dir, write_dir, n):
         copies = [float(r["Counter_Value"]) for r in tail]
         # counter KiB -> bytes, times the factor that makes the copy read/write COPY_BYTES
         scale = COPY_BYTES / (1024.0 * statistics.median(copies))
-        for name, (kern, _) in FINEST.items():
-            vals = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"].startswith("void vmg::" + kern)
-                    and int(r["Grid_Size"]) >= 2048 * 256]
-            if not vals:
-                raise SystemExit(f"{counter}: no {kern} launches")
-            per.setdefault(name, {})[counter] = {"kib_per_launch_median": statistics.median(vals),
+        for name, (pre, post, _) in FINEST.items():
+            # the probe's closing finest-level sweeps (tuned schedule): the last
+            # PROBE_SWEEPS launches of the precision's sweep kernels, in dispatch order
+            cand = [r for r in rows if r["Kernel_Name"].startswith("void vmg::" + pre)
+                    and r["Kernel_Name"].split("(")[0].endswith(post)][-PROBE_SWEEPS:]
+            kern = cand[-1]["Kernel_Name"].split("(")[0].replace("void vmg::", "") if cand else None
+            if len(cand) < PROBE_SWEEPS or any(not r["Kernel_Name"].startswith("void vmg::" + kern) for r in cand):
+                raise SystemExit(f"{counter}: the closing {pre}..{post} sweeps were not found")
+            vals = [float(r["Counter_Value"]) for r in cand]
+            per.setdefault(name, {})[counter] = {"kernel": kern, "kib_per_launch_median": statistics.median(vals),
                                                   "launches": len(vals), "copy_kib": statistics.median(copies),
                                                   "calibration_factor": scale,
                                                   "bytes_per_launch": statistics.median(vals) * 1024.0 * scale}
-    for name, (kern, bpc) in FINEST.items():
+    for name, (_, _, bpc) in FINEST.items():
         d = per[name]
-        out = {"kernel": kern, "workload": f"{WORKLOAD} ({n}^3)", "kernel_source_hash": kernel_source_hash(),
+        out = {"kernel": d["FETCH_SIZE"]["kernel"], "workload": f"{WORKLOAD} ({n}^3)",
+               "kernel_source_hash": kernel_source_hash(),
                "algorithmic_bytes_per_launch": bpc * ncell,
                "fetch": d["FETCH_SIZE"], "write": d["WRITE_SIZE"],
                "bytes_per_launch": d["FETCH_SIZE"]["bytes_per_launch"] + d["WRITE_SIZE"]["bytes_per_launch"]}
@@ -173,17 +191,17 @@ def traffic_from(fetch_dir, write_dir, n):
             f"({out['ratio_to_algorithmic']:.2f} x algorithmic) -> {p}")
 
 
-def cpu_baseline(delta, w):
+def cpu_baseline(delta, w, sweeps=5):
     from oracle import oracle as O
     import numpy as np
     phi = np.zeros_like(delta)
     t0 = time.perf_counter()
-    O.relax(delta, phi, w["alpha"], w["kappa"], 1)
+    O.relax(delta, phi, w["alpha"], w["kappa"], sweeps)
     dt = time.perf_counter() - t0
-    cells = delta.size
+    cells = delta.size * sweeps
     return {"value": cells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one lexicographic Newton-Gauss-Seidel sweep of the FP64 oracle over the full "
-                      f"{w['n']}^3 workload ({cells} cell updates, {dt:.1f} s, single thread)"}
+            "sample": f"{sweeps} lexicographic Newton-Gauss-Seidel sweeps of the FP64 oracle over the full "
+                      f"{w['n']}^3 workload from phi = 0 ({cells} cell updates, {dt:.1f} s, single thread)"}
 
 
 def main():
@@ -198,6 +216,7 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc csv outputs of --traffic-probe into profiles/*_traffic.json")
     args = ap.parse_args()
+    os.environ.setdefault("VMG_TUNE_CACHE", TUNE_CACHE)
     if args.traffic_from:
         from paper_1303_0008_amd import inputs as I
         traffic_from(args.traffic_from[0], args.traffic_from[1], I.WORKLOADS[WORKLOAD]["n"])
@@ -228,8 +247,8 @@ def main():
     results = {}
     n3 = w["n"] ** 3
     roofs = {}
-    for name, prec, bpc, kern in (("fp64", V.FP64, 24, "k_smooth<8,0> (fused red-black sweep, FP64)"),
-                                  ("mixed", V.MIXED, 20, "k_smooth_corr<8,0> (fused red-black sweep on the FP32 correction)")):
+    for name, prec, bpc, what in (("fp64", V.FP64, 24, "fused red-black sweep, FP64"),
+                                  ("mixed", V.MIXED, 20, "fused red-black sweep on the FP32 correction")):
         plan, infos, updates, dt, _ = time_solves(torch, V, delta, w, prec, args.steps, args.warmup,
                                                   V.GRAPH | V.AUTOTUNE, stream)
         sched = plan.config()
@@ -245,10 +264,12 @@ def main():
                          "smoother_us_per_launch": smooth_ms * 1e3,
                          "smoother_cell_updates_per_s": n3 / (smooth_ms * 1e-3),
                          "finest_schedule": {"tile_y": sched["tile_y"], "z_chunk": sched["z_chunk"]}}
+        kern = finest_kernel(name, sched["tile_y"])
         roofs[name] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": load_traffic(f"smooth_{name}_zeldovich256_traffic.json"),
-                       "kernel": kern, "bytes_per_launch": bpc * n3, "us_per_launch": smooth_ms * 1e3}
+                       "traffic": load_traffic(f"smooth_{name}_zeldovich256_traffic.json", kern),
+                       "kernel": f"{kern} ({what}, z chunk {sched['z_chunk']})",
+                       "bytes_per_launch": bpc * n3, "us_per_launch": smooth_ms * 1e3}
     head = "mixed"
     results["mixed_speedup_vs_fp64"] = results["fp64"]["time_to_tol_ms"] / results["mixed"]["time_to_tol_ms"]
     roof = dict(roofs[head])

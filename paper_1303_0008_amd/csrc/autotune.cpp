@@ -75,7 +75,8 @@ void remember(const std::string& key, const SmoothCfg& c, double us) {
     append_file_cache(key, c, us);
 }
 
-// Levels of the plan that run the fused sweep (every level above the coarsest).
+// Levels of the plan that run the fused sweep: every level above the coarsest,
+// except those the periodic coarse tail handles in one launch.
 int swept_levels(const Plan* P) {
     if (P->batched) {
         int n = 0;
@@ -83,7 +84,8 @@ int swept_levels(const Plan* P) {
             if (P->blev[l].nsitems > 0) n = (int)l + 1;
         return n;
     }
-    return (int)P->grids[0].lev.size() - 1;
+    const int tl = P->mixed ? -1 : tail_level(P, P->grids[0]);
+    return tl > 0 ? tl : (int)P->grids[0].lev.size() - 1;
 }
 
 // Install schedule c on level l.

@@ -114,6 +114,8 @@ vmg_status autotune(Plan* P);
 hipError_t smooth_level_public(Plan* P, GridState& G, int l);
 // schedule of the fused sweep on level l of a single-grid (periodic) plan
 SmoothCfg level_schedule(const Plan* P, int l, const Geom& g);
+// first level handled by the periodic coarse tail (FP64 plans), or -1
+int tail_level(const Plan* P, const GridState& G);
 // batched plans: rebuild the persistent smoother's work list of level l for cfg;
 // one sweep of every grid on level l
 hipError_t batch_set_level_cfg(Plan* P, int l, SmoothCfg cfg);
