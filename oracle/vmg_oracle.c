@@ -252,21 +252,35 @@ static void ghosts_to_pad(const OGrid *g, const double *ghost, double *pad) {
 /* ------------------------------------------------------------------------- */
 
 /* cbar = mean(f) - mean(L^h phi) on periodic levels, 0 on Dirichlet levels */
+/* Compensated (Neumaier) summation: the grid sums below add up to 1e8 terms
+ * that cancel (the Laplacian sums to zero on a periodic grid), where a plain
+ * running sum would lose the digits that cbar and the residual norm need. */
+typedef struct { double s, c; } KSum;
+
+static void ks_add(KSum *k, double x) {
+    const double t = k->s + x;
+    if (fabs(k->s) >= fabs(x)) k->c += (k->s - t) + x;
+    else k->c += (x - t) + k->s;
+    k->s = t;
+}
+
+static double ks_val(const KSum *k) { return k->s + k->c; }
+
 static double compat_const(const OLevel *L, const OCoef *c) {
     if (!L->g.periodic) return 0.0;
-    double sf = 0.0, sl = 0.0;
+    KSum sf = {0.0, 0.0}, sl = {0.0, 0.0};
     for (int k = 0; k < L->g.n[2]; ++k)
         for (int j = 0; j < L->g.n[1]; ++j)
             for (int i = 0; i < L->g.n[0]; ++i) {
-                sf += L->f[pidx(&L->g, i, j, k)];
-                sl += Lh(&L->g, c, L->phi, L->delta, i, j, k, NULL, NULL);
+                ks_add(&sf, L->f[pidx(&L->g, i, j, k)]);
+                ks_add(&sl, Lh(&L->g, c, L->phi, L->delta, i, j, k, NULL, NULL));
             }
-    return (sf - sl) / (double)ncells(&L->g);
+    return (ks_val(&sf) - ks_val(&sl)) / (double)ncells(&L->g);
 }
 
 /* d = L^h phi + cbar - f; returns sum d^2; optional sums of the root and guard count */
 static double residual(OLevel *L, const OCoef *c, double cbar, double *sum_root, long *nguard) {
-    double s2 = 0.0, sr = 0.0;
+    KSum s2 = {0.0, 0.0}, sr = {0.0, 0.0};
     long ng = 0;
     for (int k = 0; k < L->g.n[2]; ++k)
         for (int j = 0; j < L->g.n[1]; ++j)
@@ -276,13 +290,13 @@ static double residual(OLevel *L, const OCoef *c, double cbar, double *sum_root,
                 const long p = pidx(&L->g, i, j, k);
                 const double v = Lh(&L->g, c, L->phi, L->delta, i, j, k, &r, &gd) + cbar - L->f[p];
                 L->d[p] = v;
-                s2 += v * v;
-                sr += r;
+                ks_add(&s2, v * v);
+                ks_add(&sr, r);
                 ng += gd;
             }
-    if (sum_root) *sum_root = sr;
+    if (sum_root) *sum_root = ks_val(&sr);
     if (nguard) *nguard = ng;
-    return s2;
+    return ks_val(&s2);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -544,11 +558,11 @@ int or_solve(const int n[3], int periodic, double h, double alpha, double kappa,
         ++cyc;
     }
     if (periodic) {
-        double m = 0.0;
+        KSum ms = {0.0, 0.0};
         for (int k = 0; k < g.n[2]; ++k)
             for (int j = 0; j < g.n[1]; ++j)
-                for (int i = 0; i < g.n[0]; ++i) m += F->phi[pidx(&g, i, j, k)];
-        m /= (double)ncells(&g);
+                for (int i = 0; i < g.n[0]; ++i) ks_add(&ms, F->phi[pidx(&g, i, j, k)]);
+        const double m = ks_val(&ms) / (double)ncells(&g);
         for (int k = 0; k < g.n[2]; ++k)
             for (int j = 0; j < g.n[1]; ++j)
                 for (int i = 0; i < g.n[0]; ++i) F->phi[pidx(&g, i, j, k)] -= m;

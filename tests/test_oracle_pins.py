@@ -414,6 +414,19 @@ def test_dirichlet_vcycle_rate_independent_of_depth(oracle_mod):
     assert abs(cyc[32] - cyc[16]) <= 3 and cyc[32] <= 25
 
 
+def test_periodic_laplacian_sums_to_zero(oracle_mod):
+    """On a periodic grid the discrete Laplacian sums to zero, so with f = 0 the
+    compatibility constant mean(f) - mean(L phi) equals the mean root exactly;
+    the oracle's grid sums must keep that at 128^3 for a rough, large phi."""
+    n = 128
+    rng = np.random.Generator(np.random.PCG64(11))
+    phi = 1e-2 * rng.standard_normal((n, n, n))
+    delta = I.lognormal(n, 12, sigma=1.0)
+    _, info = oracle_mod.residual(delta, phi, 0.2, 1.5, want_field=False)
+    scale = 6 * np.abs(phi).max() * n * n          # size of one Laplacian term
+    assert abs(info["cbar"] - info["mean_root"]) <= 1e-16 * scale   # a plain running sum misses by ~5e-15 * scale
+
+
 # ---------------------------------------------------------------------------
 # refinement boundary values: trilinear interpolation is exact for linear fields
 # ---------------------------------------------------------------------------
