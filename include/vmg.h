@@ -96,7 +96,8 @@ typedef struct {
     int32_t prec;          /* vmg_precision */
     int32_t nu1, nu2;      /* pre/post smoothing sweeps; 0,0 selects the defaults (2,2) */
     uint32_t flags;        /* VMG_GRAPH | VMG_AUTOTUNE */
-    int32_t reserved;
+    int32_t inner_cycles;  /* mixed: FP32 inner V-cycles per outer FP64 iteration (0 = 2);
+                              must be 0 for VMG_FP64 */
 } vmg_params;
 
 typedef struct {
@@ -114,7 +115,8 @@ typedef struct vmg_plan vmg_plan;
  * set of refinement patches).  Allocates every workspace on the current
  * device, may run the autotuner (VMG_AUTOTUNE) and records the V-cycle graph
  * (VMG_GRAPH).  All later work is issued on `stream` (0 = null stream).
- * Errors: VMG_EINVAL (sizes, h <= 0, tol <= 0, max_cycles < 1, mixed BC kinds,
+ * Errors: VMG_EINVAL (sizes, h <= 0, tol <= 0, max_cycles < 1, inner_cycles < 0 or
+ * set for VMG_FP64, mixed BC kinds,
  * a periodic grid that does not coarsen to <= 8 cells per side, a Dirichlet
  * grid whose coarsest level exceeds 8 cells per side), VMG_ENOMEM, VMG_EHIP. */
 vmg_status vmg_plan_create(vmg_plan **plan, const vmg_grid *grids, int32_t n_grids,

@@ -320,7 +320,7 @@ hipError_t batch_enqueue_iteration(Plan* P) {
     BatchLevel& B0 = P->blev[0];
     B0.ecur = 0;
     CKE(launch_fill_f(B0.e[0], B0.pool, 0.0f, s));
-    CKE(bcycle_corr(P, 0));
+    for (int c = 0; c < P->inner; ++c) CKE(bcycle_corr(P, 0));
     CKE(launch_update_batch(B0.d_geom, B0.d_cells, B0.ncells, B0.phi[0], B0.e[B0.ecur], s));
     return bcast(P);
 }

@@ -61,6 +61,30 @@ __device__ __forceinline__ double nl_root(const Nb& v, double dl, const Coef& c,
     return guard ? c.vertex : 2.0 * q * rcp_nr(1.0 + sqrt_nr(D));
 }
 
+// nl_root that also returns the discriminant D and +-sqrt|D| (sign of D): the
+// outer FP64 pass of the mixed path hands +-sqrt|D0| to the FP32 inner problem.
+__device__ __forceinline__ double nl_root_t0(const Nb& v, double dl, const Coef& c, double inv_h4,
+                                             double& S, bool& guard, double& t0) {
+    const double sx = v.xp + v.xm, sy = v.yp + v.ym, sz = v.zp + v.zm;
+    S = sx + sy + sz;
+    const double dxy = sx - sy, dxz = sx - sz, dyz = sy - sz;
+    const double bxy = (v.xpyp + v.xmym) - (v.xpym + v.xmyp);
+    const double bxz = (v.xpzp + v.xmzm) - (v.xpzm + v.xmzp);
+    const double byz = (v.ypzp + v.ymzm) - (v.ypzm + v.ymzp);
+    const double s0 = ((dxy * dxy + dxz * dxz + dyz * dyz) * (1.0 / 3.0)
+                     + (bxy * bxy + bxz * bxz + byz * byz) * 0.125) * inv_h4;
+    const double q = c.alpha * s0 + c.kappa * dl;
+    const double D = 1.0 + c.c8 * q;
+    guard = !(D > 0.0);
+    if (guard) {
+        t0 = D < 0.0 ? -sqrt_nr(-D) : 0.0;
+        return c.vertex;
+    }
+    const double sD = sqrt_nr(D);
+    t0 = sD;
+    return 2.0 * q * rcp_nr(1.0 + sD);
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
     // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
     // contiguous range of tiles so that shared halos stay in one L2.

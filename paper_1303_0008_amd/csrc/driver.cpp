@@ -89,6 +89,7 @@ vmg_status build_plan(Plan* P, const vmg_grid* grids, int n_grids, const vmg_par
     P->nu1 = p->nu1;
     P->nu2 = p->nu2;
     if (P->nu1 == 0 && P->nu2 == 0) { P->nu1 = 2; P->nu2 = 2; }
+    P->inner = p->inner_cycles > 0 ? p->inner_cycles : 2;
     P->ncoarse = 8;
     P->cfg.ty = 8;
     P->cfg.zc = 16;
@@ -456,7 +457,7 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
             out[gi].rms = P->host_norm[gi].rms;
             out[gi].compat_c = P->host_norm[gi].cbar;
             out[gi].cycles = cycles;
-            out[gi].inner_cycles = P->mixed ? cycles : 0;
+            out[gi].inner_cycles = P->mixed ? cycles * P->inner : 0;
             out[gi].n_guarded = (int64_t)P->host_norm[gi].n_guard;
         }
     }
@@ -488,7 +489,8 @@ vmg_status vmg_plan_create(vmg_plan** plan, const vmg_grid* grids, int32_t n_gri
     if (!plan || !grids || !p || n_grids < 1) return fail(VMG_EINVAL, "null argument or n_grids < 1");
     *plan = nullptr;
     if (!(p->tol > 0.0) || p->max_cycles < 1 || (p->prec != VMG_FP64 && p->prec != VMG_MIXED) ||
-        p->nu1 < 0 || p->nu2 < 0 || !std::isfinite(p->alpha) || !std::isfinite(p->kappa))
+        p->nu1 < 0 || p->nu2 < 0 || p->inner_cycles < 0 || (p->prec == VMG_FP64 && p->inner_cycles != 0) ||
+        !std::isfinite(p->alpha) || !std::isfinite(p->kappa))
         return fail(VMG_EINVAL, "invalid parameters (tol > 0, max_cycles >= 1, prec, nu1/nu2 >= 0, finite alpha/kappa)");
     const int bc0 = grids[0].bc;
     for (int i = 0; i < n_grids; ++i) {

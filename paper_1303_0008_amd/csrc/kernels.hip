@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(NT) k_resid_tiled(ResidArgs a) {
 static hipError_t resid_launch(ResidArgs& a, int mode, int* nblocks_out, hipStream_t s) {
     a.tiles_x = (a.g.n0 + TX - 1) / TX;
     a.tiles_y = (a.g.n1 + RTY - 1) / RTY;
-    a.zc = level_zc((int64_t)a.tiles_x * a.tiles_y, a.g.n2);
+    a.zc = level_zc((int64_t)a.tiles_x * a.tiles_y, a.g.n2, 32);
     const int nb = a.tiles_x * a.tiles_y * ((a.g.n2 + a.zc - 1) / a.zc);
     *nblocks_out = nb;
 #define RL(D, M) hipLaunchKernelGGL((k_resid_tiled<D, M>), dim3(nb), dim3(NT), 0, s, a)
@@ -312,7 +312,7 @@ static hipError_t resid_launch(ResidArgs& a, int mode, int* nblocks_out, hipStre
 
 int resid_blocks(const Geom& g) {
     const int xy = ((g.n0 + TX - 1) / TX) * ((g.n1 + RTY - 1) / RTY);
-    const int zc = level_zc(xy, g.n2);
+    const int zc = level_zc(xy, g.n2, 32);
     return xy * ((g.n2 + zc - 1) / zc);
 }
 

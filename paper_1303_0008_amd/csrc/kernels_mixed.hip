@@ -638,13 +638,13 @@ __global__ void __launch_bounds__(NT) k_cast_tiled(CastArgs a) {
             const double pc = PH[sc][Y][X];
             double S;
             bool gd;
-            const double Q = nl_root(v, cdl[c2], a.c, inv_h4, S, gd);
-            const double D0 = base_discriminant(v, cdl[c2], a.c, inv_h4);
+            double t0;
+            const double Q = nl_root_t0(v, cdl[c2], a.c, inv_h4, S, gd, t0);
             const double d = (S - 6.0 * pc) * inv_h2 - Q - cfv[c2] + cb;
             const int64_t gi = g.off0 + xa + c2 + (int64_t)gy * g.sy + (int64_t)t * g.sz;
             if (UPDATE) a.phi_out[gi] = pc;
             a.pt[gi] = (float)pc;
-            a.t0[gi] = (float)(D0 >= 0.0 ? sqrt(D0) : -sqrt(-D0));
+            a.t0[gi] = (float)t0;
             a.r[gi] = (float)(-d);
             acc[R_D2] += d * d;
             acc[R_D1] += d;
@@ -1101,7 +1101,7 @@ hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, f
 static void corr_tiles(const Geom& g, int& tx, int& ty, int& zc, int& nb) {
     tx = (g.n0 + TX - 1) / TX;
     ty = (g.n1 + MTY - 1) / MTY;
-    zc = level_zc((int64_t)tx * ty, g.n2, MZC);
+    zc = level_zc((int64_t)tx * ty, g.n2, 32);
     nb = tx * ty * ((g.n2 + zc - 1) / zc);
 }
 

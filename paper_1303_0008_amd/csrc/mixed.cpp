@@ -147,7 +147,8 @@ hipError_t enqueue_outer(Plan* P) {
         L0.ecur = 0;
         const bool zero_e = P->nu1 > 0 && G.lev.size() > 1;
         if (!zero_e && (e = launch_fill_f(L0.e[0], L0.g.nstore, 0.0f, P->stream)) != hipSuccess) return e;
-        if ((e = inner_vcycle(P, G, 0, zero_e)) != hipSuccess) return e;
+        for (int c = 0; c < P->inner; ++c)
+            if ((e = inner_vcycle(P, G, 0, zero_e && c == 0)) != hipSuccess) return e;
         if ((e = cast_pass(P, G, true)) != hipSuccess) return e;
     }
     return norms_to_host(P);

@@ -76,6 +76,7 @@ struct Plan {
     SmoothCfg cfg;                         // finest-level schedule of the fused sweep
     std::vector<SmoothCfg> lcfg;           // tuned schedules of levels >= 1 (empty: level_cfg rule)
     int nu1 = 2, nu2 = 2, ncoarse = 40;
+    int inner = 2;                         // mixed: FP32 inner V-cycles per outer iteration
     bool use_tail = true;                  // periodic coarse levels <= TAIL_CELLS in one launch
     bool periodic = true;
     bool mixed = false;

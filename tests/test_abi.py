@@ -50,3 +50,7 @@ def test_plan_create_rejects_bad_arguments():
     arr = (vmg.Grid * 2)(vmg.make_grid(32), vmg.make_grid(32))
     assert lib.vmg_plan_create(ctypes.byref(h), arr, 2, ctypes.byref(p), None) == vmg.VMG_EINVAL
     assert lib.vmg_solve(None, None, None, None, None, None) == vmg.VMG_EINVAL
+    # inner cycles: only for the mixed path, never negative
+    for prec, inner in ((vmg.FP64, 2), (vmg.MIXED, -1)):
+        p = vmg.make_params(0.1, 1.5, tol=1e-8, prec=prec, inner_cycles=inner)
+        assert lib.vmg_plan_create(ctypes.byref(h), ctypes.byref(g), 1, ctypes.byref(p), None) == vmg.VMG_EINVAL
