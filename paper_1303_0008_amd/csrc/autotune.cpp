@@ -84,7 +84,7 @@ int swept_levels(const Plan* P) {
             if (P->blev[l].nsitems > 0) n = (int)l + 1;
         return n;
     }
-    const int tl = P->mixed ? -1 : tail_level(P, P->grids[0]);
+    const int tl = tail_level(P, P->grids[0]);
     return tl > 0 ? tl : (int)P->grids[0].lev.size() - 1;
 }
 

@@ -85,6 +85,54 @@ __device__ __forceinline__ double nl_root_t0(const Nb& v, double dl, const Coef&
     return 2.0 * q * rcp_nr(1.0 + sD);
 }
 
+// Discriminant D = 1 + 8 alpha q / 3 of a cell's quadratic (Sec. III.A) from
+// its 18 neighbours and density (the mixed path's base state).
+__device__ __forceinline__ double base_discriminant(const Nb& v, double dl, const Coef& c, double inv_h4) {
+    const double sx = v.xp + v.xm, sy = v.yp + v.ym, sz = v.zp + v.zm;
+    const double dxy = sx - sy, dxz = sx - sz, dyz = sy - sz;
+    const double bxy = (v.xpyp + v.xmym) - (v.xpym + v.xmyp);
+    const double bxz = (v.xpzp + v.xmzm) - (v.xpzm + v.xmzp);
+    const double byz = (v.ypzp + v.ymzm) - (v.ypzm + v.ymzp);
+    const double s0 = ((dxy * dxy + dxz * dxz + dyz * dyz) * (1.0 / 3.0)
+                     + (bxy * bxy + bxz * bxz + byz * byz) * 0.125) * inv_h4;
+    return 1.0 + c.c8 * (c.alpha * s0 + c.kappa * dl);
+}
+
+// Correction of the mixed path's FP32 inner problem: dq = alpha Phi(2 phi~ + e, e)
+// / h^4 from the neighbourhoods of e and of the base state phi~ (Phi the
+// bilinear form of Sigma0), and dQ = Q(q0 + dq) - Q(q0) from t0 = +-sqrt|D0|.
+__device__ __forceinline__ float dq_corr(const NbT<float>& e, const NbT<float>& p, float a_ih4,
+                                         float& Se) {
+    const float sxe = e.xp + e.xm, sye = e.yp + e.ym, sze = e.zp + e.zm;
+    const float sxp = p.xp + p.xm, syp = p.yp + p.ym, szp = p.zp + p.zm;
+    Se = sxe + sye + sze;
+    const float dxy_e = sxe - sye, dxz_e = sxe - sze, dyz_e = sye - sze;
+    const float dxy_w = 2.0f * (sxp - syp) + dxy_e;
+    const float dxz_w = 2.0f * (sxp - szp) + dxz_e;
+    const float dyz_w = 2.0f * (syp - szp) + dyz_e;
+    const float bxy_e = (e.xpyp + e.xmym) - (e.xpym + e.xmyp);
+    const float bxz_e = (e.xpzp + e.xmzm) - (e.xpzm + e.xmzp);
+    const float byz_e = (e.ypzp + e.ymzm) - (e.ypzm + e.ymzp);
+    const float bxy_w = 2.0f * ((p.xpyp + p.xmym) - (p.xpym + p.xmyp)) + bxy_e;
+    const float bxz_w = 2.0f * ((p.xpzp + p.xmzm) - (p.xpzm + p.xmzp)) + bxz_e;
+    const float byz_w = 2.0f * ((p.ypzp + p.ymzm) - (p.ypzm + p.ymzp)) + byz_e;
+    const float ph = (dxy_w * dxy_e + dxz_w * dxz_e + dyz_w * dyz_e) * (1.0f / 3.0f)
+                   + (bxy_w * bxy_e + bxz_w * bxz_e + byz_w * byz_e) * 0.125f;
+    return a_ih4 * ph;
+}
+
+__device__ __forceinline__ float dQ_of(float dq, float t0, const CoefF& c) {
+    const float D0 = t0 >= 0.0f ? t0 * t0 : -t0 * t0;
+    const float s0 = fmaxf(t0, 0.0f);
+    const float D1 = D0 + c.c8 * dq;
+    const float s1 = __builtin_amdgcn_sqrtf(fmaxf(D1, 0.0f));
+    if (D0 >= 0.0f && D1 >= 0.0f) {
+        const float den = s0 + s1;
+        return den > 0.0f ? 2.0f * dq * __builtin_amdgcn_rcpf(den) : 0.0f;
+    }
+    return c.a34 * (s1 - s0);
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
     // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
     // contiguous range of tiles so that shared halos stay in one L2.

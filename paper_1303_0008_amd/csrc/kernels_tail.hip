@@ -248,6 +248,248 @@ __global__ void __launch_bounds__(TAIL_NT) k_tail(TailArgs a) {
     if (tid == 0) a.sc->cbar = cbar[0];
 }
 
+// ---------------------------------------------------------------------------
+// Coarse tail of the mixed path's FP32 inner cycle: the same structure for the
+// correction problem  Lap e - dQ(e) = r - cbar_e  (e, r, phi~, t0 per level).
+// Below the tail's top level the base state phi~ is the 8-child average and
+// t0 = +-sqrt|D0| comes from the FP64 discriminant of phi~ and delta, as in the
+// multi-kernel inner cycle.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int CTAIL_POOL = 4 * TAIL_CELLS + 5 * (TAIL_CELLS / 8 + TAIL_CELLS / 64 + TAIL_CELLS / 512 + 1);
+
+struct CLev {
+    int n0, n1, n2, N;
+    float h2, inv_h2, a_ih4;
+    double inv_h4;
+    float *e, *r, *pt, *t0, *old;   // LDS
+};
+
+__device__ __forceinline__ CLev ctail_level(const TailCorrArgs& a, float* pool, int l) {
+    int off = 0;
+    for (int q = 0; q < l; ++q) off += (q == 0 ? 4 : 5) * a.n[q][0] * a.n[q][1] * a.n[q][2];
+    CLev T;
+    T.n0 = a.n[l][0];
+    T.n1 = a.n[l][1];
+    T.n2 = a.n[l][2];
+    T.N = T.n0 * T.n1 * T.n2;
+    const double h2 = a.h[l] * a.h[l];
+    T.h2 = (float)h2;
+    T.inv_h2 = (float)(1.0 / h2);
+    T.inv_h4 = 1.0 / (h2 * h2);
+    T.a_ih4 = (float)(a.c64.alpha * T.inv_h4);
+    T.e = pool + off;
+    T.r = T.e + T.N;
+    T.pt = T.r + T.N;
+    T.t0 = T.pt + T.N;
+    T.old = l > 0 ? T.t0 + T.N : nullptr;
+    return T;
+}
+
+__device__ __forceinline__ int ctail_idx(const CLev& L, int i, int j, int k) {
+    return (tw(k, L.n2) * L.n1 + tw(j, L.n1)) * L.n0 + tw(i, L.n0);
+}
+
+__device__ __forceinline__ void ctail_decode(const CLev& L, int e, int& i, int& j, int& k) {
+    i = e % L.n0;
+    const int r = e / L.n0;
+    j = r % L.n1;
+    k = r / L.n1;
+}
+
+template <typename T>
+__device__ __forceinline__ void ctail_gather(const CLev& L, const T* u, int i, int j, int k, NbT<T>& v) {
+    v.xm = u[ctail_idx(L, i - 1, j, k)];         v.xp = u[ctail_idx(L, i + 1, j, k)];
+    v.ym = u[ctail_idx(L, i, j - 1, k)];         v.yp = u[ctail_idx(L, i, j + 1, k)];
+    v.zm = u[ctail_idx(L, i, j, k - 1)];         v.zp = u[ctail_idx(L, i, j, k + 1)];
+    v.xpyp = u[ctail_idx(L, i + 1, j + 1, k)];   v.xmym = u[ctail_idx(L, i - 1, j - 1, k)];
+    v.xpym = u[ctail_idx(L, i + 1, j - 1, k)];   v.xmyp = u[ctail_idx(L, i - 1, j + 1, k)];
+    v.xpzp = u[ctail_idx(L, i + 1, j, k + 1)];   v.xmzm = u[ctail_idx(L, i - 1, j, k - 1)];
+    v.xpzm = u[ctail_idx(L, i + 1, j, k - 1)];   v.xmzp = u[ctail_idx(L, i - 1, j, k + 1)];
+    v.ypzp = u[ctail_idx(L, i, j + 1, k + 1)];   v.ymzm = u[ctail_idx(L, i, j - 1, k - 1)];
+    v.ypzm = u[ctail_idx(L, i, j + 1, k - 1)];   v.ymzp = u[ctail_idx(L, i, j - 1, k + 1)];
+}
+
+// dQ(e) at cell (i,j,k) and the neighbour sum of e
+__device__ __forceinline__ float ctail_dq(const CLev& L, const CoefF& c, int i, int j, int k, int e, float& Se) {
+    NbT<float> ve, vp;
+    ctail_gather(L, L.e, i, j, k, ve);
+    ctail_gather(L, L.pt, i, j, k, vp);
+    return dQ_of(dq_corr(ve, vp, L.a_ih4, Se), L.t0[e], c);
+}
+
+__device__ void ctail_sweep(const CLev& L, float* tmp, const CoefF& c, float cb) {
+    const int tid = threadIdx.x;
+    for (int colour = 0; colour < 2; ++colour) {
+        for (int e = tid; e < L.N; e += TAIL_NT) {
+            int i, j, k;
+            ctail_decode(L, e, i, j, k);
+            if (((i + j + k) & 1) != colour) continue;
+            float Se;
+            const float dQ = ctail_dq(L, c, i, j, k, e, Se);
+            tmp[e] = (Se - L.h2 * (dQ + L.r[e] - cb)) * (1.0f / 6.0f);
+        }
+        __syncthreads();
+        for (int e = tid; e < L.N; e += TAIL_NT) {
+            int i, j, k;
+            ctail_decode(L, e, i, j, k);
+            if (((i + j + k) & 1) == colour) L.e[e] = tmp[e];
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(TAIL_NT) k_tail_corr(TailCorrArgs a) {
+    __shared__ float pool[CTAIL_POOL];
+    __shared__ float tmp[TAIL_CELLS];
+    __shared__ double red[TAIL_NT / 64][2];
+    __shared__ float cbar[TAIL_LEVELS];
+    const int tid = threadIdx.x;
+    const int nl = a.nlev;
+    CoefF cf;
+    cf.alpha = (float)a.c64.alpha;
+    cf.c8 = (float)a.c64.c8;
+    cf.a34 = a.c64.alpha != 0.0 ? (float)(3.0 / (4.0 * a.c64.alpha)) : 0.0f;
+    {
+        const CLev T = ctail_level(a, pool, 0);
+        for (int e = tid; e < T.N; e += TAIL_NT) {
+            T.e[e] = a.e[e];
+            T.r[e] = a.r[e];
+            T.pt[e] = a.pt[e];
+            T.t0[e] = a.t0[e];
+        }
+    }
+    if (tid == 0) cbar[0] = (float)a.sc->cbar;
+    __syncthreads();
+    const int last = nl - 1;
+    for (int l = 0; l < last; ++l) {
+        const CLev F = ctail_level(a, pool, l);
+        const CLev C = ctail_level(a, pool, l + 1);
+        for (int s = 0; s < a.nu1; ++s) ctail_sweep(F, tmp, cf, cbar[l]);
+        // residual d_e, restriction of e, d_e (kept as -R d_e in r^H) and phi~
+        double sq = 0.0, sf = 0.0;
+        for (int e = tid; e < C.N; e += TAIL_NT) {
+            int I, J, K;
+            ctail_decode(C, e, I, J, K);
+            float se = 0.0f, sd = 0.0f, sp = 0.0f;
+#pragma unroll 1
+            for (int m = 0; m < 8; ++m) {
+                const int i = 2 * I + (m & 1), j = 2 * J + ((m >> 1) & 1), k = 2 * K + (m >> 2);
+                const int fe = (k * F.n1 + j) * F.n0 + i;
+                float Se;
+                const float dQ = ctail_dq(F, cf, i, j, k, fe, Se);
+                const float ec = F.e[fe];
+                sd += (Se - 6.0f * ec) * F.inv_h2 - dQ - F.r[fe] + cbar[l];
+                se += ec;
+                sp += F.pt[fe];
+                sq += dQ;
+                sf += F.r[fe];
+            }
+            C.e[e] = 0.125f * se;
+            C.old[e] = 0.125f * se;
+            C.r[e] = -0.125f * sd;
+            C.pt[e] = 0.125f * sp;
+        }
+        double SQ, SF;
+        tail_sum2(sq, sf, SQ, SF, red);
+        if (tid == 0) cbar[l] = (float)((SF + SQ) / (double)F.N);
+        // t0 of the coarse level from the FP64 discriminant of phi~ and delta
+        for (int e = tid; e < C.N; e += TAIL_NT) {
+            int I, J, K;
+            ctail_decode(C, e, I, J, K);
+            NbT<float> vp;
+            ctail_gather(C, C.pt, I, J, K, vp);
+            Nb vb;
+            vb.xm = vp.xm; vb.xp = vp.xp; vb.ym = vp.ym; vb.yp = vp.yp; vb.zm = vp.zm; vb.zp = vp.zp;
+            vb.xpyp = vp.xpyp; vb.xmym = vp.xmym; vb.xpym = vp.xpym; vb.xmyp = vp.xmyp;
+            vb.xpzp = vp.xpzp; vb.xmzm = vp.xmzm; vb.xpzm = vp.xpzm; vb.xmzp = vp.xmzp;
+            vb.ypzp = vp.ypzp; vb.ymzm = vp.ymzm; vb.ypzm = vp.ypzm; vb.ymzp = vp.ymzp;
+            const double D0 = base_discriminant(vb, a.delta[l + 1][e], a.c64, C.inv_h4);
+            C.t0[e] = (float)(D0 >= 0.0 ? sqrt(D0) : -sqrt(-D0));
+        }
+        __syncthreads();
+        // coarse rhs r^H = L_e^H(R e) - R d_e
+        sq = 0.0;
+        sf = 0.0;
+        for (int e = tid; e < C.N; e += TAIL_NT) {
+            int I, J, K;
+            ctail_decode(C, e, I, J, K);
+            float Se;
+            const float dQ = ctail_dq(C, cf, I, J, K, e, Se);
+            const float rh = (Se - 6.0f * C.e[e]) * C.inv_h2 - dQ + C.r[e];
+            C.r[e] = rh;
+            sq += dQ;
+            sf += rh;
+        }
+        tail_sum2(sq, sf, SQ, SF, red);
+        if (tid == 0) cbar[l + 1] = (float)((SF + SQ) / (double)C.N);
+        __syncthreads();
+    }
+    // coarsest level: cbar_e from the current sum of dQ before every sweep
+    {
+        const CLev C = ctail_level(a, pool, last);
+        double sf = 0.0, dummy = 0.0, SF, D;
+        for (int e = tid; e < C.N; e += TAIL_NT) sf += C.r[e];
+        tail_sum2(sf, dummy, SF, D, red);
+        for (int s = 0; s < a.ncoarse; ++s) {
+            double sq = 0.0, SQ;
+            for (int e = tid; e < C.N; e += TAIL_NT) {
+                int i, j, k;
+                ctail_decode(C, e, i, j, k);
+                float Se;
+                sq += ctail_dq(C, cf, i, j, k, e, Se);
+            }
+            tail_sum2(sq, dummy, SQ, D, red);
+            ctail_sweep(C, tmp, cf, (float)((SF + SQ) / (double)C.N));
+        }
+    }
+    // ascent: prolongation of the correction's correction, post-smoothing
+    for (int l = last - 1; l >= 0; --l) {
+        const CLev F = ctail_level(a, pool, l);
+        const CLev C = ctail_level(a, pool, l + 1);
+        for (int e = tid; e < F.N; e += TAIL_NT) {
+            int i, j, k;
+            ctail_decode(F, e, i, j, k);
+            const int I = i >> 1, J = j >> 1, K = k >> 1;
+            const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+            float acc = 0.0f;
+            for (int m = 0; m < 8; ++m) {
+                const int ai = m & 1, aj = (m >> 1) & 1, ak = m >> 2;
+                const float w = (ai ? 0.25f : 0.75f) * (aj ? 0.25f : 0.75f) * (ak ? 0.25f : 0.75f);
+                const int ci = ctail_idx(C, I + ai * si, J + aj * sj, K + ak * sk);
+                acc += w * (C.e[ci] - C.old[ci]);
+            }
+            F.e[e] += acc;
+        }
+        __syncthreads();
+        for (int s = 0; s < a.nu2; ++s) ctail_sweep(F, tmp, cf, cbar[l]);
+    }
+    {
+        const CLev T = ctail_level(a, pool, 0);
+        for (int e = tid; e < T.N; e += TAIL_NT) a.e[e] = T.e[e];
+    }
+    if (tid == 0) a.sc->cbar = cbar[0];
+}
+
+hipError_t launch_tail_corr(const TailCorrArgs& a, hipStream_t s) {
+    if (a.nlev < 1 || a.nlev > TAIL_LEVELS) return hipErrorInvalidValue;
+    int64_t need = 0;
+    for (int l = 0; l < a.nlev; ++l) {
+        const int64_t N = (int64_t)a.n[l][0] * a.n[l][1] * a.n[l][2];
+        if (N > TAIL_CELLS || a.n[l][0] < 1 || a.n[l][1] < 1 || a.n[l][2] < 1) return hipErrorInvalidValue;
+        if (l > 0)
+            for (int d = 0; d < 3; ++d)
+                if (2 * a.n[l][d] != a.n[l - 1][d]) return hipErrorInvalidValue;
+        need += (l == 0 ? 4 : 5) * N;
+    }
+    if (need > CTAIL_POOL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tail_corr, dim3(1), dim3(TAIL_NT), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_tail(const TailArgs& a, hipStream_t s) {
     if (a.nlev < 1 || a.nlev > TAIL_LEVELS) return hipErrorInvalidValue;
     int64_t need = 0;

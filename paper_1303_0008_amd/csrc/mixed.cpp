@@ -67,6 +67,29 @@ hipError_t smooth_corr_level(Plan* P, GridState& G, int l, bool zero_in) {
     return e;
 }
 
+// The periodic coarse tail of the inner cycle: levels l..last in one launch.
+static hipError_t inner_tail(Plan* P, GridState& G, int l) {
+    const int last = (int)G.lev.size() - 1;
+    TailCorrArgs a;
+    a.nlev = last - l + 1;
+    for (int q = 0; q < a.nlev; ++q) {
+        const LevelBuf& T = G.lev[l + q];
+        a.n[q][0] = T.g.n0; a.n[q][1] = T.g.n1; a.n[q][2] = T.g.n2;
+        a.h[q] = T.g.h;
+        a.delta[q] = T.delta;
+        P->cell_updates += (int64_t)(q == a.nlev - 1 ? P->ncoarse : P->nu1 + P->nu2) * T.g.ncell;
+    }
+    LevelBuf& L = G.lev[l];
+    a.e = L.e[L.ecur];
+    a.r = L.r;
+    a.pt = L.pt;
+    a.t0 = L.t0;
+    a.sc = L.scf;
+    a.c64 = P->coef;
+    a.nu1 = P->nu1; a.nu2 = P->nu2; a.ncoarse = P->ncoarse;
+    return launch_tail_corr(a, P->stream);
+}
+
 // zero_e: the level's correction is identically zero on entry (finest level,
 // first inner cycle of an outer iteration); the first sweep then reads no e.
 static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e) {
@@ -74,6 +97,7 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e) {
     const int last = (int)G.lev.size() - 1;
     const CoefF cf = make_coef_f(P->coef, L.g.h);
     hipError_t e;
+    if (l > 0 && l == tail_level(P, G)) return inner_tail(P, G, l);
     if (l == last) {
         e = launch_coarse_corr(L.g, cf, L.e[L.ecur], L.pt, L.t0, L.r, P->ncoarse, P->stream);
         P->cell_updates += (int64_t)P->ncoarse * L.g.ncell;

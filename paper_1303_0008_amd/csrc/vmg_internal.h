@@ -107,6 +107,21 @@ struct TailArgs {
     int nu1, nu2, ncoarse;
 };
 hipError_t launch_tail(const TailArgs& a, hipStream_t s);
+// the same for the mixed path's FP32 correction problem
+struct TailCorrArgs {
+    int nlev;
+    int n[TAIL_LEVELS][3];
+    double h[TAIL_LEVELS];
+    const double* delta[TAIL_LEVELS];   // density of each level (t0 below the top level)
+    float* e;                           // top-level correction (in/out)
+    const float* r;                     // top-level rhs of the correction problem
+    const float* pt;                    // top-level base state phi~
+    const float* t0;                    // top-level +-sqrt|D0|
+    LevelScalars* sc;                   // top-level inner cbar (in/out)
+    Coef c64;                           // FP64 coefficients (alpha, c8, kappa)
+    int nu1, nu2, ncoarse;
+};
+hipError_t launch_tail_corr(const TailCorrArgs& a, hipStream_t s);
 
 // ---- launchers (kernels.hip) --------------------------------------------
 hipError_t launch_smooth(const Geom& g, const Coef& c, const double* pin, double* pout,
