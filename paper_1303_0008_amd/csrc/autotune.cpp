@@ -1,7 +1,7 @@
 // Autotuner: picks the fused sweep's tile height and z chunk for every level of
 // a plan by timing the real smoother kernel on the plan's own buffers (HIP
-// events on the plan's stream).  The finest level tries heights {8,4,16} x
-// chunks {16,8,32}; each coarser level heights {8,4,16} x chunks {16,8,4,2},
+// events on the plan's stream).  The finest level tries heights {8,4,16,12} x
+// chunks {16,8,32}; each coarser level heights {8,4,16,12} x chunks {16,8,4,2},
 // since short chunks spread small grids over the chip.  Results are cached per
 // (grid shape, precision, boundary kind, batch size, level) in the process and,
 // if the environment variable VMG_TUNE_CACHE names a file, in that file
@@ -124,9 +124,9 @@ vmg_status autotune(Plan* P) {
             continue;
         }
         std::vector<SmoothCfg> cands;
-        const int tys[3] = {8, 4, 16};
+        const int tys[4] = {8, 4, 16, 12};
         const int zf[3] = {16, 8, 32}, zcoarse[4] = {16, 8, 4, 2};
-        for (int a = 0; a < 3; ++a) {
+        for (int a = 0; a < 4; ++a) {
             if (l == 0)
                 for (int b = 0; b < 3; ++b) cands.push_back(SmoothCfg{tys[a], zf[b]});
             else

@@ -1089,10 +1089,12 @@ hipError_t launch_smooth(const Geom& g, const Coef& c, const double* pin, double
     if (g.dir) {
         if (ty == 4) return smooth_launch<4, 1>(a, s);
         if (ty == 16) return smooth_launch<16, 1>(a, s);
+        if (ty == 12) return smooth_launch<12, 1>(a, s);
         return smooth_launch<8, 1>(a, s);
     }
     if (ty == 4) return smooth_launch<4, 0>(a, s);
     if (ty == 16) return smooth_launch<16, 0>(a, s);
+    if (ty == 12) return smooth_launch<12, 0>(a, s);
     return smooth_launch<8, 0>(a, s);
 }
 
@@ -1233,6 +1235,9 @@ hipError_t launch_smooth_batch(const SmoothArgs& proto, const Geom* geoms, const
     } else if (ty == 16) {
         if (f) hipLaunchKernelGGL((k_smooth_batch<16, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
         else hipLaunchKernelGGL((k_smooth_batch<16, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
+    } else if (ty == 12) {
+        if (f) hipLaunchKernelGGL((k_smooth_batch<12, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
+        else hipLaunchKernelGGL((k_smooth_batch<12, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
     } else {
         if (f) hipLaunchKernelGGL((k_smooth_batch<8, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
         else hipLaunchKernelGGL((k_smooth_batch<8, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);

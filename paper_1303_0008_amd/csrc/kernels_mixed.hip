@@ -646,8 +646,7 @@ struct CorrResArgs {
 template <int DIR, int MODE>
 __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
     constexpr int W1 = TX + 2, H1 = MTY + 2, NP1 = W1 * H1, NL1 = (NP1 + NT - 1) / NT;
-    __shared__ float EE[3][H1][W1];
-    __shared__ float PP[3][H1][W1];
+    __shared__ float2 EP[3][H1][W1];   // (e, phi~): one 8-byte read per neighbour
     const Geom& g = a.g;
     const int tid = threadIdx.x;
     int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -699,14 +698,10 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
         }
     };
     auto store_planes = [&](int sl, const float (&re)[NL1], const float (&rp)[NL1]) {
-        float* de = &EE[sl][0][0];
-        float* dp = &PP[sl][0][0];
+        float2* d = &EP[sl][0][0];
 #pragma unroll
         for (int s2 = 0; s2 < NL1; ++s2)
-            if (tid + s2 * NT < NP1) {
-                de[tid + s2 * NT] = re[s2];
-                dp[tid + s2 * NT] = rp[s2];
-            }
+            if (tid + s2 * NT < NP1) d[tid + s2 * NT] = make_float2(re[s2], rp[s2]);
     };
     auto slot = [](int z) { return (z + 3) % 3; };
     const double inv_h4_64 = 1.0 / (g.h * g.h * g.h * g.h);
@@ -747,18 +742,22 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
         for (int c2 = 0; c2 < 2; ++c2) {
             const int X = 2 * m + c2 + 1, Y = r + 1;
             if (!row_ok || xa + c2 >= g.n0) continue;
+            NbT<float2> v2;
+            v2.xm = EP[sc][Y][X - 1]; v2.xp = EP[sc][Y][X + 1]; v2.ym = EP[sc][Y - 1][X]; v2.yp = EP[sc][Y + 1][X];
+            v2.zm = EP[sm][Y][X]; v2.zp = EP[sp][Y][X];
+            v2.xpyp = EP[sc][Y + 1][X + 1]; v2.xmym = EP[sc][Y - 1][X - 1];
+            v2.xpym = EP[sc][Y - 1][X + 1]; v2.xmyp = EP[sc][Y + 1][X - 1];
+            v2.xpzp = EP[sp][Y][X + 1]; v2.xmzm = EP[sm][Y][X - 1]; v2.xpzm = EP[sm][Y][X + 1]; v2.xmzp = EP[sp][Y][X - 1];
+            v2.ypzp = EP[sp][Y + 1][X]; v2.ymzm = EP[sm][Y - 1][X]; v2.ypzm = EP[sm][Y + 1][X]; v2.ymzp = EP[sp][Y - 1][X];
             NbT<float> ve, vp;
-#define LNB(v, A)                                                                          \
-    v.xm = A[sc][Y][X - 1]; v.xp = A[sc][Y][X + 1]; v.ym = A[sc][Y - 1][X]; v.yp = A[sc][Y + 1][X]; \
-    v.zm = A[sm][Y][X]; v.zp = A[sp][Y][X];                                                \
-    v.xpyp = A[sc][Y + 1][X + 1]; v.xmym = A[sc][Y - 1][X - 1];                            \
-    v.xpym = A[sc][Y - 1][X + 1]; v.xmyp = A[sc][Y + 1][X - 1];                            \
-    v.xpzp = A[sp][Y][X + 1]; v.xmzm = A[sm][Y][X - 1]; v.xpzm = A[sm][Y][X + 1]; v.xmzp = A[sp][Y][X - 1]; \
-    v.ypzp = A[sp][Y + 1][X]; v.ymzm = A[sm][Y - 1][X]; v.ypzm = A[sm][Y + 1][X]; v.ymzp = A[sp][Y - 1][X];
-            LNB(ve, EE)
-            LNB(vp, PP)
-#undef LNB
-            const float ecv = EE[sc][Y][X];
+#define VMG_SPLIT(q) ve.q = v2.q.x; vp.q = v2.q.y;
+            VMG_SPLIT(xm) VMG_SPLIT(xp) VMG_SPLIT(ym) VMG_SPLIT(yp) VMG_SPLIT(zm) VMG_SPLIT(zp)
+            VMG_SPLIT(xpyp) VMG_SPLIT(xmym) VMG_SPLIT(xpym) VMG_SPLIT(xmyp)
+            VMG_SPLIT(xpzp) VMG_SPLIT(xmzm) VMG_SPLIT(xpzm) VMG_SPLIT(xmzp)
+            VMG_SPLIT(ypzp) VMG_SPLIT(ymzm) VMG_SPLIT(ypzm) VMG_SPLIT(ymzp)
+#undef VMG_SPLIT
+            const float2 cc = EP[sc][Y][X];
+            const float ecv = cc.x;
             float t0c = ctt[c2];
             if (MODE == 2) {
                 Nb vb;
@@ -788,7 +787,7 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
                 acc[R_NONFIN] += isfinite(d) ? 0.0 : 1.0;
                 esum += ecv;
                 dsum += d;
-                psum += PP[sc][Y][X];
+                psum += cc.y;
             }
         }
         if (MODE == 1) {
@@ -1049,10 +1048,12 @@ hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, f
     if (g.dir) {
         if (cfg.ty == 4) return corr_launch<4, 1>(a, zero_in, s);
         if (cfg.ty == 16) return corr_launch<16, 1>(a, zero_in, s);
+        if (cfg.ty == 12) return corr_launch<12, 1>(a, zero_in, s);
         return corr_launch<8, 1>(a, zero_in, s);
     }
     if (cfg.ty == 4) return corr_launch<4, 0>(a, zero_in, s);
     if (cfg.ty == 16) return corr_launch<16, 0>(a, zero_in, s);
+    if (cfg.ty == 12) return corr_launch<12, 0>(a, zero_in, s);
     return corr_launch<8, 0>(a, zero_in, s);
 }
 
@@ -1199,6 +1200,8 @@ hipError_t launch_smooth_corr_batch(const CoefF& c, const float* ein, float* eou
         hipLaunchKernelGGL(k_smooth_corr_batch<4>, dim3(nb), dim3(SNT), 0, s, a, geoms, items, nitems);
     else if (cfg.ty == 16)
         hipLaunchKernelGGL(k_smooth_corr_batch<16>, dim3(nb), dim3(SNT), 0, s, a, geoms, items, nitems);
+    else if (cfg.ty == 12)
+        hipLaunchKernelGGL(k_smooth_corr_batch<12>, dim3(nb), dim3(SNT), 0, s, a, geoms, items, nitems);
     else
         hipLaunchKernelGGL(k_smooth_corr_batch<8>, dim3(nb), dim3(SNT), 0, s, a, geoms, items, nitems);
     return hipGetLastError();

@@ -60,7 +60,7 @@ struct NormOut {
 constexpr int TX = 64;
 
 struct SmoothCfg {
-    int ty;      // 4, 8 or 16
+    int ty;      // 4, 8, 12 or 16
     int zc;      // z planes per block
 };
 
