@@ -27,11 +27,18 @@
 
 namespace vmg {
 
-// Threads per block of the fused sweep and the waves per SIMD it is built for
-// (4 blocks of 4 waves per CU: at most 128 VGPRs, 4 x 35 KB of LDS).  Wider
-// blocks measured slower: each plane step ends in two block-wide barriers.
+// Threads per block of the fused sweep.  Wider blocks measured slower: each
+// plane step ends in two block-wide barriers.
 constexpr int SNT = 256;
-constexpr int SNT_WAVES_PER_SIMD = 4;
+
+// LDS of a sweep block of tile height TY (8-byte cells: three ring-2 planes of
+// u^0 and three ring-1 planes of u^1), and the waves per SIMD its kernels are
+// built for: as many blocks per CU as that LDS allows (160 KB per CU), at most
+// 4, so that the register budget matches the occupancy the LDS permits.
+constexpr int sweep_lds_bytes(int ty) { return 3 * ((TX + 4) * (ty + 4) + (TX + 2) * (ty + 2)) * 8; }
+constexpr int sweep_waves(int ty) {
+    return (160 * 1024) / sweep_lds_bytes(ty) >= 4 ? 4 : ((160 * 1024) / sweep_lds_bytes(ty) < 1 ? 1 : (160 * 1024) / sweep_lds_bytes(ty));
+}
 
 // Neighbourhood of a cell read from a parity-split LDS plane set.  `c` is the
 // word offset of the cell's row-half position for the neighbours in its own
@@ -57,6 +64,7 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
                                             const int z1) {
     using Cell = typename K::Cell;
     using Src = typename K::Src;
+    static_assert(sizeof(Cell) == 8, "sweep_lds_bytes assumes 8-byte cells");
     constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
     constexpr int HW2 = W2 / 2, HW1 = W1 / 2;     // half-row lengths (34, 33)
     constexpr int NP2 = W2 * H2;
@@ -97,37 +105,42 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
             off2[s] = (int)(g.off0 + gx + (int64_t)gy * g.sy);
         }
     }
+    // The loop below is unrolled twice, so step t = z0 + 2k + b works on planes
+    // of fixed parity per b: red on p = t - 1, black on p2 = t - 2.  Every
+    // parity-dependent offset is therefore chosen once here, per b.
+    const int zpar = z0 & 1;
+    // The two parities of a slot's column are swapped between b = 0 and b = 1,
+    // so several per-b offsets coincide with the other b's partner offsets
+    // (the cell itself at parity par is the partner's source at 1 - par); only
+    // one copy of each is kept.
     // red cells: ring-1 row r, pair m; parity par = (y0 + r + p) & 1 puts the red cell at
     // ring-1 column 2m + par and the black one at 2m + 1 - par
     bool rv[NR];              // slot exists
-    int rpar0[NR];            // parity at p = 0
-    int rc[NR][2], ro[NR][2]; // nb_split offsets in P0 (ring 2) for each parity
-    int rw[NR][2], rb[NR][2]; // P1 cells of the red and the black cell
-    int rsrc[NR][2];          // P0 cell of the black cell (copied into P1)
+    int rc[NR][2], ro[NR][2]; // nb_split offsets in P0 (ring 2), per b; ro[q][1-b] is also
+                              // the P0 cell of step b's black partner (copied into P1)
+    int rw[NR][2];            // P1 cell of step b's red cell; rw[q][1-b] holds its black partner
     int rg[NR][2];            // global in-plane index of the red cell (-1: not a cell)
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         const int e = tid + q * NTH;
         rv[q] = e < RH * H1;
         const int r = rv[q] ? e / RH : 0, m = rv[q] ? e - r * RH : 0;
-        rpar0[q] = (y0 + r) & 1;
         const int gy = y0 - 1 + r;
 #pragma unroll
-        for (int par = 0; par < 2; ++par) {
+        for (int b = 0; b < 2; ++b) {
+            const int par = (y0 + r + zpar + b + 1) & 1;
             const int Y = r + 1;                                  // ring-2 row
-            rc[q][par] = Y * W2 + par * HW2 + m;                  // x-1 of the red cell (X = 2m+par+1)
-            ro[q][par] = Y * W2 + (1 - par) * HW2 + m + par;      // the red cell itself
-            rw[q][par] = r * W1 + par * HW1 + m;                  // ring-1 column 2m+par
-            rb[q][par] = r * W1 + (1 - par) * HW1 + m;            // ring-1 column 2m+1-par
-            rsrc[q][par] = Y * W2 + par * HW2 + m + 1 - par;      // ring-2 column 2m+2-par
+            rc[q][b] = Y * W2 + par * HW2 + m;                    // x-1 of the red cell (X = 2m+par+1)
+            ro[q][b] = Y * W2 + (1 - par) * HW2 + m + par;        // the red cell itself
+            rw[q][b] = r * W1 + par * HW1 + m;                    // ring-1 column 2m+par
             int gx = x0 - 1 + 2 * m + par, wy = gy;
             if (DIR) {
-                rg[q][par] = (rv[q] && gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1)
-                                 ? (int)(g.off0 + gx + (int64_t)gy * g.sy) : -1;
+                rg[q][b] = (rv[q] && gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1)
+                               ? (int)(g.off0 + gx + (int64_t)gy * g.sy) : -1;
             } else {
                 gx = wrapi(gx, g.n0);
                 wy = wrapi(gy, g.n1);
-                rg[q][par] = rv[q] ? (int)(gx + (int64_t)wy * g.sy) : -1;
+                rg[q][b] = rv[q] ? (int)(gx + (int64_t)wy * g.sy) : -1;
             }
         }
     }
@@ -136,28 +149,26 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     // waves so that red and black work land on different waves.
     constexpr int BOFF = NTH > BH * TY ? ((NTH - BH * TY) / 64) * 64 : 0;
     const int tb = tid - BOFF;
-    bool bv[NB];
-    int bpar0[NB], bm2[NB];
-    int bc[NB][2], bo[NB][2], brd[NB][2];
-    int64_t brow[NB];
+    int bc[NB][2], bo[NB][2];   // nb_split offsets in P1, per b; bo[q][1-b] is the red partner
+    int bcell[NB][2];           // in-plane global index of the black cell; [1-b]: its red partner
+    bool bin[NB][2];            // that cell lies inside the grid
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int e = tb + q * NTH;
         const int r = e >= 0 ? e / BH : 0, m = e >= 0 ? e - r * BH : 0;
         const int gy = y0 + r;
-        bv[q] = e >= 0 && e < BH * TY && gy < g.n1;
-        bpar0[q] = (y0 + r + 1) & 1;
-        bm2[q] = 2 * m;
-        brow[q] = g.off0 + (int64_t)gy * g.sy + x0 + 2 * m;
+        const bool bv = e >= 0 && e < BH * TY && gy < g.n1;
+        const int row = (int)(g.off0 + (int64_t)gy * g.sy) + x0 + 2 * m;
 #pragma unroll
-        for (int par = 0; par < 2; ++par) {
+        for (int b = 0; b < 2; ++b) {
+            const int par = (y0 + r + zpar + b + 1) & 1;
             const int Y = r + 1;                                   // ring-1 row
-            bc[q][par] = Y * W1 + par * HW1 + m;                   // x-1 of the black cell (X = 2m+par+1)
-            bo[q][par] = Y * W1 + (1 - par) * HW1 + m + par;       // the black cell itself
-            brd[q][par] = Y * W1 + par * HW1 + m + 1 - par;        // red partner at column 2m+2-par
+            bc[q][b] = Y * W1 + par * HW1 + m;                     // x-1 of the black cell (X = 2m+par+1)
+            bo[q][b] = Y * W1 + (1 - par) * HW1 + m + par;         // the black cell itself
+            bcell[q][b] = row + par;
+            bin[q][b] = bv && 2 * m + par < g.n0 - x0;
         }
     }
-    const int bxmax = g.n0 - x0;   // columns >= bxmax are outside the grid
     auto plane_off = [&](int t, bool& zok) -> int64_t {
         int gz;
         if (DIR) { gz = t; zok = t >= -1 && t <= g.n2; }
@@ -177,26 +188,27 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     };
     auto slot = [](int z) { return (z + 3) % 3; };   // z >= -2
 
-    auto fetch_red = [&](int p, Src (&sr)[NR]) {
+    // sources of the red cells of plane p, whose parity is that of step b's red plane
+    auto fetch_red = [&](int p, auto btag, Src (&sr)[NR]) {
+        constexpr int b = decltype(btag)::value;
         bool zok;
         int64_t zo = plane_off(p, zok);
         if (DIR) zok = p >= 0 && p < g.n2;
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
-            const int par = (rpar0[q] + p) & 1;
-            const int gi = rg[q][par];
+            const int gi = rg[q][b];
             sr[q] = (zok && gi >= 0) ? k.src(zo + gi) : k.zero_src();
         }
     };
-    auto fetch_black = [&](int p2, Src (&sr)[NB]) {
+    // sources of the black cells of plane p2, whose parity is that of step b's black plane
+    auto fetch_black = [&](int p2, auto btag, Src (&sr)[NB]) {
+        constexpr int b = decltype(btag)::value;
         const int64_t zo = (int64_t)p2 * g.sz;
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int par = (bpar0[q] + p2) & 1;
-            const bool ok = bv[q] && bm2[q] + par < bxmax;
-            sr[q] = ok ? k.src(zo + brow[q] + par) : k.zero_src();
-        }
+        for (int q = 0; q < NB; ++q) sr[q] = bin[q][b] ? k.src(zo + bcell[q][b]) : k.zero_src();
     };
+    using B0 = std::integral_constant<int, 0>;
+    using B1 = std::integral_constant<int, 1>;
 
     // Software pipeline over z.  Step t computes red on plane t-1 (u^0 planes
     // t-2..t in LDS) and black on plane t-2 (u^1 planes t-3..t-1 in LDS).
@@ -216,8 +228,8 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
             store_plane(slot(t), r2);
         }
         load_plane(z0 + 1, pq[1]);
-        fetch_red(z0 - 1, rq[0]);
-        fetch_red(z0, rq[1]);
+        fetch_red(z0 - 1, B0(), rq[0]);   // red plane of step z0
+        fetch_red(z0, B1(), rq[1]);       // red plane of step z0 + 1
     }
     __syncthreads();
 
@@ -234,16 +246,15 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
                 if (!rv[q]) continue;
-                const int par = (rpar0[q] + p) & 1;
-                const int c = rc[q][par], o = ro[q][par];
+                const int c = rc[q][b], o = ro[q][b];
                 Cell val = Pc[o];
-                const bool interior = DIR ? (rg[q][par] >= 0 && p >= 0 && p < g.n2) : true;
+                const bool interior = DIR ? (rg[q][b] >= 0 && p >= 0 && p < g.n2) : true;
                 if (interior) val = k.template update<W2>(Pm, Pc, Pp, c, o, rq[b][q]);
-                Q1[rw[q][par]] = val;
-                Q1[rb[q][par]] = Pc[rsrc[q][par]];
+                Q1[rw[q][b]] = val;
+                Q1[rw[q][1 - b]] = Pc[ro[q][1 - b]];
             }
         }
-        if (t + 1 <= z1) fetch_red(t + 1, rq[b]);
+        if (t + 1 <= z1) fetch_red(t + 1, parity_tag, rq[b]);   // plane t+1 has the parity of t-1
         __syncthreads();
         // ---- black phase on plane p2, tile interior: P1 -> u^2 -----------------
         if (p2 >= z0) {
@@ -253,24 +264,22 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
             const int64_t zo = (int64_t)p2 * g.sz;
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
-                if (!bv[q]) continue;
-                const int par = (bpar0[q] + p2) & 1;
-                if (bm2[q] + par < bxmax)
-                    k.out(zo + brow[q] + par, k.template update<W1>(Rm, Rc, Rp, bc[q][par], bo[q][par], bq[b][q]));
-                if (bm2[q] + 1 - par < bxmax) k.out(zo + brow[q] + 1 - par, Rc[brd[q][par]]);
+                if (bin[q][b])
+                    k.out(zo + bcell[q][b], k.template update<W1>(Rm, Rc, Rp, bc[q][b], bo[q][b], bq[b][q]));
+                if (bin[q][1 - b]) k.out(zo + bcell[q][1 - b], Rc[bo[q][1 - b]]);
             }
         }
-        if (t >= z0 && t < z1) fetch_black(t, bq[b]);
+        if (t >= z0 && t < z1) fetch_black(t, parity_tag, bq[b]);   // plane t has the parity of t-2
         // ---- commit u^0 plane t+1 (its slot held plane t-2, last read by this red phase)
         if (t + 1 <= z1 + 1) store_plane(slot(t + 1), pq[b ^ 1]);
         __syncthreads();
     };
     int t = z0;
     for (; t + 1 <= z1 + 1; t += 2) {
-        step(t, std::integral_constant<int, 0>());
-        step(t + 1, std::integral_constant<int, 1>());
+        step(t, B0());
+        step(t + 1, B1());
     }
-    if (t <= z1 + 1) step(t, std::integral_constant<int, 0>());
+    if (t <= z1 + 1) step(t, B0());
 }
 
 }  // namespace vmg

@@ -263,6 +263,50 @@ __global__ void k_ghost_refresh_batch(const Geom* __restrict__ gs, const int2* _
     u[gi] = ref[gi] + (T)sign * (u[ii] - ref[ii]);
 }
 
+// Fine half of a tiled prolongation u^h += P c (cell-centred trilinear, weights
+// 3/4 and 1/4 per axis) once the coarse values c around the tile sit in LDS
+// (C[.][.][0] is coarse cell (cx0, cy0, cz0)).  Lane = fine x within the
+// 64-wide tile; wave w takes fine rows q = w, w + 4, ... of the 8 x pz rows
+// (y fastest), NBAT rows per batch so that NBAT loads are in flight.
+template <int NBAT, typename T, int CZM, int CY, int CX>
+__device__ __forceinline__ void prolong_tile_rows(const Geom& gf, T* __restrict__ uf,
+                                                  const T (&C)[CZM][CY][CX], int x0, int y0, int z0,
+                                                  int cx0, int cy0, int cz0, int pz) {
+    const int i = x0 + (int)(threadIdx.x & 63);
+    if (i >= gf.n0) return;
+    const int Ii = (i >> 1) - cx0, si = (i & 1) ? 1 : -1;
+    const T a = T(0.75), b = T(0.25);
+    constexpr int NW = NT / 64;
+    const int nq = 8 * pz;
+    for (int q0 = (int)(threadIdx.x >> 6); q0 < nq; q0 += NW * NBAT) {
+        T v[NBAT];
+        int64_t gi[NBAT];
+        bool ok[NBAT];
+#pragma unroll
+        for (int u = 0; u < NBAT; ++u) {
+            const int q = q0 + u * NW;
+            const int j = y0 + (q & 7), k = z0 + (q >> 3);
+            ok[u] = q < nq && j < gf.n1 && k < gf.n2;
+            gi[u] = ok[u] ? cell_index(gf, i, j, k) : 0;
+            v[u] = ok[u] ? uf[gi[u]] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < NBAT; ++u) {
+            if (!ok[u]) continue;
+            const int q = q0 + u * NW;
+            const int j = y0 + (q & 7), k = z0 + (q >> 3);
+            const int Jj = (j >> 1) - cy0, sj = (j & 1) ? 1 : -1;
+            const int Kk = (k >> 1) - cz0, sk = (k & 1) ? 1 : -1;
+            const T x00 = a * C[Kk][Jj][Ii] + b * C[Kk][Jj][Ii + si];
+            const T x10 = a * C[Kk][Jj + sj][Ii] + b * C[Kk][Jj + sj][Ii + si];
+            const T x01 = a * C[Kk + sk][Jj][Ii] + b * C[Kk + sk][Jj][Ii + si];
+            const T x11 = a * C[Kk + sk][Jj + sj][Ii] + b * C[Kk + sk][Jj + sj][Ii + si];
+            const T y0v = a * x00 + b * x10, y1v = a * x01 + b * x11;
+            uf[gi[u]] = v[u] + (a * y0v + b * y1v);
+        }
+    }
+}
+
 static inline int grid_for(int64_t n, int cap = 65536) {
     int64_t b = (n + NT - 1) / NT;
     if (b < 1) b = 1;

@@ -151,7 +151,8 @@ vmg_status build_plan(Plan* P, const vmg_grid* grids, int n_grids, const vmg_par
     for (auto& G : P->grids)
         for (auto& L : G.lev) nb = std::max<int64_t>(nb, resid_blocks(L.g));
     nb = std::max<int64_t>(nb, batch_partials_needed(P));
-    if ((st = dalloc(P, (void**)&P->partials, sizeof(double) * R_NSLOT * (size_t)nb)) != VMG_OK) return st;
+    if ((st = dalloc(P, (void**)&P->partials, 2 * sizeof(double) * R_NSLOT * (size_t)nb)) != VMG_OK) return st;
+    P->partials_b = P->partials + R_NSLOT * (size_t)nb;
     if (hipHostMalloc((void**)&P->host_norm, sizeof(NormOut) * P->grids.size(), hipHostMallocDefault) !=
         hipSuccess)
         return fail(VMG_ENOMEM, "hipHostMalloc failed");
@@ -250,12 +251,16 @@ static hipError_t vcycle(Plan* P, GridState& G, int l) {
     if ((e = launch_residual_restrict(L.g, C.g, P->coef, L.phi[L.cur], L.delta, level_f(P, G, l), L.sc,
                                       C.phi[0], C.phiold, C.rd, P->partials, &nb, P->stream)) != hipSuccess)
         return e;
-    if ((e = launch_finalize(P->partials, nb, L.g.ncell, periodic, 0, L.sc, nullptr, P->stream)) != hipSuccess)
-        return e;
-    if ((e = launch_fas_rhs(C.g, P->coef, C.phi[0], C.delta, C.rd, C.f, P->partials, &nb, P->stream)) !=
+    int nbc = 0;
+    if ((e = launch_fas_rhs(C.g, P->coef, C.phi[0], C.delta, C.rd, C.f, P->partials_b, &nbc, P->stream)) !=
         hipSuccess)
         return e;
-    if ((e = launch_finalize(P->partials, nb, C.g.ncell, periodic, 1, C.sc, nullptr, P->stream)) != hipSuccess)
+    // new cbar of level l (read next by its post-smoothing) and of level l+1 (its
+    // first sweep); with Dirichlet faces there is no cbar and nothing to finalize
+    if (periodic &&
+        (e = launch_finalize_pair(FinJob{P->partials, nb, 1, 0, L.g.ncell, L.sc, nullptr, nullptr},
+                                  FinJob{P->partials_b, nbc, 1, 1, C.g.ncell, C.sc, nullptr, nullptr},
+                                  P->stream)) != hipSuccess)
         return e;
     if ((e = vcycle(P, G, l + 1)) != hipSuccess) return e;
     if ((e = launch_prolong(L.g, C.g, L.phi[L.cur], C.phi[C.cur], C.phiold, P->stream)) != hipSuccess)

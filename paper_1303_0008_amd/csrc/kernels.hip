@@ -76,7 +76,7 @@ struct SmoothK {
 };
 
 template <int TY, int DIR, bool HAS_F>
-__global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth(SmoothArgs a) {
+__global__ void __launch_bounds__(SNT, sweep_waves(TY)) k_smooth(SmoothArgs a) {
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % a.tiles_x;
     b /= a.tiles_x;
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth(SmoothArgs a
 // Dirichlet grid of a batch at one level in one launch.  `proto` carries the
 // pooled level buffers and coefficients; geoms[w.x] locates grid w.x in them.
 template <int TY, bool HAS_F>
-__global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth_batch(SmoothArgs proto, const Geom* __restrict__ geoms,
+__global__ void __launch_bounds__(SNT, sweep_waves(TY)) k_smooth_batch(SmoothArgs proto, const Geom* __restrict__ geoms,
                                                      const int4* __restrict__ items, int nitems) {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int4 w = items[it];
@@ -414,9 +414,16 @@ __global__ void __launch_bounds__(NT) k_fas_rhs(Geom g, Coef c, const double* __
     block_store_partials(acc, partials);
 }
 
-__global__ void __launch_bounds__(NT) k_finalize(const double* __restrict__ partials, int nblocks,
-                                                 int64_t ncell, int periodic, int mode,
-                                                 LevelScalars* sc, NormOut* out, LevelScalars* inner) {
+// Block b finalizes job b (one launch can close the restriction pass of level
+// l and the coarse right-hand-side pass of level l+1).
+__global__ void __launch_bounds__(NT) k_finalize(FinJobs jobs) {
+    const FinJob& J = jobs.j[blockIdx.x];
+    const double* __restrict__ partials = J.partials;
+    const int nblocks = J.nblocks, periodic = J.periodic, mode = J.mode;
+    const int64_t ncell = J.ncell;
+    LevelScalars* sc = J.sc;
+    NormOut* out = J.out;
+    LevelScalars* inner = J.inner;
     __shared__ double red[NT / 64][R_NSLOT];
     double acc[R_NSLOT];
 #pragma unroll
@@ -540,24 +547,7 @@ __global__ void __launch_bounds__(NT) k_prolong_tiled(Geom gf, Geom gc, double* 
         C[lz][ly][lx] = v;
     }
     __syncthreads();
-    const int lxf = threadIdx.x & 63;          // fine x within the tile
-    const int i = x0 + lxf;
-    if (i >= gf.n0) return;
-    const int Ii = (i >> 1) - cx0, si = (i & 1) ? 1 : -1;
-    for (int q = threadIdx.x >> 6; q < 8 * pz; q += NT / 64) {
-        const int j = y0 + (q & 7), k = z0 + (q >> 3);
-        if (j >= gf.n1 || k >= gf.n2) continue;
-        const int Jj = (j >> 1) - cy0, sj = (j & 1) ? 1 : -1;
-        const int Kk = (k >> 1) - cz0, sk = (k & 1) ? 1 : -1;
-        const double c000 = C[Kk][Jj][Ii], c100 = C[Kk][Jj][Ii + si];
-        const double c010 = C[Kk][Jj + sj][Ii], c110 = C[Kk][Jj + sj][Ii + si];
-        const double c001 = C[Kk + sk][Jj][Ii], c101 = C[Kk + sk][Jj][Ii + si];
-        const double c011 = C[Kk + sk][Jj + sj][Ii], c111 = C[Kk + sk][Jj + sj][Ii + si];
-        const double x00 = 0.75 * c000 + 0.25 * c100, x10 = 0.75 * c010 + 0.25 * c110;
-        const double x01 = 0.75 * c001 + 0.25 * c101, x11 = 0.75 * c011 + 0.25 * c111;
-        const double y0v = 0.75 * x00 + 0.25 * x10, y1v = 0.75 * x01 + 0.25 * x11;
-        phif[cell_index(gf, i, j, k)] += 0.75 * y0v + 0.25 * y1v;
-    }
+    prolong_tile_rows<1>(gf, phif, C, x0, y0, z0, cx0, cy0, cz0, pz);   // FP64 rows already stream well
 }
 
 // ---------------------------------------------------------------------------
@@ -1130,8 +1120,18 @@ hipError_t launch_fas_rhs(const Geom& g, const Coef& c, const double* phi, const
 
 hipError_t launch_finalize(const double* partials, int nblocks, int64_t ncell, int periodic,
                            int mode, LevelScalars* sc, NormOut* out, hipStream_t s, LevelScalars* inner) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NT), 0, s, partials, nblocks, ncell, periodic, mode,
-                       sc, out, inner);
+    FinJobs j;
+    j.j[0] = FinJob{partials, nblocks, periodic, mode, ncell, sc, out, inner};
+    j.j[1] = j.j[0];
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NT), 0, s, j);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_pair(const FinJob& a, const FinJob& b, hipStream_t s) {
+    FinJobs j;
+    j.j[0] = a;
+    j.j[1] = b;
+    hipLaunchKernelGGL(k_finalize, dim3(2), dim3(NT), 0, s, j);
     return hipGetLastError();
 }
 

@@ -83,7 +83,7 @@ struct CorrK {
 };
 
 template <int TY, int DIR, bool ZERO_E>
-__global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth_corr(CorrArgs a) {
+__global__ void __launch_bounds__(SNT, sweep_waves(TY)) k_smooth_corr(CorrArgs a) {
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % a.tiles_x;
     b /= a.tiles_x;
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth_corr(CorrArg
 
 // persistent sweep over a (grid, tile x, tile y, z chunk) work list (Dirichlet batches)
 template <int TY>
-__global__ void __launch_bounds__(SNT, SNT_WAVES_PER_SIMD) k_smooth_corr_batch(CorrArgs proto, const Geom* __restrict__ geoms,
+__global__ void __launch_bounds__(SNT, sweep_waves(TY)) k_smooth_corr_batch(CorrArgs proto, const Geom* __restrict__ geoms,
                                                           const int4* __restrict__ items, int nitems) {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int4 w = items[it];
@@ -853,21 +853,7 @@ __global__ void __launch_bounds__(NT) k_prolong_corr_tiled(Geom gf, Geom gc, flo
         C[lz][ly][lx] = v;
     }
     __syncthreads();
-    const int lxf = threadIdx.x & 63;
-    const int i = x0 + lxf;
-    if (i >= gf.n0) return;
-    const int Ii = (i >> 1) - cx0, si = (i & 1) ? 1 : -1;
-    for (int q = threadIdx.x >> 6; q < 8 * pzf; q += NT / 64) {
-        const int j = y0 + (q & 7), k = z0 + (q >> 3);
-        if (j >= gf.n1 || k >= gf.n2) continue;
-        const int Jj = (j >> 1) - cy0, sj = (j & 1) ? 1 : -1;
-        const int Kk = (k >> 1) - cz0, sk = (k & 1) ? 1 : -1;
-        const float x00 = 0.75f * C[Kk][Jj][Ii] + 0.25f * C[Kk][Jj][Ii + si];
-        const float x10 = 0.75f * C[Kk][Jj + sj][Ii] + 0.25f * C[Kk][Jj + sj][Ii + si];
-        const float x01 = 0.75f * C[Kk + sk][Jj][Ii] + 0.25f * C[Kk + sk][Jj][Ii + si];
-        const float x11 = 0.75f * C[Kk + sk][Jj + sj][Ii] + 0.25f * C[Kk + sk][Jj + sj][Ii + si];
-        ef[cell_index(gf, i, j, k)] += 0.75f * (0.75f * x00 + 0.25f * x10) + 0.25f * (0.75f * x01 + 0.25f * x11);
-    }
+    prolong_tile_rows<8>(gf, ef, C, x0, y0, z0, cx0, cy0, cz0, pzf);
 }
 
 // ---------------------------------------------------------------------------

@@ -114,13 +114,16 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e) {
     if ((e = launch_rr_corr(L.g, C.g, cf, L.e[L.ecur], L.pt, L.t0, L.r, L.scf, C.e[0], C.eold, C.rdf, C.pt,
                             P->partials, &nb, P->stream)) != hipSuccess)
         return e;
-    if ((e = launch_finalize(P->partials, nb, L.g.ncell, periodic, 0, L.scf, nullptr, P->stream)) != hipSuccess)
-        return e;
     // coarse rhs; also the coarse t0 (FP64 discriminant of the restricted base state)
-    if ((e = launch_fas_corr(C.g, cc, P->coef, C.delta, C.e[0], C.pt, C.t0, C.rdf, C.r, P->partials, &nb,
+    int nbc = 0;
+    if ((e = launch_fas_corr(C.g, cc, P->coef, C.delta, C.e[0], C.pt, C.t0, C.rdf, C.r, P->partials_b, &nbc,
                              P->stream)) != hipSuccess)
         return e;
-    if ((e = launch_finalize(P->partials, nb, C.g.ncell, periodic, 1, C.scf, nullptr, P->stream)) != hipSuccess)
+    // cbar of level l's correction equation (its post-smoothing) and of level l+1
+    if (periodic &&
+        (e = launch_finalize_pair(FinJob{P->partials, nb, 1, 0, L.g.ncell, L.scf, nullptr, nullptr},
+                                  FinJob{P->partials_b, nbc, 1, 1, C.g.ncell, C.scf, nullptr, nullptr},
+                                  P->stream)) != hipSuccess)
         return e;
     if ((e = inner_vcycle(P, G, l + 1, false)) != hipSuccess) return e;
     if ((e = launch_prolong_corr(L.g, C.g, L.e[L.ecur], C.e[C.ecur], C.eold, P->stream)) != hipSuccess) return e;

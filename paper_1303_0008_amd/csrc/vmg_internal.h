@@ -143,6 +143,20 @@ hipError_t launch_fas_rhs(const Geom& g, const Coef& c, const double* phi, const
 hipError_t launch_finalize(const double* partials, int nblocks, int64_t ncell, int periodic,
                            int mode, LevelScalars* sc, NormOut* out, hipStream_t s,
                            LevelScalars* inner = nullptr);
+// One reduction of a pass's block partials (the arguments of launch_finalize).
+struct FinJob {
+    const double* partials;
+    int nblocks, periodic, mode;
+    int64_t ncell;
+    LevelScalars* sc;
+    NormOut* out;
+    LevelScalars* inner;
+};
+struct FinJobs {
+    FinJob j[2];
+};
+// Two independent reductions in one launch (one block each).
+hipError_t launch_finalize_pair(const FinJob& a, const FinJob& b, hipStream_t s);
 hipError_t launch_prolong(const Geom& gf, const Geom& gc, double* phif, const double* phic,
                           const double* phiold_c, hipStream_t s);
 hipError_t launch_coarse_solve(const Geom& g, const Coef& c, double* phi, const double* delta,

@@ -83,6 +83,7 @@ struct Plan {
     bool has_source = false;
     bool solved = false;
     double* partials = nullptr;
+    double* partials_b = nullptr;          // second set (coarse right-hand-side pass)
     NormOut* host_norm = nullptr;          // pinned
     hipGraphExec_t graph[2];
     bool graph_ok[2] = {false, false};
