@@ -42,38 +42,48 @@ __device__ __forceinline__ double sqrt_nr(double D) {   // D > 0
     return fma(hy, fma(-s, s, D), s);
 }
 
-// Physical root Q of the per-cell quadratic (Sec. III.A, Eq. one_branch at w = 1/3)
-// from the 18 neighbours; also returns the neighbour sum S and the guard flag.
-__device__ __forceinline__ double nl_root(const Nb& v, double dl, const Coef& c, double inv_h4,
-                                          double& S, bool& guard) {
+// Right-hand side q = alpha Sigma0 + kappa delta of a cell's quadratic (Sec. III.A)
+// from its 18 neighbours (Sigma0 h^4 = (dxy^2 + dxz^2 + dyz^2)/3 + (bxy^2 + bxz^2 +
+// byz^2)/8, the phi_c-free part of (Lap phi)^2 - (d_i d_j phi)^2 at w = 1/3); also
+// the neighbour sum S.  alpha/h^4 is folded into the two weights, which are
+// kernel constants.
+__device__ __forceinline__ double nl_q(const Nb& v, double dl, const Coef& c, double inv_h4, double& S) {
     const double sx = v.xp + v.xm, sy = v.yp + v.ym, sz = v.zp + v.zm;
     S = sx + sy + sz;
     const double dxy = sx - sy, dxz = sx - sz, dyz = sy - sz;
     const double bxy = (v.xpyp + v.xmym) - (v.xpym + v.xmyp);
     const double bxz = (v.xpzp + v.xmzm) - (v.xpzm + v.xmzp);
     const double byz = (v.ypzp + v.ymzm) - (v.ypzm + v.ymzp);
-    const double s0 = ((dxy * dxy + dxz * dxz + dyz * dyz) * (1.0 / 3.0)
-                     + (bxy * bxy + bxz * bxz + byz * byz) * 0.125) * inv_h4;
-    const double q = c.alpha * s0 + c.kappa * dl;
+    const double sd = fma(dxy, dxy, fma(dxz, dxz, dyz * dyz));
+    const double sb = fma(bxy, bxy, fma(bxz, bxz, byz * byz));
+    const double a3 = c.alpha * inv_h4 * (1.0 / 3.0), a8 = c.alpha * inv_h4 * 0.125;
+    return fma(a3, sd, fma(a8, sb, c.kappa * dl));
+}
+
+// Physical root Q of the per-cell quadratic (Sec. III.A, Eq. one_branch at w = 1/3)
+// from D = 1 + 8 alpha q / 3 > 0: Q = 2q / (1 + sqrt D) = (sqrt D - 1) 3 / (4 alpha).
+// The second form needs no division; its cancellation near D = 1 costs an
+// absolute error of about eps sqrt(D) 3 / (4 |alpha|), below the rounding of
+// the residual when |alpha| >= 1e-2 (Coef::sqrt_form), else the first is used.
+__device__ __forceinline__ double nl_root_of(double q, double sD, const Coef& c) {
+    return c.sqrt_form ? fma(sD, -c.vertex, c.vertex) : 2.0 * q * rcp_nr(1.0 + sD);
+}
+
+// Q and S of a cell and the guard flag (D <= 0: the vertex -3 / (4 alpha); D == 0
+// gives the vertex from either form, so the guard branch is continuous there).
+__device__ __forceinline__ double nl_root(const Nb& v, double dl, const Coef& c, double inv_h4,
+                                          double& S, bool& guard) {
+    const double q = nl_q(v, dl, c, inv_h4, S);
     const double D = 1.0 + c.c8 * q;
     guard = !(D > 0.0);
-    // D == 0 gives 2q = vertex, so the guard branch is continuous there
-    return guard ? c.vertex : 2.0 * q * rcp_nr(1.0 + sqrt_nr(D));
+    return guard ? c.vertex : nl_root_of(q, sqrt_nr(D), c);
 }
 
 // nl_root that also returns the discriminant D and +-sqrt|D| (sign of D): the
 // outer FP64 pass of the mixed path hands +-sqrt|D0| to the FP32 inner problem.
 __device__ __forceinline__ double nl_root_t0(const Nb& v, double dl, const Coef& c, double inv_h4,
                                              double& S, bool& guard, double& t0) {
-    const double sx = v.xp + v.xm, sy = v.yp + v.ym, sz = v.zp + v.zm;
-    S = sx + sy + sz;
-    const double dxy = sx - sy, dxz = sx - sz, dyz = sy - sz;
-    const double bxy = (v.xpyp + v.xmym) - (v.xpym + v.xmyp);
-    const double bxz = (v.xpzp + v.xmzm) - (v.xpzm + v.xmzp);
-    const double byz = (v.ypzp + v.ymzm) - (v.ypzm + v.ymzp);
-    const double s0 = ((dxy * dxy + dxz * dxz + dyz * dyz) * (1.0 / 3.0)
-                     + (bxy * bxy + bxz * bxz + byz * byz) * 0.125) * inv_h4;
-    const double q = c.alpha * s0 + c.kappa * dl;
+    const double q = nl_q(v, dl, c, inv_h4, S);
     const double D = 1.0 + c.c8 * q;
     guard = !(D > 0.0);
     if (guard) {
@@ -82,20 +92,14 @@ __device__ __forceinline__ double nl_root_t0(const Nb& v, double dl, const Coef&
     }
     const double sD = sqrt_nr(D);
     t0 = sD;
-    return 2.0 * q * rcp_nr(1.0 + sD);
+    return nl_root_of(q, sD, c);
 }
 
 // Discriminant D = 1 + 8 alpha q / 3 of a cell's quadratic (Sec. III.A) from
 // its 18 neighbours and density (the mixed path's base state).
 __device__ __forceinline__ double base_discriminant(const Nb& v, double dl, const Coef& c, double inv_h4) {
-    const double sx = v.xp + v.xm, sy = v.yp + v.ym, sz = v.zp + v.zm;
-    const double dxy = sx - sy, dxz = sx - sz, dyz = sy - sz;
-    const double bxy = (v.xpyp + v.xmym) - (v.xpym + v.xmyp);
-    const double bxz = (v.xpzp + v.xmzm) - (v.xpzm + v.xmzp);
-    const double byz = (v.ypzp + v.ymzm) - (v.ypzm + v.ymzp);
-    const double s0 = ((dxy * dxy + dxz * dxz + dyz * dyz) * (1.0 / 3.0)
-                     + (bxy * bxy + bxz * bxz + byz * byz) * 0.125) * inv_h4;
-    return 1.0 + c.c8 * (c.alpha * s0 + c.kappa * dl);
+    double S;
+    return 1.0 + c.c8 * nl_q(v, dl, c, inv_h4, S);
 }
 
 // Correction of the mixed path's FP32 inner problem: dq = alpha Phi(2 phi~ + e, e)
@@ -116,13 +120,14 @@ __device__ __forceinline__ float dq_corr(const NbT<float>& e, const NbT<float>& 
     const float bxy_w = 2.0f * ((p.xpyp + p.xmym) - (p.xpym + p.xmyp)) + bxy_e;
     const float bxz_w = 2.0f * ((p.xpzp + p.xmzm) - (p.xpzm + p.xmzp)) + bxz_e;
     const float byz_w = 2.0f * ((p.ypzp + p.ymzm) - (p.ypzm + p.ymzp)) + byz_e;
-    const float ph = (dxy_w * dxy_e + dxz_w * dxz_e + dyz_w * dyz_e) * (1.0f / 3.0f)
-                   + (bxy_w * bxy_e + bxz_w * bxz_e + byz_w * byz_e) * 0.125f;
-    return a_ih4 * ph;
+    const float pd = fmaf(dxy_w, dxy_e, fmaf(dxz_w, dxz_e, dyz_w * dyz_e));
+    const float pb = fmaf(bxy_w, bxy_e, fmaf(bxz_w, bxz_e, byz_w * byz_e));
+    // alpha/h^4 folded into the weights 1/3 and 1/8 (kernel constants)
+    return fmaf(a_ih4 * (1.0f / 3.0f), pd, a_ih4 * 0.125f * pb);
 }
 
 __device__ __forceinline__ float dQ_of(float dq, float t0, const CoefF& c) {
-    const float D0 = t0 >= 0.0f ? t0 * t0 : -t0 * t0;
+    const float D0 = t0 * fabsf(t0);   // sign(t0) t0^2
     const float s0 = fmaxf(t0, 0.0f);
     const float D1 = D0 + c.c8 * dq;
     const float s1 = __builtin_amdgcn_sqrtf(fmaxf(D1, 0.0f));

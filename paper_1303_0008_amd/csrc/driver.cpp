@@ -65,6 +65,7 @@ Coef make_coef(double alpha, double kappa) {
     c.kappa = kappa;
     c.c8 = 8.0 * alpha / 3.0;
     c.vertex = alpha != 0.0 ? -3.0 / (4.0 * alpha) : 0.0;
+    c.sqrt_form = std::fabs(alpha) >= 1e-2 ? 1 : 0;
     return c;
 }
 

@@ -45,13 +45,14 @@ struct SmoothK {
     const double* __restrict__ delta;
     const double* __restrict__ f;
     Coef c;
-    double h2, inv_h4, cb;
+    double inv_h4, h2_6, cb_6;   // 1/h^4, h^2/6, h^2 cbar/6
 
     __device__ SmoothK(const SmoothArgs& a, const Geom& g, bool periodic)
         : pin(a.pin), pout(a.pout), delta(a.delta), f(a.f), c(a.c) {
-        h2 = g.h * g.h;
+        const double h2 = g.h * g.h;
         inv_h4 = 1.0 / (h2 * h2);
-        cb = periodic ? a.sc->cbar : 0.0;
+        h2_6 = h2 * (1.0 / 6.0);
+        cb_6 = periodic ? h2_6 * a.sc->cbar : 0.0;
     }
     __device__ double cell(int64_t i) const { return pin[i]; }
     __device__ double zero_cell() const { return 0.0; }
@@ -70,7 +71,9 @@ struct SmoothK {
         double S;
         bool gd;
         const double Q = nl_root(v, s.dl, c, inv_h4, S, gd);
-        return (S - h2 * (Q + (HAS_F ? s.f : 0.0) - cb)) * (1.0 / 6.0);
+        // (S - h^2 (Q + f - cbar)) / 6
+        const double base = HAS_F ? fma(-h2_6, s.f, cb_6) : cb_6;
+        return fma(S, 1.0 / 6.0, fma(-h2_6, Q, base));
     }
     __device__ void out(int64_t i, double v) const { pout[i] = v; }
 };

@@ -52,11 +52,12 @@ struct CorrK {
     const float* __restrict__ t0;
     const float* __restrict__ r;
     CoefF c;
-    float cb;
+    float h2_6, cb_6;   // h^2/6, h^2 cbar/6
 
     __device__ CorrK(const CorrArgs& a, bool periodic)
         : ein(a.ein), eout(a.eout), pt(a.pt), t0(a.t0), r(a.r), c(a.c) {
-        cb = periodic ? (float)a.sc->cbar : 0.0f;
+        h2_6 = c.h2 * (1.0f / 6.0f);
+        cb_6 = periodic ? h2_6 * (float)a.sc->cbar : 0.0f;
     }
     __device__ float2 cell(int64_t i) const { return make_float2(ZERO_E ? 0.0f : ein[i], pt[i]); }
     __device__ float2 zero_cell() const { return make_float2(0.0f, 0.0f); }
@@ -77,7 +78,8 @@ struct CorrK {
         float Se;
         const float dq = dq_corr(ve, vp, c.a_ih4, Se);
         const float dQ = dQ_of(dq, s.t0, c);
-        return make_float2((Se - c.h2 * (dQ + s.r - cb)) * (1.0f / 6.0f), Pc[o].y);
+        // (Se - h^2 (dQ + r - cbar)) / 6
+        return make_float2(fmaf(Se, 1.0f / 6.0f, fmaf(-h2_6, dQ, fmaf(-h2_6, s.r, cb_6))), Pc[o].y);
     }
     __device__ void out(int64_t i, float2 v) const { eout[i] = v.x; }
 };

@@ -25,6 +25,7 @@ struct Coef {
     double alpha, kappa;
     double c8;        // 8*alpha/3
     double vertex;    // -3/(4 alpha) (unused when alpha == 0: then D == 1)
+    int sqrt_form;    // |alpha| >= 1e-2: the root is taken as (sqrt D - 1) 3/(4 alpha)
 };
 
 // FP32 coefficients of the inner (correction) operator of the mixed path.
