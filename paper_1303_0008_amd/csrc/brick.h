@@ -69,7 +69,8 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     constexpr int HW2 = W2 / 2, HW1 = W1 / 2;     // half-row lengths (34, 33)
     constexpr int NP2 = W2 * H2;
     constexpr int NL2 = (NP2 + NTH - 1) / NTH;
-    constexpr int RH = W1 / 2;        // red/black pairs per ring-1 row
+    constexpr int RH = W1 / 2;        // red/black pairs per ring-1 row (33)
+    static_assert(RH == 33, "the red slot mapping assumes 33 pairs per ring-1 row");
     constexpr int BH = TX / 2;        // black cells per interior row
     constexpr int NR = (RH * H1 + NTH - 1) / NTH;   // red cells per thread
     constexpr int NB = (BH * TY + NTH - 1) / NTH;   // black cells per thread
@@ -124,7 +125,12 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     for (int q = 0; q < NR; ++q) {
         const int e = tid + q * NTH;
         rv[q] = e < RH * H1;
-        const int r = rv[q] ? e / RH : 0, m = rv[q] ? e - r * RH : 0;
+        // pairs 0..31 of every row take 32 consecutive threads, so a 16-lane LDS
+        // access group never straddles two rows (no bank conflicts); the last
+        // pair of each row (m = 32) goes to the threads after them
+        const bool main_part = e < 32 * H1;
+        const int r = !rv[q] ? 0 : (main_part ? e >> 5 : e - 32 * H1);
+        const int m = !rv[q] ? 0 : (main_part ? (e & 31) : 32);
         const int gy = y0 - 1 + r;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {

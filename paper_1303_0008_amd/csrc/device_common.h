@@ -138,6 +138,15 @@ __device__ __forceinline__ float dQ_of(float dq, float t0, const CoefF& c) {
     return c.a34 * (s1 - s0);
 }
 
+// Column X of an LDS tile row of even width W stored split by parity (even
+// columns first).  A lane handling cells X = 2m+1 and 2m+2 then reads each
+// neighbour column from consecutive words across lanes (no bank conflicts).
+template <int W>
+__device__ __forceinline__ int split_col(int X) {
+    static_assert(W % 2 == 0, "split rows need an even width");
+    return (X & 1) * (W / 2) + (X >> 1);
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
     // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
     // contiguous range of tiles so that shared halos stay in one L2.

@@ -159,13 +159,14 @@ __global__ void __launch_bounds__(NT) k_resid_tiled(ResidArgs a) {
     const int xa = x0 + 2 * m;                       // first cell of the pair
     const bool row_ok = gy < g.n1;
 
-    int off1[NL1];
+    int off1[NL1], lds1[NL1];   // global in-plane offset, LDS word (rows split by parity)
     bool ok1[NL1];
 #pragma unroll
     for (int s = 0; s < NL1; ++s) {
         const int e = tid + s * NT;
         ok1[s] = false;
         off1[s] = 0;
+        lds1[s] = (e / W1) * W1 + split_col<W1>(e % W1);
         if (e < NP1) {
             int gx = x0 - 1 + e % W1, gyy = y0 - 1 + e / W1;
             if (DIR) {
@@ -194,7 +195,7 @@ __global__ void __launch_bounds__(NT) k_resid_tiled(ResidArgs a) {
         double* dst = &PH[sl][0][0];
 #pragma unroll
         for (int s = 0; s < NL1; ++s)
-            if (tid + s * NT < NP1) dst[tid + s * NT] = rr[s];
+            if (tid + s * NT < NP1) dst[lds1[s]] = rr[s];
     };
     auto slot = [](int z) { return (z + 3) % 3; };
     auto src_fetch = [&](int t, double (&dl)[2], double (&fv)[2]) {
@@ -233,16 +234,16 @@ __global__ void __launch_bounds__(NT) k_resid_tiled(ResidArgs a) {
             const int X = 2 * m + c2 + 1, Y = r + 1;
             if (!row_ok || xa + c2 >= g.n0) continue;
             Nb v;
-            v.xm = PH[sc][Y][X - 1]; v.xp = PH[sc][Y][X + 1];
-            v.ym = PH[sc][Y - 1][X]; v.yp = PH[sc][Y + 1][X];
-            v.zm = PH[sm][Y][X];     v.zp = PH[sp][Y][X];
-            v.xpyp = PH[sc][Y + 1][X + 1]; v.xmym = PH[sc][Y - 1][X - 1];
-            v.xpym = PH[sc][Y - 1][X + 1]; v.xmyp = PH[sc][Y + 1][X - 1];
-            v.xpzp = PH[sp][Y][X + 1]; v.xmzm = PH[sm][Y][X - 1];
-            v.xpzm = PH[sm][Y][X + 1]; v.xmzp = PH[sp][Y][X - 1];
-            v.ypzp = PH[sp][Y + 1][X]; v.ymzm = PH[sm][Y - 1][X];
-            v.ypzm = PH[sm][Y + 1][X]; v.ymzp = PH[sp][Y - 1][X];
-            const double pc = PH[sc][Y][X];
+            v.xm = PH[sc][Y][split_col<W1>(X - 1)]; v.xp = PH[sc][Y][split_col<W1>(X + 1)];
+            v.ym = PH[sc][Y - 1][split_col<W1>(X)]; v.yp = PH[sc][Y + 1][split_col<W1>(X)];
+            v.zm = PH[sm][Y][split_col<W1>(X)];     v.zp = PH[sp][Y][split_col<W1>(X)];
+            v.xpyp = PH[sc][Y + 1][split_col<W1>(X + 1)]; v.xmym = PH[sc][Y - 1][split_col<W1>(X - 1)];
+            v.xpym = PH[sc][Y - 1][split_col<W1>(X + 1)]; v.xmyp = PH[sc][Y + 1][split_col<W1>(X - 1)];
+            v.xpzp = PH[sp][Y][split_col<W1>(X + 1)]; v.xmzm = PH[sm][Y][split_col<W1>(X - 1)];
+            v.xpzm = PH[sm][Y][split_col<W1>(X + 1)]; v.xmzp = PH[sp][Y][split_col<W1>(X - 1)];
+            v.ypzp = PH[sp][Y + 1][split_col<W1>(X)]; v.ymzm = PH[sm][Y - 1][split_col<W1>(X)];
+            v.ypzm = PH[sm][Y + 1][split_col<W1>(X)]; v.ymzp = PH[sp][Y - 1][split_col<W1>(X)];
+            const double pc = PH[sc][Y][split_col<W1>(X)];
             double S;
             bool gd;
             const double Q = nl_root(v, cdl[c2], a.c, inv_h4, S, gd);
@@ -288,7 +289,7 @@ __global__ void __launch_bounds__(NT) k_resid_tiled(ResidArgs a) {
             double* dst = &PH[slot(t + 2)][0][0];   // slot of plane t-1: no longer read
 #pragma unroll
             for (int s = 0; s < NL1; ++s)
-                if (tid + s * NT < NP1) dst[tid + s * NT] = nxt[s];
+                if (tid + s * NT < NP1) dst[lds1[s]] = nxt[s];
         }
         cdl[0] = ndl[0]; cdl[1] = ndl[1];
         cfv[0] = nfv[0]; cfv[1] = nfv[1];

@@ -511,13 +511,14 @@ __global__ void __launch_bounds__(NT) k_cast_tiled(CastArgs a) {
     const int m = tid & 31, r = tid >> 5;
     const int gy = y0 + r, xa = x0 + 2 * m;
     const bool row_ok = gy < g.n1;
-    int off1[NL1];
+    int off1[NL1], lds1[NL1];   // global in-plane offset, LDS word (rows split by parity)
     bool ok1[NL1];
 #pragma unroll
     for (int s2 = 0; s2 < NL1; ++s2) {
         const int e = tid + s2 * NT;
         ok1[s2] = false;
         off1[s2] = 0;
+        lds1[s2] = (e / W1) * W1 + split_col<W1>(e % W1);
         if (e < NP1) {
             int gx = x0 - 1 + e % W1, gyy = y0 - 1 + e / W1;
             if (DIR) {
@@ -551,7 +552,7 @@ __global__ void __launch_bounds__(NT) k_cast_tiled(CastArgs a) {
         double* dst = &PH[sl][0][0];
 #pragma unroll
         for (int s2 = 0; s2 < NL1; ++s2)
-            if (tid + s2 * NT < NP1) dst[tid + s2 * NT] = rr[s2];
+            if (tid + s2 * NT < NP1) dst[lds1[s2]] = rr[s2];
     };
     auto slot = [](int z) { return (z + 3) % 3; };
     auto src_fetch = [&](int t, double (&dl)[2], double (&fv)[2]) {
@@ -586,16 +587,16 @@ __global__ void __launch_bounds__(NT) k_cast_tiled(CastArgs a) {
             const int X = 2 * m + c2 + 1, Y = r + 1;
             if (!row_ok || xa + c2 >= g.n0) continue;
             Nb v;
-            v.xm = PH[sc][Y][X - 1]; v.xp = PH[sc][Y][X + 1];
-            v.ym = PH[sc][Y - 1][X]; v.yp = PH[sc][Y + 1][X];
-            v.zm = PH[sm][Y][X];     v.zp = PH[sp][Y][X];
-            v.xpyp = PH[sc][Y + 1][X + 1]; v.xmym = PH[sc][Y - 1][X - 1];
-            v.xpym = PH[sc][Y - 1][X + 1]; v.xmyp = PH[sc][Y + 1][X - 1];
-            v.xpzp = PH[sp][Y][X + 1]; v.xmzm = PH[sm][Y][X - 1];
-            v.xpzm = PH[sm][Y][X + 1]; v.xmzp = PH[sp][Y][X - 1];
-            v.ypzp = PH[sp][Y + 1][X]; v.ymzm = PH[sm][Y - 1][X];
-            v.ypzm = PH[sm][Y + 1][X]; v.ymzp = PH[sp][Y - 1][X];
-            const double pc = PH[sc][Y][X];
+            v.xm = PH[sc][Y][split_col<W1>(X - 1)]; v.xp = PH[sc][Y][split_col<W1>(X + 1)];
+            v.ym = PH[sc][Y - 1][split_col<W1>(X)]; v.yp = PH[sc][Y + 1][split_col<W1>(X)];
+            v.zm = PH[sm][Y][split_col<W1>(X)];     v.zp = PH[sp][Y][split_col<W1>(X)];
+            v.xpyp = PH[sc][Y + 1][split_col<W1>(X + 1)]; v.xmym = PH[sc][Y - 1][split_col<W1>(X - 1)];
+            v.xpym = PH[sc][Y - 1][split_col<W1>(X + 1)]; v.xmyp = PH[sc][Y + 1][split_col<W1>(X - 1)];
+            v.xpzp = PH[sp][Y][split_col<W1>(X + 1)]; v.xmzm = PH[sm][Y][split_col<W1>(X - 1)];
+            v.xpzm = PH[sm][Y][split_col<W1>(X + 1)]; v.xmzp = PH[sp][Y][split_col<W1>(X - 1)];
+            v.ypzp = PH[sp][Y + 1][split_col<W1>(X)]; v.ymzm = PH[sm][Y - 1][split_col<W1>(X)];
+            v.ypzm = PH[sm][Y + 1][split_col<W1>(X)]; v.ymzp = PH[sp][Y - 1][split_col<W1>(X)];
+            const double pc = PH[sc][Y][split_col<W1>(X)];
             double S;
             bool gd;
             double t0;
@@ -664,13 +665,14 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
     const int m = tid & 31, r = tid >> 5;
     const int gy = y0 + r, xa = x0 + 2 * m;
     const bool row_ok = gy < g.n1;
-    int off1[NL1];
+    int off1[NL1], lds1[NL1];   // global in-plane offset, LDS word (rows split by parity)
     bool ok1[NL1];
 #pragma unroll
     for (int s2 = 0; s2 < NL1; ++s2) {
         const int e = tid + s2 * NT;
         ok1[s2] = false;
         off1[s2] = 0;
+        lds1[s2] = (e / W1) * W1 + split_col<W1>(e % W1);
         if (e < NP1) {
             int gx = x0 - 1 + e % W1, gyy = y0 - 1 + e / W1;
             if (DIR) {
@@ -703,7 +705,7 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
         float2* d = &EP[sl][0][0];
 #pragma unroll
         for (int s2 = 0; s2 < NL1; ++s2)
-            if (tid + s2 * NT < NP1) d[tid + s2 * NT] = make_float2(re[s2], rp[s2]);
+            if (tid + s2 * NT < NP1) d[lds1[s2]] = make_float2(re[s2], rp[s2]);
     };
     auto slot = [](int z) { return (z + 3) % 3; };
     const double inv_h4_64 = 1.0 / (g.h * g.h * g.h * g.h);
@@ -745,12 +747,12 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
             const int X = 2 * m + c2 + 1, Y = r + 1;
             if (!row_ok || xa + c2 >= g.n0) continue;
             NbT<float2> v2;
-            v2.xm = EP[sc][Y][X - 1]; v2.xp = EP[sc][Y][X + 1]; v2.ym = EP[sc][Y - 1][X]; v2.yp = EP[sc][Y + 1][X];
-            v2.zm = EP[sm][Y][X]; v2.zp = EP[sp][Y][X];
-            v2.xpyp = EP[sc][Y + 1][X + 1]; v2.xmym = EP[sc][Y - 1][X - 1];
-            v2.xpym = EP[sc][Y - 1][X + 1]; v2.xmyp = EP[sc][Y + 1][X - 1];
-            v2.xpzp = EP[sp][Y][X + 1]; v2.xmzm = EP[sm][Y][X - 1]; v2.xpzm = EP[sm][Y][X + 1]; v2.xmzp = EP[sp][Y][X - 1];
-            v2.ypzp = EP[sp][Y + 1][X]; v2.ymzm = EP[sm][Y - 1][X]; v2.ypzm = EP[sm][Y + 1][X]; v2.ymzp = EP[sp][Y - 1][X];
+            v2.xm = EP[sc][Y][split_col<W1>(X - 1)]; v2.xp = EP[sc][Y][split_col<W1>(X + 1)]; v2.ym = EP[sc][Y - 1][split_col<W1>(X)]; v2.yp = EP[sc][Y + 1][split_col<W1>(X)];
+            v2.zm = EP[sm][Y][split_col<W1>(X)]; v2.zp = EP[sp][Y][split_col<W1>(X)];
+            v2.xpyp = EP[sc][Y + 1][split_col<W1>(X + 1)]; v2.xmym = EP[sc][Y - 1][split_col<W1>(X - 1)];
+            v2.xpym = EP[sc][Y - 1][split_col<W1>(X + 1)]; v2.xmyp = EP[sc][Y + 1][split_col<W1>(X - 1)];
+            v2.xpzp = EP[sp][Y][split_col<W1>(X + 1)]; v2.xmzm = EP[sm][Y][split_col<W1>(X - 1)]; v2.xpzm = EP[sm][Y][split_col<W1>(X + 1)]; v2.xmzp = EP[sp][Y][split_col<W1>(X - 1)];
+            v2.ypzp = EP[sp][Y + 1][split_col<W1>(X)]; v2.ymzm = EP[sm][Y - 1][split_col<W1>(X)]; v2.ypzm = EP[sm][Y + 1][split_col<W1>(X)]; v2.ymzp = EP[sp][Y - 1][split_col<W1>(X)];
             NbT<float> ve, vp;
 #define VMG_SPLIT(q) ve.q = v2.q.x; vp.q = v2.q.y;
             VMG_SPLIT(xm) VMG_SPLIT(xp) VMG_SPLIT(ym) VMG_SPLIT(yp) VMG_SPLIT(zm) VMG_SPLIT(zp)
@@ -758,7 +760,7 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
             VMG_SPLIT(xpzp) VMG_SPLIT(xmzm) VMG_SPLIT(xpzm) VMG_SPLIT(xmzp)
             VMG_SPLIT(ypzp) VMG_SPLIT(ymzm) VMG_SPLIT(ypzm) VMG_SPLIT(ymzp)
 #undef VMG_SPLIT
-            const float2 cc = EP[sc][Y][X];
+            const float2 cc = EP[sc][Y][split_col<W1>(X)];
             const float ecv = cc.x;
             float t0c = ctt[c2];
             if (MODE == 2) {
