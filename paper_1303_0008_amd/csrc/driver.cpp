@@ -232,6 +232,56 @@ static hipError_t tail_cycle(Plan* P, GridState& G, int l) {
     return launch_tail(a, P->stream);
 }
 
+static hipError_t vcycle(Plan* P, GridState& G, int l);
+
+// A V-cycle on level l < last in two parts.  The head pre-smooths, then one
+// pass computes the residual and restricts phi and d to level l+1; with
+// `norm` it also closes the reductions of that pass at once (new cbar of level
+// l and the RMS of the pre-smoothed state into *norm).  The tail forms the
+// coarse right-hand side, runs the coarse cycle, prolongs and post-smooths.
+// `nb` carries the residual pass's block count from head to tail.
+static hipError_t vcycle_head(Plan* P, GridState& G, int l, NormOut* norm, int* nb) {
+    LevelBuf& L = G.lev[l];
+    hipError_t e;
+    for (int s = 0; s < P->nu1; ++s)
+        if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
+    LevelBuf& C = G.lev[l + 1];
+    C.cur = 0;
+    if ((e = launch_residual_restrict(L.g, C.g, P->coef, L.phi[L.cur], L.delta, level_f(P, G, l), L.sc,
+                                      C.phi[0], C.phiold, C.rd, P->partials, nb, P->stream)) != hipSuccess)
+        return e;
+    if (norm)
+        return launch_finalize(P->partials, *nb, L.g.ncell, L.g.dir ? 0 : 1, 0, L.sc, norm, P->stream);
+    return hipSuccess;
+}
+
+// closed: the head already finalized the residual pass (it was given `norm`)
+static hipError_t vcycle_tail(Plan* P, GridState& G, int l, int nb, bool closed) {
+    LevelBuf& L = G.lev[l];
+    LevelBuf& C = G.lev[l + 1];
+    hipError_t e;
+    const int periodic = L.g.dir ? 0 : 1;
+    int nbc = 0;
+    if ((e = launch_fas_rhs(C.g, P->coef, C.phi[0], C.delta, C.rd, C.f, P->partials_b, &nbc, P->stream)) !=
+        hipSuccess)
+        return e;
+    // new cbar of level l (read next by its post-smoothing) and of level l+1 (its
+    // first sweep); with Dirichlet faces there is no cbar and nothing to finalize
+    if (periodic) {
+        const FinJob coarse{P->partials_b, nbc, 1, 1, C.g.ncell, C.sc, nullptr, nullptr};
+        e = closed ? launch_finalize(coarse.partials, coarse.nblocks, coarse.ncell, 1, 1, C.sc, nullptr, P->stream)
+                   : launch_finalize_pair(FinJob{P->partials, nb, 1, 0, L.g.ncell, L.sc, nullptr, nullptr}, coarse,
+                                          P->stream);
+        if (e != hipSuccess) return e;
+    }
+    if ((e = vcycle(P, G, l + 1)) != hipSuccess) return e;
+    if ((e = launch_prolong(L.g, C.g, L.phi[L.cur], C.phi[C.cur], C.phiold, P->stream)) != hipSuccess)
+        return e;
+    for (int s = 0; s < P->nu2; ++s)
+        if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
 static hipError_t vcycle(Plan* P, GridState& G, int l) {
     LevelBuf& L = G.lev[l];
     const int last = (int)G.lev.size() - 1;
@@ -243,32 +293,9 @@ static hipError_t vcycle(Plan* P, GridState& G, int l) {
         P->cell_updates += (int64_t)P->ncoarse * L.g.ncell;
         return e;
     }
-    for (int s = 0; s < P->nu1; ++s)
-        if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
-    LevelBuf& C = G.lev[l + 1];
-    C.cur = 0;
     int nb = 0;
-    const int periodic = L.g.dir ? 0 : 1;
-    if ((e = launch_residual_restrict(L.g, C.g, P->coef, L.phi[L.cur], L.delta, level_f(P, G, l), L.sc,
-                                      C.phi[0], C.phiold, C.rd, P->partials, &nb, P->stream)) != hipSuccess)
-        return e;
-    int nbc = 0;
-    if ((e = launch_fas_rhs(C.g, P->coef, C.phi[0], C.delta, C.rd, C.f, P->partials_b, &nbc, P->stream)) !=
-        hipSuccess)
-        return e;
-    // new cbar of level l (read next by its post-smoothing) and of level l+1 (its
-    // first sweep); with Dirichlet faces there is no cbar and nothing to finalize
-    if (periodic &&
-        (e = launch_finalize_pair(FinJob{P->partials, nb, 1, 0, L.g.ncell, L.sc, nullptr, nullptr},
-                                  FinJob{P->partials_b, nbc, 1, 1, C.g.ncell, C.sc, nullptr, nullptr},
-                                  P->stream)) != hipSuccess)
-        return e;
-    if ((e = vcycle(P, G, l + 1)) != hipSuccess) return e;
-    if ((e = launch_prolong(L.g, C.g, L.phi[L.cur], C.phi[C.cur], C.phiold, P->stream)) != hipSuccess)
-        return e;
-    for (int s = 0; s < P->nu2; ++s)
-        if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
-    return hipSuccess;
+    if ((e = vcycle_head(P, G, l, nullptr, &nb)) != hipSuccess) return e;
+    return vcycle_tail(P, G, l, nb, false);
 }
 
 static hipError_t norm_pass(Plan* P, GridState& G) {
@@ -280,19 +307,57 @@ static hipError_t norm_pass(Plan* P, GridState& G) {
     return launch_finalize(P->partials, nb, L.g.ncell, L.g.dir ? 0 : 1, 0, L.sc, G.norm_dev, P->stream);
 }
 
-// Enqueue one full cycle for every grid + norms + the copy of the norms to the host.
-static hipError_t enqueue_cycle(Plan* P) {
-    hipError_t e;
-    for (auto& G : P->grids) {
-        if ((e = vcycle(P, G, 0)) != hipSuccess) return e;
-        if ((e = norm_pass(P, G)) != hipSuccess) return e;
-    }
+// FP64 cycles on a grid with coarser levels are run shifted by one head: the
+// convergence test reads the residual of the pre-smoothed state, which the
+// finest residual-and-restriction pass computes anyway, so no separate norm
+// pass is needed.  The solve runs one head, then units (tail of cycle k, head
+// of cycle k+1) until that residual meets the tolerance; the result is the
+// pre-smoothed state whose residual was measured.
+static bool shifted_cycles(const Plan* P) {
+    if (P->mixed || P->batched) return false;
+    for (const auto& G : P->grids)
+        if (G.lev.size() < 2) return false;
+    return true;
+}
+
+static hipError_t norms_to_host_fp64(Plan* P) {
     for (size_t gi = 0; gi < P->grids.size(); ++gi) {
-        e = hipMemcpyAsync(&P->host_norm[gi], P->grids[gi].norm_dev, sizeof(NormOut),
-                           hipMemcpyDeviceToHost, P->stream);
+        hipError_t e = hipMemcpyAsync(&P->host_norm[gi], P->grids[gi].norm_dev, sizeof(NormOut),
+                                      hipMemcpyDeviceToHost, P->stream);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// The first head of a shifted solve (pre-smoothing and the residual of its result).
+static hipError_t enqueue_first_head(Plan* P) {
+    hipError_t e;
+    for (auto& G : P->grids) {
+        int nb = 0;
+        if ((e = vcycle_head(P, G, 0, G.norm_dev, &nb)) != hipSuccess) return e;
+        G.head_nb = nb;
+    }
+    return norms_to_host_fp64(P);
+}
+
+// Enqueue one cycle for every grid + norms + the copy of the norms to the host:
+// a full cycle and a norm pass, or (shifted) the tail of one cycle and the head
+// of the next.
+static hipError_t enqueue_cycle(Plan* P) {
+    hipError_t e;
+    const bool shifted = shifted_cycles(P);
+    for (auto& G : P->grids) {
+        if (shifted) {
+            int nb = 0;
+            if ((e = vcycle_tail(P, G, 0, G.head_nb, true)) != hipSuccess) return e;
+            if ((e = vcycle_head(P, G, 0, G.norm_dev, &nb)) != hipSuccess) return e;
+            G.head_nb = nb;
+        } else {
+            if ((e = vcycle(P, G, 0)) != hipSuccess) return e;
+            if ((e = norm_pass(P, G)) != hipSuccess) return e;
+        }
+    }
+    return norms_to_host_fp64(P);
 }
 
 static hipError_t enqueue_iteration(Plan* P) {
@@ -428,6 +493,10 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
             if (!(P->host_norm[gi].rms <= P->params.tol)) return false;
         return true;
     };
+    if (shifted_cycles(P) && !converged()) {
+        CKH(enqueue_first_head(P));
+        CKH(hipStreamSynchronize(s));
+    }
     while (!converged()) {
         if (cycles >= P->params.max_cycles) {
             status = VMG_ENOCONV;

@@ -61,8 +61,12 @@ def test_lognormal512a_mixed(torch_cuda, V, oracle_mod):
     pm = phi_m.cpu().numpy()
     pd = phi_d.cpu().numpy()
     del phi_m, phi_d
-    # both stop at rms <= 1e-8; the error of such a phi is ~ |J^-1| rms ~ 0.03 rms
-    assert np.abs(pm - pd).max() <= 1e-8 * np.abs(pd).max()
+    # Both stop once the RMS residual is below the tolerance, so each phi is off
+    # the discrete solution by about |J^-1| rms; on the periodic unit box the
+    # smallest non-zero eigenvalue of the Laplacian, (2 pi)^2, gives |J^-1| ~ 0.025.
+    bound = 0.1 * (rm["rms"] + rd["rms"])
+    say("  max |phi_mixed - phi_fp64| = %.3e, bound %.3e" % (np.abs(pm - pd).max(), bound))
+    assert np.abs(pm - pd).max() <= bound
     say("  oracle residual of the mixed phi")
     _, info = oracle_mod.residual(delta, pm, w["alpha"], w["kappa"], want_field=False)
     say("  oracle", info)
