@@ -629,8 +629,8 @@ struct CorrResArgs {
     CoefF c;
     const float* e;
     const float* pt;
-    const float* t0;
-    const float* r;            // inner rhs (MODE 1) or R d_e (MODE 2)
+    const float* t0;           // MODE 1, 3
+    const float* r;            // inner rhs (MODE 1) or R d_e (MODE 2, 3)
     const LevelScalars* sc;    // inner cbar (MODE 1, periodic)
     float *ec, *eold_c, *rd_c; // MODE 1
     float* ptc;                // MODE 1: restricted base state (may be null)
@@ -646,6 +646,8 @@ struct CorrResArgs {
 // MODE 2: coarse inner rhs rout = Lap e - dQ(e) - rd, reductions of dQ and rout; the
 //         level's t0 = +-sqrt|D0| of the base state is computed here (FP64 discriminant
 //         of phi~ and delta) and written for the smoother of this level
+// MODE 3: as MODE 2, with the level's t0 read instead (its base state has not
+//         changed since a MODE 2 pass set it)
 template <int DIR, int MODE>
 __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
     constexpr int W1 = TX + 2, H1 = MTY + 2, NP1 = W1 * H1, NL1 = (NP1 + NT - 1) / NT;
@@ -660,7 +662,7 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
     const int x0 = tx * TX, y0 = ty * MTY, z0 = ch * a.zc;
     const int z1 = min(z0 + a.zc, g.n2);
     double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
-    const float cb = (DIR || MODE == 2) ? 0.0f : (float)a.sc->cbar;
+    const float cb = (DIR || MODE >= 2) ? 0.0f : (float)a.sc->cbar;
     const float inv_h2 = 1.0f / a.c.h2;
     const int m = tid & 31, r = tid >> 5;
     const int gy = y0 + r, xa = x0 + 2 * m;
@@ -718,7 +720,7 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
             if (!row_ok || xa + c2 >= g.n0 || t >= z1) continue;
             const int64_t gi = g.off0 + xa + c2 + (int64_t)gy * g.sy + (int64_t)t * g.sz;
             if (MODE == 2) dl[c2] = a.delta[gi];
-            else tt[c2] = a.t0[gi];
+            else tt[c2] = a.t0[gi];   // MODE 1, and MODE 3 (t0 of this level already set)
             rv[c2] = a.r[gi];
         }
     };
@@ -777,7 +779,7 @@ __global__ void __launch_bounds__(NT) k_corr_tiled(CorrResArgs a) {
             const float dq = dq_corr(ve, vp, a.c.a_ih4, Se);
             const float dQ = dQ_of(dq, t0c, a.c);
             const float L = (Se - 6.0f * ecv) * inv_h2 - dQ;
-            if (MODE == 2) {
+            if (MODE >= 2) {
                 const float rh = L - crv[c2];
                 a.rout[g.off0 + xa + c2 + (int64_t)gy * g.sy + (int64_t)t * g.sz] = rh;
                 acc[R_Q] += dQ;
@@ -1073,18 +1075,22 @@ hipError_t launch_rr_corr(const Geom& gf, const Geom& gc, const CoefF& c, const 
 
 hipError_t launch_fas_corr(const Geom& g, const CoefF& c, const Coef& c64, const double* delta, const float* e,
                            const float* pt, float* t0, const float* rd, float* r, double* partials,
-                           int* nblocks_out, hipStream_t s) {
+                           int* nblocks_out, hipStream_t s, bool fresh_base) {
     CorrResArgs a;
     std::memset(&a, 0, sizeof(a));
     a.g = g; a.c = c; a.c64 = c64; a.delta = delta; a.e = e; a.pt = pt; a.t0out = t0; a.r = rd; a.rout = r;
+    a.t0 = t0;
     a.partials = partials;
     int nb;
     corr_tiles(g, a.tiles_x, a.tiles_y, a.zc, nb);
     *nblocks_out = nb;
-    if (g.dir)
-        hipLaunchKernelGGL((k_corr_tiled<1, 2>), dim3(nb), dim3(NT), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_corr_tiled<0, 2>), dim3(nb), dim3(NT), 0, s, a);
+    if (g.dir) {
+        if (fresh_base) hipLaunchKernelGGL((k_corr_tiled<1, 2>), dim3(nb), dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((k_corr_tiled<1, 3>), dim3(nb), dim3(NT), 0, s, a);
+    } else {
+        if (fresh_base) hipLaunchKernelGGL((k_corr_tiled<0, 2>), dim3(nb), dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((k_corr_tiled<0, 3>), dim3(nb), dim3(NT), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -92,7 +92,10 @@ static hipError_t inner_tail(Plan* P, GridState& G, int l) {
 
 // zero_e: the level's correction is identically zero on entry (finest level,
 // first inner cycle of an outer iteration); the first sweep then reads no e.
-static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e) {
+// fresh_base: the first inner cycle of an outer iteration restricts the base
+// state phi~ and computes the coarse t0; later inner cycles of the same outer
+// iteration reuse them (phi~ only changes in the outer FP64 pass).
+static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e, bool fresh_base) {
     LevelBuf& L = G.lev[l];
     const int last = (int)G.lev.size() - 1;
     const CoefF cf = make_coef_f(P->coef, L.g.h);
@@ -111,13 +114,13 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e) {
     int nb = 0;
     const int periodic = L.g.dir ? 0 : 1;
     // restriction of e and d_e; the coarse base state phi~ is restricted in the same pass
-    if ((e = launch_rr_corr(L.g, C.g, cf, L.e[L.ecur], L.pt, L.t0, L.r, L.scf, C.e[0], C.eold, C.rdf, C.pt,
-                            P->partials, &nb, P->stream)) != hipSuccess)
+    if ((e = launch_rr_corr(L.g, C.g, cf, L.e[L.ecur], L.pt, L.t0, L.r, L.scf, C.e[0], C.eold, C.rdf,
+                            fresh_base ? C.pt : nullptr, P->partials, &nb, P->stream)) != hipSuccess)
         return e;
     // coarse rhs; also the coarse t0 (FP64 discriminant of the restricted base state)
     int nbc = 0;
     if ((e = launch_fas_corr(C.g, cc, P->coef, C.delta, C.e[0], C.pt, C.t0, C.rdf, C.r, P->partials_b, &nbc,
-                             P->stream)) != hipSuccess)
+                             P->stream, fresh_base)) != hipSuccess)
         return e;
     // cbar of level l's correction equation (its post-smoothing) and of level l+1
     if (periodic &&
@@ -125,7 +128,7 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e) {
                                   FinJob{P->partials_b, nbc, 1, 1, C.g.ncell, C.scf, nullptr, nullptr},
                                   P->stream)) != hipSuccess)
         return e;
-    if ((e = inner_vcycle(P, G, l + 1, false)) != hipSuccess) return e;
+    if ((e = inner_vcycle(P, G, l + 1, false, fresh_base)) != hipSuccess) return e;
     if ((e = launch_prolong_corr(L.g, C.g, L.e[L.ecur], C.e[C.ecur], C.eold, P->stream)) != hipSuccess) return e;
     for (int s = 0; s < P->nu2; ++s)
         if ((e = smooth_corr_level(P, G, l)) != hipSuccess) return e;
@@ -175,7 +178,7 @@ hipError_t enqueue_outer(Plan* P) {
         const bool zero_e = P->nu1 > 0 && G.lev.size() > 1;
         if (!zero_e && (e = launch_fill_f(L0.e[0], L0.g.nstore, 0.0f, P->stream)) != hipSuccess) return e;
         for (int c = 0; c < P->inner; ++c)
-            if ((e = inner_vcycle(P, G, 0, zero_e && c == 0)) != hipSuccess) return e;
+            if ((e = inner_vcycle(P, G, 0, zero_e && c == 0, c == 0)) != hipSuccess) return e;
         if ((e = cast_pass(P, G, true)) != hipSuccess) return e;
     }
     return norms_to_host(P);

@@ -189,10 +189,11 @@ hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, f
 hipError_t launch_rr_corr(const Geom& gf, const Geom& gc, const CoefF& c, const float* e, const float* pt,
                           const float* t0, const float* r, const LevelScalars* sc, float* ec, float* eold_c,
                           float* rd_c, float* ptc, double* partials, int* nblocks_out, hipStream_t s);
-// also computes and writes the level's t0 from phi~ and delta (FP64 discriminant)
+// fresh_base: also computes and writes the level's t0 from phi~ and delta (FP64
+// discriminant); otherwise reads the t0 a previous call wrote (same base state)
 hipError_t launch_fas_corr(const Geom& g, const CoefF& c, const Coef& c64, const double* delta, const float* e,
                            const float* pt, float* t0, const float* rd, float* r, double* partials,
-                           int* nblocks_out, hipStream_t s);
+                           int* nblocks_out, hipStream_t s, bool fresh_base = true);
 hipError_t launch_prolong_corr(const Geom& gf, const Geom& gc, float* ef, const float* ec, const float* eold_c,
                                hipStream_t s);
 hipError_t launch_coarse_corr(const Geom& g, const CoefF& c, float* e, const float* pt, const float* t0,
