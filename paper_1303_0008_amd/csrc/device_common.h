@@ -277,6 +277,40 @@ __global__ void k_ghost_refresh_batch(const Geom* __restrict__ gs, const int2* _
     u[gi] = ref[gi] + (T)sign * (u[ii] - ref[ii]);
 }
 
+// Coarse half of a tiled prolongation: C[lz][ly][lx] = u^H - u^H_old at coarse
+// cell (cx0 + lx, cy0 + ly, cz0 + lz) for lz < cz (periodic wrap; zero outside a
+// Dirichlet grid).  The loop has a fixed trip count, so all its loads are
+// issued before the first is needed.
+template <int DIR, typename T, int CZM, int CY, int CX>
+__device__ __forceinline__ void stage_coarse_diff(const Geom& gc, const T* __restrict__ uc,
+                                                  const T* __restrict__ oldc, T (&C)[CZM][CY][CX], int cz,
+                                                  int cx0, int cy0, int cz0) {
+    constexpr int NS = (CZM * CY * CX + NT - 1) / NT;
+    T v[NS];
+    int li[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int e = (int)threadIdx.x + s * NT;
+        const int lx = e % CX, ly = (e / CX) % CY, lz = e / (CX * CY);
+        int I = cx0 + lx, J = cy0 + ly, K = cz0 + lz;
+        bool ok = lz < cz;
+        if (DIR) {
+            ok = ok && I >= 0 && I < gc.n0 && J >= 0 && J < gc.n1 && K >= 0 && K < gc.n2;
+        } else {
+            I = wrapi(I, gc.n0);
+            J = wrapi(J, gc.n1);
+            K = wrapi(K, gc.n2);
+        }
+        const int64_t ci = ok ? cell_index(gc, I, J, K) : 0;
+        const T a = uc[ci], b = oldc[ci];
+        v[s] = ok ? a - b : T(0);
+        li[s] = lz < cz ? e : -1;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+        if (li[s] >= 0) (&C[0][0][0])[li[s]] = v[s];
+}
+
 // Fine half of a tiled prolongation u^h += P c (cell-centred trilinear, weights
 // 3/4 and 1/4 per axis) once the coarse values c around the tile sit in LDS
 // (C[.][.][0] is coarse cell (cx0, cy0, cz0)).  Lane = fine x within the

@@ -840,24 +840,7 @@ __global__ void __launch_bounds__(NT) k_prolong_corr_tiled(Geom gf, Geom gc, flo
     const int ch = b / tiles_y;
     const int x0 = tx * TX, y0 = ty * 8, z0 = ch * pzf;
     const int cx0 = x0 / 2 - 1, cy0 = y0 / 2 - 1, cz0 = z0 / 2 - 1;
-    for (int e = threadIdx.x; e < CX * CY * CZ; e += NT) {
-        const int lx = e % CX, ly = (e / CX) % CY, lz = e / (CX * CY);
-        int I = cx0 + lx, J = cy0 + ly, K = cz0 + lz;
-        float v = 0.0f;
-        if (DIR) {
-            if (I >= 0 && I < gc.n0 && J >= 0 && J < gc.n1 && K >= 0 && K < gc.n2) {
-                const int64_t ci = cell_index(gc, I, J, K);
-                v = ecs[ci] - oldc[ci];
-            }
-        } else {
-            I = wrapi(I, gc.n0);
-            J = wrapi(J, gc.n1);
-            K = wrapi(K, gc.n2);
-            const int64_t ci = cell_index(gc, I, J, K);
-            v = ecs[ci] - oldc[ci];
-        }
-        C[lz][ly][lx] = v;
-    }
+    stage_coarse_diff<DIR>(gc, ecs, oldc, C, CZ, cx0, cy0, cz0);
     __syncthreads();
     prolong_tile_rows<8>(gf, ef, C, x0, y0, z0, cx0, cy0, cz0, pzf);
 }

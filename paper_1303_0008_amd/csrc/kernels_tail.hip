@@ -43,17 +43,52 @@ __device__ __forceinline__ int tail_idx(const TLev& L, int i, int j, int k) {
     return (tw(k, L.n2) * L.n1 + tw(j, L.n1)) * L.n0 + tw(i, L.n0);
 }
 
+// Wrapped x offsets, row offsets and plane offsets of a cell and its two
+// neighbours along each axis ([0] = -1, [1] = the cell, [2] = +1): every
+// neighbour index is then a sum of three of them.
+struct TNbr {
+    int x[3], y[3], z[3];
+};
+
+__device__ __forceinline__ TNbr tail_nbr(int n0, int n1, int n2, int i, int j, int k) {
+    TNbr o;
+    const int p = n0 * n1;
+    o.x[0] = i == 0 ? n0 - 1 : i - 1;
+    o.x[1] = i;
+    o.x[2] = i == n0 - 1 ? 0 : i + 1;
+    o.y[0] = (j == 0 ? n1 - 1 : j - 1) * n0;
+    o.y[1] = j * n0;
+    o.y[2] = (j == n1 - 1 ? 0 : j + 1) * n0;
+    o.z[0] = (k == 0 ? n2 - 1 : k - 1) * p;
+    o.z[1] = k * p;
+    o.z[2] = (k == n2 - 1 ? 0 : k + 1) * p;
+    return o;
+}
+
+template <typename T>
+__device__ __forceinline__ void tail_gather_o(const TNbr& o, const T* u, NbT<T>& v) {
+    auto at = [&](int a, int b, int c) { return u[o.z[c] + o.y[b] + o.x[a]]; };
+    v.xm = at(0, 1, 1);   v.xp = at(2, 1, 1);
+    v.ym = at(1, 0, 1);   v.yp = at(1, 2, 1);
+    v.zm = at(1, 1, 0);   v.zp = at(1, 1, 2);
+    v.xpyp = at(2, 2, 1); v.xmym = at(0, 0, 1); v.xpym = at(2, 0, 1); v.xmyp = at(0, 2, 1);
+    v.xpzp = at(2, 1, 2); v.xmzm = at(0, 1, 0); v.xpzm = at(2, 1, 0); v.xmzp = at(0, 1, 2);
+    v.ypzp = at(1, 2, 2); v.ymzm = at(1, 0, 0); v.ypzm = at(1, 2, 0); v.ymzp = at(1, 0, 2);
+}
+
 template <typename T>
 __device__ __forceinline__ void tail_gather(const TLev& L, const T* u, int i, int j, int k, NbT<T>& v) {
-    v.xm = u[tail_idx(L, i - 1, j, k)];         v.xp = u[tail_idx(L, i + 1, j, k)];
-    v.ym = u[tail_idx(L, i, j - 1, k)];         v.yp = u[tail_idx(L, i, j + 1, k)];
-    v.zm = u[tail_idx(L, i, j, k - 1)];         v.zp = u[tail_idx(L, i, j, k + 1)];
-    v.xpyp = u[tail_idx(L, i + 1, j + 1, k)];   v.xmym = u[tail_idx(L, i - 1, j - 1, k)];
-    v.xpym = u[tail_idx(L, i + 1, j - 1, k)];   v.xmyp = u[tail_idx(L, i - 1, j + 1, k)];
-    v.xpzp = u[tail_idx(L, i + 1, j, k + 1)];   v.xmzm = u[tail_idx(L, i - 1, j, k - 1)];
-    v.xpzm = u[tail_idx(L, i + 1, j, k - 1)];   v.xmzp = u[tail_idx(L, i - 1, j, k + 1)];
-    v.ypzp = u[tail_idx(L, i, j + 1, k + 1)];   v.ymzm = u[tail_idx(L, i, j - 1, k - 1)];
-    v.ypzm = u[tail_idx(L, i, j + 1, k - 1)];   v.ymzp = u[tail_idx(L, i, j - 1, k + 1)];
+    tail_gather_o(tail_nbr(L.n0, L.n1, L.n2, i, j, k), u, v);
+}
+
+// Cell q of colour `colour` ((i+j+k) & 1) on an n0 x n1 x n2 grid with n0 even:
+// q runs over the row-pairs' halves, so every thread works on a cell of the colour.
+__device__ __forceinline__ void colour_cell(int n0, int n1, int q, int colour, int& i, int& j, int& k) {
+    const int h = n0 >> 1;
+    const int r = q / h;
+    j = r % n1;
+    k = r / n1;
+    i = 2 * (q - r * h) + ((j + k + colour) & 1);
 }
 
 // Block-wide sums of two values in a fixed order; every thread gets the totals.
@@ -80,23 +115,41 @@ __device__ __forceinline__ void tail_sum2(double a, double b, double& A, double&
 // cell of a colour is computed from the same state.
 __device__ void tail_sweep(const TLev& L, double* tmp, const Coef& c, double cb) {
     const int tid = threadIdx.x;
+    auto update = [&](int i, int j, int k) {
+        const int e = (k * L.n1 + j) * L.n0 + i;
+        Nb v;
+        tail_gather(L, L.phi, i, j, k, v);
+        double S;
+        bool gd;
+        const double Q = nl_root(v, L.del[e], c, L.inv_h4, S, gd);
+        tmp[e] = (S - L.h2 * (Q + L.f[e] - cb)) * (1.0 / 6.0);
+    };
     for (int colour = 0; colour < 2; ++colour) {
-        for (int e = tid; e < L.N; e += TAIL_NT) {
-            int i, j, k;
-            tail_decode(L, e, i, j, k);
-            if (((i + j + k) & 1) != colour) continue;
-            Nb v;
-            tail_gather(L, L.phi, i, j, k, v);
-            double S;
-            bool gd;
-            const double Q = nl_root(v, L.del[e], c, L.inv_h4, S, gd);
-            tmp[e] = (S - L.h2 * (Q + L.f[e] - cb)) * (1.0 / 6.0);
-        }
-        __syncthreads();
-        for (int e = tid; e < L.N; e += TAIL_NT) {
-            int i, j, k;
-            tail_decode(L, e, i, j, k);
-            if (((i + j + k) & 1) == colour) L.phi[e] = tmp[e];
+        if ((L.n0 & 1) == 0) {
+            for (int q = tid; q < (L.N >> 1); q += TAIL_NT) {
+                int i, j, k;
+                colour_cell(L.n0, L.n1, q, colour, i, j, k);
+                update(i, j, k);
+            }
+            __syncthreads();
+            for (int q = tid; q < (L.N >> 1); q += TAIL_NT) {
+                int i, j, k;
+                colour_cell(L.n0, L.n1, q, colour, i, j, k);
+                const int e = (k * L.n1 + j) * L.n0 + i;
+                L.phi[e] = tmp[e];
+            }
+        } else {
+            for (int e = tid; e < L.N; e += TAIL_NT) {
+                int i, j, k;
+                tail_decode(L, e, i, j, k);
+                if (((i + j + k) & 1) == colour) update(i, j, k);
+            }
+            __syncthreads();
+            for (int e = tid; e < L.N; e += TAIL_NT) {
+                int i, j, k;
+                tail_decode(L, e, i, j, k);
+                if (((i + j + k) & 1) == colour) L.phi[e] = tmp[e];
+            }
         }
         __syncthreads();
     }
@@ -151,26 +204,31 @@ __global__ void __launch_bounds__(TAIL_NT) k_tail(TailArgs a) {
         const TLev F = tail_level(a, pool, l);
         const TLev C = tail_level(a, pool, l + 1);
         for (int s = 0; s < a.nu1; ++s) tail_sweep(F, tmp, a.c, cbar[l]);
-        // residual, restriction of phi and d (R d is kept as -R d in f^H)
+        // residual of every fine cell into tmp, then the 8-child averages of phi
+        // and d (R d is kept as -R d in f^H); children are summed in a fixed order
         double sq = 0.0, sf = 0.0;
+        for (int fe = tid; fe < F.N; fe += TAIL_NT) {
+            int i, j, k;
+            tail_decode(F, fe, i, j, k);
+            Nb v;
+            tail_gather(F, F.phi, i, j, k, v);
+            double S;
+            bool gd;
+            const double Q = nl_root(v, F.del[fe], a.c, F.inv_h4, S, gd);
+            tmp[fe] = (S - 6.0 * F.phi[fe]) * F.inv_h2 - Q - F.f[fe] + cbar[l];
+            sq += Q;
+            sf += F.f[fe];
+        }
+        __syncthreads();
         for (int e = tid; e < C.N; e += TAIL_NT) {
             int I, J, K;
             tail_decode(C, e, I, J, K);
             double sp = 0.0, sd = 0.0;
-#pragma unroll 1
+#pragma unroll
             for (int m = 0; m < 8; ++m) {
-                const int i = 2 * I + (m & 1), j = 2 * J + ((m >> 1) & 1), k = 2 * K + (m >> 2);
-                const int fe = (k * F.n1 + j) * F.n0 + i;
-                Nb v;
-                tail_gather(F, F.phi, i, j, k, v);
-                double S;
-                bool gd;
-                const double Q = nl_root(v, F.del[fe], a.c, F.inv_h4, S, gd);
-                const double pc = F.phi[fe];
-                sd += (S - 6.0 * pc) * F.inv_h2 - Q - F.f[fe] + cbar[l];
-                sp += pc;
-                sq += Q;
-                sf += F.f[fe];
+                const int fe = ((2 * K + (m >> 2)) * F.n1 + 2 * J + ((m >> 1) & 1)) * F.n0 + 2 * I + (m & 1);
+                sd += tmp[fe];
+                sp += F.phi[fe];
             }
             C.phi[e] = 0.125 * sp;
             C.old[e] = 0.125 * sp;
@@ -300,41 +358,52 @@ __device__ __forceinline__ void ctail_decode(const CLev& L, int e, int& i, int& 
 
 template <typename T>
 __device__ __forceinline__ void ctail_gather(const CLev& L, const T* u, int i, int j, int k, NbT<T>& v) {
-    v.xm = u[ctail_idx(L, i - 1, j, k)];         v.xp = u[ctail_idx(L, i + 1, j, k)];
-    v.ym = u[ctail_idx(L, i, j - 1, k)];         v.yp = u[ctail_idx(L, i, j + 1, k)];
-    v.zm = u[ctail_idx(L, i, j, k - 1)];         v.zp = u[ctail_idx(L, i, j, k + 1)];
-    v.xpyp = u[ctail_idx(L, i + 1, j + 1, k)];   v.xmym = u[ctail_idx(L, i - 1, j - 1, k)];
-    v.xpym = u[ctail_idx(L, i + 1, j - 1, k)];   v.xmyp = u[ctail_idx(L, i - 1, j + 1, k)];
-    v.xpzp = u[ctail_idx(L, i + 1, j, k + 1)];   v.xmzm = u[ctail_idx(L, i - 1, j, k - 1)];
-    v.xpzm = u[ctail_idx(L, i + 1, j, k - 1)];   v.xmzp = u[ctail_idx(L, i - 1, j, k + 1)];
-    v.ypzp = u[ctail_idx(L, i, j + 1, k + 1)];   v.ymzm = u[ctail_idx(L, i, j - 1, k - 1)];
-    v.ypzm = u[ctail_idx(L, i, j + 1, k - 1)];   v.ymzp = u[ctail_idx(L, i, j - 1, k + 1)];
+    tail_gather_o(tail_nbr(L.n0, L.n1, L.n2, i, j, k), u, v);
 }
 
 // dQ(e) at cell (i,j,k) and the neighbour sum of e
 __device__ __forceinline__ float ctail_dq(const CLev& L, const CoefF& c, int i, int j, int k, int e, float& Se) {
+    const TNbr o = tail_nbr(L.n0, L.n1, L.n2, i, j, k);
     NbT<float> ve, vp;
-    ctail_gather(L, L.e, i, j, k, ve);
-    ctail_gather(L, L.pt, i, j, k, vp);
+    tail_gather_o(o, L.e, ve);
+    tail_gather_o(o, L.pt, vp);
     return dQ_of(dq_corr(ve, vp, L.a_ih4, Se), L.t0[e], c);
 }
 
 __device__ void ctail_sweep(const CLev& L, float* tmp, const CoefF& c, float cb) {
     const int tid = threadIdx.x;
+    auto update = [&](int i, int j, int k) {
+        const int e = (k * L.n1 + j) * L.n0 + i;
+        float Se;
+        const float dQ = ctail_dq(L, c, i, j, k, e, Se);
+        tmp[e] = (Se - L.h2 * (dQ + L.r[e] - cb)) * (1.0f / 6.0f);
+    };
     for (int colour = 0; colour < 2; ++colour) {
-        for (int e = tid; e < L.N; e += TAIL_NT) {
-            int i, j, k;
-            ctail_decode(L, e, i, j, k);
-            if (((i + j + k) & 1) != colour) continue;
-            float Se;
-            const float dQ = ctail_dq(L, c, i, j, k, e, Se);
-            tmp[e] = (Se - L.h2 * (dQ + L.r[e] - cb)) * (1.0f / 6.0f);
-        }
-        __syncthreads();
-        for (int e = tid; e < L.N; e += TAIL_NT) {
-            int i, j, k;
-            ctail_decode(L, e, i, j, k);
-            if (((i + j + k) & 1) == colour) L.e[e] = tmp[e];
+        if ((L.n0 & 1) == 0) {
+            for (int q = tid; q < (L.N >> 1); q += TAIL_NT) {
+                int i, j, k;
+                colour_cell(L.n0, L.n1, q, colour, i, j, k);
+                update(i, j, k);
+            }
+            __syncthreads();
+            for (int q = tid; q < (L.N >> 1); q += TAIL_NT) {
+                int i, j, k;
+                colour_cell(L.n0, L.n1, q, colour, i, j, k);
+                const int e = (k * L.n1 + j) * L.n0 + i;
+                L.e[e] = tmp[e];
+            }
+        } else {
+            for (int e = tid; e < L.N; e += TAIL_NT) {
+                int i, j, k;
+                ctail_decode(L, e, i, j, k);
+                if (((i + j + k) & 1) == colour) update(i, j, k);
+            }
+            __syncthreads();
+            for (int e = tid; e < L.N; e += TAIL_NT) {
+                int i, j, k;
+                ctail_decode(L, e, i, j, k);
+                if (((i + j + k) & 1) == colour) L.e[e] = tmp[e];
+            }
         }
         __syncthreads();
     }
@@ -369,24 +438,29 @@ __global__ void __launch_bounds__(TAIL_NT) k_tail_corr(TailCorrArgs a) {
         const CLev F = ctail_level(a, pool, l);
         const CLev C = ctail_level(a, pool, l + 1);
         for (int s = 0; s < a.nu1; ++s) ctail_sweep(F, tmp, cf, cbar[l]);
-        // residual d_e, restriction of e, d_e (kept as -R d_e in r^H) and phi~
+        // residual d_e of every fine cell into tmp, then the 8-child averages of
+        // e, d_e (kept as -R d_e in r^H) and phi~, children summed in a fixed order
         double sq = 0.0, sf = 0.0;
+        for (int fe = tid; fe < F.N; fe += TAIL_NT) {
+            int i, j, k;
+            ctail_decode(F, fe, i, j, k);
+            float Se;
+            const float dQ = ctail_dq(F, cf, i, j, k, fe, Se);
+            tmp[fe] = (Se - 6.0f * F.e[fe]) * F.inv_h2 - dQ - F.r[fe] + cbar[l];
+            sq += dQ;
+            sf += F.r[fe];
+        }
+        __syncthreads();
         for (int e = tid; e < C.N; e += TAIL_NT) {
             int I, J, K;
             ctail_decode(C, e, I, J, K);
             float se = 0.0f, sd = 0.0f, sp = 0.0f;
-#pragma unroll 1
+#pragma unroll
             for (int m = 0; m < 8; ++m) {
-                const int i = 2 * I + (m & 1), j = 2 * J + ((m >> 1) & 1), k = 2 * K + (m >> 2);
-                const int fe = (k * F.n1 + j) * F.n0 + i;
-                float Se;
-                const float dQ = ctail_dq(F, cf, i, j, k, fe, Se);
-                const float ec = F.e[fe];
-                sd += (Se - 6.0f * ec) * F.inv_h2 - dQ - F.r[fe] + cbar[l];
-                se += ec;
+                const int fe = ((2 * K + (m >> 2)) * F.n1 + 2 * J + ((m >> 1) & 1)) * F.n0 + 2 * I + (m & 1);
+                sd += tmp[fe];
+                se += F.e[fe];
                 sp += F.pt[fe];
-                sq += dQ;
-                sf += F.r[fe];
             }
             C.e[e] = 0.125f * se;
             C.old[e] = 0.125f * se;
