@@ -176,6 +176,19 @@ vmg_status vmg_fill_interior(const double *parent, const int32_t np[3], double p
                              const vmg_grid *grids, const int32_t *origins, int32_t n_grids,
                              double *phi, hipStream_t stream);
 
+/* Total potential and force (Sec. II.B: the model's total potential is
+ * Psi = phi_N + phi/2, differenced to give the force on particles; Sec. III.B:
+ * the gradient is the central difference (u_{i+1} - u_{i-1}) / 2h).  On a
+ * periodic n[0] x n[1] x n[2] grid of cell size h (device arrays, x fastest):
+ * phi_newton is the Newtonian potential (Eq. newton, Lap phi_N = (3/2) Omega_m a
+ * delta: vmg_solve with alpha = 0 and kappa = 1.5 Omega_m a solves it), phi the
+ * brane-bending mode.  Writes psi = phi_newton + phi/2 (may be NULL) and the
+ * acceleration -grad Psi into force: 3 N values, the x, y and z components one
+ * after another.  Enqueued on `stream`; the caller owns every buffer.
+ * Errors: VMG_EINVAL (null input or force, n < 1, h not finite and > 0), VMG_EHIP. */
+vmg_status vmg_total_force(const double *phi_newton, const double *phi, const int32_t n[3], double h,
+                           double *psi, double *force, hipStream_t stream);
+
 /* Number of ghost values of a Dirichlet grid with n cells per axis. */
 int64_t vmg_ghost_count(const int32_t n[3]);
 
@@ -194,9 +207,10 @@ vmg_status vmg_plan_stats(const vmg_plan *plan, int64_t *cell_updates, int64_t *
                           int64_t *finest_cells);
 
 /* Schedule a plan uses (host pointers, each may be NULL): tile height and
- * z-chunk of the fused sweep (chosen by the autotuner with VMG_AUTOTUNE, which
- * times the finest-level smoother for heights {4,8,16} x chunks {8,16,32} at
- * plan creation; Sec. V of the paper notes the code needed more tuning),
+ * z-chunk of the finest level's fused sweep (chosen by the autotuner with
+ * VMG_AUTOTUNE, which times every swept level's smoother for tile heights
+ * {4,8,12,16} x z chunks at plan creation; Sec. V of the paper notes the code
+ * needed more tuning),
  * pre/post sweeps and coarsest-level sweeps.  Errors: VMG_EINVAL. */
 vmg_status vmg_plan_config(const vmg_plan *plan, int32_t *tile_y, int32_t *z_chunk, int32_t *nu1,
                            int32_t *nu2, int32_t *coarse_sweeps);

@@ -55,6 +55,7 @@ def lib():
                                        ctypes.c_int, ctypes.c_int, dp]
         L.or_fill_ghosts.argtypes = [ip, ctypes.c_double, dp, ip, ctypes.c_double, ip, dp]
         L.or_fill_interior.argtypes = [ip, ctypes.c_double, dp, ip, ctypes.c_double, ip, dp]
+        L.or_total_force.argtypes = [ip, ctypes.c_double, dp, dp, dp, dp]
         L.or_ghost_count.argtypes = [ip]
         L.or_ghost_count.restype = ctypes.c_long
         _lib = L
@@ -159,3 +160,16 @@ def fill_ghosts(parent, n, h, origin):
     rc = lib().or_fill_ghosts(_ivec(npar), H, _dp(parent), _ivec(nn), h, _ivec(origin), _dp(g))
     assert rc == 0
     return g
+
+
+def total_force(phi_n, phi, h):
+    """Total potential Psi = phi_N + phi/2 (Sec. II.B) and the acceleration
+    -grad Psi by periodic central differences (Sec. III.B) on a grid of cell
+    size h.  Returns (psi, g) with g shaped (3, n2, n1, n0): gx, gy, gz."""
+    phi_n, phi = _f64(phi_n), _f64(phi)
+    n = _dims(phi)
+    psi = np.zeros_like(phi)
+    g = np.zeros((3,) + phi.shape)
+    rc = lib().or_total_force(_ivec(n), float(h), _dp(phi_n), _dp(phi), _dp(psi), _dp(g))
+    assert rc == 0
+    return psi, g

@@ -691,3 +691,32 @@ int or_fill_ghosts(const int np_[3], double H, const double *parent, const int n
 }
 
 long or_ghost_count(const int n[3]) { return ghost_count(n); }
+
+/* ------------------------------------------------------------------------- */
+/* total potential and force (Sec. II.B, Sec. III.B)                          */
+/* ------------------------------------------------------------------------- */
+/* On a periodic n[0] x n[1] x n[2] grid (x fastest) of cell size h: the total
+ * potential Psi = phi_N + phi/2 of the model, and the acceleration -grad Psi
+ * by the central difference (Psi_{i+1} - Psi_{i-1}) / (2h) along each axis,
+ * with periodic neighbours.  psi and g[3 * N] (gx, then gy, then gz) are
+ * written; phi_N solves the Newtonian Poisson equation.  Returns 0. */
+int or_total_force(const int n[3], double h, const double *phi_n, const double *phi, double *psi, double *g) {
+    const int n0 = n[0], n1 = n[1], n2 = n[2];
+    const long N = (long)n0 * n1 * n2;
+    for (long e = 0; e < N; ++e) psi[e] = phi_n[e] + 0.5 * phi[e];
+    for (int k = 0; k < n2; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n0; ++i) {
+                const long e = ((long)k * n1 + j) * n0 + i;
+                const long xp = ((long)k * n1 + j) * n0 + wrap(i + 1, n0);
+                const long xm = ((long)k * n1 + j) * n0 + wrap(i - 1, n0);
+                const long yp = ((long)k * n1 + wrap(j + 1, n1)) * n0 + i;
+                const long ym = ((long)k * n1 + wrap(j - 1, n1)) * n0 + i;
+                const long zp = ((long)wrap(k + 1, n2) * n1 + j) * n0 + i;
+                const long zm = ((long)wrap(k - 1, n2) * n1 + j) * n0 + i;
+                g[e] = -(psi[xp] - psi[xm]) / (2.0 * h);
+                g[N + e] = -(psi[yp] - psi[ym]) / (2.0 * h);
+                g[2 * N + e] = -(psi[zp] - psi[zm]) / (2.0 * h);
+            }
+    return 0;
+}

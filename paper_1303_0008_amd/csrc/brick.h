@@ -9,12 +9,14 @@
 //     blocks own, so no block reads another block's output) and stores the
 //     full u^1 plane (red computed, black copied) in LDS (3 planes),
 //   * the black phase runs on the tile and writes u^2 once.
-// Loads run two plane steps ahead of their use (see the pipeline below), so a
-// sweep reads u^0 and the per-cell sources once and writes u^2 once.
+// Loads run one or two plane steps ahead of their use (K::AHEAD, see the
+// pipeline below); a sweep reads u^0 and the per-cell sources once and writes
+// u^2 once.
 //
 // The arithmetic lives in a policy K:
 //   K::Cell                 what a cell holds in LDS (double phi, or float2 (e, phi~))
 //   K::Src                  per-cell sources of the update (delta and f, or t0 and r)
+//   K::AHEAD                plane steps the loads run ahead of their use (1 or 2)
 //   k.cell(i), k.src(i)     the input state / sources at storage index i
 //   k.zero_cell(), k.zero_src()
 //   k.template update<W>(Pm, Pc, Pp, c, o, src)   updated cell from its neighbourhood
@@ -216,68 +218,94 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     using B0 = std::integral_constant<int, 0>;
     using B1 = std::integral_constant<int, 1>;
 
+    // ---- red phase on plane p, ring 1: P0 -> P1 (sources sr of plane p) -----
+    auto red_phase = [&](const int p, auto btag, const Src (&sr)[NR]) {
+        constexpr int b = decltype(btag)::value;
+        const Cell* Pm = P0 + slot(p - 1) * S2;
+        const Cell* Pc = P0 + slot(p) * S2;
+        const Cell* Pp = P0 + slot(p + 1) * S2;
+        Cell* Q1 = P1 + slot(p) * S1;
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            if (!rv[q]) continue;
+            const int c = rc[q][b], o = ro[q][b];
+            Cell val = Pc[o];
+            const bool interior = DIR ? (rg[q][b] >= 0 && p >= 0 && p < g.n2) : true;
+            if (interior) val = k.template update<W2>(Pm, Pc, Pp, c, o, sr[q]);
+            Q1[rw[q][b]] = val;
+            Q1[rw[q][1 - b]] = Pc[ro[q][1 - b]];
+        }
+    };
+    // ---- black phase on plane p2, tile interior: P1 -> u^2 (sources sr) ------
+    auto black_phase = [&](const int p2, auto btag, const Src (&sr)[NB]) {
+        constexpr int b = decltype(btag)::value;
+        const Cell* Rm = P1 + slot(p2 - 1) * S1;
+        const Cell* Rc = P1 + slot(p2) * S1;
+        const Cell* Rp = P1 + slot(p2 + 1) * S1;
+        const int64_t zo = (int64_t)p2 * g.sz;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            if (bin[q][b])
+                k.out(zo + bcell[q][b], k.template update<W1>(Rm, Rc, Rp, bc[q][b], bo[q][b], sr[q]));
+            if (bin[q][1 - b]) k.out(zo + bcell[q][1 - b], Rc[bo[q][1 - b]]);
+        }
+    };
+
     // Software pipeline over z.  Step t computes red on plane t-1 (u^0 planes
-    // t-2..t in LDS) and black on plane t-2 (u^1 planes t-3..t-1 in LDS).
-    // Loads run two steps ahead of their use: the u^0 plane t+2 is issued at
-    // the start of step t and committed to LDS at the end of step t+1; the
-    // sources of a red (black) plane are issued right after the red (black)
-    // phase that consumed their register buffer, two steps before use.
-    // Buffers alternate with the step's parity b, so the loop body is unrolled
-    // twice and every buffer index is a compile-time constant.
-    Cell pq[2][NL2];        // u^0 planes in flight
-    Src rq[2][NR];          // red sources: plane t-1 in [b] at step t
-    Src bq[2][NB];          // black sources: plane t-2 in [b] at step t
+    // t-2..t in LDS) and black on plane t-2 (u^1 planes t-3..t-1 in LDS).  The
+    // loop body is unrolled twice, so parity-dependent offsets and buffer
+    // indices are compile-time selections.  K::AHEAD sets how far loads run
+    // ahead of their use:
+    //   2: the u^0 plane t+2 is issued at the start of step t and committed to
+    //      LDS at the end of step t+1; sources are issued two steps before use
+    //      (register buffers alternate with the step's parity);
+    //   1: the u^0 plane t+1 is issued at the start of step t and committed at
+    //      its end; the next plane's sources are issued right after the phase
+    //      that consumed the buffer (half the registers).
+    static_assert(K::AHEAD == 1 || K::AHEAD == 2, "pipeline depth 1 or 2");
+    constexpr int NBUF = K::AHEAD;
+    Cell pq[NBUF][NL2];     // u^0 planes in flight
+    Src rq[NBUF][NR];       // red sources
+    Src bq[NBUF][NB];       // black sources
     {
         Cell r2[NL2];
         for (int t = z0 - 2; t <= z0; ++t) {
             load_plane(t, r2);
             store_plane(slot(t), r2);
         }
-        load_plane(z0 + 1, pq[1]);
-        fetch_red(z0 - 1, B0(), rq[0]);   // red plane of step z0
-        fetch_red(z0, B1(), rq[1]);       // red plane of step z0 + 1
+        if (K::AHEAD == 2) {
+            load_plane(z0 + 1, pq[NBUF - 1]);
+            fetch_red(z0, B1(), rq[NBUF - 1]);   // red plane of step z0 + 1
+        }
+        fetch_red(z0 - 1, B0(), rq[0]);          // red plane of step z0
     }
     __syncthreads();
 
     auto step = [&](const int t, auto parity_tag) {
         constexpr int b = decltype(parity_tag)::value;
+        using BN = std::integral_constant<int, 1 - b>;   // parity of step t+1
+        constexpr int cur = K::AHEAD == 2 ? b : 0;        // buffers used by this step
         const int p = t - 1, p2 = t - 2;
-        if (t + 2 <= z1 + 1) load_plane(t + 2, pq[b]);
-        // ---- red phase on plane p, ring 1: P0 -> P1 ---------------------------
-        {
-            const Cell* Pm = P0 + slot(p - 1) * S2;
-            const Cell* Pc = P0 + slot(p) * S2;
-            const Cell* Pp = P0 + slot(p + 1) * S2;
-            Cell* Q1 = P1 + slot(p) * S1;
-#pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                if (!rv[q]) continue;
-                const int c = rc[q][b], o = ro[q][b];
-                Cell val = Pc[o];
-                const bool interior = DIR ? (rg[q][b] >= 0 && p >= 0 && p < g.n2) : true;
-                if (interior) val = k.template update<W2>(Pm, Pc, Pp, c, o, rq[b][q]);
-                Q1[rw[q][b]] = val;
-                Q1[rw[q][1 - b]] = Pc[ro[q][1 - b]];
-            }
+        if (K::AHEAD == 2) {
+            if (t + 2 <= z1 + 1) load_plane(t + 2, pq[cur]);
+        } else {
+            if (t + 1 <= z1 + 1) load_plane(t + 1, pq[0]);
         }
-        if (t + 1 <= z1) fetch_red(t + 1, parity_tag, rq[b]);   // plane t+1 has the parity of t-1
+        red_phase(p, parity_tag, rq[cur]);
+        if (K::AHEAD == 2) {
+            if (t + 1 <= z1) fetch_red(t + 1, parity_tag, rq[cur]);   // plane t+1 has the parity of t-1
+        } else {
+            if (t <= z1) fetch_red(t, BN(), rq[0]);                  // red plane of step t+1
+        }
         __syncthreads();
-        // ---- black phase on plane p2, tile interior: P1 -> u^2 -----------------
-        if (p2 >= z0) {
-            const Cell* Rm = P1 + slot(p2 - 1) * S1;
-            const Cell* Rc = P1 + slot(p2) * S1;
-            const Cell* Rp = P1 + slot(p2 + 1) * S1;
-            const int64_t zo = (int64_t)p2 * g.sz;
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                if (bin[q][b])
-                    k.out(zo + bcell[q][b], k.template update<W1>(Rm, Rc, Rp, bc[q][b], bo[q][b], bq[b][q]));
-                if (bin[q][1 - b]) k.out(zo + bcell[q][1 - b], Rc[bo[q][1 - b]]);
-            }
+        if (p2 >= z0) black_phase(p2, parity_tag, bq[cur]);
+        if (K::AHEAD == 2) {
+            if (t >= z0 && t < z1) fetch_black(t, parity_tag, bq[cur]);   // plane t has the parity of t-2
+        } else {
+            if (t - 1 >= z0 && t - 1 < z1) fetch_black(t - 1, BN(), bq[0]);   // black plane of step t+1
         }
-        if (t >= z0 && t < z1) fetch_black(t, parity_tag, bq[b]);   // plane t has the parity of t-2
         // ---- commit u^0 plane t+1 (its slot held plane t-2, last read by this red phase)
-        if (t + 1 <= z1 + 1) store_plane(slot(t + 1), pq[b ^ 1]);
+        if (t + 1 <= z1 + 1) store_plane(slot(t + 1), pq[K::AHEAD == 2 ? (b ^ 1) : 0]);
         __syncthreads();
     };
     int t = z0;

@@ -714,6 +714,16 @@ vmg_status vmg_fill_interior(const double* parent, const int32_t np[3], double p
     return VMG_OK;
 }
 
+vmg_status vmg_total_force(const double* phi_newton, const double* phi, const int32_t n[3], double h, double* psi,
+                           double* force, hipStream_t stream) {
+    g_err.clear();
+    if (!phi_newton || !phi || !n || !force) return fail(VMG_EINVAL, "null argument");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1 || !(h > 0.0) || !std::isfinite(h))
+        return fail(VMG_EINVAL, "total force needs n >= 1 per axis and a finite h > 0");
+    CKH(launch_total_force(n[0], n[1], n[2], h, phi_newton, phi, psi, force, stream));
+    return VMG_OK;
+}
+
 vmg_status vmg_smooth(vmg_plan* plan, int32_t sweeps) {
     g_err.clear();
     if (!plan || sweeps < 0) return fail(VMG_EINVAL, "null plan or sweeps < 0");

@@ -55,7 +55,7 @@ class Result(ctypes.Structure):
 # Every symbol declared in include/vmg.h (checked by the CPU test-suite).
 EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
            "vmg_solve_periodic", "vmg_residual", "vmg_fill_ghosts", "vmg_ghost_count",
-           "vmg_smooth", "vmg_plan_stats", "vmg_plan_config", "vmg_fill_interior"]
+           "vmg_smooth", "vmg_plan_stats", "vmg_plan_config", "vmg_fill_interior", "vmg_total_force"]
 
 _lib = None
 
@@ -85,6 +85,7 @@ def load():
     L.vmg_ghost_count.argtypes = [P(ctypes.c_int32)]
     L.vmg_ghost_count.restype = ctypes.c_int64
     L.vmg_smooth.argtypes = [vp, ctypes.c_int32]
+    L.vmg_total_force.argtypes = [vp, vp, P(ctypes.c_int32), ctypes.c_double, vp, vp, vp]
     L.vmg_plan_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
     i32p = P(ctypes.c_int32)
     L.vmg_plan_config.argtypes = [vp, i32p, i32p, i32p, i32p, i32p]
@@ -209,6 +210,20 @@ def fill_interior(parent, parent_h, grids, origins, phi, stream=None):
     org = (ctypes.c_int32 * len(flat))(*flat)
     _check(load().vmg_fill_interior(_ptr(parent), npar, parent_h, arr, org, len(grids), _ptr(phi),
                                     _stream(stream)))
+
+
+def total_force(phi_newton, phi, h, psi=None, force=None, stream=None):
+    """vmg_total_force: Psi = phi_N + phi/2 and the acceleration -grad Psi on a
+    periodic grid (device float64 tensors shaped (n2, n1, n0)).  Returns
+    (psi, force) with force shaped (3, n2, n1, n0); psi is None unless given."""
+    n2, n1, n0 = phi.shape
+    if force is None:
+        import torch
+        force = torch.empty((3,) + tuple(phi.shape), dtype=phi.dtype, device=phi.device)
+    n = (ctypes.c_int32 * 3)(n0, n1, n2)
+    _check(load().vmg_total_force(_ptr(phi_newton), _ptr(phi), n, float(h), _ptr(psi), _ptr(force),
+                                  _stream(stream)))
+    return psi, force
 
 
 def smooth(handle, sweeps):

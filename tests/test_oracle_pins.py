@@ -515,3 +515,57 @@ def test_tophat_closed_form(oracle_mod):
     err_wrong = mismatch(phi, 0.0)          # the linear (unscreened) profile must not fit
     assert err_nl < 0.05, err_nl
     assert err_wrong > 4 * err_nl, (err_nl, err_wrong)
+
+
+# ---------------------------------------------------------------------------
+# total potential and force (Sec. II.B: Psi = phi_N + phi/2; Sec. III.B: the
+# gradient is the central difference (u_{i+1} - u_{i-1}) / 2h)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(16, 16, 16), (12, 10, 8)])
+def test_total_force_closed_form(oracle_mod, shape):
+    """Psi = sin(2 pi a x) + sin(2 pi b y) + sin(2 pi c z) on the unit box: the
+    periodic central difference of sin(k x) is cos(k x) sin(k h) / h exactly,
+    so -grad Psi has a closed form on each axis.  phi carries the y and z parts
+    with weight 2, so a wrong 1/2 in Psi = phi_N + phi/2 fails."""
+    n2, n1, n0 = shape
+    h = 1.0 / n0                            # periodic lengths n h per axis
+    x = (np.arange(n0) + 0.5) * h
+    y = (np.arange(n1) + 0.5) * h
+    z = (np.arange(n2) + 0.5) * h
+    kx, ky, kz = 2 * np.pi * 2 / (n0 * h), 2 * np.pi * 1 / (n1 * h), 2 * np.pi * 3 / (n2 * h)
+    X, Y, Z = np.meshgrid(x, y, z, indexing="ij")
+    X, Y, Z = X.transpose(2, 1, 0), Y.transpose(2, 1, 0), Z.transpose(2, 1, 0)
+    phi_n = np.sin(kx * X)
+    phi = 2.0 * (np.sin(ky * Y) + np.sin(kz * Z))
+    psi, g = oracle_mod.total_force(phi_n, phi, h)
+    ref_psi = np.sin(kx * X) + np.sin(ky * Y) + np.sin(kz * Z)
+    assert np.abs(psi - ref_psi).max() <= 1e-15 * 4
+    for comp, k, C in ((0, kx, X), (1, ky, Y), (2, kz, Z)):
+        ref = -np.cos(k * C) * np.sin(k * h) / h
+        assert np.abs(g[comp] - ref).max() <= 1e-12 * np.abs(ref).max(), comp
+
+
+def test_total_force_sums_to_zero_and_wraps(oracle_mod):
+    """On a periodic grid each force component telescopes to zero, and a
+    single spike of Psi produces +-1/(2h) at its two neighbours only, across
+    the periodic boundary when the spike sits on it."""
+    rng = np.random.default_rng(7)
+    shape = (6, 5, 4)
+    h = 0.25
+    phi_n = rng.standard_normal(shape)
+    phi = rng.standard_normal(shape)
+    _, g = oracle_mod.total_force(phi_n, phi, h)
+    for comp in range(3):
+        assert abs(g[comp].sum()) <= 1e-12 * np.abs(g[comp]).sum()
+    spike = np.zeros(shape)
+    spike[0, 0, 0] = 1.0
+    _, g = oracle_mod.total_force(spike, np.zeros(shape), h)
+    expect = np.zeros((3,) + shape)
+    # at i = +1: -(Psi(2) - Psi(0)) / 2h = +1/2h; at i = -1 (wrapped to n-1): -(Psi(0) - Psi(-2)) / 2h
+    expect[0, 0, 0, 1] = 1.0 / (2 * h)
+    expect[0, 0, 0, 3] = -1.0 / (2 * h)
+    expect[1, 0, 1, 0] = 1.0 / (2 * h)
+    expect[1, 0, 4, 0] = -1.0 / (2 * h)
+    expect[2, 1, 0, 0] = 1.0 / (2 * h)
+    expect[2, 5, 0, 0] = -1.0 / (2 * h)
+    assert np.array_equal(g, expect)
