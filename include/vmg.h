@@ -98,6 +98,10 @@ typedef struct {
     uint32_t flags;        /* VMG_GRAPH | VMG_AUTOTUNE */
     int32_t inner_cycles;  /* mixed: FP32 inner V-cycles per outer FP64 iteration (0 = 2);
                               must be 0 for VMG_FP64 */
+    double tau_factor;     /* > 0: also stop once |d^h| <= tau_factor |tau^h| on every grid,
+                              tau^h = L^H(R phi) - R L^h(phi) the truncation-error estimate of
+                              Sec. III.C (the paper takes the factor <= 1/3); FP64 plans of
+                              grids with coarser levels only; 0 = off */
 } vmg_params;
 
 typedef struct {
@@ -107,6 +111,8 @@ typedef struct {
     int32_t cycles;        /* V-cycles run (FP64) or outer iterations (mixed) */
     int32_t inner_cycles;  /* FP32 inner V-cycles (mixed), 0 otherwise */
     int64_t n_guarded;     /* cells where D < 0 at the returned phi */
+    double tau_rms;        /* with tau_factor > 0: RMS over the next coarser level's cells of
+                              tau^h at the returned phi (mean removed on periodic grids); else 0 */
 } vmg_result;
 
 typedef struct vmg_plan vmg_plan;
@@ -116,7 +122,8 @@ typedef struct vmg_plan vmg_plan;
  * device, may run the autotuner (VMG_AUTOTUNE) and records the V-cycle graph
  * (VMG_GRAPH).  All later work is issued on `stream` (0 = null stream).
  * Errors: VMG_EINVAL (sizes, h <= 0, tol <= 0, max_cycles < 1, inner_cycles < 0 or
- * set for VMG_FP64, mixed BC kinds,
+ * set for VMG_FP64, tau_factor < 0 or not finite, tau_factor > 0 with VMG_MIXED, with
+ * several grids or with a grid that has no coarser level, mixed BC kinds,
  * a periodic grid that does not coarsen to <= 8 cells per side, a Dirichlet
  * grid whose coarsest level exceeds 8 cells per side), VMG_ENOMEM, VMG_EHIP. */
 vmg_status vmg_plan_create(vmg_plan **plan, const vmg_grid *grids, int32_t n_grids,

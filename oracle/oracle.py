@@ -56,6 +56,8 @@ def lib():
         L.or_fill_ghosts.argtypes = [ip, ctypes.c_double, dp, ip, ctypes.c_double, ip, dp]
         L.or_fill_interior.argtypes = [ip, ctypes.c_double, dp, ip, ctypes.c_double, ip, dp]
         L.or_total_force.argtypes = [ip, ctypes.c_double, dp, dp, dp, dp]
+        L.or_truncation_error.argtypes = [ip, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          dp, dp, dp, dp]
         L.or_ghost_count.argtypes = [ip]
         L.or_ghost_count.restype = ctypes.c_long
         _lib = L
@@ -173,3 +175,18 @@ def total_force(phi_n, phi, h):
     rc = lib().or_total_force(_ivec(n), float(h), _dp(phi_n), _dp(phi), _dp(psi), _dp(g))
     assert rc == 0
     return psi, g
+
+
+def truncation_error(delta, phi, alpha, kappa, h=None, w=W_PAPER):
+    """Truncation-error estimate tau^h = L^H(R phi) - R L^h(phi) of Sec. III.C on
+    the next coarser level of a periodic grid (even sides).  Returns (tau, rms)
+    with rms the RMS of tau after removing its mean."""
+    delta, phi = _f64(delta), _f64(phi)
+    n = _dims(delta)
+    h = 1.0 / n[0] if h is None else h
+    tau = np.zeros(tuple(s // 2 for s in delta.shape))
+    rms = ctypes.c_double()
+    rc = lib().or_truncation_error(_ivec(n), h, alpha, kappa, w, _dp(delta), _dp(phi), _dp(tau),
+                                   ctypes.cast(ctypes.pointer(rms), ctypes.POINTER(ctypes.c_double)))
+    assert rc == 0
+    return tau, rms.value

@@ -720,3 +720,42 @@ int or_total_force(const int n[3], double h, const double *phi_n, const double *
             }
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* truncation-error estimate (Sec. III.C)                                     */
+/* ------------------------------------------------------------------------- */
+/* tau^h = L^H(R phi^h) - R L^h(phi^h) on the next coarser level of a periodic
+ * grid with even sides (coarse density R delta), written unpadded to tau
+ * (n/2 cells per axis); *rms = RMS of tau with its mean removed (a constant
+ * carries no information on a periodic grid).  Returns 0, or -1 for odd sides. */
+int or_truncation_error(const int n[3], double h, double alpha, double kappa, double w, const double *delta,
+                        const double *phi, double *tau, double *rms) {
+    if ((n[0] & 1) || (n[1] & 1) || (n[2] & 1)) return -1;
+    const OGrid gf = {{n[0], n[1], n[2]}, 1, h};
+    const OGrid gc = {{n[0] / 2, n[1] / 2, n[2] / 2}, 1, 2.0 * h};
+    const OCoef c = or_coeffs(alpha, kappa, w);
+    double *pf = calloc(npad(&gf), sizeof(double)), *df = calloc(npad(&gf), sizeof(double));
+    double *lf = calloc(npad(&gf), sizeof(double));
+    double *pc = calloc(npad(&gc), sizeof(double)), *dc = calloc(npad(&gc), sizeof(double));
+    unpack(&gf, phi, pf);
+    unpack(&gf, delta, df);
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) lf[pidx(&gf, i, j, k)] = Lh(&gf, &c, pf, df, i, j, k, NULL, NULL);
+    restrict_field(&gf, pf, &gc, pc);
+    restrict_field(&gf, df, &gc, dc);
+    KSum s1 = {0.0, 0.0}, s2 = {0.0, 0.0};
+    long q = 0;
+    for (int K = 0; K < gc.n[2]; ++K)
+        for (int J = 0; J < gc.n[1]; ++J)
+            for (int I = 0; I < gc.n[0]; ++I, ++q) {
+                const double t = Lh(&gc, &c, pc, dc, I, J, K, NULL, NULL) - child_mean(&gf, lf, I, J, K);
+                tau[q] = t;
+                ks_add(&s1, t);
+                ks_add(&s2, t * t);
+            }
+    const double N = (double)q, m = ks_val(&s1) / N;
+    *rms = sqrt(fmax(ks_val(&s2) / N - m * m, 0.0));
+    free(pf); free(df); free(lf); free(pc); free(dc);
+    return 0;
+}

@@ -235,45 +235,39 @@ static hipError_t tail_cycle(Plan* P, GridState& G, int l) {
 static hipError_t vcycle(Plan* P, GridState& G, int l);
 
 // A V-cycle on level l < last in two parts.  The head pre-smooths, then one
-// pass computes the residual and restricts phi and d to level l+1; with
-// `norm` it also closes the reductions of that pass at once (new cbar of level
-// l and the RMS of the pre-smoothed state into *norm).  The tail forms the
-// coarse right-hand side, runs the coarse cycle, prolongs and post-smooths.
-// `nb` carries the residual pass's block count from head to tail.
-static hipError_t vcycle_head(Plan* P, GridState& G, int l, NormOut* norm, int* nb) {
+// pass computes the residual and restricts phi and d to level l+1, and a second
+// forms the coarse right-hand side f^H = L^H(R phi) - R d (Sec. III.C); one
+// two-block launch closes both passes' reductions: the new cbar of both levels
+// and, with `norm`, the RMS of the pre-smoothed state's residual and of its
+// truncation-error estimate tau^h = L^H(R phi) - R L^h(phi) (Sec. III.C; only
+// the finest level asks for them).  The tail runs the coarse cycle, prolongs
+// and post-smooths.
+static hipError_t vcycle_head(Plan* P, GridState& G, int l, NormOut* norm) {
     LevelBuf& L = G.lev[l];
     hipError_t e;
     for (int s = 0; s < P->nu1; ++s)
         if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
     LevelBuf& C = G.lev[l + 1];
     C.cur = 0;
+    int nb = 0, nbc = 0;
     if ((e = launch_residual_restrict(L.g, C.g, P->coef, L.phi[L.cur], L.delta, level_f(P, G, l), L.sc,
-                                      C.phi[0], C.phiold, C.rd, P->partials, nb, P->stream)) != hipSuccess)
+                                      C.phi[0], C.phiold, C.rd, P->partials, &nb, P->stream)) != hipSuccess)
         return e;
-    if (norm)
-        return launch_finalize(P->partials, *nb, L.g.ncell, L.g.dir ? 0 : 1, 0, L.sc, norm, P->stream);
-    return hipSuccess;
+    if ((e = launch_fas_rhs(C.g, P->coef, C.phi[0], C.delta, C.rd, C.f, P->partials_b, &nbc, P->stream,
+                            norm ? level_f(P, G, l) : nullptr, &L.g)) != hipSuccess)
+        return e;
+    // with Dirichlet faces there is no cbar: only the norms need finalizing
+    const int periodic = L.g.dir ? 0 : 1;
+    if (!periodic && !norm) return hipSuccess;
+    return launch_finalize_pair(FinJob{P->partials, nb, periodic, 0, L.g.ncell, L.sc, norm, nullptr},
+                                FinJob{P->partials_b, nbc, periodic, 1, C.g.ncell, C.sc, norm, nullptr},
+                                P->stream);
 }
 
-// closed: the head already finalized the residual pass (it was given `norm`)
-static hipError_t vcycle_tail(Plan* P, GridState& G, int l, int nb, bool closed) {
+static hipError_t vcycle_tail(Plan* P, GridState& G, int l) {
     LevelBuf& L = G.lev[l];
     LevelBuf& C = G.lev[l + 1];
     hipError_t e;
-    const int periodic = L.g.dir ? 0 : 1;
-    int nbc = 0;
-    if ((e = launch_fas_rhs(C.g, P->coef, C.phi[0], C.delta, C.rd, C.f, P->partials_b, &nbc, P->stream)) !=
-        hipSuccess)
-        return e;
-    // new cbar of level l (read next by its post-smoothing) and of level l+1 (its
-    // first sweep); with Dirichlet faces there is no cbar and nothing to finalize
-    if (periodic) {
-        const FinJob coarse{P->partials_b, nbc, 1, 1, C.g.ncell, C.sc, nullptr, nullptr};
-        e = closed ? launch_finalize(coarse.partials, coarse.nblocks, coarse.ncell, 1, 1, C.sc, nullptr, P->stream)
-                   : launch_finalize_pair(FinJob{P->partials, nb, 1, 0, L.g.ncell, L.sc, nullptr, nullptr}, coarse,
-                                          P->stream);
-        if (e != hipSuccess) return e;
-    }
     if ((e = vcycle(P, G, l + 1)) != hipSuccess) return e;
     if ((e = launch_prolong(L.g, C.g, L.phi[L.cur], C.phi[C.cur], C.phiold, P->stream)) != hipSuccess)
         return e;
@@ -293,9 +287,8 @@ static hipError_t vcycle(Plan* P, GridState& G, int l) {
         P->cell_updates += (int64_t)P->ncoarse * L.g.ncell;
         return e;
     }
-    int nb = 0;
-    if ((e = vcycle_head(P, G, l, nullptr, &nb)) != hipSuccess) return e;
-    return vcycle_tail(P, G, l, nb, false);
+    if ((e = vcycle_head(P, G, l, nullptr)) != hipSuccess) return e;
+    return vcycle_tail(P, G, l);
 }
 
 static hipError_t norm_pass(Plan* P, GridState& G) {
@@ -332,11 +325,8 @@ static hipError_t norms_to_host_fp64(Plan* P) {
 // The first head of a shifted solve (pre-smoothing and the residual of its result).
 static hipError_t enqueue_first_head(Plan* P) {
     hipError_t e;
-    for (auto& G : P->grids) {
-        int nb = 0;
-        if ((e = vcycle_head(P, G, 0, G.norm_dev, &nb)) != hipSuccess) return e;
-        G.head_nb = nb;
-    }
+    for (auto& G : P->grids)
+        if ((e = vcycle_head(P, G, 0, G.norm_dev)) != hipSuccess) return e;
     return norms_to_host_fp64(P);
 }
 
@@ -348,10 +338,8 @@ static hipError_t enqueue_cycle(Plan* P) {
     const bool shifted = shifted_cycles(P);
     for (auto& G : P->grids) {
         if (shifted) {
-            int nb = 0;
-            if ((e = vcycle_tail(P, G, 0, G.head_nb, true)) != hipSuccess) return e;
-            if ((e = vcycle_head(P, G, 0, G.norm_dev, &nb)) != hipSuccess) return e;
-            G.head_nb = nb;
+            if ((e = vcycle_tail(P, G, 0)) != hipSuccess) return e;
+            if ((e = vcycle_head(P, G, 0, G.norm_dev)) != hipSuccess) return e;
         } else {
             if ((e = vcycle(P, G, 0)) != hipSuccess) return e;
             if ((e = norm_pass(P, G)) != hipSuccess) return e;
@@ -488,9 +476,16 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
     // ---- cycles ------------------------------------------------------------
     int cycles = 0;
     vmg_status status = VMG_OK;
+    // tau_rms is written by the heads of shifted cycles only; 0 before the first
+    const double tf = P->params.tau_factor;
+    for (int gi = 0; gi < ng; ++gi) P->host_norm[gi].tau_rms = 0.0;
     auto converged = [&]() {
-        for (int gi = 0; gi < ng; ++gi)
-            if (!(P->host_norm[gi].rms <= P->params.tol)) return false;
+        for (int gi = 0; gi < ng; ++gi) {
+            const NormOut& no = P->host_norm[gi];
+            const bool by_tol = no.rms <= P->params.tol;
+            const bool by_tau = tf > 0.0 && no.tau_rms > 0.0 && no.rms <= tf * no.tau_rms;
+            if (!(by_tol || by_tau)) return false;
+        }
         return true;
     };
     if (shifted_cycles(P) && !converged()) {
@@ -534,6 +529,7 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
             out[gi].cycles = cycles;
             out[gi].inner_cycles = P->mixed ? cycles * P->inner : 0;
             out[gi].n_guarded = (int64_t)P->host_norm[gi].n_guard;
+            out[gi].tau_rms = tf > 0.0 ? P->host_norm[gi].tau_rms : 0.0;
         }
     }
     CKH(hipStreamSynchronize(s));
@@ -565,8 +561,12 @@ vmg_status vmg_plan_create(vmg_plan** plan, const vmg_grid* grids, int32_t n_gri
     *plan = nullptr;
     if (!(p->tol > 0.0) || p->max_cycles < 1 || (p->prec != VMG_FP64 && p->prec != VMG_MIXED) ||
         p->nu1 < 0 || p->nu2 < 0 || p->inner_cycles < 0 || (p->prec == VMG_FP64 && p->inner_cycles != 0) ||
-        !std::isfinite(p->alpha) || !std::isfinite(p->kappa))
-        return fail(VMG_EINVAL, "invalid parameters (tol > 0, max_cycles >= 1, prec, nu1/nu2 >= 0, finite alpha/kappa)");
+        !std::isfinite(p->alpha) || !std::isfinite(p->kappa) || !(p->tau_factor >= 0.0) ||
+        !std::isfinite(p->tau_factor))
+        return fail(VMG_EINVAL, "invalid parameters (tol > 0, max_cycles >= 1, prec, nu1/nu2 >= 0, finite alpha/kappa, "
+                                "tau_factor >= 0)");
+    if (p->tau_factor > 0.0 && (p->prec != VMG_FP64 || n_grids != 1))
+        return fail(VMG_EINVAL, "tau_factor needs an FP64 plan of one grid");
     const int bc0 = grids[0].bc;
     for (int i = 0; i < n_grids; ++i) {
         const vmg_grid& g = grids[i];
@@ -582,6 +582,8 @@ vmg_status vmg_plan_create(vmg_plan** plan, const vmg_grid* grids, int32_t n_gri
     Plan* P = new (std::nothrow) Plan();
     if (!P) return fail(VMG_ENOMEM, "host allocation failed");
     vmg_status st = build_plan(P, grids, n_grids, p, stream);
+    if (st == VMG_OK && p->tau_factor > 0.0 && !shifted_cycles(P))
+        st = fail(VMG_EINVAL, "tau_factor needs a grid with a coarser level (tau^h lives on it)");
     if (st != VMG_OK) {
         std::string msg = g_err;
         destroy_plan(P);

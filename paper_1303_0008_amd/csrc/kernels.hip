@@ -133,6 +133,8 @@ struct ResidArgs {
     double* phiold_c;         // mode 1
     double* rd_c;             // mode 1
     double* fout;             // mode 2
+    const double* f_fine;     // mode 2, optional: the finer level's f, for tau (R f^h)
+    Geom gfine;               // mode 2: geometry of that finer level
     double* partials;
     int zc, tiles_x, tiles_y;
 };
@@ -256,6 +258,20 @@ __global__ void __launch_bounds__(NT) k_resid_tiled(ResidArgs a) {
                 a.fout[g.off0 + xa + c2 + (int64_t)gy * g.sy + (int64_t)t * g.sz] = fh;
                 acc[R_Q] += Q;
                 acc[R_F] += fh;
+                // tau^h = L^H(R phi) - R L^h(phi) = f^H - R f^h + cbar^h (a constant on
+                // periodic grids): its sums give the RMS of tau^h (Sec. III.C)
+                double tau = fh;
+                if (a.f_fine) {
+                    const Geom& gf = a.gfine;
+                    double rf = 0.0;
+#pragma unroll
+                    for (int m = 0; m < 8; ++m)
+                        rf += a.f_fine[cell_index(gf, 2 * (xa + c2) + (m & 1), 2 * gy + ((m >> 1) & 1),
+                                                  2 * t + (m >> 2))];
+                    tau -= 0.125 * rf;
+                }
+                acc[R_D1] += tau;
+                acc[R_D2] += tau * tau;
             } else {
                 const double d = L - cfv[c2] + cb;
                 acc[R_D2] += d * d;
@@ -455,6 +471,10 @@ __global__ void __launch_bounds__(NT) k_finalize(FinJobs jobs) {
     const double N = (double)ncell;
     if (mode == 1) {
         if (periodic) sc->cbar = (tot[R_F] + tot[R_Q]) / N;
+        if (out) {   // RMS of tau^h over this (coarse) level, mean removed on periodic grids
+            const double m = periodic ? tot[R_D1] / N : 0.0;
+            out->tau_rms = sqrt(fmax(tot[R_D2] / N - m * m, 0.0));
+        }
         return;
     }
     double d2 = tot[R_D2];
@@ -1101,10 +1121,12 @@ hipError_t launch_residual_norm(const Geom& g, const Coef& c, const double* phi,
 
 hipError_t launch_fas_rhs(const Geom& g, const Coef& c, const double* phi, const double* delta,
                           const double* rd, double* f, double* partials, int* nblocks_out,
-                          hipStream_t s) {
+                          hipStream_t s, const double* f_fine, const Geom* gfine) {
     ResidArgs a;
     std::memset(&a, 0, sizeof(a));
     a.g = g; a.c = c; a.phi = phi; a.delta = delta; a.f = rd; a.fout = f; a.partials = partials;
+    a.f_fine = f_fine;
+    if (gfine) a.gfine = *gfine;
     return resid_launch(a, 2, nblocks_out, s);
 }
 

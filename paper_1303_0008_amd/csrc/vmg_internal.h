@@ -54,7 +54,8 @@ struct NormOut {
     double n_guard;
     double n_nonfinite;
     double sum_q;
-    double pad[2];
+    double tau_rms;   // RMS of tau^h on the next coarser level (mean-free on periodic grids)
+    double pad;
 };
 
 // Fused red-black sweep tile configuration.
@@ -137,9 +138,10 @@ hipError_t launch_residual_norm(const Geom& g, const Coef& c, const double* phi,
                                 double* d_out, double* partials, int* nblocks_out, hipStream_t s);
 hipError_t launch_fas_rhs(const Geom& g, const Coef& c, const double* phi, const double* delta,
                           const double* rd, double* f, double* partials, int* nblocks_out,
-                          hipStream_t s);
+                          hipStream_t s,
+                          const double* f_fine = nullptr, const Geom* gfine = nullptr);
 // mode 0: residual pass (updates cbar from sum Q + sum f, corrects the lagged sums, writes NormOut)
-// mode 1: FAS rhs pass (cbar = mean f + mean Q)
+// mode 1: FAS rhs pass (cbar = mean f + mean Q; with `out`, also out->tau_rms)
 // mode 2: as mode 0, and also sets inner->cbar = -mean(d) (mean of the inner right-hand side)
 hipError_t launch_finalize(const double* partials, int nblocks, int64_t ncell, int periodic,
                            int mode, LevelScalars* sc, NormOut* out, hipStream_t s,

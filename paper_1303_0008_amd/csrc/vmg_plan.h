@@ -34,7 +34,6 @@ struct GridState {
     vmg_grid desc;
     std::vector<LevelBuf> lev;
     NormOut* norm_dev = nullptr;
-    int head_nb = 0;                 // block count of the last finest residual pass
 };
 
 // One level of a batch of Dirichlet grids: pooled buffers shared by every grid

@@ -40,13 +40,14 @@ class Grid(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("kappa", ctypes.c_double), ("tol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int32), ("prec", ctypes.c_int32), ("nu1", ctypes.c_int32),
-                ("nu2", ctypes.c_int32), ("flags", ctypes.c_uint32), ("inner_cycles", ctypes.c_int32)]
+                ("nu2", ctypes.c_int32), ("flags", ctypes.c_uint32), ("inner_cycles", ctypes.c_int32),
+                ("tau_factor", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("rms0", ctypes.c_double), ("rms", ctypes.c_double), ("compat_c", ctypes.c_double),
                 ("cycles", ctypes.c_int32), ("inner_cycles", ctypes.c_int32),
-                ("n_guarded", ctypes.c_int64)]
+                ("n_guarded", ctypes.c_int64), ("tau_rms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -139,11 +140,13 @@ def make_grid(n, h=None, bc=PERIODIC, offset=0, ghost_offset=0):
     return g
 
 
-def make_params(alpha, kappa, tol, max_cycles=100, prec=FP64, nu1=0, nu2=0, flags=0, inner_cycles=0):
+def make_params(alpha, kappa, tol, max_cycles=100, prec=FP64, nu1=0, nu2=0, flags=0, inner_cycles=0,
+                tau_factor=0.0):
     p = Params()
     p.alpha, p.kappa, p.tol = alpha, kappa, tol
     p.max_cycles, p.prec, p.nu1, p.nu2, p.flags = max_cycles, prec, nu1, nu2, flags
     p.inner_cycles = inner_cycles
+    p.tau_factor = tau_factor
     return p
 
 

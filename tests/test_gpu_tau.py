@@ -1,0 +1,74 @@
+"""The truncation-error stopping rule of Sec. III.C (|d^h| <= f |tau^h|, f <= 1/3)
+on the FP64 path, against the oracle's own estimate tau^h = L^H(R phi) -
+R L^h(phi) evaluated at the phi the GPU returns.
+
+The GPU forms tau^h as f^H - R f^h (+ cbar, a constant removed on periodic
+grids) inside the coarse right-hand-side pass; the oracle from its definition.
+Both RMS values must agree to 1e-9 relative (rounding of two different
+formulas at FP64, on values of size ~|L phi|)."""
+import numpy as np
+import pytest
+
+from paper_1303_0008_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def V():
+    from paper_1303_0008_amd import vmg
+    vmg.load()
+    return vmg
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("shape,alpha,seed", [((32, 32, 32), 0.1, 701), ((48, 32, 40), 0.2, 702)])
+def test_tau_stopping_rule(torch_cuda, V, oracle_mod, shape, alpha, seed):
+    torch = torch_cuda
+    say("tau stop", shape, alpha)
+    delta = I.lognormal(shape, seed, sigma=1.0)
+    n2, n1, n0 = delta.shape
+    d_t = dev(torch, delta)
+    factor = 1.0 / 3.0
+    # reference: the same solve to a tight tolerance only
+    phi_full = torch.zeros_like(d_t)
+    with V.Plan([V.make_grid((n0, n1, n2))], V.make_params(alpha, 1.5, 1e-12, 80)) as p:
+        r_full = p.solve(d_t, phi_full, allow_noconv=True)[0]
+    phi_t = torch.zeros_like(d_t)
+    with V.Plan([V.make_grid((n0, n1, n2))], V.make_params(alpha, 1.5, 1e-12, 80, tau_factor=factor)) as p:
+        r = p.solve(d_t, phi_t)[0]
+    say("  tau stop", r, "full", r_full["cycles"], r_full["rms"])
+    assert r["status"] == V.VMG_OK and r["tau_rms"] > 0.0
+    assert r["rms"] <= factor * r["tau_rms"]            # the rule that stopped the solve
+    assert r["cycles"] < r_full["cycles"]               # it stops well before the tolerance
+    phi = phi_t.cpu().numpy()
+    _, tau_rms = oracle_mod.truncation_error(delta, phi, alpha, 1.5)
+    say("  oracle tau rms", tau_rms)
+    assert abs(r["tau_rms"] - tau_rms) <= 1e-9 * tau_rms
+    # the returned phi is off the discrete solution by far less than the
+    # discretisation error that tau estimates (|J^-1| |d| with |d| <= |tau|/3)
+    err = np.abs(phi - phi_full.cpu().numpy()).max()
+    say("  |phi - phi_converged|", err, "tau rms", r["tau_rms"])
+    assert err <= 0.1 * r["tau_rms"]
+
+
+def test_tau_factor_rejected_where_not_supported(torch_cuda, V):
+    with pytest.raises(V.VmgError):
+        V.Plan([V.make_grid(16)], V.make_params(0.1, 1.5, 1e-8, 10, V.MIXED, tau_factor=0.3))
+    with pytest.raises(V.VmgError):
+        V.Plan([V.make_grid(16)], V.make_params(0.1, 1.5, 1e-8, 10, tau_factor=-1.0))

@@ -569,3 +569,52 @@ def test_total_force_sums_to_zero_and_wraps(oracle_mod):
     expect[2, 1, 0, 0] = 1.0 / (2 * h)
     expect[2, 5, 0, 0] = -1.0 / (2 * h)
     assert np.array_equal(g, expect)
+
+
+# ---------------------------------------------------------------------------
+# truncation-error estimate tau^h = L^H(R phi) - R L^h(phi) (Sec. III.C)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("axis,m", [(0, 3), (1, 1), (2, 2)])
+def test_truncation_error_closed_form_linear(oracle_mod, axis, m):
+    """alpha = 0: for phi = sin(k x) the 8-child average is cos(k h/2) sin(k X) and
+    the 7-point Laplacian multiplies a mode by -(4/h^2) sin^2(k h/2), so
+    tau = cos(k h/2) sin(k X) [(4/h^2) sin^2(k h/2) - (4/H^2) sin^2(k H/2)], H = 2h;
+    the density cancels (it enters both terms as -kappa R delta)."""
+    n = 16
+    h, H = 1.0 / n, 2.0 / n
+    k = 2 * np.pi * m
+    x = (np.arange(n) + 0.5) * h
+    X = (np.arange(n // 2) + 0.5) * H
+    shape = [1, 1, 1]
+    shape[2 - axis] = n
+    phi = np.broadcast_to(np.sin(k * x).reshape(shape), (n, n, n)).copy()
+    delta = np.random.default_rng(11 + axis).standard_normal((n, n, n))
+    tau, rms = oracle_mod.truncation_error(delta, phi, 0.0, 1.5)
+    cshape = [1, 1, 1]
+    cshape[2 - axis] = n // 2
+    ref = (np.cos(k * h / 2) * np.sin(k * X)
+           * (4 / h**2 * np.sin(k * h / 2) ** 2 - 4 / H**2 * np.sin(k * H / 2) ** 2)).reshape(cshape)
+    assert np.abs(tau - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert abs(rms - np.sqrt(np.mean(np.broadcast_to(ref, tau.shape) ** 2))) <= 1e-12 * np.abs(ref).max()
+
+
+def test_truncation_error_vanishes_on_uniform_state(oracle_mod):
+    """A constant phi over a uniform density is a solution on every level, so the
+    coarse and fine operators agree on it and tau = 0 (alpha != 0)."""
+    n = 8
+    phi = np.full((n, n, n), 0.37)
+    delta = np.full((n, n, n), 0.0)
+    tau, rms = oracle_mod.truncation_error(delta, phi, 0.2, 1.5)
+    assert np.abs(tau).max() == 0.0 and rms == 0.0
+
+
+def test_truncation_error_mirror_symmetry(oracle_mod):
+    """Mirroring the fine fields along x mirrors tau along x (index/orientation check
+    of the nonlinear operator on both levels)."""
+    rng = np.random.default_rng(5)
+    n = 8
+    phi = 0.01 * rng.standard_normal((n, n, n))
+    delta = rng.standard_normal((n, n, n))
+    tau, _ = oracle_mod.truncation_error(delta, phi, 0.2, 1.5)
+    tau_m, _ = oracle_mod.truncation_error(delta[:, :, ::-1].copy(), phi[:, :, ::-1].copy(), 0.2, 1.5)
+    assert np.abs(tau_m[:, :, ::-1] - tau).max() <= 1e-12 * np.abs(tau).max()
