@@ -56,6 +56,7 @@ def lib():
         L.or_fill_ghosts.argtypes = [ip, ctypes.c_double, dp, ip, ctypes.c_double, ip, dp]
         L.or_fill_interior.argtypes = [ip, ctypes.c_double, dp, ip, ctypes.c_double, ip, dp]
         L.or_total_force.argtypes = [ip, ctypes.c_double, dp, dp, dp, dp]
+        L.or_mass_assign.argtypes = [dp, ctypes.c_long, ip, ctypes.c_int, dp]
         L.or_truncation_error.argtypes = [ip, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           dp, dp, dp, dp]
         L.or_ghost_count.argtypes = [ip]
@@ -190,3 +191,16 @@ def truncation_error(delta, phi, alpha, kappa, h=None, w=W_PAPER):
                                    ctypes.cast(ctypes.pointer(rms), ctypes.POINTER(ctypes.c_double)))
     assert rc == 0
     return tau, rms.value
+
+
+def mass_assign(pos, n, scheme="tsc"):
+    """Density contrast delta = rho/mean(rho) - 1 of unit-mass particles (pos:
+    N x 3, box units in [0, 1), columns x, y, z) on a periodic unit box of n
+    cells (int or (n0, n1, n2)) by cloud-in-cell ("cic") or triangular-shaped
+    cloud ("tsc", the scheme of Sec. VI) assignment; shaped (n2, n1, n0)."""
+    pos = _f64(pos)
+    nn = (n,) * 3 if np.isscalar(n) else tuple(n)
+    out = np.zeros(nn[::-1])
+    rc = lib().or_mass_assign(_dp(pos), pos.shape[0], _ivec(nn), {"cic": 1, "tsc": 2}[scheme], _dp(out))
+    assert rc == 0
+    return out

@@ -759,3 +759,56 @@ int or_truncation_error(const int n[3], double h, double alpha, double kappa, do
     free(pf); free(df); free(lf); free(pc); free(dc);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* mass assignment: particles -> density contrast on the grid                 */
+/* ------------------------------------------------------------------------- */
+/* Unit-mass particles at pos[3*p + a] in [0, 1) (box units, a = x, y, z) on a
+ * periodic unit box of n[0] x n[1] x n[2] cells (cell centres at (i + 1/2)/n).
+ * With u = pos * n in cell units along an axis:
+ *   scheme 1, cloud in cell: u' = u - 1/2, weight 1 - t to cell floor(u') and t
+ *     to the next, t = u' - floor(u');
+ *   scheme 2, triangular-shaped cloud (the scheme of Sec. VI): nearest cell
+ *     c = floor(u), d = u - (c + 1/2); weights (1/2 - d)^2 / 2, 3/4 - d^2 and
+ *     (1/2 + d)^2 / 2 to cells c - 1, c, c + 1.
+ * The 3-D weight is the product of the axes' weights (periodic cells).
+ * A coordinate outside [0, 1) is taken modulo 1 first (periodic box); a particle
+ * with a non-finite coordinate deposits nothing but still counts in the mean.
+ * delta = rho / mean(rho) - 1 with mean(rho) = n_particles / n_cells.
+ * Returns 0, or -1 for an unknown scheme or n_particles < 1. */
+int or_mass_assign(const double *pos, long np, const int n[3], int scheme, double *delta) {
+    if ((scheme != 1 && scheme != 2) || np < 1) return -1;
+    const int m = scheme == 1 ? 2 : 3;
+    const long N = (long)n[0] * n[1] * n[2];
+    for (long e = 0; e < N; ++e) delta[e] = 0.0;
+    for (long p = 0; p < np; ++p) {
+        int c[3][3];
+        double w[3][3];
+        if (!isfinite(pos[3 * p]) || !isfinite(pos[3 * p + 1]) || !isfinite(pos[3 * p + 2])) continue;
+        for (int a = 0; a < 3; ++a) {
+            const double u = (pos[3 * p + a] - floor(pos[3 * p + a])) * n[a];
+            if (scheme == 1) {
+                const double f = floor(u - 0.5);
+                const double t = (u - 0.5) - f;
+                c[a][0] = wrap((int)f, n[a]);
+                c[a][1] = wrap((int)f + 1, n[a]);
+                w[a][0] = 1.0 - t;
+                w[a][1] = t;
+            } else {
+                const double f = floor(u);
+                const double d = u - (f + 0.5);
+                for (int q = 0; q < 3; ++q) c[a][q] = wrap((int)f + q - 1, n[a]);
+                w[a][0] = 0.5 * (0.5 - d) * (0.5 - d);
+                w[a][1] = 0.75 - d * d;
+                w[a][2] = 0.5 * (0.5 + d) * (0.5 + d);
+            }
+        }
+        for (int qz = 0; qz < m; ++qz)
+            for (int qy = 0; qy < m; ++qy)
+                for (int qx = 0; qx < m; ++qx)
+                    delta[((long)c[2][qz] * n[1] + c[1][qy]) * n[0] + c[0][qx]] += w[0][qx] * w[1][qy] * w[2][qz];
+    }
+    const double scale = (double)N / (double)np;
+    for (long e = 0; e < N; ++e) delta[e] = delta[e] * scale - 1.0;
+    return 0;
+}

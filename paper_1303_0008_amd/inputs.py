@@ -165,6 +165,14 @@ def zeldovich_cic(n, seed, amplitude, spectral_index=-1.5, kcut_frac_nyquist=0.2
     return _deposit_displaced(n, q, psi, amplitude)
 
 
+def zeldovich_particles(n, seed, amplitude, spectral_index=-1.5, kcut_frac_nyquist=0.25):
+    """Positions (N x 3 array, columns x, y, z, in [0, 1)) of the n^3 lattice
+    particles of zeldovich_cic after the same Zel'dovich displacement."""
+    q, psi = _zeldovich_positions(n, seed, spectral_index, kcut_frac_nyquist)
+    return np.ascontiguousarray(np.stack([np.mod(qc + amplitude * pc, 1.0).ravel() for qc, pc in zip(q, psi)],
+                                         axis=1))
+
+
 def scan_zeldovich_amplitude(n, seed, amplitudes, spectral_index=-1.5, kcut_frac_nyquist=0.25):
     """max(delta) for each displacement amplitude (the displacement field is built once).
 

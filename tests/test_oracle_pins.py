@@ -618,3 +618,113 @@ def test_truncation_error_mirror_symmetry(oracle_mod):
     tau, _ = oracle_mod.truncation_error(delta, phi, 0.2, 1.5)
     tau_m, _ = oracle_mod.truncation_error(delta[:, :, ::-1].copy(), phi[:, :, ::-1].copy(), 0.2, 1.5)
     assert np.abs(tau_m[:, :, ::-1] - tau).max() <= 1e-12 * np.abs(tau).max()
+
+
+# ---------------------------------------------------------------------------
+# mass assignment (Sec. VI: the mesh density comes from triangular-shaped-cloud
+# assignment of the particles; cloud in cell is the lower-order member)
+# ---------------------------------------------------------------------------
+def _moments(rho, pos, n):
+    """Mass, first moment (relative to the particle, in cells, unwrapped around
+    it) and second moment per axis of a single particle's assignment."""
+    out = []
+    for axis in range(3):
+        prof = rho.sum(axis=tuple(a for a in range(3) if a != 2 - axis))   # profile along `axis`
+        u = pos[axis] * n
+        c = (np.arange(n) + 0.5)
+        dx = (c - u + n / 2) % n - n / 2                                   # nearest periodic image
+        out.append((prof.sum(), (prof * dx).sum(), (prof * dx * dx).sum()))
+    return out
+
+
+@pytest.mark.parametrize("scheme", ["cic", "tsc"])
+def test_mass_assign_moments(oracle_mod, scheme):
+    """One particle, many positions (also across the periodic edge): the weights
+    sum to one and keep the particle's centre (first moment zero about it); the
+    second moment is t(1 - t) for cloud in cell (t the distance past the cell
+    centre below) and the constant 1/4 cell^2 for the triangular-shaped cloud."""
+    n = 8
+    rng = np.random.default_rng(5)
+    pts = np.concatenate([rng.random((40, 3)), [[0.0, 0.999, 0.5], [1 - 1e-12, 0.0625, 0.9375]]])
+    for p in pts:
+        d = oracle_mod.mass_assign(p[None, :], n, scheme)
+        rho = (d + 1.0) / n ** 3                                            # mass per cell (one particle)
+        for axis, (m0, m1, m2) in enumerate(_moments(rho, p, n)):
+            assert abs(m0 - 1.0) <= 1e-14
+            assert abs(m1) <= 1e-12
+            if scheme == "tsc":
+                assert abs(m2 - 0.25) <= 1e-12, (p, axis, m2)
+            else:
+                t = (p[axis] * n - 0.5) % 1.0
+                assert abs(m2 - t * (1 - t)) <= 1e-12, (p, axis, m2)
+
+
+def test_mass_assign_special_positions(oracle_mod):
+    """A particle at a cell centre: all its mass in that cell (cloud in cell),
+    weights 1/8, 3/4, 1/8 per axis (triangular-shaped cloud).  At a cell corner
+    both schemes give 1/8 to each of the 8 cells sharing it.  Coordinates are
+    periodic: x + 1 and x - 1 deposit as x."""
+    n = 4
+    centre = np.array([[1.5, 2.5, 0.5]]) / n
+    rho_c = (oracle_mod.mass_assign(centre, n, "cic") + 1.0) / n ** 3
+    e = np.zeros((n, n, n))
+    e[0, 2, 1] = 1.0
+    assert np.array_equal(rho_c, e)
+    rho_t = (oracle_mod.mass_assign(centre, n, "tsc") + 1.0) / n ** 3
+    w = {-1: 0.125, 0: 0.75, 1: 0.125}
+    e = np.zeros((n, n, n))
+    for a in (-1, 0, 1):
+        for b in (-1, 0, 1):
+            for c in (-1, 0, 1):
+                e[(0 + a) % n, (2 + b) % n, (1 + c) % n] = w[a] * w[b] * w[c]
+    assert np.abs(rho_t - e).max() <= 1e-16
+    corner = np.array([[2.0, 1.0, 0.0]]) / n            # shared by cells i in {1,2}, j in {0,1}, k in {3,0}
+    e = np.zeros((n, n, n))
+    for k in (3, 0):
+        for j in (0, 1):
+            for i in (1, 2):
+                e[k, j, i] = 0.125
+    for scheme in ("cic", "tsc"):
+        rho = (oracle_mod.mass_assign(corner, n, scheme) + 1.0) / n ** 3
+        assert np.abs(rho - e).max() <= 1e-16, scheme
+    p = np.array([[0.3, 0.7, 0.1]])
+    for scheme in ("cic", "tsc"):
+        ref = oracle_mod.mass_assign(p, n, scheme)
+        for shift in ([1, 0, 0], [0, -1, 0], [0, 0, 2], [-1, 1, -3]):
+            assert np.abs(oracle_mod.mass_assign(p + np.array(shift, float), n, scheme) - ref).max() <= 1e-13
+
+
+@pytest.mark.parametrize("scheme", ["cic", "tsc"])
+def test_mass_assign_shifted_lattice_is_uniform(oracle_mod, scheme):
+    """One particle per cell on a lattice rigidly shifted by any offset: every
+    cell receives exactly one particle's mass (partition of unity), so delta = 0
+    up to rounding, on cubic and non-cubic grids; the mean of delta is zero for
+    any particle set."""
+    for shape, off in (((6, 6, 6), (0.0, 0.0, 0.0)), ((6, 5, 4), (0.37, -0.81, 0.5)), ((3, 7, 2), (0.99, 0.01, 0.25))):
+        n0, n1, n2 = shape
+        g = np.meshgrid((np.arange(n0) + 0.5 + off[0]) / n0, (np.arange(n1) + 0.5 + off[1]) / n1,
+                        (np.arange(n2) + 0.5 + off[2]) / n2, indexing="ij")
+        pos = np.stack([a.ravel() for a in g], axis=1)
+        d = oracle_mod.mass_assign(pos, shape, scheme)
+        assert d.shape == (n2, n1, n0)
+        assert np.abs(d).max() <= 1e-13, (shape, off)
+    pos = np.random.default_rng(9).random((777, 3))
+    d = oracle_mod.mass_assign(pos, (5, 9, 7), scheme)
+    assert abs(d.mean()) <= 1e-14
+
+
+def test_mass_assign_nonfinite_and_small_grids(oracle_mod):
+    """A particle with a non-finite coordinate deposits nothing but counts in
+    the mean; on a single-cell grid everything lands in the one cell; on two
+    cells the triangular-shaped cloud's outer weights wrap onto the same cell."""
+    pos = np.array([[0.1, 0.2, 0.3], [np.nan, 0.5, 0.5], [0.5, np.inf, 0.5]])
+    for scheme in ("cic", "tsc"):
+        d = oracle_mod.mass_assign(pos, 4, scheme)
+        ref = oracle_mod.mass_assign(pos[:1], 4, scheme)
+        assert np.abs((d + 1.0) * 3 - (ref + 1.0)).max() <= 1e-14
+        assert np.abs(oracle_mod.mass_assign(pos[:1], 1, scheme)).max() <= 1e-15
+    # n = 2 along x: cell centres at 1/4, 3/4.  x = 1/4 exactly: TSC weights 1/8, 3/4, 1/8 on cells
+    # 1, 0, 1, i.e. 3/4 on cell 0 and 1/4 on cell 1
+    d = oracle_mod.mass_assign(np.array([[0.25, 0.5, 0.5]]), (2, 1, 1), "tsc")
+    rho = (d + 1.0) / 2
+    assert np.abs(rho.ravel() - [0.75, 0.25]).max() <= 1e-15
