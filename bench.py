@@ -15,6 +15,10 @@ sweep: algorithmic bytes per launch (24 B per cell: read phi, read delta,
 write phi) divided by its average duration, timed here with HIP events around
 back-to-back launches on the plan's stream.
 
+``results.mass_assign_zeldovich256`` times the mass assignment (triangular-
+shaped cloud and cloud in cell) of the workload's 256^3 particles onto the
+256^3 grid, outside the solve.
+
 ``cpu_baseline`` times the CPU oracle (plain FP64 C, one thread) on a bounded
 sample of the same workload: five lexicographic Newton-Gauss-Seidel sweeps
 over the full 256^3 grid.
@@ -191,6 +195,33 @@ def traffic_from(fetch_dir, write_dir, n):
             f"({out['ratio_to_algorithmic']:.2f} x algorithmic) -> {p}")
 
 
+def time_mass_assign(torch, V, stream, launches):
+    """Mass assignment of the workload's particles (256^3 lattice particles after
+    the Zel'dovich displacement) with both schemes: average duration per call from
+    HIP events on `stream` (each call = zero fill + scatter + finishing pass)."""
+    from paper_1303_0008_amd import inputs as I
+    pos_np = I.zeldovich_particles(256, I.BASE_SEED + 3, I.ZELDOVICH_AMPLITUDE)
+    pos = torch.from_numpy(pos_np).to("cuda")
+    delta = torch.empty((256, 256, 256), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    out = {}
+    for name, scheme, m in (("tsc", V.ASSIGN_TSC, 27), ("cic", V.ASSIGN_CIC, 8)):
+        V.mass_assign(pos, 256, scheme, delta=delta, stream=stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(launches):
+            V.mass_assign(pos, 256, scheme, delta=delta, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / launches
+        npart = pos_np.shape[0]
+        out[name] = {"ms_per_call": ms, "particles_per_s": npart / (ms * 1e-3),
+                     "atomics_per_s": npart * m / (ms * 1e-3), "particles": npart, "grid": 256}
+        log(f"mass assignment {name}: {ms * 1e3:.1f} us per call, {npart / (ms * 1e-3) / 1e9:.2f} G particles/s")
+    return out
+
+
 def cpu_baseline(delta, w, sweeps=5):
     from oracle import oracle as O
     import numpy as np
@@ -211,6 +242,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--smooth-launches", type=int, default=50)
+    ap.add_argument("--assign-launches", type=int, default=20,
+                    help="timed calls of the mass assignment (0: skip it)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only the kernels of the HBM counter runs (under rocprofv3 --pmc)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -270,6 +303,8 @@ def main():
                        "traffic": load_traffic(f"smooth_{name}_zeldovich256_traffic.json", kern),
                        "kernel": f"{kern} ({what}, z chunk {sched['z_chunk']})",
                        "bytes_per_launch": bpc * n3, "us_per_launch": smooth_ms * 1e3}
+    if args.assign_launches > 0:
+        results["mass_assign_zeldovich256"] = time_mass_assign(torch, V, stream, args.assign_launches)
     head = "mixed"
     results["mixed_speedup_vs_fp64"] = results["fp64"]["time_to_tol_ms"] / results["mixed"]["time_to_tol_ms"]
     roof = dict(roofs[head])

@@ -196,6 +196,32 @@ vmg_status vmg_fill_interior(const double *parent, const int32_t np[3], double p
 vmg_status vmg_total_force(const double *phi_newton, const double *phi, const int32_t n[3], double h,
                            double *psi, double *force, hipStream_t stream);
 
+/* Mass assignment (Sec. VI: the density on the mesh is obtained by assigning
+ * the particles with the triangular-shaped-cloud scheme, and the solver needs
+ * no further smoothing of it).  Unit-mass particles at pos (device array,
+ * n_particles x 3 doubles, row p = x, y, z of particle p in box units; the box
+ * is periodic and a coordinate is taken modulo 1) are assigned to a periodic
+ * grid of n[0] x n[1] x n[2] cells whose cell i along an axis is centred at
+ * (i + 1/2)/n.  With u = x * n along an axis:
+ *   VMG_ASSIGN_CIC  weights 1 - t and t on cells floor(u - 1/2) and the next,
+ *                   t = u - 1/2 - floor(u - 1/2);
+ *   VMG_ASSIGN_TSC  nearest cell c = floor(u), d = u - c - 1/2, weights
+ *                   (1/2 - d)^2/2, 3/4 - d^2, (1/2 + d)^2/2 on cells c-1, c, c+1;
+ * the 3-D weight is the product of the three axes' weights.  Writes delta =
+ * rho / mean(rho) - 1 (x fastest; mean(rho) = n_particles / cells), so the
+ * result is the right-hand side's density contrast.  A particle with a
+ * non-finite coordinate deposits nothing but counts in the mean.  Masses are
+ * summed in 64-bit fixed point (2^-40 of a particle, each contribution rounded
+ * once, integer atomics), so the result is bitwise reproducible; a cell may
+ * receive the mass of fewer than 2^24 particles.  delta doubles as the accumulator:
+ * its previous contents are ignored.  Enqueued on `stream`; the caller owns
+ * both buffers.  Errors: VMG_EINVAL (null pointer, n_particles < 1, n < 1,
+ * unknown scheme), VMG_EHIP. */
+#define VMG_ASSIGN_CIC 1
+#define VMG_ASSIGN_TSC 2
+vmg_status vmg_mass_assign(const double *pos, int64_t n_particles, const int32_t n[3], int32_t scheme,
+                           double *delta, hipStream_t stream);
+
 /* Number of ghost values of a Dirichlet grid with n cells per axis. */
 int64_t vmg_ghost_count(const int32_t n[3]);
 

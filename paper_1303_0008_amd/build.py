@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvmg.so")
-SOURCES = ["kernels.hip", "kernels_mixed.hip", "kernels_tail.hip", "driver.cpp", "mixed.cpp", "batch.cpp",
+SOURCES = ["kernels.hip", "kernels_mixed.hip", "kernels_tail.hip", "kernels_assign.hip", "driver.cpp", "mixed.cpp", "batch.cpp",
            "autotune.cpp"]
 ARCH = os.environ.get("VMG_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

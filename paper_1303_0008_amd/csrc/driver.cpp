@@ -726,6 +726,17 @@ vmg_status vmg_total_force(const double* phi_newton, const double* phi, const in
     return VMG_OK;
 }
 
+vmg_status vmg_mass_assign(const double* pos, int64_t n_particles, const int32_t n[3], int32_t scheme, double* delta,
+                           hipStream_t stream) {
+    g_err.clear();
+    if (!pos || !n || !delta) return fail(VMG_EINVAL, "null argument");
+    if (n_particles < 1) return fail(VMG_EINVAL, "mass assignment needs n_particles >= 1");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1) return fail(VMG_EINVAL, "mass assignment needs n >= 1 per axis");
+    if (scheme != VMG_ASSIGN_CIC && scheme != VMG_ASSIGN_TSC) return fail(VMG_EINVAL, "unknown assignment scheme");
+    CKH(launch_mass_assign(pos, n_particles, n[0], n[1], n[2], scheme, delta, stream));
+    return VMG_OK;
+}
+
 vmg_status vmg_smooth(vmg_plan* plan, int32_t sweeps) {
     g_err.clear();
     if (!plan || sweeps < 0) return fail(VMG_EINVAL, "null plan or sweeps < 0");

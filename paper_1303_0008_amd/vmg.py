@@ -56,7 +56,8 @@ class Result(ctypes.Structure):
 # Every symbol declared in include/vmg.h (checked by the CPU test-suite).
 EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
            "vmg_solve_periodic", "vmg_residual", "vmg_fill_ghosts", "vmg_ghost_count",
-           "vmg_smooth", "vmg_plan_stats", "vmg_plan_config", "vmg_fill_interior", "vmg_total_force"]
+           "vmg_smooth", "vmg_plan_stats", "vmg_plan_config", "vmg_fill_interior", "vmg_total_force",
+           "vmg_mass_assign"]
 
 _lib = None
 
@@ -87,6 +88,7 @@ def load():
     L.vmg_ghost_count.restype = ctypes.c_int64
     L.vmg_smooth.argtypes = [vp, ctypes.c_int32]
     L.vmg_total_force.argtypes = [vp, vp, P(ctypes.c_int32), ctypes.c_double, vp, vp, vp]
+    L.vmg_mass_assign.argtypes = [vp, ctypes.c_int64, P(ctypes.c_int32), ctypes.c_int32, vp, vp]
     L.vmg_plan_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
     i32p = P(ctypes.c_int32)
     L.vmg_plan_config.argtypes = [vp, i32p, i32p, i32p, i32p, i32p]
@@ -227,6 +229,23 @@ def total_force(phi_newton, phi, h, psi=None, force=None, stream=None):
     _check(load().vmg_total_force(_ptr(phi_newton), _ptr(phi), n, float(h), _ptr(psi), _ptr(force),
                                   _stream(stream)))
     return psi, force
+
+
+ASSIGN_CIC, ASSIGN_TSC = 1, 2
+
+
+def mass_assign(pos, n, scheme=ASSIGN_TSC, delta=None, stream=None):
+    """vmg_mass_assign: density contrast of unit-mass particles (device float64
+    tensor of shape (N, 3), columns x, y, z in box units) on a periodic grid of
+    n cells (int or (n0, n1, n2)); returns delta shaped (n2, n1, n0)."""
+    nn = (n,) * 3 if isinstance(n, int) else tuple(int(v) for v in n)
+    if delta is None:
+        import torch
+        delta = torch.empty(nn[::-1], dtype=torch.float64, device=pos.device)
+    c = (ctypes.c_int32 * 3)(*nn)
+    _check(load().vmg_mass_assign(_ptr(pos), int(pos.shape[0]) if pos.dim() else 0, c, int(scheme), _ptr(delta),
+                                  _stream(stream)))
+    return delta
 
 
 def smooth(handle, sweeps):

@@ -54,3 +54,18 @@ def test_plan_create_rejects_bad_arguments():
     for prec, inner in ((vmg.FP64, 2), (vmg.MIXED, -1)):
         p = vmg.make_params(0.1, 1.5, tol=1e-8, prec=prec, inner_cycles=inner)
         assert lib.vmg_plan_create(ctypes.byref(h), ctypes.byref(g), 1, ctypes.byref(p), None) == vmg.VMG_EINVAL
+
+
+def test_mass_assign_rejects_bad_arguments():
+    """vmg_mass_assign validates before any device call (Sec. VI assignment)."""
+    from paper_1303_0008_amd import vmg
+    lib = vmg.load()
+    n = (ctypes.c_int32 * 3)(8, 8, 8)
+    fake = ctypes.c_void_p(16)          # never dereferenced: each call fails validation first
+    assert lib.vmg_mass_assign(None, 1, n, vmg.ASSIGN_TSC, fake, None) == vmg.VMG_EINVAL
+    assert lib.vmg_mass_assign(fake, 0, n, vmg.ASSIGN_TSC, fake, None) == vmg.VMG_EINVAL
+    assert "n_particles" in vmg.last_error()
+    assert lib.vmg_mass_assign(fake, 1, n, 3, fake, None) == vmg.VMG_EINVAL
+    assert "scheme" in vmg.last_error()
+    bad = (ctypes.c_int32 * 3)(8, 0, 8)
+    assert lib.vmg_mass_assign(fake, 1, bad, vmg.ASSIGN_CIC, fake, None) == vmg.VMG_EINVAL
