@@ -198,20 +198,22 @@ def traffic_from(fetch_dir, write_dir, n):
 def time_mass_assign(torch, V, stream, launches):
     """Mass assignment of the workload's particles (256^3 lattice particles after
     the Zel'dovich displacement) with both schemes: average duration per call from
-    HIP events on `stream` (each call = zero fill + scatter + finishing pass)."""
+    HIP events on `stream` (each call = binning by brick, LDS accumulation and the
+    outer-layer passes)."""
     from paper_1303_0008_amd import inputs as I
     pos_np = I.zeldovich_particles(256, I.BASE_SEED + 3, I.ZELDOVICH_AMPLITUDE)
     pos = torch.from_numpy(pos_np).to("cuda")
     delta = torch.empty((256, 256, 256), dtype=torch.float64, device="cuda")
+    work = torch.empty(V.mass_assign_workspace(pos_np.shape[0], 256), dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     out = {}
     for name, scheme, m in (("tsc", V.ASSIGN_TSC, 27), ("cic", V.ASSIGN_CIC, 8)):
-        V.mass_assign(pos, 256, scheme, delta=delta, stream=stream)
+        V.mass_assign(pos, 256, scheme, delta=delta, workspace=work, stream=stream)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(launches):
-            V.mass_assign(pos, 256, scheme, delta=delta, stream=stream)
+            V.mass_assign(pos, 256, scheme, delta=delta, workspace=work, stream=stream)
         e1.record(stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1) / launches

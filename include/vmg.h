@@ -212,15 +212,25 @@ vmg_status vmg_total_force(const double *phi_newton, const double *phi, const in
  * result is the right-hand side's density contrast.  A particle with a
  * non-finite coordinate deposits nothing but counts in the mean.  Masses are
  * summed in 64-bit fixed point (2^-40 of a particle, each contribution rounded
- * once, integer atomics), so the result is bitwise reproducible; a cell may
- * receive the mass of fewer than 2^24 particles.  delta doubles as the accumulator:
- * its previous contents are ignored.  Enqueued on `stream`; the caller owns
- * both buffers.  Errors: VMG_EINVAL (null pointer, n_particles < 1, n < 1,
- * unknown scheme), VMG_EHIP. */
+ * once, integer sums), so the result is bitwise reproducible and independent
+ * of the particles' order; a cell may receive the mass of fewer than 2^24
+ * particles.  The previous contents of delta are ignored.
+ * workspace: device memory of at least vmg_mass_assign_workspace(n_particles,
+ * n) bytes, 256-byte aligned, owned by the caller, contents ignored (it holds
+ * the particles binned by 16^3-cell brick of the grid and each brick's
+ * boundary sums); calls that share a workspace
+ * must be ordered on one stream.  Enqueued on `stream`; the caller owns every
+ * buffer.  Errors: VMG_EINVAL (null pointer, n_particles outside
+ * [1, 2^31 - 1], n < 1, n[1] or n[2] above 65535, unknown scheme, workspace
+ * too small or misaligned), VMG_EHIP. */
 #define VMG_ASSIGN_CIC 1
 #define VMG_ASSIGN_TSC 2
 vmg_status vmg_mass_assign(const double *pos, int64_t n_particles, const int32_t n[3], int32_t scheme,
-                           double *delta, hipStream_t stream);
+                           void *workspace, int64_t workspace_bytes, double *delta, hipStream_t stream);
+
+/* Workspace bytes vmg_mass_assign needs (about 8 bytes per particle plus 12
+ * per grid cell), or -1 for arguments vmg_mass_assign rejects. */
+int64_t vmg_mass_assign_workspace(int64_t n_particles, const int32_t n[3]);
 
 /* Number of ghost values of a Dirichlet grid with n cells per axis. */
 int64_t vmg_ghost_count(const int32_t n[3]);

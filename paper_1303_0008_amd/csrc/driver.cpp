@@ -726,14 +726,29 @@ vmg_status vmg_total_force(const double* phi_newton, const double* phi, const in
     return VMG_OK;
 }
 
-vmg_status vmg_mass_assign(const double* pos, int64_t n_particles, const int32_t n[3], int32_t scheme, double* delta,
-                           hipStream_t stream) {
+static bool assign_args_ok(int64_t n_particles, const int32_t n[3]) {
+    return n && n_particles >= 1 && n_particles <= INT32_MAX && n[0] >= 1 && n[1] >= 1 && n[2] >= 1 &&
+           n[1] <= 65535 && n[2] <= 65535 &&
+           mass_assign_bricks(n[0], n[1], n[2]) <= (int64_t(1) << 26);
+}
+
+int64_t vmg_mass_assign_workspace(int64_t n_particles, const int32_t n[3]) {
+    if (!assign_args_ok(n_particles, n)) return -1;
+    return mass_assign_workspace(n_particles, n[0], n[1], n[2]);
+}
+
+vmg_status vmg_mass_assign(const double* pos, int64_t n_particles, const int32_t n[3], int32_t scheme,
+                           void* workspace, int64_t workspace_bytes, double* delta, hipStream_t stream) {
     g_err.clear();
-    if (!pos || !n || !delta) return fail(VMG_EINVAL, "null argument");
-    if (n_particles < 1) return fail(VMG_EINVAL, "mass assignment needs n_particles >= 1");
-    if (n[0] < 1 || n[1] < 1 || n[2] < 1) return fail(VMG_EINVAL, "mass assignment needs n >= 1 per axis");
+    if (!pos || !n || !delta || !workspace) return fail(VMG_EINVAL, "null argument");
+    if (n_particles < 1 || n_particles > INT32_MAX)
+        return fail(VMG_EINVAL, "mass assignment needs 1 <= n_particles <= 2^31 - 1");
+    if (!assign_args_ok(n_particles, n)) return fail(VMG_EINVAL, "mass assignment needs n >= 1 per axis");
     if (scheme != VMG_ASSIGN_CIC && scheme != VMG_ASSIGN_TSC) return fail(VMG_EINVAL, "unknown assignment scheme");
-    CKH(launch_mass_assign(pos, n_particles, n[0], n[1], n[2], scheme, delta, stream));
+    if (workspace_bytes < mass_assign_workspace(n_particles, n[0], n[1], n[2]) ||
+        reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(VMG_EINVAL, "mass assignment workspace too small or not 256-byte aligned");
+    CKH(launch_mass_assign(pos, n_particles, n[0], n[1], n[2], scheme, workspace, delta, stream));
     return VMG_OK;
 }
 

@@ -3,11 +3,28 @@
 // assignment of the particles; cloud in cell is the next-lower-order member of
 // the same family of shape functions).
 //
-// Accumulation is in 64-bit fixed point (2^-40 of a particle's mass per unit):
-// every contribution is rounded once, then added with an integer atomic, so the
-// sums do not depend on the order in which the atomics land and the result is
-// bitwise reproducible.  The density buffer itself holds the integers until the
-// finishing pass converts them in place to delta.
+// Both schemes touch the particle's nearest cell and its 26 neighbours at most,
+// so the grid is cut into bricks of BRICK^3 cells and every particle belongs to
+// the brick of its nearest cell:
+//   1. k_bin<0>       particles per brick: each workgroup takes a chunk of
+//                     particles, counts them per brick in an LDS hash table and
+//                     adds each nonzero count to one of the brick's global
+//                     counters (SUB per brick);
+//   2. k_scan_*       exclusive prefix sum of the counters;
+//   3. k_bin<1>       the same chunks again: each nonzero (chunk, brick) count
+//                     reserves a range of that brick's slots with one atomic,
+//                     and the particle indices are written sorted by brick;
+//   4. k_bin_assign   one workgroup per brick: the brick and a one-cell halo
+//                     are accumulated in LDS; interior cells (which no other
+//                     brick reaches) are stored as final delta, the outer layer
+//                     and halo entries are staged in the workspace;
+//   5. k_layer_gather every outer-layer cell sums the staged entries of the
+//                     bricks that reach it (at most 8; 27 where bricks are one
+//                     cell wide).
+// No global atomics touch the density, so the sums are formed in a fixed order.
+// Masses are 64-bit fixed point (2^-40 of a particle per unit): every
+// contribution is rounded once and all sums are integer, so the result does
+// not depend on the order of particles or of atomics.
 #include "device_common.h"
 #include "vmg_internal.h"
 
@@ -16,93 +33,412 @@ namespace {
 
 constexpr double FIX_ONE = 1099511627776.0;           // 2^40
 constexpr double FIX_INV = 1.0 / 1099511627776.0;     // 2^-40
+constexpr int BRICK = 16;                             // cells per brick edge
+constexpr int REG = BRICK + 2;                        // brick + halo, LDS region edge
+constexpr int REGN = REG * REG * REG;
+constexpr uint32_t NO_KEY = 0xffffffffu;
 
-__global__ void __launch_bounds__(NT) k_zero_u64(unsigned long long* __restrict__ q, int64_t N) {
-    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < N; e += (int64_t)gridDim.x * NT) q[e] = 0ull;
-}
+struct AGrid {
+    int n0, n1, n2;          // cells
+    int b0, b1, b2;          // bricks per axis
+};
 
-// Cell index i in [-n, 3n) wrapped onto [0, n).
-__device__ __forceinline__ int wrap3(int i, int n) {
+__device__ __forceinline__ int wrap3(int i, int n) {    // [-n, 3n) -> [0, n)
     i += i < 0 ? n : 0;
     i -= i >= n ? n : 0;
     i -= i >= n ? n : 0;
     return i;
 }
 
-// Per-axis cells and weights of one coordinate x (box units) on n cells.
-// CIC: u' = u - 1/2, weights (1 - t, t) on cells floor(u'), floor(u') + 1.
-// TSC: nearest cell c, d = u - (c + 1/2), weights (1/2 - d)^2/2, 3/4 - d^2,
-// (1/2 + d)^2/2 on cells c - 1, c, c + 1.
+// u = position in cells along an axis, in [0, n]; f = floor(u) unwrapped; the
+// nearest cell is f mod n.
+__device__ __forceinline__ double cells_of(double x, int n) { return (x - floor(x)) * (double)n; }
+
+__device__ __forceinline__ bool finite3(double x, double y, double z) {
+    return isfinite(x) && isfinite(y) && isfinite(z);
+}
+
+__device__ __forceinline__ uint32_t brick_key(const AGrid& g, double x, double y, double z) {
+    int c0 = (int)floor(cells_of(x, g.n0)), c1 = (int)floor(cells_of(y, g.n1)), c2 = (int)floor(cells_of(z, g.n2));
+    c0 -= c0 >= g.n0 ? g.n0 : 0;
+    c1 -= c1 >= g.n1 ? g.n1 : 0;
+    c2 -= c2 >= g.n2 ? g.n2 : 0;
+    return ((uint32_t)(c2 / BRICK) * g.b1 + (uint32_t)(c1 / BRICK)) * g.b0 + (uint32_t)(c0 / BRICK);
+}
+
+// round(a * b) as an integer, for 0 <= a * b < 2^51: the exact product plus
+// 2^52 is rounded once (to nearest, ties to even) to a double whose low 52
+// mantissa bits hold that integer.
+__device__ __forceinline__ unsigned long long fix_round(double a, double b) {
+    const double v = fma(a, b, 4503599627370496.0);
+    return (unsigned long long)__double_as_longlong(v) & 0x000fffffffffffffull;
+}
+
+__global__ void __launch_bounds__(NT) k_fill_u32(uint32_t* __restrict__ p, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < n; e += (int64_t)gridDim.x * NT) p[e] = 0u;
+}
+
+constexpr int ANT = 512;                              // threads of the brick accumulation
+constexpr int SUB = 16;                               // counters per brick (chunk ch uses ch % SUB)
+constexpr int CHUNK_PER_THREAD = 8;
+constexpr int CHUNK = CHUNK_PER_THREAD * NT;          // particles per chunk
+constexpr int TAB = 2 * CHUNK;                        // LDS hash table entries (load <= 1/2)
+static_assert(TAB == 1 << 12, "the hash keeps the top 12 bits of the product");
+
+// MODE 0: add every chunk's per-brick counts to counter[] and store each
+// particle's brick key.  MODE 1: reserve each chunk's range of every brick's
+// slots from counter[] (the cursors) and write the particle indices there.
+// Chunk ch counts into sub-counter ch % SUB of a brick, which spreads the
+// global atomics of unordered particles over SUB addresses per brick.
+// Bricks are found in the LDS table by linear probing from a multiplicative
+// hash of the key.
+template <int MODE>
+__global__ void __launch_bounds__(NT) k_bin(AGrid g, const double* __restrict__ pos, int64_t np,
+                                            uint32_t* __restrict__ counter, uint32_t* __restrict__ keys,
+                                            uint32_t* __restrict__ idx) {
+    __shared__ uint32_t tkey[TAB], tcnt[TAB];
+    const int64_t nchunk = (np + CHUNK - 1) / CHUNK;
+    for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        for (int e = threadIdx.x; e < TAB; e += NT) {
+            tkey[e] = NO_KEY;
+            tcnt[e] = 0u;
+        }
+        __syncthreads();
+        uint32_t key[CHUNK_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < CHUNK_PER_THREAD; ++k) {
+            const int64_t p = ch * CHUNK + k * NT + threadIdx.x;
+            key[k] = NO_KEY;
+            if (p >= np) continue;
+            if (MODE == 0) {
+                const double x = pos[3 * p], y = pos[3 * p + 1], z = pos[3 * p + 2];
+                if (finite3(x, y, z)) key[k] = brick_key(g, x, y, z);
+                keys[p] = key[k];
+            } else {
+                key[k] = keys[p];
+            }
+        }
+        // Lanes of a wavefront hold consecutive particles; a run of adjacent
+        // lanes with one key is entered by its first lane, which reserves the
+        // run's slots with one LDS atomic.
+        const int lane = threadIdx.x & 63;
+        const unsigned long long below = (2ull << lane) - 1ull;         // lanes 0..lane
+        int hs[CHUNK_PER_THREAD];
+        uint32_t loc[CHUNK_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < CHUNK_PER_THREAD; ++k) {
+            const uint32_t prev = (uint32_t)__shfl_up((int)key[k], 1);
+            const bool head = lane == 0 || key[k] != prev;
+            const unsigned long long heads = __ballot(head);
+            const int first = 63 - __clzll(heads & below);               // head of this lane's run
+            const unsigned long long after = heads & ~below;
+            const int len = (after ? __ffsll(after) - 1 : 64) - lane;    // run length, read by heads only
+            int h = -1;
+            uint32_t base = 0;
+            if (head && key[k] != NO_KEY) {
+                h = (int)((key[k] * 2654435761u) >> 20) & (TAB - 1);
+                for (;;) {                                // at most CHUNK distinct keys: always a free entry
+                    const uint32_t old = atomicCAS(&tkey[h], NO_KEY, key[k]);
+                    if (old == NO_KEY || old == key[k]) break;
+                    h = (h + 1) & (TAB - 1);
+                }
+                base = atomicAdd(&tcnt[h], (uint32_t)len);
+            }
+            hs[k] = __shfl(h, first);
+            loc[k] = (uint32_t)__shfl((int)base, first) + (uint32_t)(lane - first);
+            if (key[k] == NO_KEY) hs[k] = -1;
+        }
+        __syncthreads();
+        const uint32_t sub = (uint32_t)(ch % SUB);
+        for (int e = threadIdx.x; e < TAB; e += NT) {
+            const uint32_t k = tkey[e];
+            if (k == NO_KEY) continue;
+            if (MODE == 0)
+                atomicAdd(counter + (size_t)k * SUB + sub, tcnt[e]);
+            else
+                tcnt[e] = atomicAdd(counter + (size_t)k * SUB + sub, tcnt[e]);   // this chunk's first slot
+        }
+        if (MODE == 1) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < CHUNK_PER_THREAD; ++k)
+                if (hs[k] >= 0) idx[tcnt[hs[k]] + loc[k]] = (uint32_t)(ch * CHUNK + k * NT + threadIdx.x);
+        }
+        __syncthreads();
+    }
+}
+
+// Exclusive prefix sum of the nc counters into start[0..nc] and cursor[0..nc),
+// in three launches: per-block sums of SCAN_TILE counters, an exclusive scan
+// of those sums in one block, and block-local scans offset by them.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* part, uint32_t* total) {
+    const int t = threadIdx.x;
+    part[t] = v;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {                 // inclusive Hillis-Steele scan
+        const uint32_t u = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += u;
+        __syncthreads();
+    }
+    const uint32_t incl = part[t];
+    *total = part[NT - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+constexpr int SCAN_PER_THREAD = 16;
+constexpr int SCAN_TILE = SCAN_PER_THREAD * NT;
+
+__global__ void __launch_bounds__(NT) k_scan_sums(const uint32_t* __restrict__ count, int64_t nc,
+                                                  uint32_t* __restrict__ sums) {
+    __shared__ uint32_t part[NT];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) s += base + k < nc ? count[base + k] : 0u;
+    uint32_t total;
+    block_exclusive_scan(s, part, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// One block: exclusive scan of the m tile sums in place (contiguous runs per thread).
+__global__ void __launch_bounds__(NT) k_scan_top(uint32_t* __restrict__ sums, int64_t m) {
+    __shared__ uint32_t part[NT];
+    const int64_t per = (m + NT - 1) / NT;
+    const int64_t lo = threadIdx.x * per, hi = lo + per < m ? lo + per : m;
+    uint32_t s = 0;
+    for (int64_t b = lo; b < hi; ++b) s += sums[b];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, part, &total);
+    for (int64_t b = lo; b < hi; ++b) {
+        const uint32_t v = sums[b];
+        sums[b] = run;
+        run += v;
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_scan_tiles(const uint32_t* __restrict__ count, int64_t nc,
+                                                   const uint32_t* __restrict__ sums, uint32_t* __restrict__ start,
+                                                   uint32_t* __restrict__ cursor) {
+    __shared__ uint32_t part[NT];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+    uint32_t v[SCAN_PER_THREAD];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+        v[k] = base + k < nc ? count[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t total;
+    uint32_t run = sums[blockIdx.x] + block_exclusive_scan(s, part, &total);
+#pragma unroll
+    for (int k = 0; k < SCAN_PER_THREAD; ++k) {
+        if (base + k < nc) {
+            start[base + k] = run;
+            cursor[base + k] = run;
+        }
+        run += v[k];
+    }
+    if (base + SCAN_PER_THREAD >= nc && base < nc) start[nc] = run;    // the thread holding the last counter
+}
+
+// Brick-local LDS index of a cell whose brick-local coordinates are l0, l1, l2
+// in [-1, BRICK].
+__device__ __forceinline__ int reg_index(int l0, int l1, int l2) { return ((l2 + 1) * REG + (l1 + 1)) * REG + (l0 + 1); }
+
+// Per-axis local cells (brick-local coordinate of the first stencil cell) and
+// weights.  CIC: weights 1 - t, t on cells floor(u - 1/2) and the next; TSC:
+// nearest cell c, d = u - (c + 1/2), weights (1/2 - d)^2/2, 3/4 - d^2,
+// (1/2 + d)^2/2 on cells c - 1, c, c + 1.  `org` is the brick's first cell.
 template <int M>
-__device__ __forceinline__ void axis_weights(double x, int n, int (&c)[M], double (&w)[M]) {
-    const double u = (x - floor(x)) * (double)n;       // [0, n]
+__device__ __forceinline__ int axis_local(double x, int n, int org, double (&w)[M]) {
+    const double u = cells_of(x, n);
+    const double f = floor(u);
+    int c = (int)f;
+    c -= c >= n ? n : 0;                                  // nearest cell, in this brick
     if constexpr (M == 2) {
-        const double f = floor(u - 0.5);
-        const double t = (u - 0.5) - f;
-        c[0] = wrap3((int)f, n);
-        c[1] = wrap3((int)f + 1, n);
+        const double g = floor(u - 0.5);                  // f - 1 or f
+        const double t = (u - 0.5) - g;
         w[0] = 1.0 - t;
         w[1] = t;
+        return c - org + (int)(g - f);
     } else {
-        const double f = floor(u);
         const double d = u - (f + 0.5);
-        c[0] = wrap3((int)f - 1, n);
-        c[1] = wrap3((int)f, n);
-        c[2] = wrap3((int)f + 1, n);
         const double a = 0.5 - d, b = 0.5 + d;
         w[0] = 0.5 * (a * a);
         w[1] = 0.75 - d * d;
         w[2] = 0.5 * (b * b);
+        return c - org - 1;
     }
 }
 
-// One particle per thread (grid-stride).  The y-z weights are folded into the
-// x weights before rounding, so each of the M^3 contributions is rounded once.
+__device__ __forceinline__ bool on_layer(int i, int n) {     // outer layer of its brick along an axis
+    const int l = i % BRICK;
+    const int w = min(BRICK, n - (i - l));
+    return l == 0 || l == w - 1;
+}
+
 template <int M>
-__global__ void __launch_bounds__(NT) k_assign(const double* __restrict__ pos, int64_t np, int n0, int n1, int n2,
-                                               unsigned long long* __restrict__ q) {
-    for (int64_t p = (int64_t)blockIdx.x * NT + threadIdx.x; p < np; p += (int64_t)gridDim.x * NT) {
-        const double x = pos[3 * p], y = pos[3 * p + 1], z = pos[3 * p + 2];
-        if (!isfinite(x) || !isfinite(y) || !isfinite(z)) continue;
-        int cx[M], cy[M], cz[M];
+__global__ void __launch_bounds__(ANT) k_bin_assign(AGrid g, const double* __restrict__ pos,
+                                                   const uint32_t* __restrict__ start,
+                                                   const uint32_t* __restrict__ idx, double scale,
+                                                   unsigned long long* __restrict__ stage,
+                                                   double* __restrict__ delta) {
+    __shared__ unsigned long long acc[REGN];
+    const int key = blockIdx.x;
+    const int bx = key % g.b0, by = (key / g.b0) % g.b1, bz = key / (g.b0 * g.b1);
+    const int o0 = bx * BRICK, o1 = by * BRICK, o2 = bz * BRICK;
+    const int w0 = min(BRICK, g.n0 - o0), w1 = min(BRICK, g.n1 - o1), w2 = min(BRICK, g.n2 - o2);
+    for (int e = threadIdx.x; e < REGN; e += ANT) acc[e] = 0ull;
+    __syncthreads();
+    const uint32_t lo = start[(size_t)key * SUB], hi = start[(size_t)(key + 1) * SUB];
+    // the next particle's index and position are loaded before this one's
+    // LDS atomics are issued
+    uint32_t t = lo + threadIdx.x;
+    double x = 0.0, y = 0.0, z = 0.0;
+    if (t < hi) {
+        const int64_t p = idx[t];
+        x = pos[3 * p];
+        y = pos[3 * p + 1];
+        z = pos[3 * p + 2];
+    }
+    for (; t < hi; t += ANT) {
+        double xn = 0.0, yn = 0.0, zn = 0.0;
+        if (t + ANT < hi) {
+            const int64_t p = idx[t + ANT];
+            xn = pos[3 * p];
+            yn = pos[3 * p + 1];
+            zn = pos[3 * p + 2];
+        }
         double wx[M], wy[M], wz[M];
-        axis_weights<M>(x, n0, cx, wx);
-        axis_weights<M>(y, n1, cy, wy);
-        axis_weights<M>(z, n2, cz, wz);
+        const int l0 = axis_local<M>(x, g.n0, o0, wx);
+        const int l1 = axis_local<M>(y, g.n1, o1, wy);
+        const int l2 = axis_local<M>(z, g.n2, o2, wz);
 #pragma unroll
         for (int a = 0; a < M; ++a) {
 #pragma unroll
             for (int b = 0; b < M; ++b) {
                 const double wyz = wz[a] * wy[b] * FIX_ONE;
-                unsigned long long* row = q + ((int64_t)cz[a] * n1 + cy[b]) * n0;
+                const int r = reg_index(l0, l1 + b, l2 + a);
 #pragma unroll
                 for (int c = 0; c < M; ++c)
-                    atomicAdd(row + cx[c], (unsigned long long)__double2ll_rn(wx[c] * wyz));
+                    atomicAdd(&acc[r + c], fix_round(wx[c], wyz));
             }
         }
+        x = xn;
+        y = yn;
+        z = zn;
+    }
+    __syncthreads();
+    const int r0 = w0 + 2, r1 = w1 + 2, r2 = w2 + 2;
+    const int64_t pl = (int64_t)g.n0 * g.n1;
+    unsigned long long* st = stage + (size_t)key * REGN;
+    for (int e = threadIdx.x; e < r0 * r1 * r2; e += ANT) {
+        const int l0 = e % r0 - 1, l1 = (e / r0) % r1 - 1, l2 = e / (r0 * r1) - 1;
+        const int r = reg_index(l0, l1, l2);
+        const unsigned long long q = acc[r];
+        const bool interior = l0 >= 1 && l0 <= w0 - 2 && l1 >= 1 && l1 <= w1 - 2 && l2 >= 1 && l2 <= w2 - 2;
+        if (interior)
+            delta[(int64_t)(o2 + l2) * pl + (int64_t)(o1 + l1) * g.n0 + (o0 + l0)] = (double)q * scale - 1.0;
+        else
+            st[r] = q;
     }
 }
 
-// In place: integer mass q (units of 2^-40) -> delta = q * scale - 1.
-__global__ void __launch_bounds__(NT) k_assign_finish(double* __restrict__ d, int64_t N, double scale) {
-    unsigned long long* q = reinterpret_cast<unsigned long long*>(d);
-    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < N; e += (int64_t)gridDim.x * NT)
-        d[e] = (double)q[e] * scale - 1.0;
+// The (brick, brick-local coordinate) pairs along one axis whose LDS region
+// entries land on cell i: the cell's own brick, and for the first (last) cell
+// of a brick the right (left) halo entry of the previous (next) brick, with
+// periodic wrap; returns how many (1 to 3).
+__device__ __forceinline__ int axis_sources(int i, int n, int nbrick, int (&b)[3], int (&l)[3]) {
+    const int bi = i / BRICK, li = i - bi * BRICK, w = min(BRICK, n - bi * BRICK);
+    int m = 0;
+    b[m] = bi;
+    l[m++] = li;
+    if (li == 0) {
+        const int bp = bi == 0 ? nbrick - 1 : bi - 1;
+        b[m] = bp;
+        l[m++] = min(BRICK, n - bp * BRICK);
+    }
+    if (li == w - 1) {
+        b[m] = bi == nbrick - 1 ? 0 : bi + 1;
+        l[m++] = -1;
+    }
+    return m;
 }
+
+// Outer-layer cells: the sum of the staged region entries of every brick that
+// reaches the cell, converted to delta = q * scale - 1.  Interior cells were
+// written by the accumulation.  One block per row (blockIdx.x = j, blockIdx.y = k).
+__global__ void __launch_bounds__(NT) k_layer_gather(AGrid g, const unsigned long long* __restrict__ stage,
+                                                     double scale, double* __restrict__ d) {
+    const int j = blockIdx.x, k = blockIdx.y;
+    const bool row_on = on_layer(j, g.n1) || on_layer(k, g.n2);
+    int b1[3], l1[3], b2[3], l2[3];
+    const int m1 = axis_sources(j, g.n1, g.b1, b1, l1);
+    const int m2 = axis_sources(k, g.n2, g.b2, b2, l2);
+    double* row = d + ((int64_t)k * g.n1 + j) * g.n0;
+    for (int i = threadIdx.x; i < g.n0; i += NT) {
+        if (!(row_on || on_layer(i, g.n0))) continue;
+        int b0[3], l0[3];
+        const int m0 = axis_sources(i, g.n0, g.b0, b0, l0);
+        unsigned long long q = 0ull;
+        for (int c = 0; c < m2; ++c)
+            for (int b = 0; b < m1; ++b)
+                for (int a = 0; a < m0; ++a) {
+                    const size_t key = ((size_t)b2[c] * g.b1 + b1[b]) * g.b0 + b0[a];
+                    q += stage[key * REGN + reg_index(l0[a], l1[b], l2[c])];
+                }
+        row[i] = (double)q * scale - 1.0;
+    }
+}
+
+inline int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 }  // namespace
 
-hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int n2, int scheme, double* delta,
-                              hipStream_t s) {
-    const int64_t N = (int64_t)n0 * n1 * n2;
-    unsigned long long* q = reinterpret_cast<unsigned long long*>(delta);
-    hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(N)), dim3(NT), 0, s, q, N);
+int64_t mass_assign_bricks(int n0, int n1, int n2) {
+    return (int64_t)((n0 + BRICK - 1) / BRICK) * ((n1 + BRICK - 1) / BRICK) * ((n2 + BRICK - 1) / BRICK);
+}
+
+int64_t mass_assign_workspace(int64_t np, int n0, int n1, int n2) {
+    const int64_t nc = mass_assign_bricks(n0, n1, n2) * SUB;
+    return 2 * align256(nc * 4) + align256((nc + 1) * 4) + align256((nc + SCAN_TILE - 1) / SCAN_TILE * 4) +
+           2 * align256(np * 4) + align256(mass_assign_bricks(n0, n1, n2) * REGN * 8);
+}
+
+hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int n2, int scheme, void* work,
+                              double* delta, hipStream_t s) {
+    AGrid g{n0, n1, n2, (n0 + BRICK - 1) / BRICK, (n1 + BRICK - 1) / BRICK, (n2 + BRICK - 1) / BRICK};
+    const int64_t nb = (int64_t)g.b0 * g.b1 * g.b2, nc = nb * SUB, N = (int64_t)n0 * n1 * n2;
+    char* w = static_cast<char*>(work);
+    uint32_t* count = reinterpret_cast<uint32_t*>(w);
+    w += align256(nc * 4);
+    uint32_t* cursor = reinterpret_cast<uint32_t*>(w);
+    w += align256(nc * 4);
+    uint32_t* start = reinterpret_cast<uint32_t*>(w);
+    w += align256((nc + 1) * 4);
+    uint32_t* sums = reinterpret_cast<uint32_t*>(w);
+    const int64_t ntile = (nc + SCAN_TILE - 1) / SCAN_TILE;
+    w += align256(ntile * 4);
+    uint32_t* keys = reinterpret_cast<uint32_t*>(w);
+    w += align256(np * 4);
+    uint32_t* idx = reinterpret_cast<uint32_t*>(w);
+    w += align256(np * 4);
+    unsigned long long* stage = reinterpret_cast<unsigned long long*>(w);
+    const double scale = FIX_INV * ((double)N / (double)np);
+    const int chunks = grid_for((np + CHUNK - 1) / CHUNK * NT, 8192);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nc)), dim3(NT), 0, s, count, nc);
+    hipLaunchKernelGGL(k_bin<0>, dim3(chunks), dim3(NT), 0, s, g, pos, np, count, keys, idx);
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)ntile), dim3(NT), 0, s, count, nc, sums);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(NT), 0, s, sums, ntile);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntile), dim3(NT), 0, s, count, nc, sums, start, cursor);
+    hipLaunchKernelGGL(k_bin<1>, dim3(chunks), dim3(NT), 0, s, g, pos, np, cursor, keys, idx);
     if (scheme == 1)
-        hipLaunchKernelGGL(k_assign<2>, dim3(grid_for(np)), dim3(NT), 0, s, pos, np, n0, n1, n2, q);
+        hipLaunchKernelGGL(k_bin_assign<2>, dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, scale, stage, delta);
     else
-        hipLaunchKernelGGL(k_assign<3>, dim3(grid_for(np)), dim3(NT), 0, s, pos, np, n0, n1, n2, q);
-    hipLaunchKernelGGL(k_assign_finish, dim3(grid_for(N)), dim3(NT), 0, s, delta, N,
-                       FIX_INV * ((double)N / (double)np));
+        hipLaunchKernelGGL(k_bin_assign<3>, dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, scale, stage, delta);
+    hipLaunchKernelGGL(k_layer_gather, dim3(n1, n2), dim3(NT), 0, s, g, stage, scale, delta);
     return hipGetLastError();
 }
 

@@ -184,9 +184,12 @@ hipError_t launch_total_force(int n0, int n1, int n2, double h, const double* ph
 hipError_t launch_interior_fill(const double* parent, int np0, int np1, int np2, double H, int n0, int n1, int n2,
                                 double h, int o0, int o1, int o2, double* phi, hipStream_t s);
 // Particles (np x 3, box units) -> delta on a periodic n0 x n1 x n2 grid;
-// scheme 1 cloud in cell, 2 triangular-shaped cloud (kernels_assign.hip)
-hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int n2, int scheme, double* delta,
-                              hipStream_t s);
+// scheme 1 cloud in cell, 2 triangular-shaped cloud (kernels_assign.hip).
+// work: mass_assign_workspace(np, n0, n1, n2) bytes, 256-byte aligned.
+int64_t mass_assign_bricks(int n0, int n1, int n2);
+int64_t mass_assign_workspace(int64_t np, int n0, int n1, int n2);
+hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int n2, int scheme, void* work,
+                              double* delta, hipStream_t s);
 
 // ---- mixed path (kernels_mixed.hip) ---------------------------------------
 // zero_in: the input correction is identically zero (first sweep of an inner

@@ -57,7 +57,7 @@ class Result(ctypes.Structure):
 EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
            "vmg_solve_periodic", "vmg_residual", "vmg_fill_ghosts", "vmg_ghost_count",
            "vmg_smooth", "vmg_plan_stats", "vmg_plan_config", "vmg_fill_interior", "vmg_total_force",
-           "vmg_mass_assign"]
+           "vmg_mass_assign", "vmg_mass_assign_workspace"]
 
 _lib = None
 
@@ -88,12 +88,15 @@ def load():
     L.vmg_ghost_count.restype = ctypes.c_int64
     L.vmg_smooth.argtypes = [vp, ctypes.c_int32]
     L.vmg_total_force.argtypes = [vp, vp, P(ctypes.c_int32), ctypes.c_double, vp, vp, vp]
-    L.vmg_mass_assign.argtypes = [vp, ctypes.c_int64, P(ctypes.c_int32), ctypes.c_int32, vp, vp]
+    L.vmg_mass_assign.argtypes = [vp, ctypes.c_int64, P(ctypes.c_int32), ctypes.c_int32, vp, ctypes.c_int64, vp,
+                                  vp]
+    L.vmg_mass_assign_workspace.argtypes = [ctypes.c_int64, P(ctypes.c_int32)]
+    L.vmg_mass_assign_workspace.restype = ctypes.c_int64
     L.vmg_plan_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
     i32p = P(ctypes.c_int32)
     L.vmg_plan_config.argtypes = [vp, i32p, i32p, i32p, i32p, i32p]
     for name in EXPORTS:
-        if name != "vmg_last_error" and name != "vmg_ghost_count":
+        if name not in ("vmg_last_error", "vmg_ghost_count", "vmg_mass_assign_workspace"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -234,17 +237,31 @@ def total_force(phi_newton, phi, h, psi=None, force=None, stream=None):
 ASSIGN_CIC, ASSIGN_TSC = 1, 2
 
 
-def mass_assign(pos, n, scheme=ASSIGN_TSC, delta=None, stream=None):
+def mass_assign_workspace(n_particles, n):
+    """vmg_mass_assign_workspace: device workspace bytes for mass_assign."""
+    nn = (n,) * 3 if isinstance(n, int) else tuple(int(v) for v in n)
+    return int(load().vmg_mass_assign_workspace(int(n_particles), (ctypes.c_int32 * 3)(*nn)))
+
+
+def mass_assign(pos, n, scheme=ASSIGN_TSC, delta=None, workspace=None, stream=None):
     """vmg_mass_assign: density contrast of unit-mass particles (device float64
     tensor of shape (N, 3), columns x, y, z in box units) on a periodic grid of
-    n cells (int or (n0, n1, n2)); returns delta shaped (n2, n1, n0)."""
+    n cells (int or (n0, n1, n2)); returns delta shaped (n2, n1, n0).
+    `workspace` (a device uint8 tensor of at least mass_assign_workspace bytes)
+    is allocated when not given."""
+    import torch
     nn = (n,) * 3 if isinstance(n, int) else tuple(int(v) for v in n)
     if delta is None:
-        import torch
         delta = torch.empty(nn[::-1], dtype=torch.float64, device=pos.device)
+    npart = int(pos.shape[0]) if pos.dim() else 0
+    if workspace is None:
+        need = mass_assign_workspace(npart, nn)
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=pos.device)
+    if not workspace.is_cuda or workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 tensor on the GPU")
     c = (ctypes.c_int32 * 3)(*nn)
-    _check(load().vmg_mass_assign(_ptr(pos), int(pos.shape[0]) if pos.dim() else 0, c, int(scheme), _ptr(delta),
-                                  _stream(stream)))
+    _check(load().vmg_mass_assign(_ptr(pos), npart, c, int(scheme), ctypes.c_void_p(workspace.data_ptr()),
+                                  workspace.numel(), _ptr(delta), _stream(stream)))
     return delta
 
 

@@ -61,11 +61,22 @@ def test_mass_assign_rejects_bad_arguments():
     from paper_1303_0008_amd import vmg
     lib = vmg.load()
     n = (ctypes.c_int32 * 3)(8, 8, 8)
-    fake = ctypes.c_void_p(16)          # never dereferenced: each call fails validation first
-    assert lib.vmg_mass_assign(None, 1, n, vmg.ASSIGN_TSC, fake, None) == vmg.VMG_EINVAL
-    assert lib.vmg_mass_assign(fake, 0, n, vmg.ASSIGN_TSC, fake, None) == vmg.VMG_EINVAL
+    fake = ctypes.c_void_p(256)         # never dereferenced: each call fails validation first
+    need = lib.vmg_mass_assign_workspace(100, n)
+    assert need >= 100 * 12
+    assert lib.vmg_mass_assign_workspace(0, n) == -1
+    args = (n, vmg.ASSIGN_TSC, fake, need, fake, None)
+    assert lib.vmg_mass_assign(None, 100, *args) == vmg.VMG_EINVAL
+    assert lib.vmg_mass_assign(fake, 0, *args) == vmg.VMG_EINVAL
     assert "n_particles" in vmg.last_error()
-    assert lib.vmg_mass_assign(fake, 1, n, 3, fake, None) == vmg.VMG_EINVAL
+    assert lib.vmg_mass_assign(fake, 1 << 31, *args) == vmg.VMG_EINVAL
+    assert lib.vmg_mass_assign(fake, 100, n, 3, fake, need, fake, None) == vmg.VMG_EINVAL
     assert "scheme" in vmg.last_error()
-    bad = (ctypes.c_int32 * 3)(8, 0, 8)
-    assert lib.vmg_mass_assign(fake, 1, bad, vmg.ASSIGN_CIC, fake, None) == vmg.VMG_EINVAL
+    for bad in ((8, 0, 8), (8, 8, 65536)):
+        bad = (ctypes.c_int32 * 3)(*bad)
+        assert lib.vmg_mass_assign(fake, 100, bad, vmg.ASSIGN_CIC, fake, need, fake, None) == vmg.VMG_EINVAL
+    assert lib.vmg_mass_assign(fake, 100, n, vmg.ASSIGN_CIC, fake, need - 1, fake, None) == vmg.VMG_EINVAL
+    assert "workspace" in vmg.last_error()
+    assert lib.vmg_mass_assign(fake, 100, n, vmg.ASSIGN_CIC, ctypes.c_void_p(264), need, fake,
+                               None) == vmg.VMG_EINVAL
+    assert lib.vmg_mass_assign(fake, 100, n, vmg.ASSIGN_CIC, None, need, fake, None) == vmg.VMG_EINVAL
