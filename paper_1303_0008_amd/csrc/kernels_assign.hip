@@ -15,12 +15,11 @@
 //                     reserves a range of that brick's slots with one atomic,
 //                     and the particle indices are written sorted by brick;
 //   4. k_bin_assign   one workgroup per brick: the brick and a one-cell halo
-//                     are accumulated in LDS; interior cells (which no other
-//                     brick reaches) are stored as final delta, the outer layer
-//                     and halo entries are staged in the workspace;
-//   5. k_layer_gather every outer-layer cell sums the staged entries of the
-//                     bricks that reach it (at most 8; 27 where bricks are one
-//                     cell wide).
+//                     are accumulated in LDS and the region is copied to the
+//                     workspace;
+//   5. k_gather       every cell sums the staged entries of the bricks that
+//                     reach it (one; up to 8 on the outer layer of a brick, 27
+//                     where bricks are one cell wide) and writes delta.
 // No global atomics touch the density, so the sums are formed in a fixed order.
 // Masses are 64-bit fixed point (2^-40 of a particle per unit): every
 // contribution is rounded once and all sums are integer, so the result does
@@ -42,13 +41,6 @@ struct AGrid {
     int n0, n1, n2;          // cells
     int b0, b1, b2;          // bricks per axis
 };
-
-__device__ __forceinline__ int wrap3(int i, int n) {    // [-n, 3n) -> [0, n)
-    i += i < 0 ? n : 0;
-    i -= i >= n ? n : 0;
-    i -= i >= n ? n : 0;
-    return i;
-}
 
 // u = position in cells along an axis, in [0, n]; f = floor(u) unwrapped; the
 // nearest cell is f mod n.
@@ -273,23 +265,15 @@ __device__ __forceinline__ int axis_local(double x, int n, int org, double (&w)[
     }
 }
 
-__device__ __forceinline__ bool on_layer(int i, int n) {     // outer layer of its brick along an axis
-    const int l = i % BRICK;
-    const int w = min(BRICK, n - (i - l));
-    return l == 0 || l == w - 1;
-}
-
 template <int M>
 __global__ void __launch_bounds__(ANT) k_bin_assign(AGrid g, const double* __restrict__ pos,
                                                    const uint32_t* __restrict__ start,
-                                                   const uint32_t* __restrict__ idx, double scale,
-                                                   unsigned long long* __restrict__ stage,
-                                                   double* __restrict__ delta) {
+                                                   const uint32_t* __restrict__ idx,
+                                                   unsigned long long* __restrict__ stage) {
     __shared__ unsigned long long acc[REGN];
     const int key = blockIdx.x;
     const int bx = key % g.b0, by = (key / g.b0) % g.b1, bz = key / (g.b0 * g.b1);
     const int o0 = bx * BRICK, o1 = by * BRICK, o2 = bz * BRICK;
-    const int w0 = min(BRICK, g.n0 - o0), w1 = min(BRICK, g.n1 - o1), w2 = min(BRICK, g.n2 - o2);
     for (int e = threadIdx.x; e < REGN; e += ANT) acc[e] = 0ull;
     __syncthreads();
     const uint32_t lo = start[(size_t)key * SUB], hi = start[(size_t)(key + 1) * SUB];
@@ -331,19 +315,8 @@ __global__ void __launch_bounds__(ANT) k_bin_assign(AGrid g, const double* __res
         z = zn;
     }
     __syncthreads();
-    const int r0 = w0 + 2, r1 = w1 + 2, r2 = w2 + 2;
-    const int64_t pl = (int64_t)g.n0 * g.n1;
     unsigned long long* st = stage + (size_t)key * REGN;
-    for (int e = threadIdx.x; e < r0 * r1 * r2; e += ANT) {
-        const int l0 = e % r0 - 1, l1 = (e / r0) % r1 - 1, l2 = e / (r0 * r1) - 1;
-        const int r = reg_index(l0, l1, l2);
-        const unsigned long long q = acc[r];
-        const bool interior = l0 >= 1 && l0 <= w0 - 2 && l1 >= 1 && l1 <= w1 - 2 && l2 >= 1 && l2 <= w2 - 2;
-        if (interior)
-            delta[(int64_t)(o2 + l2) * pl + (int64_t)(o1 + l1) * g.n0 + (o0 + l0)] = (double)q * scale - 1.0;
-        else
-            st[r] = q;
-    }
+    for (int e = threadIdx.x; e < REGN; e += ANT) st[e] = acc[e];
 }
 
 // The (brick, brick-local coordinate) pairs along one axis whose LDS region
@@ -367,19 +340,18 @@ __device__ __forceinline__ int axis_sources(int i, int n, int nbrick, int (&b)[3
     return m;
 }
 
-// Outer-layer cells: the sum of the staged region entries of every brick that
-// reaches the cell, converted to delta = q * scale - 1.  Interior cells were
-// written by the accumulation.  One block per row (blockIdx.x = j, blockIdx.y = k).
-__global__ void __launch_bounds__(NT) k_layer_gather(AGrid g, const unsigned long long* __restrict__ stage,
-                                                     double scale, double* __restrict__ d) {
+// Every cell: the sum of the staged region entries of the bricks that reach it
+// (its own brick's entry, plus halo entries of neighbours for outer-layer
+// cells), converted to delta = q * scale - 1.  One block per row
+// (blockIdx.x = j, blockIdx.y = k), so the density is written in whole rows.
+__global__ void __launch_bounds__(NT) k_gather(AGrid g, const unsigned long long* __restrict__ stage, double scale,
+                                               double* __restrict__ d) {
     const int j = blockIdx.x, k = blockIdx.y;
-    const bool row_on = on_layer(j, g.n1) || on_layer(k, g.n2);
     int b1[3], l1[3], b2[3], l2[3];
     const int m1 = axis_sources(j, g.n1, g.b1, b1, l1);
     const int m2 = axis_sources(k, g.n2, g.b2, b2, l2);
     double* row = d + ((int64_t)k * g.n1 + j) * g.n0;
     for (int i = threadIdx.x; i < g.n0; i += NT) {
-        if (!(row_on || on_layer(i, g.n0))) continue;
         int b0[3], l0[3];
         const int m0 = axis_sources(i, g.n0, g.b0, b0, l0);
         unsigned long long q = 0ull;
@@ -435,10 +407,10 @@ hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntile), dim3(NT), 0, s, count, nc, sums, start, cursor);
     hipLaunchKernelGGL(k_bin<1>, dim3(chunks), dim3(NT), 0, s, g, pos, np, cursor, keys, idx);
     if (scheme == 1)
-        hipLaunchKernelGGL(k_bin_assign<2>, dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, scale, stage, delta);
+        hipLaunchKernelGGL(k_bin_assign<2>, dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, stage);
     else
-        hipLaunchKernelGGL(k_bin_assign<3>, dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, scale, stage, delta);
-    hipLaunchKernelGGL(k_layer_gather, dim3(n1, n2), dim3(NT), 0, s, g, stage, scale, delta);
+        hipLaunchKernelGGL(k_bin_assign<3>, dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, stage);
+    hipLaunchKernelGGL(k_gather, dim3(n1, n2), dim3(NT), 0, s, g, stage, scale, delta);
     return hipGetLastError();
 }
 
