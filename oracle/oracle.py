@@ -138,13 +138,14 @@ def cell_operator(delta, phi, alpha, kappa, ijk, h=None, ghost=None, w=W_PAPER):
     return tuple(out)
 
 
-def fill_interior(parent, n, h, origin):
-    """Initial guess on a patch (n cells of size h, cell (0,0,0) at origin*h):
-    trilinear interpolation of the periodic cell-centred ``parent`` at every
-    cell centre, shaped (n2, n1, n0)."""
+def fill_interior(parent, n, h, origin, H=None):
+    """Initial guess on a patch (n cells of size h, cell (0,0,0) at origin*h from
+    the parent's cell (0,0,0) corner): trilinear interpolation of the
+    cell-centred ``parent`` (cells of size H, default: the unit box; periodic
+    indexing) at every cell centre, shaped (n2, n1, n0)."""
     parent = _f64(parent)
     npar = _dims(parent)
-    H = 1.0 / npar[0]
+    H = 1.0 / npar[0] if H is None else H
     nn = (n,) * 3 if np.isscalar(n) else tuple(n)
     out = np.zeros(nn[::-1])
     rc = lib().or_fill_interior(_ivec(npar), H, _dp(parent), _ivec(nn), h, _ivec(origin), _dp(out))
@@ -152,17 +153,49 @@ def fill_interior(parent, n, h, origin):
     return out
 
 
-def fill_ghosts(parent, n, h, origin):
-    """Ghost shell of a patch (n cells of size h, cell (0,0,0) at origin*h) by
-    trilinear interpolation of the periodic cell-centred ``parent`` field."""
+def fill_ghosts(parent, n, h, origin, H=None):
+    """Ghost shell of a patch (n cells of size h, cell (0,0,0) at origin*h from
+    the parent's cell (0,0,0) corner) by trilinear interpolation of the
+    cell-centred ``parent`` field (cells of size H, default: the unit box;
+    periodic indexing)."""
     parent = _f64(parent)
     npar = _dims(parent)
-    H = 1.0 / npar[0]
+    H = 1.0 / npar[0] if H is None else H
     nn = (n,) * 3 if np.isscalar(n) else tuple(n)
     g = np.zeros(ghost_count(nn))
     rc = lib().or_fill_ghosts(_ivec(npar), H, _dp(parent), _ivec(nn), h, _ivec(origin), _dp(g))
     assert rc == 0
     return g
+
+
+def solve_levels(levels, alpha, kappa, tol=0.0, max_cycles=200):
+    """Multilevel solve (Sec. III.C: the domain grid and every refinement are
+    solved, a refinement taking its boundary values interpolated from the
+    coarser level; Sec. IV.D: a refinement over the overdensity with boundary
+    values from the domain grid).  ``levels``: list of dicts in parent-before-
+    child order with keys delta (n2, n1, n0), h, parent (-1 for the root),
+    origin (3 ints: cell (0,0,0) of the grid in its own cells from the
+    parent's cell (0,0,0) corner) and, for a root, ghost (None: periodic).
+    Each refinement starts from the trilinear interpolation of its parent's
+    solution (ghost shell and interior) and is solved to ``tol``.  Returns
+    (phis, infos)."""
+    phis, infos = [], []
+    for g in levels:
+        if g["parent"] < 0:
+            phi, info = solve(g["delta"], alpha, kappa, h=g["h"], ghost=g.get("ghost"), tol=tol,
+                              max_cycles=max_cycles)
+        else:
+            par = levels[g["parent"]]
+            n = _dims(g["delta"])
+            P = phis[g["parent"]]
+            ghost = fill_ghosts(P, n, g["h"], g["origin"], H=par["h"])
+            phi0 = fill_interior(P, n, g["h"], g["origin"], H=par["h"])
+            phi, info = solve(g["delta"], alpha, kappa, h=g["h"], ghost=ghost, phi0=phi0, tol=tol,
+                              max_cycles=max_cycles)
+            info["ghost"] = ghost
+        phis.append(phi)
+        infos.append(info)
+    return phis, infos
 
 
 def total_force(phi_n, phi, h):

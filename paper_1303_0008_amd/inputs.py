@@ -61,6 +61,24 @@ def tophat(n, radius=0.1, amplitude=50.0, centre=(0.5, 0.5, 0.5)):
     return np.ascontiguousarray(d - d.mean())
 
 
+def tophat_region(shape, h, corner, domain_n, radius=0.1, amplitude=50.0, centre=(0.5, 0.5, 0.5)):
+    """The top-hat of ``tophat(domain_n, ...)`` sampled at the cell centres of a
+    region of ``shape`` = (n0, n1, n2) cells of size ``h`` whose cell (0,0,0)
+    corner sits at ``corner`` (box units; taken modulo 1), minus the same mean
+    as the domain field, shaped (n2, n1, n0)."""
+    n0, n1, n2 = shape
+    dom = np.where(_tophat_r2(cell_centres(domain_n), centre) < radius * radius, amplitude, 0.0)
+    axes = [np.mod(corner[a] + (np.arange(n) + 0.5) * h, 1.0) for a, n in enumerate((n0, n1, n2))]
+    d = np.where(_tophat_r2(axes, centre) < radius * radius, amplitude, 0.0)
+    return np.ascontiguousarray(d - dom.mean())
+
+
+def _tophat_r2(axes, centre):
+    x, y, z = axes
+    return ((z[:, None, None] - centre[2]) ** 2 + (y[None, :, None] - centre[1]) ** 2
+            + (x[None, None, :] - centre[0]) ** 2)
+
+
 def gaussian_field(n, spectral_index, seed, std=1.0, kmax_cells=None):
     """Gaussian random field with power spectrum P(k) proportional to k**spectral_index.
 
