@@ -172,6 +172,39 @@ vmg_status vmg_fill_ghosts(const double *parent, const int32_t np[3], double par
                            const vmg_grid *grids, const int32_t *origins, int32_t n_grids,
                            double *ghost, hipStream_t stream);
 
+/* Place of a refinement in a multilevel hierarchy: the index of its parent in
+ * the hierarchy's grid array (-1 for the domain grid) and the position of its
+ * cell (0,0,0) corner from the parent's cell (0,0,0) corner, in units of its
+ * own cell size (the origins of vmg_fill_ghosts). */
+typedef struct {
+    int32_t parent;
+    int32_t origin[3];
+} vmg_nest;
+
+/* Multilevel solve (Sec. III.C: the domain grid and the refinements are each
+ * solved with multigrid, a refinement taking the boundary values of its edge
+ * cells interpolated from the coarser level; Sec. IV.D: a refinement placed
+ * over the overdensity, with the same density on it).  grids[0] is the
+ * periodic domain grid (nest[0].parent = -1); every other grid is a Dirichlet
+ * refinement whose parent comes earlier in the array, with half the parent's
+ * cell size.  Under the domain grid a refinement may sit anywhere (origin in
+ * [0, 2 n) per axis; it wraps); under a refinement it keeps one parent cell of
+ * margin (origin >= 2 and origin + n <= 2 n_parent - 2 per axis), so the
+ * interpolation needs no value outside the parent.  The solve runs level by
+ * level: the domain grid from the phi given at its offset, then each depth of
+ * the tree as one batched plan, every refinement starting from ghost values
+ * (written to `ghost` at its ghost_offset) and an initial guess interpolated
+ * trilinearly from its parent's solution (as vmg_fill_ghosts and
+ * vmg_fill_interior).  Refinements do not feed back into their parents.
+ * delta, ghost and phi are device arrays holding every grid at its offset (x
+ * fastest); phi receives every solution.  p applies to every level (tau_factor
+ * to the domain grid only); out: host array of n_grids results.  Creates and
+ * destroys its plans (allocates).  Errors: VMG_EINVAL (nesting or arguments),
+ * otherwise the first failing level's status (VMG_ENOCONV, VMG_ENONFINITE,
+ * ...; deeper levels are then not solved), VMG_EHIP. */
+vmg_status vmg_solve_levels(const vmg_grid *grids, const vmg_nest *nest, int32_t n_grids, const vmg_params *p,
+                            const double *delta, double *ghost, double *phi, vmg_result *out, hipStream_t stream);
+
 /* Initial guess on refinements (Sec. III.C, IV.D: a refinement starts from the
  * solution of the coarser level, interpolated): the same trilinear
  * interpolation of the periodic parent as vmg_fill_ghosts, at every cell centre

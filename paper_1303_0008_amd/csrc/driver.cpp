@@ -642,6 +642,73 @@ vmg_status vmg_solve_periodic(const double* delta, int32_t n, double alpha, doub
     return st;
 }
 
+// Multilevel solve: the domain grid, then every depth of the refinement tree in
+// one batched plan, each refinement starting from its parent's solution
+// interpolated to its ghost shell and interior.
+vmg_status vmg_solve_levels(const vmg_grid* grids, const vmg_nest* nest, int32_t n_grids, const vmg_params* p,
+                            const double* delta, double* ghost, double* phi, vmg_result* out, hipStream_t stream) {
+    g_err.clear();
+    if (!grids || !nest || !p || !delta || !phi || !out || n_grids < 1) return fail(VMG_EINVAL, "null argument");
+    if (nest[0].parent != -1 || grids[0].bc != VMG_PERIODIC)
+        return fail(VMG_EINVAL, "grid 0 must be the periodic domain grid (parent -1)");
+    if (n_grids > 1 && !ghost) return fail(VMG_EINVAL, "refinements need a ghost array");
+    std::vector<int> depth(n_grids, 0);
+    int max_depth = 0;
+    for (int i = 1; i < n_grids; ++i) {
+        const int pa = nest[i].parent;
+        if (pa < 0 || pa >= i)
+            return fail(VMG_EINVAL, "grid " + std::to_string(i) + ": the parent must be an earlier grid");
+        const vmg_grid& g = grids[i];
+        const vmg_grid& P = grids[pa];
+        if (g.bc != VMG_DIRICHLET) return fail(VMG_EINVAL, "grid " + std::to_string(i) + ": refinements are Dirichlet");
+        if (!(std::fabs(2.0 * g.h - P.h) <= 1e-12 * P.h))
+            return fail(VMG_EINVAL, "grid " + std::to_string(i) + ": a refinement halves its parent's cell size");
+        for (int d = 0; d < 3; ++d) {
+            const int o = nest[i].origin[d];
+            const bool ok = P.bc == VMG_PERIODIC ? (o >= 0 && o < 2 * P.n[d])
+                                                 : (o >= 2 && o + g.n[d] <= 2 * P.n[d] - 2);
+            if (!ok)
+                return fail(VMG_EINVAL, "grid " + std::to_string(i) +
+                                            ": origin outside the parent (a refinement parent needs one cell of margin)");
+        }
+        depth[i] = depth[pa] + 1;
+        max_depth = std::max(max_depth, depth[i]);
+    }
+    vmg_params pr = *p;
+    for (int d = 0; d <= max_depth; ++d) {
+        std::vector<vmg_grid> sub;
+        std::vector<int> idx;
+        for (int i = 0; i < n_grids; ++i)
+            if (depth[i] == d) {
+                sub.push_back(grids[i]);
+                idx.push_back(i);
+            }
+        if (d > 0) {
+            pr.tau_factor = 0.0;                  // the truncation-error rule applies to the domain grid only
+            for (int i : idx) {
+                const vmg_grid& g = grids[i];
+                const vmg_grid& P = grids[nest[i].parent];
+                const int* o = nest[i].origin;
+                CKH(launch_ghost_fill(phi + P.offset, P.n[0], P.n[1], P.n[2], P.h, g.n[0], g.n[1], g.n[2], g.h, o[0],
+                                      o[1], o[2], ghost + g.ghost_offset, stream));
+                CKH(launch_interior_fill(phi + P.offset, P.n[0], P.n[1], P.n[2], P.h, g.n[0], g.n[1], g.n[2], g.h,
+                                         o[0], o[1], o[2], phi + g.offset, stream));
+            }
+        }
+        vmg_plan* plan = nullptr;
+        vmg_status st = vmg_plan_create(&plan, sub.data(), (int32_t)sub.size(), &pr, stream);
+        if (st != VMG_OK) return st;
+        std::vector<vmg_result> res(sub.size());
+        st = vmg_solve(plan, delta, d > 0 ? ghost : nullptr, nullptr, phi, res.data());
+        const std::string msg = g_err;
+        vmg_plan_destroy(plan);
+        g_err = msg;
+        for (size_t k = 0; k < idx.size(); ++k) out[idx[k]] = res[k];
+        if (st != VMG_OK) return st;
+    }
+    return VMG_OK;
+}
+
 vmg_status vmg_residual(vmg_plan* plan, int32_t gi, const double* delta, const double* ghost,
                         const double* source, const double* phi, double* d, vmg_result* res) {
     g_err.clear();

@@ -53,11 +53,15 @@ class Result(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Nest(ctypes.Structure):
+    _fields_ = [("parent", ctypes.c_int32), ("origin", ctypes.c_int32 * 3)]
+
+
 # Every symbol declared in include/vmg.h (checked by the CPU test-suite).
 EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
            "vmg_solve_periodic", "vmg_residual", "vmg_fill_ghosts", "vmg_ghost_count",
            "vmg_smooth", "vmg_plan_stats", "vmg_plan_config", "vmg_fill_interior", "vmg_total_force",
-           "vmg_mass_assign", "vmg_mass_assign_workspace"]
+           "vmg_mass_assign", "vmg_mass_assign_workspace", "vmg_solve_levels"]
 
 _lib = None
 
@@ -91,6 +95,7 @@ def load():
     L.vmg_mass_assign.argtypes = [vp, ctypes.c_int64, P(ctypes.c_int32), ctypes.c_int32, vp, ctypes.c_int64, vp,
                                   vp]
     L.vmg_mass_assign_workspace.argtypes = [ctypes.c_int64, P(ctypes.c_int32)]
+    L.vmg_solve_levels.argtypes = [P(Grid), P(Nest), ctypes.c_int32, P(Params), vp, vp, vp, P(Result), vp]
     L.vmg_mass_assign_workspace.restype = ctypes.c_int64
     L.vmg_plan_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
     i32p = P(ctypes.c_int32)
@@ -207,6 +212,31 @@ def fill_ghosts(parent, parent_h, grids, origins, ghost, stream=None):
     org = (ctypes.c_int32 * len(flat))(*flat)
     _check(load().vmg_fill_ghosts(_ptr(parent), npar, parent_h, arr, org, len(grids), _ptr(ghost),
                                   _stream(stream)))
+
+
+def make_nest(parent, origin=(0, 0, 0)):
+    n = Nest()
+    n.parent = parent
+    n.origin[:] = tuple(int(v) for v in origin)
+    return n
+
+
+def solve_levels(grids, nests, params, delta, ghost, phi, stream=None, allow_noconv=False):
+    """vmg_solve_levels: the domain grid (grids[0]) and its nested refinements,
+    level by level, each refinement from its parent's interpolated solution.
+    delta/ghost/phi: device float64 tensors holding every grid at its offset.
+    Returns a list of result dicts (one per grid)."""
+    n = len(grids)
+    garr = (Grid * n)(*grids)
+    narr = (Nest * n)(*nests)
+    res = (Result * n)()
+    st = load().vmg_solve_levels(garr, narr, n, ctypes.byref(params), _ptr(delta), _ptr(ghost), _ptr(phi), res,
+                                 _stream(stream))
+    _check(st, allow=(VMG_ENOCONV,) if allow_noconv else ())
+    out = [r.as_dict() for r in res]
+    for r in out:
+        r["status"] = st
+    return out
 
 
 def fill_interior(parent, parent_h, grids, origins, phi, stream=None):

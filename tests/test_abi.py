@@ -80,3 +80,41 @@ def test_mass_assign_rejects_bad_arguments():
     assert lib.vmg_mass_assign(fake, 100, n, vmg.ASSIGN_CIC, ctypes.c_void_p(264), need, fake,
                                None) == vmg.VMG_EINVAL
     assert lib.vmg_mass_assign(fake, 100, n, vmg.ASSIGN_CIC, None, need, fake, None) == vmg.VMG_EINVAL
+
+
+def test_solve_levels_rejects_bad_nesting():
+    """vmg_solve_levels validates the tree before any device call (Sec. III.C
+    refinements: half the parent's cell size, inside the parent)."""
+    from paper_1303_0008_amd import vmg
+    lib = vmg.load()
+    fake = ctypes.c_void_p(256)
+    p = vmg.make_params(0.1, 1.5, 1e-8)
+
+    def call(grids, nests):
+        n = len(grids)
+        res = (vmg.Result * n)()
+        return lib.vmg_solve_levels((vmg.Grid * n)(*grids), (vmg.Nest * n)(*nests), n, ctypes.byref(p), fake,
+                                    fake, fake, res, None)
+
+    dom = vmg.make_grid(32)
+    ok = vmg.make_grid(8, 1 / 64, vmg.DIRICHLET, 32 ** 3, 0)
+    # the domain grid must come first, periodic, parent -1
+    assert call([ok], [vmg.make_nest(-1)]) == vmg.VMG_EINVAL
+    assert call([dom, ok], [vmg.make_nest(0), vmg.make_nest(0)]) == vmg.VMG_EINVAL
+    # parent must precede the child; cell size must halve
+    assert call([dom, ok], [vmg.make_nest(-1), vmg.make_nest(1)]) == vmg.VMG_EINVAL
+    bad_h = vmg.make_grid(8, 1 / 48, vmg.DIRICHLET, 32 ** 3, 0)
+    assert call([dom, bad_h], [vmg.make_nest(-1), vmg.make_nest(0)]) == vmg.VMG_EINVAL
+    assert "halves" in vmg.last_error()
+    # origin outside a periodic parent
+    assert call([dom, ok], [vmg.make_nest(-1), vmg.make_nest(0, (64, 0, 0))]) == vmg.VMG_EINVAL
+    # under a refinement: one parent cell of margin on every side
+    child = vmg.make_grid(4, 1 / 128, vmg.DIRICHLET, 32 ** 3 + 512, 400)
+    for origin in ((1, 2, 2), (2, 2, 13)):      # 13 + 4 > 2 * 8 - 2
+        assert call([dom, ok, child], [vmg.make_nest(-1), vmg.make_nest(0, (8, 8, 8)),
+                                        vmg.make_nest(1, origin)]) == vmg.VMG_EINVAL
+        assert "margin" in vmg.last_error()
+    # refinements need a ghost array
+    res = (vmg.Result * 2)()
+    assert lib.vmg_solve_levels((vmg.Grid * 2)(dom, ok), (vmg.Nest * 2)(vmg.make_nest(-1), vmg.make_nest(0)), 2,
+                                ctypes.byref(p), fake, None, fake, res, None) == vmg.VMG_EINVAL
