@@ -19,6 +19,11 @@ back-to-back launches on the plan's stream.
 shaped cloud and cloud in cell) of the workload's 256^3 particles onto the
 256^3 grid, outside the solve.
 
+``results`` also holds, each outside the timed solves: the total potential and
+force kernel at 256^3 (bandwidth in algorithmic bytes), FP64 solves stopped by
+the truncation-error rule (|d| <= |tau|/3), and a multilevel solve of the
+workload with two nested levels of refinements.
+
 ``cpu_baseline`` times the CPU oracle (plain FP64 C, one thread) on a bounded
 sample of the same workload: five lexicographic Newton-Gauss-Seidel sweeps
 over the full 256^3 grid.
@@ -70,9 +75,9 @@ def load_traffic(name, kernel):
     return d.get("bytes_per_launch")
 
 
-def time_solves(torch, V, delta, w, prec, steps, warmup, flags, stream):
+def time_solves(torch, V, delta, w, prec, steps, warmup, flags, stream, tau_factor=0.0):
     n = w["n"]
-    params = V.make_params(w["alpha"], w["kappa"], w["tol"], 100, prec, flags=flags)
+    params = V.make_params(w["alpha"], w["kappa"], w["tol"], 100, prec, flags=flags, tau_factor=tau_factor)
     plan = V.Plan([V.make_grid(n)], params, stream=stream)
     phis = [torch.zeros_like(delta) for _ in range(steps + warmup)]
     infos = []
@@ -224,6 +229,93 @@ def time_mass_assign(torch, V, stream, launches):
     return out
 
 
+def time_total_force(torch, V, delta, w, stream, launches):
+    """Total potential and force (vmg_total_force) on the workload's 256^3 grid from
+    the solved brane-bending mode and the Newtonian potential (alpha = 0 solve of
+    the same density, kappa = (3/2) Omega_m a with Omega_m = 0.257, a = 1)."""
+    n = w["n"]
+    phi, _ = V.solve_field(delta, w["alpha"], w["kappa"], tol=w["tol"])
+    phin, _ = V.solve_field(delta, 0.0, 1.5 * 0.257, tol=w["tol"])
+    psi = torch.empty_like(phi)
+    force = torch.empty((3,) + tuple(phi.shape), dtype=torch.float64, device="cuda")
+    V.total_force(phin, phi, 1.0 / n, psi=psi, force=force, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(launches):
+        V.total_force(phin, phi, 1.0 / n, psi=psi, force=force, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / launches
+    bpc = 48                                   # phi_N, phi in; Psi and three force components out
+    gbs = bpc * n ** 3 / (us * 1e-6) / 1e9
+    log(f"total force: {us:.1f} us per call = {gbs:.0f} GB/s algorithmic")
+    return {"us_per_call": us, "algorithmic_bytes_per_cell": bpc, "achieved_gbs": gbs,
+            "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+
+
+def time_tau_rule(torch, V, delta, w, stream, steps):
+    """FP64 solves that also stop on the truncation-error rule |d| <= |tau|/3."""
+    plan, infos, updates, dt, _ = time_solves(torch, V, delta, dict(w), V.FP64, steps, 1, V.GRAPH | V.AUTOTUNE,
+                                              stream, tau_factor=1.0 / 3.0)
+    plan.close()
+    r = infos[-1]
+    log(f"tau rule (1/3): {1e3 * dt / steps:.3f} ms/solve, cycles {r['cycles']}, rms {r['rms']:.3e}, "
+        f"tau rms {r['tau_rms']:.3e}")
+    return {"tau_factor": 1.0 / 3.0, "time_to_stop_ms": 1e3 * dt / steps, "cycles": r["cycles"], "rms": r["rms"],
+            "tau_rms": r["tau_rms"]}
+
+
+def time_levels(torch, V, delta_np, w, steps):
+    """vmg_solve_levels on the workload's domain grid with 8 first-level 64^3
+    refinements at h = 1/512 centred on the 8 densest cells at least 40 cells
+    apart (so the refinements do not overlap) and a
+    64^3 second level at h = 1/1024 in the middle of each (mixed precision, tol as
+    the workload); each refinement's density is a seeded lognormal (sigma 1.5).
+    Wall time per vmg_levels_solve on a plan created beforehand."""
+    import numpy as np
+    from paper_1303_0008_amd import inputs as I
+    n = w["n"]
+    flat = np.argsort(delta_np.ravel())[::-1]
+    peaks = []
+    for f in flat:
+        k, j, i = np.unravel_index(f, delta_np.shape)
+        if all(max(min(abs(c - q), n - abs(c - q)) for c, q in zip((i, j, k), p)) >= 40 for p in peaks):
+            peaks.append((i, j, k))
+        if len(peaks) == 8:
+            break
+    grids = [V.make_grid(n)]
+    nests = [V.make_nest(-1)]
+    deltas = [delta_np]
+    off, goff = delta_np.size, 0
+    for lev, h in ((1, 1.0 / (2 * n)), (2, 1.0 / (4 * n))):
+        for t, p in enumerate(peaks):
+            parent = 0 if lev == 1 else 1 + t
+            origin = tuple((2 * c - 32) % (2 * n) for c in p) if lev == 1 else (32, 32, 32)
+            grids.append(V.make_grid(64, h, V.DIRICHLET, off, goff))
+            nests.append(V.make_nest(parent, origin))
+            deltas.append(I.lognormal(64, I.BASE_SEED + 500 + 10 * lev + t, sigma=1.5))
+            off += 64 ** 3
+            goff += V.ghost_count(64)
+    d = torch.from_numpy(np.concatenate([x.ravel() for x in deltas])).to("cuda")
+    ghost = torch.zeros(goff, dtype=torch.float64, device="cuda")
+    params = V.make_params(w["alpha"], w["kappa"], w["tol"], 100, V.MIXED, flags=V.GRAPH)
+    phis = [torch.zeros_like(d) for _ in range(steps + 1)]
+    with V.LevelsPlan(grids, nests, params) as L:
+        L.solve(d, ghost, phis[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            res = L.solve(d, ghost, phis[k + 1])
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+    log(f"levels: {ms:.2f} ms per multilevel solve ({len(grids)} grids, {off} cells), "
+        f"max rms {max(r['rms'] for r in res):.2e}")
+    return {"ms_per_solve": ms, "grids": len(grids), "cells": off, "max_rms": max(r["rms"] for r in res),
+            "cycles": [r["cycles"] for r in res],
+            "note": "vmg_levels_solve on a plan created beforehand, from phi = 0, mixed precision"}
+
+
 def cpu_baseline(delta, w, sweeps=5):
     from oracle import oracle as O
     import numpy as np
@@ -246,6 +338,8 @@ def main():
     ap.add_argument("--smooth-launches", type=int, default=50)
     ap.add_argument("--assign-launches", type=int, default=20,
                     help="timed calls of the mass assignment (0: skip it)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the total-force, truncation-error-rule and multilevel timings")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only the kernels of the HBM counter runs (under rocprofv3 --pmc)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -307,6 +401,10 @@ def main():
                        "bytes_per_launch": bpc * n3, "us_per_launch": smooth_ms * 1e3}
     if args.assign_launches > 0:
         results["mass_assign_zeldovich256"] = time_mass_assign(torch, V, stream, args.assign_launches)
+    if not args.no_extras:
+        results["total_force_zeldovich256"] = time_total_force(torch, V, delta, w, stream, 20)
+        results["tau_rule_zeldovich256"] = time_tau_rule(torch, V, delta, w, stream, 3)
+        results["levels_zeldovich256"] = time_levels(torch, V, delta_np, w, 2)
     head = "mixed"
     results["mixed_speedup_vs_fp64"] = results["fp64"]["time_to_tol_ms"] / results["mixed"]["time_to_tol_ms"]
     roof = dict(roofs[head])

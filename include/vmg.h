@@ -201,9 +201,23 @@ typedef struct {
  * to the domain grid only); out: host array of n_grids results.  Creates and
  * destroys its plans (allocates).  Errors: VMG_EINVAL (nesting or arguments),
  * otherwise the first failing level's status (VMG_ENOCONV, VMG_ENONFINITE,
- * ...; deeper levels are then not solved), VMG_EHIP. */
+ * ...; deeper levels are then not solved), VMG_EHIP.  Equivalent to
+ * vmg_levels_create + vmg_levels_solve + vmg_levels_destroy. */
 vmg_status vmg_solve_levels(const vmg_grid *grids, const vmg_nest *nest, int32_t n_grids, const vmg_params *p,
                             const double *delta, double *ghost, double *phi, vmg_result *out, hipStream_t stream);
+
+/* The multilevel solve as a reusable plan: vmg_levels_create validates the
+ * tree as vmg_solve_levels does and allocates one plan per depth (the domain
+ * grid's, then one batched plan per refinement depth) on `stream`;
+ * vmg_levels_solve runs the level-by-level solve on those plans without
+ * allocating (same arrays, results and errors as vmg_solve_levels; returns
+ * after the stream has finished); vmg_levels_destroy frees the plans (NULL is
+ * ignored).  A levels plan must not be used from two threads at once. */
+typedef struct vmg_levels vmg_levels;
+vmg_status vmg_levels_create(vmg_levels **levels, const vmg_grid *grids, const vmg_nest *nest, int32_t n_grids,
+                             const vmg_params *p, hipStream_t stream);
+vmg_status vmg_levels_solve(vmg_levels *levels, const double *delta, double *ghost, double *phi, vmg_result *out);
+void vmg_levels_destroy(vmg_levels *levels);
 
 /* Initial guess on refinements (Sec. III.C, IV.D: a refinement starts from the
  * solution of the coarser level, interpolated): the same trilinear
@@ -225,7 +239,8 @@ vmg_status vmg_fill_interior(const double *parent, const int32_t np[3], double p
  * brane-bending mode.  Writes psi = phi_newton + phi/2 (may be NULL) and the
  * acceleration -grad Psi into force: 3 N values, the x, y and z components one
  * after another.  Enqueued on `stream`; the caller owns every buffer.
- * Errors: VMG_EINVAL (null input or force, n < 1, h not finite and > 0), VMG_EHIP. */
+ * Errors: VMG_EINVAL (null input or force, n < 1, n[1] n[2] >= 2^31, h not
+ * finite and > 0), VMG_EHIP. */
 vmg_status vmg_total_force(const double *phi_newton, const double *phi, const int32_t n[3], double h,
                            double *psi, double *force, hipStream_t stream);
 

@@ -642,18 +642,22 @@ vmg_status vmg_solve_periodic(const double* delta, int32_t n, double alpha, doub
     return st;
 }
 
-// Multilevel solve: the domain grid, then every depth of the refinement tree in
-// one batched plan, each refinement starting from its parent's solution
-// interpolated to its ghost shell and interior.
-vmg_status vmg_solve_levels(const vmg_grid* grids, const vmg_nest* nest, int32_t n_grids, const vmg_params* p,
-                            const double* delta, double* ghost, double* phi, vmg_result* out, hipStream_t stream) {
-    g_err.clear();
-    if (!grids || !nest || !p || !delta || !phi || !out || n_grids < 1) return fail(VMG_EINVAL, "null argument");
+// Multilevel plans: the domain grid, then every depth of the refinement tree
+// as one batched plan; a solve fills each refinement's ghost shell and initial
+// guess from its parent's solution before solving that depth.
+struct vmg_levels {
+    std::vector<vmg_grid> grids;
+    std::vector<vmg_nest> nest;
+    std::vector<std::vector<int>> members;     // grid indices per depth
+    std::vector<vmg_plan*> plans;              // one per depth
+    hipStream_t stream = nullptr;
+};
+
+static vmg_status levels_check(const vmg_grid* grids, const vmg_nest* nest, int32_t n_grids, std::vector<int>& depth) {
+    if (!grids || !nest || n_grids < 1) return fail(VMG_EINVAL, "null argument");
     if (nest[0].parent != -1 || grids[0].bc != VMG_PERIODIC)
         return fail(VMG_EINVAL, "grid 0 must be the periodic domain grid (parent -1)");
-    if (n_grids > 1 && !ghost) return fail(VMG_EINVAL, "refinements need a ghost array");
-    std::vector<int> depth(n_grids, 0);
-    int max_depth = 0;
+    depth.assign(n_grids, 0);
     for (int i = 1; i < n_grids; ++i) {
         const int pa = nest[i].parent;
         if (pa < 0 || pa >= i)
@@ -672,41 +676,89 @@ vmg_status vmg_solve_levels(const vmg_grid* grids, const vmg_nest* nest, int32_t
                                             ": origin outside the parent (a refinement parent needs one cell of margin)");
         }
         depth[i] = depth[pa] + 1;
-        max_depth = std::max(max_depth, depth[i]);
     }
+    return VMG_OK;
+}
+
+vmg_status vmg_levels_create(vmg_levels** out, const vmg_grid* grids, const vmg_nest* nest, int32_t n_grids,
+                             const vmg_params* p, hipStream_t stream) {
+    g_err.clear();
+    if (!out || !p) return fail(VMG_EINVAL, "null argument");
+    *out = nullptr;
+    std::vector<int> depth;
+    vmg_status st = levels_check(grids, nest, n_grids, depth);
+    if (st != VMG_OK) return st;
+    vmg_levels* L = new (std::nothrow) vmg_levels();
+    if (!L) return fail(VMG_ENOMEM, "host allocation failed");
+    L->grids.assign(grids, grids + n_grids);
+    L->nest.assign(nest, nest + n_grids);
+    L->stream = stream;
+    const int max_depth = *std::max_element(depth.begin(), depth.end());
+    L->members.resize(max_depth + 1);
+    for (int i = 0; i < n_grids; ++i) L->members[depth[i]].push_back(i);
     vmg_params pr = *p;
     for (int d = 0; d <= max_depth; ++d) {
+        if (d > 0) pr.tau_factor = 0.0;            // the truncation-error rule applies to the domain grid only
         std::vector<vmg_grid> sub;
-        std::vector<int> idx;
-        for (int i = 0; i < n_grids; ++i)
-            if (depth[i] == d) {
-                sub.push_back(grids[i]);
-                idx.push_back(i);
-            }
-        if (d > 0) {
-            pr.tau_factor = 0.0;                  // the truncation-error rule applies to the domain grid only
-            for (int i : idx) {
-                const vmg_grid& g = grids[i];
-                const vmg_grid& P = grids[nest[i].parent];
-                const int* o = nest[i].origin;
-                CKH(launch_ghost_fill(phi + P.offset, P.n[0], P.n[1], P.n[2], P.h, g.n[0], g.n[1], g.n[2], g.h, o[0],
-                                      o[1], o[2], ghost + g.ghost_offset, stream));
-                CKH(launch_interior_fill(phi + P.offset, P.n[0], P.n[1], P.n[2], P.h, g.n[0], g.n[1], g.n[2], g.h,
-                                         o[0], o[1], o[2], phi + g.offset, stream));
-            }
-        }
+        for (int i : L->members[d]) sub.push_back(grids[i]);
         vmg_plan* plan = nullptr;
-        vmg_status st = vmg_plan_create(&plan, sub.data(), (int32_t)sub.size(), &pr, stream);
-        if (st != VMG_OK) return st;
-        std::vector<vmg_result> res(sub.size());
-        st = vmg_solve(plan, delta, d > 0 ? ghost : nullptr, nullptr, phi, res.data());
-        const std::string msg = g_err;
-        vmg_plan_destroy(plan);
-        g_err = msg;
+        st = vmg_plan_create(&plan, sub.data(), (int32_t)sub.size(), &pr, stream);
+        if (st != VMG_OK) {
+            const std::string msg = g_err;
+            vmg_levels_destroy(L);
+            g_err = msg;
+            return st;
+        }
+        L->plans.push_back(plan);
+    }
+    *out = L;
+    return VMG_OK;
+}
+
+vmg_status vmg_levels_solve(vmg_levels* L, const double* delta, double* ghost, double* phi, vmg_result* out) {
+    g_err.clear();
+    if (!L || !delta || !phi || !out) return fail(VMG_EINVAL, "null argument");
+    if (L->grids.size() > 1 && !ghost) return fail(VMG_EINVAL, "refinements need a ghost array");
+    for (size_t d = 0; d < L->plans.size(); ++d) {
+        const std::vector<int>& idx = L->members[d];
+        if (d > 0)
+            for (int i : idx) {
+                const vmg_grid& g = L->grids[i];
+                const vmg_grid& P = L->grids[L->nest[i].parent];
+                const int* o = L->nest[i].origin;
+                CKH(launch_ghost_fill(phi + P.offset, P.n[0], P.n[1], P.n[2], P.h, g.n[0], g.n[1], g.n[2], g.h, o[0],
+                                      o[1], o[2], ghost + g.ghost_offset, L->stream));
+                CKH(launch_interior_fill(phi + P.offset, P.n[0], P.n[1], P.n[2], P.h, g.n[0], g.n[1], g.n[2], g.h,
+                                         o[0], o[1], o[2], phi + g.offset, L->stream));
+            }
+        std::vector<vmg_result> res(idx.size());
+        const vmg_status st = vmg_solve(L->plans[d], delta, d > 0 ? ghost : nullptr, nullptr, phi, res.data());
         for (size_t k = 0; k < idx.size(); ++k) out[idx[k]] = res[k];
         if (st != VMG_OK) return st;
     }
     return VMG_OK;
+}
+
+void vmg_levels_destroy(vmg_levels* L) {
+    if (!L) return;
+    for (vmg_plan* p : L->plans) vmg_plan_destroy(p);
+    delete L;
+}
+
+vmg_status vmg_solve_levels(const vmg_grid* grids, const vmg_nest* nest, int32_t n_grids, const vmg_params* p,
+                            const double* delta, double* ghost, double* phi, vmg_result* out, hipStream_t stream) {
+    g_err.clear();
+    if (!delta || !phi || !out) return fail(VMG_EINVAL, "null argument");
+    if (n_grids > 1 && !ghost) return fail(VMG_EINVAL, "refinements need a ghost array");
+    vmg_levels* L = nullptr;
+    vmg_status st = vmg_levels_create(&L, grids, nest, n_grids, p, stream);
+    if (st != VMG_OK) return st;
+    for (int32_t i = 0; i < n_grids; ++i) std::memset(&out[i], 0, sizeof(vmg_result));
+    st = vmg_levels_solve(L, delta, ghost, phi, out);
+    const std::string msg = g_err;
+    vmg_levels_destroy(L);
+    g_err = msg;
+    return st;
 }
 
 vmg_status vmg_residual(vmg_plan* plan, int32_t gi, const double* delta, const double* ghost,
@@ -787,8 +839,8 @@ vmg_status vmg_total_force(const double* phi_newton, const double* phi, const in
                            double* force, hipStream_t stream) {
     g_err.clear();
     if (!phi_newton || !phi || !n || !force) return fail(VMG_EINVAL, "null argument");
-    if (n[0] < 1 || n[1] < 1 || n[2] < 1 || !(h > 0.0) || !std::isfinite(h))
-        return fail(VMG_EINVAL, "total force needs n >= 1 per axis and a finite h > 0");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1 || (int64_t)n[1] * n[2] > INT32_MAX || !(h > 0.0) || !std::isfinite(h))
+        return fail(VMG_EINVAL, "total force needs n >= 1 per axis, n[1] n[2] < 2^31 and a finite h > 0");
     CKH(launch_total_force(n[0], n[1], n[2], h, phi_newton, phi, psi, force, stream));
     return VMG_OK;
 }

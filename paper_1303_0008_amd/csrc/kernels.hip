@@ -1210,36 +1210,33 @@ hipError_t launch_ghost_fill(const double* parent, int np0, int np1, int np2, do
 }
 
 // Total potential Psi = phi_N + phi/2 and acceleration -grad Psi (periodic
-// central differences), one cell per thread; Psi of the neighbours is formed
-// from the two inputs on the fly, so psi is only written (optional).
+// central differences).  One block per row, threads along x.  Psi of the
+// neighbours is formed from the two inputs on the fly, so psi is only written
+// (optional).
 __global__ void __launch_bounds__(NT) k_total_force(int n0, int n1, int n2, double inv_2h,
                                                    const double* __restrict__ phin,
                                                    const double* __restrict__ phi, double* __restrict__ psi,
                                                    double* __restrict__ g) {
-    const int64_t N = (int64_t)n0 * n1 * n2;
-    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < N; e += (int64_t)gridDim.x * NT) {
-        const int i = (int)(e % n0);
-        const int64_t r = e / n0;
-        const int j = (int)(r % n1), k = (int)(r / n1);
-        const int64_t row = e - i, pl = (int64_t)n0 * n1;
-        auto P = [&](int64_t q) { return phin[q] + 0.5 * phi[q]; };
+    const int j = (int)(blockIdx.x % (unsigned)n1), k = (int)(blockIdx.x / (unsigned)n1);
+    const int64_t N = (int64_t)n0 * n1 * n2, pl = (int64_t)n0 * n1;
+    const int64_t row = (int64_t)k * pl + (int64_t)j * n0;
+    const int64_t yp = (j == n1 - 1 ? -(int64_t)(n1 - 1) * n0 : n0), ym = (j == 0 ? (int64_t)(n1 - 1) * n0 : -(int64_t)n0);
+    const int64_t zp = (k == n2 - 1 ? -(int64_t)(n2 - 1) * pl : pl), zm = (k == 0 ? (int64_t)(n2 - 1) * pl : -pl);
+    auto P = [&](int64_t q) { return phin[q] + 0.5 * phi[q]; };
+    for (int i = threadIdx.x; i < n0; i += NT) {
+        const int64_t e = row + i;
         const int64_t xp = row + (i == n0 - 1 ? 0 : i + 1), xm = row + (i == 0 ? n0 - 1 : i - 1);
-        const int64_t yp = e + (j == n1 - 1 ? -(int64_t)(n1 - 1) * n0 : n0);
-        const int64_t ym = e + (j == 0 ? (int64_t)(n1 - 1) * n0 : -(int64_t)n0);
-        const int64_t zp = e + (k == n2 - 1 ? -(int64_t)(n2 - 1) * pl : pl);
-        const int64_t zm = e + (k == 0 ? (int64_t)(n2 - 1) * pl : -pl);
         if (psi) psi[e] = P(e);
         g[e] = -(P(xp) - P(xm)) * inv_2h;
-        g[N + e] = -(P(yp) - P(ym)) * inv_2h;
-        g[2 * N + e] = -(P(zp) - P(zm)) * inv_2h;
+        g[N + e] = -(P(e + yp) - P(e + ym)) * inv_2h;
+        g[2 * N + e] = -(P(e + zp) - P(e + zm)) * inv_2h;
     }
 }
 
 hipError_t launch_total_force(int n0, int n1, int n2, double h, const double* phin, const double* phi, double* psi,
                               double* g, hipStream_t s) {
-    const int64_t N = (int64_t)n0 * n1 * n2;
-    hipLaunchKernelGGL(k_total_force, dim3(grid_for(N)), dim3(NT), 0, s, n0, n1, n2, 1.0 / (2.0 * h), phin, phi,
-                       psi, g);
+    hipLaunchKernelGGL(k_total_force, dim3((unsigned)((int64_t)n1 * n2)), dim3(NT), 0, s, n0, n1, n2,
+                       1.0 / (2.0 * h), phin, phi, psi, g);
     return hipGetLastError();
 }
 

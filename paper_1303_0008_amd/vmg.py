@@ -61,7 +61,8 @@ class Nest(ctypes.Structure):
 EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
            "vmg_solve_periodic", "vmg_residual", "vmg_fill_ghosts", "vmg_ghost_count",
            "vmg_smooth", "vmg_plan_stats", "vmg_plan_config", "vmg_fill_interior", "vmg_total_force",
-           "vmg_mass_assign", "vmg_mass_assign_workspace", "vmg_solve_levels"]
+           "vmg_mass_assign", "vmg_mass_assign_workspace", "vmg_solve_levels", "vmg_levels_create",
+           "vmg_levels_solve", "vmg_levels_destroy"]
 
 _lib = None
 
@@ -96,12 +97,16 @@ def load():
                                   vp]
     L.vmg_mass_assign_workspace.argtypes = [ctypes.c_int64, P(ctypes.c_int32)]
     L.vmg_solve_levels.argtypes = [P(Grid), P(Nest), ctypes.c_int32, P(Params), vp, vp, vp, P(Result), vp]
+    L.vmg_levels_create.argtypes = [P(vp), P(Grid), P(Nest), ctypes.c_int32, P(Params), vp]
+    L.vmg_levels_solve.argtypes = [vp, vp, vp, vp, P(Result)]
+    L.vmg_levels_destroy.argtypes = [vp]
+    L.vmg_levels_destroy.restype = None
     L.vmg_mass_assign_workspace.restype = ctypes.c_int64
     L.vmg_plan_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
     i32p = P(ctypes.c_int32)
     L.vmg_plan_config.argtypes = [vp, i32p, i32p, i32p, i32p, i32p]
     for name in EXPORTS:
-        if name not in ("vmg_last_error", "vmg_ghost_count", "vmg_mass_assign_workspace"):
+        if name not in ("vmg_last_error", "vmg_ghost_count", "vmg_mass_assign_workspace", "vmg_levels_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -237,6 +242,42 @@ def solve_levels(grids, nests, params, delta, ghost, phi, stream=None, allow_noc
     for r in out:
         r["status"] = st
     return out
+
+
+class LevelsPlan:
+    """Owning wrapper of a vmg_levels plan (create once, solve many times)."""
+
+    def __init__(self, grids, nests, params, stream=None):
+        self.n = len(grids)
+        self.handle = ctypes.c_void_p()
+        _check(load().vmg_levels_create(ctypes.byref(self.handle), (Grid * self.n)(*grids),
+                                        (Nest * self.n)(*nests), self.n, ctypes.byref(params), _stream(stream)))
+
+    def solve(self, delta, ghost, phi, allow_noconv=False):
+        res = (Result * self.n)()
+        st = load().vmg_levels_solve(self.handle, _ptr(delta), _ptr(ghost), _ptr(phi), res)
+        _check(st, allow=(VMG_ENOCONV,) if allow_noconv else ())
+        out = [r.as_dict() for r in res]
+        for r in out:
+            r["status"] = st
+        return out
+
+    def close(self):
+        if self.handle:
+            load().vmg_levels_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fill_interior(parent, parent_h, grids, origins, phi, stream=None):
