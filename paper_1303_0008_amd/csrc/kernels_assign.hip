@@ -277,6 +277,8 @@ __global__ void __launch_bounds__(ANT) k_bin_assign(AGrid g, const double* __res
     for (int e = threadIdx.x; e < REGN; e += ANT) acc[e] = 0ull;
     __syncthreads();
     const uint32_t lo = start[(size_t)key * SUB], hi = start[(size_t)(key + 1) * SUB];
+    const int lane = threadIdx.x & 63;
+    const int rx = lane % M, ry = (lane >> 4) % M;
     // the next particle's index and position are loaded before this one's
     // LDS atomics are issued
     uint32_t t = lo + threadIdx.x;
@@ -299,15 +301,33 @@ __global__ void __launch_bounds__(ANT) k_bin_assign(AGrid g, const double* __res
         const int l0 = axis_local<M>(x, g.n0, o0, wx);
         const int l1 = axis_local<M>(y, g.n1, o1, wy);
         const int l2 = axis_local<M>(z, g.n2, o2, wz);
+        // rotate the x and y stencil order by lane so that neighbouring lanes
+        // (often the same nearest cell) add to different cells in one instruction
+        double wxr[M], wyr[M];
+        int oxr[M], oyr[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const int sx = c + rx >= M ? c + rx - M : c + rx;
+            const int sy = c + ry >= M ? c + ry - M : c + ry;
+            wxr[c] = wx[0];
+            wyr[c] = wy[0];
+#pragma unroll
+            for (int q = 1; q < M; ++q) {
+                wxr[c] = sx == q ? wx[q] : wxr[c];
+                wyr[c] = sy == q ? wy[q] : wyr[c];
+            }
+            oxr[c] = sx;
+            oyr[c] = sy;
+        }
 #pragma unroll
         for (int a = 0; a < M; ++a) {
 #pragma unroll
             for (int b = 0; b < M; ++b) {
-                const double wyz = wz[a] * wy[b] * FIX_ONE;
-                const int r = reg_index(l0, l1 + b, l2 + a);
+                const double wyz = wz[a] * wyr[b] * FIX_ONE;
+                const int r = reg_index(l0, l1 + oyr[b], l2 + a);
 #pragma unroll
                 for (int c = 0; c < M; ++c)
-                    atomicAdd(&acc[r + c], fix_round(wx[c], wyz));
+                    atomicAdd(&acc[r + oxr[c]], fix_round(wxr[c], wyz));
             }
         }
         x = xn;
