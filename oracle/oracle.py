@@ -57,6 +57,8 @@ def lib():
         L.or_fill_interior.argtypes = [ip, ctypes.c_double, dp, ip, ctypes.c_double, ip, dp]
         L.or_total_force.argtypes = [ip, ctypes.c_double, dp, dp, dp, dp]
         L.or_mass_assign.argtypes = [dp, ctypes.c_long, ip, ctypes.c_int, dp]
+        L.or_mass_assign_region.argtypes = [dp, ctypes.c_long, ip, ctypes.c_double, dp, ctypes.c_double,
+                                             ctypes.c_int, dp]
         L.or_truncation_error.argtypes = [ip, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                           dp, dp, dp, dp]
         L.or_ghost_count.argtypes = [ip]
@@ -235,5 +237,20 @@ def mass_assign(pos, n, scheme="tsc"):
     nn = (n,) * 3 if np.isscalar(n) else tuple(n)
     out = np.zeros(nn[::-1])
     rc = lib().or_mass_assign(_dp(pos), pos.shape[0], _ivec(nn), {"cic": 1, "tsc": 2}[scheme], _dp(out))
+    assert rc == 0
+    return out
+
+
+def mass_assign_region(pos, n, h, corner, mean_count, scheme="tsc"):
+    """Density contrast on a refinement region of n cells (int or (n0, n1, n2))
+    of size h with cell (0,0,0) corner at ``corner`` (box units, not periodic):
+    mass per cell / mean_count - 1, mean_count the box's mean particles per cell
+    of this size; shaped (n2, n1, n0)."""
+    pos = _f64(pos)
+    nn = (n,) * 3 if np.isscalar(n) else tuple(n)
+    out = np.zeros(nn[::-1])
+    c = np.asarray(corner, dtype=np.float64)
+    rc = lib().or_mass_assign_region(_dp(pos), pos.shape[0], _ivec(nn), float(h), _dp(c), float(mean_count),
+                                     {"cic": 1, "tsc": 2}[scheme], _dp(out))
     assert rc == 0
     return out

@@ -812,3 +812,58 @@ int or_mass_assign(const double *pos, long np, const int n[3], int scheme, doubl
     for (long e = 0; e < N; ++e) delta[e] = delta[e] * scale - 1.0;
     return 0;
 }
+
+/* The same assignment onto a refinement region: n[0] x n[1] x n[2] cells of
+ * size h whose cell (0,0,0) corner sits at corner[] (box units), not periodic.
+ * Along an axis a particle's offset from the corner is taken modulo 1 into
+ * [0, 1) and moved to (offset - 1) when it lies more than n h + 2h past the
+ * corner, so a particle just below the corner counts there; with n h <= 1 - 4h
+ * at most one periodic image of a particle reaches the region.  In cell units
+ * u = offset / h the weights are those of or_mass_assign; contributions to
+ * cells outside the region are dropped.  delta = mass / mean_count - 1, with
+ * mean_count the box's mean number of particles per cell of this size.
+ * Returns 0, or -1 for bad arguments. */
+int or_mass_assign_region(const double *pos, long np, const int n[3], double h, const double corner[3],
+                          double mean_count, int scheme, double *delta) {
+    if ((scheme != 1 && scheme != 2) || np < 0 || !(h > 0.0) || !(mean_count > 0.0)) return -1;
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] * h > 1.0 - 4.0 * h) return -1;
+    const int m = scheme == 1 ? 2 : 3;
+    const long N = (long)n[0] * n[1] * n[2];
+    for (long e = 0; e < N; ++e) delta[e] = 0.0;
+    for (long p = 0; p < np; ++p) {
+        int c[3][3];
+        double w[3][3];
+        if (!isfinite(pos[3 * p]) || !isfinite(pos[3 * p + 1]) || !isfinite(pos[3 * p + 2])) continue;
+        for (int a = 0; a < 3; ++a) {
+            double d = pos[3 * p + a] - corner[a];
+            d -= floor(d);
+            if (d > n[a] * h + 2.0 * h) d -= 1.0;
+            const double u = d / h;
+            if (scheme == 1) {
+                const double f = floor(u - 0.5);
+                const double t = (u - 0.5) - f;
+                c[a][0] = (int)f;
+                c[a][1] = (int)f + 1;
+                w[a][0] = 1.0 - t;
+                w[a][1] = t;
+            } else {
+                const double f = floor(u);
+                const double dd = u - (f + 0.5);
+                for (int q = 0; q < 3; ++q) c[a][q] = (int)f + q - 1;
+                w[a][0] = 0.5 * (0.5 - dd) * (0.5 - dd);
+                w[a][1] = 0.75 - dd * dd;
+                w[a][2] = 0.5 * (0.5 + dd) * (0.5 + dd);
+            }
+        }
+        for (int qz = 0; qz < m; ++qz)
+            for (int qy = 0; qy < m; ++qy)
+                for (int qx = 0; qx < m; ++qx) {
+                    const int i = c[0][qx], j = c[1][qy], k = c[2][qz];
+                    if (i < 0 || i >= n[0] || j < 0 || j >= n[1] || k < 0 || k >= n[2]) continue;
+                    delta[((long)k * n[1] + j) * n[0] + i] += w[0][qx] * w[1][qy] * w[2][qz];
+                }
+    }
+    for (long e = 0; e < N; ++e) delta[e] = delta[e] / mean_count - 1.0;
+    return 0;
+}

@@ -794,3 +794,42 @@ def test_levels_tophat_refinement(oracle_mod):
     dom = phis[0][8:24, 8:24, 8:24]
     diff = avg - dom
     assert np.abs(diff - diff.mean()).max() / (dom.max() - dom.min()) < 0.05
+
+
+@pytest.mark.parametrize("scheme", ["cic", "tsc"])
+def test_mass_assign_region_is_the_box_deposit_cut_out(oracle_mod, scheme):
+    """A region whose cells are cells of a periodic box grid (same size, corner on
+    a cell corner, also wrapping across the box edge) receives exactly what the
+    periodic box deposit puts in those cells: every particle whose stencil
+    reaches the region, from the right periodic image, with the box's mean
+    density.  Checked at the box resolution and at twice it."""
+    pos = I.zeldovich_particles(32, I.BASE_SEED + 61, 1.2)
+    npart = pos.shape[0]
+    for nb in (32, 64):
+        full = oracle_mod.mass_assign(pos, nb, scheme)
+        for n, o in (((10, 8, 12), (5, 20, 30)), ((6, 6, 6), (0, 13, 27)), ((9, 11, 7), (nb - 4, 1, nb - 2))):
+            corner = tuple(v / nb for v in o)
+            reg = oracle_mod.mass_assign_region(pos, n, 1.0 / nb, corner, npart / nb ** 3, scheme)
+            idx = np.ix_([(o[2] + k) % nb for k in range(n[2])], [(o[1] + j) % nb for j in range(n[1])],
+                         [(o[0] + i) % nb for i in range(n[0])])
+            assert np.abs(reg - full[idx]).max() <= 1e-13, (nb, n, o)
+
+
+def test_mass_assign_region_single_particles(oracle_mod):
+    """One particle deep inside a region puts all its mass there; one whose
+    nearest cell is the cell just outside the low face (below the corner, so
+    it arrives through the periodic image) puts in only its stencil's inner
+    slice: (1/2 + d)^2 / 2 of its mass along that axis (TSC), nothing for CIC
+    once it is more than half a cell out."""
+    n, h, corner = (8, 8, 8), 1.0 / 64, (0.0, 0.25, 0.5)
+    inside = np.array([[corner[0] + 4.3 * h, corner[1] + 3.6 * h, corner[2] + 5.1 * h]])
+    for scheme in ("cic", "tsc"):
+        d = oracle_mod.mass_assign_region(inside, n, h, corner, 1.0, scheme)
+        assert abs((d + 1.0).sum() - 1.0) <= 1e-14
+    out = np.array([[1.0 - 0.3 * h, corner[1] + 4.5 * h, corner[2] + 4.5 * h]])   # u_x = -0.3: nearest cell -1
+    d = oracle_mod.mass_assign_region(out, n, h, corner, 1.0, "tsc")
+    dd = -0.3 - (-0.5)
+    assert abs((d + 1.0).sum() - 0.5 * (0.5 + dd) ** 2) <= 1e-14
+    assert np.abs((d + 1.0)[:, :, 1:]).max() == 0.0
+    far = np.array([[1.0 - 0.6 * h, corner[1] + 4.5 * h, corner[2] + 4.5 * h]])
+    assert np.abs(oracle_mod.mass_assign_region(far, n, h, corner, 1.0, "cic") + 1.0).max() == 0.0
