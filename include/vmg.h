@@ -276,6 +276,26 @@ vmg_status vmg_total_force(const double *phi_newton, const double *phi, const in
 vmg_status vmg_mass_assign(const double *pos, int64_t n_particles, const int32_t n[3], int32_t scheme,
                            void *workspace, int64_t workspace_bytes, double *delta, hipStream_t stream);
 
+/* Mass assignment onto a refinement (Sec. VI: the mesh density comes from the
+ * particles on every level): the region of n[0] x n[1] x n[2] cells of size h
+ * whose cell (0,0,0) corner sits at corner[] (box units), not periodic.  Along
+ * each axis a particle's offset from the corner is taken modulo 1 and moved
+ * below the corner (offset - 1) when it lies more than n h + 2h past it; the
+ * region must leave at least 4 of its cells of the unit box uncovered per axis
+ * (n h <= 1 - 4h), so at most one periodic image of a particle reaches it.
+ * With u = offset / h the weights are those of vmg_mass_assign; contributions
+ * to cells outside the region are dropped.  Writes delta = mass / mean_count
+ * - 1 (x fastest), mean_count being the box's mean number of particles per
+ * cell of this size (N_box h^3 for N_box particles in the unit box); the
+ * particles passed may be any subset that includes every particle within two
+ * cells of the region.  Arithmetic, workspace (vmg_mass_assign_workspace with
+ * this n), reproducibility and streams as vmg_mass_assign.  Errors:
+ * VMG_EINVAL (as vmg_mass_assign, plus h, mean_count or corner not finite and
+ * positive, a region too large for the box), VMG_EHIP. */
+vmg_status vmg_mass_assign_region(const double *pos, int64_t n_particles, const int32_t n[3], double h,
+                                  const double corner[3], double mean_count, int32_t scheme, void *workspace,
+                                  int64_t workspace_bytes, double *delta, hipStream_t stream);
+
 /* Workspace bytes vmg_mass_assign needs (about 8 bytes per particle plus 12
  * per grid cell), or -1 for arguments vmg_mass_assign rejects. */
 int64_t vmg_mass_assign_workspace(int64_t n_particles, const int32_t n[3]);

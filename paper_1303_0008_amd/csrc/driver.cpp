@@ -867,7 +867,33 @@ vmg_status vmg_mass_assign(const double* pos, int64_t n_particles, const int32_t
     if (workspace_bytes < mass_assign_workspace(n_particles, n[0], n[1], n[2]) ||
         reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
         return fail(VMG_EINVAL, "mass assignment workspace too small or not 256-byte aligned");
-    CKH(launch_mass_assign(pos, n_particles, n[0], n[1], n[2], scheme, workspace, delta, stream));
+    const double mean_count = (double)n_particles / ((double)n[0] * n[1] * n[2]);
+    CKH(launch_mass_assign(pos, n_particles, n[0], n[1], n[2], scheme, true, 0.0, nullptr, mean_count, workspace,
+                           delta, stream));
+    return VMG_OK;
+}
+
+vmg_status vmg_mass_assign_region(const double* pos, int64_t n_particles, const int32_t n[3], double h,
+                                  const double corner[3], double mean_count, int32_t scheme, void* workspace,
+                                  int64_t workspace_bytes, double* delta, hipStream_t stream) {
+    g_err.clear();
+    if (!pos || !n || !corner || !delta || !workspace) return fail(VMG_EINVAL, "null argument");
+    if (n_particles < 1 || n_particles > INT32_MAX)
+        return fail(VMG_EINVAL, "mass assignment needs 1 <= n_particles <= 2^31 - 1");
+    if (!assign_args_ok(n_particles, n)) return fail(VMG_EINVAL, "mass assignment needs n >= 1 per axis");
+    if (!(h > 0.0) || !std::isfinite(h) || !(mean_count > 0.0) || !std::isfinite(mean_count))
+        return fail(VMG_EINVAL, "region assignment needs a finite h > 0 and mean_count > 0");
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(corner[a])) return fail(VMG_EINVAL, "region corner must be finite");
+        if (!(n[a] * h <= 1.0 - 4.0 * h))
+            return fail(VMG_EINVAL, "a region must leave at least 4 of its cells of the box uncovered per axis");
+    }
+    if (scheme != VMG_ASSIGN_CIC && scheme != VMG_ASSIGN_TSC) return fail(VMG_EINVAL, "unknown assignment scheme");
+    if (workspace_bytes < mass_assign_workspace(n_particles, n[0], n[1], n[2]) ||
+        reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(VMG_EINVAL, "mass assignment workspace too small or not 256-byte aligned");
+    CKH(launch_mass_assign(pos, n_particles, n[0], n[1], n[2], scheme, false, h, corner, mean_count, workspace, delta,
+                           stream));
     return VMG_OK;
 }
 

@@ -40,21 +40,58 @@ constexpr uint32_t NO_KEY = 0xffffffffu;
 struct AGrid {
     int n0, n1, n2;          // cells
     int b0, b1, b2;          // bricks per axis
+    // refinement region (not periodic): cell size, corner of cell (0,0,0) and
+    // n h + 2h per axis (offsets beyond it belong to the image below the corner)
+    double h, cr[3], far[3];
 };
 
-// u = position in cells along an axis, in [0, n]; f = floor(u) unwrapped; the
-// nearest cell is f mod n.
+// Periodic box: u = position in cells along an axis, in [0, n]; f = floor(u)
+// unwrapped; the nearest cell is f mod n.
 __device__ __forceinline__ double cells_of(double x, int n) { return (x - floor(x)) * (double)n; }
+
+// Region: the offset from the corner taken modulo 1, moved below the corner
+// when it lies beyond the region's far side plus two cells; in cells.
+__device__ __forceinline__ double region_u(double x, double corner, double far, double h) {
+    double d = x - corner;
+    d -= floor(d);
+    if (d > far) d -= 1.0;
+    return d / h;
+}
+
+template <bool PER>
+__device__ __forceinline__ double axis_u(const AGrid& g, int a, double x, int n) {
+    if constexpr (PER)
+        return cells_of(x, n);
+    else
+        return region_u(x, g.cr[a], g.far[a], g.h);
+}
 
 __device__ __forceinline__ bool finite3(double x, double y, double z) {
     return isfinite(x) && isfinite(y) && isfinite(z);
 }
 
+// Brick of the particle's nearest cell.  Region: a particle whose nearest cell
+// is more than one cell outside reaches no cell of the region (NO_KEY); one
+// cell outside, it goes to the brick on that face.
+template <bool PER>
 __device__ __forceinline__ uint32_t brick_key(const AGrid& g, double x, double y, double z) {
-    int c0 = (int)floor(cells_of(x, g.n0)), c1 = (int)floor(cells_of(y, g.n1)), c2 = (int)floor(cells_of(z, g.n2));
-    c0 -= c0 >= g.n0 ? g.n0 : 0;
-    c1 -= c1 >= g.n1 ? g.n1 : 0;
-    c2 -= c2 >= g.n2 ? g.n2 : 0;
+    const double f0 = floor(axis_u<PER>(g, 0, x, g.n0)), f1 = floor(axis_u<PER>(g, 1, y, g.n1)),
+                 f2 = floor(axis_u<PER>(g, 2, z, g.n2));
+    int c0, c1, c2;
+    if constexpr (PER) {
+        c0 = (int)f0;
+        c1 = (int)f1;
+        c2 = (int)f2;
+        c0 -= c0 >= g.n0 ? g.n0 : 0;
+        c1 -= c1 >= g.n1 ? g.n1 : 0;
+        c2 -= c2 >= g.n2 ? g.n2 : 0;
+    } else {
+        // compared as doubles: far from a small region u can exceed the int range
+        if (!(f0 >= -1.0 && f0 <= g.n0 && f1 >= -1.0 && f1 <= g.n1 && f2 >= -1.0 && f2 <= g.n2)) return NO_KEY;
+        c0 = min(max((int)f0, 0), g.n0 - 1);
+        c1 = min(max((int)f1, 0), g.n1 - 1);
+        c2 = min(max((int)f2, 0), g.n2 - 1);
+    }
     return ((uint32_t)(c2 / BRICK) * g.b1 + (uint32_t)(c1 / BRICK)) * g.b0 + (uint32_t)(c0 / BRICK);
 }
 
@@ -84,7 +121,7 @@ static_assert(TAB == 1 << 12, "the hash keeps the top 12 bits of the product");
 // global atomics of unordered particles over SUB addresses per brick.
 // Bricks are found in the LDS table by linear probing from a multiplicative
 // hash of the key.
-template <int MODE>
+template <int MODE, bool PER>
 __global__ void __launch_bounds__(NT) k_bin(AGrid g, const double* __restrict__ pos, int64_t np,
                                             uint32_t* __restrict__ counter, uint32_t* __restrict__ keys,
                                             uint32_t* __restrict__ idx) {
@@ -104,7 +141,7 @@ __global__ void __launch_bounds__(NT) k_bin(AGrid g, const double* __restrict__ 
             if (p >= np) continue;
             if (MODE == 0) {
                 const double x = pos[3 * p], y = pos[3 * p + 1], z = pos[3 * p + 2];
-                if (finite3(x, y, z)) key[k] = brick_key(g, x, y, z);
+                if (finite3(x, y, z)) key[k] = brick_key<PER>(g, x, y, z);
                 keys[p] = key[k];
             } else {
                 key[k] = keys[p];
@@ -239,16 +276,17 @@ __global__ void __launch_bounds__(NT) k_scan_tiles(const uint32_t* __restrict__ 
 // in [-1, BRICK].
 __device__ __forceinline__ int reg_index(int l0, int l1, int l2) { return ((l2 + 1) * REG + (l1 + 1)) * REG + (l0 + 1); }
 
+__device__ __forceinline__ bool in_reg(int l) { return (unsigned)(l + 1) <= (unsigned)(BRICK + 1); }
+
 // Per-axis local cells (brick-local coordinate of the first stencil cell) and
 // weights.  CIC: weights 1 - t, t on cells floor(u - 1/2) and the next; TSC:
 // nearest cell c, d = u - (c + 1/2), weights (1/2 - d)^2/2, 3/4 - d^2,
 // (1/2 + d)^2/2 on cells c - 1, c, c + 1.  `org` is the brick's first cell.
-template <int M>
-__device__ __forceinline__ int axis_local(double x, int n, int org, double (&w)[M]) {
-    const double u = cells_of(x, n);
+template <int M, bool PER>
+__device__ __forceinline__ int axis_local(double u, int n, int org, double (&w)[M]) {
     const double f = floor(u);
     int c = (int)f;
-    c -= c >= n ? n : 0;                                  // nearest cell, in this brick
+    if constexpr (PER) c -= c >= n ? n : 0;               // nearest cell, in this brick (region: may be -1 or n)
     if constexpr (M == 2) {
         const double g = floor(u - 0.5);                  // f - 1 or f
         const double t = (u - 0.5) - g;
@@ -265,7 +303,7 @@ __device__ __forceinline__ int axis_local(double x, int n, int org, double (&w)[
     }
 }
 
-template <int M>
+template <int M, bool PER>
 __global__ void __launch_bounds__(ANT) k_bin_assign(AGrid g, const double* __restrict__ pos,
                                                    const uint32_t* __restrict__ start,
                                                    const uint32_t* __restrict__ idx,
@@ -298,9 +336,9 @@ __global__ void __launch_bounds__(ANT) k_bin_assign(AGrid g, const double* __res
             zn = pos[3 * p + 2];
         }
         double wx[M], wy[M], wz[M];
-        const int l0 = axis_local<M>(x, g.n0, o0, wx);
-        const int l1 = axis_local<M>(y, g.n1, o1, wy);
-        const int l2 = axis_local<M>(z, g.n2, o2, wz);
+        const int l0 = axis_local<M, PER>(axis_u<PER>(g, 0, x, g.n0), g.n0, o0, wx);
+        const int l1 = axis_local<M, PER>(axis_u<PER>(g, 1, y, g.n1), g.n1, o1, wy);
+        const int l2 = axis_local<M, PER>(axis_u<PER>(g, 2, z, g.n2), g.n2, o2, wz);
         // rotate the x and y stencil order by lane so that neighbouring lanes
         // (often the same nearest cell) add to different cells in one instruction
         double wxr[M], wyr[M];
@@ -326,8 +364,12 @@ __global__ void __launch_bounds__(ANT) k_bin_assign(AGrid g, const double* __res
                 const double wyz = wz[a] * wyr[b] * FIX_ONE;
                 const int r = reg_index(l0, l1 + oyr[b], l2 + a);
 #pragma unroll
-                for (int c = 0; c < M; ++c)
+                for (int c = 0; c < M; ++c) {
+                    // region: a stencil cell beyond the LDS halo lies outside
+                    // the region; its contribution is dropped
+                    if (!PER && !(in_reg(l0 + oxr[c]) && in_reg(l1 + oyr[b]) && in_reg(l2 + a))) continue;
                     atomicAdd(&acc[r + oxr[c]], fix_round(wxr[c], wyz));
+                }
             }
         }
         x = xn;
@@ -342,18 +384,19 @@ __global__ void __launch_bounds__(ANT) k_bin_assign(AGrid g, const double* __res
 // The (brick, brick-local coordinate) pairs along one axis whose LDS region
 // entries land on cell i: the cell's own brick, and for the first (last) cell
 // of a brick the right (left) halo entry of the previous (next) brick, with
-// periodic wrap; returns how many (1 to 3).
-__device__ __forceinline__ int axis_sources(int i, int n, int nbrick, int (&b)[3], int (&l)[3]) {
+// periodic wrap (a region has no brick before its first or after its last);
+// returns how many (1 to 3).
+__device__ __forceinline__ int axis_sources(int i, int n, int nbrick, bool periodic, int (&b)[3], int (&l)[3]) {
     const int bi = i / BRICK, li = i - bi * BRICK, w = min(BRICK, n - bi * BRICK);
     int m = 0;
     b[m] = bi;
     l[m++] = li;
-    if (li == 0) {
+    if (li == 0 && (periodic || bi > 0)) {
         const int bp = bi == 0 ? nbrick - 1 : bi - 1;
         b[m] = bp;
         l[m++] = min(BRICK, n - bp * BRICK);
     }
-    if (li == w - 1) {
+    if (li == w - 1 && (periodic || bi < nbrick - 1)) {
         b[m] = bi == nbrick - 1 ? 0 : bi + 1;
         l[m++] = -1;
     }
@@ -364,16 +407,16 @@ __device__ __forceinline__ int axis_sources(int i, int n, int nbrick, int (&b)[3
 // (its own brick's entry, plus halo entries of neighbours for outer-layer
 // cells), converted to delta = q * scale - 1.  One block per row
 // (blockIdx.x = j, blockIdx.y = k), so the density is written in whole rows.
-__global__ void __launch_bounds__(NT) k_gather(AGrid g, const unsigned long long* __restrict__ stage, double scale,
-                                               double* __restrict__ d) {
+__global__ void __launch_bounds__(NT) k_gather(AGrid g, bool periodic, const unsigned long long* __restrict__ stage,
+                                               double scale, double* __restrict__ d) {
     const int j = blockIdx.x, k = blockIdx.y;
     int b1[3], l1[3], b2[3], l2[3];
-    const int m1 = axis_sources(j, g.n1, g.b1, b1, l1);
-    const int m2 = axis_sources(k, g.n2, g.b2, b2, l2);
+    const int m1 = axis_sources(j, g.n1, g.b1, periodic, b1, l1);
+    const int m2 = axis_sources(k, g.n2, g.b2, periodic, b2, l2);
     double* row = d + ((int64_t)k * g.n1 + j) * g.n0;
     for (int i = threadIdx.x; i < g.n0; i += NT) {
         int b0[3], l0[3];
-        const int m0 = axis_sources(i, g.n0, g.b0, b0, l0);
+        const int m0 = axis_sources(i, g.n0, g.b0, periodic, b0, l0);
         unsigned long long q = 0ull;
         for (int c = 0; c < m2; ++c)
             for (int b = 0; b < m1; ++b)
@@ -399,10 +442,18 @@ int64_t mass_assign_workspace(int64_t np, int n0, int n1, int n2) {
            2 * align256(np * 4) + align256(mass_assign_bricks(n0, n1, n2) * REGN * 8);
 }
 
-hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int n2, int scheme, void* work,
-                              double* delta, hipStream_t s) {
-    AGrid g{n0, n1, n2, (n0 + BRICK - 1) / BRICK, (n1 + BRICK - 1) / BRICK, (n2 + BRICK - 1) / BRICK};
-    const int64_t nb = (int64_t)g.b0 * g.b1 * g.b2, nc = nb * SUB, N = (int64_t)n0 * n1 * n2;
+hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int n2, int scheme, bool periodic,
+                              double h, const double* corner, double mean_count, void* work, double* delta,
+                              hipStream_t s) {
+    AGrid g{n0, n1, n2, (n0 + BRICK - 1) / BRICK, (n1 + BRICK - 1) / BRICK, (n2 + BRICK - 1) / BRICK, h, {0, 0, 0},
+            {0, 0, 0}};
+    const int nn[3] = {n0, n1, n2};
+    if (!periodic)
+        for (int a = 0; a < 3; ++a) {
+            g.cr[a] = corner[a];
+            g.far[a] = nn[a] * h + 2.0 * h;
+        }
+    const int64_t nb = (int64_t)g.b0 * g.b1 * g.b2, nc = nb * SUB;
     char* w = static_cast<char*>(work);
     uint32_t* count = reinterpret_cast<uint32_t*>(w);
     w += align256(nc * 4);
@@ -418,19 +469,26 @@ hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int
     uint32_t* idx = reinterpret_cast<uint32_t*>(w);
     w += align256(np * 4);
     unsigned long long* stage = reinterpret_cast<unsigned long long*>(w);
-    const double scale = FIX_INV * ((double)N / (double)np);
+    const double scale = FIX_INV / mean_count;
     const int chunks = grid_for((np + CHUNK - 1) / CHUNK * NT, 8192);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nc)), dim3(NT), 0, s, count, nc);
-    hipLaunchKernelGGL(k_bin<0>, dim3(chunks), dim3(NT), 0, s, g, pos, np, count, keys, idx);
+    if (periodic)
+        hipLaunchKernelGGL((k_bin<0, true>), dim3(chunks), dim3(NT), 0, s, g, pos, np, count, keys, idx);
+    else
+        hipLaunchKernelGGL((k_bin<0, false>), dim3(chunks), dim3(NT), 0, s, g, pos, np, count, keys, idx);
     hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)ntile), dim3(NT), 0, s, count, nc, sums);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(NT), 0, s, sums, ntile);
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntile), dim3(NT), 0, s, count, nc, sums, start, cursor);
-    hipLaunchKernelGGL(k_bin<1>, dim3(chunks), dim3(NT), 0, s, g, pos, np, cursor, keys, idx);
-    if (scheme == 1)
-        hipLaunchKernelGGL(k_bin_assign<2>, dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, stage);
+    hipLaunchKernelGGL((k_bin<1, true>), dim3(chunks), dim3(NT), 0, s, g, pos, np, cursor, keys, idx);
+    if (scheme == 1 && periodic)
+        hipLaunchKernelGGL((k_bin_assign<2, true>), dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, stage);
+    else if (scheme == 1)
+        hipLaunchKernelGGL((k_bin_assign<2, false>), dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, stage);
+    else if (periodic)
+        hipLaunchKernelGGL((k_bin_assign<3, true>), dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, stage);
     else
-        hipLaunchKernelGGL(k_bin_assign<3>, dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, stage);
-    hipLaunchKernelGGL(k_gather, dim3(n1, n2), dim3(NT), 0, s, g, stage, scale, delta);
+        hipLaunchKernelGGL((k_bin_assign<3, false>), dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, stage);
+    hipLaunchKernelGGL(k_gather, dim3(n1, n2), dim3(NT), 0, s, g, periodic, stage, scale, delta);
     return hipGetLastError();
 }
 

@@ -188,8 +188,11 @@ hipError_t launch_interior_fill(const double* parent, int np0, int np1, int np2,
 // work: mass_assign_workspace(np, n0, n1, n2) bytes, 256-byte aligned.
 int64_t mass_assign_bricks(int n0, int n1, int n2);
 int64_t mass_assign_workspace(int64_t np, int n0, int n1, int n2);
-hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int n2, int scheme, void* work,
-                              double* delta, hipStream_t s);
+// periodic: the whole box (h, corner unused); else a region of cells of size h
+// whose cell (0,0,0) corner is at corner[3].  delta = mass / mean_count - 1.
+hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int n2, int scheme, bool periodic,
+                              double h, const double* corner, double mean_count, void* work, double* delta,
+                              hipStream_t s);
 
 // ---- mixed path (kernels_mixed.hip) ---------------------------------------
 // zero_in: the input correction is identically zero (first sweep of an inner

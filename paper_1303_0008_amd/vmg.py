@@ -62,7 +62,7 @@ EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
            "vmg_solve_periodic", "vmg_residual", "vmg_fill_ghosts", "vmg_ghost_count",
            "vmg_smooth", "vmg_plan_stats", "vmg_plan_config", "vmg_fill_interior", "vmg_total_force",
            "vmg_mass_assign", "vmg_mass_assign_workspace", "vmg_solve_levels", "vmg_levels_create",
-           "vmg_levels_solve", "vmg_levels_destroy"]
+           "vmg_levels_solve", "vmg_levels_destroy", "vmg_mass_assign_region"]
 
 _lib = None
 
@@ -96,6 +96,9 @@ def load():
     L.vmg_mass_assign.argtypes = [vp, ctypes.c_int64, P(ctypes.c_int32), ctypes.c_int32, vp, ctypes.c_int64, vp,
                                   vp]
     L.vmg_mass_assign_workspace.argtypes = [ctypes.c_int64, P(ctypes.c_int32)]
+    L.vmg_mass_assign_region.argtypes = [vp, ctypes.c_int64, P(ctypes.c_int32), ctypes.c_double,
+                                         P(ctypes.c_double), ctypes.c_double, ctypes.c_int32, vp, ctypes.c_int64,
+                                         vp, vp]
     L.vmg_solve_levels.argtypes = [P(Grid), P(Nest), ctypes.c_int32, P(Params), vp, vp, vp, P(Result), vp]
     L.vmg_levels_create.argtypes = [P(vp), P(Grid), P(Nest), ctypes.c_int32, P(Params), vp]
     L.vmg_levels_solve.argtypes = [vp, vp, vp, vp, P(Result)]
@@ -333,6 +336,28 @@ def mass_assign(pos, n, scheme=ASSIGN_TSC, delta=None, workspace=None, stream=No
     c = (ctypes.c_int32 * 3)(*nn)
     _check(load().vmg_mass_assign(_ptr(pos), npart, c, int(scheme), ctypes.c_void_p(workspace.data_ptr()),
                                   workspace.numel(), _ptr(delta), _stream(stream)))
+    return delta
+
+
+def mass_assign_region(pos, n, h, corner, mean_count, scheme=ASSIGN_TSC, delta=None, workspace=None, stream=None):
+    """vmg_mass_assign_region: density contrast on a refinement region of n cells
+    (int or (n0, n1, n2)) of size h, cell (0,0,0) corner at ``corner`` (box
+    units); mean_count = the box's mean particles per cell of size h.  Returns
+    delta shaped (n2, n1, n0)."""
+    import torch
+    nn = (n,) * 3 if isinstance(n, int) else tuple(int(v) for v in n)
+    if delta is None:
+        delta = torch.empty(nn[::-1], dtype=torch.float64, device=pos.device)
+    npart = int(pos.shape[0]) if pos.dim() else 0
+    if workspace is None:
+        workspace = torch.empty(max(mass_assign_workspace(npart, nn), 1), dtype=torch.uint8, device=pos.device)
+    if not workspace.is_cuda or workspace.dtype != torch.uint8 or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous uint8 tensor on the GPU")
+    c = (ctypes.c_int32 * 3)(*nn)
+    cr = (ctypes.c_double * 3)(*[float(v) for v in corner])
+    _check(load().vmg_mass_assign_region(_ptr(pos), npart, c, float(h), cr, float(mean_count), int(scheme),
+                                         ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _ptr(delta),
+                                         _stream(stream)))
     return delta
 
 

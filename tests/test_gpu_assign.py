@@ -167,3 +167,54 @@ def test_assign_zeldovich256_full(torch_cuda, V, oracle_mod, particles256, schem
     assert np.array_equal(got, again)
     assert abs(got.mean()) <= 1e-12
     print(f"{scheme} 256^3 max |diff| {err:.3e}")
+
+
+def region_contribution_bound(pos, shape, h, corner):
+    """K_c for a region: particles whose nearest cell (taken as the region
+    defines it: offset from the corner modulo 1, moved below the corner beyond
+    n h + 2h) lies in the 3 x 3 x 3 block around c."""
+    n0, n1, n2 = shape
+    p = pos[np.isfinite(pos).all(axis=1)]
+    c = []
+    for a, n in enumerate(shape):
+        d = p[:, a] - corner[a]
+        d = d - np.floor(d)
+        d = np.where(d > n * h + 2 * h, d - 1.0, d)
+        c.append(np.floor(d / h).astype(np.int64))
+    ok = np.all([(c[a] >= -1) & (c[a] <= shape[a]) for a in range(3)], axis=0)
+    cnt = np.zeros((n2 + 2, n1 + 2, n0 + 2))
+    np.add.at(cnt, (c[2][ok] + 1, c[1][ok] + 1, c[0][ok] + 1), 1.0)
+    k = np.zeros((n2, n1, n0))
+    for dz in (0, 1, 2):
+        for dy in (0, 1, 2):
+            for dx in (0, 1, 2):
+                k += cnt[dz:dz + n2, dy:dy + n1, dx:dx + n0]
+    return k
+
+
+@pytest.mark.parametrize("scheme", ["cic", "tsc"])
+def test_assign_region_parity(torch_cuda, V, oracle_mod, scheme):
+    """Refinement regions (Sec. VI: the density comes from the particles on
+    every level): a region at twice the resolution of the particle lattice
+    wrapping across the box edge, a non-cubic one with partial bricks at the
+    lattice resolution wrapping in x, a region smaller than one brick, all from
+    64^3 Zel'dovich particles (so particles sit below the corners and far
+    away); every cell against the oracle under the bound of check_parity with
+    s = 1 / mean_count and the position term taken at 1/h."""
+    pos = I.zeldovich_particles(64, I.BASE_SEED + 71, I.ZELDOVICH_AMPLITUDE)
+    npart = pos.shape[0]
+    for shape, h, corner in (((40, 36, 44), 1 / 128, (0.3, 0.55, 0.8)),
+                             ((17, 33, 20), 1 / 64, (60 / 64, 2 / 64, 0.5)),
+                             ((3, 2, 5), 1 / 256, (0.1, 0.2, 0.3))):
+        mean = npart * h ** 3
+        got = V.mass_assign_region(dev(torch_cuda, pos), shape, h, corner, mean, SCHEMES[scheme]).cpu().numpy()
+        ref = oracle_mod.mass_assign_region(pos, shape, h, corner, mean, scheme)
+        assert got.shape == ref.shape
+        k = region_contribution_bound(pos, shape, h, corner)
+        rho = (ref + 1.0) * mean
+        tol = (k * (2.0 ** -41 + 4 * (1 / h) * EPS + EPS * (rho + 3)) / mean
+               + 4 * EPS * (np.abs(ref) + 2))
+        err = np.abs(got - ref)
+        bad = np.argwhere(err > tol)
+        assert bad.size == 0, (scheme, shape, [(tuple(b), err[tuple(b)], tol[tuple(b)]) for b in bad[:5]])
+        print(f"region {shape} h={h:g}: max |diff| {err.max():.2e}, mass {(ref + 1).sum() * mean:.1f}", flush=True)
