@@ -267,12 +267,14 @@ def time_tau_rule(torch, V, delta, w, stream, steps):
 
 
 def time_levels(torch, V, delta_np, w, steps):
-    """vmg_solve_levels on the workload's domain grid with 8 first-level 64^3
+    """vmg_levels_solve on the workload's domain grid with 8 first-level 64^3
     refinements at h = 1/512 centred on the 8 densest cells at least 40 cells
-    apart (so the refinements do not overlap) and a
-    64^3 second level at h = 1/1024 in the middle of each (mixed precision, tol as
-    the workload); each refinement's density is a seeded lognormal (sigma 1.5).
-    Wall time per vmg_levels_solve on a plan created beforehand."""
+    apart (so the refinements do not overlap) and a 64^3 second level at
+    h = 1/1024 in the middle of each (mixed precision, tol as the workload).
+    Each refinement's density is the cloud-in-cell assignment of the
+    workload's particles onto it (vmg_mass_assign_region), the recipe of the
+    domain grid at the finer spacing.  Wall time per vmg_levels_solve on a plan
+    created beforehand; the assignment of all 16 refinements is timed apart."""
     import numpy as np
     from paper_1303_0008_amd import inputs as I
     n = w["n"]
@@ -284,20 +286,40 @@ def time_levels(torch, V, delta_np, w, steps):
             peaks.append((i, j, k))
         if len(peaks) == 8:
             break
+    pos_np = I.zeldovich_particles(n, I.BASE_SEED + 3, I.ZELDOVICH_AMPLITUDE)
+    pos = torch.from_numpy(pos_np).to("cuda")
     grids = [V.make_grid(n)]
     nests = [V.make_nest(-1)]
-    deltas = [delta_np]
+    regions = []                       # (offset, h, corner) of each refinement
     off, goff = delta_np.size, 0
+    corners = {}
     for lev, h in ((1, 1.0 / (2 * n)), (2, 1.0 / (4 * n))):
         for t, p in enumerate(peaks):
             parent = 0 if lev == 1 else 1 + t
             origin = tuple((2 * c - 32) % (2 * n) for c in p) if lev == 1 else (32, 32, 32)
+            base = (0.0, 0.0, 0.0) if lev == 1 else corners[parent]
+            corner = tuple((base[a] + origin[a] * h) % 1.0 for a in range(3))
+            corners[len(grids)] = corner
             grids.append(V.make_grid(64, h, V.DIRICHLET, off, goff))
             nests.append(V.make_nest(parent, origin))
-            deltas.append(I.lognormal(64, I.BASE_SEED + 500 + 10 * lev + t, sigma=1.5))
+            regions.append((off, h, corner))
             off += 64 ** 3
             goff += V.ghost_count(64)
-    d = torch.from_numpy(np.concatenate([x.ravel() for x in deltas])).to("cuda")
+    d = torch.empty(off, dtype=torch.float64, device="cuda")
+    d[:delta_np.size] = torch.from_numpy(delta_np.ravel()).to("cuda")
+    work = torch.empty(V.mass_assign_workspace(pos_np.shape[0], 64), dtype=torch.uint8, device="cuda")
+
+    def assign_all():
+        for o, h, corner in regions:
+            V.mass_assign_region(pos, 64, h, corner, pos_np.shape[0] * h ** 3, V.ASSIGN_CIC,
+                                 delta=d[o:o + 64 ** 3].view(64, 64, 64), workspace=work)
+
+    assign_all()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    assign_all()
+    torch.cuda.synchronize()
+    assign_ms = 1e3 * (time.perf_counter() - t0)
     ghost = torch.zeros(goff, dtype=torch.float64, device="cuda")
     params = V.make_params(w["alpha"], w["kappa"], w["tol"], 100, V.MIXED, flags=V.GRAPH)
     phis = [torch.zeros_like(d) for _ in range(steps + 1)]
@@ -310,10 +332,11 @@ def time_levels(torch, V, delta_np, w, steps):
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / steps
     log(f"levels: {ms:.2f} ms per multilevel solve ({len(grids)} grids, {off} cells), "
-        f"max rms {max(r['rms'] for r in res):.2e}")
+        f"max rms {max(r['rms'] for r in res):.2e}; refinement densities assigned in {assign_ms:.2f} ms")
     return {"ms_per_solve": ms, "grids": len(grids), "cells": off, "max_rms": max(r["rms"] for r in res),
-            "cycles": [r["cycles"] for r in res],
-            "note": "vmg_levels_solve on a plan created beforehand, from phi = 0, mixed precision"}
+            "cycles": [r["cycles"] for r in res], "refinement_assign_ms": assign_ms,
+            "note": "vmg_levels_solve on a plan created beforehand, from phi = 0, mixed precision; refinement "
+                    "densities by cloud-in-cell region assignment of the workload's particles"}
 
 
 def cpu_baseline(delta, w, sweeps=5):
