@@ -1,7 +1,9 @@
-// Mass assignment: unit-mass particles to the density contrast on a periodic
-// mesh (Sec. VI: the mesh density comes from triangular-shaped-cloud
-// assignment of the particles; cloud in cell is the next-lower-order member of
-// the same family of shape functions).
+// Mass assignment: unit-mass particles to the density contrast on the periodic
+// domain mesh or on a refinement region (Sec. VI: the mesh density comes from
+// triangular-shaped-cloud assignment of the particles; cloud in cell is the
+// next-lower-order member of the same family of shape functions).  A region is
+// not periodic: each particle is taken from the periodic image that reaches
+// it, and contributions outside it are dropped.
 //
 // Both schemes touch the particle's nearest cell and its 26 neighbours at most,
 // so the grid is cut into bricks of BRICK^3 cells and every particle belongs to
