@@ -16,7 +16,8 @@
 //   3. k_bin<1>       the same chunks again: each nonzero (chunk, brick) count
 //                     reserves a range of that brick's slots with one atomic,
 //                     and the particle indices are written sorted by brick;
-//   4. k_bin_assign   one workgroup per brick: the brick and a one-cell halo
+//   4. k_bin_assign   one workgroup per brick (heaviest bricks first for the
+//                     triangular-shaped cloud): the brick and a one-cell halo
 //                     are accumulated in LDS and the region is copied to the
 //                     workspace;
 //   5. k_gather       every cell sums the staged entries of the bricks that
@@ -305,13 +306,44 @@ __device__ __forceinline__ int axis_local(double u, int n, int org, double (&w)[
     }
 }
 
+// Bricks in order of decreasing particle count (64 buckets of 128 particles;
+// one block), so the heaviest bricks start first and do not trail the launch
+// (used for the triangular-shaped cloud, whose per-particle work makes the
+// imbalance worth the extra launch).
+constexpr int ORD_NT = 1024;
+__global__ void __launch_bounds__(ORD_NT) k_brick_order(const uint32_t* __restrict__ start, int64_t nb,
+                                                        uint32_t* __restrict__ order) {
+    __shared__ uint32_t hist[64];
+    if (threadIdx.x < 64) hist[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int64_t b = threadIdx.x; b < nb; b += ORD_NT) {
+        const uint32_t cnt = start[(b + 1) * SUB] - start[b * SUB];
+        atomicAdd(&hist[63 - min(cnt >> 7, 63u)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < 64; ++k) {
+            const uint32_t v = hist[k];
+            hist[k] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    for (int64_t b = threadIdx.x; b < nb; b += ORD_NT) {
+        const uint32_t cnt = start[(b + 1) * SUB] - start[b * SUB];
+        order[atomicAdd(&hist[63 - min(cnt >> 7, 63u)], 1u)] = (uint32_t)b;
+    }
+}
+
 template <int M, bool PER>
 __global__ void __launch_bounds__(ANT) k_bin_assign(AGrid g, const double* __restrict__ pos,
                                                    const uint32_t* __restrict__ start,
                                                    const uint32_t* __restrict__ idx,
+                                                   const uint32_t* __restrict__ order,
                                                    unsigned long long* __restrict__ stage) {
     __shared__ unsigned long long acc[REGN];
-    const int key = blockIdx.x;
+    const int key = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
     const int bx = key % g.b0, by = (key / g.b0) % g.b1, bz = key / (g.b0 * g.b1);
     const int o0 = bx * BRICK, o1 = by * BRICK, o2 = bz * BRICK;
     for (int e = threadIdx.x; e < REGN; e += ANT) acc[e] = 0ull;
@@ -441,7 +473,8 @@ int64_t mass_assign_bricks(int n0, int n1, int n2) {
 int64_t mass_assign_workspace(int64_t np, int n0, int n1, int n2) {
     const int64_t nc = mass_assign_bricks(n0, n1, n2) * SUB;
     return 2 * align256(nc * 4) + align256((nc + 1) * 4) + align256((nc + SCAN_TILE - 1) / SCAN_TILE * 4) +
-           2 * align256(np * 4) + align256(mass_assign_bricks(n0, n1, n2) * REGN * 8);
+           2 * align256(np * 4) + align256(mass_assign_bricks(n0, n1, n2) * REGN * 8) +
+           align256(mass_assign_bricks(n0, n1, n2) * 4);
 }
 
 hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int n2, int scheme, bool periodic,
@@ -471,6 +504,8 @@ hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int
     uint32_t* idx = reinterpret_cast<uint32_t*>(w);
     w += align256(np * 4);
     unsigned long long* stage = reinterpret_cast<unsigned long long*>(w);
+    w += align256(nb * REGN * 8);
+    uint32_t* order = reinterpret_cast<uint32_t*>(w);
     const double scale = FIX_INV / mean_count;
     const int chunks = grid_for((np + CHUNK - 1) / CHUNK * NT, 8192);
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nc)), dim3(NT), 0, s, count, nc);
@@ -482,14 +517,18 @@ hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(NT), 0, s, sums, ntile);
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntile), dim3(NT), 0, s, count, nc, sums, start, cursor);
     hipLaunchKernelGGL((k_bin<1, true>), dim3(chunks), dim3(NT), 0, s, g, pos, np, cursor, keys, idx);
-    if (scheme == 1 && periodic)
-        hipLaunchKernelGGL((k_bin_assign<2, true>), dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, stage);
-    else if (scheme == 1)
-        hipLaunchKernelGGL((k_bin_assign<2, false>), dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, stage);
-    else if (periodic)
-        hipLaunchKernelGGL((k_bin_assign<3, true>), dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, stage);
+    if (scheme == 2)
+        hipLaunchKernelGGL(k_brick_order, dim3(1), dim3(ORD_NT), 0, s, start, nb, order);
     else
-        hipLaunchKernelGGL((k_bin_assign<3, false>), dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, stage);
+        order = nullptr;
+    if (scheme == 1 && periodic)
+        hipLaunchKernelGGL((k_bin_assign<2, true>), dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, order, stage);
+    else if (scheme == 1)
+        hipLaunchKernelGGL((k_bin_assign<2, false>), dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, order, stage);
+    else if (periodic)
+        hipLaunchKernelGGL((k_bin_assign<3, true>), dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, order, stage);
+    else
+        hipLaunchKernelGGL((k_bin_assign<3, false>), dim3((unsigned)nb), dim3(ANT), 0, s, g, pos, start, idx, order, stage);
     hipLaunchKernelGGL(k_gather, dim3(n1, n2), dim3(NT), 0, s, g, periodic, stage, scale, delta);
     return hipGetLastError();
 }
