@@ -129,13 +129,16 @@ __global__ void __launch_bounds__(NT) k_bin(AGrid g, const double* __restrict__ 
                                             uint32_t* __restrict__ counter, uint32_t* __restrict__ keys,
                                             uint32_t* __restrict__ idx) {
     __shared__ uint32_t tkey[TAB], tcnt[TAB];
+    __shared__ uint16_t used[CHUNK];                      // entries this chunk filled, in fill order
+    __shared__ uint32_t n_used;
+    for (int e = threadIdx.x; e < TAB; e += NT) {
+        tkey[e] = NO_KEY;
+        tcnt[e] = 0u;
+    }
+    if (threadIdx.x == 0) n_used = 0u;
+    __syncthreads();
     const int64_t nchunk = (np + CHUNK - 1) / CHUNK;
     for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-        for (int e = threadIdx.x; e < TAB; e += NT) {
-            tkey[e] = NO_KEY;
-            tcnt[e] = 0u;
-        }
-        __syncthreads();
         uint32_t key[CHUNK_PER_THREAD];
 #pragma unroll
         for (int k = 0; k < CHUNK_PER_THREAD; ++k) {
@@ -171,7 +174,11 @@ __global__ void __launch_bounds__(NT) k_bin(AGrid g, const double* __restrict__ 
                 h = (int)((key[k] * 2654435761u) >> 20) & (TAB - 1);
                 for (;;) {                                // at most CHUNK distinct keys: always a free entry
                     const uint32_t old = atomicCAS(&tkey[h], NO_KEY, key[k]);
-                    if (old == NO_KEY || old == key[k]) break;
+                    if (old == NO_KEY) {
+                        used[atomicAdd(&n_used, 1u)] = (uint16_t)h;
+                        break;
+                    }
+                    if (old == key[k]) break;
                     h = (h + 1) & (TAB - 1);
                 }
                 base = atomicAdd(&tcnt[h], (uint32_t)len);
@@ -182,9 +189,10 @@ __global__ void __launch_bounds__(NT) k_bin(AGrid g, const double* __restrict__ 
         }
         __syncthreads();
         const uint32_t sub = (uint32_t)(ch % SUB);
-        for (int e = threadIdx.x; e < TAB; e += NT) {
+        const int nu = (int)n_used;
+        for (int u = threadIdx.x; u < nu; u += NT) {
+            const int e = used[u];
             const uint32_t k = tkey[e];
-            if (k == NO_KEY) continue;
             if (MODE == 0)
                 atomicAdd(counter + (size_t)k * SUB + sub, tcnt[e]);
             else
@@ -196,6 +204,15 @@ __global__ void __launch_bounds__(NT) k_bin(AGrid g, const double* __restrict__ 
             for (int k = 0; k < CHUNK_PER_THREAD; ++k)
                 if (hs[k] >= 0) idx[tcnt[hs[k]] + loc[k]] = (uint32_t)(ch * CHUNK + k * NT + threadIdx.x);
         }
+        __syncthreads();
+        // empty the filled entries for the next chunk
+        for (int u = threadIdx.x; u < nu; u += NT) {
+            const int e = used[u];
+            tkey[e] = NO_KEY;
+            tcnt[e] = 0u;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) n_used = 0u;
         __syncthreads();
     }
 }
