@@ -204,3 +204,32 @@ def test_levels_plan_reuse(torch_cuda, V, oracle_tree):
         phi = torch.zeros_like(d)
         V.solve_levels(grids, nests, p, d, ghost, phi)
         assert np.array_equal(phi.cpu().numpy(), ref)
+
+
+def test_levels_deep_and_trivial_trees(torch_cuda, V, oracle_mod):
+    """A tree four levels deep (32^3 domain, then 16^3 refinements nested three
+    times, each one parent cell inside its parent) against the oracle's
+    composition; and a tree that is only the domain grid, which must give the
+    plain periodic solve bit for bit."""
+    torch = torch_cuda
+    levels = [dict(delta=I.tophat(32, radius=R, amplitude=D0), h=1 / 32, parent=-1, origin=(0, 0, 0))]
+    corner = (0.0, 0.0, 0.0)
+    for depth in range(1, 4):
+        h = levels[-1]["h"] / 2
+        origin = (24, 24, 24) if depth == 1 else (8, 8, 8)          # centred on the sphere, one cell of margin
+        corner = tuple(corner[a] + origin[a] * h for a in range(3))
+        levels.append(dict(delta=I.tophat_region((16, 16, 16), h, corner, 32, radius=R, amplitude=D0), h=h,
+                           parent=len(levels) - 1, origin=origin))
+    ref, _ = oracle_mod.solve_levels(levels, ALPHA, KAPPA, tol=1e-13)
+    res, got, _ = gpu_tree(torch, V, levels, V.make_params(ALPHA, KAPPA, 1e-11, 100, flags=V.GRAPH))
+    for i, (r, a, b) in enumerate(zip(res, got, ref)):
+        print("deep", i, "rms", r["rms"], "relerr", relerr(a, b), flush=True)
+        assert r["rms"] <= 1e-11 and relerr(a, b) <= 1e-10
+    p = V.make_params(ALPHA, KAPPA, 1e-11, 100, flags=V.GRAPH)
+    d = dev(torch, levels[0]["delta"])
+    phi1 = torch.zeros_like(d)
+    V.solve_levels([V.make_grid(32)], [V.make_nest(-1)], p, d.ravel(), None, phi1.view(-1))
+    phi2 = torch.zeros_like(d)
+    with V.Plan([V.make_grid(32)], p) as plan:
+        plan.solve(d, phi2)
+    assert torch.equal(phi1, phi2)
