@@ -368,24 +368,9 @@ __global__ void __launch_bounds__(ANT) k_bin_assign(AGrid g, const double* __res
     const uint32_t lo = start[(size_t)key * SUB], hi = start[(size_t)(key + 1) * SUB];
     const int lane = threadIdx.x & 63;
     const int rx = lane % M, ry = (lane >> 4) % M;
-    // the next particle's index and position are loaded before this one's
-    // LDS atomics are issued
-    uint32_t t = lo + threadIdx.x;
-    double x = 0.0, y = 0.0, z = 0.0;
-    if (t < hi) {
+    for (uint32_t t = lo + threadIdx.x; t < hi; t += ANT) {
         const int64_t p = idx[t];
-        x = pos[3 * p];
-        y = pos[3 * p + 1];
-        z = pos[3 * p + 2];
-    }
-    for (; t < hi; t += ANT) {
-        double xn = 0.0, yn = 0.0, zn = 0.0;
-        if (t + ANT < hi) {
-            const int64_t p = idx[t + ANT];
-            xn = pos[3 * p];
-            yn = pos[3 * p + 1];
-            zn = pos[3 * p + 2];
-        }
+        const double x = pos[3 * p], y = pos[3 * p + 1], z = pos[3 * p + 2];
         double wx[M], wy[M], wz[M];
         const int l0 = axis_local<M, PER>(axis_u<PER>(g, 0, x, g.n0), g.n0, o0, wx);
         const int l1 = axis_local<M, PER>(axis_u<PER>(g, 1, y, g.n1), g.n1, o1, wy);
@@ -423,9 +408,6 @@ __global__ void __launch_bounds__(ANT) k_bin_assign(AGrid g, const double* __res
                 }
             }
         }
-        x = xn;
-        y = yn;
-        z = zn;
     }
     __syncthreads();
     unsigned long long* st = stage + (size_t)key * REGN;
