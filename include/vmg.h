@@ -210,8 +210,9 @@ vmg_status vmg_solve_levels(const vmg_grid *grids, const vmg_nest *nest, int32_t
  * tree as vmg_solve_levels does and allocates one plan per depth (the domain
  * grid's, then one batched plan per refinement depth) on `stream`;
  * vmg_levels_solve runs the level-by-level solve on those plans without
- * allocating (same arrays, results and errors as vmg_solve_levels; returns
- * after the stream has finished); vmg_levels_destroy frees the plans (NULL is
+ * allocating (same arrays, results and errors as vmg_solve_levels; the
+ * results of levels it does not reach are zeroed; returns after the stream
+ * has finished); vmg_levels_destroy frees the plans (NULL is
  * ignored).  A levels plan must not be used from two threads at once. */
 typedef struct vmg_levels vmg_levels;
 vmg_status vmg_levels_create(vmg_levels **levels, const vmg_grid *grids, const vmg_nest *nest, int32_t n_grids,

@@ -719,6 +719,7 @@ vmg_status vmg_levels_solve(vmg_levels* L, const double* delta, double* ghost, d
     g_err.clear();
     if (!L || !delta || !phi || !out) return fail(VMG_EINVAL, "null argument");
     if (L->grids.size() > 1 && !ghost) return fail(VMG_EINVAL, "refinements need a ghost array");
+    for (size_t i = 0; i < L->grids.size(); ++i) std::memset(&out[i], 0, sizeof(vmg_result));   // unsolved levels stay 0
     for (size_t d = 0; d < L->plans.size(); ++d) {
         const std::vector<int>& idx = L->members[d];
         if (d > 0)
@@ -753,7 +754,6 @@ vmg_status vmg_solve_levels(const vmg_grid* grids, const vmg_nest* nest, int32_t
     vmg_levels* L = nullptr;
     vmg_status st = vmg_levels_create(&L, grids, nest, n_grids, p, stream);
     if (st != VMG_OK) return st;
-    for (int32_t i = 0; i < n_grids; ++i) std::memset(&out[i], 0, sizeof(vmg_result));
     st = vmg_levels_solve(L, delta, ghost, phi, out);
     const std::string msg = g_err;
     vmg_levels_destroy(L);
