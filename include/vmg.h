@@ -101,7 +101,7 @@ typedef struct {
     double tau_factor;     /* > 0: also stop once |d^h| <= tau_factor |tau^h| on every grid,
                               tau^h = L^H(R phi) - R L^h(phi) the truncation-error estimate of
                               Sec. III.C (the paper takes the factor <= 1/3); FP64 plans of
-                              grids with coarser levels only; 0 = off */
+                              one periodic grid with coarser levels only; 0 = off */
 } vmg_params;
 
 typedef struct {

@@ -565,8 +565,8 @@ vmg_status vmg_plan_create(vmg_plan** plan, const vmg_grid* grids, int32_t n_gri
         !std::isfinite(p->tau_factor))
         return fail(VMG_EINVAL, "invalid parameters (tol > 0, max_cycles >= 1, prec, nu1/nu2 >= 0, finite alpha/kappa, "
                                 "tau_factor >= 0)");
-    if (p->tau_factor > 0.0 && (p->prec != VMG_FP64 || n_grids != 1))
-        return fail(VMG_EINVAL, "tau_factor needs an FP64 plan of one grid");
+    if (p->tau_factor > 0.0 && (p->prec != VMG_FP64 || n_grids != 1 || grids[0].bc != VMG_PERIODIC))
+        return fail(VMG_EINVAL, "tau_factor needs an FP64 plan of one periodic grid");
     const int bc0 = grids[0].bc;
     for (int i = 0; i < n_grids; ++i) {
         const vmg_grid& g = grids[i];

@@ -72,3 +72,5 @@ def test_tau_factor_rejected_where_not_supported(torch_cuda, V):
         V.Plan([V.make_grid(16)], V.make_params(0.1, 1.5, 1e-8, 10, V.MIXED, tau_factor=0.3))
     with pytest.raises(V.VmgError):
         V.Plan([V.make_grid(16)], V.make_params(0.1, 1.5, 1e-8, 10, tau_factor=-1.0))
+    with pytest.raises(V.VmgError):                      # the estimate is defined on periodic grids only
+        V.Plan([V.make_grid(16, 1 / 64, V.DIRICHLET)], V.make_params(0.1, 1.5, 1e-8, 10, tau_factor=0.3))
