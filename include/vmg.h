@@ -240,8 +240,8 @@ vmg_status vmg_fill_interior(const double *parent, const int32_t np[3], double p
  * brane-bending mode.  Writes psi = phi_newton + phi/2 (may be NULL) and the
  * acceleration -grad Psi into force: 3 N values, the x, y and z components one
  * after another.  Enqueued on `stream`; the caller owns every buffer.
- * Errors: VMG_EINVAL (null input or force, n < 1, n[1] n[2] >= 2^31, h not
- * finite and > 0), VMG_EHIP. */
+ * Errors: VMG_EINVAL (null input or force, n < 1, more than 2^31 - 1 tiles
+ * of 64 x 8 x 16 cells, h not finite and > 0), VMG_EHIP. */
 vmg_status vmg_total_force(const double *phi_newton, const double *phi, const int32_t n[3], double h,
                            double *psi, double *force, hipStream_t stream);
 

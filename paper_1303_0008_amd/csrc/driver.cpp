@@ -839,8 +839,9 @@ vmg_status vmg_total_force(const double* phi_newton, const double* phi, const in
                            double* force, hipStream_t stream) {
     g_err.clear();
     if (!phi_newton || !phi || !n || !force) return fail(VMG_EINVAL, "null argument");
-    if (n[0] < 1 || n[1] < 1 || n[2] < 1 || (int64_t)n[1] * n[2] > INT32_MAX || !(h > 0.0) || !std::isfinite(h))
-        return fail(VMG_EINVAL, "total force needs n >= 1 per axis, n[1] n[2] < 2^31 and a finite h > 0");
+    if (n[0] < 1 || n[1] < 1 || n[2] < 1 || !(h > 0.0) || !std::isfinite(h) ||
+        total_force_blocks(n[0], n[1], n[2]) > INT32_MAX)
+        return fail(VMG_EINVAL, "total force needs n >= 1 per axis, a grid of fewer than 2^31 tiles and a finite h > 0");
     CKH(launch_total_force(n[0], n[1], n[2], h, phi_newton, phi, psi, force, stream));
     return VMG_OK;
 }

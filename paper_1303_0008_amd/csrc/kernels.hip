@@ -1210,32 +1210,80 @@ hipError_t launch_ghost_fill(const double* parent, int np0, int np1, int np2, do
 }
 
 // Total potential Psi = phi_N + phi/2 and acceleration -grad Psi (periodic
-// central differences).  One block per row, threads along x.  Psi of the
-// neighbours is formed from the two inputs on the fly, so psi is only written
-// (optional).
-__global__ void __launch_bounds__(NT) k_total_force(int n0, int n1, int n2, double inv_2h,
-                                                   const double* __restrict__ phin,
-                                                   const double* __restrict__ phi, double* __restrict__ psi,
-                                                   double* __restrict__ g) {
-    const int j = (int)(blockIdx.x % (unsigned)n1), k = (int)(blockIdx.x / (unsigned)n1);
+// central differences).  A block of FX x FY threads owns an FX x FY column of
+// cells and marches up a chunk of FZC planes: Psi of each plane, with a
+// one-cell ring, is staged in LDS (two buffers: plane k and k + 1), so each
+// input is read about once; the z neighbours are the previous plane's value
+// (kept in a register) and the next plane's tile.
+constexpr int FX = 64, FY = 8, FZC = 16, FNT = FX * FY;
+constexpr int FW = FX + 2, FH = FY + 2, FNP = FW * FH, FNL = (FNP + FNT - 1) / FNT;
+
+__global__ void __launch_bounds__(FNT) k_total_force(int n0, int n1, int n2, double inv_2h,
+                                                    const double* __restrict__ phin,
+                                                    const double* __restrict__ phi, double* __restrict__ psi,
+                                                    double* __restrict__ g) {
+    __shared__ double T[2][FH][FW];
+    const int tiles_x = (n0 + FX - 1) / FX, tiles_y = (n1 + FY - 1) / FY;
+    int b = blockIdx.x;
+    const int tx = b % tiles_x;
+    b /= tiles_x;
+    const int ty = b % tiles_y;
+    const int z0 = (b / tiles_y) * FZC, z1 = min(z0 + FZC, n2);
+    const int lx = threadIdx.x % FX, ly = threadIdx.x / FX;
+    const int i = tx * FX + lx, j = ty * FY + ly;
+    const bool active = i < n0 && j < n1;
     const int64_t N = (int64_t)n0 * n1 * n2, pl = (int64_t)n0 * n1;
-    const int64_t row = (int64_t)k * pl + (int64_t)j * n0;
-    const int64_t yp = (j == n1 - 1 ? -(int64_t)(n1 - 1) * n0 : n0), ym = (j == 0 ? (int64_t)(n1 - 1) * n0 : -(int64_t)n0);
-    const int64_t zp = (k == n2 - 1 ? -(int64_t)(n2 - 1) * pl : pl), zm = (k == 0 ? (int64_t)(n2 - 1) * pl : -pl);
-    auto P = [&](int64_t q) { return phin[q] + 0.5 * phi[q]; };
-    for (int i = threadIdx.x; i < n0; i += NT) {
-        const int64_t e = row + i;
-        const int64_t xp = row + (i == n0 - 1 ? 0 : i + 1), xm = row + (i == 0 ? n0 - 1 : i - 1);
-        if (psi) psi[e] = P(e);
-        g[e] = -(P(xp) - P(xm)) * inv_2h;
-        g[N + e] = -(P(e + yp) - P(e + ym)) * inv_2h;
-        g[2 * N + e] = -(P(e + zp) - P(e + zm)) * inv_2h;
+    // in-plane offsets of this thread's loader slots (ring included, periodic wrap)
+    int64_t off[FNL];
+#pragma unroll
+    for (int s2 = 0; s2 < FNL; ++s2) {
+        const int e = threadIdx.x + s2 * FNT;
+        off[s2] = 0;
+        if (e < FNP) {
+            int gx = (tx * FX - 1 + e % FW) % n0, gy = (ty * FY - 1 + e / FW) % n1;
+            gx += gx < 0 ? n0 : 0;
+            gy += gy < 0 ? n1 : 0;
+            off[s2] = (int64_t)gy * n0 + gx;
+        }
     }
+    auto P = [&](int64_t q) { return phin[q] + 0.5 * phi[q]; };
+    auto load_tile = [&](int buf, int k) {
+        const int64_t zo = (int64_t)k * pl;
+#pragma unroll
+        for (int s2 = 0; s2 < FNL; ++s2) {
+            const int e = threadIdx.x + s2 * FNT;
+            if (e < FNP) T[buf][e / FW][e % FW] = P(zo + off[s2]);
+        }
+    };
+    const int64_t col = active ? (int64_t)j * n0 + i : 0;
+    double pm = P((int64_t)(z0 == 0 ? n2 - 1 : z0 - 1) * pl + col);     // Psi at (i, j, z0 - 1)
+    load_tile(0, z0);
+    int cur = 0;
+    for (int k = z0; k < z1; ++k) {
+        load_tile(cur ^ 1, k + 1 == n2 ? 0 : k + 1);
+        __syncthreads();
+        const double pc = T[cur][ly + 1][lx + 1];
+        const double pp = T[cur ^ 1][ly + 1][lx + 1];
+        if (active) {
+            const int64_t e = (int64_t)k * pl + col;
+            if (psi) psi[e] = pc;
+            g[e] = -(T[cur][ly + 1][lx + 2] - T[cur][ly + 1][lx]) * inv_2h;
+            g[N + e] = -(T[cur][ly + 2][lx + 1] - T[cur][ly][lx + 1]) * inv_2h;
+            g[2 * N + e] = -(pp - pm) * inv_2h;
+        }
+        pm = pc;
+        cur ^= 1;
+        __syncthreads();
+    }
+}
+
+int64_t total_force_blocks(int n0, int n1, int n2) {
+    return (int64_t)((n0 + FX - 1) / FX) * ((n1 + FY - 1) / FY) * ((n2 + FZC - 1) / FZC);
 }
 
 hipError_t launch_total_force(int n0, int n1, int n2, double h, const double* phin, const double* phi, double* psi,
                               double* g, hipStream_t s) {
-    hipLaunchKernelGGL(k_total_force, dim3((unsigned)((int64_t)n1 * n2)), dim3(NT), 0, s, n0, n1, n2,
+    hipLaunchKernelGGL(k_total_force, dim3((unsigned)total_force_blocks(n0, n1, n2)), dim3(FNT), 0, s, n0, n1, n2,
                        1.0 / (2.0 * h), phin, phi, psi, g);
     return hipGetLastError();
 }

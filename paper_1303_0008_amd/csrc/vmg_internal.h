@@ -181,6 +181,7 @@ hipError_t launch_ghost_fill(const double* parent, int np0, int np1, int np2, do
 // Psi = phi_N + phi/2 (psi may be null) and g = -grad Psi (gx, gy, gz blocks of N), periodic
 hipError_t launch_total_force(int n0, int n1, int n2, double h, const double* phin, const double* phi, double* psi,
                               double* g, hipStream_t s);
+int64_t total_force_blocks(int n0, int n1, int n2);
 hipError_t launch_interior_fill(const double* parent, int np0, int np1, int np2, double H, int n0, int n1, int n2,
                                 double h, int o0, int o1, int o2, double* phi, hipStream_t s);
 // Particles (np x 3, box units) -> delta on a periodic n0 x n1 x n2 grid;
