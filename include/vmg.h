@@ -67,7 +67,6 @@ typedef enum { VMG_PERIODIC = 0, VMG_DIRICHLET = 1 } vmg_bc;
 /* flags */
 #define VMG_GRAPH 1u          /* replay the V-cycle as a captured hipGraph */
 #define VMG_AUTOTUNE 2u       /* time tile/schedule choices at plan creation */
-#define VMG_QUIET_NOCONV 4u   /* reserved */
 
 /* One grid.  A plan holds either exactly one periodic grid or one or more
  * Dirichlet grids (refinement patches, solved as one batch). */
@@ -119,8 +118,11 @@ typedef struct vmg_plan vmg_plan;
 
 /* Create a solver plan for `n_grids` grids (Sec. III.C: the domain grid, or a
  * set of refinement patches).  Allocates every workspace on the current
- * device, may run the autotuner (VMG_AUTOTUNE) and records the V-cycle graph
- * (VMG_GRAPH).  All later work is issued on `stream` (0 = null stream).
+ * device, may run the autotuner (VMG_AUTOTUNE) and, with VMG_GRAPH, records
+ * and instantiates the hipGraphs of one iteration (one per finest-level
+ * ping-pong parity, with and without a source), so that vmg_solve replays them
+ * without allocating.  All later work is issued on `stream` (0: a blocking
+ * stream the plan creates, since the legacy null stream cannot be captured).
  * Errors: VMG_EINVAL (sizes, h <= 0, tol <= 0, max_cycles < 1, inner_cycles < 0 or
  * set for VMG_FP64, tau_factor < 0 or not finite, tau_factor > 0 with VMG_MIXED, with
  * several grids or with a grid that has no coarser level, mixed BC kinds,
@@ -131,10 +133,14 @@ vmg_status vmg_plan_create(vmg_plan **plan, const vmg_grid *grids, int32_t n_gri
 
 /* Solve (Sec. III.C: V-cycles until |d| < tol).  delta: density contrast of
  * every grid; ghost: Dirichlet ghost values (may be NULL for a periodic plan);
- * source: optional additive right-hand side f (NULL = 0; not supported with
- * VMG_MIXED); phi: initial guess in, solution out (periodic: mean removed).
- * out: host array of n_grids results.  Never allocates device memory; runs on
- * the plan's stream and returns after it has finished.
+ * source: optional additive right-hand side f (NULL = 0), in either precision
+ * (the mixed path's FP64 defect includes it); phi: initial guess in, solution
+ * out (periodic: mean removed).  out: host array of n_grids results.  Never
+ * allocates device memory (with VMG_GRAPH it replays the graphs recorded at
+ * plan creation); runs on the plan's stream and returns after it has finished.
+ * Divergence: a non-finite residual, a residual 1e4 times above the smallest
+ * one seen so far, or (after the first four iterations, whose nonlinear start
+ * phase may raise it) three iterations in a row 10 times above it.
  * Errors: VMG_EINVAL (null pointers), VMG_ENONFINITE (non-finite delta or
  * residual, divergence; phi holds the last iterate), VMG_ENOCONV (max_cycles
  * reached; phi and out are filled), VMG_EHIP. */
@@ -326,6 +332,25 @@ vmg_status vmg_plan_stats(const vmg_plan *plan, int64_t *cell_updates, int64_t *
  * pre/post sweeps and coarsest-level sweeps.  Errors: VMG_EINVAL. */
 vmg_status vmg_plan_config(const vmg_plan *plan, int32_t *tile_y, int32_t *z_chunk, int32_t *nu1,
                            int32_t *nu2, int32_t *coarse_sweeps);
+
+/* Number of levels of a plan that run the fused red-black sweep (the finest
+ * level and every coarser one above the single-launch coarse tail), i.e. the
+ * levels vmg_plan_set_schedule and vmg_plan_schedule accept; -1 for NULL. */
+int32_t vmg_plan_level_count(const vmg_plan *plan);
+
+/* Install a sweep schedule on one level (Sec. V of the paper notes that the
+ * code needed more tuning; this is how a caller reuses schedules the autotuner
+ * found, or forces one): the fused sweep of level `level` then runs tiles of
+ * 64 x tile_y cells marching z_chunk planes.  The schedule changes only the
+ * blocking of the same red-black update, not the result's definition.  With
+ * VMG_GRAPH the iteration graphs are recorded again (allocates).
+ * Errors: VMG_EINVAL (null plan, level outside [0, vmg_plan_level_count),
+ * tile_y not in {4, 8, 12, 16}, z_chunk odd or outside [2, 1024]), VMG_EHIP. */
+vmg_status vmg_plan_set_schedule(vmg_plan *plan, int32_t level, int32_t tile_y, int32_t z_chunk);
+
+/* The sweep schedule a level runs (host pointers, each may be NULL).
+ * Errors: VMG_EINVAL (null plan, level outside [0, vmg_plan_level_count)). */
+vmg_status vmg_plan_schedule(const vmg_plan *plan, int32_t level, int32_t *tile_y, int32_t *z_chunk);
 
 #ifdef __cplusplus
 }

@@ -75,19 +75,6 @@ void remember(const std::string& key, const SmoothCfg& c, double us) {
     append_file_cache(key, c, us);
 }
 
-// Levels of the plan that run the fused sweep: every level above the coarsest,
-// except those the periodic coarse tail handles in one launch.
-int swept_levels(const Plan* P) {
-    if (P->batched) {
-        int n = 0;
-        for (size_t l = 0; l < P->blev.size(); ++l)
-            if (P->blev[l].nsitems > 0) n = (int)l + 1;
-        return n;
-    }
-    const int tl = tail_level(P, P->grids[0]);
-    return tl > 0 ? tl : (int)P->grids[0].lev.size() - 1;
-}
-
 // Install schedule c on level l.
 hipError_t apply(Plan* P, int l, const SmoothCfg& c) {
     if (l == 0) P->cfg = c;
@@ -107,13 +94,27 @@ hipError_t sweep_level(Plan* P, int l) {
 }
 }  // namespace
 
+// Levels of the plan that run the fused sweep: every level above the coarsest,
+// except those the periodic coarse tail handles in one launch.
+int swept_level_count(const Plan* P) {
+    if (P->batched) {
+        int n = 0;
+        for (size_t l = 0; l < P->blev.size(); ++l)
+            if (P->blev[l].nsitems > 0) n = (int)l + 1;
+        return n;
+    }
+    const int tl = tail_level(P, P->grids[0]);
+    return tl > 0 ? tl : (int)P->grids[0].lev.size() - 1;
+}
+
+
 vmg_status autotune(Plan* P) {
     if (!P->batched) P->lcfg.assign(P->grids[0].lev.size(), SmoothCfg{0, 0});
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(VMG_EHIP, "hipEventCreate failed");
     const int64_t cu = P->cell_updates, fs = P->finest_sweeps;
-    const int nlev = swept_levels(P);
+    const int nlev = swept_level_count(P);
     vmg_status st = VMG_OK;
     for (int l = 0; l < nlev && st == VMG_OK; ++l) {
         const std::string key = tune_key(P, l);

@@ -165,9 +165,10 @@ vmg_status build_plan(Plan* P, const vmg_grid* grids, int n_grids, const vmg_par
     return VMG_OK;
 }
 
+static void release_graphs(Plan* P);
+
 void destroy_plan(Plan* P) {
-    for (int q = 0; q < 2; ++q)
-        if (P->graph_ok[q]) (void)hipGraphExecDestroy(P->graph[q]);
+    release_graphs(P);
     for (void* a : P->allocs) (void)hipFree(a);
     if (P->host_norm) (void)hipHostFree(P->host_norm);
     if (P->own_stream) (void)hipStreamDestroy(P->own_stream);
@@ -306,6 +307,8 @@ static hipError_t norm_pass(Plan* P, GridState& G) {
 // pass is needed.  The solve runs one head, then units (tail of cycle k, head
 // of cycle k+1) until that residual meets the tolerance; the result is the
 // pre-smoothed state whose residual was measured.
+constexpr int DIVERGE_GRACE = 4;   // iterations before the 10x divergence rule applies
+
 static bool shifted_cycles(const Plan* P) {
     if (P->mixed || P->batched) return false;
     for (const auto& G : P->grids)
@@ -355,42 +358,78 @@ static hipError_t enqueue_iteration(Plan* P) {
 
 static int finest_parity(const Plan* P) { return P->batched ? batch_parity(P) : P->grids[0].lev[0].cur; }
 
+static void release_graphs(Plan* P) {
+    for (int src = 0; src < 2; ++src)
+        for (int q = 0; q < 2; ++q)
+            if (P->graph_ok[src][q]) {
+                (void)hipGraphExecDestroy(P->graph[src][q]);
+                P->graph_ok[src][q] = false;
+            }
+}
+
+// Record one iteration (enqueue_iteration) as a hipGraph for the given source
+// flag and finest-level parity.  Capture only records work, so every piece of
+// host-side state that enqueueing advances is restored afterwards; the
+// iteration's cell-update counts are kept for the replays.
+static vmg_status capture_graph(Plan* P, int src, int parity) {
+    std::vector<int> saved;
+    for (auto& G : P->grids) saved.push_back(G.lev[0].cur);
+    const int saved_b = finest_parity(P);
+    const bool saved_src = P->has_source;
+    P->has_source = src != 0;
+    if (P->batched) {
+        if (batch_parity(P) != parity) batch_flip_parity(P);
+    } else {
+        for (auto& G : P->grids) G.lev[0].cur = parity;
+    }
+    const int64_t cu = P->cell_updates, fs = P->finest_sweeps;
+    hipGraph_t graph;
+    hipError_t e0 = hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal);
+    hipError_t e = e0 == hipSuccess ? enqueue_iteration(P) : e0;
+    hipError_t e2 = e0 == hipSuccess ? hipStreamEndCapture(P->stream, &graph) : e0;
+    P->graph_updates[src][parity] = P->cell_updates - cu;
+    P->graph_finest[src][parity] = P->finest_sweeps - fs;
+    P->cell_updates = cu;
+    P->finest_sweeps = fs;
+    for (size_t gi = 0; gi < P->grids.size(); ++gi) P->grids[gi].lev[0].cur = saved[gi];
+    if (P->batched && batch_parity(P) != saved_b) batch_flip_parity(P);
+    P->has_source = saved_src;
+    if (e != hipSuccess) return fail(VMG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    CKH(e2);
+    hipError_t ei = hipGraphInstantiate(&P->graph[src][parity], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    CKH(ei);
+    P->graph_ok[src][parity] = true;
+    return VMG_OK;
+}
+
+// With VMG_GRAPH, record the iteration for both source flags and both
+// finest-level parities (so a solve replays without instantiating anything);
+// called when a plan is created and again when its schedule changes.
+vmg_status capture_graphs(Plan* P) {
+    release_graphs(P);
+    if (!(P->params.flags & VMG_GRAPH)) return VMG_OK;
+    for (int src = 0; src < 2; ++src)
+        for (int q = 0; q < 2; ++q) {
+            vmg_status st = capture_graph(P, src, q);
+            if (st != VMG_OK) return st;
+        }
+    return VMG_OK;
+}
+
 static vmg_status run_cycle(Plan* P) {
-    const bool use_graph = (P->params.flags & VMG_GRAPH) != 0;
+    const int src = P->has_source ? 1 : 0;
     const int parity = finest_parity(P);
-    if (!use_graph) {
+    if (!(P->params.flags & VMG_GRAPH) || !P->graph_ok[src][parity]) {
         CKH(enqueue_iteration(P));
         CKH(hipStreamSynchronize(P->stream));
         return VMG_OK;
     }
-    if (!P->graph_ok[parity]) {
-        // capture the cycle once for this ping-pong parity of the finest level
-        std::vector<int> saved;
-        for (auto& G : P->grids) saved.push_back(G.lev[0].cur);
-        const int saved_b = finest_parity(P);
-        const int64_t cu = P->cell_updates, fs = P->finest_sweeps;
-        hipGraph_t graph;
-        CKH(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_iteration(P);
-        hipError_t e2 = hipStreamEndCapture(P->stream, &graph);
-        if (e != hipSuccess) return fail(VMG_EHIP, std::string("capture: ") + hipGetErrorString(e));
-        CKH(e2);
-        CKH(hipGraphInstantiate(&P->graph[parity], graph, nullptr, nullptr, 0));
-        (void)hipGraphDestroy(graph);
-        P->graph_ok[parity] = true;
-        P->cycle_updates = P->cell_updates - cu;
-        P->cycle_finest = P->finest_sweeps - fs;
-        for (size_t gi = 0; gi < P->grids.size(); ++gi) P->grids[gi].lev[0].cur = saved[gi];
-        if (P->batched && batch_parity(P) != saved_b) batch_flip_parity(P);
-        P->cell_updates = cu;
-        P->finest_sweeps = fs;
-    }
-    CKH(hipGraphLaunch(P->graph[parity], P->stream));
+    CKH(hipGraphLaunch(P->graph[src][parity], P->stream));
     CKH(hipStreamSynchronize(P->stream));
-    // the captured cycle flips the finest level exactly as the eager one would
-    P->cell_updates += P->cycle_updates;
-    P->finest_sweeps += P->cycle_finest;
-    // the captured iteration leaves the finest phi in the other buffer when it
+    P->cell_updates += P->graph_updates[src][parity];
+    P->finest_sweeps += P->graph_finest[src][parity];
+    // the replayed iteration leaves the finest phi in the other buffer when it
     // did an odd number of FP64 sweeps, and always on the periodic mixed path
     // (its update pass writes phi + e to the second buffer); the batched mixed
     // path updates in place
@@ -475,6 +514,7 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
     }
     // ---- cycles ------------------------------------------------------------
     int cycles = 0;
+    std::vector<int> worse(ng, 0);   // consecutive iterations more than 10x above the best RMS
     vmg_status status = VMG_OK;
     // tau_rms is written by the heads of shifted cycles only; 0 before the first
     const double tf = P->params.tau_factor;
@@ -500,11 +540,15 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
         vmg_status st = run_cycle(P);
         if (st != VMG_OK) return st;
         ++cycles;
+        // divergence: a non-finite residual, one 1e4 times above the best so far, or
+        // three iterations in a row 10 times above it once the first few iterations
+        // (whose nonlinear start phase may raise the residual) are past
         bool bad = false;
         for (int gi = 0; gi < ng; ++gi) {
             const NormOut& no = P->host_norm[gi];
-            if (no.n_nonfinite > 0 || !std::isfinite(no.rms) || no.rms > 1e6 * std::max(best[gi], 1e-300))
-                bad = true;
+            const double b = std::max(best[gi], 1e-300);
+            worse[gi] = (cycles > DIVERGE_GRACE && no.rms > 10.0 * b) ? worse[gi] + 1 : 0;
+            if (no.n_nonfinite > 0 || !std::isfinite(no.rms) || no.rms > 1e4 * b || worse[gi] >= 3) bad = true;
             best[gi] = std::min(best[gi], no.rms);
         }
         if (bad) {
@@ -584,6 +628,7 @@ vmg_status vmg_plan_create(vmg_plan** plan, const vmg_grid* grids, int32_t n_gri
     vmg_status st = build_plan(P, grids, n_grids, p, stream);
     if (st == VMG_OK && p->tau_factor > 0.0 && !shifted_cycles(P))
         st = fail(VMG_EINVAL, "tau_factor needs a grid with a coarser level (tau^h lives on it)");
+    if (st == VMG_OK) st = capture_graphs(P);
     if (st != VMG_OK) {
         std::string msg = g_err;
         destroy_plan(P);
@@ -911,6 +956,43 @@ vmg_status vmg_smooth(vmg_plan* plan, int32_t sweeps) {
         for (auto& G : P->grids) CKH(P->mixed ? smooth_corr_level(P, G, 0) : smooth_level(P, G, 0));
     }
     return VMG_OK;
+}
+
+vmg_status vmg_plan_set_schedule(vmg_plan* plan, int32_t level, int32_t tile_y, int32_t z_chunk) {
+    g_err.clear();
+    if (!plan) return fail(VMG_EINVAL, "null plan");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    if (tile_y != 4 && tile_y != 8 && tile_y != 12 && tile_y != 16)
+        return fail(VMG_EINVAL, "tile_y must be 4, 8, 12 or 16");
+    if (z_chunk < 2 || z_chunk > 1024 || (z_chunk & 1)) return fail(VMG_EINVAL, "z_chunk must be even, in [2, 1024]");
+    if (level < 0 || level >= swept_level_count(P))
+        return fail(VMG_EINVAL, "level " + std::to_string(level) + " has no fused sweep in this plan");
+    const SmoothCfg c{tile_y, z_chunk};
+    if (level == 0) P->cfg = c;
+    if (P->batched) {
+        CKH(batch_set_level_cfg(P, level, c));
+    } else if (level > 0) {
+        if ((int)P->lcfg.size() < (int)P->grids[0].lev.size()) P->lcfg.resize(P->grids[0].lev.size(), SmoothCfg{0, 0});
+        P->lcfg[level] = c;
+    }
+    CKH(hipStreamSynchronize(P->stream));
+    return capture_graphs(P);
+}
+
+vmg_status vmg_plan_schedule(const vmg_plan* plan, int32_t level, int32_t* tile_y, int32_t* z_chunk) {
+    if (!plan) return fail(VMG_EINVAL, "null plan");
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (level < 0 || level >= swept_level_count(P))
+        return fail(VMG_EINVAL, "level " + std::to_string(level) + " has no fused sweep in this plan");
+    const SmoothCfg c = P->batched ? P->blev[level].cfg : level_schedule(P, level, P->grids[0].lev[level].g);
+    if (tile_y) *tile_y = c.ty;
+    if (z_chunk) *z_chunk = c.zc;
+    return VMG_OK;
+}
+
+int32_t vmg_plan_level_count(const vmg_plan* plan) {
+    if (!plan) return -1;
+    return swept_level_count(reinterpret_cast<const Plan*>(plan));
 }
 
 vmg_status vmg_plan_config(const vmg_plan* plan, int32_t* tile_y, int32_t* z_chunk, int32_t* nu1, int32_t* nu2,

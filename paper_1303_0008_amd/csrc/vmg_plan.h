@@ -85,10 +85,13 @@ struct Plan {
     double* partials = nullptr;
     double* partials_b = nullptr;          // second set (coarse right-hand-side pass)
     NormOut* host_norm = nullptr;          // pinned
-    hipGraphExec_t graph[2];
-    bool graph_ok[2] = {false, false};
+    // replayable iterations, one per (source given, finest-level ping-pong parity);
+    // all four are captured when the plan is created (VMG_GRAPH)
+    hipGraphExec_t graph[2][2];
+    bool graph_ok[2][2] = {{false, false}, {false, false}};
+    int64_t graph_updates[2][2] = {{0, 0}, {0, 0}};   // cell updates / finest sweeps of one replay
+    int64_t graph_finest[2][2] = {{0, 0}, {0, 0}};
     int64_t cell_updates = 0, finest_sweeps = 0;
-    int64_t cycle_updates = 0, cycle_finest = 0;
     std::vector<void*> allocs;
     // batched Dirichlet plans
     bool tuned_from_cache = false;
@@ -113,6 +116,10 @@ hipError_t mixed_prepare(Plan* P);          // per-solve set-up of the FP32 ghos
 hipError_t smooth_corr_level(Plan* P, GridState& G, int l, bool zero_in = false);
 vmg_status build_batch(Plan* P);
 vmg_status autotune(Plan* P);
+// levels of a plan that run the fused sweep (the levels a schedule applies to)
+int swept_level_count(const Plan* P);
+// (re)record the replayable iterations of a VMG_GRAPH plan (no-op without the flag)
+vmg_status capture_graphs(Plan* P);
 hipError_t smooth_level_public(Plan* P, GridState& G, int l);
 // schedule of the fused sweep on level l of a single-grid (periodic) plan
 SmoothCfg level_schedule(const Plan* P, int l, const Geom& g);

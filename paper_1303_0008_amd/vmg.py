@@ -5,7 +5,9 @@ kernels.  PyTorch supplies device memory (``Tensor.data_ptr()``) and the
 current HIP stream.  The functions mirror the C ABI in ``include/vmg.h``:
 ``plan_create``, ``solve``, ``plan_destroy``, ``last_error``,
 ``solve_periodic``, ``residual``, ``fill_ghosts``, ``fill_interior``, ``ghost_count``,
-``smooth``, ``plan_stats``; ``Plan`` wraps a plan handle.
+``smooth``, ``plan_stats``, ``plan_config``, ``plan_level_count``, ``plan_set_schedule``,
+``plan_schedule``, ``total_force``, ``mass_assign``, ``mass_assign_region``,
+``solve_levels``; ``Plan`` and ``LevelsPlan`` wrap plan handles.
 
 There is no fallback: if the library is missing or no GPU is present the
 calls raise.
@@ -62,7 +64,8 @@ EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
            "vmg_solve_periodic", "vmg_residual", "vmg_fill_ghosts", "vmg_ghost_count",
            "vmg_smooth", "vmg_plan_stats", "vmg_plan_config", "vmg_fill_interior", "vmg_total_force",
            "vmg_mass_assign", "vmg_mass_assign_workspace", "vmg_solve_levels", "vmg_levels_create",
-           "vmg_levels_solve", "vmg_levels_destroy", "vmg_mass_assign_region"]
+           "vmg_levels_solve", "vmg_levels_destroy", "vmg_mass_assign_region", "vmg_plan_level_count",
+           "vmg_plan_set_schedule", "vmg_plan_schedule"]
 
 _lib = None
 
@@ -108,8 +111,13 @@ def load():
     L.vmg_plan_stats.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
     i32p = P(ctypes.c_int32)
     L.vmg_plan_config.argtypes = [vp, i32p, i32p, i32p, i32p, i32p]
+    L.vmg_plan_level_count.argtypes = [vp]
+    L.vmg_plan_level_count.restype = ctypes.c_int32
+    L.vmg_plan_set_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.vmg_plan_schedule.argtypes = [vp, ctypes.c_int32, i32p, i32p]
     for name in EXPORTS:
-        if name not in ("vmg_last_error", "vmg_ghost_count", "vmg_mass_assign_workspace", "vmg_levels_destroy"):
+        if name not in ("vmg_last_error", "vmg_ghost_count", "vmg_mass_assign_workspace", "vmg_levels_destroy",
+                        "vmg_plan_level_count"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -380,6 +388,23 @@ def plan_config(handle):
     return dict(zip(("tile_y", "z_chunk", "nu1", "nu2", "coarse_sweeps"), (x.value for x in v)))
 
 
+def plan_level_count(handle):
+    """vmg_plan_level_count: levels of the plan that run the fused sweep."""
+    return int(load().vmg_plan_level_count(ctypes.c_void_p(handle)))
+
+
+def plan_set_schedule(handle, level, tile_y, z_chunk):
+    """vmg_plan_set_schedule: install a sweep schedule (tile height, z chunk) on one level."""
+    _check(load().vmg_plan_set_schedule(ctypes.c_void_p(handle), int(level), int(tile_y), int(z_chunk)))
+
+
+def plan_schedule(handle, level):
+    """vmg_plan_schedule: (tile_y, z_chunk) the fused sweep of a level runs."""
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().vmg_plan_schedule(ctypes.c_void_p(handle), int(level), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
 class Plan:
     """Owning wrapper of a plan handle."""
 
@@ -401,6 +426,15 @@ class Plan:
 
     def config(self):
         return plan_config(self.handle)
+
+    def level_count(self):
+        return plan_level_count(self.handle)
+
+    def set_schedule(self, level, tile_y, z_chunk):
+        plan_set_schedule(self.handle, level, tile_y, z_chunk)
+
+    def schedule(self, level):
+        return plan_schedule(self.handle, level)
 
     def close(self):
         if self.handle:

@@ -3,8 +3,9 @@ mixed precision with hipGraph-replayed V-cycles, checked at full size through
 properties the oracle evaluates cell by cell (a full oracle solve at 512^3 is
 out of reach on the CPU).
 
-* alpha = 0.2: the solve reaches the tolerance; the oracle's residual of the
-  returned phi agrees with the reported RMS and cbar; FP64 and mixed agree.
+* alpha = 0.2: the solve reaches the tolerance; the GPU's residual field of
+  the returned phi equals the oracle's cell by cell (within rounding), and its
+  RMS and cbar agree with the reported ones; FP64 and mixed agree.
 * alpha = -0.2 (about 9 % of the cells take the discriminant guard): the
   clamped system stalls under relaxation at these densities (max delta ~2200;
   the oracle's own Gauss-Seidel started from the stalled state does not lower
@@ -13,6 +14,7 @@ out of reach on the CPU).
 """
 import numpy as np
 import pytest
+from conftest import residual_fields
 
 from paper_1303_0008_amd import inputs as I
 
@@ -67,9 +69,13 @@ def test_lognormal512a_mixed(torch_cuda, V, oracle_mod):
     bound = 0.1 * (rm["rms"] + rd["rms"])
     say("  max |phi_mixed - phi_fp64| = %.3e, bound %.3e" % (np.abs(pm - pd).max(), bound))
     assert np.abs(pm - pd).max() <= bound
-    say("  oracle residual of the mixed phi")
-    _, info = oracle_mod.residual(delta, pm, w["alpha"], w["kappa"], want_field=False)
-    say("  oracle", info)
+    del pd
+    say("  residual field of the mixed phi: GPU vs oracle, cell by cell")
+    phi_t = torch.from_numpy(pm).to("cuda")
+    err, bound, dmax, rg, info = residual_fields(V, torch, oracle_mod, delta, d_t, phi_t, w["alpha"], w["kappa"])
+    del phi_t
+    say(f"  max |d_gpu - d_oracle| = {err:.2e} (bound {bound:.2e}, max |d| {dmax:.2e}); oracle {info}")
+    assert err <= bound
     assert abs(info["rms"] - rm["rms"]) <= 1e-3 * rm["rms"]
     assert abs(info["cbar"] - rm["compat_c"]) <= 1e-9 * max(1.0, abs(info["cbar"]))
     assert info["n_guarded"] == rm["n_guarded"] == 0
@@ -89,9 +95,12 @@ def test_lognormal512b_guarded_reports_stall(torch_cuda, V, oracle_mod):
     ph = phi.cpu().numpy()
     del phi
     assert np.all(np.isfinite(ph))
-    say("  oracle residual of the returned phi")
-    _, info = oracle_mod.residual(delta, ph, w["alpha"], w["kappa"], want_field=False)
-    say("  oracle", info)
+    say("  residual field of the returned phi: GPU vs oracle, cell by cell")
+    phi_t = torch.from_numpy(ph).to("cuda")
+    err, bound, dmax, rg, info = residual_fields(V, torch, oracle_mod, delta, d_t, phi_t, w["alpha"], w["kappa"])
+    del phi_t
+    say(f"  max |d_gpu - d_oracle| = {err:.2e} (bound {bound:.2e}, max |d| {dmax:.2e}); oracle {info}")
+    assert err <= bound
     assert abs(info["rms"] - r["rms"]) <= 1e-3 * r["rms"]
     assert abs(info["cbar"] - r["compat_c"]) <= 1e-9 * max(1.0, abs(info["cbar"]))
     assert abs(info["n_guarded"] - r["n_guarded"]) <= 1e-4 * r["n_guarded"]
