@@ -303,6 +303,21 @@ vmg_status vmg_mass_assign_region(const double *pos, int64_t n_particles, const 
                                   const double corner[3], double mean_count, int32_t scheme, void *workspace,
                                   int64_t workspace_bytes, double *delta, hipStream_t stream);
 
+/* Allocation-free variant of vmg_mass_assign, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same computation, arguments and result
+ * as vmg_mass_assign, with the workspace taken from a static device array of
+ * the library (64 MiB, held by every GPU the library runs on until the process
+ * ends) instead of a caller workspace.  It calls no allocating routine.  Calls
+ * on one GPU share that array: calls that overlap in time on one GPU (on
+ * different streams, or from different threads) race and must be ordered by
+ * the caller; each call rewrites every part of the array it reads.  Errors:
+ * VMG_EINVAL (as vmg_mass_assign, and a call whose workspace,
+ * vmg_mass_assign_workspace(n_particles, n), exceeds 64 MiB: e.g. a 128^3 grid
+ * with more than about 4.8 M particles), VMG_EHIP. */
+vmg_status vmg_mass_assign_noalloc(const double *pos, int64_t n_particles, const int32_t n[3], int32_t scheme,
+                                   double *delta, hipStream_t stream);
+
 /* Workspace bytes vmg_mass_assign needs (about 8 bytes per particle plus 12
  * per grid cell), or -1 for arguments vmg_mass_assign rejects. */
 int64_t vmg_mass_assign_workspace(int64_t n_particles, const int32_t n[3]);

@@ -919,6 +919,27 @@ vmg_status vmg_mass_assign(const double* pos, int64_t n_particles, const int32_t
     return VMG_OK;
 }
 
+vmg_status vmg_mass_assign_noalloc(const double* pos, int64_t n_particles, const int32_t n[3], int32_t scheme,
+                                   double* delta, hipStream_t stream) {
+    g_err.clear();
+    if (!pos || !n || !delta) return fail(VMG_EINVAL, "null argument");
+    if (n_particles < 1 || n_particles > INT32_MAX)
+        return fail(VMG_EINVAL, "mass assignment needs 1 <= n_particles <= 2^31 - 1");
+    if (!assign_args_ok(n_particles, n)) return fail(VMG_EINVAL, "mass assignment needs n >= 1 per axis");
+    if (scheme != VMG_ASSIGN_CIC && scheme != VMG_ASSIGN_TSC) return fail(VMG_EINVAL, "unknown assignment scheme");
+    const int64_t need = mass_assign_workspace(n_particles, n[0], n[1], n[2]);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(VMG_EINVAL, "vmg_mass_assign_noalloc: the workspace this call needs (" + std::to_string(need) +
+                                    " bytes) exceeds the static scratch of " +
+                                    std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes");
+    void* work = nullptr;
+    CKH(noalloc_scratch(&work));
+    const double mean_count = (double)n_particles / ((double)n[0] * n[1] * n[2]);
+    CKH(launch_mass_assign(pos, n_particles, n[0], n[1], n[2], scheme, true, 0.0, nullptr, mean_count, work, delta,
+                           stream));
+    return VMG_OK;
+}
+
 vmg_status vmg_mass_assign_region(const double* pos, int64_t n_particles, const int32_t n[3], double h,
                                   const double corner[3], double mean_count, int32_t scheme, void* workspace,
                                   int64_t workspace_bytes, double* delta, hipStream_t stream) {

@@ -27,6 +27,8 @@
 // Masses are 64-bit fixed point (2^-40 of a particle per unit): every
 // contribution is rounded once and all sums are integer, so the result does
 // not depend on the order of particles or of atomics.
+#include <mutex>
+
 #include "device_common.h"
 #include "vmg_internal.h"
 
@@ -474,6 +476,35 @@ int64_t mass_assign_workspace(int64_t np, int n0, int n1, int n2) {
     return 2 * align256(nc * 4) + align256((nc + 1) * 4) + align256((nc + SCAN_TILE - 1) / SCAN_TILE * 4) +
            2 * align256(np * 4) + align256(mass_assign_bricks(n0, n1, n2) * REGN * 8) +
            align256(mass_assign_bricks(n0, n1, n2) * 4);
+}
+
+// Workspace of the allocation-free mass assignment: a file-scope device array
+// that every GPU the library runs on holds until the process ends.  Host code
+// must not use the array's name as an address (it is a host-side stand-in);
+// noalloc_scratch() returns the device address, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(void** ptr) {
+    *ptr = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0) return hipErrorInvalidValue;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int n2, int scheme, bool periodic,

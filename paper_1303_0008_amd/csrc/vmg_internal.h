@@ -189,6 +189,12 @@ hipError_t launch_interior_fill(const double* parent, int np0, int np1, int np2,
 // work: mass_assign_workspace(np, n0, n1, n2) bytes, 256-byte aligned.
 int64_t mass_assign_bricks(int n0, int n1, int n2);
 int64_t mass_assign_workspace(int64_t np, int n0, int n1, int n2);
+// The allocation-free variant's workspace: a static device array of
+// NOALLOC_SCRATCH_BYTES per GPU; noalloc_scratch() gives the current device's
+// address (looked up with hipGetSymbolAddress on a device's first call).
+constexpr int64_t NOALLOC_SCRATCH_BYTES = int64_t(64) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+hipError_t noalloc_scratch(void** ptr);
 // periodic: the whole box (h, corner unused); else a region of cells of size h
 // whose cell (0,0,0) corner is at corner[3].  delta = mass / mean_count - 1.
 hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int n2, int scheme, bool periodic,

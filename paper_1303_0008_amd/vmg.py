@@ -65,7 +65,7 @@ EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
            "vmg_smooth", "vmg_plan_stats", "vmg_plan_config", "vmg_fill_interior", "vmg_total_force",
            "vmg_mass_assign", "vmg_mass_assign_workspace", "vmg_solve_levels", "vmg_levels_create",
            "vmg_levels_solve", "vmg_levels_destroy", "vmg_mass_assign_region", "vmg_plan_level_count",
-           "vmg_plan_set_schedule", "vmg_plan_schedule"]
+           "vmg_plan_set_schedule", "vmg_plan_schedule", "vmg_mass_assign_noalloc"]
 
 _lib = None
 
@@ -99,6 +99,7 @@ def load():
     L.vmg_mass_assign.argtypes = [vp, ctypes.c_int64, P(ctypes.c_int32), ctypes.c_int32, vp, ctypes.c_int64, vp,
                                   vp]
     L.vmg_mass_assign_workspace.argtypes = [ctypes.c_int64, P(ctypes.c_int32)]
+    L.vmg_mass_assign_noalloc.argtypes = [vp, ctypes.c_int64, P(ctypes.c_int32), ctypes.c_int32, vp, vp]
     L.vmg_mass_assign_region.argtypes = [vp, ctypes.c_int64, P(ctypes.c_int32), ctypes.c_double,
                                          P(ctypes.c_double), ctypes.c_double, ctypes.c_int32, vp, ctypes.c_int64,
                                          vp, vp]
@@ -344,6 +345,16 @@ def mass_assign(pos, n, scheme=ASSIGN_TSC, delta=None, workspace=None, stream=No
     c = (ctypes.c_int32 * 3)(*nn)
     _check(load().vmg_mass_assign(_ptr(pos), npart, c, int(scheme), ctypes.c_void_p(workspace.data_ptr()),
                                   workspace.numel(), _ptr(delta), _stream(stream)))
+    return delta
+
+
+def mass_assign_noalloc(pos, n, delta, scheme=ASSIGN_TSC, stream=None):
+    """vmg_mass_assign_noalloc: mass_assign with the library's static workspace
+    (allocates nothing; ``delta`` (n2, n1, n0) float64 must be given)."""
+    nn = (n,) * 3 if isinstance(n, int) else tuple(int(v) for v in n)
+    npart = int(pos.shape[0]) if pos.dim() else 0
+    _check(load().vmg_mass_assign_noalloc(_ptr(pos), npart, (ctypes.c_int32 * 3)(*nn), int(scheme), _ptr(delta),
+                                          _stream(stream)))
     return delta
 
 
