@@ -17,10 +17,19 @@
 //   K::Cell                 what a cell holds in LDS (double phi, or float2 (e, phi~))
 //   K::Src                  per-cell sources of the update (delta and f, or t0 and r)
 //   K::AHEAD                plane steps the loads run ahead of their use (1 or 2)
-//   k.cell(i), k.src(i)     the input state / sources at storage index i
-//   k.zero_cell(), k.zero_src()
+//   K::EB                   bytes of one element of the policy's arrays
+//   k.in_plane(zo, ok), k.src_plane(zo, ok), k.out_plane(zo, ok)
+//                           buffer resources of the input state / sources / output
+//                           for the plane starting at element zo (ok false: all
+//                           accesses out of range, i.e. zero)
+//   k.cell_b(P, bo), k.src_b(S, bo)   the input state / sources at byte offset bo
+//                           of a plane (out of range: zero)
 //   k.template update<W>(Pm, Pc, Pp, c, o, src)   updated cell from its neighbourhood
-//   k.out(i, cell)          write the output state at storage index i
+//   k.out_b(O, bo, cell)    write the output state at byte offset bo (out of range:
+//                           dropped)
+// Every global load and store is issued by every lane (masked cells use an
+// out-of-range offset), so the loads in flight for later steps are never
+// waited for early.
 #pragma once
 
 #include <type_traits>
@@ -29,15 +38,29 @@
 
 namespace vmg {
 
-// Threads per block of the fused sweep.  Wider blocks measured slower: each
-// plane step ends in two block-wide barriers.
+// Threads per block of the fused sweep.
 constexpr int SNT = 256;
 
-// LDS of a sweep block of tile height TY (8-byte cells: three ring-2 planes of
-// u^0 and three ring-1 planes of u^1), and the waves per SIMD its kernels are
-// built for: as many blocks per CU as that LDS allows (160 KB per CU), at most
-// 4, so that the register budget matches the occupancy the LDS permits.
-constexpr int sweep_lds_bytes(int ty) { return 3 * ((TX + 4) * (ty + 4) + (TX + 2) * (ty + 2)) * 8; }
+// Pipeline shape.  With SWEEP_DEFER the black phase of a step works two planes
+// behind its red phase instead of one, so the two phases of a step touch
+// disjoint LDS planes and run without a barrier between them (one barrier per
+// step, and red and black updates of a thread are independent work); the
+// plane rings then hold four planes instead of three.
+#ifndef VMG_SWEEP_DEFER
+#define VMG_SWEEP_DEFER 1
+#endif
+constexpr bool SWEEP_DEFER = VMG_SWEEP_DEFER != 0;
+constexpr int SWEEP_SLOTS = SWEEP_DEFER ? 4 : 3;   // planes per LDS ring
+constexpr int SWEEP_LAG = SWEEP_DEFER ? 3 : 2;     // step t: red on plane t-1, black on plane t-LAG
+
+// LDS of a sweep block of tile height TY (8-byte cells: SWEEP_SLOTS ring-2
+// planes of u^0 and as many ring-1 planes of u^1), and the waves per SIMD its
+// kernels are built for: as many blocks per CU as that LDS allows (160 KB per
+// CU), at most 4, so that the register budget matches the occupancy the LDS
+// permits.
+constexpr int sweep_lds_bytes(int ty) {
+    return SWEEP_SLOTS * ((TX + 4) * (ty + 4) + (TX + 2) * (ty + 2)) * 8;
+}
 constexpr int sweep_waves(int ty) {
     return (160 * 1024) / sweep_lds_bytes(ty) >= 4 ? 4 : ((160 * 1024) / sweep_lds_bytes(ty) < 1 ? 1 : (160 * 1024) / sweep_lds_bytes(ty));
 }
@@ -79,33 +102,36 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     constexpr int S2 = H2 * W2, S1 = H1 * W1;     // cells per plane
     // Rows are stored split by x parity: cell (Y, X) lives at Y*W + (X&1)*W/2 + (X>>1),
     // so lanes working on every other cell of a row touch consecutive words.
-    __shared__ Cell P0[3 * S2];  // u^0, ring 2, slot = z mod 3
-    __shared__ Cell P1[3 * S1];  // u^1 (red computed, black copied), ring 1
+    constexpr int NSL = SWEEP_SLOTS, LAG = SWEEP_LAG;
+    __shared__ Cell P0[NSL * S2];  // u^0, ring 2, slot = z mod NSL
+    __shared__ Cell P1[NSL * S1];  // u^1 (red computed, black copied), ring 1
 
     const int tid = threadIdx.x;
     if (z0 >= g.n2) return;
+    constexpr int EB = K::EB;
+    // in-plane offsets are taken from the grid's own storage start (a pooled
+    // batch adds g.base to the plane resources instead)
+    const int64_t loff0 = g.off0 - g.base;
 
     // ---- per-thread constants (everything that does not depend on z) -------
-    int off2[NL2], lds2[NL2];
-    bool ok2[NL2];
+    int ob2[NL2], lds2[NL2];   // byte offset in a plane of u^0 (out of range: zero), LDS word
 #pragma unroll
     for (int s = 0; s < NL2; ++s) {
         const int e = tid + s * NTH;
-        ok2[s] = false;
-        off2[s] = 0;
+        ob2[s] = BUF_OOB;
         lds2[s] = 0;
         if (e < NP2) {
             const int X = e % W2, Y = e / W2;
             lds2[s] = Y * W2 + (X & 1) * HW2 + (X >> 1);
             int gx = x0 - 2 + X, gy = y0 - 2 + Y;
+            bool ok = true;
             if (DIR) {
-                ok2[s] = gx >= -1 && gx <= g.n0 && gy >= -1 && gy <= g.n1;
+                ok = gx >= -1 && gx <= g.n0 && gy >= -1 && gy <= g.n1;
             } else {
                 gx = wrapi(gx, g.n0);
                 gy = wrapi(gy, g.n1);
-                ok2[s] = true;
             }
-            off2[s] = (int)(g.off0 + gx + (int64_t)gy * g.sy);
+            if (ok) ob2[s] = (int)(loff0 + gx + (int64_t)gy * g.sy) * EB;
         }
     }
     // The loop below is unrolled twice, so step t = z0 + 2k + b works on planes
@@ -123,6 +149,7 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
                               // the P0 cell of step b's black partner (copied into P1)
     int rw[NR][2];            // P1 cell of step b's red cell; rw[q][1-b] holds its black partner
     int rg[NR][2];            // global in-plane index of the red cell (-1: not a cell)
+    int rgb[NR][2];           // its byte offset in a source plane (out of range: not a cell)
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         const int e = tid + q * NTH;
@@ -144,12 +171,13 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
             int gx = x0 - 1 + 2 * m + par, wy = gy;
             if (DIR) {
                 rg[q][b] = (rv[q] && gx >= 0 && gx < g.n0 && gy >= 0 && gy < g.n1)
-                               ? (int)(g.off0 + gx + (int64_t)gy * g.sy) : -1;
+                               ? (int)(loff0 + gx + (int64_t)gy * g.sy) : -1;
             } else {
                 gx = wrapi(gx, g.n0);
                 wy = wrapi(gy, g.n1);
                 rg[q][b] = rv[q] ? (int)(gx + (int64_t)wy * g.sy) : -1;
             }
+            rgb[q][b] = rg[q][b] >= 0 ? rg[q][b] * EB : BUF_OOB;
         }
     }
     // black cells: interior row r, pair m; black at column 2m + ((y0 + r + p2 + 1) & 1).
@@ -158,62 +186,67 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     constexpr int BOFF = NTH > BH * TY ? ((NTH - BH * TY) / 64) * 64 : 0;
     const int tb = tid - BOFF;
     int bc[NB][2], bo[NB][2];   // nb_split offsets in P1, per b; bo[q][1-b] is the red partner
-    int bcell[NB][2];           // in-plane global index of the black cell; [1-b]: its red partner
+    int bcb[NB][2];             // byte offset of the black cell in a plane ([1-b]: its red
+                                // partner); out of range when that cell is not in the grid
     bool bin[NB][2];            // that cell lies inside the grid
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int e = tb + q * NTH;
-        const int r = e >= 0 ? e / BH : 0, m = e >= 0 ? e - r * BH : 0;
+        const bool slot = e >= 0 && e < BH * TY;                  // a black cell of the tile
+        const int r = slot ? e / BH : 0, m = slot ? e - r * BH : 0;   // (0, 0) keeps LDS reads in range
         const int gy = y0 + r;
-        const bool bv = e >= 0 && e < BH * TY && gy < g.n1;
-        const int row = (int)(g.off0 + (int64_t)gy * g.sy) + x0 + 2 * m;
+        const bool bv = slot && gy < g.n1;
+        const int row = (int)(loff0 + (int64_t)gy * g.sy) + x0 + 2 * m;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const int par = (y0 + r + zpar + b + 1) & 1;
             const int Y = r + 1;                                   // ring-1 row
             bc[q][b] = Y * W1 + par * HW1 + m;                     // x-1 of the black cell (X = 2m+par+1)
             bo[q][b] = Y * W1 + (1 - par) * HW1 + m + par;         // the black cell itself
-            bcell[q][b] = row + par;
             bin[q][b] = bv && 2 * m + par < g.n0 - x0;
+            bcb[q][b] = bin[q][b] ? (row + par) * EB : BUF_OOB;
         }
     }
+    // element offset of plane t of the grid (storage start included) and whether it
+    // exists (Dirichlet: the ghost planes -1 and n2 do; periodic planes wrap)
     auto plane_off = [&](int t, bool& zok) -> int64_t {
         int gz;
         if (DIR) { gz = t; zok = t >= -1 && t <= g.n2; }
         else { gz = t < 0 ? t + g.n2 : (t >= g.n2 ? t - g.n2 : t); zok = true; }
-        return (int64_t)gz * g.sz;
+        return g.base + (int64_t)gz * g.sz;
     };
-    auto load_plane = [&](int t, Cell (&r)[NL2]) {
+    // `use` false (uniform): the accesses are still issued but read zero, so every
+    // step issues the same memory instructions whether or not its planes exist
+    auto load_plane = [&](int t, bool use, Cell (&r)[NL2]) {
         bool zok;
         const int64_t zo = plane_off(t, zok);
+        const auto P = k.in_plane(use ? zo : g.base, zok && use);
 #pragma unroll
-        for (int s = 0; s < NL2; ++s) r[s] = (ok2[s] && zok) ? k.cell(zo + off2[s]) : k.zero_cell();
+        for (int s = 0; s < NL2; ++s) r[s] = k.cell_b(P, ob2[s]);
     };
     auto store_plane = [&](int sl, const Cell (&r)[NL2]) {
 #pragma unroll
         for (int s = 0; s < NL2; ++s)
             if (tid + s * NTH < NP2) P0[sl * S2 + lds2[s]] = r[s];
     };
-    auto slot = [](int z) { return (z + 3) % 3; };   // z >= -2
+    auto slot = [](int z) { return (z + 3 * NSL) % NSL; };   // z >= -3 NSL
 
     // sources of the red cells of plane p, whose parity is that of step b's red plane
-    auto fetch_red = [&](int p, auto btag, Src (&sr)[NR]) {
+    auto fetch_red = [&](int p, bool use, auto btag, Src (&sr)[NR]) {
         constexpr int b = decltype(btag)::value;
         bool zok;
-        int64_t zo = plane_off(p, zok);
+        const int64_t zo = plane_off(p, zok);
         if (DIR) zok = p >= 0 && p < g.n2;
+        const auto S = k.src_plane(use ? zo : g.base, zok && use);
 #pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            const int gi = rg[q][b];
-            sr[q] = (zok && gi >= 0) ? k.src(zo + gi) : k.zero_src();
-        }
+        for (int q = 0; q < NR; ++q) sr[q] = k.src_b(S, rgb[q][b]);
     };
     // sources of the black cells of plane p2, whose parity is that of step b's black plane
-    auto fetch_black = [&](int p2, auto btag, Src (&sr)[NB]) {
+    auto fetch_black = [&](int p2, bool use, auto btag, Src (&sr)[NB]) {
         constexpr int b = decltype(btag)::value;
-        const int64_t zo = (int64_t)p2 * g.sz;
+        const auto S = k.src_plane(use ? g.base + (int64_t)p2 * g.sz : g.base, use);
 #pragma unroll
-        for (int q = 0; q < NB; ++q) sr[q] = bin[q][b] ? k.src(zo + bcell[q][b]) : k.zero_src();
+        for (int q = 0; q < NB; ++q) sr[q] = k.src_b(S, bcb[q][b]);
     };
     using B0 = std::integral_constant<int, 0>;
     using B1 = std::integral_constant<int, 1>;
@@ -242,26 +275,33 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
         const Cell* Rm = P1 + slot(p2 - 1) * S1;
         const Cell* Rc = P1 + slot(p2) * S1;
         const Cell* Rp = P1 + slot(p2 + 1) * S1;
-        const int64_t zo = (int64_t)p2 * g.sz;
+        const auto O = k.out_plane(g.base + (int64_t)p2 * g.sz, true);
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            if (bin[q][b])
-                k.out(zo + bcell[q][b], k.template update<W1>(Rm, Rc, Rp, bc[q][b], bo[q][b], sr[q]));
-            if (bin[q][1 - b]) k.out(zo + bcell[q][1 - b], Rc[bo[q][1 - b]]);
+            Cell v = Rc[bo[q][b]];
+            if (bin[q][b]) v = k.template update<W1>(Rm, Rc, Rp, bc[q][b], bo[q][b], sr[q]);
+            k.out_b(O, bcb[q][b], v);
+            k.out_b(O, bcb[q][1 - b], Rc[bo[q][1 - b]]);
         }
     };
 
     // Software pipeline over z.  Step t computes red on plane t-1 (u^0 planes
-    // t-2..t in LDS) and black on plane t-2 (u^1 planes t-3..t-1 in LDS).  The
-    // loop body is unrolled twice, so parity-dependent offsets and buffer
-    // indices are compile-time selections.  K::AHEAD sets how far loads run
-    // ahead of their use:
+    // t-2..t in LDS) and black on plane t-LAG (u^1 planes t-LAG-1..t-LAG+1 in
+    // LDS).  LAG = 2: the black phase reads the red phase's plane, so a barrier
+    // separates them; LAG = 3: the phases touch disjoint planes of the four-plane
+    // rings and a step has one barrier.  The loop body is unrolled twice, so
+    // parity-dependent offsets and buffer indices are compile-time selections.
+    // K::AHEAD sets how far loads run ahead of their use:
     //   2: the u^0 plane t+2 is issued at the start of step t and committed to
     //      LDS at the end of step t+1; sources are issued two steps before use
     //      (register buffers alternate with the step's parity);
     //   1: the u^0 plane t+1 is issued at the start of step t and committed at
-    //      its end; the next plane's sources are issued right after the phase
+    //      its end; the next step's sources are issued right after the phase
     //      that consumed the buffer (half the registers).
+    // The steps without a black plane (the first LAG) and, with LAG = 3, the last
+    // step (no red plane) are peeled off, so the loop body issues the same loads
+    // and stores every step (loads of planes past the chunk read zero through an
+    // empty resource).
     static_assert(K::AHEAD == 1 || K::AHEAD == 2, "pipeline depth 1 or 2");
     constexpr int NBUF = K::AHEAD;
     Cell pq[NBUF][NL2];     // u^0 planes in flight
@@ -270,50 +310,78 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     {
         Cell r2[NL2];
         for (int t = z0 - 2; t <= z0; ++t) {
-            load_plane(t, r2);
+            load_plane(t, true, r2);
             store_plane(slot(t), r2);
         }
         if (K::AHEAD == 2) {
-            load_plane(z0 + 1, pq[NBUF - 1]);
-            fetch_red(z0, B1(), rq[NBUF - 1]);   // red plane of step z0 + 1
+            load_plane(z0 + 1, true, pq[NBUF - 1]);
+            fetch_red(z0, true, B1(), rq[NBUF - 1]);   // red plane of step z0 + 1
         }
-        fetch_red(z0 - 1, B0(), rq[0]);          // red plane of step z0
+        fetch_red(z0 - 1, true, B0(), rq[0]);          // red plane of step z0
     }
     __syncthreads();
 
-    auto step = [&](const int t, auto parity_tag) {
+    // parity class (for the black offsets) of black plane pl: (pl - z0) & 1
+    auto step = [&](const int t, auto parity_tag, auto red_tag, auto black_tag) {
         constexpr int b = decltype(parity_tag)::value;
-        using BN = std::integral_constant<int, 1 - b>;   // parity of step t+1
-        constexpr int cur = K::AHEAD == 2 ? b : 0;        // buffers used by this step
-        const int p = t - 1, p2 = t - 2;
-        if (K::AHEAD == 2) {
-            if (t + 2 <= z1 + 1) load_plane(t + 2, pq[cur]);
-        } else {
-            if (t + 1 <= z1 + 1) load_plane(t + 1, pq[0]);
+        constexpr bool RED = decltype(red_tag)::value;      // a red plane (t - 1 <= z1)
+        constexpr bool BLACK = decltype(black_tag)::value;  // a black plane (t - LAG >= z0)
+        using BN = std::integral_constant<int, 1 - b>;       // parity of step t+1
+        // black offsets of plane t - LAG: class b for LAG = 2, 1 - b for LAG = 3
+        using BB = std::integral_constant<int, LAG == 2 ? b : 1 - b>;
+        constexpr int cur = K::AHEAD == 2 ? b : 0;            // buffers used by this step
+        const int p = t - 1, pb = t - LAG;
+        if (RED) {
+            if (K::AHEAD == 2)
+                load_plane(t + 2, t + 2 <= z1 + 1, pq[cur]);
+            else
+                load_plane(t + 1, t + 1 <= z1 + 1, pq[0]);
+            red_phase(p, parity_tag, rq[cur]);
+            if (K::AHEAD == 2)
+                fetch_red(t + 1, t + 1 <= z1, parity_tag, rq[cur]);   // plane t+1 has the parity of t-1
+            else
+                fetch_red(t, t <= z1, BN(), rq[0]);                   // red plane of step t+1
         }
-        red_phase(p, parity_tag, rq[cur]);
-        if (K::AHEAD == 2) {
-            if (t + 1 <= z1) fetch_red(t + 1, parity_tag, rq[cur]);   // plane t+1 has the parity of t-1
-        } else {
-            if (t <= z1) fetch_red(t, BN(), rq[0]);                  // red plane of step t+1
+        if (LAG == 2) __syncthreads();
+        if (BLACK) black_phase(pb, BB(), bq[cur]);
+        if (RED) {
+            // sources of the black plane of step t + AHEAD (plane t + AHEAD - LAG)
+            const int pn = t + K::AHEAD - LAG;
+            using BNX = std::integral_constant<int, ((K::AHEAD - LAG) & 1) ? 1 - b : b>;
+            fetch_black(pn, pn >= z0 && pn < z1, BNX(), bq[cur]);
+            // commit u^0 plane t+1 (its slot is read by no phase of this step; past
+            // the chunk's last red step the slot is never read again)
+            store_plane(slot(t + 1), pq[K::AHEAD == 2 ? (b ^ 1) : 0]);
         }
-        __syncthreads();
-        if (p2 >= z0) black_phase(p2, parity_tag, bq[cur]);
-        if (K::AHEAD == 2) {
-            if (t >= z0 && t < z1) fetch_black(t, parity_tag, bq[cur]);   // plane t has the parity of t-2
-        } else {
-            if (t - 1 >= z0 && t - 1 < z1) fetch_black(t - 1, BN(), bq[0]);   // black plane of step t+1
-        }
-        // ---- commit u^0 plane t+1 (its slot held plane t-2, last read by this red phase)
-        if (t + 1 <= z1 + 1) store_plane(slot(t + 1), pq[K::AHEAD == 2 ? (b ^ 1) : 0]);
         __syncthreads();
     };
-    int t = z0;
-    for (; t + 1 <= z1 + 1; t += 2) {
-        step(t, B0());
-        step(t + 1, B1());
+    using Yes = std::true_type;
+    using No = std::false_type;
+    step(z0, B0(), Yes(), No());
+    step(z0 + 1, B1(), Yes(), No());
+    int t = z0 + 2;
+    if (LAG == 2) {
+        for (; t + 1 <= z1 + 1; t += 2) {
+            step(t, B0(), Yes(), Yes());
+            step(t + 1, B1(), Yes(), Yes());
+        }
+        if (t <= z1 + 1) step(t, B0(), Yes(), Yes());
+    } else {
+        step(t, B0(), Yes(), No());
+        for (t = z0 + 3; t + 1 <= z1 + 1; t += 2) {
+            step(t, B1(), Yes(), Yes());
+            step(t + 1, B0(), Yes(), Yes());
+        }
+        if (t <= z1 + 1) {
+            step(t, B1(), Yes(), Yes());
+            ++t;
+        }
+        // last step: black on plane z1 - 1 only
+        if (((t - z0) & 1) == 0)
+            step(t, B0(), No(), Yes());
+        else
+            step(t, B1(), No(), Yes());
     }
-    if (t <= z1 + 1) step(t, B0());
 }
 
 }  // namespace vmg

@@ -13,6 +13,43 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 }
 
 
+// ---------------------------------------------------------------------------
+// Raw buffer access (gfx9 buffer resource).  A load whose byte offset is at or
+// beyond the resource's record count returns 0 and such a store is dropped, so
+// tile edges and masked cells need no branch around the memory instruction:
+// every lane issues every load and store, and the compiler can count the
+// outstanding memory operations exactly (a branch around a load makes it wait
+// for all of them, which would stall a software pipeline on its own
+// prefetches).  A resource covers one z plane of an array: its base is the
+// plane's first element and in-plane offsets stay 32-bit.
+// ---------------------------------------------------------------------------
+constexpr int BUF_RECORDS = 0x7FFFFFF0;    // bytes a plane resource covers
+constexpr int BUF_OOB = 0x7FFFFFF8;        // byte offset of a masked access (out of range)
+constexpr int BUF_WORD3 = 0x00020000;      // gfx9 resource word 3: 32-bit data format, raw access
+
+// resource for the array element at index `elem` (may be negative: the
+// plane's in-plane offsets bring the address back into the array) of an array
+// of `eb`-byte elements; `ok` false makes every access through it out of range
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int64_t elem, int eb, bool ok) {
+    const uintptr_t a = reinterpret_cast<uintptr_t>(base) + (uintptr_t)(elem * eb);
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(a), (short)0, ok ? BUF_RECORDS : 0, BUF_WORD3);
+}
+
+typedef unsigned int vmg_u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ double buf_ld_f64(__amdgpu_buffer_rsrc_t r, int bo) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, bo, 0, 0));
+}
+__device__ __forceinline__ float buf_ld_f32(__amdgpu_buffer_rsrc_t r, int bo) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, bo, 0, 0));
+}
+__device__ __forceinline__ void buf_st_f64(__amdgpu_buffer_rsrc_t r, int bo, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(vmg_u32x2, v), r, bo, 0, 0);
+}
+__device__ __forceinline__ void buf_st_f32(__amdgpu_buffer_rsrc_t r, int bo, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, bo, 0, 0);
+}
+
 // 18 stencil neighbours of a cell (the centre is not needed by the root).
 template <typename T>
 struct NbT {

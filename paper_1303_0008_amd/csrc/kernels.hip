@@ -57,15 +57,29 @@ struct SmoothK {
         h2_6 = h2 * (1.0 / 6.0);
         cb_6 = periodic ? h2_6 * a.sc->cbar : 0.0;
     }
-    __device__ double cell(int64_t i) const { return pin[i]; }
-    __device__ double zero_cell() const { return 0.0; }
-    __device__ Src src(int64_t i) const {
+    static constexpr int EB = 8;
+    struct InPlane {
+        __amdgpu_buffer_rsrc_t u;
+    };
+    struct SrcPlane {
+        __amdgpu_buffer_rsrc_t d, f;
+    };
+    struct OutPlane {
+        __amdgpu_buffer_rsrc_t u;
+    };
+    __device__ InPlane in_plane(int64_t zo, bool ok) const { return InPlane{plane_rsrc(pin, zo, EB, ok)}; }
+    __device__ SrcPlane src_plane(int64_t zo, bool ok) const {
+        return SrcPlane{plane_rsrc(delta, zo, EB, ok), plane_rsrc(HAS_F ? f : delta, zo, EB, ok && HAS_F)};
+    }
+    __device__ OutPlane out_plane(int64_t zo, bool ok) const { return OutPlane{plane_rsrc(pout, zo, EB, ok)}; }
+    __device__ double cell_b(const InPlane& P, int bo) const { return buf_ld_f64(P.u, bo); }
+    __device__ Src src_b(const SrcPlane& S, int bo) const {
         Src s;
-        s.dl = delta[i];
-        s.f = HAS_F ? f[i] : 0.0;
+        s.dl = buf_ld_f64(S.d, bo);
+        s.f = HAS_F ? buf_ld_f64(S.f, bo) : 0.0;
         return s;
     }
-    __device__ Src zero_src() const { return Src{0.0, 0.0}; }
+    __device__ void out_b(const OutPlane& O, int bo, double v) const { buf_st_f64(O.u, bo, v); }
     template <int W>
     __device__ double update(const double* Pm, const double* Pc, const double* Pp, int co, int o,
                              const Src& s) const {
@@ -78,7 +92,6 @@ struct SmoothK {
         const double base = HAS_F ? fma(-h2_6, s.f, cb_6) : cb_6;
         return fma(S, 1.0 / 6.0, fma(-h2_6, Q, base));
     }
-    __device__ void out(int64_t i, double v) const { pout[i] = v; }
 };
 
 template <int TY, int DIR, bool HAS_F>

@@ -60,10 +60,29 @@ struct CorrK {
         h2_6 = c.h2 * (1.0f / 6.0f);
         cb_6 = periodic ? h2_6 * (float)a.sc->cbar : 0.0f;
     }
-    __device__ float2 cell(int64_t i) const { return make_float2(ZERO_E ? 0.0f : ein[i], pt[i]); }
-    __device__ float2 zero_cell() const { return make_float2(0.0f, 0.0f); }
-    __device__ Src src(int64_t i) const { return Src{t0[i], r[i]}; }
-    __device__ Src zero_src() const { return Src{1.0f, 0.0f}; }
+    static constexpr int EB = 4;
+    struct InPlane {
+        __amdgpu_buffer_rsrc_t e, p;
+    };
+    struct SrcPlane {
+        __amdgpu_buffer_rsrc_t t, r;
+    };
+    struct OutPlane {
+        __amdgpu_buffer_rsrc_t e;
+    };
+    __device__ InPlane in_plane(int64_t zo, bool ok) const {
+        return InPlane{plane_rsrc(ZERO_E ? pt : ein, zo, EB, ok && !ZERO_E), plane_rsrc(pt, zo, EB, ok)};
+    }
+    __device__ SrcPlane src_plane(int64_t zo, bool ok) const {
+        return SrcPlane{plane_rsrc(t0, zo, EB, ok), plane_rsrc(r, zo, EB, ok)};
+    }
+    __device__ OutPlane out_plane(int64_t zo, bool ok) const { return OutPlane{plane_rsrc(eout, zo, EB, ok)}; }
+    __device__ float2 cell_b(const InPlane& P, int bo) const {
+        return make_float2(ZERO_E ? 0.0f : buf_ld_f32(P.e, bo), buf_ld_f32(P.p, bo));
+    }
+    // a cell outside the grid reads t0 = 0 and r = 0; no update is formed from it
+    __device__ Src src_b(const SrcPlane& S, int bo) const { return Src{buf_ld_f32(S.t, bo), buf_ld_f32(S.r, bo)}; }
+    __device__ void out_b(const OutPlane& O, int bo, float2 v) const { buf_st_f32(O.e, bo, v.x); }
     template <int W>
     __device__ float2 update(const float2* Pm, const float2* Pc, const float2* Pp, int co, int o,
                              const Src& s) const {
@@ -82,7 +101,6 @@ struct CorrK {
         // (Se - h^2 (dQ + r - cbar)) / 6
         return make_float2(fmaf(Se, 1.0f / 6.0f, fmaf(-h2_6, dQ, fmaf(-h2_6, s.r, cb_6))), Pc[o].y);
     }
-    __device__ void out(int64_t i, float2 v) const { eout[i] = v.x; }
 };
 
 template <int TY, int DIR, bool ZERO_E>
