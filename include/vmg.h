@@ -342,11 +342,54 @@ vmg_status vmg_plan_stats(const vmg_plan *plan, int64_t *cell_updates, int64_t *
 /* Schedule a plan uses (host pointers, each may be NULL): tile height and
  * z-chunk of the finest level's fused sweep (chosen by the autotuner with
  * VMG_AUTOTUNE, which times every swept level's smoother for tile heights
- * {4,8,12,16} x z chunks at plan creation; Sec. V of the paper notes the code
- * needed more tuning),
- * pre/post sweeps and coarsest-level sweeps.  Errors: VMG_EINVAL. */
+ * {4,8,12,16} x z chunks x pipeline shapes at plan creation, and installs a
+ * cached cycle schedule of vmg_plan_tune_cycle; Sec. V of the paper notes the
+ * code needed more tuning), pre/post sweeps and coarsest-level sweeps.
+ * Errors: VMG_EINVAL. */
 vmg_status vmg_plan_config(const vmg_plan *plan, int32_t *tile_y, int32_t *z_chunk, int32_t *nu1,
                            int32_t *nu2, int32_t *coarse_sweeps);
+
+/* Cycle schedule of a plan (Sec. III.C leaves the number of relaxation
+ * sweeps and the cycle shape to the implementation; Sec. V notes the code
+ * needed more tuning).  Changing it changes the iteration, not the discrete
+ * problem solved. */
+typedef struct {
+    int32_t nu1, nu2;        /* pre/post smoothing sweeps per level, 0..8, nu1 + nu2 >= 1 */
+    int32_t inner_cycles;    /* mixed plans: FP32 inner V-cycles per outer iteration, 1..8;
+                                FP64 plans: 0 */
+    int32_t coarse_sweeps;   /* relaxation sweeps on the coarsest level, 1..64 */
+    int32_t coarse_tail;     /* periodic plans: 1 = the levels of at most 512 cells run in one
+                                single-workgroup launch, 0 = level by level; Dirichlet: 0 */
+    int32_t batch_blocks;    /* Dirichlet plans: blocks of the persistent smoother launch,
+                                64..65536; periodic plans: 0 */
+} vmg_cycle;
+
+/* The cycle schedule a plan runs (host pointer).  Errors: VMG_EINVAL. */
+vmg_status vmg_plan_get_cycle(const vmg_plan *plan, vmg_cycle *cycle);
+
+/* Install a cycle schedule (re-records the iteration graphs with VMG_GRAPH,
+ * so it may allocate).  Errors: VMG_EINVAL (null arguments, a field outside
+ * its range or set for the wrong kind of plan), VMG_EHIP. */
+vmg_status vmg_plan_set_cycle(vmg_plan *plan, const vmg_cycle *cycle);
+
+/* Cycle-schedule autotuner (Sec. V: "more tunings of the code are needed").
+ * Times complete solves of the given input (the arrays of vmg_solve; phi_work
+ * is a device array of phi's layout that each trial starts from zero and
+ * overwrites) to the plan's tolerance for candidate schedules, by coordinate
+ * search: nu1/nu2 over (1,1) .. (3,3), then inner cycles 1..3 (mixed), then
+ * coarsest sweeps {2, 4, 8, 16}, then the coarse tail on/off (periodic) or the
+ * persistent launch size {512, 1024, 2048} (Dirichlet).  A candidate that does
+ * not reach the tolerance within max_cycles is discarded.  The fastest
+ * schedule is installed, returned in *best (may be NULL) with its median time
+ * in *best_ms (may be NULL), and cached per (shape, precision, boundary kind,
+ * grid count) in the process and in the file named by VMG_TUNE_CACHE, where a
+ * later plan created with VMG_AUTOTUNE finds it (fields the caller set in
+ * vmg_params, nu1/nu2 and inner_cycles, take precedence).  Allocates (graph
+ * re-recording).  Errors: VMG_EINVAL (null plan, delta or phi_work; ghost
+ * missing for Dirichlet plans), VMG_ENOCONV (no candidate converged), the
+ * errors of vmg_solve. */
+vmg_status vmg_plan_tune_cycle(vmg_plan *plan, const double *delta, const double *ghost, const double *source,
+                               double *phi_work, vmg_cycle *best, double *best_ms);
 
 /* Number of levels of a plan that run the fused red-black sweep (the finest
  * level and every coarser one above the single-launch coarse tail), i.e. the
@@ -356,16 +399,20 @@ int32_t vmg_plan_level_count(const vmg_plan *plan);
 /* Install a sweep schedule on one level (Sec. V of the paper notes that the
  * code needed more tuning; this is how a caller reuses schedules the autotuner
  * found, or forces one): the fused sweep of level `level` then runs tiles of
- * 64 x tile_y cells marching z_chunk planes.  The schedule changes only the
- * blocking of the same red-black update, not the result's definition.  With
- * VMG_GRAPH the iteration graphs are recorded again (allocates).
- * Errors: VMG_EINVAL (null plan, level outside [0, vmg_plan_level_count),
- * tile_y not in {4, 8, 12, 16}, z_chunk odd or outside [2, 1024]), VMG_EHIP. */
-vmg_status vmg_plan_set_schedule(vmg_plan *plan, int32_t level, int32_t tile_y, int32_t z_chunk);
+ * 64 x tile_y cells marching z_chunk planes, with pipeline shape `pipe`: 0 =
+ * the black phase one plane behind the red phase (two barriers per plane
+ * step, three-plane LDS rings), 1 = two planes behind (one barrier, four-plane
+ * rings).  The schedule changes only the blocking of the same red-black
+ * update, not the result's definition.  With VMG_GRAPH the iteration graphs
+ * are recorded again (allocates).  Errors: VMG_EINVAL (null plan, level
+ * outside [0, vmg_plan_level_count), tile_y not in {4, 8, 12, 16}, z_chunk odd
+ * or outside [2, 1024], pipe not 0 or 1), VMG_EHIP. */
+vmg_status vmg_plan_set_schedule(vmg_plan *plan, int32_t level, int32_t tile_y, int32_t z_chunk, int32_t pipe);
 
 /* The sweep schedule a level runs (host pointers, each may be NULL).
  * Errors: VMG_EINVAL (null plan, level outside [0, vmg_plan_level_count)). */
-vmg_status vmg_plan_schedule(const vmg_plan *plan, int32_t level, int32_t *tile_y, int32_t *z_chunk);
+vmg_status vmg_plan_schedule(const vmg_plan *plan, int32_t level, int32_t *tile_y, int32_t *z_chunk,
+                             int32_t *pipe);
 
 #ifdef __cplusplus
 }

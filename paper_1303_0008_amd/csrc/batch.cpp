@@ -201,7 +201,6 @@ int64_t batch_partials_needed(const Plan* P) {
     return P->blev.empty() ? 0 : P->blev[0].ncells + 1;
 }
 
-static int max_resident_blocks() { return 256 * 4; }   // CUs x resident smoother blocks per CU
 
 static const double* bf(const Plan* P, int l) {
     const BatchLevel& B = P->blev[l];
@@ -215,7 +214,7 @@ static const double* bf(const Plan* P, int l) {
 static hipError_t bsmooth(Plan* P, int l) {
     BatchLevel& B = P->blev[l];
     CKE(launch_smooth_batch_args(P->coef, B.phi[B.cur], B.phi[B.cur ^ 1], B.delta, bf(P, l), B.cfg, B.d_geom,
-                                 B.d_sitems, B.nsitems, max_resident_blocks(), P->stream));
+                                 B.d_sitems, B.nsitems, P->batch_blocks, P->stream));
     B.cur ^= 1;
     P->cell_updates += B.cells_A;
     if (l == 0) P->finest_sweeps += 1;
@@ -262,7 +261,7 @@ static hipError_t bsmooth_corr(Plan* P, int l) {
     BatchLevel& B = P->blev[l];
     const CoefF cf = make_coef_f(P->coef, 1.0);   // per-grid h is applied inside the kernels
     CKE(launch_smooth_corr_batch(cf, B.e[B.ecur], B.e[B.ecur ^ 1], B.pt, B.t0, B.r, B.cfg, B.d_geom, B.d_sitems,
-                                 B.nsitems, max_resident_blocks(), P->stream));
+                                 B.nsitems, P->batch_blocks, P->stream));
     B.ecur ^= 1;
     P->cell_updates += B.cells_A;
     if (l == 0) P->finest_sweeps += 1;

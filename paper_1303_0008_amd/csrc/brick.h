@@ -41,28 +41,26 @@ namespace vmg {
 // Threads per block of the fused sweep.
 constexpr int SNT = 256;
 
-// Pipeline shape.  With SWEEP_DEFER the black phase of a step works two planes
-// behind its red phase instead of one, so the two phases of a step touch
-// disjoint LDS planes and run without a barrier between them (one barrier per
-// step, and red and black updates of a thread are independent work); the
-// plane rings then hold four planes instead of three.
-#ifndef VMG_SWEEP_DEFER
-#define VMG_SWEEP_DEFER 1
-#endif
-constexpr bool SWEEP_DEFER = VMG_SWEEP_DEFER != 0;
-constexpr int SWEEP_SLOTS = SWEEP_DEFER ? 4 : 3;   // planes per LDS ring
-constexpr int SWEEP_LAG = SWEEP_DEFER ? 3 : 2;     // step t: red on plane t-1, black on plane t-LAG
+// Pipeline shape (a run-time choice of the schedule, SmoothCfg::pipe).  With
+// DEFER the black phase of a step works two planes behind its red phase
+// instead of one, so the two phases of a step touch disjoint LDS planes and run
+// without a barrier between them (one barrier per step, and red and black
+// updates of a thread are independent work); the plane rings then hold four
+// planes instead of three.
+constexpr int sweep_slots(bool defer) { return defer ? 4 : 3; }
 
-// LDS of a sweep block of tile height TY (8-byte cells: SWEEP_SLOTS ring-2
+// LDS of a sweep block of tile height TY (8-byte cells: the ring's ring-2
 // planes of u^0 and as many ring-1 planes of u^1), and the waves per SIMD its
 // kernels are built for: as many blocks per CU as that LDS allows (160 KB per
 // CU), at most 4, so that the register budget matches the occupancy the LDS
 // permits.
-constexpr int sweep_lds_bytes(int ty) {
-    return SWEEP_SLOTS * ((TX + 4) * (ty + 4) + (TX + 2) * (ty + 2)) * 8;
+constexpr int sweep_lds_bytes(int ty, bool defer) {
+    return sweep_slots(defer) * ((TX + 4) * (ty + 4) + (TX + 2) * (ty + 2)) * 8;
 }
-constexpr int sweep_waves(int ty) {
-    return (160 * 1024) / sweep_lds_bytes(ty) >= 4 ? 4 : ((160 * 1024) / sweep_lds_bytes(ty) < 1 ? 1 : (160 * 1024) / sweep_lds_bytes(ty));
+constexpr int sweep_waves(int ty, bool defer) {
+    return (160 * 1024) / sweep_lds_bytes(ty, defer) >= 4
+               ? 4
+               : ((160 * 1024) / sweep_lds_bytes(ty, defer) < 1 ? 1 : (160 * 1024) / sweep_lds_bytes(ty, defer));
 }
 
 // Neighbourhood of a cell read from a parity-split LDS plane set.  `c` is the
@@ -84,7 +82,7 @@ __device__ __forceinline__ void nb_split(const T* __restrict__ Pm, const T* __re
     v.ymzp = Pp[o - W];     v.ypzp = Pp[o + W];
 }
 
-template <int TY, int DIR, int NTH, typename K>
+template <int TY, int DIR, int NTH, bool DEFER, typename K>
 __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int x0, const int y0, const int z0,
                                             const int z1) {
     using Cell = typename K::Cell;
@@ -102,7 +100,7 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     constexpr int S2 = H2 * W2, S1 = H1 * W1;     // cells per plane
     // Rows are stored split by x parity: cell (Y, X) lives at Y*W + (X&1)*W/2 + (X>>1),
     // so lanes working on every other cell of a row touch consecutive words.
-    constexpr int NSL = SWEEP_SLOTS, LAG = SWEEP_LAG;
+    constexpr int NSL = sweep_slots(DEFER), LAG = DEFER ? 3 : 2;
     __shared__ Cell P0[NSL * S2];  // u^0, ring 2, slot = z mod NSL
     __shared__ Cell P1[NSL * S1];  // u^1 (red computed, black copied), ring 1
 

@@ -417,6 +417,35 @@ vmg_status capture_graphs(Plan* P) {
     return VMG_OK;
 }
 
+void get_cycle(const Plan* P, vmg_cycle* c) {
+    c->nu1 = P->nu1;
+    c->nu2 = P->nu2;
+    c->inner_cycles = P->mixed ? P->inner : 0;
+    c->coarse_sweeps = P->ncoarse;
+    c->coarse_tail = P->periodic && P->use_tail ? 1 : 0;
+    c->batch_blocks = P->batched ? P->batch_blocks : 0;
+}
+
+vmg_status set_cycle(Plan* P, const vmg_cycle* c) {
+    if (c->nu1 < 0 || c->nu1 > 8 || c->nu2 < 0 || c->nu2 > 8 || c->nu1 + c->nu2 < 1)
+        return fail(VMG_EINVAL, "cycle: nu1, nu2 in [0, 8] with nu1 + nu2 >= 1");
+    if (P->mixed ? (c->inner_cycles < 1 || c->inner_cycles > 8) : c->inner_cycles != 0)
+        return fail(VMG_EINVAL, "cycle: inner_cycles in [1, 8] for mixed plans, 0 for FP64 plans");
+    if (c->coarse_sweeps < 1 || c->coarse_sweeps > 64) return fail(VMG_EINVAL, "cycle: coarse_sweeps in [1, 64]");
+    if ((c->coarse_tail != 0 && c->coarse_tail != 1) || (!P->periodic && c->coarse_tail != 0))
+        return fail(VMG_EINVAL, "cycle: coarse_tail 0 or 1 (periodic plans), 0 (Dirichlet plans)");
+    if (P->batched ? (c->batch_blocks < 64 || c->batch_blocks > 65536) : c->batch_blocks != 0)
+        return fail(VMG_EINVAL, "cycle: batch_blocks in [64, 65536] for Dirichlet plans, 0 for periodic plans");
+    P->nu1 = c->nu1;
+    P->nu2 = c->nu2;
+    if (P->mixed) P->inner = c->inner_cycles;
+    P->ncoarse = c->coarse_sweeps;
+    if (P->periodic) P->use_tail = c->coarse_tail != 0;
+    if (P->batched) P->batch_blocks = c->batch_blocks;
+    CKH(hipStreamSynchronize(P->stream));
+    return capture_graphs(P);
+}
+
 static vmg_status run_cycle(Plan* P) {
     const int src = P->has_source ? 1 : 0;
     const int parity = finest_parity(P);
@@ -628,6 +657,20 @@ vmg_status vmg_plan_create(vmg_plan** plan, const vmg_grid* grids, int32_t n_gri
     vmg_status st = build_plan(P, grids, n_grids, p, stream);
     if (st == VMG_OK && p->tau_factor > 0.0 && !shifted_cycles(P))
         st = fail(VMG_EINVAL, "tau_factor needs a grid with a coarser level (tau^h lives on it)");
+    if (st == VMG_OK && (p->flags & VMG_AUTOTUNE)) {
+        // a cycle schedule vmg_plan_tune_cycle cached for this plan's key; the
+        // caller's explicit nu1/nu2 and inner_cycles take precedence
+        vmg_cycle c;
+        if (cached_cycle(P, &c)) {
+            if (p->nu1 != 0 || p->nu2 != 0) { c.nu1 = P->nu1; c.nu2 = P->nu2; }
+            if (p->inner_cycles != 0) c.inner_cycles = P->inner;
+            if (!P->mixed) c.inner_cycles = 0;
+            if (!P->periodic) c.coarse_tail = 0;
+            if (!P->batched) c.batch_blocks = 0;
+            else if (c.batch_blocks == 0) c.batch_blocks = P->batch_blocks;
+            st = set_cycle(P, &c);
+        }
+    }
     if (st == VMG_OK) st = capture_graphs(P);
     if (st != VMG_OK) {
         std::string msg = g_err;
@@ -979,28 +1022,30 @@ vmg_status vmg_smooth(vmg_plan* plan, int32_t sweeps) {
     return VMG_OK;
 }
 
-vmg_status vmg_plan_set_schedule(vmg_plan* plan, int32_t level, int32_t tile_y, int32_t z_chunk) {
+vmg_status vmg_plan_set_schedule(vmg_plan* plan, int32_t level, int32_t tile_y, int32_t z_chunk, int32_t pipe) {
     g_err.clear();
     if (!plan) return fail(VMG_EINVAL, "null plan");
     Plan* P = reinterpret_cast<Plan*>(plan);
     if (tile_y != 4 && tile_y != 8 && tile_y != 12 && tile_y != 16)
         return fail(VMG_EINVAL, "tile_y must be 4, 8, 12 or 16");
     if (z_chunk < 2 || z_chunk > 1024 || (z_chunk & 1)) return fail(VMG_EINVAL, "z_chunk must be even, in [2, 1024]");
+    if (pipe != 0 && pipe != 1) return fail(VMG_EINVAL, "pipe must be 0 or 1");
     if (level < 0 || level >= swept_level_count(P))
         return fail(VMG_EINVAL, "level " + std::to_string(level) + " has no fused sweep in this plan");
-    const SmoothCfg c{tile_y, z_chunk};
+    const SmoothCfg c{tile_y, z_chunk, pipe};
     if (level == 0) P->cfg = c;
     if (P->batched) {
         CKH(batch_set_level_cfg(P, level, c));
     } else if (level > 0) {
-        if ((int)P->lcfg.size() < (int)P->grids[0].lev.size()) P->lcfg.resize(P->grids[0].lev.size(), SmoothCfg{0, 0});
+        if ((int)P->lcfg.size() < (int)P->grids[0].lev.size())
+            P->lcfg.resize(P->grids[0].lev.size(), SmoothCfg{0, 0, 1});
         P->lcfg[level] = c;
     }
     CKH(hipStreamSynchronize(P->stream));
     return capture_graphs(P);
 }
 
-vmg_status vmg_plan_schedule(const vmg_plan* plan, int32_t level, int32_t* tile_y, int32_t* z_chunk) {
+vmg_status vmg_plan_schedule(const vmg_plan* plan, int32_t level, int32_t* tile_y, int32_t* z_chunk, int32_t* pipe) {
     if (!plan) return fail(VMG_EINVAL, "null plan");
     const Plan* P = reinterpret_cast<const Plan*>(plan);
     if (level < 0 || level >= swept_level_count(P))
@@ -1008,7 +1053,29 @@ vmg_status vmg_plan_schedule(const vmg_plan* plan, int32_t level, int32_t* tile_
     const SmoothCfg c = P->batched ? P->blev[level].cfg : level_schedule(P, level, P->grids[0].lev[level].g);
     if (tile_y) *tile_y = c.ty;
     if (z_chunk) *z_chunk = c.zc;
+    if (pipe) *pipe = c.pipe;
     return VMG_OK;
+}
+
+vmg_status vmg_plan_get_cycle(const vmg_plan* plan, vmg_cycle* cycle) {
+    if (!plan || !cycle) return fail(VMG_EINVAL, "null argument");
+    get_cycle(reinterpret_cast<const Plan*>(plan), cycle);
+    return VMG_OK;
+}
+
+vmg_status vmg_plan_set_cycle(vmg_plan* plan, const vmg_cycle* cycle) {
+    g_err.clear();
+    if (!plan || !cycle) return fail(VMG_EINVAL, "null argument");
+    return set_cycle(reinterpret_cast<Plan*>(plan), cycle);
+}
+
+vmg_status vmg_plan_tune_cycle(vmg_plan* plan, const double* delta, const double* ghost, const double* source,
+                               double* phi_work, vmg_cycle* best, double* best_ms) {
+    g_err.clear();
+    if (!plan || !delta || !phi_work) return fail(VMG_EINVAL, "null plan, delta or phi_work");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    if (!P->periodic && !ghost) return fail(VMG_EINVAL, "Dirichlet grids need ghost values");
+    return tune_cycle(P, delta, ghost, source, phi_work, best, best_ms);
 }
 
 int32_t vmg_plan_level_count(const vmg_plan* plan) {

@@ -94,8 +94,8 @@ struct SmoothK {
     }
 };
 
-template <int TY, int DIR, bool HAS_F>
-__global__ void __launch_bounds__(SNT, sweep_waves(TY)) k_smooth(SmoothArgs a) {
+template <int TY, int DIR, bool HAS_F, bool DEFER>
+__global__ void __launch_bounds__(SNT, sweep_waves(TY, DEFER)) k_smooth(SmoothArgs a) {
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % a.tiles_x;
     b /= a.tiles_x;
@@ -104,14 +104,14 @@ __global__ void __launch_bounds__(SNT, sweep_waves(TY)) k_smooth(SmoothArgs a) {
     const int z0 = ch * a.zc;
     if (z0 >= a.g.n2) return;
     const SmoothK<HAS_F> k(a, a.g, DIR == 0);
-    fused_sweep<TY, DIR, SNT>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
+    fused_sweep<TY, DIR, SNT, DEFER>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
 }
 
 // Persistent sweep over a (grid, tile x, tile y, z chunk) work list: every
 // Dirichlet grid of a batch at one level in one launch.  `proto` carries the
 // pooled level buffers and coefficients; geoms[w.x] locates grid w.x in them.
-template <int TY, bool HAS_F>
-__global__ void __launch_bounds__(SNT, sweep_waves(TY)) k_smooth_batch(SmoothArgs proto, const Geom* __restrict__ geoms,
+template <int TY, bool HAS_F, bool DEFER>
+__global__ void __launch_bounds__(SNT, sweep_waves(TY, DEFER)) k_smooth_batch(SmoothArgs proto, const Geom* __restrict__ geoms,
                                                      const int4* __restrict__ items, int nitems) {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int4 w = items[it];
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(SNT, sweep_waves(TY)) k_smooth_batch(SmoothArg
         a.g = geoms[w.x];
         const int z0 = w.w * a.zc;
         const SmoothK<HAS_F> k(a, a.g, false);
-        fused_sweep<TY, 1, SNT>(k, a.g, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
+        fused_sweep<TY, 1, SNT, DEFER>(k, a.g, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
     }
 }
 
@@ -1080,13 +1080,16 @@ int64_t ghost_count(int n0, int n1, int n2) {
 }
 
 template <int TY, int DIR>
-static hipError_t smooth_launch(const SmoothArgs& a, hipStream_t s) {
+static hipError_t smooth_launch(const SmoothArgs& a, bool defer, hipStream_t s) {
     const int chunks = (a.g.n2 + a.zc - 1) / a.zc;
     const int nb = a.tiles_x * a.tiles_y * chunks;
-    if (a.f)
-        hipLaunchKernelGGL((k_smooth<TY, DIR, true>), dim3(nb), dim3(SNT), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_smooth<TY, DIR, false>), dim3(nb), dim3(SNT), 0, s, a);
+    if (a.f) {
+        if (defer) hipLaunchKernelGGL((k_smooth<TY, DIR, true, true>), dim3(nb), dim3(SNT), 0, s, a);
+        else hipLaunchKernelGGL((k_smooth<TY, DIR, true, false>), dim3(nb), dim3(SNT), 0, s, a);
+    } else {
+        if (defer) hipLaunchKernelGGL((k_smooth<TY, DIR, false, true>), dim3(nb), dim3(SNT), 0, s, a);
+        else hipLaunchKernelGGL((k_smooth<TY, DIR, false, false>), dim3(nb), dim3(SNT), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -1099,16 +1102,17 @@ hipError_t launch_smooth(const Geom& g, const Coef& c, const double* pin, double
     a.tiles_x = (g.n0 + TX - 1) / TX;
     const int ty = cfg.ty;
     a.tiles_y = (g.n1 + ty - 1) / ty;
+    const bool d = cfg.pipe != 0;
     if (g.dir) {
-        if (ty == 4) return smooth_launch<4, 1>(a, s);
-        if (ty == 16) return smooth_launch<16, 1>(a, s);
-        if (ty == 12) return smooth_launch<12, 1>(a, s);
-        return smooth_launch<8, 1>(a, s);
+        if (ty == 4) return smooth_launch<4, 1>(a, d, s);
+        if (ty == 16) return smooth_launch<16, 1>(a, d, s);
+        if (ty == 12) return smooth_launch<12, 1>(a, d, s);
+        return smooth_launch<8, 1>(a, d, s);
     }
-    if (ty == 4) return smooth_launch<4, 0>(a, s);
-    if (ty == 16) return smooth_launch<16, 0>(a, s);
-    if (ty == 12) return smooth_launch<12, 0>(a, s);
-    return smooth_launch<8, 0>(a, s);
+    if (ty == 4) return smooth_launch<4, 0>(a, d, s);
+    if (ty == 16) return smooth_launch<16, 0>(a, d, s);
+    if (ty == 12) return smooth_launch<12, 0>(a, d, s);
+    return smooth_launch<8, 0>(a, d, s);
 }
 
 hipError_t launch_residual_restrict(const Geom& gf, const Geom& gc, const Coef& c,
@@ -1328,24 +1332,25 @@ hipError_t launch_check_finite(const double* p, int64_t n, double* partials, int
 }
 
 // ---- batched launchers --------------------------------------------------------
+template <int TY>
+static void smooth_batch_ty(const SmoothArgs& proto, const Geom* geoms, const int4* items, int nitems, int nb,
+                            bool defer, hipStream_t s) {
+    const bool f = proto.f != nullptr;
+    if (f && defer) hipLaunchKernelGGL((k_smooth_batch<TY, true, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
+    else if (f) hipLaunchKernelGGL((k_smooth_batch<TY, true, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
+    else if (defer) hipLaunchKernelGGL((k_smooth_batch<TY, false, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
+    else hipLaunchKernelGGL((k_smooth_batch<TY, false, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
+}
+
 hipError_t launch_smooth_batch(const SmoothArgs& proto, const Geom* geoms, const int4* items, int nitems,
-                               int ty, int max_blocks, hipStream_t s) {
+                               SmoothCfg cfg, int max_blocks, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     const int nb = std::min(nitems, max_blocks);
-    const bool f = proto.f != nullptr;
-    if (ty == 4) {
-        if (f) hipLaunchKernelGGL((k_smooth_batch<4, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
-        else hipLaunchKernelGGL((k_smooth_batch<4, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
-    } else if (ty == 16) {
-        if (f) hipLaunchKernelGGL((k_smooth_batch<16, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
-        else hipLaunchKernelGGL((k_smooth_batch<16, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
-    } else if (ty == 12) {
-        if (f) hipLaunchKernelGGL((k_smooth_batch<12, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
-        else hipLaunchKernelGGL((k_smooth_batch<12, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
-    } else {
-        if (f) hipLaunchKernelGGL((k_smooth_batch<8, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
-        else hipLaunchKernelGGL((k_smooth_batch<8, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
-    }
+    const bool d = cfg.pipe != 0;
+    if (cfg.ty == 4) smooth_batch_ty<4>(proto, geoms, items, nitems, nb, d, s);
+    else if (cfg.ty == 16) smooth_batch_ty<16>(proto, geoms, items, nitems, nb, d, s);
+    else if (cfg.ty == 12) smooth_batch_ty<12>(proto, geoms, items, nitems, nb, d, s);
+    else smooth_batch_ty<8>(proto, geoms, items, nitems, nb, d, s);
     return hipGetLastError();
 }
 
@@ -1356,7 +1361,7 @@ hipError_t launch_smooth_batch_args(const Coef& c, const double* pin, double* po
     std::memset(&a, 0, sizeof(a));
     a.c = c; a.pin = pin; a.pout = pout; a.delta = delta; a.f = f; a.sc = nullptr;
     a.zc = cfg.zc > 0 ? cfg.zc : 16;
-    return launch_smooth_batch(a, geoms, items, nitems, cfg.ty, max_blocks, s);
+    return launch_smooth_batch(a, geoms, items, nitems, cfg, max_blocks, s);
 }
 
 hipError_t launch_rr_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, const Coef& c,

@@ -103,8 +103,8 @@ struct CorrK {
     }
 };
 
-template <int TY, int DIR, bool ZERO_E>
-__global__ void __launch_bounds__(SNT, sweep_waves(TY)) k_smooth_corr(CorrArgs a) {
+template <int TY, int DIR, bool ZERO_E, bool DEFER>
+__global__ void __launch_bounds__(SNT, sweep_waves(TY, DEFER)) k_smooth_corr(CorrArgs a) {
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % a.tiles_x;
     b /= a.tiles_x;
@@ -113,12 +113,12 @@ __global__ void __launch_bounds__(SNT, sweep_waves(TY)) k_smooth_corr(CorrArgs a
     const int z0 = ch * a.zc;
     if (z0 >= a.g.n2) return;
     const CorrK<ZERO_E> k(a, DIR == 0);
-    fused_sweep<TY, DIR, SNT>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
+    fused_sweep<TY, DIR, SNT, DEFER>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
 }
 
 // persistent sweep over a (grid, tile x, tile y, z chunk) work list (Dirichlet batches)
-template <int TY>
-__global__ void __launch_bounds__(SNT, sweep_waves(TY)) k_smooth_corr_batch(CorrArgs proto, const Geom* __restrict__ geoms,
+template <int TY, bool DEFER>
+__global__ void __launch_bounds__(SNT, sweep_waves(TY, DEFER)) k_smooth_corr_batch(CorrArgs proto, const Geom* __restrict__ geoms,
                                                           const int4* __restrict__ items, int nitems) {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int4 w = items[it];
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(SNT, sweep_waves(TY)) k_smooth_corr_batch(Corr
         a.c.h2 = (float)(a.g.h * a.g.h);
         const int z0 = w.w * a.zc;
         const CorrK<false> k(a, false);
-        fused_sweep<TY, 1, SNT>(k, a.g, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
+        fused_sweep<TY, 1, SNT, DEFER>(k, a.g, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
     }
 }
 
@@ -1022,12 +1022,12 @@ __global__ void k_update_batch(const Geom* __restrict__ gs, const int2* __restri
 // launchers
 // ---------------------------------------------------------------------------
 template <int TY, int DIR>
-static hipError_t corr_launch(const CorrArgs& a, bool zero_in, hipStream_t s) {
-    const int chunks = (a.g.n2 + a.zc - 1) / a.zc;
-    if (zero_in)
-        hipLaunchKernelGGL((k_smooth_corr<TY, DIR, true>), dim3(a.tiles_x * a.tiles_y * chunks), dim3(SNT), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_smooth_corr<TY, DIR, false>), dim3(a.tiles_x * a.tiles_y * chunks), dim3(SNT), 0, s, a);
+static hipError_t corr_launch(const CorrArgs& a, bool zero_in, bool defer, hipStream_t s) {
+    const dim3 nb(a.tiles_x * a.tiles_y * ((a.g.n2 + a.zc - 1) / a.zc));
+    if (zero_in && defer) hipLaunchKernelGGL((k_smooth_corr<TY, DIR, true, true>), nb, dim3(SNT), 0, s, a);
+    else if (zero_in) hipLaunchKernelGGL((k_smooth_corr<TY, DIR, true, false>), nb, dim3(SNT), 0, s, a);
+    else if (defer) hipLaunchKernelGGL((k_smooth_corr<TY, DIR, false, true>), nb, dim3(SNT), 0, s, a);
+    else hipLaunchKernelGGL((k_smooth_corr<TY, DIR, false, false>), nb, dim3(SNT), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1039,16 +1039,17 @@ hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, f
     a.zc = cfg.zc > 0 ? cfg.zc : 16;
     a.tiles_x = (g.n0 + TX - 1) / TX;
     a.tiles_y = (g.n1 + cfg.ty - 1) / cfg.ty;
+    const bool d = cfg.pipe != 0;
     if (g.dir) {
-        if (cfg.ty == 4) return corr_launch<4, 1>(a, zero_in, s);
-        if (cfg.ty == 16) return corr_launch<16, 1>(a, zero_in, s);
-        if (cfg.ty == 12) return corr_launch<12, 1>(a, zero_in, s);
-        return corr_launch<8, 1>(a, zero_in, s);
+        if (cfg.ty == 4) return corr_launch<4, 1>(a, zero_in, d, s);
+        if (cfg.ty == 16) return corr_launch<16, 1>(a, zero_in, d, s);
+        if (cfg.ty == 12) return corr_launch<12, 1>(a, zero_in, d, s);
+        return corr_launch<8, 1>(a, zero_in, d, s);
     }
-    if (cfg.ty == 4) return corr_launch<4, 0>(a, zero_in, s);
-    if (cfg.ty == 16) return corr_launch<16, 0>(a, zero_in, s);
-    if (cfg.ty == 12) return corr_launch<12, 0>(a, zero_in, s);
-    return corr_launch<8, 0>(a, zero_in, s);
+    if (cfg.ty == 4) return corr_launch<4, 0>(a, zero_in, d, s);
+    if (cfg.ty == 16) return corr_launch<16, 0>(a, zero_in, d, s);
+    if (cfg.ty == 12) return corr_launch<12, 0>(a, zero_in, d, s);
+    return corr_launch<8, 0>(a, zero_in, d, s);
 }
 
 static void corr_tiles(const Geom& g, int& tx, int& ty, int& zc, int& nb) {
@@ -1193,15 +1194,18 @@ hipError_t launch_smooth_corr_batch(const CoefF& c, const float* ein, float* eou
     std::memset(&a, 0, sizeof(a));
     a.c = c; a.ein = ein; a.eout = eout; a.pt = pt; a.t0 = t0; a.r = r; a.sc = nullptr;
     a.zc = cfg.zc > 0 ? cfg.zc : 16;
-    const int nb = std::min(nitems, max_blocks);
-    if (cfg.ty == 4)
-        hipLaunchKernelGGL(k_smooth_corr_batch<4>, dim3(nb), dim3(SNT), 0, s, a, geoms, items, nitems);
-    else if (cfg.ty == 16)
-        hipLaunchKernelGGL(k_smooth_corr_batch<16>, dim3(nb), dim3(SNT), 0, s, a, geoms, items, nitems);
-    else if (cfg.ty == 12)
-        hipLaunchKernelGGL(k_smooth_corr_batch<12>, dim3(nb), dim3(SNT), 0, s, a, geoms, items, nitems);
-    else
-        hipLaunchKernelGGL(k_smooth_corr_batch<8>, dim3(nb), dim3(SNT), 0, s, a, geoms, items, nitems);
+    const dim3 nb(std::min(nitems, max_blocks));
+    const bool d = cfg.pipe != 0;
+#define VMG_CORR_BATCH(T)                                                                                   \
+    do {                                                                                                   \
+        if (d) hipLaunchKernelGGL((k_smooth_corr_batch<T, true>), nb, dim3(SNT), 0, s, a, geoms, items, nitems); \
+        else hipLaunchKernelGGL((k_smooth_corr_batch<T, false>), nb, dim3(SNT), 0, s, a, geoms, items, nitems);  \
+    } while (0)
+    if (cfg.ty == 4) VMG_CORR_BATCH(4);
+    else if (cfg.ty == 16) VMG_CORR_BATCH(16);
+    else if (cfg.ty == 12) VMG_CORR_BATCH(12);
+    else VMG_CORR_BATCH(8);
+#undef VMG_CORR_BATCH
     return hipGetLastError();
 }
 

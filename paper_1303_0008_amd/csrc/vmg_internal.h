@@ -64,6 +64,8 @@ constexpr int TX = 64;
 struct SmoothCfg {
     int ty;      // 4, 8, 12 or 16
     int zc;      // z planes per block
+    int pipe = 1;   // 0: black one plane behind red, two barriers per plane step;
+                    // 1: black two planes behind, one barrier (four-plane rings)
 };
 
 // Blocks a tiled pass should at least launch: four per compute unit.

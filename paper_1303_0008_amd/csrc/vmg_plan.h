@@ -78,6 +78,7 @@ struct Plan {
     int nu1 = 2, nu2 = 2, ncoarse = 40;
     int inner = 2;                         // mixed: FP32 inner V-cycles per outer iteration
     bool use_tail = true;                  // periodic coarse levels <= TAIL_CELLS in one launch
+    int batch_blocks = 1024;               // blocks of a batched plan's persistent smoother launch
     bool periodic = true;
     bool mixed = false;
     bool has_source = false;
@@ -120,6 +121,16 @@ vmg_status autotune(Plan* P);
 int swept_level_count(const Plan* P);
 // (re)record the replayable iterations of a VMG_GRAPH plan (no-op without the flag)
 vmg_status capture_graphs(Plan* P);
+// cycle schedule of a plan (nu1, nu2, inner cycles, coarsest sweeps, coarse tail,
+// persistent launch size); set_cycle validates, installs and re-records graphs
+void get_cycle(const Plan* P, vmg_cycle* c);
+vmg_status set_cycle(Plan* P, const vmg_cycle* c);
+// cached cycle schedule for this plan's key, if the tuning cache holds one
+bool cached_cycle(const Plan* P, vmg_cycle* c);
+vmg_status tune_cycle(Plan* P, const double* delta, const double* ghost, const double* source, double* phi_work,
+                      vmg_cycle* best, double* best_ms);
+vmg_status solve(Plan* P, const double* delta, const double* ghost, const double* source, double* phi,
+                 vmg_result* out);
 hipError_t smooth_level_public(Plan* P, GridState& G, int l);
 // schedule of the fused sweep on level l of a single-grid (periodic) plan
 SmoothCfg level_schedule(const Plan* P, int l, const Geom& g);

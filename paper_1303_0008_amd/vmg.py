@@ -6,7 +6,7 @@ current HIP stream.  The functions mirror the C ABI in ``include/vmg.h``:
 ``plan_create``, ``solve``, ``plan_destroy``, ``last_error``,
 ``solve_periodic``, ``residual``, ``fill_ghosts``, ``fill_interior``, ``ghost_count``,
 ``smooth``, ``plan_stats``, ``plan_config``, ``plan_level_count``, ``plan_set_schedule``,
-``plan_schedule``, ``total_force``, ``mass_assign``, ``mass_assign_region``,
+``plan_schedule``, ``plan_get_cycle``, ``plan_set_cycle``, ``plan_tune_cycle``, ``total_force``, ``mass_assign``, ``mass_assign_region``,
 ``solve_levels``; ``Plan`` and ``LevelsPlan`` wrap plan handles.
 
 There is no fallback: if the library is missing or no GPU is present the
@@ -55,6 +55,14 @@ class Result(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Cycle(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("inner_cycles", ctypes.c_int32),
+                ("coarse_sweeps", ctypes.c_int32), ("coarse_tail", ctypes.c_int32), ("batch_blocks", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Nest(ctypes.Structure):
     _fields_ = [("parent", ctypes.c_int32), ("origin", ctypes.c_int32 * 3)]
 
@@ -65,7 +73,8 @@ EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
            "vmg_smooth", "vmg_plan_stats", "vmg_plan_config", "vmg_fill_interior", "vmg_total_force",
            "vmg_mass_assign", "vmg_mass_assign_workspace", "vmg_solve_levels", "vmg_levels_create",
            "vmg_levels_solve", "vmg_levels_destroy", "vmg_mass_assign_region", "vmg_plan_level_count",
-           "vmg_plan_set_schedule", "vmg_plan_schedule", "vmg_mass_assign_noalloc"]
+           "vmg_plan_set_schedule", "vmg_plan_schedule", "vmg_mass_assign_noalloc", "vmg_plan_get_cycle",
+           "vmg_plan_set_cycle", "vmg_plan_tune_cycle"]
 
 _lib = None
 
@@ -114,8 +123,11 @@ def load():
     L.vmg_plan_config.argtypes = [vp, i32p, i32p, i32p, i32p, i32p]
     L.vmg_plan_level_count.argtypes = [vp]
     L.vmg_plan_level_count.restype = ctypes.c_int32
-    L.vmg_plan_set_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
-    L.vmg_plan_schedule.argtypes = [vp, ctypes.c_int32, i32p, i32p]
+    L.vmg_plan_set_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.vmg_plan_schedule.argtypes = [vp, ctypes.c_int32, i32p, i32p, i32p]
+    L.vmg_plan_get_cycle.argtypes = [vp, P(Cycle)]
+    L.vmg_plan_set_cycle.argtypes = [vp, P(Cycle)]
+    L.vmg_plan_tune_cycle.argtypes = [vp, vp, vp, vp, vp, P(Cycle), P(ctypes.c_double)]
     for name in EXPORTS:
         if name not in ("vmg_last_error", "vmg_ghost_count", "vmg_mass_assign_workspace", "vmg_levels_destroy",
                         "vmg_plan_level_count"):
@@ -404,16 +416,43 @@ def plan_level_count(handle):
     return int(load().vmg_plan_level_count(ctypes.c_void_p(handle)))
 
 
-def plan_set_schedule(handle, level, tile_y, z_chunk):
-    """vmg_plan_set_schedule: install a sweep schedule (tile height, z chunk) on one level."""
-    _check(load().vmg_plan_set_schedule(ctypes.c_void_p(handle), int(level), int(tile_y), int(z_chunk)))
+def plan_set_schedule(handle, level, tile_y, z_chunk, pipe=1):
+    """vmg_plan_set_schedule: install a sweep schedule (tile height, z chunk, pipeline shape) on one level."""
+    _check(load().vmg_plan_set_schedule(ctypes.c_void_p(handle), int(level), int(tile_y), int(z_chunk), int(pipe)))
 
 
 def plan_schedule(handle, level):
-    """vmg_plan_schedule: (tile_y, z_chunk) the fused sweep of a level runs."""
-    a, b = ctypes.c_int32(), ctypes.c_int32()
-    _check(load().vmg_plan_schedule(ctypes.c_void_p(handle), int(level), ctypes.byref(a), ctypes.byref(b)))
-    return a.value, b.value
+    """vmg_plan_schedule: (tile_y, z_chunk, pipe) the fused sweep of a level runs."""
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().vmg_plan_schedule(ctypes.c_void_p(handle), int(level), ctypes.byref(a), ctypes.byref(b),
+                                    ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def plan_get_cycle(handle):
+    """vmg_plan_get_cycle: the plan's cycle schedule as a dict."""
+    c = Cycle()
+    _check(load().vmg_plan_get_cycle(ctypes.c_void_p(handle), ctypes.byref(c)))
+    return c.as_dict()
+
+
+def plan_set_cycle(handle, **fields):
+    """vmg_plan_set_cycle: change fields of the plan's cycle schedule (others kept)."""
+    c = Cycle()
+    _check(load().vmg_plan_get_cycle(ctypes.c_void_p(handle), ctypes.byref(c)))
+    for k, v in fields.items():
+        setattr(c, k, int(v))
+    _check(load().vmg_plan_set_cycle(ctypes.c_void_p(handle), ctypes.byref(c)))
+
+
+def plan_tune_cycle(handle, delta, phi_work, ghost=None, source=None):
+    """vmg_plan_tune_cycle: time solves of this input for candidate cycle
+    schedules, install the fastest; returns (cycle dict, median ms)."""
+    c = Cycle()
+    ms = ctypes.c_double()
+    _check(load().vmg_plan_tune_cycle(ctypes.c_void_p(handle), _ptr(delta), _ptr(ghost), _ptr(source),
+                                      _ptr(phi_work), ctypes.byref(c), ctypes.byref(ms)))
+    return c.as_dict(), ms.value
 
 
 class Plan:
@@ -441,11 +480,20 @@ class Plan:
     def level_count(self):
         return plan_level_count(self.handle)
 
-    def set_schedule(self, level, tile_y, z_chunk):
-        plan_set_schedule(self.handle, level, tile_y, z_chunk)
+    def set_schedule(self, level, tile_y, z_chunk, pipe=1):
+        plan_set_schedule(self.handle, level, tile_y, z_chunk, pipe)
 
     def schedule(self, level):
         return plan_schedule(self.handle, level)
+
+    def cycle(self):
+        return plan_get_cycle(self.handle)
+
+    def set_cycle(self, **fields):
+        plan_set_cycle(self.handle, **fields)
+
+    def tune_cycle(self, delta, phi_work, ghost=None, source=None):
+        return plan_tune_cycle(self.handle, delta, phi_work, ghost, source)
 
     def close(self):
         if self.handle:

@@ -25,26 +25,42 @@ TUNE_FILE = os.path.join(ROOT, "paper_1303_0008_amd", "tune_gfx950.txt")
 
 
 def bench_schedules(prec_name, n=256):
-    """Per-level sweep schedules {level: (tile_y, z_chunk)} of the committed tuning
-    file for the periodic n^3 plan of one precision ("fp64" or "mixed") -- the
-    schedules the benchmark replays."""
+    """Per-level sweep schedules {level: (tile_y, z_chunk, pipe)} of the committed
+    tuning file for the periodic n^3 plan of one precision ("fp64" or "mixed")
+    -- the schedules the benchmark replays."""
     out = {}
     with open(TUNE_FILE) as f:
         for line in f:
             parts = line.split()
-            if len(parts) != 4:
+            key = parts[0].split(":") if parts else []
+            if len(key) != 6 or not key[5].startswith("L") or len(parts) not in (4, 5):
                 continue
-            key = parts[0].split(":")
             if key[1] == f"{n}x{n}x{n}" and key[2] == prec_name and key[3] == "per" and key[4] == "1":
-                out[int(key[5][1:])] = (int(parts[1]), int(parts[2]))
+                pipe = int(parts[3]) if len(parts) == 5 else 0
+                out[int(key[5][1:])] = (int(parts[1]), int(parts[2]), pipe)
     return out
 
 
-def install_schedules(plan, schedules):
-    """Install {level: (tile_y, z_chunk)} on the levels the plan sweeps."""
-    for lev, (ty, zc) in sorted(schedules.items()):
+def bench_cycle(prec_name, n=256):
+    """Cycle schedule of the committed tuning file for the periodic n^3 plan, or None."""
+    with open(TUNE_FILE) as f:
+        for line in f:
+            parts = line.split()
+            if parts and parts[0] == f"gfx950:{n}x{n}x{n}:{prec_name}:per:1:cycle" and len(parts) == 8:
+                v = [int(x) for x in parts[1:7]]
+                return dict(zip(("nu1", "nu2", "inner_cycles", "coarse_sweeps", "coarse_tail", "batch_blocks"), v))
+    return None
+
+
+def install_schedules(plan, schedules, cycle=None):
+    """Install {level: (tile_y, z_chunk, pipe)} on the levels the plan sweeps, and
+    a cycle schedule if given (before the sweep schedules: the coarse tail
+    decides which levels are swept)."""
+    if cycle is not None:
+        plan.set_cycle(**cycle)
+    for lev, (ty, zc, pipe) in sorted(schedules.items()):
         if lev < plan.level_count():
-            plan.set_schedule(lev, ty, zc)
+            plan.set_schedule(lev, ty, zc, pipe)
 
 
 def residual_fields(V, torch, oracle_mod, delta, d_t, phi_t, alpha, kappa):

@@ -21,7 +21,7 @@ import os
 
 import numpy as np
 import pytest
-from conftest import bench_schedules, install_schedules
+from conftest import bench_cycle, bench_schedules, install_schedules
 
 from paper_1303_0008_amd import inputs as I
 
@@ -89,7 +89,7 @@ def solve_scheduled(torch, V, d_t, w, tol, prec, prec_name):
     """A GRAPH plan with the benchmark's per-level sweep schedules installed."""
     phi = torch.zeros_like(d_t)
     with V.Plan([V.make_grid(w["n"])], V.make_params(w["alpha"], w["kappa"], tol, 200, prec, flags=V.GRAPH)) as p:
-        install_schedules(p, bench_schedules(prec_name, w["n"]))
+        install_schedules(p, bench_schedules(prec_name, w["n"]), bench_cycle(prec_name, w["n"]))
         sched = [p.schedule(l) for l in range(p.level_count())]
         info = p.solve(d_t, phi)[0]
     return phi, info, sched

@@ -183,3 +183,42 @@ def test_patches96_gpu_pipeline(torch_cuda, V):
         assert res[0]["cycles"] <= 30
         outs[prec] = phi.cpu().numpy()
     assert relerr(outs[V.MIXED], outs[V.FP64]) <= 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_cycle_tuner_and_schedules(torch_cuda, V, oracle_mod, prec):
+    """Dirichlet batch: the cycle tuner (including the persistent launch size)
+    and every pipeline shape of the persistent smoother give the oracle's
+    solution."""
+    torch = torch_cuda
+    sizes = [(16, 16, 16), (24, 24, 24), (8, 12, 16), (32, 32, 32)]
+    h = 1.0 / 512
+    grids, deltas, ghosts = _batch(V, oracle_mod, sizes, h, 29)
+    dt = dev(torch, np.concatenate([d.ravel() for d in deltas]))
+    gt = dev(torch, np.concatenate(ghosts))
+    refs = [oracle_mod.solve(deltas[i], 0.1, 1.5, h=h, ghost=ghosts[i])[0] for i in range(len(sizes))]
+    p = V.make_params(0.1, 1.5, 1e-12, 100, V.FP64 if prec == "fp64" else V.MIXED, flags=V.GRAPH)
+    bar = 1e-10 if prec == "fp64" else 1e-8
+
+    def check(plan, label):
+        phi = torch.zeros_like(dt)
+        res = plan.solve(dt, phi, ghost=gt)
+        out = phi.cpu().numpy()
+        off = 0
+        for i, n in enumerate(sizes):
+            m = n[0] * n[1] * n[2]
+            e = relerr(out[off:off + m].reshape(n[2], n[1], n[0]), refs[i])
+            assert res[i]["rms"] <= 1e-11 and e <= bar, (label, n, e)
+            off += m
+        say(f"  {label}: ok")
+
+    with V.Plan(grids, p) as plan:
+        work = torch.zeros_like(dt)
+        best, ms = plan.tune_cycle(dt, work, ghost=gt)
+        say(f"{prec} batch tuned cycle {best} ({ms:.3f} ms)")
+        assert best["batch_blocks"] in (512, 1024, 2048) and best["coarse_tail"] == 0
+        check(plan, "tuned cycle")
+        for pipe in (0, 1):
+            for lev in range(plan.level_count()):
+                plan.set_schedule(lev, 12 if lev == 0 else 4, 6 if lev == 0 else 2, pipe)
+            check(plan, f"pipe {pipe}")

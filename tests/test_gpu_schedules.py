@@ -13,7 +13,7 @@ must give the same iterate.
 """
 import numpy as np
 import pytest
-from conftest import bench_schedules
+from conftest import bench_cycle, bench_schedules
 
 from paper_1303_0008_amd import inputs as I
 
@@ -59,16 +59,19 @@ def case_ref(oracle_mod, name):
     return _ref_cache[name]
 
 
-def solve_with(torch, V, delta, alpha, prec, schedules, flags=0, tol=None, max_cycles=80):
+def solve_with(torch, V, delta, alpha, prec, schedules, flags=0, tol=None, max_cycles=80, cycle=None):
     n2, n1, n0 = delta.shape
     d_t = torch.from_numpy(delta).to("cuda")
     phi = torch.zeros_like(d_t)
     tol = tol if tol is not None else (1e-12 if prec == V.FP64 else 1e-11)
     with V.Plan([V.make_grid((n0, n1, n2))], V.make_params(alpha, 1.5, tol, max_cycles, prec, flags=flags)) as p:
-        for lev, (ty, zc) in schedules.items():
+        if cycle is not None:
+            p.set_cycle(**cycle)
+        for lev, sch in schedules.items():
+            sch = tuple(sch) + (1,) * (3 - len(sch))
             if lev < p.level_count():
-                p.set_schedule(lev, ty, zc)
-                assert p.schedule(lev) == (ty, zc)
+                p.set_schedule(lev, *sch)
+                assert p.schedule(lev) == sch
         info = p.solve(d_t, phi, allow_noconv=max_cycles < 10)[0]
     return phi.cpu().numpy(), info
 
@@ -80,11 +83,12 @@ def test_tile_heights_vs_oracle(torch_cuda, V, oracle_mod, prec, ty):
     bar = 1e-10 if p == V.FP64 else 1e-8
     for name in CASES:
         delta, ref = case_ref(oracle_mod, name)
-        for zc in (2, 16, 32):
-            sched = {0: (ty, zc), 1: (ty, max(2, zc // 4))}
+        for zc, pipe in ((2, 1), (16, 0), (32, 1), (32, 0), (6, 1)):
+            sched = {0: (ty, zc, pipe), 1: (ty, max(2, zc // 4), 1 - pipe)}
             phi, info = solve_with(torch_cuda, V, delta, CASES[name]["alpha"], p, sched)
             e = relerr(phi, ref)
-            say(f"{prec} {name} TY {ty} zc {zc}: err {e:.2e} cycles {info['cycles']} rms {info['rms']:.2e}")
+            say(f"{prec} {name} TY {ty} zc {zc} pipe {pipe}: err {e:.2e} cycles {info['cycles']} "
+                f"rms {info['rms']:.2e}")
             assert e <= bar
 
 
@@ -94,12 +98,13 @@ def test_benchmark_schedules_vs_oracle(torch_cuda, V, oracle_mod, prec):
     levels of smaller grids (same kernel instantiations), against the oracle."""
     p = V.FP64 if prec == "fp64" else V.MIXED
     sched = bench_schedules(prec)
+    cycle = bench_cycle(prec)
     assert 0 in sched and 1 in sched
-    say(prec, "benchmark schedules", sched)
+    say(prec, "benchmark schedules", sched, "cycle", cycle)
     for name in CASES:
         delta, ref = case_ref(oracle_mod, name)
         for flags in (0, V.GRAPH):
-            phi, info = solve_with(torch_cuda, V, delta, CASES[name]["alpha"], p, sched, flags=flags)
+            phi, info = solve_with(torch_cuda, V, delta, CASES[name]["alpha"], p, sched, flags=flags, cycle=cycle)
             e = relerr(phi, ref)
             say(f"  {name} flags {flags}: err {e:.2e} cycles {info['cycles']}")
             assert e <= (1e-10 if p == V.FP64 else 1e-8)
@@ -111,10 +116,11 @@ def test_schedules_give_the_same_iterate(torch_cuda, V, oracle_mod):
     delta, _ = case_ref(oracle_mod, "ragged")
     outs = []
     for ty in (4, 8, 12, 16):
-        phi, info = solve_with(torch_cuda, V, delta, 0.1, V.FP64, {0: (ty, 8), 1: (ty, 2)}, tol=1e-30,
-                               max_cycles=3)
-        assert info["cycles"] == 3
-        outs.append(phi)
+        for pipe in (0, 1):
+            phi, info = solve_with(torch_cuda, V, delta, 0.1, V.FP64, {0: (ty, 8, pipe), 1: (ty, 2, pipe)},
+                                   tol=1e-30, max_cycles=3)
+            assert info["cycles"] == 3
+            outs.append(phi)
     for o in outs[1:]:
         assert np.abs(o - outs[0]).max() <= 1e-12 * np.abs(outs[0]).max()
 
@@ -123,10 +129,17 @@ def test_set_schedule_rejects_bad_arguments(torch_cuda, V):
     with V.Plan([V.make_grid(32)], V.make_params(0.1, 1.5, 1e-8)) as p:
         n = p.level_count()
         assert n >= 1
-        for lev, ty, zc in ((n, 8, 16), (-1, 8, 16), (0, 6, 16), (0, 8, 3), (0, 8, 0), (0, 8, 2048)):
+        for lev, ty, zc, pipe in ((n, 8, 16, 1), (-1, 8, 16, 1), (0, 6, 16, 1), (0, 8, 3, 1), (0, 8, 0, 1),
+                                  (0, 8, 2048, 1), (0, 8, 16, 2), (0, 8, 16, -1)):
             with pytest.raises(V.VmgError) as ei:
-                p.set_schedule(lev, ty, zc)
+                p.set_schedule(lev, ty, zc, pipe)
             assert ei.value.status == V.VMG_EINVAL
+        for bad in (dict(nu1=0, nu2=0), dict(nu1=9), dict(inner_cycles=2), dict(coarse_sweeps=0),
+                    dict(coarse_sweeps=65), dict(coarse_tail=2), dict(batch_blocks=1024)):
+            with pytest.raises(V.VmgError) as ei:
+                p.set_cycle(**bad)
+            assert ei.value.status == V.VMG_EINVAL
+        assert p.cycle() == dict(nu1=2, nu2=2, inner_cycles=0, coarse_sweeps=8, coarse_tail=1, batch_blocks=0)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -180,3 +193,45 @@ def test_graph_first_and_second_solve_same_path(torch_cuda, V):
     assert np.array_equal(runs[0][0], runs[1][0])
     assert runs[0][1]["cycles"] == runs[1][1]["cycles"]
     assert runs[0][2] == runs[1][2]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("cycle", [dict(nu1=1, nu2=1, coarse_sweeps=2, coarse_tail=0),
+                                   dict(nu1=3, nu2=2, coarse_sweeps=16, coarse_tail=1),
+                                   dict(nu1=0, nu2=2, coarse_sweeps=4, coarse_tail=0)])
+def test_cycle_schedules_vs_oracle(torch_cuda, V, oracle_mod, prec, cycle):
+    """Every cycle schedule the tuner may pick solves the same discrete problem."""
+    p = V.FP64 if prec == "fp64" else V.MIXED
+    c = dict(cycle)
+    if p == V.MIXED:
+        c["inner_cycles"] = 1 + c["nu1"] % 3
+    for name in CASES:
+        delta, ref = case_ref(oracle_mod, name)
+        phi, info = solve_with(torch_cuda, V, delta, CASES[name]["alpha"], p, {}, flags=V.GRAPH, cycle=c,
+                               max_cycles=200)
+        e = relerr(phi, ref)
+        say(f"{prec} {name} cycle {c}: err {e:.2e} cycles {info['cycles']}")
+        assert e <= (1e-10 if p == V.FP64 else 1e-8)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_cycle_tuner(torch_cuda, V, oracle_mod, prec):
+    """vmg_plan_tune_cycle installs the fastest converging schedule it timed; the
+    tuned plan's solution matches the oracle."""
+    torch = torch_cuda
+    p = V.FP64 if prec == "fp64" else V.MIXED
+    delta, ref = case_ref(oracle_mod, "cube64")
+    d_t = torch.from_numpy(delta).to("cuda")
+    work = torch.zeros_like(d_t)
+    tol = 1e-12 if p == V.FP64 else 1e-11
+    with V.Plan([V.make_grid(64)], V.make_params(0.2, 1.5, tol, 100, p, flags=V.GRAPH)) as pl:
+        best, ms = pl.tune_cycle(d_t, work)
+        say(f"{prec} tuned cycle {best} ({ms:.3f} ms)")
+        assert pl.cycle() == best and ms > 0
+        assert 1 <= best["nu1"] + best["nu2"] and best["coarse_sweeps"] in (2, 4, 8, 16)
+        assert (best["inner_cycles"] in (1, 2, 3)) if p == V.MIXED else best["inner_cycles"] == 0
+        phi = torch.zeros_like(d_t)
+        info = pl.solve(d_t, phi)[0]
+    e = relerr(phi.cpu().numpy(), ref)
+    say(f"  tuned plan vs oracle: {e:.2e}, {info['cycles']} cycles")
+    assert e <= (1e-10 if p == V.FP64 else 1e-8)
