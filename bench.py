@@ -3,30 +3,35 @@
 Workload (the configuration the headline metric is quoted on): periodic 256^3
 unit box, density contrast from a CIC deposit of 256^3 lattice particles
 displaced by a seeded Zel'dovich field (P(k) ~ k^-1.5, cut at k_Nyquist/4),
-alpha = 0.2, kappa = 1.5, solved from phi = 0 to RMS residual 1e-8.
+alpha = 0.2, kappa = 1.5, mixed precision, solved from phi = 0 to RMS
+residual 1e-8.
 
 One step = one complete solve (all V-cycles, every level, norms and host
 checks) with the inputs already resident in HBM.  ``value`` is smoother cell
 updates (all levels, all sweeps) per second of wall time over the timed
-steps; ``ms_per_step`` is the time to tolerance.
+steps; ``ms_per_step`` is the time to tolerance.  The schedules (sweep tiles
+per level and the cycle schedule) are those of the committed tuning file
+(paper_1303_0008_amd/tune_gfx950.txt, written by ``--retune``).
 
 ``roofline`` describes the dominant kernel, the finest-level fused red-black
-sweep: algorithmic bytes per launch (24 B per cell: read phi, read delta,
-write phi) divided by its average duration, timed here with HIP events around
-back-to-back launches on the plan's stream.
+sweep: algorithmic bytes per launch (24 B per cell FP64: read phi, read delta,
+write phi; 20 B FP32 correction: e, phi~, t0, r in, e out) divided by its
+average duration, measured with HIP events that the library records around
+every finest-level sweep of the timed solves (vmg_plan_time_sweeps) on the
+plan's stream.  ``traffic`` is the HBM bytes per launch from the committed
+FETCH_SIZE / WRITE_SIZE counter runs of ``--traffic-probe`` (null if the
+kernel source changed since).
 
-``results.mass_assign_zeldovich256`` times the mass assignment (triangular-
-shaped cloud and cloud in cell) of the workload's 256^3 particles onto the
-256^3 grid, outside the solve.
+``results`` also holds, outside the timed solves: the other configurations
+(32^3 top-hat, 128^3 lognormal, the 96 refinement patches, the two 512^3
+lognormal sets with the 512^3 finest-sweep roofline), the mass assignment, the
+total force, the truncation-error rule and a multilevel solve.
 
-``results`` also holds, each outside the timed solves: the total potential and
-force kernel at 256^3 (bandwidth in algorithmic bytes), FP64 solves stopped by
-the truncation-error rule (|d| <= |tau|/3), and a multilevel solve of the
-workload with two nested levels of refinements.
-
-``cpu_baseline`` times the CPU oracle (plain FP64 C, one thread) on a bounded
-sample of the same workload: five lexicographic Newton-Gauss-Seidel sweeps
-over the full 256^3 grid.
+``cpu_baseline`` times the CPU oracle (plain FP64 C, single-threaded) on a
+bounded sample of the same workload: one FAS V(2,2) cycle of its own solver
+over the full 256^3 grid from phi = 0, as cell updates (all levels) per
+second; once on one core and once as concurrent independent copies, one per
+host core (the value).
 """
 from __future__ import annotations
 
@@ -75,55 +80,54 @@ def load_traffic(name, kernel):
     return d.get("bytes_per_launch")
 
 
-def time_solves(torch, V, delta, w, prec, steps, warmup, flags, stream, tau_factor=0.0):
-    n = w["n"]
+def time_solves(torch, V, delta, w, prec, steps, warmup, flags, stream, tau_factor=0.0, grids=None, ghost=None,
+                phi0=None, time_sweeps=False):
+    """Solve the same input `steps` times after `warmup` untimed solves; wall time
+    over the timed solves (bracketed by device synchronisation).  With
+    time_sweeps, the library times every finest-level sweep of the timed solves
+    with HIP events on the plan's stream.  Returns (plan, infos, cell updates,
+    seconds, last phi, (summed sweep us, sweep launches))."""
+    grids = grids or [V.make_grid(w["n"])]
     params = V.make_params(w["alpha"], w["kappa"], w["tol"], 100, prec, flags=flags, tau_factor=tau_factor)
-    plan = V.Plan([V.make_grid(n)], params, stream=stream)
-    phis = [torch.zeros_like(delta) for _ in range(steps + warmup)]
+    plan = V.Plan(grids, params, stream=stream)
+    # every solve starts from its own resident copy of the initial guess
+    phis = [torch.zeros_like(delta) if phi0 is None else phi0.clone() for _ in range(steps + warmup)]
     infos = []
     with torch.cuda.stream(stream):
         for i in range(warmup):
-            plan.solve(delta, phis[i])
+            plan.solve(delta, phis[i], ghost=ghost)
+        if time_sweeps:
+            plan.time_sweeps(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         updates = 0
         for i in range(steps):
-            infos.append(plan.solve(delta, phis[warmup + i])[0])
+            r = plan.solve(delta, phis[warmup + i], ghost=ghost)
+            infos.append(r[0] if len(grids) == 1 else r)
             updates += plan.stats()["cell_updates"]
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-    return plan, infos, updates, (t1 - t0), phis[-1]
-
-
-def time_smoother(torch, plan, stream, launches):
-    """Average duration of the finest-level smoother, from HIP events on the plan's stream."""
-    plan.smooth(2)                      # warm
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    plan.smooth(launches)
-    e1.record(stream)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / launches
+        sweeps = plan.sweep_time() if time_sweeps else (0.0, 0)
+    return plan, infos, updates, (t1 - t0), phis[-1], sweeps
 
 
 COPY_BYTES = 256 << 20       # calibration copy: 256 MiB read + 256 MiB written
-# finest-level sweep of each precision: kernel name prefix / suffix (the tile height
-# between them is the autotuner's choice) and algorithmic bytes per cell
-FINEST = {"fp64": ("k_smooth<", ", 0, false>", 24), "mixed": ("k_smooth_corr<", ", 0, false>", 20)}
+# finest-level sweep of each precision: kernel name prefix and algorithmic bytes per cell
+FINEST = {"fp64": ("k_smooth<", 24), "mixed": ("k_smooth_corr<", 20)}
 
 
-def finest_kernel(name, tile_y):
-    pre, post, _ = FINEST[name]
-    return f"{pre}{tile_y}{post}"
+def finest_kernel(name, tile_y, pipe):
+    """Name of the finest-level sweep kernel of a precision for a schedule."""
+    return f"{FINEST[name][0]}{tile_y}, 0, false, {'true' if pipe else 'false'}>"
 
 
 PROBE_SWEEPS = 10
 
 
 def traffic_probe(torch, V, delta, w, launches=PROBE_SWEEPS):
-    """Kernels for the HBM counter runs: finest-level sweeps of both precisions on
-    a solved state, then a plain device copy of COPY_BYTES (calibration)."""
+    """Kernels for the HBM counter runs: finest-level sweeps of both precisions (the
+    tuned schedules) on a solved state, then a plain device copy of COPY_BYTES
+    (calibration)."""
     stream = torch.cuda.Stream()
     for prec in (V.FP64, V.MIXED):
         plan = V.Plan([V.make_grid(w["n"])],
@@ -172,20 +176,21 @@ def traffic_from(fetch_dir, write_dir, n):
         copies = [float(r["Counter_Value"]) for r in tail]
         # counter KiB -> bytes, times the factor that makes the copy read/write COPY_BYTES
         scale = COPY_BYTES / (1024.0 * statistics.median(copies))
-        for name, (pre, post, _) in FINEST.items():
+        for name, (pre, _) in FINEST.items():
             # the probe's closing finest-level sweeps (tuned schedule): the last
-            # PROBE_SWEEPS launches of the precision's sweep kernels, in dispatch order
+            # PROBE_SWEEPS launches of the precision's periodic sweep kernels
+            # (no FAS source, correction read from memory), in dispatch order
             cand = [r for r in rows if r["Kernel_Name"].startswith("void vmg::" + pre)
-                    and r["Kernel_Name"].split("(")[0].endswith(post)][-PROBE_SWEEPS:]
+                    and ", 0, false, " in r["Kernel_Name"].split("(")[0]][-PROBE_SWEEPS:]
             kern = cand[-1]["Kernel_Name"].split("(")[0].replace("void vmg::", "") if cand else None
             if len(cand) < PROBE_SWEEPS or any(not r["Kernel_Name"].startswith("void vmg::" + kern) for r in cand):
-                raise SystemExit(f"{counter}: the closing {pre}..{post} sweeps were not found")
+                raise SystemExit(f"{counter}: the closing {pre}... sweeps were not found")
             vals = [float(r["Counter_Value"]) for r in cand]
             per.setdefault(name, {})[counter] = {"kernel": kern, "kib_per_launch_median": statistics.median(vals),
                                                   "launches": len(vals), "copy_kib": statistics.median(copies),
                                                   "calibration_factor": scale,
                                                   "bytes_per_launch": statistics.median(vals) * 1024.0 * scale}
-    for name, (_, _, bpc) in FINEST.items():
+    for name, (_, bpc) in FINEST.items():
         d = per[name]
         out = {"kernel": d["FETCH_SIZE"]["kernel"], "workload": f"{WORKLOAD} ({n}^3)",
                "kernel_source_hash": kernel_source_hash(),
@@ -256,8 +261,8 @@ def time_total_force(torch, V, delta, w, stream, launches):
 
 def time_tau_rule(torch, V, delta, w, stream, steps):
     """FP64 solves that also stop on the truncation-error rule |d| <= |tau|/3."""
-    plan, infos, updates, dt, _ = time_solves(torch, V, delta, dict(w), V.FP64, steps, 1, V.GRAPH | V.AUTOTUNE,
-                                              stream, tau_factor=1.0 / 3.0)
+    plan, infos, updates, dt, _, _ = time_solves(torch, V, delta, dict(w), V.FP64, steps, 1, V.GRAPH | V.AUTOTUNE,
+                                                 stream, tau_factor=1.0 / 3.0)
     plan.close()
     r = infos[-1]
     log(f"tau rule (1/3): {1e3 * dt / steps:.3f} ms/solve, cycles {r['cycles']}, rms {r['rms']:.3e}, "
@@ -339,17 +344,180 @@ def time_levels(torch, V, delta_np, w, steps):
                     "densities by cloud-in-cell region assignment of the workload's particles"}
 
 
-def cpu_baseline(delta, w, sweeps=5):
+def oracle_cycle_updates(n, nu=4, ncoarse=60):
+    """Cell updates of one FAS V(2,2) cycle of the oracle on a periodic n^3 grid:
+    nu1 + nu2 sweeps on every level above the coarsest (4^3), ncoarse sweeps on it."""
+    upd, m = 0, n
+    while m % 2 == 0 and m // 2 >= 4:
+        upd += nu * m ** 3
+        m //= 2
+    return upd + ncoarse * m ** 3
+
+
+def cpu_baseline(delta, w):
+    """The oracle (single-threaded C) on one FAS V(2,2) cycle of the 256^3 workload
+    from phi = 0: once alone, then as one independent copy per host core at once
+    (threads: the oracle runs in C with the interpreter lock released)."""
+    import threading
     from oracle import oracle as O
-    import numpy as np
-    phi = np.zeros_like(delta)
+    upd = oracle_cycle_updates(w["n"])
+
+    def one():
+        O.solve(delta, w["alpha"], w["kappa"], tol=0.0, max_cycles=1)
+
     t0 = time.perf_counter()
-    O.relax(delta, phi, w["alpha"], w["kappa"], sweeps)
-    dt = time.perf_counter() - t0
-    cells = delta.size * sweeps
-    return {"value": cells / dt, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sweeps} lexicographic Newton-Gauss-Seidel sweeps of the FP64 oracle over the full "
-                      f"{w['n']}^3 workload from phi = 0 ({cells} cell updates, {dt:.1f} s, single thread)"}
+    one()
+    t1 = time.perf_counter() - t0
+    cores = max(1, min(16, os.cpu_count() or 1))
+    ths = [threading.Thread(target=one) for _ in range(cores)]
+    t0 = time.perf_counter()
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    tc = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    log(f"cpu baseline: one cycle {t1:.1f} s on 1 core; {cores} concurrent copies {tc:.1f} s ({model})")
+    return {"value": cores * upd / tc, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"one FAS V(2,2) cycle of the FP64 oracle (lexicographic Newton-Gauss-Seidel, its own "
+                      f"hierarchy down to 4^3, 60 coarsest sweeps) over the full {w['n']}^3 workload from phi = 0, "
+                      f"{upd} cell updates per copy, wall time including the oracle's set-up and residual "
+                      f"evaluations; {cores} independent copies on {cores} threads ran in {tc:.1f} s",
+            "single_core_value": upd / t1, "single_core_seconds": t1, "host_cpu": model,
+            "host_cpu_count": os.cpu_count()}
+
+
+def patches96_inputs(torch, V, I):
+    """The 96 refinement patches (sides {16..64}, h = 1/512) with ghosts and initial
+    guess interpolated trilinearly from the GPU's solution of the 128^3 lognormal
+    parent."""
+    import numpy as np
+    pd = torch.from_numpy(I.workload_delta("lognormal128")).to("cuda")
+    parent_phi, _ = V.solve_field(pd, 0.1, 1.5, tol=1e-10, max_cycles=60)
+    patches = I.patch_set()
+    h = 1.0 / 512
+    grids, origins, off, goff = [], [], 0, 0
+    for pch in patches:
+        grids.append(V.make_grid(pch.n, h, V.DIRICHLET, off, goff))
+        origins.append(pch.origin)
+        off += pch.delta.size
+        goff += V.ghost_count(pch.n)
+    ghost = torch.zeros(goff, dtype=torch.float64, device="cuda")
+    V.fill_ghosts(parent_phi, 1.0 / 128, grids, origins, ghost)
+    guess = torch.zeros(off, dtype=torch.float64, device="cuda")
+    V.fill_interior(parent_phi, 1.0 / 128, grids, origins, guess)
+    dt = torch.from_numpy(np.concatenate([p.delta.ravel() for p in patches])).to("cuda")
+    torch.cuda.synchronize()
+    return grids, dt, ghost, guess
+
+
+def solve_entry(name, infos, updates, dt, steps, sweeps=None, bpc=None, cells=None, kernel=None):
+    last = infos[-1] if isinstance(infos[-1], dict) else max(infos[-1], key=lambda r: r["rms"])
+    out = {"time_to_tol_ms": 1e3 * dt / steps, "cycles": last["cycles"], "rms": last["rms"],
+           "cell_updates_per_s": updates / dt}
+    if sweeps and sweeps[1] > 0:
+        us = sweeps[0] / sweeps[1]
+        gbs = bpc * cells / (us * 1e-6) / 1e9
+        out["finest_sweep"] = {"kernel": kernel, "us_per_launch": us, "launches_timed": sweeps[1],
+                               "algorithmic_bytes_per_launch": bpc * cells, "achieved_gbs": gbs,
+                               "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    log(f"{name}: {out['time_to_tol_ms']:.3f} ms/solve, cycles {out['cycles']}, rms {out['rms']:.2e}" +
+        (f"; finest sweep {out['finest_sweep']['us_per_launch']:.1f} us = {out['finest_sweep']['achieved_gbs']:.0f} GB/s"
+         if "finest_sweep" in out else ""))
+    return out
+
+
+def other_configs(torch, V, I, stream, steps):
+    """The other benchmark configurations, each solved `steps` times (GRAPH,
+    tuned schedules), with the finest sweep timed in the solves where it is
+    bandwidth-relevant (the 96 patches, 512^3)."""
+    import numpy as np
+    res = {}
+    flags = V.GRAPH | V.AUTOTUNE
+    for name, precs in (("tophat32", ("fp64",)), ("lognormal128", ("fp64", "mixed"))):
+        w = dict(I.WORKLOADS[name])
+        d = torch.from_numpy(I.workload_delta(name)).to("cuda")
+        for pn in precs:
+            prec = V.FP64 if pn == "fp64" else V.MIXED
+            plan, infos, upd, dt, _, _ = time_solves(torch, V, d, w, prec, steps, 2, flags, stream)
+            plan.close()
+            res[f"{name}_{pn}"] = solve_entry(f"{name} {pn}", infos, upd, dt, steps)
+    grids, dt_p, ghost, guess = patches96_inputs(torch, V, I)
+    cells = int(dt_p.numel())
+    wp = dict(I.WORKLOADS["patches96"])
+    for pn, prec, bpc, pre in (("mixed", V.MIXED, 20, "k_smooth_corr_batch"), ("fp64", V.FP64, 24, "k_smooth_batch")):
+        plan, infos, upd, dt, _, sw = time_solves(torch, V, dt_p, wp, prec, steps, 2, flags, stream, grids=grids,
+                                                  ghost=ghost, phi0=guess, time_sweeps=True)
+        ty, zc, pipe = plan.schedule(0)
+        plan.close()
+        res[f"patches96_{pn}"] = solve_entry(f"patches96 {pn} ({len(grids)} patches, {cells} cells)", infos, upd, dt,
+                                             steps, sw, bpc, cells,
+                                             f"{pre}<{ty}, ...> (persistent, z chunk {zc}, pipe {pipe})")
+    del dt_p, ghost, guess
+    t = time.perf_counter()
+    d512 = torch.from_numpy(I.workload_delta("lognormal512a")).to("cuda")
+    log(f"lognormal512: generated in {time.perf_counter() - t:.1f} s")
+    n3 = 512 ** 3
+    for name, alpha in (("lognormal512a", 0.2), ("lognormal512b", -0.2)):
+        w = dict(I.WORKLOADS[name])
+        for pn, prec, bpc in (("mixed", V.MIXED, 20), ("fp64", V.FP64, 24)):
+            if name == "lognormal512b":
+                params = V.make_params(w["alpha"], w["kappa"], w["tol"], 30, prec, flags=flags)
+                phi = torch.zeros_like(d512)
+                with torch.cuda.stream(stream):
+                    with V.Plan([V.make_grid(512)], params, stream=stream) as plan:
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        r = plan.solve(d512, phi, allow_noconv=True)[0]
+                        torch.cuda.synchronize()
+                        ms = 1e3 * (time.perf_counter() - t0)
+                res[f"{name}_{pn}"] = {"status": V.STATUS_NAMES[r["status"]], "rms": r["rms"], "cycles": r["cycles"],
+                                       "n_guarded": r["n_guarded"], "ms": ms, "max_cycles": 30}
+                log(f"{name} {pn}: {V.STATUS_NAMES[r['status']]}, rms {r['rms']:.2e} after {r['cycles']} "
+                    f"iterations ({ms:.0f} ms), {r['n_guarded']} guarded cells")
+                del phi
+                continue
+            plan, infos, upd, dt, _, sw = time_solves(torch, V, d512, w, prec, max(2, steps // 4), 1, flags, stream,
+                                                      time_sweeps=True)
+            ty, zc, pipe = plan.schedule(0)
+            plan.close()
+            res[f"{name}_{pn}"] = solve_entry(f"{name} {pn}", infos, upd, dt, max(2, steps // 4), sw, bpc, n3,
+                                              finest_kernel(pn, ty, pipe) + f" (z chunk {zc})")
+            torch.cuda.empty_cache()
+    del d512
+    torch.cuda.empty_cache()
+    return res
+
+
+def retune(torch, V, I, stream, path):
+    """Write a fresh tuning file: sweep schedules of every plan the benchmark and
+    tests replay (VMG_AUTOTUNE) and their cycle schedules (vmg_plan_tune_cycle)."""
+    if os.path.exists(path):
+        os.remove(path)
+    os.environ["VMG_TUNE_CACHE"] = path
+    jobs = []
+    for name in ("zeldovich256", "lognormal128", "tophat32", "lognormal512a"):
+        w = dict(I.WORKLOADS[name])
+        d = torch.from_numpy(I.workload_delta(name)).to("cuda")
+        for prec in ((V.FP64,) if name == "tophat32" else (V.FP64, V.MIXED)):
+            jobs.append((name, [V.make_grid(w["n"])], w, prec, d, None, None))
+    grids, dt_p, ghost, guess = patches96_inputs(torch, V, I)
+    for prec in (V.FP64, V.MIXED):
+        jobs.append(("patches96", grids, dict(I.WORKLOADS["patches96"]), prec, dt_p, ghost, guess))
+    for name, grids, w, prec, d, gh, g0 in jobs:
+        params = V.make_params(w["alpha"], w["kappa"], w["tol"], 100, prec, flags=V.GRAPH | V.AUTOTUNE)
+        with V.Plan(grids, params, stream=stream) as plan:
+            work = torch.zeros_like(d) if g0 is None else g0.clone()
+            best, ms = plan.tune_cycle(d, work, ghost=gh)
+            log(f"retune {name} {'fp64' if prec == V.FP64 else 'mixed'}: schedules "
+                f"{[plan.schedule(l) for l in range(plan.level_count())]}, cycle {best}, {ms:.3f} ms")
+        torch.cuda.empty_cache()
+    log(f"tuning file written: {path}")
 
 
 def main():
@@ -358,15 +526,17 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--smooth-launches", type=int, default=50)
     ap.add_argument("--assign-launches", type=int, default=20,
                     help="timed calls of the mass assignment (0: skip it)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the total-force, truncation-error-rule and multilevel timings")
+                    help="skip the other configurations and the total-force, truncation-error-rule, mass "
+                         "assignment and multilevel timings")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only the kernels of the HBM counter runs (under rocprofv3 --pmc)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc csv outputs of --traffic-probe into profiles/*_traffic.json")
+    ap.add_argument("--retune", metavar="FILE",
+                    help="write a fresh tuning file (sweep and cycle schedules of every configuration) and exit")
     args = ap.parse_args()
     os.environ.setdefault("VMG_TUNE_CACHE", TUNE_CACHE)
     if args.traffic_from:
@@ -378,13 +548,16 @@ def main():
               "(the solver is a single-GPU build).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_1303_0008_amd import inputs as I
     from paper_1303_0008_amd import vmg as V
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     V.load()
+    stream = torch.cuda.Stream()        # default priority
+    if args.retune:
+        retune(torch, V, I, stream, os.path.abspath(args.retune))
+        return
     w = dict(I.WORKLOADS[WORKLOAD])
     t = time.perf_counter()
     delta_np = I.workload_delta(WORKLOAD)
@@ -393,43 +566,45 @@ def main():
     if args.traffic_probe:
         traffic_probe(torch, V, delta, w)
         return
-    stream = torch.cuda.Stream()        # default priority
     torch.cuda.synchronize()
 
     results = {}
     n3 = w["n"] ** 3
     roofs = {}
-    for name, prec, bpc, what in (("fp64", V.FP64, 24, "fused red-black sweep, FP64"),
-                                  ("mixed", V.MIXED, 20, "fused red-black sweep on the FP32 correction")):
-        plan, infos, updates, dt, _ = time_solves(torch, V, delta, w, prec, args.steps, args.warmup,
-                                                  V.GRAPH | V.AUTOTUNE, stream)
-        sched = plan.config()
-        ms = 1e3 * dt / args.steps
-        smooth_ms = time_smoother(torch, plan, stream, args.smooth_launches)
+    for name, prec, what in (("fp64", V.FP64, "fused red-black sweep, FP64"),
+                             ("mixed", V.MIXED, "fused red-black sweep on the FP32 correction")):
+        bpc = FINEST[name][1]
+        # timed solves (the value), then the same number again with every finest
+        # sweep bracketed by HIP events (the roofline)
+        plan, infos, updates, dt, _, _ = time_solves(torch, V, delta, w, prec, args.steps, args.warmup,
+                                                     V.GRAPH | V.AUTOTUNE, stream)
         plan.close()
-        achieved = bpc * n3 / (smooth_ms * 1e-3) / 1e9
-        log(f"{name}: {ms:.3f} ms/solve, cycles {infos[-1]['cycles']}, rms {infos[-1]['rms']:.3e}; "
-            f"smoother {smooth_ms * 1e3:.1f} us/launch = {achieved:.0f} GB/s, "
-            f"{n3 / (smooth_ms * 1e-3) / 1e9:.1f} G cell-updates/s")
-        results[name] = {"time_to_tol_ms": ms, "cycles": infos[-1]["cycles"], "rms": infos[-1]["rms"],
-                         "cell_updates_per_s": updates / dt,
-                         "smoother_us_per_launch": smooth_ms * 1e3,
-                         "smoother_cell_updates_per_s": n3 / (smooth_ms * 1e-3),
-                         "finest_schedule": {"tile_y": sched["tile_y"], "z_chunk": sched["z_chunk"]}}
-        kern = finest_kernel(name, sched["tile_y"])
-        roofs[name] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": load_traffic(f"smooth_{name}_zeldovich256_traffic.json", kern),
-                       "kernel": f"{kern} ({what}, z chunk {sched['z_chunk']})",
-                       "bytes_per_launch": bpc * n3, "us_per_launch": smooth_ms * 1e3}
-    if args.assign_launches > 0:
-        results["mass_assign_zeldovich256"] = time_mass_assign(torch, V, stream, args.assign_launches)
+        plan, infos_t, _, dt_t, _, sw = time_solves(torch, V, delta, w, prec, args.steps, 1, V.GRAPH | V.AUTOTUNE,
+                                                    stream, time_sweeps=True)
+        ty, zc, pipe = plan.schedule(0)
+        sched = [plan.schedule(l) for l in range(plan.level_count())]
+        cyc = plan.cycle()
+        plan.close()
+        kern = finest_kernel(name, ty, pipe)
+        results[name] = solve_entry(name, infos, updates, dt, args.steps, sw, bpc, n3, kern)
+        results[name]["timed_solves_ms_per_step"] = 1e3 * dt_t / args.steps
+        results[name]["schedules"] = {"sweep_per_level": sched, "cycle": cyc}
+        fs = results[name]["finest_sweep"]
+        roofs[name] = {"bound": "hbm", "achieved": fs["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": fs["achieved_gbs"] / HBM_PEAK_GBS,
+                       "traffic": load_traffic(f"smooth_{name}_{WORKLOAD}_traffic.json", kern),
+                       "kernel": f"{kern} ({what}, z chunk {zc})",
+                       "bytes_per_launch": bpc * n3, "us_per_launch": fs["us_per_launch"],
+                       "launches_timed": fs["launches_timed"]}
+    results["mixed_speedup_vs_fp64"] = results["fp64"]["time_to_tol_ms"] / results["mixed"]["time_to_tol_ms"]
     if not args.no_extras:
+        results["configs"] = other_configs(torch, V, I, stream, args.steps)
+        if args.assign_launches > 0:
+            results["mass_assign_zeldovich256"] = time_mass_assign(torch, V, stream, args.assign_launches)
         results["total_force_zeldovich256"] = time_total_force(torch, V, delta, w, stream, 20)
         results["tau_rule_zeldovich256"] = time_tau_rule(torch, V, delta, w, stream, 3)
         results["levels_zeldovich256"] = time_levels(torch, V, delta_np, w, 2)
     head = "mixed"
-    results["mixed_speedup_vs_fp64"] = results["fp64"]["time_to_tol_ms"] / results["mixed"]["time_to_tol_ms"]
     roof = dict(roofs[head])
     roof["fp64_smoother"] = roofs["fp64"]
 
@@ -450,7 +625,8 @@ def main():
                                "cut k_Nyq/4), alpha=0.2, kappa=1.5, tol 1e-8, phi0=0",
                    "n": w["n"], "alpha": w["alpha"], "kappa": w["kappa"], "tol": w["tol"],
                    "precision": "mixed (FP32 correction V-cycle, FP64 defect correction)",
-                   "schedule": "V(2,2) fused red-black, hipGraph, autotuned tiles per level"},
+                   "schedule": "fused red-black sweeps, hipGraph, tuned sweep tiles per level and tuned cycle "
+                               "(tune_gfx950.txt)"},
         "roofline": roof,
         "results": results,
     }

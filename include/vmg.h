@@ -332,6 +332,17 @@ int64_t vmg_ghost_count(const int32_t n[3]);
  * Errors: VMG_EINVAL (no solve yet, sweeps < 0), VMG_EHIP. */
 vmg_status vmg_smooth(vmg_plan *plan, int32_t sweeps);
 
+/* Measurement hook: with enable != 0, every finest-level sweep that later
+ * solves launch is bracketed by HIP events on the plan's stream, and
+ * vmg_plan_sweep_time returns the summed duration (microseconds) and the number
+ * of those launches since this call.  While it is enabled a VMG_GRAPH plan
+ * issues its iterations directly instead of replaying graphs (event nodes of a
+ * graph carry no timestamps on this runtime): the same kernels on the same
+ * data, launched one by one.  enable = 0 stops it and records the graphs again.
+ * Allocates (events, graphs).  Errors: VMG_EINVAL, VMG_EHIP. */
+vmg_status vmg_plan_time_sweeps(vmg_plan *plan, int32_t enable);
+vmg_status vmg_plan_sweep_time(const vmg_plan *plan, double *total_us, int64_t *launches);
+
 /* Counters of the last vmg_solve (host pointers, each may be NULL):
  * cell_updates  = smoother cell updates over all levels and sweeps,
  * finest_sweeps = finest-level smoother sweeps (launches of that kernel),
@@ -374,8 +385,9 @@ vmg_status vmg_plan_set_cycle(vmg_plan *plan, const vmg_cycle *cycle);
 
 /* Cycle-schedule autotuner (Sec. V: "more tunings of the code are needed").
  * Times complete solves of the given input (the arrays of vmg_solve; phi_work
- * is a device array of phi's layout that each trial starts from zero and
- * overwrites) to the plan's tolerance for candidate schedules, by coordinate
+ * is a device array of phi's layout holding the initial guess, from which every
+ * trial starts, and receives the last trial's solution) to the plan's
+ * tolerance for candidate schedules, by coordinate
  * search: nu1/nu2 over (1,1) .. (3,3), then inner cycles 1..3 (mixed), then
  * coarsest sweeps {2, 4, 8, 16}, then the coarse tail on/off (periodic) or the
  * persistent launch size {512, 1024, 2048} (Dirichlet).  A candidate that does

@@ -7,7 +7,8 @@
 //    chunks spread small grids over the chip) x both pipeline shapes, and keep
 //    the fastest.
 //  * The cycle schedule, on request (vmg_plan_tune_cycle): time complete
-//    solves of a given input to the plan's tolerance for candidate nu1/nu2,
+//    solves of a given input (from the caller's initial guess) to the plan's
+//    tolerance for candidate nu1/nu2,
 //    inner cycles, coarsest sweeps, coarse tail and persistent launch size, by
 //    coordinate search, and keep the fastest.
 //
@@ -232,12 +233,28 @@ vmg_status tune_cycle(Plan* P, const double* delta, const double* ghost, const d
     int64_t nphi = 0;
     for (const auto& G : P->grids)
         nphi = std::max<int64_t>(nphi, G.desc.offset + (int64_t)G.desc.n[0] * G.desc.n[1] * G.desc.n[2]);
-    // median of three solves from phi = 0; < 0 when the candidate does not converge
+    // every trial starts from the initial guess phi_work holds on entry
+    double* guess = nullptr;
+    if (hipMalloc((void**)&guess, sizeof(double) * (size_t)nphi) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(VMG_ENOMEM, "tune_cycle: hipMalloc failed");
+    }
+    if (hipMemcpyAsync(guess, phi_work, sizeof(double) * (size_t)nphi, hipMemcpyDeviceToDevice, P->stream) !=
+        hipSuccess) {
+        (void)hipFree(guess);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(VMG_EHIP, "tune_cycle: copy of the initial guess failed");
+    }
+    // median of three solves; < 0 when the candidate does not converge
     auto time_solve = [&](double& ms_out) -> vmg_status {
         std::vector<double> ts;
         std::vector<vmg_result> res(P->grids.size());
         for (int r = 0; r < 3; ++r) {
-            if (launch_fill(phi_work, nphi, 0.0, P->stream) != hipSuccess) return fail(VMG_EHIP, "fill failed");
+            if (hipMemcpyAsync(phi_work, guess, sizeof(double) * (size_t)nphi, hipMemcpyDeviceToDevice, P->stream) !=
+                hipSuccess)
+                return fail(VMG_EHIP, "tune_cycle: copy of the initial guess failed");
             if (hipEventRecord(e0, P->stream) != hipSuccess) return fail(VMG_EHIP, "event record failed");
             const vmg_status st = solve(P, delta, ghost, source, phi_work, res.data());
             if (st == VMG_ENOCONV || st == VMG_ENONFINITE) {
@@ -301,6 +318,8 @@ vmg_status tune_cycle(Plan* P, const double* delta, const double* ghost, const d
             if (c.batch_blocks != best.batch_blocks) st = consider(c);
         }
     }
+    (void)hipStreamSynchronize(P->stream);
+    (void)hipFree(guess);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != VMG_OK) return st;

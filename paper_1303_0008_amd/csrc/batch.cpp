@@ -232,7 +232,9 @@ static hipError_t bcycle(Plan* P, int l) {
         P->cell_updates += (int64_t)P->ncoarse * B.cells_C;
     }
     if (l + 1 >= (int)P->blev.size() || B.cells_A == 0) return hipSuccess;
+    if (l == 0) CKE(sweep_mark(P, true, P->nu1));
     for (int q = 0; q < P->nu1; ++q) CKE(bsmooth(P, l));
+    if (l == 0) CKE(sweep_mark(P, false, P->nu1));
     BatchLevel& C = P->blev[l + 1];
     C.cur = 0;
     CKE(launch_rr_batch(C.d_geom_fine, C.d_geom, C.d_cells, C.ncells, P->coef, B.phi[B.cur], B.delta, bf(P, l),
@@ -242,7 +244,9 @@ static hipError_t bcycle(Plan* P, int l) {
     CKE(bcycle(P, l + 1));
     CKE(launch_prolong_batch(C.d_geom_fine, C.d_geom, C.d_fcells, C.nfcells, B.phi[B.cur], C.phi[C.cur],
                              C.phiold, s));
+    if (l == 0) CKE(sweep_mark(P, true, P->nu2));
     for (int q = 0; q < P->nu2; ++q) CKE(bsmooth(P, l));
+    if (l == 0) CKE(sweep_mark(P, false, P->nu2));
     return hipSuccess;
 }
 
@@ -279,7 +283,9 @@ static hipError_t bcycle_corr(Plan* P, int l) {
         P->cell_updates += (int64_t)P->ncoarse * B.cells_C;
     }
     if (l + 1 >= (int)P->blev.size() || B.cells_A == 0) return hipSuccess;
+    if (l == 0) CKE(sweep_mark(P, true, P->nu1));
     for (int q = 0; q < P->nu1; ++q) CKE(bsmooth_corr(P, l));
+    if (l == 0) CKE(sweep_mark(P, false, P->nu1));
     BatchLevel& C = P->blev[l + 1];
     C.ecur = 0;
     CKE(launch_rr_corr_batch(C.d_geom_fine, C.d_geom, C.d_cells, C.ncells, cf, B.e[B.ecur], B.pt, B.t0, B.r,
@@ -289,7 +295,9 @@ static hipError_t bcycle_corr(Plan* P, int l) {
     CKE(bcycle_corr(P, l + 1));
     CKE(launch_prolong_corr_batch(C.d_geom_fine, C.d_geom, C.d_fcells, C.nfcells, B.e[B.ecur], C.e[C.ecur],
                                   C.eold, s));
+    if (l == 0) CKE(sweep_mark(P, true, P->nu2));
     for (int q = 0; q < P->nu2; ++q) CKE(bsmooth_corr(P, l));
+    if (l == 0) CKE(sweep_mark(P, false, P->nu2));
     return hipSuccess;
 }
 

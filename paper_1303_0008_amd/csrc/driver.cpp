@@ -169,6 +169,7 @@ static void release_graphs(Plan* P);
 
 void destroy_plan(Plan* P) {
     release_graphs(P);
+    for (hipEvent_t ev : P->tev) (void)hipEventDestroy(ev);
     for (void* a : P->allocs) (void)hipFree(a);
     if (P->host_norm) (void)hipHostFree(P->host_norm);
     if (P->own_stream) (void)hipStreamDestroy(P->own_stream);
@@ -180,6 +181,28 @@ void destroy_plan(Plan* P) {
 static const double* level_f(const Plan* P, const GridState& G, int l) {
     if (l > 0) return G.lev[l].f;
     return P->has_source ? G.lev[0].f : nullptr;
+}
+
+hipError_t sweep_mark(Plan* P, bool begin, int launches) {
+    if (!P->time_sweeps || !P->timing_active || launches <= 0 || P->tev_used >= (int)P->tev.size() / 2)
+        return hipSuccess;
+    if (begin) return hipEventRecord(P->tev[2 * P->tev_used], P->stream);
+    P->tev_count[P->tev_used] = launches;
+    return hipEventRecord(P->tev[2 * P->tev_used++ + 1], P->stream);
+}
+
+// accumulate the durations of the first n recorded runs of sweep launches
+// (after the stream has finished them)
+static hipError_t collect_sweeps(Plan* P, int n) {
+    for (int i = 0; i < n; ++i) {
+        float ms = 0.0f;
+        hipError_t e = hipEventElapsedTime(&ms, P->tev[2 * i], P->tev[2 * i + 1]);
+        if (e != hipSuccess) return e;
+        P->sweep_us += 1e3 * ms;
+        P->sweep_n += P->tev_count[i];
+    }
+    P->tev_used = 0;
+    return hipSuccess;
 }
 
 static hipError_t smooth_level(Plan* P, GridState& G, int l) {
@@ -246,8 +269,10 @@ static hipError_t vcycle(Plan* P, GridState& G, int l);
 static hipError_t vcycle_head(Plan* P, GridState& G, int l, NormOut* norm) {
     LevelBuf& L = G.lev[l];
     hipError_t e;
+    if (l == 0 && (e = sweep_mark(P, true, P->nu1)) != hipSuccess) return e;
     for (int s = 0; s < P->nu1; ++s)
         if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
+    if (l == 0 && (e = sweep_mark(P, false, P->nu1)) != hipSuccess) return e;
     LevelBuf& C = G.lev[l + 1];
     C.cur = 0;
     int nb = 0, nbc = 0;
@@ -272,8 +297,10 @@ static hipError_t vcycle_tail(Plan* P, GridState& G, int l) {
     if ((e = vcycle(P, G, l + 1)) != hipSuccess) return e;
     if ((e = launch_prolong(L.g, C.g, L.phi[L.cur], C.phi[C.cur], C.phiold, P->stream)) != hipSuccess)
         return e;
+    if (l == 0 && (e = sweep_mark(P, true, P->nu2)) != hipSuccess) return e;
     for (int s = 0; s < P->nu2; ++s)
         if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
+    if (l == 0 && (e = sweep_mark(P, false, P->nu2)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -384,9 +411,14 @@ static vmg_status capture_graph(Plan* P, int src, int parity) {
     }
     const int64_t cu = P->cell_updates, fs = P->finest_sweeps;
     hipGraph_t graph;
+    P->tev_used = 0;
+    P->timing_active = true;
     hipError_t e0 = hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal);
     hipError_t e = e0 == hipSuccess ? enqueue_iteration(P) : e0;
     hipError_t e2 = e0 == hipSuccess ? hipStreamEndCapture(P->stream, &graph) : e0;
+    P->timing_active = false;
+    P->graph_tev[src][parity] = P->tev_used;
+    P->tev_used = 0;
     P->graph_updates[src][parity] = P->cell_updates - cu;
     P->graph_finest[src][parity] = P->finest_sweeps - fs;
     P->cell_updates = cu;
@@ -408,7 +440,9 @@ static vmg_status capture_graph(Plan* P, int src, int parity) {
 // called when a plan is created and again when its schedule changes.
 vmg_status capture_graphs(Plan* P) {
     release_graphs(P);
-    if (!(P->params.flags & VMG_GRAPH)) return VMG_OK;
+    // event-record nodes of a graph carry no timestamps on this runtime, so a
+    // plan that times its sweeps issues its iterations directly
+    if (!(P->params.flags & VMG_GRAPH) || P->time_sweeps) return VMG_OK;
     for (int src = 0; src < 2; ++src)
         for (int q = 0; q < 2; ++q) {
             vmg_status st = capture_graph(P, src, q);
@@ -452,10 +486,12 @@ static vmg_status run_cycle(Plan* P) {
     if (!(P->params.flags & VMG_GRAPH) || !P->graph_ok[src][parity]) {
         CKH(enqueue_iteration(P));
         CKH(hipStreamSynchronize(P->stream));
+        if (P->time_sweeps) CKH(collect_sweeps(P, P->tev_used));
         return VMG_OK;
     }
     CKH(hipGraphLaunch(P->graph[src][parity], P->stream));
     CKH(hipStreamSynchronize(P->stream));
+    if (P->time_sweeps) CKH(collect_sweeps(P, P->graph_tev[src][parity]));
     P->cell_updates += P->graph_updates[src][parity];
     P->finest_sweeps += P->graph_finest[src][parity];
     // the replayed iteration leaves the finest phi in the other buffer when it
@@ -476,6 +512,7 @@ static vmg_status run_cycle(Plan* P) {
 vmg_status solve(Plan* P, const double* delta, const double* ghost, const double* source, double* phi,
                  vmg_result* out) {
     hipStream_t s = P->stream;
+    P->timing_active = false;
     P->has_source = source != nullptr;
     P->cell_updates = 0;
     P->finest_sweeps = 0;
@@ -557,9 +594,12 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
         }
         return true;
     };
+    P->timing_active = true;
+    P->tev_used = 0;
     if (shifted_cycles(P) && !converged()) {
         CKH(enqueue_first_head(P));
         CKH(hipStreamSynchronize(s));
+        if (P->time_sweeps) CKH(collect_sweeps(P, P->tev_used));
     }
     while (!converged()) {
         if (cycles >= P->params.max_cycles) {
@@ -586,6 +626,7 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
             break;
         }
     }
+    P->timing_active = false;
     // ---- outputs -------------------------------------------------------------
     if (P->batched) CKH(batch_outputs(P, phi));
     for (int gi = 0; gi < ng; ++gi) {
@@ -1054,6 +1095,31 @@ vmg_status vmg_plan_schedule(const vmg_plan* plan, int32_t level, int32_t* tile_
     if (tile_y) *tile_y = c.ty;
     if (z_chunk) *z_chunk = c.zc;
     if (pipe) *pipe = c.pipe;
+    return VMG_OK;
+}
+
+vmg_status vmg_plan_time_sweeps(vmg_plan* plan, int32_t enable) {
+    g_err.clear();
+    if (!plan) return fail(VMG_EINVAL, "null plan");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    CKH(hipStreamSynchronize(P->stream));
+    if (enable && P->tev.empty()) {
+        P->tev.assign(2 * 256, nullptr);
+        P->tev_count.assign(256, 0);
+        for (auto& ev : P->tev) CKH(hipEventCreate(&ev));
+    }
+    P->time_sweeps = enable != 0;
+    P->sweep_us = 0.0;
+    P->sweep_n = 0;
+    P->tev_used = 0;
+    return capture_graphs(P);
+}
+
+vmg_status vmg_plan_sweep_time(const vmg_plan* plan, double* total_us, int64_t* launches) {
+    if (!plan) return fail(VMG_EINVAL, "null plan");
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (total_us) *total_us = P->sweep_us;
+    if (launches) *launches = P->sweep_n;
     return VMG_OK;
 }
 

@@ -106,8 +106,13 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e, bool f
         P->cell_updates += (int64_t)P->ncoarse * L.g.ncell;
         return e;
     }
-    for (int s = 0; s < P->nu1; ++s)
+    // the sweep that reads no correction (zero_e) is another kernel: it is not timed
+    const int t1 = zero_e ? P->nu1 - 1 : P->nu1;
+    for (int s = 0; s < P->nu1; ++s) {
+        if (l == 0 && s == P->nu1 - t1 && (e = sweep_mark(P, true, t1)) != hipSuccess) return e;
         if ((e = smooth_corr_level(P, G, l, zero_e && s == 0)) != hipSuccess) return e;
+    }
+    if (l == 0 && t1 > 0 && (e = sweep_mark(P, false, t1)) != hipSuccess) return e;
     LevelBuf& C = G.lev[l + 1];
     const CoefF cc = make_coef_f(P->coef, C.g.h);
     C.ecur = 0;
@@ -130,8 +135,10 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e, bool f
         return e;
     if ((e = inner_vcycle(P, G, l + 1, false, fresh_base)) != hipSuccess) return e;
     if ((e = launch_prolong_corr(L.g, C.g, L.e[L.ecur], C.e[C.ecur], C.eold, P->stream)) != hipSuccess) return e;
+    if (l == 0 && (e = sweep_mark(P, true, P->nu2)) != hipSuccess) return e;
     for (int s = 0; s < P->nu2; ++s)
         if ((e = smooth_corr_level(P, G, l)) != hipSuccess) return e;
+    if (l == 0 && (e = sweep_mark(P, false, P->nu2)) != hipSuccess) return e;
     return hipSuccess;
 }
 

@@ -94,6 +94,16 @@ struct Plan {
     int64_t graph_finest[2][2] = {{0, 0}, {0, 0}};
     int64_t cell_updates = 0, finest_sweeps = 0;
     std::vector<void*> allocs;
+    // finest-sweep timing (vmg_plan_time_sweeps): event pairs around every
+    // finest-level sweep launched by a solve, also recorded into the graphs
+    bool time_sweeps = false;
+    bool timing_active = false;            // inside a solve or a graph capture
+    std::vector<hipEvent_t> tev;           // [2i] before, [2i+1] after run i of consecutive sweeps
+    std::vector<int> tev_count;            // sweeps in run i
+    int tev_used = 0;                      // pairs recorded since the last collection
+    int graph_tev[2][2] = {{0, 0}, {0, 0}};
+    double sweep_us = 0.0;
+    int64_t sweep_n = 0;
     // batched Dirichlet plans
     bool tuned_from_cache = false;
     struct TuneEntry { int level; SmoothCfg cfg; double us; };
@@ -109,6 +119,9 @@ struct Plan {
 };
 
 vmg_status fail(vmg_status st, const std::string& msg);
+// bracket a run of `launches` consecutive finest-level sweeps with timing
+// events (no-op unless enabled)
+hipError_t sweep_mark(Plan* P, bool begin, int launches);
 CoefF make_coef_f(const Coef& c, double h);
 vmg_status alloc_mixed(Plan* P);
 hipError_t enqueue_outer(Plan* P);          // one mixed-precision outer iteration (+ norms to host)

@@ -6,7 +6,8 @@ current HIP stream.  The functions mirror the C ABI in ``include/vmg.h``:
 ``plan_create``, ``solve``, ``plan_destroy``, ``last_error``,
 ``solve_periodic``, ``residual``, ``fill_ghosts``, ``fill_interior``, ``ghost_count``,
 ``smooth``, ``plan_stats``, ``plan_config``, ``plan_level_count``, ``plan_set_schedule``,
-``plan_schedule``, ``plan_get_cycle``, ``plan_set_cycle``, ``plan_tune_cycle``, ``total_force``, ``mass_assign``, ``mass_assign_region``,
+``plan_schedule``, ``plan_get_cycle``, ``plan_set_cycle``, ``plan_tune_cycle``, ``plan_time_sweeps``,
+``plan_sweep_time``, ``total_force``, ``mass_assign``, ``mass_assign_region``,
 ``solve_levels``; ``Plan`` and ``LevelsPlan`` wrap plan handles.
 
 There is no fallback: if the library is missing or no GPU is present the
@@ -74,7 +75,7 @@ EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
            "vmg_mass_assign", "vmg_mass_assign_workspace", "vmg_solve_levels", "vmg_levels_create",
            "vmg_levels_solve", "vmg_levels_destroy", "vmg_mass_assign_region", "vmg_plan_level_count",
            "vmg_plan_set_schedule", "vmg_plan_schedule", "vmg_mass_assign_noalloc", "vmg_plan_get_cycle",
-           "vmg_plan_set_cycle", "vmg_plan_tune_cycle"]
+           "vmg_plan_set_cycle", "vmg_plan_tune_cycle", "vmg_plan_time_sweeps", "vmg_plan_sweep_time"]
 
 _lib = None
 
@@ -125,6 +126,8 @@ def load():
     L.vmg_plan_level_count.restype = ctypes.c_int32
     L.vmg_plan_set_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.vmg_plan_schedule.argtypes = [vp, ctypes.c_int32, i32p, i32p, i32p]
+    L.vmg_plan_time_sweeps.argtypes = [vp, ctypes.c_int32]
+    L.vmg_plan_sweep_time.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
     L.vmg_plan_get_cycle.argtypes = [vp, P(Cycle)]
     L.vmg_plan_set_cycle.argtypes = [vp, P(Cycle)]
     L.vmg_plan_tune_cycle.argtypes = [vp, vp, vp, vp, vp, P(Cycle), P(ctypes.c_double)]
@@ -429,6 +432,18 @@ def plan_schedule(handle, level):
     return a.value, b.value, c.value
 
 
+def plan_time_sweeps(handle, enable=True):
+    """vmg_plan_time_sweeps: time every finest-level sweep of later solves with HIP events."""
+    _check(load().vmg_plan_time_sweeps(ctypes.c_void_p(handle), 1 if enable else 0))
+
+
+def plan_sweep_time(handle):
+    """vmg_plan_sweep_time: (summed microseconds, launches) of the timed finest sweeps."""
+    us, n = ctypes.c_double(), ctypes.c_int64()
+    _check(load().vmg_plan_sweep_time(ctypes.c_void_p(handle), ctypes.byref(us), ctypes.byref(n)))
+    return us.value, n.value
+
+
 def plan_get_cycle(handle):
     """vmg_plan_get_cycle: the plan's cycle schedule as a dict."""
     c = Cycle()
@@ -485,6 +500,12 @@ class Plan:
 
     def schedule(self, level):
         return plan_schedule(self.handle, level)
+
+    def time_sweeps(self, enable=True):
+        plan_time_sweeps(self.handle, enable)
+
+    def sweep_time(self):
+        return plan_sweep_time(self.handle)
 
     def cycle(self):
         return plan_get_cycle(self.handle)
