@@ -180,11 +180,11 @@ vmg_status autotune(Plan* P) {
         }
         std::vector<SmoothCfg> cands;
         const int tys[4] = {8, 4, 16, 12};
-        const int zf[3] = {16, 8, 32}, zcoarse[4] = {16, 8, 4, 2};
+        const int zf[4] = {16, 8, 32, 64}, zcoarse[4] = {16, 8, 4, 2};
         for (int pipe = 1; pipe >= 0; --pipe)
             for (int a = 0; a < 4; ++a) {
                 if (l == 0)
-                    for (int b = 0; b < 3; ++b) cands.push_back(SmoothCfg{tys[a], zf[b], pipe});
+                    for (int b = 0; b < 4; ++b) cands.push_back(SmoothCfg{tys[a], zf[b], pipe});
                 else
                     for (int b = 0; b < 4; ++b) cands.push_back(SmoothCfg{tys[a], zcoarse[b], pipe});
             }

@@ -38,8 +38,13 @@
 
 namespace vmg {
 
-// Threads per block of the fused sweep.
-constexpr int SNT = 256;
+// Threads per block of the fused sweep: one thread per black cell of a tile
+// plane (32 TY) for the tall tiles, 256 for the short ones, whose tiles have
+// fewer cells than that.
+#ifndef VMG_WIDE_TY
+#define VMG_WIDE_TY 16
+#endif
+constexpr int sweep_threads(int ty) { return ty >= VMG_WIDE_TY ? 32 * ty : 256; }
 
 // Pipeline shape (a run-time choice of the schedule, SmoothCfg::pipe).  With
 // DEFER the black phase of a step works two planes behind its red phase
@@ -57,10 +62,14 @@ constexpr int sweep_slots(bool defer) { return defer ? 4 : 3; }
 constexpr int sweep_lds_bytes(int ty, bool defer) {
     return sweep_slots(defer) * ((TX + 4) * (ty + 4) + (TX + 2) * (ty + 2)) * 8;
 }
-constexpr int sweep_waves(int ty, bool defer) {
+constexpr int sweep_blocks_per_cu(int ty, bool defer) {
     return (160 * 1024) / sweep_lds_bytes(ty, defer) >= 4
                ? 4
                : ((160 * 1024) / sweep_lds_bytes(ty, defer) < 1 ? 1 : (160 * 1024) / sweep_lds_bytes(ty, defer));
+}
+// waves per SIMD (the launch bound): the resident blocks' waves over the CU's 4 SIMDs
+constexpr int sweep_waves(int ty, bool defer) {
+    return (sweep_blocks_per_cu(ty, defer) * (sweep_threads(ty) / 64) + 3) / 4;
 }
 
 // Neighbourhood of a cell read from a parity-split LDS plane set.  `c` is the

@@ -95,7 +95,7 @@ struct SmoothK {
 };
 
 template <int TY, int DIR, bool HAS_F, bool DEFER>
-__global__ void __launch_bounds__(SNT, sweep_waves(TY, DEFER)) k_smooth(SmoothArgs a) {
+__global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER)) k_smooth(SmoothArgs a) {
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % a.tiles_x;
     b /= a.tiles_x;
@@ -104,14 +104,14 @@ __global__ void __launch_bounds__(SNT, sweep_waves(TY, DEFER)) k_smooth(SmoothAr
     const int z0 = ch * a.zc;
     if (z0 >= a.g.n2) return;
     const SmoothK<HAS_F> k(a, a.g, DIR == 0);
-    fused_sweep<TY, DIR, SNT, DEFER>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
+    fused_sweep<TY, DIR, sweep_threads(TY), DEFER>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
 }
 
 // Persistent sweep over a (grid, tile x, tile y, z chunk) work list: every
 // Dirichlet grid of a batch at one level in one launch.  `proto` carries the
 // pooled level buffers and coefficients; geoms[w.x] locates grid w.x in them.
 template <int TY, bool HAS_F, bool DEFER>
-__global__ void __launch_bounds__(SNT, sweep_waves(TY, DEFER)) k_smooth_batch(SmoothArgs proto, const Geom* __restrict__ geoms,
+__global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER)) k_smooth_batch(SmoothArgs proto, const Geom* __restrict__ geoms,
                                                      const int4* __restrict__ items, int nitems) {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int4 w = items[it];
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(SNT, sweep_waves(TY, DEFER)) k_smooth_batch(Sm
         a.g = geoms[w.x];
         const int z0 = w.w * a.zc;
         const SmoothK<HAS_F> k(a, a.g, false);
-        fused_sweep<TY, 1, SNT, DEFER>(k, a.g, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
+        fused_sweep<TY, 1, sweep_threads(TY), DEFER>(k, a.g, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
     }
 }
 
@@ -1084,11 +1084,11 @@ static hipError_t smooth_launch(const SmoothArgs& a, bool defer, hipStream_t s) 
     const int chunks = (a.g.n2 + a.zc - 1) / a.zc;
     const int nb = a.tiles_x * a.tiles_y * chunks;
     if (a.f) {
-        if (defer) hipLaunchKernelGGL((k_smooth<TY, DIR, true, true>), dim3(nb), dim3(SNT), 0, s, a);
-        else hipLaunchKernelGGL((k_smooth<TY, DIR, true, false>), dim3(nb), dim3(SNT), 0, s, a);
+        if (defer) hipLaunchKernelGGL((k_smooth<TY, DIR, true, true>), dim3(nb), dim3(sweep_threads(TY)), 0, s, a);
+        else hipLaunchKernelGGL((k_smooth<TY, DIR, true, false>), dim3(nb), dim3(sweep_threads(TY)), 0, s, a);
     } else {
-        if (defer) hipLaunchKernelGGL((k_smooth<TY, DIR, false, true>), dim3(nb), dim3(SNT), 0, s, a);
-        else hipLaunchKernelGGL((k_smooth<TY, DIR, false, false>), dim3(nb), dim3(SNT), 0, s, a);
+        if (defer) hipLaunchKernelGGL((k_smooth<TY, DIR, false, true>), dim3(nb), dim3(sweep_threads(TY)), 0, s, a);
+        else hipLaunchKernelGGL((k_smooth<TY, DIR, false, false>), dim3(nb), dim3(sweep_threads(TY)), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -1336,10 +1336,10 @@ template <int TY>
 static void smooth_batch_ty(const SmoothArgs& proto, const Geom* geoms, const int4* items, int nitems, int nb,
                             bool defer, hipStream_t s) {
     const bool f = proto.f != nullptr;
-    if (f && defer) hipLaunchKernelGGL((k_smooth_batch<TY, true, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
-    else if (f) hipLaunchKernelGGL((k_smooth_batch<TY, true, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
-    else if (defer) hipLaunchKernelGGL((k_smooth_batch<TY, false, true>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
-    else hipLaunchKernelGGL((k_smooth_batch<TY, false, false>), dim3(nb), dim3(SNT), 0, s, proto, geoms, items, nitems);
+    if (f && defer) hipLaunchKernelGGL((k_smooth_batch<TY, true, true>), dim3(nb), dim3(sweep_threads(TY)), 0, s, proto, geoms, items, nitems);
+    else if (f) hipLaunchKernelGGL((k_smooth_batch<TY, true, false>), dim3(nb), dim3(sweep_threads(TY)), 0, s, proto, geoms, items, nitems);
+    else if (defer) hipLaunchKernelGGL((k_smooth_batch<TY, false, true>), dim3(nb), dim3(sweep_threads(TY)), 0, s, proto, geoms, items, nitems);
+    else hipLaunchKernelGGL((k_smooth_batch<TY, false, false>), dim3(nb), dim3(sweep_threads(TY)), 0, s, proto, geoms, items, nitems);
 }
 
 hipError_t launch_smooth_batch(const SmoothArgs& proto, const Geom* geoms, const int4* items, int nitems,

@@ -104,7 +104,7 @@ struct CorrK {
 };
 
 template <int TY, int DIR, bool ZERO_E, bool DEFER>
-__global__ void __launch_bounds__(SNT, sweep_waves(TY, DEFER)) k_smooth_corr(CorrArgs a) {
+__global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER)) k_smooth_corr(CorrArgs a) {
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % a.tiles_x;
     b /= a.tiles_x;
@@ -113,12 +113,12 @@ __global__ void __launch_bounds__(SNT, sweep_waves(TY, DEFER)) k_smooth_corr(Cor
     const int z0 = ch * a.zc;
     if (z0 >= a.g.n2) return;
     const CorrK<ZERO_E> k(a, DIR == 0);
-    fused_sweep<TY, DIR, SNT, DEFER>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
+    fused_sweep<TY, DIR, sweep_threads(TY), DEFER>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
 }
 
 // persistent sweep over a (grid, tile x, tile y, z chunk) work list (Dirichlet batches)
 template <int TY, bool DEFER>
-__global__ void __launch_bounds__(SNT, sweep_waves(TY, DEFER)) k_smooth_corr_batch(CorrArgs proto, const Geom* __restrict__ geoms,
+__global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER)) k_smooth_corr_batch(CorrArgs proto, const Geom* __restrict__ geoms,
                                                           const int4* __restrict__ items, int nitems) {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int4 w = items[it];
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(SNT, sweep_waves(TY, DEFER)) k_smooth_corr_bat
         a.c.h2 = (float)(a.g.h * a.g.h);
         const int z0 = w.w * a.zc;
         const CorrK<false> k(a, false);
-        fused_sweep<TY, 1, SNT, DEFER>(k, a.g, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
+        fused_sweep<TY, 1, sweep_threads(TY), DEFER>(k, a.g, w.y * TX, w.z * TY, z0, min(z0 + a.zc, a.g.n2));
     }
 }
 
@@ -1024,10 +1024,10 @@ __global__ void k_update_batch(const Geom* __restrict__ gs, const int2* __restri
 template <int TY, int DIR>
 static hipError_t corr_launch(const CorrArgs& a, bool zero_in, bool defer, hipStream_t s) {
     const dim3 nb(a.tiles_x * a.tiles_y * ((a.g.n2 + a.zc - 1) / a.zc));
-    if (zero_in && defer) hipLaunchKernelGGL((k_smooth_corr<TY, DIR, true, true>), nb, dim3(SNT), 0, s, a);
-    else if (zero_in) hipLaunchKernelGGL((k_smooth_corr<TY, DIR, true, false>), nb, dim3(SNT), 0, s, a);
-    else if (defer) hipLaunchKernelGGL((k_smooth_corr<TY, DIR, false, true>), nb, dim3(SNT), 0, s, a);
-    else hipLaunchKernelGGL((k_smooth_corr<TY, DIR, false, false>), nb, dim3(SNT), 0, s, a);
+    if (zero_in && defer) hipLaunchKernelGGL((k_smooth_corr<TY, DIR, true, true>), nb, dim3(sweep_threads(TY)), 0, s, a);
+    else if (zero_in) hipLaunchKernelGGL((k_smooth_corr<TY, DIR, true, false>), nb, dim3(sweep_threads(TY)), 0, s, a);
+    else if (defer) hipLaunchKernelGGL((k_smooth_corr<TY, DIR, false, true>), nb, dim3(sweep_threads(TY)), 0, s, a);
+    else hipLaunchKernelGGL((k_smooth_corr<TY, DIR, false, false>), nb, dim3(sweep_threads(TY)), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1198,8 +1198,8 @@ hipError_t launch_smooth_corr_batch(const CoefF& c, const float* ein, float* eou
     const bool d = cfg.pipe != 0;
 #define VMG_CORR_BATCH(T)                                                                                   \
     do {                                                                                                   \
-        if (d) hipLaunchKernelGGL((k_smooth_corr_batch<T, true>), nb, dim3(SNT), 0, s, a, geoms, items, nitems); \
-        else hipLaunchKernelGGL((k_smooth_corr_batch<T, false>), nb, dim3(SNT), 0, s, a, geoms, items, nitems);  \
+        if (d) hipLaunchKernelGGL((k_smooth_corr_batch<T, true>), nb, dim3(sweep_threads(T)), 0, s, a, geoms, items, nitems); \
+        else hipLaunchKernelGGL((k_smooth_corr_batch<T, false>), nb, dim3(sweep_threads(T)), 0, s, a, geoms, items, nitems);  \
     } while (0)
     if (cfg.ty == 4) VMG_CORR_BATCH(4);
     else if (cfg.ty == 16) VMG_CORR_BATCH(16);
