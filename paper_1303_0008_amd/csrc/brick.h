@@ -27,6 +27,12 @@
 //   k.template update<W>(Pm, Pc, Pp, c, o, src)   updated cell from its neighbourhood
 //   k.out_b(O, bo, cell)    write the output state at byte offset bo (out of range:
 //                           dropped)
+// and, for a sweep that first adds the prolonged coarse correction (PRO):
+//   K::Corr                 type of the coarse correction u^H - u^H_old
+//   k.gc                    the coarse level's geometry
+//   k.coarse_plane(zo), k.coarse_b(C, bo)   u^H - u^H_old of coarse plane zo at
+//                           byte offset bo
+//   k.add_corr(cell, v)     the cell with the correction v added to its state
 // Every global load and store is issued by every lane (masked cells use an
 // out-of-range offset), so the loads in flight for later steps are never
 // waited for early.
@@ -59,17 +65,23 @@ constexpr int sweep_slots(bool defer) { return defer ? 4 : 3; }
 // kernels are built for: as many blocks per CU as that LDS allows (160 KB per
 // CU), at most 4, so that the register budget matches the occupancy the LDS
 // permits.
-constexpr int sweep_lds_bytes(int ty, bool defer) {
-    return sweep_slots(defer) * ((TX + 4) * (ty + 4) + (TX + 2) * (ty + 2)) * 8;
+// With the prolongation folded in (pro), four coarse correction planes of the
+// tile's window ((TX/2 + 4) x (ty/2 + 4) cells, counted at 8 bytes) are added.
+constexpr int PRO_SLOTS = 4;
+constexpr int pro_window(int ty) { return (TX / 2 + 4) * (ty / 2 + 4); }
+constexpr int sweep_lds_bytes(int ty, bool defer, bool pro = false) {
+    return sweep_slots(defer) * ((TX + 4) * (ty + 4) + (TX + 2) * (ty + 2)) * 8 +
+           (pro ? PRO_SLOTS * pro_window(ty) * 8 : 0);
 }
-constexpr int sweep_blocks_per_cu(int ty, bool defer) {
-    return (160 * 1024) / sweep_lds_bytes(ty, defer) >= 4
+constexpr int sweep_blocks_per_cu(int ty, bool defer, bool pro = false) {
+    return (160 * 1024) / sweep_lds_bytes(ty, defer, pro) >= 4
                ? 4
-               : ((160 * 1024) / sweep_lds_bytes(ty, defer) < 1 ? 1 : (160 * 1024) / sweep_lds_bytes(ty, defer));
+               : ((160 * 1024) / sweep_lds_bytes(ty, defer, pro) < 1 ? 1
+                                                                     : (160 * 1024) / sweep_lds_bytes(ty, defer, pro));
 }
 // waves per SIMD (the launch bound): the resident blocks' waves over the CU's 4 SIMDs
-constexpr int sweep_waves(int ty, bool defer) {
-    return (sweep_blocks_per_cu(ty, defer) * (sweep_threads(ty) / 64) + 3) / 4;
+constexpr int sweep_waves(int ty, bool defer, bool pro = false) {
+    return (sweep_blocks_per_cu(ty, defer, pro) * (sweep_threads(ty) / 64) + 3) / 4;
 }
 
 // Neighbourhood of a cell read from a parity-split LDS plane set.  `c` is the
@@ -91,9 +103,10 @@ __device__ __forceinline__ void nb_split(const T* __restrict__ Pm, const T* __re
     v.ymzp = Pp[o - W];     v.ypzp = Pp[o + W];
 }
 
-template <int TY, int DIR, int NTH, bool DEFER, typename K>
+template <int TY, int DIR, int NTH, bool DEFER, bool PRO = false, typename K>
 __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int x0, const int y0, const int z0,
                                             const int z1) {
+    static_assert(!(PRO && DIR), "the folded prolongation is for periodic grids");
     using Cell = typename K::Cell;
     using Src = typename K::Src;
     static_assert(sizeof(Cell) == 8, "sweep_lds_bytes assumes 8-byte cells");
@@ -141,6 +154,70 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
             if (ok) ob2[s] = (int)(loff0 + gx + (int64_t)gy * g.sy) * EB;
         }
     }
+    // ---- folded prolongation (PRO) --------------------------------------------
+    // u^0 = u^h + P(u^H - u^H_old) is formed as the planes are staged: each
+    // ring-2 cell adds the cell-centred trilinear interpolation (weights 3/4 and
+    // 1/4 per axis, in the order of the separate prolongation pass) of the coarse
+    // correction.  The tile's ring-2 cells draw on the coarse window
+    // cx0 .. cx0 + CW - 1, cy0 .. cy0 + CH - 1 (cx0 = x0/2 - 2, cy0 = y0/2 - 2;
+    // x0, y0 even); coarse plane K of the window sits in slot K & 3 of PC.  A
+    // fine plane p needs coarse planes p >> 1 and (p >> 1) -+ 1 (p even / odd).
+    using Corr = typename K::Corr;
+    constexpr int CW = TX / 2 + 4, CH = TY / 2 + 4, CWH = CW * CH;
+    constexpr int NCW = PRO ? (CWH + NTH - 1) / NTH : 1;
+    constexpr int NPB = PRO ? NL2 : 1;
+    __shared__ Corr PC[PRO ? PRO_SLOTS * CWH : 1];
+    int cob[NCW], cl[NCW];   // byte offset of a window cell in a coarse plane, its LDS word (-1: none)
+    int pwin[NPB][3];        // per ring-2 cell: window word of (I, J), x step (+-1), y step (+-CW)
+    if (PRO) {
+#pragma unroll
+        for (int q = 0; q < NCW; ++q) {
+            const int e = tid + q * NTH;
+            cl[q] = e < CWH ? e : -1;
+            cob[q] = BUF_OOB;
+            if (e < CWH) {
+                const int I = wrapi((x0 >> 1) - 2 + e % CW, k.gc.n0), J = wrapi((y0 >> 1) - 2 + e / CW, k.gc.n1);
+                cob[q] = (int)(k.gc.off0 - k.gc.base + I + (int64_t)J * k.gc.sy) * EB;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NPB; ++s) {
+            const int e = tid + s * NTH;
+            const int X = e < NP2 ? e % W2 : 0, Y = e < NP2 ? e / W2 : 0;
+            pwin[s][0] = (1 + (Y >> 1)) * CW + 1 + (X >> 1);
+            pwin[s][1] = (X & 1) ? 1 : -1;
+            pwin[s][2] = (Y & 1) ? CW : -CW;
+        }
+    }
+    auto coarse_load = [&](int kc, Corr (&v)[NCW]) {
+        const auto C = k.coarse_plane(k.gc.base + (int64_t)wrapi(kc, k.gc.n2) * k.gc.sz);
+#pragma unroll
+        for (int q = 0; q < NCW; ++q) v[q] = k.coarse_b(C, cob[q]);
+    };
+    auto coarse_store = [&](int kc, const Corr (&v)[NCW]) {
+        Corr* dst = PC + (kc & (PRO_SLOTS - 1)) * CWH;
+#pragma unroll
+        for (int q = 0; q < NCW; ++q)
+            if (cl[q] >= 0) dst[cl[q]] = v[q];
+    };
+    auto add_prolonged = [&](int p, Cell (&r)[NL2]) {
+        const int kp = p >> 1, sk = (p & 1) ? 1 : -1;
+        const Corr* C0 = PC + (kp & (PRO_SLOTS - 1)) * CWH;
+        const Corr* C1 = PC + ((kp + sk) & (PRO_SLOTS - 1)) * CWH;
+        const Corr a = Corr(0.75), b = Corr(0.25);
+#pragma unroll
+        for (int s = 0; s < NPB; ++s) {
+            if (tid + s * NTH >= NP2) continue;
+            const int o = pwin[s][0], dx = pwin[s][1], dy = pwin[s][2];
+            const Corr x00 = a * C0[o] + b * C0[o + dx];
+            const Corr x10 = a * C0[o + dy] + b * C0[o + dy + dx];
+            const Corr x01 = a * C1[o] + b * C1[o + dx];
+            const Corr x11 = a * C1[o + dy] + b * C1[o + dy + dx];
+            const Corr y0v = a * x00 + b * x10, y1v = a * x01 + b * x11;
+            r[s] = k.add_corr(r[s], a * y0v + b * y1v);
+        }
+    };
+
     // The loop below is unrolled twice, so step t = z0 + 2k + b works on planes
     // of fixed parity per b: red on p = t - 1, black on p2 = t - 2.  Every
     // parity-dependent offset is therefore chosen once here, per b.
@@ -314,10 +391,21 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     Cell pq[NBUF][NL2];     // u^0 planes in flight
     Src rq[NBUF][NR];       // red sources
     Src bq[NBUF][NB];       // black sources
+    Corr cq[NCW];           // PRO: coarse plane in flight (issued on odd steps)
+    if (PRO) {
+        // coarse planes z0/2 - 2 .. z0/2 + 1: those of fine planes z0 - 2 .. z0 + 1
+        Corr cv[PRO_SLOTS][NCW];
+#pragma unroll
+        for (int j = 0; j < PRO_SLOTS; ++j) coarse_load((z0 >> 1) - 2 + j, cv[j]);
+#pragma unroll
+        for (int j = 0; j < PRO_SLOTS; ++j) coarse_store((z0 >> 1) - 2 + j, cv[j]);
+        __syncthreads();
+    }
     {
         Cell r2[NL2];
         for (int t = z0 - 2; t <= z0; ++t) {
             load_plane(t, true, r2);
+            if (PRO) add_prolonged(t, r2);
             store_plane(slot(t), r2);
         }
         if (K::AHEAD == 2) {
@@ -338,6 +426,11 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
         using BB = std::integral_constant<int, LAG == 2 ? b : 1 - b>;
         constexpr int cur = K::AHEAD == 2 ? b : 0;            // buffers used by this step
         const int p = t - 1, pb = t - LAG;
+        // PRO: an odd step (z0 is even) issues coarse plane (t + 3) / 2, first
+        // needed by fine plane t + 3 two steps on; its slot last served fine plane
+        // t - 3, staged two steps before
+        constexpr bool CLOAD = PRO && b == 1;
+        if (RED && CLOAD) coarse_load((t + 3) >> 1, cq);
         if (RED) {
             if (K::AHEAD == 2)
                 load_plane(t + 2, t + 2 <= z1 + 1, pq[cur]);
@@ -358,7 +451,9 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
             fetch_black(pn, pn >= z0 && pn < z1, BNX(), bq[cur]);
             // commit u^0 plane t+1 (its slot is read by no phase of this step; past
             // the chunk's last red step the slot is never read again)
+            if (PRO) add_prolonged(t + 1, pq[K::AHEAD == 2 ? (b ^ 1) : 0]);
             store_plane(slot(t + 1), pq[K::AHEAD == 2 ? (b ^ 1) : 0]);
+            if (CLOAD) coarse_store((t + 3) >> 1, cq);
         }
         __syncthreads();
     };

@@ -205,11 +205,11 @@ static hipError_t collect_sweeps(Plan* P, int n) {
     return hipSuccess;
 }
 
-static hipError_t smooth_level(Plan* P, GridState& G, int l) {
+static hipError_t smooth_level(Plan* P, GridState& G, int l, const ProlongIn* pro = nullptr) {
     LevelBuf& L = G.lev[l];
     const SmoothCfg cfg = level_schedule(P, l, L.g);
     hipError_t e = launch_smooth(L.g, P->coef, L.phi[L.cur], L.phi[L.cur ^ 1], L.delta,
-                                 level_f(P, G, l), L.sc, cfg, P->stream);
+                                 level_f(P, G, l), L.sc, cfg, P->stream, pro);
     L.cur ^= 1;
     P->cell_updates += L.g.ncell;
     if (l == 0) P->finest_sweeps += 1;
@@ -295,12 +295,20 @@ static hipError_t vcycle_tail(Plan* P, GridState& G, int l) {
     LevelBuf& C = G.lev[l + 1];
     hipError_t e;
     if ((e = vcycle(P, G, l + 1)) != hipSuccess) return e;
-    if ((e = launch_prolong(L.g, C.g, L.phi[L.cur], C.phi[C.cur], C.phiold, P->stream)) != hipSuccess)
+    // phi^h += P(phi^H - phi^H_old): on periodic grids folded into the first
+    // post-sweep (which is then not timed with the plain sweeps)
+    const SmoothCfg cfg = level_schedule(P, l, L.g);
+    const int s0 = P->fold_prolong && P->nu2 > 0 && can_fold_prolong(L.g, C.g, cfg.zc > 0 ? cfg.zc : 16) ? 1 : 0;
+    if (s0) {
+        const ProlongIn pro{C.g, C.phi[C.cur], C.phiold};
+        if ((e = smooth_level(P, G, l, &pro)) != hipSuccess) return e;
+    } else if ((e = launch_prolong(L.g, C.g, L.phi[L.cur], C.phi[C.cur], C.phiold, P->stream)) != hipSuccess) {
         return e;
-    if (l == 0 && (e = sweep_mark(P, true, P->nu2)) != hipSuccess) return e;
-    for (int s = 0; s < P->nu2; ++s)
+    }
+    if (l == 0 && (e = sweep_mark(P, true, P->nu2 - s0)) != hipSuccess) return e;
+    for (int s = s0; s < P->nu2; ++s)
         if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
-    if (l == 0 && (e = sweep_mark(P, false, P->nu2)) != hipSuccess) return e;
+    if (l == 0 && (e = sweep_mark(P, false, P->nu2 - s0)) != hipSuccess) return e;
     return hipSuccess;
 }
 

@@ -28,6 +28,10 @@ struct SmoothArgs {
     const double* delta;
     const double* f;      // may be null
     const LevelScalars* sc;
+    // prolongation folded into the sweep (periodic): pin += P(uc - oc) first
+    Geom gc;
+    const double* uc;     // null: no prolongation
+    const double* oc;
     int zc, tiles_x, tiles_y;
 };
 
@@ -37,6 +41,7 @@ struct SmoothArgs {
 template <bool HAS_F>
 struct SmoothK {
     using Cell = double;
+    using Corr = double;
     // loads two plane steps ahead on the finest level (measured faster); one on
     // coarse levels, whose extra source f would otherwise spill at tile height 8
     static constexpr int AHEAD = HAS_F ? 1 : 2;
@@ -49,9 +54,12 @@ struct SmoothK {
     const double* __restrict__ f;
     Coef c;
     double inv_h4, h2_6, cb_6;   // 1/h^4, h^2/6, h^2 cbar/6
+    Geom gc;                     // folded prolongation: coarse level and its phi^H, phi^H_old
+    const double* __restrict__ uc;
+    const double* __restrict__ oc;
 
     __device__ SmoothK(const SmoothArgs& a, const Geom& g, bool periodic)
-        : pin(a.pin), pout(a.pout), delta(a.delta), f(a.f), c(a.c) {
+        : pin(a.pin), pout(a.pout), delta(a.delta), f(a.f), c(a.c), gc(a.gc), uc(a.uc), oc(a.oc) {
         const double h2 = g.h * g.h;
         inv_h4 = 1.0 / (h2 * h2);
         h2_6 = h2 * (1.0 / 6.0);
@@ -80,6 +88,16 @@ struct SmoothK {
         return s;
     }
     __device__ void out_b(const OutPlane& O, int bo, double v) const { buf_st_f64(O.u, bo, v); }
+    struct CoarsePlane {
+        __amdgpu_buffer_rsrc_t u, o;
+    };
+    __device__ CoarsePlane coarse_plane(int64_t zo) const {
+        return CoarsePlane{plane_rsrc(uc, zo, EB, true), plane_rsrc(oc, zo, EB, true)};
+    }
+    __device__ double coarse_b(const CoarsePlane& C, int bo) const {
+        return buf_ld_f64(C.u, bo) - buf_ld_f64(C.o, bo);
+    }
+    __device__ double add_corr(double u, double v) const { return u + v; }
     template <int W>
     __device__ double update(const double* Pm, const double* Pc, const double* Pp, int co, int o,
                              const Src& s) const {
@@ -94,8 +112,10 @@ struct SmoothK {
     }
 };
 
-template <int TY, int DIR, bool HAS_F, bool DEFER>
-__global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER)) k_smooth(SmoothArgs a) {
+// PRO: the sweep starts from pin + P(uc - oc), the coarse correction prolonged
+// as the planes are staged (periodic grids, even z chunks)
+template <int TY, int DIR, bool HAS_F, bool DEFER, bool PRO = false>
+__global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER, PRO)) k_smooth(SmoothArgs a) {
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % a.tiles_x;
     b /= a.tiles_x;
@@ -104,7 +124,7 @@ __global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER)) k_s
     const int z0 = ch * a.zc;
     if (z0 >= a.g.n2) return;
     const SmoothK<HAS_F> k(a, a.g, DIR == 0);
-    fused_sweep<TY, DIR, sweep_threads(TY), DEFER>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
+    fused_sweep<TY, DIR, sweep_threads(TY), DEFER, PRO>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
 }
 
 // Persistent sweep over a (grid, tile x, tile y, z chunk) work list: every
@@ -1083,6 +1103,16 @@ template <int TY, int DIR>
 static hipError_t smooth_launch(const SmoothArgs& a, bool defer, hipStream_t s) {
     const int chunks = (a.g.n2 + a.zc - 1) / a.zc;
     const int nb = a.tiles_x * a.tiles_y * chunks;
+    if (!DIR && a.uc) {
+        if (a.f) {
+            if (defer) hipLaunchKernelGGL((k_smooth<TY, 0, true, true, true>), dim3(nb), dim3(sweep_threads(TY)), 0, s, a);
+            else hipLaunchKernelGGL((k_smooth<TY, 0, true, false, true>), dim3(nb), dim3(sweep_threads(TY)), 0, s, a);
+        } else {
+            if (defer) hipLaunchKernelGGL((k_smooth<TY, 0, false, true, true>), dim3(nb), dim3(sweep_threads(TY)), 0, s, a);
+            else hipLaunchKernelGGL((k_smooth<TY, 0, false, false, true>), dim3(nb), dim3(sweep_threads(TY)), 0, s, a);
+        }
+        return hipGetLastError();
+    }
     if (a.f) {
         if (defer) hipLaunchKernelGGL((k_smooth<TY, DIR, true, true>), dim3(nb), dim3(sweep_threads(TY)), 0, s, a);
         else hipLaunchKernelGGL((k_smooth<TY, DIR, true, false>), dim3(nb), dim3(sweep_threads(TY)), 0, s, a);
@@ -1095,10 +1125,17 @@ static hipError_t smooth_launch(const SmoothArgs& a, bool defer, hipStream_t s) 
 
 hipError_t launch_smooth(const Geom& g, const Coef& c, const double* pin, double* pout,
                          const double* delta, const double* f, const LevelScalars* sc,
-                         SmoothCfg cfg, hipStream_t s) {
+                         SmoothCfg cfg, hipStream_t s, const ProlongIn* pro) {
     SmoothArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.g = g; a.c = c; a.pin = pin; a.pout = pout; a.delta = delta; a.f = f; a.sc = sc;
     a.zc = cfg.zc > 0 ? cfg.zc : 16;
+    if (pro) {
+        if (!can_fold_prolong(g, pro->gc, a.zc)) return hipErrorInvalidValue;
+        a.gc = pro->gc;
+        a.uc = pro->uc;
+        a.oc = pro->oc;
+    }
     a.tiles_x = (g.n0 + TX - 1) / TX;
     const int ty = cfg.ty;
     a.tiles_y = (g.n1 + ty - 1) / ty;

@@ -34,6 +34,10 @@ struct CorrArgs {
     const float* t0;
     const float* r;
     const LevelScalars* sc;   // inner cbar
+    // prolongation folded into the sweep (periodic): ein += P(uc - oc) first
+    Geom gc;
+    const float* uc;          // null: no prolongation
+    const float* oc;
     int zc, tiles_x, tiles_y;
 };
 
@@ -43,6 +47,7 @@ struct CorrArgs {
 template <bool ZERO_E>
 struct CorrK {
     using Cell = float2;   // (e, phi~)
+    using Corr = float;
     static constexpr int AHEAD = 1;   // fewer registers; measured faster than 2 here
     struct Src {
         float t0, r;
@@ -54,9 +59,12 @@ struct CorrK {
     const float* __restrict__ r;
     CoefF c;
     float h2_6, cb_6;   // h^2/6, h^2 cbar/6
+    Geom gc;            // folded prolongation: coarse level and its e^H, e^H_old
+    const float* __restrict__ uc;
+    const float* __restrict__ oc;
 
     __device__ CorrK(const CorrArgs& a, bool periodic)
-        : ein(a.ein), eout(a.eout), pt(a.pt), t0(a.t0), r(a.r), c(a.c) {
+        : ein(a.ein), eout(a.eout), pt(a.pt), t0(a.t0), r(a.r), c(a.c), gc(a.gc), uc(a.uc), oc(a.oc) {
         h2_6 = c.h2 * (1.0f / 6.0f);
         cb_6 = periodic ? h2_6 * (float)a.sc->cbar : 0.0f;
     }
@@ -83,6 +91,16 @@ struct CorrK {
     // a cell outside the grid reads t0 = 0 and r = 0; no update is formed from it
     __device__ Src src_b(const SrcPlane& S, int bo) const { return Src{buf_ld_f32(S.t, bo), buf_ld_f32(S.r, bo)}; }
     __device__ void out_b(const OutPlane& O, int bo, float2 v) const { buf_st_f32(O.e, bo, v.x); }
+    struct CoarsePlane {
+        __amdgpu_buffer_rsrc_t u, o;
+    };
+    __device__ CoarsePlane coarse_plane(int64_t zo) const {
+        return CoarsePlane{plane_rsrc(uc, zo, EB, true), plane_rsrc(oc, zo, EB, true)};
+    }
+    __device__ float coarse_b(const CoarsePlane& C, int bo) const {
+        return buf_ld_f32(C.u, bo) - buf_ld_f32(C.o, bo);
+    }
+    __device__ float2 add_corr(float2 u, float v) const { return make_float2(u.x + v, u.y); }
     template <int W>
     __device__ float2 update(const float2* Pm, const float2* Pc, const float2* Pp, int co, int o,
                              const Src& s) const {
@@ -103,8 +121,10 @@ struct CorrK {
     }
 };
 
-template <int TY, int DIR, bool ZERO_E, bool DEFER>
-__global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER)) k_smooth_corr(CorrArgs a) {
+// PRO: the sweep starts from ein + P(uc - oc), the coarse correction prolonged
+// as the planes are staged (periodic grids, even z chunks)
+template <int TY, int DIR, bool ZERO_E, bool DEFER, bool PRO = false>
+__global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER, PRO)) k_smooth_corr(CorrArgs a) {
     int b = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = b % a.tiles_x;
     b /= a.tiles_x;
@@ -113,7 +133,7 @@ __global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER)) k_s
     const int z0 = ch * a.zc;
     if (z0 >= a.g.n2) return;
     const CorrK<ZERO_E> k(a, DIR == 0);
-    fused_sweep<TY, DIR, sweep_threads(TY), DEFER>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
+    fused_sweep<TY, DIR, sweep_threads(TY), DEFER, PRO>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
 }
 
 // persistent sweep over a (grid, tile x, tile y, z chunk) work list (Dirichlet batches)
@@ -1024,6 +1044,11 @@ __global__ void k_update_batch(const Geom* __restrict__ gs, const int2* __restri
 template <int TY, int DIR>
 static hipError_t corr_launch(const CorrArgs& a, bool zero_in, bool defer, hipStream_t s) {
     const dim3 nb(a.tiles_x * a.tiles_y * ((a.g.n2 + a.zc - 1) / a.zc));
+    if (!DIR && a.uc && !zero_in) {
+        if (defer) hipLaunchKernelGGL((k_smooth_corr<TY, 0, false, true, true>), nb, dim3(sweep_threads(TY)), 0, s, a);
+        else hipLaunchKernelGGL((k_smooth_corr<TY, 0, false, false, true>), nb, dim3(sweep_threads(TY)), 0, s, a);
+        return hipGetLastError();
+    }
     if (zero_in && defer) hipLaunchKernelGGL((k_smooth_corr<TY, DIR, true, true>), nb, dim3(sweep_threads(TY)), 0, s, a);
     else if (zero_in) hipLaunchKernelGGL((k_smooth_corr<TY, DIR, true, false>), nb, dim3(sweep_threads(TY)), 0, s, a);
     else if (defer) hipLaunchKernelGGL((k_smooth_corr<TY, DIR, false, true>), nb, dim3(sweep_threads(TY)), 0, s, a);
@@ -1033,10 +1058,17 @@ static hipError_t corr_launch(const CorrArgs& a, bool zero_in, bool defer, hipSt
 
 hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, float* eout,
                               const float* pt, const float* t0, const float* r, const LevelScalars* sc,
-                              SmoothCfg cfg, hipStream_t s, bool zero_in) {
+                              SmoothCfg cfg, hipStream_t s, bool zero_in, const ProlongInF* pro) {
     CorrArgs a;
+    std::memset(&a, 0, sizeof(a));
     a.g = g; a.c = c; a.ein = ein; a.eout = eout; a.pt = pt; a.t0 = t0; a.r = r; a.sc = sc;
     a.zc = cfg.zc > 0 ? cfg.zc : 16;
+    if (pro) {
+        if (zero_in || !can_fold_prolong(g, pro->gc, a.zc)) return hipErrorInvalidValue;
+        a.gc = pro->gc;
+        a.uc = pro->uc;
+        a.oc = pro->oc;
+    }
     a.tiles_x = (g.n0 + TX - 1) / TX;
     a.tiles_y = (g.n1 + cfg.ty - 1) / cfg.ty;
     const bool d = cfg.pipe != 0;

@@ -55,12 +55,12 @@ hipError_t mixed_prepare(Plan* P) {
     return hipSuccess;
 }
 
-hipError_t smooth_corr_level(Plan* P, GridState& G, int l, bool zero_in) {
+hipError_t smooth_corr_level(Plan* P, GridState& G, int l, bool zero_in, const ProlongInF* pro) {
     LevelBuf& L = G.lev[l];
     const CoefF cf = make_coef_f(P->coef, L.g.h);
     const SmoothCfg cfg = level_schedule(P, l, L.g);
     hipError_t e = launch_smooth_corr(L.g, cf, L.e[L.ecur], L.e[L.ecur ^ 1], L.pt, L.t0, L.r, L.scf, cfg,
-                                      P->stream, zero_in);
+                                      P->stream, zero_in, pro);
     L.ecur ^= 1;
     P->cell_updates += L.g.ncell;
     if (l == 0) P->finest_sweeps += 1;
@@ -134,11 +134,20 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e, bool f
                                   P->stream)) != hipSuccess)
         return e;
     if ((e = inner_vcycle(P, G, l + 1, false, fresh_base)) != hipSuccess) return e;
-    if ((e = launch_prolong_corr(L.g, C.g, L.e[L.ecur], C.e[C.ecur], C.eold, P->stream)) != hipSuccess) return e;
-    if (l == 0 && (e = sweep_mark(P, true, P->nu2)) != hipSuccess) return e;
-    for (int s = 0; s < P->nu2; ++s)
+    // e^h += P(e^H - e^H_old): on periodic grids folded into the first
+    // post-sweep (which is then not timed with the plain sweeps)
+    const SmoothCfg cfg = level_schedule(P, l, L.g);
+    const int s0 = P->fold_prolong && P->nu2 > 0 && can_fold_prolong(L.g, C.g, cfg.zc > 0 ? cfg.zc : 16) ? 1 : 0;
+    if (s0) {
+        const ProlongInF pro{C.g, C.e[C.ecur], C.eold};
+        if ((e = smooth_corr_level(P, G, l, false, &pro)) != hipSuccess) return e;
+    } else if ((e = launch_prolong_corr(L.g, C.g, L.e[L.ecur], C.e[C.ecur], C.eold, P->stream)) != hipSuccess) {
+        return e;
+    }
+    if (l == 0 && (e = sweep_mark(P, true, P->nu2 - s0)) != hipSuccess) return e;
+    for (int s = s0; s < P->nu2; ++s)
         if ((e = smooth_corr_level(P, G, l)) != hipSuccess) return e;
-    if (l == 0 && (e = sweep_mark(P, false, P->nu2)) != hipSuccess) return e;
+    if (l == 0 && (e = sweep_mark(P, false, P->nu2 - s0)) != hipSuccess) return e;
     return hipSuccess;
 }
 

@@ -128,9 +128,24 @@ struct TailCorrArgs {
 hipError_t launch_tail_corr(const TailCorrArgs& a, hipStream_t s);
 
 // ---- launchers (kernels.hip) --------------------------------------------
+// Coarse correction prolonged inside a sweep: the sweep starts from
+// u^h + P(uc - oc) (cell-centred trilinear) instead of u^h.
+template <typename T>
+struct ProlongInT {
+    Geom gc;
+    const T* uc;
+    const T* oc;
+};
+using ProlongIn = ProlongInT<double>;
+using ProlongInF = ProlongInT<float>;
+// The folded prolongation needs a periodic grid twice the coarse one per axis
+// and an even z chunk (the coarse planes are staged on odd steps).
+inline bool can_fold_prolong(const Geom& g, const Geom& gc, int zc) {
+    return !g.dir && !gc.dir && (zc & 1) == 0 && g.n0 == 2 * gc.n0 && g.n1 == 2 * gc.n1 && g.n2 == 2 * gc.n2;
+}
 hipError_t launch_smooth(const Geom& g, const Coef& c, const double* pin, double* pout,
                          const double* delta, const double* f, const LevelScalars* sc,
-                         SmoothCfg cfg, hipStream_t s);
+                         SmoothCfg cfg, hipStream_t s, const ProlongIn* pro = nullptr);
 hipError_t launch_residual_restrict(const Geom& gf, const Geom& gc, const Coef& c,
                                     const double* phi, const double* delta, const double* f,
                                     const LevelScalars* sc, double* phic, double* phiold_c,
@@ -208,7 +223,8 @@ hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int
 // cycle); ein is then not read.
 hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, float* eout,
                               const float* pt, const float* t0, const float* r, const LevelScalars* sc,
-                              SmoothCfg cfg, hipStream_t s, bool zero_in = false);
+                              SmoothCfg cfg, hipStream_t s, bool zero_in = false,
+                              const ProlongInF* pro = nullptr);
 // ptc (may be null): receives the restricted base state phi~ of the coarse level
 hipError_t launch_rr_corr(const Geom& gf, const Geom& gc, const CoefF& c, const float* e, const float* pt,
                           const float* t0, const float* r, const LevelScalars* sc, float* ec, float* eold_c,

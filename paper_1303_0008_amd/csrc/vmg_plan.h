@@ -8,6 +8,10 @@
 #include "../../include/vmg.h"
 #include "vmg_internal.h"
 
+#ifndef VMG_FOLD_PROLONG
+#define VMG_FOLD_PROLONG true
+#endif
+
 namespace vmg {
 
 struct LevelBuf {
@@ -78,6 +82,7 @@ struct Plan {
     int nu1 = 2, nu2 = 2, ncoarse = 40;
     int inner = 2;                         // mixed: FP32 inner V-cycles per outer iteration
     bool use_tail = true;                  // periodic coarse levels <= TAIL_CELLS in one launch
+    bool fold_prolong = VMG_FOLD_PROLONG;  // periodic: prolongation folded into the first post-sweep
     int batch_blocks = 1024;               // blocks of a batched plan's persistent smoother launch
     bool periodic = true;
     bool mixed = false;
@@ -127,7 +132,7 @@ vmg_status alloc_mixed(Plan* P);
 hipError_t enqueue_outer(Plan* P);          // one mixed-precision outer iteration (+ norms to host)
 hipError_t mixed_initial_pass(Plan* P);     // cast pass of the initial guess (+ norms to host)
 hipError_t mixed_prepare(Plan* P);          // per-solve set-up of the FP32 ghost shells
-hipError_t smooth_corr_level(Plan* P, GridState& G, int l, bool zero_in = false);
+hipError_t smooth_corr_level(Plan* P, GridState& G, int l, bool zero_in = false, const ProlongInF* pro = nullptr);
 vmg_status build_batch(Plan* P);
 vmg_status autotune(Plan* P);
 // levels of a plan that run the fused sweep (the levels a schedule applies to)
