@@ -65,17 +65,23 @@ constexpr int sweep_slots(bool defer) { return defer ? 4 : 3; }
 // kernels are built for: as many blocks per CU as that LDS allows (160 KB per
 // CU), at most 4, so that the register budget matches the occupancy the LDS
 // permits.
-// With the prolongation folded in (pro), four coarse correction planes of the
-// tile's window ((TX/2 + 4) x (ty/2 + 4) cells, counted at 8 bytes) are added.
+// With the prolongation folded in (pro): four coarse correction planes of the
+// tile's window ((TX/2 + 4) x (ty/2 + 4) cells) and two planes of their
+// interpolation onto the tile's ring-2 rows ((ty + 4) x (TX/2 + 4)), counted at
+// 8 bytes.
 constexpr int PRO_SLOTS = 4;
 constexpr int pro_window(int ty) { return (TX / 2 + 4) * (ty / 2 + 4); }
+constexpr int pro_rows(int ty) { return (TX / 2 + 4) * (ty + 4); }
 constexpr int sweep_lds_bytes(int ty, bool defer, bool pro = false) {
     return sweep_slots(defer) * ((TX + 4) * (ty + 4) + (TX + 2) * (ty + 2)) * 8 +
-           (pro ? PRO_SLOTS * pro_window(ty) * 8 : 0);
+           (pro ? (PRO_SLOTS * pro_window(ty) + 2 * pro_rows(ty)) * 8 : 0);
 }
+// (at most 4 blocks; with the folded prolongation, whose extra state would not
+// fit that register budget, at most 3 for tile height 4 and 2 above)
+constexpr int sweep_max_blocks(int ty, bool pro) { return pro ? (ty <= 4 ? 3 : 2) : 4; }
 constexpr int sweep_blocks_per_cu(int ty, bool defer, bool pro = false) {
-    return (160 * 1024) / sweep_lds_bytes(ty, defer, pro) >= 4
-               ? 4
+    return (160 * 1024) / sweep_lds_bytes(ty, defer, pro) >= sweep_max_blocks(ty, pro)
+               ? sweep_max_blocks(ty, pro)
                : ((160 * 1024) / sweep_lds_bytes(ty, defer, pro) < 1 ? 1
                                                                      : (160 * 1024) / sweep_lds_bytes(ty, defer, pro));
 }
@@ -157,18 +163,23 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     // ---- folded prolongation (PRO) --------------------------------------------
     // u^0 = u^h + P(u^H - u^H_old) is formed as the planes are staged: each
     // ring-2 cell adds the cell-centred trilinear interpolation (weights 3/4 and
-    // 1/4 per axis, in the order of the separate prolongation pass) of the coarse
-    // correction.  The tile's ring-2 cells draw on the coarse window
-    // cx0 .. cx0 + CW - 1, cy0 .. cy0 + CH - 1 (cx0 = x0/2 - 2, cy0 = y0/2 - 2;
-    // x0, y0 even); coarse plane K of the window sits in slot K & 3 of PC.  A
-    // fine plane p needs coarse planes p >> 1 and (p >> 1) -+ 1 (p even / odd).
+    // 1/4 per axis) of the coarse correction.  The tile's ring-2 cells draw on the
+    // coarse window cx0 .. cx0 + CW - 1, cy0 .. cy0 + CH - 1 (cx0 = x0/2 - 2,
+    // cy0 = y0/2 - 2; x0, y0 even); coarse plane K of the window sits in slot
+    // K & 3 of PC.  A fine plane p needs coarse planes p >> 1 and (p >> 1) -+ 1
+    // (p even / odd).  The interpolation is separable: for plane p, EY (slot
+    // p & 1) first holds the z- and y-interpolated window column of every ring-2
+    // row; a cell then needs two of them.
     using Corr = typename K::Corr;
-    constexpr int CW = TX / 2 + 4, CH = TY / 2 + 4, CWH = CW * CH;
+    constexpr int CW = TX / 2 + 4, CH = TY / 2 + 4, CWH = CW * CH, EYS = H2 * CW;
     constexpr int NCW = PRO ? (CWH + NTH - 1) / NTH : 1;
+    constexpr int NEY = PRO ? (EYS + NTH - 1) / NTH : 1;
     constexpr int NPB = PRO ? NL2 : 1;
     __shared__ Corr PC[PRO ? PRO_SLOTS * CWH : 1];
+    __shared__ Corr EY[PRO ? 2 * EYS : 1];
     int cob[NCW], cl[NCW];   // byte offset of a window cell in a coarse plane, its LDS word (-1: none)
-    int pwin[NPB][3];        // per ring-2 cell: window word of (I, J), x step (+-1), y step (+-CW)
+    int eyo[NEY], eyd[NEY];  // EY entry: window word of (J, column) (-1: none), y step (+-CW)
+    int pwin[NPB][2];        // ring-2 cell: EY word of (row, I), x step (+-1)
     if (PRO) {
 #pragma unroll
         for (int q = 0; q < NCW; ++q) {
@@ -181,12 +192,18 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
             }
         }
 #pragma unroll
+        for (int q = 0; q < NEY; ++q) {
+            const int e = tid + q * NTH;
+            const int Y = e / CW, c = e % CW;      // ring-2 row, window column
+            eyo[q] = e < EYS ? (1 + (Y >> 1)) * CW + c : -1;
+            eyd[q] = (Y & 1) ? CW : -CW;
+        }
+#pragma unroll
         for (int s = 0; s < NPB; ++s) {
             const int e = tid + s * NTH;
             const int X = e < NP2 ? e % W2 : 0, Y = e < NP2 ? e / W2 : 0;
-            pwin[s][0] = (1 + (Y >> 1)) * CW + 1 + (X >> 1);
+            pwin[s][0] = Y * CW + 1 + (X >> 1);
             pwin[s][1] = (X & 1) ? 1 : -1;
-            pwin[s][2] = (Y & 1) ? CW : -CW;
         }
     }
     auto coarse_load = [&](int kc, Corr (&v)[NCW]) {
@@ -200,22 +217,37 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
         for (int q = 0; q < NCW; ++q)
             if (cl[q] >= 0) dst[cl[q]] = v[q];
     };
-    auto add_prolonged = [&](int p, Cell (&r)[NL2]) {
+    // EY of fine plane p from its two coarse planes (z, then y)
+    auto make_ey = [&](int p) {
         const int kp = p >> 1, sk = (p & 1) ? 1 : -1;
         const Corr* C0 = PC + (kp & (PRO_SLOTS - 1)) * CWH;
         const Corr* C1 = PC + ((kp + sk) & (PRO_SLOTS - 1)) * CWH;
+        Corr* E = EY + (p & 1) * EYS;
+        const Corr a = Corr(0.75), b = Corr(0.25);
+#pragma unroll
+        for (int q = 0; q < NEY; ++q) {
+            if (eyo[q] < 0) continue;
+            const int o = eyo[q], dy = eyd[q];
+            const Corr z0v = a * C0[o] + b * C1[o];
+            const Corr z1v = a * C0[o + dy] + b * C1[o + dy];
+            E[tid + q * NTH] = a * z0v + b * z1v;
+        }
+    };
+    // the correction of plane p (its EY written and synchronised) at this
+    // thread's ring-2 cells, and its addition to the staged cells
+    auto read_prolonged = [&](int p, Corr (&v)[NPB]) {
+        const Corr* E = EY + (p & 1) * EYS;
         const Corr a = Corr(0.75), b = Corr(0.25);
 #pragma unroll
         for (int s = 0; s < NPB; ++s) {
-            if (tid + s * NTH >= NP2) continue;
-            const int o = pwin[s][0], dx = pwin[s][1], dy = pwin[s][2];
-            const Corr x00 = a * C0[o] + b * C0[o + dx];
-            const Corr x10 = a * C0[o + dy] + b * C0[o + dy + dx];
-            const Corr x01 = a * C1[o] + b * C1[o + dx];
-            const Corr x11 = a * C1[o + dy] + b * C1[o + dy + dx];
-            const Corr y0v = a * x00 + b * x10, y1v = a * x01 + b * x11;
-            r[s] = k.add_corr(r[s], a * y0v + b * y1v);
+            const int o = pwin[s][0];
+            v[s] = a * E[o] + b * E[o + pwin[s][1]];
         }
+    };
+    auto add_prolonged = [&](const Corr (&v)[NPB], Cell (&r)[NL2]) {
+#pragma unroll
+        for (int s = 0; s < NPB; ++s)
+            if (tid + s * NTH < NP2) r[s] = k.add_corr(r[s], v[s]);
     };
 
     // The loop below is unrolled twice, so step t = z0 + 2k + b works on planes
@@ -391,9 +423,9 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     Cell pq[NBUF][NL2];     // u^0 planes in flight
     Src rq[NBUF][NR];       // red sources
     Src bq[NBUF][NB];       // black sources
-    Corr cq[NCW];           // PRO: coarse plane in flight (issued on odd steps)
+    Corr cq[NCW];           // PRO: coarse plane in flight (issued on even steps)
     if (PRO) {
-        // coarse planes z0/2 - 2 .. z0/2 + 1: those of fine planes z0 - 2 .. z0 + 1
+        // coarse planes z0/2 - 2 .. z0/2 + 1: those of fine planes z0 - 2 .. z0 + 2
         Corr cv[PRO_SLOTS][NCW];
 #pragma unroll
         for (int j = 0; j < PRO_SLOTS; ++j) coarse_load((z0 >> 1) - 2 + j, cv[j]);
@@ -405,9 +437,16 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
         Cell r2[NL2];
         for (int t = z0 - 2; t <= z0; ++t) {
             load_plane(t, true, r2);
-            if (PRO) add_prolonged(t, r2);
+            if (PRO) {
+                make_ey(t);
+                __syncthreads();
+                Corr v[NPB];
+                read_prolonged(t, v);
+                add_prolonged(v, r2);
+            }
             store_plane(slot(t), r2);
         }
+        if (PRO) make_ey(z0 + 1);   // stored by step z0
         if (K::AHEAD == 2) {
             load_plane(z0 + 1, true, pq[NBUF - 1]);
             fetch_red(z0, true, B1(), rq[NBUF - 1]);   // red plane of step z0 + 1
@@ -426,11 +465,16 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
         using BB = std::integral_constant<int, LAG == 2 ? b : 1 - b>;
         constexpr int cur = K::AHEAD == 2 ? b : 0;            // buffers used by this step
         const int p = t - 1, pb = t - LAG;
-        // PRO: an odd step (z0 is even) issues coarse plane (t + 3) / 2, first
-        // needed by fine plane t + 3 two steps on; its slot last served fine plane
-        // t - 3, staged two steps before
-        constexpr bool CLOAD = PRO && b == 1;
-        if (RED && CLOAD) coarse_load((t + 3) >> 1, cq);
+        // PRO: step t forms EY of fine plane t + 2 (stored by step t + 1) in slot
+        // t & 1, whose last reader was step t - 1.  An even step (z0 is even)
+        // issues coarse plane t/2 + 2, first read by step t + 1; its slot last
+        // served EY of plane t - 2.
+        constexpr bool CLOAD = PRO && b == 0;
+        if (RED && CLOAD) coarse_load((t >> 1) + 2, cq);
+        if (RED && PRO) make_ey(t + 2);
+        // correction of plane t + 1, read early so that its LDS latency is hidden
+        Corr pv[NPB];
+        if (RED && PRO) read_prolonged(t + 1, pv);
         if (RED) {
             if (K::AHEAD == 2)
                 load_plane(t + 2, t + 2 <= z1 + 1, pq[cur]);
@@ -451,9 +495,9 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
             fetch_black(pn, pn >= z0 && pn < z1, BNX(), bq[cur]);
             // commit u^0 plane t+1 (its slot is read by no phase of this step; past
             // the chunk's last red step the slot is never read again)
-            if (PRO) add_prolonged(t + 1, pq[K::AHEAD == 2 ? (b ^ 1) : 0]);
+            if (PRO) add_prolonged(pv, pq[K::AHEAD == 2 ? (b ^ 1) : 0]);
             store_plane(slot(t + 1), pq[K::AHEAD == 2 ? (b ^ 1) : 0]);
-            if (CLOAD) coarse_store((t + 3) >> 1, cq);
+            if (CLOAD) coarse_store((t >> 1) + 2, cq);
         }
         __syncthreads();
     };

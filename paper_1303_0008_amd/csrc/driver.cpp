@@ -298,7 +298,8 @@ static hipError_t vcycle_tail(Plan* P, GridState& G, int l) {
     // phi^h += P(phi^H - phi^H_old): on periodic grids folded into the first
     // post-sweep (which is then not timed with the plain sweeps)
     const SmoothCfg cfg = level_schedule(P, l, L.g);
-    const int s0 = P->fold_prolong && P->nu2 > 0 && can_fold_prolong(L.g, C.g, cfg.zc > 0 ? cfg.zc : 16) ? 1 : 0;
+    const int zc = cfg.zc > 0 ? cfg.zc : 16;
+    const int s0 = P->fold_prolong && P->nu2 > 0 && can_fold_prolong(L.g, C.g, zc) && fold_prolong_pays(L.g, zc) ? 1 : 0;
     if (s0) {
         const ProlongIn pro{C.g, C.phi[C.cur], C.phiold};
         if ((e = smooth_level(P, G, l, &pro)) != hipSuccess) return e;

@@ -137,7 +137,8 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e, bool f
     // e^h += P(e^H - e^H_old): on periodic grids folded into the first
     // post-sweep (which is then not timed with the plain sweeps)
     const SmoothCfg cfg = level_schedule(P, l, L.g);
-    const int s0 = P->fold_prolong && P->nu2 > 0 && can_fold_prolong(L.g, C.g, cfg.zc > 0 ? cfg.zc : 16) ? 1 : 0;
+    const int zc = cfg.zc > 0 ? cfg.zc : 16;
+    const int s0 = P->fold_prolong && P->nu2 > 0 && can_fold_prolong(L.g, C.g, zc) && fold_prolong_pays(L.g, zc) ? 1 : 0;
     if (s0) {
         const ProlongInF pro{C.g, C.e[C.ecur], C.eold};
         if ((e = smooth_corr_level(P, G, l, false, &pro)) != hipSuccess) return e;

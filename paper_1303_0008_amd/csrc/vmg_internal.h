@@ -143,6 +143,11 @@ using ProlongInF = ProlongInT<float>;
 inline bool can_fold_prolong(const Geom& g, const Geom& gc, int zc) {
     return !g.dir && !gc.dir && (zc & 1) == 0 && g.n0 == 2 * gc.n0 && g.n1 == 2 * gc.n1 && g.n2 == 2 * gc.n2;
 }
+// Where folding pays (measured on 128^3-512^3 solves): a z chunk of at least 8
+// planes amortises the block's start-up (four coarse planes staged, three ring
+// planes corrected), and on levels of at most 64^3 cells the saved launch
+// outweighs it.  A 128^3 level swept in chunks of 4 loses.
+inline bool fold_prolong_pays(const Geom& g, int zc) { return zc >= 8 || g.ncell <= (int64_t)1 << 18; }
 hipError_t launch_smooth(const Geom& g, const Coef& c, const double* pin, double* pout,
                          const double* delta, const double* f, const LevelScalars* sc,
                          SmoothCfg cfg, hipStream_t s, const ProlongIn* pro = nullptr);
