@@ -117,8 +117,9 @@ FINEST = {"fp64": ("k_smooth<", 24), "mixed": ("k_smooth_corr<", 20)}
 
 
 def finest_kernel(name, tile_y, pipe):
-    """Name of the finest-level sweep kernel of a precision for a schedule."""
-    return f"{FINEST[name][0]}{tile_y}, 0, false, {'true' if pipe else 'false'}>"
+    """Name of the finest-level sweep kernel of a precision for a schedule (the
+    plain sweep: no prolongation folded in)."""
+    return f"{FINEST[name][0]}{tile_y}, 0, false, {'true' if pipe else 'false'}, false>"
 
 
 PROBE_SWEEPS = 10
@@ -535,6 +536,8 @@ def main():
                     help="run only the kernels of the HBM counter runs (under rocprofv3 --pmc)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc csv outputs of --traffic-probe into profiles/*_traffic.json")
+    ap.add_argument("--history", metavar="FILE",
+                    help="append the residual history of a solve of each precision to FILE (JSON lines)")
     ap.add_argument("--retune", metavar="FILE",
                     help="write a fresh tuning file (sweep and cycle schedules of every configuration) and exit")
     args = ap.parse_args()
@@ -584,11 +587,25 @@ def main():
         ty, zc, pipe = plan.schedule(0)
         sched = [plan.schedule(l) for l in range(plan.level_count())]
         cyc = plan.cycle()
+        # one more solve with every level's share of each iteration timed, and its
+        # residual history
+        plan.time_sweeps(False)
+        plan.time_levels(True)
+        with torch.cuda.stream(stream):
+            phi_l = torch.zeros_like(delta)
+            plan.solve(delta, phi_l)
+        torch.cuda.synchronize()
+        lev = [plan.level_time(l) for l in range(plan.level_count() + 1)]
+        hist = plan.history()
         plan.close()
+        if args.history:
+            V.write_history_jsonl(args.history, hist, workload=WORKLOAD, precision=name)
         kern = finest_kernel(name, ty, pipe)
         results[name] = solve_entry(name, infos, updates, dt, args.steps, sw, bpc, n3, kern)
         results[name]["timed_solves_ms_per_step"] = 1e3 * dt_t / args.steps
         results[name]["schedules"] = {"sweep_per_level": sched, "cycle": cyc}
+        results[name]["level_us_per_iteration"] = [round(us / max(k, 1), 2) for us, k in lev]
+        results[name]["residual_history"] = [h["rms"] for h in hist]
         fs = results[name]["finest_sweep"]
         roofs[name] = {"bound": "hbm", "achieved": fs["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": fs["achieved_gbs"] / HBM_PEAK_GBS,

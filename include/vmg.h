@@ -343,6 +343,36 @@ vmg_status vmg_smooth(vmg_plan *plan, int32_t sweeps);
 vmg_status vmg_plan_time_sweeps(vmg_plan *plan, int32_t enable);
 vmg_status vmg_plan_sweep_time(const vmg_plan *plan, double *total_us, int64_t *launches);
 
+/* Measurement hook: with enable != 0, the work of every level in the
+ * iterations of later solves is bracketed by HIP events on the plan's stream:
+ * for a level l with a coarser level, its share of a V-cycle (the pre-sweeps,
+ * the residual and restriction and the coarse right-hand side, then the
+ * prolongation and the post-sweeps); the periodic coarse tail and the coarsest
+ * solve are one piece, reported at the level where they start.  On the mixed
+ * path the inner cycles' pieces and the outer FP64 pass (level 0) are timed.
+ * vmg_plan_level_time returns the summed microseconds of `level` and the
+ * number of iterations timed since this call.  While enabled a VMG_GRAPH plan
+ * issues its iterations directly (as with vmg_plan_time_sweeps), and ROCTX
+ * ranges name each level's pieces for rocprofv3 --marker-trace.  Batched
+ * patch plans are not timed per level (level_time reports 0).  Allocates
+ * events.  Errors: VMG_EINVAL (null plan, level out of range), VMG_EHIP. */
+vmg_status vmg_plan_time_levels(vmg_plan *plan, int32_t enable);
+vmg_status vmg_plan_level_time(const vmg_plan *plan, int32_t level, double *total_us, int64_t *iterations);
+
+/* Residual history of the last vmg_solve of grid `grid` (Sec. III.C's
+ * stopping test is on these norms): entry 0 holds the norms of the initial
+ * guess, entry k those after iteration k (FP64: one V-cycle; mixed: one outer
+ * defect-correction step).  Copies min(count, cap) entries into `out` (may be
+ * null with cap 0) and returns count in *n.  The plan owns nothing the caller
+ * passes.  Errors: VMG_EINVAL (null plan or n, grid out of range). */
+typedef struct {
+    double rms;        /* RMS of the FP64 residual d = L(phi) - f + cbar */
+    double cbar;       /* periodic compatibility constant in use */
+    double n_guarded;  /* cells on the guarded (vertex) branch of the root */
+    double tau_rms;    /* RMS of tau^h on the next coarser level (tau rule), else 0 */
+} vmg_history;
+vmg_status vmg_plan_history(const vmg_plan *plan, int32_t grid, vmg_history *out, int32_t cap, int32_t *n);
+
 /* Counters of the last vmg_solve (host pointers, each may be NULL):
  * cell_updates  = smoother cell updates over all levels and sweeps,
  * finest_sweeps = finest-level smoother sweeps (launches of that kernel),

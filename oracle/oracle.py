@@ -23,6 +23,9 @@ _SRC = os.path.join(_HERE, "vmg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 W_PAPER = 1.0 / 3.0
 _lib = None
+# VMG_ORACLE_LIB names another build of vmg_oracle.c to load instead (the
+# sanitizer build of the tests); it is used as it is, never rebuilt here
+_LIB_ENV = "VMG_ORACLE_LIB"
 
 
 def build(force=True):
@@ -34,12 +37,26 @@ def build(force=True):
     return _LIB
 
 
+def build_sanitized(path):
+    """Compile the oracle with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every report fatal) into ``path``.  Load it by setting VMG_ORACLE_LIB=path
+    in a process started with the ASan runtime preloaded."""
+    cmd = ["gcc", "-O1", "-g", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+           "-o", path, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    return path
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = ctypes.CDLL(_LIB)
+        path = os.environ.get(_LIB_ENV)
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER
         dp = P(ctypes.c_double)
         ip = P(ctypes.c_int)

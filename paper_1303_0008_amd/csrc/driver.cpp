@@ -12,6 +12,8 @@
 
 #include "../../include/vmg.h"
 #include "vmg_internal.h"
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "vmg_plan.h"
 
 namespace vmg {
@@ -170,6 +172,7 @@ static void release_graphs(Plan* P);
 void destroy_plan(Plan* P) {
     release_graphs(P);
     for (hipEvent_t ev : P->tev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : P->lev_ev) (void)hipEventDestroy(ev);
     for (void* a : P->allocs) (void)hipFree(a);
     if (P->host_norm) (void)hipHostFree(P->host_norm);
     if (P->own_stream) (void)hipStreamDestroy(P->own_stream);
@@ -202,6 +205,37 @@ static hipError_t collect_sweeps(Plan* P, int n) {
         P->sweep_n += P->tev_count[i];
     }
     P->tev_used = 0;
+    return hipSuccess;
+}
+
+// Per-level timing: event pairs tagged with the level, and a ROCTX range per piece.
+hipError_t level_mark(Plan* P, int l, bool begin) {
+    if (!P->time_levels || !P->timing_active) return hipSuccess;
+    if (begin) {
+        if (P->lev_used >= (int)P->lev_tag.size()) return hipSuccess;   // pool full: piece not timed
+        static const char* names[] = {"vmg level 0", "vmg level 1", "vmg level 2", "vmg level 3",
+                                      "vmg level 4", "vmg level 5", "vmg level 6", "vmg level 7",
+                                      "vmg level 8", "vmg level 9", "vmg level 10+"};
+        roctxRangePushA(names[l < 10 ? l : 10]);
+        P->lev_tag[P->lev_used] = -1 - l;   // open
+        return hipEventRecord(P->lev_ev[2 * P->lev_used], P->stream);
+    }
+    if (P->lev_used >= (int)P->lev_tag.size() || P->lev_tag[P->lev_used] != -1 - l) return hipSuccess;
+    roctxRangePop();
+    P->lev_tag[P->lev_used] = l;
+    return hipEventRecord(P->lev_ev[2 * P->lev_used++ + 1], P->stream);
+}
+
+// accumulate the recorded pieces (after the stream has finished them)
+static hipError_t collect_levels(Plan* P) {
+    for (int i = 0; i < P->lev_used; ++i) {
+        float ms = 0.0f;
+        hipError_t e = hipEventElapsedTime(&ms, P->lev_ev[2 * i], P->lev_ev[2 * i + 1]);
+        if (e != hipSuccess) return e;
+        const int l = P->lev_tag[i];
+        if (l >= 0 && l < (int)P->level_us.size()) P->level_us[l] += 1e3 * ms;
+    }
+    P->lev_used = 0;
     return hipSuccess;
 }
 
@@ -269,6 +303,7 @@ static hipError_t vcycle(Plan* P, GridState& G, int l);
 static hipError_t vcycle_head(Plan* P, GridState& G, int l, NormOut* norm) {
     LevelBuf& L = G.lev[l];
     hipError_t e;
+    if ((e = level_mark(P, l, true)) != hipSuccess) return e;
     if (l == 0 && (e = sweep_mark(P, true, P->nu1)) != hipSuccess) return e;
     for (int s = 0; s < P->nu1; ++s)
         if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
@@ -284,10 +319,12 @@ static hipError_t vcycle_head(Plan* P, GridState& G, int l, NormOut* norm) {
         return e;
     // with Dirichlet faces there is no cbar: only the norms need finalizing
     const int periodic = L.g.dir ? 0 : 1;
-    if (!periodic && !norm) return hipSuccess;
-    return launch_finalize_pair(FinJob{P->partials, nb, periodic, 0, L.g.ncell, L.sc, norm, nullptr},
-                                FinJob{P->partials_b, nbc, periodic, 1, C.g.ncell, C.sc, norm, nullptr},
-                                P->stream);
+    if (!periodic && !norm) return level_mark(P, l, false);
+    if ((e = launch_finalize_pair(FinJob{P->partials, nb, periodic, 0, L.g.ncell, L.sc, norm, nullptr},
+                                  FinJob{P->partials_b, nbc, periodic, 1, C.g.ncell, C.sc, norm, nullptr},
+                                  P->stream)) != hipSuccess)
+        return e;
+    return level_mark(P, l, false);
 }
 
 static hipError_t vcycle_tail(Plan* P, GridState& G, int l) {
@@ -295,6 +332,7 @@ static hipError_t vcycle_tail(Plan* P, GridState& G, int l) {
     LevelBuf& C = G.lev[l + 1];
     hipError_t e;
     if ((e = vcycle(P, G, l + 1)) != hipSuccess) return e;
+    if ((e = level_mark(P, l, true)) != hipSuccess) return e;
     // phi^h += P(phi^H - phi^H_old): on periodic grids folded into the first
     // post-sweep (which is then not timed with the plain sweeps)
     const SmoothCfg cfg = level_schedule(P, l, L.g);
@@ -310,19 +348,24 @@ static hipError_t vcycle_tail(Plan* P, GridState& G, int l) {
     for (int s = s0; s < P->nu2; ++s)
         if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
     if (l == 0 && (e = sweep_mark(P, false, P->nu2 - s0)) != hipSuccess) return e;
-    return hipSuccess;
+    return level_mark(P, l, false);
 }
 
 static hipError_t vcycle(Plan* P, GridState& G, int l) {
     LevelBuf& L = G.lev[l];
     const int last = (int)G.lev.size() - 1;
     hipError_t e;
-    if (l > 0 && l == tail_level(P, G)) return tail_cycle(P, G, l);
+    if (l > 0 && l == tail_level(P, G)) {
+        if ((e = level_mark(P, l, true)) != hipSuccess || (e = tail_cycle(P, G, l)) != hipSuccess) return e;
+        return level_mark(P, l, false);
+    }
     if (l == last) {
+        if ((e = level_mark(P, l, true)) != hipSuccess) return e;
         e = launch_coarse_solve(L.g, P->coef, L.phi[L.cur], L.delta, level_f(P, G, l), L.sc,
                                 P->ncoarse, P->stream);
         P->cell_updates += (int64_t)P->ncoarse * L.g.ncell;
-        return e;
+        if (e != hipSuccess) return e;
+        return level_mark(P, l, false);
     }
     if ((e = vcycle_head(P, G, l, nullptr)) != hipSuccess) return e;
     return vcycle_tail(P, G, l);
@@ -451,7 +494,7 @@ vmg_status capture_graphs(Plan* P) {
     release_graphs(P);
     // event-record nodes of a graph carry no timestamps on this runtime, so a
     // plan that times its sweeps issues its iterations directly
-    if (!(P->params.flags & VMG_GRAPH) || P->time_sweeps) return VMG_OK;
+    if (!(P->params.flags & VMG_GRAPH) || P->time_sweeps || P->time_levels) return VMG_OK;
     for (int src = 0; src < 2; ++src)
         for (int q = 0; q < 2; ++q) {
             vmg_status st = capture_graph(P, src, q);
@@ -496,6 +539,10 @@ static vmg_status run_cycle(Plan* P) {
         CKH(enqueue_iteration(P));
         CKH(hipStreamSynchronize(P->stream));
         if (P->time_sweeps) CKH(collect_sweeps(P, P->tev_used));
+        if (P->time_levels) {
+            CKH(collect_levels(P));
+            ++P->level_cycles;
+        }
         return VMG_OK;
     }
     CKH(hipGraphLaunch(P->graph[src][parity], P->stream));
@@ -581,6 +628,13 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
     CKH(hipStreamSynchronize(s));
     const int ng = (int)P->grids.size();
     std::vector<double> rms0(ng), best(ng);
+    auto record = [&]() {
+        for (int gi = 0; gi < ng; ++gi) {
+            const NormOut& no = P->host_norm[gi];
+            P->history[gi].push_back(vmg_history{no.rms, no.cbar, no.n_guard, no.tau_rms});
+        }
+    };
+    P->history.assign(ng, std::vector<vmg_history>());
     for (int gi = 0; gi < ng; ++gi) {
         rms0[gi] = P->host_norm[gi].rms;
         best[gi] = rms0[gi];
@@ -594,6 +648,7 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
     // tau_rms is written by the heads of shifted cycles only; 0 before the first
     const double tf = P->params.tau_factor;
     for (int gi = 0; gi < ng; ++gi) P->host_norm[gi].tau_rms = 0.0;
+    record();
     auto converged = [&]() {
         for (int gi = 0; gi < ng; ++gi) {
             const NormOut& no = P->host_norm[gi];
@@ -609,15 +664,19 @@ vmg_status solve(Plan* P, const double* delta, const double* ghost, const double
         CKH(enqueue_first_head(P));
         CKH(hipStreamSynchronize(s));
         if (P->time_sweeps) CKH(collect_sweeps(P, P->tev_used));
+        if (P->time_levels) CKH(collect_levels(P));
     }
     while (!converged()) {
         if (cycles >= P->params.max_cycles) {
             status = VMG_ENOCONV;
             break;
         }
+        roctxRangePushA("vmg iteration");
         vmg_status st = run_cycle(P);
+        roctxRangePop();
         if (st != VMG_OK) return st;
         ++cycles;
+        record();
         // divergence: a non-finite residual, one 1e4 times above the best so far, or
         // three iterations in a row 10 times above it once the first few iterations
         // (whose nonlinear start phase may raise the residual) are past
@@ -748,7 +807,10 @@ vmg_status vmg_solve(vmg_plan* plan, const double* delta, const double* ghost, c
     if (!plan || !delta || !phi) return fail(VMG_EINVAL, "null plan, delta or phi");
     Plan* P = reinterpret_cast<Plan*>(plan);
     if (!P->periodic && !ghost) return fail(VMG_EINVAL, "Dirichlet grids need ghost values");
-    return solve(P, delta, ghost, source, phi, out);
+    roctxRangePushA("vmg_solve");
+    const vmg_status st = solve(P, delta, ghost, source, phi, out);
+    roctxRangePop();
+    return st;
 }
 
 vmg_status vmg_solve_periodic(const double* delta, int32_t n, double alpha, double kappa, double tol,
@@ -1129,6 +1191,48 @@ vmg_status vmg_plan_sweep_time(const vmg_plan* plan, double* total_us, int64_t* 
     const Plan* P = reinterpret_cast<const Plan*>(plan);
     if (total_us) *total_us = P->sweep_us;
     if (launches) *launches = P->sweep_n;
+    return VMG_OK;
+}
+
+vmg_status vmg_plan_time_levels(vmg_plan* plan, int32_t enable) {
+    g_err.clear();
+    if (!plan) return fail(VMG_EINVAL, "null plan");
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    CKH(hipStreamSynchronize(P->stream));
+    if (enable && P->lev_ev.empty()) {
+        P->lev_ev.assign(2 * 512, nullptr);
+        P->lev_tag.assign(512, 0);
+        for (auto& ev : P->lev_ev) CKH(hipEventCreate(&ev));
+    }
+    size_t nlev = 0;
+    for (const auto& G : P->grids) nlev = std::max(nlev, G.lev.size());
+    P->time_levels = enable != 0 && !P->batched;
+    P->level_us.assign(nlev, 0.0);
+    P->level_cycles = 0;
+    P->lev_used = 0;
+    return capture_graphs(P);
+}
+
+vmg_status vmg_plan_level_time(const vmg_plan* plan, int32_t level, double* total_us, int64_t* iterations) {
+    if (!plan) return fail(VMG_EINVAL, "null plan");
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    size_t nlev = 0;
+    for (const auto& G : P->grids) nlev = std::max(nlev, G.lev.size());
+    if (level < 0 || (size_t)level >= nlev) return fail(VMG_EINVAL, "level out of range");
+    if (total_us) *total_us = (size_t)level < P->level_us.size() ? P->level_us[level] : 0.0;
+    if (iterations) *iterations = P->level_cycles;
+    return VMG_OK;
+}
+
+vmg_status vmg_plan_history(const vmg_plan* plan, int32_t grid, vmg_history* out, int32_t cap, int32_t* n) {
+    if (!plan || !n) return fail(VMG_EINVAL, "null argument");
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (grid < 0 || grid >= (int32_t)P->grids.size()) return fail(VMG_EINVAL, "grid out of range");
+    if (cap < 0 || (cap > 0 && !out)) return fail(VMG_EINVAL, "bad output buffer");
+    const std::vector<vmg_history> none;
+    const auto& h = (size_t)grid < P->history.size() ? P->history[grid] : none;
+    *n = (int32_t)h.size();
+    for (int32_t i = 0; i < cap && i < (int32_t)h.size(); ++i) out[i] = h[i];
     return VMG_OK;
 }
 

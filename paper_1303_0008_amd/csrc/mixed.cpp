@@ -100,12 +100,18 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e, bool f
     const int last = (int)G.lev.size() - 1;
     const CoefF cf = make_coef_f(P->coef, L.g.h);
     hipError_t e;
-    if (l > 0 && l == tail_level(P, G)) return inner_tail(P, G, l);
+    if (l > 0 && l == tail_level(P, G)) {
+        if ((e = level_mark(P, l, true)) != hipSuccess || (e = inner_tail(P, G, l)) != hipSuccess) return e;
+        return level_mark(P, l, false);
+    }
     if (l == last) {
+        if ((e = level_mark(P, l, true)) != hipSuccess) return e;
         e = launch_coarse_corr(L.g, cf, L.e[L.ecur], L.pt, L.t0, L.r, P->ncoarse, P->stream);
         P->cell_updates += (int64_t)P->ncoarse * L.g.ncell;
-        return e;
+        if (e != hipSuccess) return e;
+        return level_mark(P, l, false);
     }
+    if ((e = level_mark(P, l, true)) != hipSuccess) return e;
     // the sweep that reads no correction (zero_e) is another kernel: it is not timed
     const int t1 = zero_e ? P->nu1 - 1 : P->nu1;
     for (int s = 0; s < P->nu1; ++s) {
@@ -133,7 +139,9 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e, bool f
                                   FinJob{P->partials_b, nbc, 1, 1, C.g.ncell, C.scf, nullptr, nullptr},
                                   P->stream)) != hipSuccess)
         return e;
+    if ((e = level_mark(P, l, false)) != hipSuccess) return e;
     if ((e = inner_vcycle(P, G, l + 1, false, fresh_base)) != hipSuccess) return e;
+    if ((e = level_mark(P, l, true)) != hipSuccess) return e;
     // e^h += P(e^H - e^H_old): on periodic grids folded into the first
     // post-sweep (which is then not timed with the plain sweeps)
     const SmoothCfg cfg = level_schedule(P, l, L.g);
@@ -149,7 +157,7 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e, bool f
     for (int s = s0; s < P->nu2; ++s)
         if ((e = smooth_corr_level(P, G, l)) != hipSuccess) return e;
     if (l == 0 && (e = sweep_mark(P, false, P->nu2 - s0)) != hipSuccess) return e;
-    return hipSuccess;
+    return level_mark(P, l, false);
 }
 
 static const double* level0_f(const Plan* P, const GridState& G) {
@@ -161,12 +169,16 @@ static const double* level0_f(const Plan* P, const GridState& G) {
 static hipError_t cast_pass(Plan* P, GridState& G, bool update) {
     LevelBuf& L = G.lev[0];
     int nb = 0;
-    hipError_t e = launch_cast_update(L.g, P->coef, L.phi[L.cur], update ? L.e[L.ecur] : nullptr,
-                                      L.phi[L.cur ^ 1], L.delta, level0_f(P, G), L.sc, L.pt, L.t0, L.r,
-                                      P->partials, &nb, P->stream);
+    hipError_t e = level_mark(P, 0, true);
+    if (e != hipSuccess) return e;
+    e = launch_cast_update(L.g, P->coef, L.phi[L.cur], update ? L.e[L.ecur] : nullptr, L.phi[L.cur ^ 1],
+                           L.delta, level0_f(P, G), L.sc, L.pt, L.t0, L.r, P->partials, &nb, P->stream);
     if (e != hipSuccess) return e;
     if (update) L.cur ^= 1;
-    return launch_finalize(P->partials, nb, L.g.ncell, L.g.dir ? 0 : 1, 2, L.sc, G.norm_dev, P->stream, L.scf);
+    if ((e = launch_finalize(P->partials, nb, L.g.ncell, L.g.dir ? 0 : 1, 2, L.sc, G.norm_dev, P->stream,
+                             L.scf)) != hipSuccess)
+        return e;
+    return level_mark(P, 0, false);
 }
 
 static hipError_t norms_to_host(Plan* P) {

@@ -109,6 +109,19 @@ struct Plan {
     int graph_tev[2][2] = {{0, 0}, {0, 0}};
     double sweep_us = 0.0;
     int64_t sweep_n = 0;
+    // per-level timing (vmg_plan_time_levels): event pairs around the work of
+    // each level of a cycle (head: pre-sweeps, restriction, coarse rhs; tail:
+    // prolongation, post-sweeps; the coarse tail / coarsest solve as one piece at
+    // its top level), tagged with the level; solves then launch directly
+    bool time_levels = false;
+    std::vector<hipEvent_t> lev_ev;        // [2i] before, [2i+1] after piece i
+    std::vector<int> lev_tag;              // level of piece i
+    int lev_used = 0;
+    std::vector<double> level_us;          // summed per level since enabled
+    int64_t level_cycles = 0;              // iterations timed since enabled
+    // residual history of the last solve (vmg_plan_history): per grid, the
+    // norms before the first iteration and after each one
+    std::vector<std::vector<vmg_history>> history;
     // batched Dirichlet plans
     bool tuned_from_cache = false;
     struct TuneEntry { int level; SmoothCfg cfg; double us; };
@@ -127,6 +140,8 @@ vmg_status fail(vmg_status st, const std::string& msg);
 // bracket a run of `launches` consecutive finest-level sweeps with timing
 // events (no-op unless enabled)
 hipError_t sweep_mark(Plan* P, bool begin, int launches);
+// bracket the work of level l (begin / end) when per-level timing is on
+hipError_t level_mark(Plan* P, int l, bool begin);
 CoefF make_coef_f(const Coef& c, double h);
 vmg_status alloc_mixed(Plan* P);
 hipError_t enqueue_outer(Plan* P);          // one mixed-precision outer iteration (+ norms to host)

@@ -64,6 +64,14 @@ class Cycle(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class History(ctypes.Structure):
+    _fields_ = [("rms", ctypes.c_double), ("cbar", ctypes.c_double), ("n_guarded", ctypes.c_double),
+                ("tau_rms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Nest(ctypes.Structure):
     _fields_ = [("parent", ctypes.c_int32), ("origin", ctypes.c_int32 * 3)]
 
@@ -75,7 +83,8 @@ EXPORTS = ["vmg_plan_create", "vmg_solve", "vmg_plan_destroy", "vmg_last_error",
            "vmg_mass_assign", "vmg_mass_assign_workspace", "vmg_solve_levels", "vmg_levels_create",
            "vmg_levels_solve", "vmg_levels_destroy", "vmg_mass_assign_region", "vmg_plan_level_count",
            "vmg_plan_set_schedule", "vmg_plan_schedule", "vmg_mass_assign_noalloc", "vmg_plan_get_cycle",
-           "vmg_plan_set_cycle", "vmg_plan_tune_cycle", "vmg_plan_time_sweeps", "vmg_plan_sweep_time"]
+           "vmg_plan_set_cycle", "vmg_plan_tune_cycle", "vmg_plan_time_sweeps", "vmg_plan_sweep_time",
+           "vmg_plan_time_levels", "vmg_plan_level_time", "vmg_plan_history"]
 
 _lib = None
 
@@ -128,6 +137,9 @@ def load():
     L.vmg_plan_schedule.argtypes = [vp, ctypes.c_int32, i32p, i32p, i32p]
     L.vmg_plan_time_sweeps.argtypes = [vp, ctypes.c_int32]
     L.vmg_plan_sweep_time.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_int64)]
+    L.vmg_plan_time_levels.argtypes = [vp, ctypes.c_int32]
+    L.vmg_plan_level_time.argtypes = [vp, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
+    L.vmg_plan_history.argtypes = [vp, ctypes.c_int32, P(History), ctypes.c_int32, i32p]
     L.vmg_plan_get_cycle.argtypes = [vp, P(Cycle)]
     L.vmg_plan_set_cycle.argtypes = [vp, P(Cycle)]
     L.vmg_plan_tune_cycle.argtypes = [vp, vp, vp, vp, vp, P(Cycle), P(ctypes.c_double)]
@@ -444,6 +456,37 @@ def plan_sweep_time(handle):
     return us.value, n.value
 
 
+def plan_time_levels(handle, enable=True):
+    """vmg_plan_time_levels: time each level's share of later iterations with HIP events."""
+    _check(load().vmg_plan_time_levels(ctypes.c_void_p(handle), 1 if enable else 0))
+
+
+def plan_level_time(handle, level):
+    """vmg_plan_level_time: (summed microseconds, iterations timed) of a level."""
+    us, n = ctypes.c_double(), ctypes.c_int64()
+    _check(load().vmg_plan_level_time(ctypes.c_void_p(handle), int(level), ctypes.byref(us), ctypes.byref(n)))
+    return us.value, n.value
+
+
+def plan_history(handle, grid=0):
+    """vmg_plan_history: the norms of the last solve's initial guess and after each
+    iteration, as a list of dicts (rms, cbar, n_guarded, tau_rms)."""
+    n = ctypes.c_int32()
+    _check(load().vmg_plan_history(ctypes.c_void_p(handle), int(grid), None, 0, ctypes.byref(n)))
+    buf = (History * max(n.value, 1))()
+    _check(load().vmg_plan_history(ctypes.c_void_p(handle), int(grid), buf, n.value, ctypes.byref(n)))
+    return [buf[i].as_dict() for i in range(n.value)]
+
+
+def write_history_jsonl(path, history, **meta):
+    """Append one JSON line per iteration of a residual history (plan_history) to
+    ``path``: {"iteration": k, "rms": ..., ...} plus the ``meta`` fields."""
+    import json
+    with open(path, "a") as fh:
+        for k, h in enumerate(history):
+            fh.write(json.dumps(dict(meta, iteration=k, **h)) + "\n")
+
+
 def plan_get_cycle(handle):
     """vmg_plan_get_cycle: the plan's cycle schedule as a dict."""
     c = Cycle()
@@ -506,6 +549,15 @@ class Plan:
 
     def sweep_time(self):
         return plan_sweep_time(self.handle)
+
+    def time_levels(self, enable=True):
+        plan_time_levels(self.handle, enable)
+
+    def level_time(self, level):
+        return plan_level_time(self.handle, level)
+
+    def history(self, grid=0):
+        return plan_history(self.handle, grid)
 
     def cycle(self):
         return plan_get_cycle(self.handle)
