@@ -161,7 +161,7 @@ def _counter_rows(path):
     return rows
 
 
-def traffic_from(fetch_dir, write_dir, n):
+def traffic_from(fetch_dir, write_dir, n, workload=WORKLOAD):
     """Per-launch HBM bytes of the finest sweeps from a FETCH_SIZE run and a
     WRITE_SIZE run of --traffic-probe, each scaled so that the calibration copy
     reads / writes exactly COPY_BYTES; writes the JSON files the roofline reads."""
@@ -193,13 +193,13 @@ def traffic_from(fetch_dir, write_dir, n):
                                                   "bytes_per_launch": statistics.median(vals) * 1024.0 * scale}
     for name, (_, bpc) in FINEST.items():
         d = per[name]
-        out = {"kernel": d["FETCH_SIZE"]["kernel"], "workload": f"{WORKLOAD} ({n}^3)",
+        out = {"kernel": d["FETCH_SIZE"]["kernel"], "workload": f"{workload} ({n}^3)",
                "kernel_source_hash": kernel_source_hash(),
                "algorithmic_bytes_per_launch": bpc * ncell,
                "fetch": d["FETCH_SIZE"], "write": d["WRITE_SIZE"],
                "bytes_per_launch": d["FETCH_SIZE"]["bytes_per_launch"] + d["WRITE_SIZE"]["bytes_per_launch"]}
         out["ratio_to_algorithmic"] = out["bytes_per_launch"] / out["algorithmic_bytes_per_launch"]
-        p = os.path.join(ROOT, "profiles", f"smooth_{name}_{WORKLOAD}_traffic.json")
+        p = os.path.join(ROOT, "profiles", f"smooth_{name}_{workload}_traffic.json")
         with open(p, "w") as fh:
             json.dump(out, fh, indent=1)
         log(f"{name}: {out['bytes_per_launch'] / 1e6:.1f} MB per launch "
@@ -487,8 +487,13 @@ def other_configs(torch, V, I, stream, steps):
                                                       time_sweeps=True)
             ty, zc, pipe = plan.schedule(0)
             plan.close()
+            kern = finest_kernel(pn, ty, pipe)
             res[f"{name}_{pn}"] = solve_entry(f"{name} {pn}", infos, upd, dt, max(2, steps // 4), sw, bpc, n3,
-                                              finest_kernel(pn, ty, pipe) + f" (z chunk {zc})")
+                                              kern + f" (z chunk {zc})")
+            # HBM bytes per launch from the committed counter runs at 512^3
+            if "finest_sweep" in res[f"{name}_{pn}"]:
+                res[f"{name}_{pn}"]["finest_sweep"]["traffic"] = load_traffic(f"smooth_{pn}_{name}_traffic.json",
+                                                                              kern)
             torch.cuda.empty_cache()
     del d512
     torch.cuda.empty_cache()
@@ -534,6 +539,8 @@ def main():
                          "assignment and multilevel timings")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run only the kernels of the HBM counter runs (under rocprofv3 --pmc)")
+    ap.add_argument("--probe-workload", default=WORKLOAD, choices=("zeldovich256", "lognormal512a"),
+                    help="workload of --traffic-probe / --traffic-from (default: the headline one)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc csv outputs of --traffic-probe into profiles/*_traffic.json")
     ap.add_argument("--history", metavar="FILE",
@@ -544,7 +551,8 @@ def main():
     os.environ.setdefault("VMG_TUNE_CACHE", TUNE_CACHE)
     if args.traffic_from:
         from paper_1303_0008_amd import inputs as I
-        traffic_from(args.traffic_from[0], args.traffic_from[1], I.WORKLOADS[WORKLOAD]["n"])
+        traffic_from(args.traffic_from[0], args.traffic_from[1], I.WORKLOADS[args.probe_workload]["n"],
+                     args.probe_workload)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -567,7 +575,13 @@ def main():
     log(f"workload {WORKLOAD}: generated in {time.perf_counter() - t:.1f} s, max delta {delta_np.max():.1f}")
     delta = torch.from_numpy(delta_np).to("cuda")
     if args.traffic_probe:
-        traffic_probe(torch, V, delta, w)
+        if args.probe_workload != WORKLOAD:
+            wp = dict(I.WORKLOADS[args.probe_workload])
+            dp = torch.from_numpy(I.workload_delta(args.probe_workload)).to("cuda")
+            del delta
+            traffic_probe(torch, V, dp, wp)
+        else:
+            traffic_probe(torch, V, delta, w)
         return
     torch.cuda.synchronize()
 
