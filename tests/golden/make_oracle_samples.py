@@ -9,8 +9,9 @@ over the grid, plus every cell of the 9^3 block around the densest cell (the
 most nonlinear region).  The file also records the input's SHA-256, the
 oracle's RMS residual, cbar, |phi|_inf and the cycle count.
 
-Usage: python tests/golden/make_oracle_samples.py zeldovich256 [n_uniform]
-(a 256^3 solve takes several minutes on one core).
+Usage: python tests/golden/make_oracle_samples.py WORKLOAD [n_uniform]
+with WORKLOAD zeldovich256 (the oracle takes about 17 minutes on one core) or
+lognormal512a (about 2.6 hours).
 """
 import json
 import os

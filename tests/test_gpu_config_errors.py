@@ -9,9 +9,10 @@ the reference, and four GPU solutions are measured against it:
     reported, and bounded by the stopping rule: the error of a solve stopped
     at RMS residual tol is at most about tol / lambda_min, lambda_min = 4 pi^2
     on the unit box, relative to |phi|_inf).
-For the 256^3 Zel'dovich configuration (the benchmark's) the oracle's solution
-at the FP64 floor is stored at a seeded sample of cells (a uniform sample plus
-the block around the densest cell) by tests/golden/make_oracle_samples.py,
+For the 256^3 Zel'dovich configuration (the benchmark's) and the 512^3 lognormal
+one (alpha = 0.2) the oracle's solution at the FP64 floor is stored at a seeded
+sample of cells (a uniform sample plus the block around the densest cell) by
+tests/golden/make_oracle_samples.py,
 which calls only the oracle and the input generator; the GPU solutions are
 compared with it there, on plans running the benchmark's per-level sweep
 schedules.  |.| is the max norm relative to |phi_ref|_inf.
@@ -95,28 +96,34 @@ def solve_scheduled(torch, V, d_t, w, tol, prec, prec_name):
     return phi, info, sched
 
 
-def test_config_errors_zeldovich256(torch_cuda, V):
-    """256^3 Zel'dovich workload, the benchmark's kernels and schedules, against
-    the oracle's solution at the FP64 floor (stored at a seeded sample of cells
-    by tests/golden/make_oracle_samples.py): FP64 at 1e-11 <= 1e-10, mixed at
-    1e-10 <= 1e-8, and both at the configuration's tolerance within the
-    stopping-rule bound."""
+@pytest.mark.parametrize("name", ["zeldovich256", "lognormal512a"])
+def test_config_errors_sampled(torch_cuda, V, name):
+    """The 256^3 Zel'dovich workload and the 512^3 lognormal one (alpha = 0.2),
+    the benchmark's kernels and schedules, against the oracle's solution at the
+    FP64 floor (stored at a seeded sample of cells by
+    tests/golden/make_oracle_samples.py): FP64 at 1e-11 <= 1e-10, mixed at 1e-10
+    <= 1e-8, and both at the configuration's tolerance within the stopping-rule
+    bound."""
     torch = torch_cuda
-    w = I.WORKLOADS["zeldovich256"]
-    g, idx, ref = load_sample("zeldovich256")
-    delta = I.workload_delta("zeldovich256")
+    w = I.WORKLOADS[name]
+    g, idx, ref = load_sample(name)
+    print(f"sampled parity {name} ({w['n']}^3): generating the input", flush=True)
+    delta = I.workload_delta(name)
     assert I.sha256(delta) == g["delta_sha256"]
     d_t = torch.from_numpy(delta).to("cuda")
+    del delta
     scale = g["phi_absmax"]
     out = {}
     for label, tol, prec, pn in (("fp64@1e-11", 1e-11, V.FP64, "fp64"), ("mixed@1e-10", 1e-10, V.MIXED, "mixed"),
                                  ("fp64@1e-8", w["tol"], V.FP64, "fp64"), ("mixed@1e-8", w["tol"], V.MIXED, "mixed")):
+        print(f"  {label}", flush=True)
         phi, info, sched = solve_scheduled(torch, V, d_t, w, tol, prec, pn)
         assert info["rms"] <= tol
         got = phi.reshape(-1)[torch.from_numpy(idx).to("cuda")].cpu().numpy()
         out[label] = (float(np.abs(got - ref).max() / scale), info["cycles"], sched)
         del phi
-    print("config zeldovich256 vs oracle sample (%d cells, oracle rms %.1e): " % (idx.size, g["oracle"]["rms"]) +
+        torch.cuda.empty_cache()
+    print(f"config {name} vs oracle sample (%d cells, oracle rms %.1e): " % (idx.size, g["oracle"]["rms"]) +
           ", ".join(f"{k} err {e:.2e} ({c} cycles, schedules {s})" for k, (e, c, s) in out.items()), flush=True)
     assert out["fp64@1e-11"][0] <= 1e-10
     assert out["mixed@1e-10"][0] <= 1e-8

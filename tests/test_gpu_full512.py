@@ -6,11 +6,17 @@ out of reach on the CPU).
 * alpha = 0.2: the solve reaches the tolerance; the GPU's residual field of
   the returned phi equals the oracle's cell by cell (within rounding), and its
   RMS and cbar agree with the reported ones; FP64 and mixed agree.
-* alpha = -0.2 (about 9 % of the cells take the discriminant guard): the
-  clamped system stalls under relaxation at these densities (max delta ~2200;
-  the oracle's own Gauss-Seidel started from the stalled state does not lower
-  the residual either), so the solver must report VMG_ENOCONV with a finite
-  state whose residual, cbar and guard count the oracle confirms.
+* alpha = -0.2 (about 9 % of the cells take the discriminant guard): this
+  configuration does NOT meet its tolerance.  A discrete solution exists (a
+  Newton solve with one-sided derivatives converges on a cut-out around the
+  cells that keep the residual), but at these densities (max delta ~2200) the
+  closed-form Gauss-Seidel update oscillates with period 2 at ~160 cells next to
+  the guard boundary, where its sensitivity to a neighbour, ~1/sqrt(D), exceeds
+  one; the oracle's own Gauss-Seidel started from the stalled state does not
+  lower the residual either.  What is tested is the error path: the solver
+  reports VMG_ENOCONV with a finite state whose residual, cbar and guard count
+  the oracle confirms.  (The element-wise parity of the alpha = 0.2 run against
+  the oracle's solution is in test_gpu_config_errors.py.)
 """
 import numpy as np
 import pytest
@@ -81,7 +87,7 @@ def test_lognormal512a_mixed(torch_cuda, V, oracle_mod):
     assert info["n_guarded"] == rm["n_guarded"] == 0
 
 
-def test_lognormal512b_guarded_reports_stall(torch_cuda, V, oracle_mod):
+def test_lognormal512b_unmet_tolerance_reports_noconv(torch_cuda, V, oracle_mod):
     torch = torch_cuda
     w = I.WORKLOADS["lognormal512b"]
     say("lognormal512b: generate")
