@@ -403,6 +403,8 @@ typedef struct {
                                 single-workgroup launch, 0 = level by level; Dirichlet: 0 */
     int32_t batch_blocks;    /* Dirichlet plans: blocks of the persistent smoother launch,
                                 64..65536; periodic plans: 0 */
+    int32_t coarse_nu1, coarse_nu2;  /* pre/post sweeps on every level below the finest, 0..8
+                                with coarse_nu1 + coarse_nu2 >= 1; both 0: nu1 and nu2 there too */
 } vmg_cycle;
 
 /* The cycle schedule a plan runs (host pointer).  Errors: VMG_EINVAL. */
@@ -418,7 +420,8 @@ vmg_status vmg_plan_set_cycle(vmg_plan *plan, const vmg_cycle *cycle);
  * is a device array of phi's layout holding the initial guess, from which every
  * trial starts, and receives the last trial's solution) to the plan's
  * tolerance for candidate schedules, by coordinate
- * search: nu1/nu2 over (1,1) .. (3,3), then inner cycles 1..3 (mixed), then
+ * search: nu1/nu2 over (1,1) .. (3,3), then the sweeps below the finest level
+ * (as the finest, (1,1), (1,2), (2,1)), then inner cycles 1..3 (mixed), then
  * coarsest sweeps {2, 4, 8, 16}, then the coarse tail on/off (periodic) or the
  * persistent launch size {512, 1024, 2048} (Dirichlet).  A candidate that does
  * not reach the tolerance within max_cycles is discarded.  The fastest

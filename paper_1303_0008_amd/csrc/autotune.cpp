@@ -52,8 +52,9 @@ std::string plan_key(const Plan* P) {
 std::string tune_key(const Plan* P, int l) { return plan_key(P) + ":L" + std::to_string(l); }
 std::string cycle_key(const Plan* P) { return plan_key(P) + ":cycle"; }
 
-// Lines: "key ty zc us" (pipeline shape 0), "key ty zc pipe us" or
-// "key:cycle nu1 nu2 inner coarse tail blocks ms".
+// Lines: "key ty zc us" (pipeline shape 0), "key ty zc pipe us",
+// "key:cycle nu1 nu2 inner coarse tail blocks ms" (coarse levels as the finest) or
+// "key:cycle nu1 nu2 inner coarse tail blocks coarse_nu1 coarse_nu2 ms".
 void load_file_cache() {
     g_file_loaded = true;
     const char* path = std::getenv("VMG_TUNE_CACHE");
@@ -69,10 +70,12 @@ void load_file_cache() {
         double x;
         while (in >> x) v.push_back(x);
         const bool cyc = key.size() > 6 && key.compare(key.size() - 6, 6, ":cycle") == 0;
-        if (cyc && v.size() == 7) {
+        if (cyc && (v.size() == 7 || v.size() == 9)) {
             vmg_cycle c;
             c.nu1 = (int)v[0]; c.nu2 = (int)v[1]; c.inner_cycles = (int)v[2];
             c.coarse_sweeps = (int)v[3]; c.coarse_tail = (int)v[4]; c.batch_blocks = (int)v[5];
+            c.coarse_nu1 = v.size() == 9 ? (int)v[6] : 0;
+            c.coarse_nu2 = v.size() == 9 ? (int)v[7] : 0;
             g_cycle_cache[key] = c;
         } else if (!cyc && (v.size() == 3 || v.size() == 4)) {
             SmoothCfg c;
@@ -115,8 +118,8 @@ void remember_cycle(const std::string& key, const vmg_cycle& c, double ms) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_cycle_cache[key] = c;
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%s %d %d %d %d %d %d %.3f", key.c_str(), c.nu1, c.nu2, c.inner_cycles,
-                  c.coarse_sweeps, c.coarse_tail, c.batch_blocks, ms);
+    std::snprintf(buf, sizeof(buf), "%s %d %d %d %d %d %d %d %d %.3f", key.c_str(), c.nu1, c.nu2, c.inner_cycles,
+                  c.coarse_sweeps, c.coarse_tail, c.batch_blocks, c.coarse_nu1, c.coarse_nu2, ms);
     append_line(buf);
 }
 
@@ -293,6 +296,14 @@ vmg_status tune_cycle(Plan* P, const double* delta, const double* ghost, const d
         c.nu1 = nus[i][0];
         c.nu2 = nus[i][1];
         if (c.nu1 != best.nu1 || c.nu2 != best.nu2) st = consider(c);
+    }
+    // sweeps below the finest level: as the finest, or fewer
+    const int cnus[4][2] = {{0, 0}, {1, 1}, {1, 2}, {2, 1}};
+    for (int i = 0; i < 4 && st == VMG_OK; ++i) {
+        vmg_cycle c = best;
+        c.coarse_nu1 = cnus[i][0];
+        c.coarse_nu2 = cnus[i][1];
+        if (c.coarse_nu1 != best.coarse_nu1 || c.coarse_nu2 != best.coarse_nu2) st = consider(c);
     }
     if (P->mixed)
         for (int k = 1; k <= 3 && st == VMG_OK; ++k) {

@@ -232,9 +232,9 @@ static hipError_t bcycle(Plan* P, int l) {
         P->cell_updates += (int64_t)P->ncoarse * B.cells_C;
     }
     if (l + 1 >= (int)P->blev.size() || B.cells_A == 0) return hipSuccess;
-    if (l == 0) CKE(sweep_mark(P, true, P->nu1));
-    for (int q = 0; q < P->nu1; ++q) CKE(bsmooth(P, l));
-    if (l == 0) CKE(sweep_mark(P, false, P->nu1));
+    if (l == 0) CKE(sweep_mark(P, true, pre_sweeps(P, l)));
+    for (int q = 0; q < pre_sweeps(P, l); ++q) CKE(bsmooth(P, l));
+    if (l == 0) CKE(sweep_mark(P, false, pre_sweeps(P, l)));
     BatchLevel& C = P->blev[l + 1];
     C.cur = 0;
     CKE(launch_rr_batch(C.d_geom_fine, C.d_geom, C.d_cells, C.ncells, P->coef, B.phi[B.cur], B.delta, bf(P, l),
@@ -244,9 +244,9 @@ static hipError_t bcycle(Plan* P, int l) {
     CKE(bcycle(P, l + 1));
     CKE(launch_prolong_batch(C.d_geom_fine, C.d_geom, C.d_fcells, C.nfcells, B.phi[B.cur], C.phi[C.cur],
                              C.phiold, s));
-    if (l == 0) CKE(sweep_mark(P, true, P->nu2));
-    for (int q = 0; q < P->nu2; ++q) CKE(bsmooth(P, l));
-    if (l == 0) CKE(sweep_mark(P, false, P->nu2));
+    if (l == 0) CKE(sweep_mark(P, true, post_sweeps(P, l)));
+    for (int q = 0; q < post_sweeps(P, l); ++q) CKE(bsmooth(P, l));
+    if (l == 0) CKE(sweep_mark(P, false, post_sweeps(P, l)));
     return hipSuccess;
 }
 
@@ -283,9 +283,9 @@ static hipError_t bcycle_corr(Plan* P, int l) {
         P->cell_updates += (int64_t)P->ncoarse * B.cells_C;
     }
     if (l + 1 >= (int)P->blev.size() || B.cells_A == 0) return hipSuccess;
-    if (l == 0) CKE(sweep_mark(P, true, P->nu1));
-    for (int q = 0; q < P->nu1; ++q) CKE(bsmooth_corr(P, l));
-    if (l == 0) CKE(sweep_mark(P, false, P->nu1));
+    if (l == 0) CKE(sweep_mark(P, true, pre_sweeps(P, l)));
+    for (int q = 0; q < pre_sweeps(P, l); ++q) CKE(bsmooth_corr(P, l));
+    if (l == 0) CKE(sweep_mark(P, false, pre_sweeps(P, l)));
     BatchLevel& C = P->blev[l + 1];
     C.ecur = 0;
     CKE(launch_rr_corr_batch(C.d_geom_fine, C.d_geom, C.d_cells, C.ncells, cf, B.e[B.ecur], B.pt, B.t0, B.r,
@@ -295,9 +295,9 @@ static hipError_t bcycle_corr(Plan* P, int l) {
     CKE(bcycle_corr(P, l + 1));
     CKE(launch_prolong_corr_batch(C.d_geom_fine, C.d_geom, C.d_fcells, C.nfcells, B.e[B.ecur], C.e[C.ecur],
                                   C.eold, s));
-    if (l == 0) CKE(sweep_mark(P, true, P->nu2));
-    for (int q = 0; q < P->nu2; ++q) CKE(bsmooth_corr(P, l));
-    if (l == 0) CKE(sweep_mark(P, false, P->nu2));
+    if (l == 0) CKE(sweep_mark(P, true, post_sweeps(P, l)));
+    for (int q = 0; q < post_sweeps(P, l); ++q) CKE(bsmooth_corr(P, l));
+    if (l == 0) CKE(sweep_mark(P, false, post_sweeps(P, l)));
     return hipSuccess;
 }
 

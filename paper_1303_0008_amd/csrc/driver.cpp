@@ -279,14 +279,15 @@ static hipError_t tail_cycle(Plan* P, GridState& G, int l) {
         a.n[q][0] = T.g.n0; a.n[q][1] = T.g.n1; a.n[q][2] = T.g.n2;
         a.h[q] = T.g.h;
         a.delta[q] = T.delta;
-        P->cell_updates += (int64_t)(q == a.nlev - 1 ? P->ncoarse : P->nu1 + P->nu2) * T.g.ncell;
+        P->cell_updates += (int64_t)(q == a.nlev - 1 ? P->ncoarse : pre_sweeps(P, l + q) + post_sweeps(P, l + q)) *
+                           T.g.ncell;
     }
     LevelBuf& L = G.lev[l];
     a.phi = L.phi[L.cur];
     a.f = level_f(P, G, l);
     a.sc = L.sc;
     a.c = P->coef;
-    a.nu1 = P->nu1; a.nu2 = P->nu2; a.ncoarse = P->ncoarse;
+    a.nu1 = pre_sweeps(P, l); a.nu2 = post_sweeps(P, l); a.ncoarse = P->ncoarse;
     return launch_tail(a, P->stream);
 }
 
@@ -304,10 +305,11 @@ static hipError_t vcycle_head(Plan* P, GridState& G, int l, NormOut* norm) {
     LevelBuf& L = G.lev[l];
     hipError_t e;
     if ((e = level_mark(P, l, true)) != hipSuccess) return e;
-    if (l == 0 && (e = sweep_mark(P, true, P->nu1)) != hipSuccess) return e;
-    for (int s = 0; s < P->nu1; ++s)
+    const int nu1 = pre_sweeps(P, l);
+    if (l == 0 && (e = sweep_mark(P, true, nu1)) != hipSuccess) return e;
+    for (int s = 0; s < nu1; ++s)
         if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
-    if (l == 0 && (e = sweep_mark(P, false, P->nu1)) != hipSuccess) return e;
+    if (l == 0 && (e = sweep_mark(P, false, nu1)) != hipSuccess) return e;
     LevelBuf& C = G.lev[l + 1];
     C.cur = 0;
     int nb = 0, nbc = 0;
@@ -337,17 +339,18 @@ static hipError_t vcycle_tail(Plan* P, GridState& G, int l) {
     // post-sweep (which is then not timed with the plain sweeps)
     const SmoothCfg cfg = level_schedule(P, l, L.g);
     const int zc = cfg.zc > 0 ? cfg.zc : 16;
-    const int s0 = P->fold_prolong && P->nu2 > 0 && can_fold_prolong(L.g, C.g, zc) && fold_prolong_pays(L.g, zc) ? 1 : 0;
+    const int nu2 = post_sweeps(P, l);
+    const int s0 = P->fold_prolong && nu2 > 0 && can_fold_prolong(L.g, C.g, zc) && fold_prolong_pays(L.g, zc) ? 1 : 0;
     if (s0) {
         const ProlongIn pro{C.g, C.phi[C.cur], C.phiold};
         if ((e = smooth_level(P, G, l, &pro)) != hipSuccess) return e;
     } else if ((e = launch_prolong(L.g, C.g, L.phi[L.cur], C.phi[C.cur], C.phiold, P->stream)) != hipSuccess) {
         return e;
     }
-    if (l == 0 && (e = sweep_mark(P, true, P->nu2 - s0)) != hipSuccess) return e;
-    for (int s = s0; s < P->nu2; ++s)
+    if (l == 0 && (e = sweep_mark(P, true, nu2 - s0)) != hipSuccess) return e;
+    for (int s = s0; s < nu2; ++s)
         if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
-    if (l == 0 && (e = sweep_mark(P, false, P->nu2 - s0)) != hipSuccess) return e;
+    if (l == 0 && (e = sweep_mark(P, false, nu2 - s0)) != hipSuccess) return e;
     return level_mark(P, l, false);
 }
 
@@ -510,6 +513,8 @@ void get_cycle(const Plan* P, vmg_cycle* c) {
     c->coarse_sweeps = P->ncoarse;
     c->coarse_tail = P->periodic && P->use_tail ? 1 : 0;
     c->batch_blocks = P->batched ? P->batch_blocks : 0;
+    c->coarse_nu1 = P->nu1c;
+    c->coarse_nu2 = P->nu2c;
 }
 
 vmg_status set_cycle(Plan* P, const vmg_cycle* c) {
@@ -522,8 +527,12 @@ vmg_status set_cycle(Plan* P, const vmg_cycle* c) {
         return fail(VMG_EINVAL, "cycle: coarse_tail 0 or 1 (periodic plans), 0 (Dirichlet plans)");
     if (P->batched ? (c->batch_blocks < 64 || c->batch_blocks > 65536) : c->batch_blocks != 0)
         return fail(VMG_EINVAL, "cycle: batch_blocks in [64, 65536] for Dirichlet plans, 0 for periodic plans");
+    if (c->coarse_nu1 < 0 || c->coarse_nu1 > 8 || c->coarse_nu2 < 0 || c->coarse_nu2 > 8)
+        return fail(VMG_EINVAL, "cycle: coarse_nu1, coarse_nu2 in [0, 8] (both 0: nu1, nu2)");
     P->nu1 = c->nu1;
     P->nu2 = c->nu2;
+    P->nu1c = c->coarse_nu1;
+    P->nu2c = c->coarse_nu2;
     if (P->mixed) P->inner = c->inner_cycles;
     P->ncoarse = c->coarse_sweeps;
     if (P->periodic) P->use_tail = c->coarse_tail != 0;
@@ -771,7 +780,11 @@ vmg_status vmg_plan_create(vmg_plan** plan, const vmg_grid* grids, int32_t n_gri
         // caller's explicit nu1/nu2 and inner_cycles take precedence
         vmg_cycle c;
         if (cached_cycle(P, &c)) {
-            if (p->nu1 != 0 || p->nu2 != 0) { c.nu1 = P->nu1; c.nu2 = P->nu2; }
+            if (p->nu1 != 0 || p->nu2 != 0) {
+                c.nu1 = P->nu1;
+                c.nu2 = P->nu2;
+                c.coarse_nu1 = c.coarse_nu2 = 0;
+            }
             if (p->inner_cycles != 0) c.inner_cycles = P->inner;
             if (!P->mixed) c.inner_cycles = 0;
             if (!P->periodic) c.coarse_tail = 0;

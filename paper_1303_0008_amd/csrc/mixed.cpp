@@ -77,7 +77,8 @@ static hipError_t inner_tail(Plan* P, GridState& G, int l) {
         a.n[q][0] = T.g.n0; a.n[q][1] = T.g.n1; a.n[q][2] = T.g.n2;
         a.h[q] = T.g.h;
         a.delta[q] = T.delta;
-        P->cell_updates += (int64_t)(q == a.nlev - 1 ? P->ncoarse : P->nu1 + P->nu2) * T.g.ncell;
+        P->cell_updates += (int64_t)(q == a.nlev - 1 ? P->ncoarse : pre_sweeps(P, l + q) + post_sweeps(P, l + q)) *
+                           T.g.ncell;
     }
     LevelBuf& L = G.lev[l];
     a.e = L.e[L.ecur];
@@ -86,7 +87,7 @@ static hipError_t inner_tail(Plan* P, GridState& G, int l) {
     a.t0 = L.t0;
     a.sc = L.scf;
     a.c64 = P->coef;
-    a.nu1 = P->nu1; a.nu2 = P->nu2; a.ncoarse = P->ncoarse;
+    a.nu1 = pre_sweeps(P, l); a.nu2 = post_sweeps(P, l); a.ncoarse = P->ncoarse;
     return launch_tail_corr(a, P->stream);
 }
 
@@ -113,9 +114,10 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e, bool f
     }
     if ((e = level_mark(P, l, true)) != hipSuccess) return e;
     // the sweep that reads no correction (zero_e) is another kernel: it is not timed
-    const int t1 = zero_e ? P->nu1 - 1 : P->nu1;
-    for (int s = 0; s < P->nu1; ++s) {
-        if (l == 0 && s == P->nu1 - t1 && (e = sweep_mark(P, true, t1)) != hipSuccess) return e;
+    const int nu1 = pre_sweeps(P, l);
+    const int t1 = zero_e ? nu1 - 1 : nu1;
+    for (int s = 0; s < nu1; ++s) {
+        if (l == 0 && s == nu1 - t1 && (e = sweep_mark(P, true, t1)) != hipSuccess) return e;
         if ((e = smooth_corr_level(P, G, l, zero_e && s == 0)) != hipSuccess) return e;
     }
     if (l == 0 && t1 > 0 && (e = sweep_mark(P, false, t1)) != hipSuccess) return e;
@@ -146,17 +148,18 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e, bool f
     // post-sweep (which is then not timed with the plain sweeps)
     const SmoothCfg cfg = level_schedule(P, l, L.g);
     const int zc = cfg.zc > 0 ? cfg.zc : 16;
-    const int s0 = P->fold_prolong && P->nu2 > 0 && can_fold_prolong(L.g, C.g, zc) && fold_prolong_pays(L.g, zc) ? 1 : 0;
+    const int nu2 = post_sweeps(P, l);
+    const int s0 = P->fold_prolong && nu2 > 0 && can_fold_prolong(L.g, C.g, zc) && fold_prolong_pays(L.g, zc) ? 1 : 0;
     if (s0) {
         const ProlongInF pro{C.g, C.e[C.ecur], C.eold};
         if ((e = smooth_corr_level(P, G, l, false, &pro)) != hipSuccess) return e;
     } else if ((e = launch_prolong_corr(L.g, C.g, L.e[L.ecur], C.e[C.ecur], C.eold, P->stream)) != hipSuccess) {
         return e;
     }
-    if (l == 0 && (e = sweep_mark(P, true, P->nu2 - s0)) != hipSuccess) return e;
-    for (int s = s0; s < P->nu2; ++s)
+    if (l == 0 && (e = sweep_mark(P, true, nu2 - s0)) != hipSuccess) return e;
+    for (int s = s0; s < nu2; ++s)
         if ((e = smooth_corr_level(P, G, l)) != hipSuccess) return e;
-    if (l == 0 && (e = sweep_mark(P, false, P->nu2 - s0)) != hipSuccess) return e;
+    if (l == 0 && (e = sweep_mark(P, false, nu2 - s0)) != hipSuccess) return e;
     return level_mark(P, l, false);
 }
 

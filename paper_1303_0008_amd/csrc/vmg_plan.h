@@ -81,6 +81,7 @@ struct Plan {
     std::vector<SmoothCfg> lcfg;           // tuned schedules of levels >= 1 (empty: level_cfg rule)
     int nu1 = 2, nu2 = 2, ncoarse = 40;
     int inner = 2;                         // mixed: FP32 inner V-cycles per outer iteration
+    int nu1c = 0, nu2c = 0;                // sweeps below the finest level (0, 0: nu1, nu2)
     bool use_tail = true;                  // periodic coarse levels <= TAIL_CELLS in one launch
     bool fold_prolong = VMG_FOLD_PROLONG;  // periodic: prolongation folded into the first post-sweep
     int batch_blocks = 1024;               // blocks of a batched plan's persistent smoother launch
@@ -139,6 +140,10 @@ struct Plan {
 vmg_status fail(vmg_status st, const std::string& msg);
 // bracket a run of `launches` consecutive finest-level sweeps with timing
 // events (no-op unless enabled)
+// pre- and post-smoothing sweeps of level l (the finest level runs nu1/nu2, the
+// coarser ones nu1c/nu2c when those are set)
+inline int pre_sweeps(const Plan* P, int l) { return l > 0 && (P->nu1c | P->nu2c) ? P->nu1c : P->nu1; }
+inline int post_sweeps(const Plan* P, int l) { return l > 0 && (P->nu1c | P->nu2c) ? P->nu2c : P->nu2; }
 hipError_t sweep_mark(Plan* P, bool begin, int launches);
 // bracket the work of level l (begin / end) when per-level timing is on
 hipError_t level_mark(Plan* P, int l, bool begin);

@@ -58,7 +58,8 @@ class Result(ctypes.Structure):
 
 class Cycle(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("inner_cycles", ctypes.c_int32),
-                ("coarse_sweeps", ctypes.c_int32), ("coarse_tail", ctypes.c_int32), ("batch_blocks", ctypes.c_int32)]
+                ("coarse_sweeps", ctypes.c_int32), ("coarse_tail", ctypes.c_int32), ("batch_blocks", ctypes.c_int32),
+                ("coarse_nu1", ctypes.c_int32), ("coarse_nu2", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

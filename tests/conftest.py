@@ -46,9 +46,10 @@ def bench_cycle(prec_name, n=256):
     with open(TUNE_FILE) as f:
         for line in f:
             parts = line.split()
-            if parts and parts[0] == f"gfx950:{n}x{n}x{n}:{prec_name}:per:1:cycle" and len(parts) == 8:
-                v = [int(x) for x in parts[1:7]]
-                return dict(zip(("nu1", "nu2", "inner_cycles", "coarse_sweeps", "coarse_tail", "batch_blocks"), v))
+            if parts and parts[0] == f"gfx950:{n}x{n}x{n}:{prec_name}:per:1:cycle" and len(parts) in (8, 10):
+                v = [int(x) for x in parts[1:-1]] + [0, 0]
+                return dict(zip(("nu1", "nu2", "inner_cycles", "coarse_sweeps", "coarse_tail", "batch_blocks",
+                                 "coarse_nu1", "coarse_nu2"), v))
     return None
 
 

@@ -135,11 +135,13 @@ def test_set_schedule_rejects_bad_arguments(torch_cuda, V):
                 p.set_schedule(lev, ty, zc, pipe)
             assert ei.value.status == V.VMG_EINVAL
         for bad in (dict(nu1=0, nu2=0), dict(nu1=9), dict(inner_cycles=2), dict(coarse_sweeps=0),
-                    dict(coarse_sweeps=65), dict(coarse_tail=2), dict(batch_blocks=1024)):
+                    dict(coarse_sweeps=65), dict(coarse_tail=2), dict(batch_blocks=1024), dict(coarse_nu1=9),
+                    dict(coarse_nu2=-1)):
             with pytest.raises(V.VmgError) as ei:
                 p.set_cycle(**bad)
             assert ei.value.status == V.VMG_EINVAL
-        assert p.cycle() == dict(nu1=2, nu2=2, inner_cycles=0, coarse_sweeps=8, coarse_tail=1, batch_blocks=0)
+        assert p.cycle() == dict(nu1=2, nu2=2, inner_cycles=0, coarse_sweeps=8, coarse_tail=1, batch_blocks=0,
+                                 coarse_nu1=0, coarse_nu2=0)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -198,7 +200,9 @@ def test_graph_first_and_second_solve_same_path(torch_cuda, V):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("cycle", [dict(nu1=1, nu2=1, coarse_sweeps=2, coarse_tail=0),
                                    dict(nu1=3, nu2=2, coarse_sweeps=16, coarse_tail=1),
-                                   dict(nu1=0, nu2=2, coarse_sweeps=4, coarse_tail=0)])
+                                   dict(nu1=0, nu2=2, coarse_sweeps=4, coarse_tail=0),
+                                   dict(nu1=2, nu2=2, coarse_sweeps=2, coarse_tail=1, coarse_nu1=1, coarse_nu2=1),
+                                   dict(nu1=2, nu2=3, coarse_sweeps=2, coarse_tail=0, coarse_nu1=2, coarse_nu2=1)])
 def test_cycle_schedules_vs_oracle(torch_cuda, V, oracle_mod, prec, cycle):
     """Every cycle schedule the tuner may pick solves the same discrete problem."""
     p = V.FP64 if prec == "fp64" else V.MIXED
