@@ -76,8 +76,8 @@ def lib():
         L.or_mass_assign.argtypes = [dp, ctypes.c_long, ip, ctypes.c_int, dp]
         L.or_mass_assign_region.argtypes = [dp, ctypes.c_long, ip, ctypes.c_double, dp, ctypes.c_double,
                                              ctypes.c_int, dp]
-        L.or_truncation_error.argtypes = [ip, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                          dp, dp, dp, dp]
+        L.or_truncation_error.argtypes = [ip, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, dp, dp, dp, dp, dp]
         L.or_ghost_count.argtypes = [ip]
         L.or_ghost_count.restype = ctypes.c_long
         _lib = L
@@ -230,16 +230,19 @@ def total_force(phi_n, phi, h):
     return psi, g
 
 
-def truncation_error(delta, phi, alpha, kappa, h=None, w=W_PAPER):
+def truncation_error(delta, phi, alpha, kappa, h=None, ghost=None, w=W_PAPER):
     """Truncation-error estimate tau^h = L^H(R phi) - R L^h(phi) of Sec. III.C on
-    the next coarser level of a periodic grid (even sides).  Returns (tau, rms)
-    with rms the RMS of tau after removing its mean."""
-    delta, phi = _f64(delta), _f64(phi)
+    the next coarser level of a grid with even sides: periodic if ``ghost`` is
+    None, else Dirichlet with those boundary values (the coarse level reads their
+    restriction).  Returns (tau, rms): rms is the RMS of tau, with its mean
+    removed on a periodic grid."""
+    delta, phi, ghost = _f64(delta), _f64(phi), _f64(ghost)
     n = _dims(delta)
     h = 1.0 / n[0] if h is None else h
     tau = np.zeros(tuple(s // 2 for s in delta.shape))
     rms = ctypes.c_double()
-    rc = lib().or_truncation_error(_ivec(n), h, alpha, kappa, w, _dp(delta), _dp(phi), _dp(tau),
+    rc = lib().or_truncation_error(_ivec(n), 1 if ghost is None else 0, h, alpha, kappa, w, _dp(delta),
+                                   _dp(ghost), _dp(phi), _dp(tau),
                                    ctypes.cast(ctypes.pointer(rms), ctypes.POINTER(ctypes.c_double)))
     assert rc == 0
     return tau, rms.value

@@ -724,21 +724,32 @@ int or_total_force(const int n[3], double h, const double *phi_n, const double *
 /* ------------------------------------------------------------------------- */
 /* truncation-error estimate (Sec. III.C)                                     */
 /* ------------------------------------------------------------------------- */
-/* tau^h = L^H(R phi^h) - R L^h(phi^h) on the next coarser level of a periodic
- * grid with even sides (coarse density R delta), written unpadded to tau
- * (n/2 cells per axis); *rms = RMS of tau with its mean removed (a constant
- * carries no information on a periodic grid).  Returns 0, or -1 for odd sides. */
-int or_truncation_error(const int n[3], double h, double alpha, double kappa, double w, const double *delta,
-                        const double *phi, double *tau, double *rms) {
-    if ((n[0] & 1) || (n[1] & 1) || (n[2] & 1)) return -1;
-    const OGrid gf = {{n[0], n[1], n[2]}, 1, h};
-    const OGrid gc = {{n[0] / 2, n[1] / 2, n[2] / 2}, 1, 2.0 * h};
+/* tau^h = L^H(R phi^h) - R L^h(phi^h) on the next coarser level of a grid with
+ * even sides (coarse density R delta), written unpadded to tau (n/2 cells per
+ * axis).
+ * Periodic: *rms = RMS of tau with its mean removed (a constant carries no
+ * information on a periodic grid).
+ * Dirichlet (ghost = the grid's boundary values in the compact order of
+ * ghosts_to_pad): the coarse operator reads the restricted boundary values (mean
+ * of the fine ghost cells inside each coarse ghost cell), the values a coarse
+ * level of the V-cycle holds when its right-hand side is formed; *rms = plain RMS
+ * of tau (no free constant on such a grid).
+ * Returns 0, or -1 for odd sides or a Dirichlet grid without ghosts. */
+int or_truncation_error(const int n[3], int periodic, double h, double alpha, double kappa, double w,
+                        const double *delta, const double *ghost, const double *phi, double *tau, double *rms) {
+    if ((n[0] & 1) || (n[1] & 1) || (n[2] & 1) || (!periodic && !ghost)) return -1;
+    const OGrid gf = {{n[0], n[1], n[2]}, periodic, h};
+    const OGrid gc = {{n[0] / 2, n[1] / 2, n[2] / 2}, periodic, 2.0 * h};
     const OCoef c = or_coeffs(alpha, kappa, w);
     double *pf = calloc(npad(&gf), sizeof(double)), *df = calloc(npad(&gf), sizeof(double));
     double *lf = calloc(npad(&gf), sizeof(double));
     double *pc = calloc(npad(&gc), sizeof(double)), *dc = calloc(npad(&gc), sizeof(double));
     unpack(&gf, phi, pf);
     unpack(&gf, delta, df);
+    if (!periodic) {
+        ghosts_to_pad(&gf, ghost, pf);
+        restrict_ghosts(&gf, pf, &gc, pc);
+    }
     for (int k = 0; k < n[2]; ++k)
         for (int j = 0; j < n[1]; ++j)
             for (int i = 0; i < n[0]; ++i) lf[pidx(&gf, i, j, k)] = Lh(&gf, &c, pf, df, i, j, k, NULL, NULL);
@@ -754,7 +765,7 @@ int or_truncation_error(const int n[3], double h, double alpha, double kappa, do
                 ks_add(&s1, t);
                 ks_add(&s2, t * t);
             }
-    const double N = (double)q, m = ks_val(&s1) / N;
+    const double N = (double)q, m = periodic ? ks_val(&s1) / N : 0.0;
     *rms = sqrt(fmax(ks_val(&s2) / N - m * m, 0.0));
     free(pf); free(df); free(lf); free(pc); free(dc);
     return 0;

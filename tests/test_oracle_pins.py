@@ -620,6 +620,70 @@ def test_truncation_error_mirror_symmetry(oracle_mod):
     assert np.abs(tau_m[:, :, ::-1] - tau).max() <= 1e-12 * np.abs(tau).max()
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_truncation_error_dirichlet_closed_form_linear(oracle_mod, axis):
+    """alpha = 0 on a Dirichlet grid whose ghosts hold phi = sin(k x) itself (k not
+    a box mode).  The fine operator is then exact at every cell, so R L^h phi keeps
+    the periodic closed form; the coarse ghost along the axis is the fine ghost
+    (the only fine ghost cell inside it) instead of the coarse extension
+    cos(k h/2) sin(k X), which adds (ghost - cos(k h/2) sin(k X_ghost)) / H^2 at the
+    two coarse cells next to the boundary; the transverse ghosts carry the same
+    restricted values as the interior and add nothing."""
+    n, h = 16, 1.0 / 16
+    H = 2 * h
+    k = 2 * np.pi * 1.37
+    x = (np.arange(-1, n + 1) + 0.5) * h                   # cell centres, ghosts included
+    X = (np.arange(-1, n // 2 + 1) + 0.5) * H
+    shape = [1, 1, 1]
+    shape[2 - axis] = n + 2
+    P = np.broadcast_to(np.sin(k * x).reshape(shape), (n + 2,) * 3).copy()
+    phi = P[1:-1, 1:-1, 1:-1].copy()
+    delta = np.random.default_rng(21 + axis).standard_normal((n, n, n))
+    tau, rms = oracle_mod.truncation_error(delta, phi, 0.0, 1.5, h=h, ghost=pack_ghosts(P))
+    c = np.cos(k * h / 2)
+    ref = c * np.sin(k * X[1:-1]) * (4 / h**2 * np.sin(k * h / 2) ** 2 - 4 / H**2 * np.sin(k * H / 2) ** 2)
+    ref[0] += (np.sin(k * x[0]) - c * np.sin(k * X[0])) / H**2
+    ref[-1] += (np.sin(k * x[-1]) - c * np.sin(k * X[-1])) / H**2
+    cshape = [1, 1, 1]
+    cshape[2 - axis] = n // 2
+    ref = np.broadcast_to(ref.reshape(cshape), tau.shape)
+    assert np.abs(tau - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert abs(rms - np.sqrt(np.mean(ref ** 2))) <= 1e-12 * np.abs(ref).max()     # no mean removed
+
+
+def test_truncation_error_dirichlet_embedded_in_periodic(oracle_mod):
+    """alpha != 0: a Dirichlet box cut from a periodic field, with ghosts taken from
+    that field, has the periodic field's tau at every coarse cell when the field
+    repeats the ghost layer one cell further out (then each coarse ghost, the mean
+    of the fine ghosts inside it, equals the periodic coarse value there, edges
+    included).  Checks the ghost shell of both levels and the nonlinear operator
+    at the boundary against the periodic estimate, pinned by closed forms above."""
+    rng = np.random.default_rng(23)
+    N, lo, hi = 16, 4, 12
+    G = 0.01 * rng.standard_normal((N, N, N))
+    c = np.clip(np.arange(N), lo - 1, hi)
+    phi_p = G[np.ix_(c, c, c)]
+    delta_p = rng.standard_normal((N, N, N))
+    tau_p, _ = oracle_mod.truncation_error(delta_p, phi_p, 0.2, 1.5)
+    s = slice(lo, hi)
+    ghost = pack_ghosts(phi_p[lo - 1:hi + 1, lo - 1:hi + 1, lo - 1:hi + 1])
+    tau_d, rms_d = oracle_mod.truncation_error(delta_p[s, s, s], phi_p[s, s, s], 0.2, 1.5, h=1.0 / N, ghost=ghost)
+    cs = slice(lo // 2, hi // 2)
+    ref = tau_p[cs, cs, cs]
+    assert np.abs(tau_d - ref).max() <= 1e-11 * np.abs(ref).max()
+    assert abs(rms_d - np.sqrt(np.mean(ref ** 2))) <= 1e-11 * np.abs(ref).max()
+
+
+def test_truncation_error_dirichlet_uniform_state(oracle_mod):
+    """A constant phi with the same constant on the ghosts, uniform density:
+    both levels' operators vanish, tau = 0 (alpha != 0)."""
+    n = 8
+    P = np.full((n + 2,) * 3, -0.41)
+    tau, rms = oracle_mod.truncation_error(np.zeros((n, n, n)), P[1:-1, 1:-1, 1:-1].copy(), 0.2, 1.5,
+                                           h=1.0 / 32, ghost=pack_ghosts(P))
+    assert np.abs(tau).max() == 0.0 and rms == 0.0
+
+
 # ---------------------------------------------------------------------------
 # mass assignment (Sec. VI: the mesh density comes from triangular-shaped-cloud
 # assignment of the particles; cloud in cell is the lower-order member)

@@ -38,6 +38,7 @@ SCRIPT = textwrap.dedent("""
     d = rng.standard_normal((8, 8, 8))
     phi, info = O.solve(d, 0.2, 1.5, h=1.0 / 16, ghost=gh, phi0=p0, tol=1e-9, max_cycles=20)
     O.residual(d, phi, 0.2, 1.5, h=1.0 / 16, ghost=gh)
+    O.truncation_error(d, phi, 0.2, 1.5, h=1.0 / 16, ghost=gh)
     # multilevel tree: domain and one refinement
     root = dict(delta=P * 0 + rng.standard_normal((8, 8, 8)), h=1.0 / 8, parent=-1, origin=(0, 0, 0))
     root["delta"] -= root["delta"].mean()
