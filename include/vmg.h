@@ -99,8 +99,9 @@ typedef struct {
                               must be 0 for VMG_FP64 */
     double tau_factor;     /* > 0: also stop once |d^h| <= tau_factor |tau^h| on every grid,
                               tau^h = L^H(R phi) - R L^h(phi) the truncation-error estimate of
-                              Sec. III.C (the paper takes the factor <= 1/3); FP64 plans of
-                              one periodic grid with coarser levels only; 0 = off */
+                              Sec. III.C (the paper takes the factor <= 1/3), both at the same
+                              phi; on a Dirichlet grid the coarse operator reads the restricted
+                              boundary values.  Every grid needs a coarser level; 0 = off */
 } vmg_params;
 
 typedef struct {
@@ -124,8 +125,8 @@ typedef struct vmg_plan vmg_plan;
  * without allocating.  All later work is issued on `stream` (0: a blocking
  * stream the plan creates, since the legacy null stream cannot be captured).
  * Errors: VMG_EINVAL (sizes, h <= 0, tol <= 0, max_cycles < 1, inner_cycles < 0 or
- * set for VMG_FP64, tau_factor < 0 or not finite, tau_factor > 0 with VMG_MIXED, with
- * several grids or with a grid that has no coarser level, mixed BC kinds,
+ * set for VMG_FP64, tau_factor < 0 or not finite, tau_factor > 0 with a grid that has
+ * no coarser level, mixed BC kinds,
  * a periodic grid that does not coarsen to <= 8 cells per side, a Dirichlet
  * grid whose coarsest level exceeds 8 cells per side), VMG_ENOMEM, VMG_EHIP. */
 vmg_status vmg_plan_create(vmg_plan **plan, const vmg_grid *grids, int32_t n_grids,
@@ -203,8 +204,8 @@ typedef struct {
  * trilinearly from its parent's solution (as vmg_fill_ghosts and
  * vmg_fill_interior).  Refinements do not feed back into their parents.
  * delta, ghost and phi are device arrays holding every grid at its offset (x
- * fastest); phi receives every solution.  p applies to every level (tau_factor
- * to the domain grid only); out: host array of n_grids results.  Creates and
+ * fastest); phi receives every solution.  p applies to every level; out: host
+ * array of n_grids results.  Creates and
  * destroys its plans (allocates).  Errors: VMG_EINVAL (nesting or arguments),
  * otherwise the first failing level's status (VMG_ENOCONV, VMG_ENONFINITE,
  * ...; deeper levels are then not solved), VMG_EHIP.  Equivalent to

@@ -186,13 +186,27 @@ vmg_status build_batch(Plan* P) {
         blk += (int)((g.ncell + 255) / 256);
     }
     first.push_back(blk);
+    // level-1 block ranges, for the truncation-error estimate
+    std::vector<int> first1;
+    if (P->blev.size() > 1 && P->blev[1].members.size() == B0.members.size()) {
+        int b1 = 0;
+        for (size_t k = 0; k < B0.members.size(); ++k) {
+            first1.push_back(b1);
+            b1 += (int)((P->grids[B0.members[k]].lev[1].g.ncell + 255) / 256);
+        }
+        first1.push_back(b1);
+    }
     P->bngitems = (int)gitems.size();
     if (upload(P, &P->d_uoff, uoff) != hipSuccess || upload(P, &P->d_goff, goff) != hipSuccess ||
-        upload(P, &P->d_gitems, gitems) != hipSuccess || upload(P, &P->d_first, first) != hipSuccess)
+        upload(P, &P->d_gitems, gitems) != hipSuccess || upload(P, &P->d_first, first) != hipSuccess ||
+        upload(P, &P->d_first1, first1) != hipSuccess)
         return fail(VMG_EHIP, "upload of batch metadata failed");
     if (hipMalloc((void**)&P->d_norms, sizeof(NormOut) * B0.members.size()) != hipSuccess)
         return fail(VMG_ENOMEM, "hipMalloc failed (batch norms)");
     P->allocs.push_back(P->d_norms);
+    if (launch_fill((double*)P->d_norms, (int64_t)B0.members.size() * (sizeof(NormOut) / sizeof(double)), 0.0,
+                    P->stream) != hipSuccess)
+        return fail(VMG_EHIP, "fill failed");
     if (batch_build_smooth_items(P) != hipSuccess) return fail(VMG_EHIP, "upload of smoother items failed");
     return VMG_OK;
 }
@@ -250,10 +264,29 @@ static hipError_t bcycle(Plan* P, int l) {
     return hipSuccess;
 }
 
+// Truncation-error estimate tau^h = L^H(R phi) - R L^h(phi) of every grid at the
+// finest state phi (Sec. III.C) into d_norms[k].tau_rms, when the plan stops on
+// it: restriction of phi and d to level 1 (as the head of a cycle), the coarse
+// ghosts reset to the restricted boundary values, then the estimate.  Level 1 is
+// scratch between cycles (the next head rewrites what this overwrites).
+static hipError_t btau(Plan* P, const double* phi) {
+    if (!(P->params.tau_factor > 0.0)) return hipSuccess;
+    if (!P->d_first1) return hipErrorInvalidValue;   // plan creation requires level 1 on every grid
+    BatchLevel& B = P->blev[0];
+    BatchLevel& C = P->blev[1];
+    hipStream_t s = P->stream;
+    CKE(launch_rr_batch(C.d_geom_fine, C.d_geom, C.d_cells, C.ncells, P->coef, phi, B.delta, bf(P, 0), C.phi[0],
+                        C.phiold, C.rd, s));
+    CKE(launch_ghost_refresh_batch(C.d_geom, C.d_ghosts, C.nghost_items, C.phi[0], C.phiold, s));
+    return launch_tau_batch(C.d_geom, C.d_geom_fine, C.d_cells, C.ncells, P->coef, C.phi[0], C.delta, C.rd,
+                            bf(P, 0), P->partials, P->d_first1, (int)C.members.size(), P->d_norms, s);
+}
+
 static hipError_t bnorms(Plan* P) {
     BatchLevel& B = P->blev[0];
     CKE(launch_norm_batch(B.d_geom, B.d_cells, B.ncells, P->coef, B.phi[B.cur], B.delta, bf(P, 0), P->partials,
                           P->d_first, (int)B.members.size(), P->d_norms, P->stream));
+    CKE(btau(P, B.phi[B.cur]));
     return hipMemcpyAsync(P->host_norm, P->d_norms, sizeof(NormOut) * B.members.size(), hipMemcpyDeviceToHost,
                           P->stream);
 }
@@ -306,6 +339,7 @@ static hipError_t bcast(Plan* P) {
     CKE(launch_cast_batch(B.d_geom, B.d_cells, B.ncells, P->coef, B.phi[0], B.delta, bf(P, 0), B.pt, B.t0, B.r,
                           P->partials, P->stream));
     CKE(launch_finalize_batch(P->partials, P->d_first, B.d_geom, (int)B.members.size(), P->d_norms, P->stream));
+    CKE(btau(P, B.phi[0]));
     return hipMemcpyAsync(P->host_norm, P->d_norms, sizeof(NormOut) * B.members.size(), hipMemcpyDeviceToHost,
                           P->stream);
 }

@@ -148,8 +148,10 @@ vmg_status build_plan(Plan* P, const vmg_grid* grids, int n_grids, const vmg_par
         }
         if (P->mixed && (st = alloc_mixed(P)) != VMG_OK) return st;
     }
-    for (auto& G : P->grids)
+    for (auto& G : P->grids) {
         if ((st = dalloc(P, (void**)&G.norm_dev, sizeof(NormOut))) != VMG_OK) return st;
+        CKH(launch_fill((double*)G.norm_dev, sizeof(NormOut) / sizeof(double), 0.0, stream));
+    }
     int64_t nb = partial_blocks_for(max_cells);
     for (auto& G : P->grids)
         for (auto& L : G.lev) nb = std::max<int64_t>(nb, resid_blocks(L.g));
@@ -756,8 +758,6 @@ vmg_status vmg_plan_create(vmg_plan** plan, const vmg_grid* grids, int32_t n_gri
         !std::isfinite(p->tau_factor))
         return fail(VMG_EINVAL, "invalid parameters (tol > 0, max_cycles >= 1, prec, nu1/nu2 >= 0, finite alpha/kappa, "
                                 "tau_factor >= 0)");
-    if (p->tau_factor > 0.0 && (p->prec != VMG_FP64 || n_grids != 1 || grids[0].bc != VMG_PERIODIC))
-        return fail(VMG_EINVAL, "tau_factor needs an FP64 plan of one periodic grid");
     const int bc0 = grids[0].bc;
     for (int i = 0; i < n_grids; ++i) {
         const vmg_grid& g = grids[i];
@@ -770,11 +770,16 @@ vmg_status vmg_plan_create(vmg_plan** plan, const vmg_grid* grids, int32_t n_gri
         if (g.offset < 0 || g.ghost_offset < 0) return fail(VMG_EINVAL, "negative offset");
     }
     if (bc0 == VMG_PERIODIC && n_grids != 1) return fail(VMG_EINVAL, "a periodic plan holds exactly one grid");
+    if (p->tau_factor > 0.0)
+        for (int i = 0; i < n_grids; ++i) {
+            const vmg_grid& g = grids[i];
+            if (!can_coarsen(make_geom(g.n[0], g.n[1], g.n[2], g.bc == VMG_DIRICHLET, g.h)))
+                return fail(VMG_EINVAL, "tau_factor needs grids with a coarser level (tau^h lives on it); grid " +
+                                            std::to_string(i) + " has none");
+        }
     Plan* P = new (std::nothrow) Plan();
     if (!P) return fail(VMG_ENOMEM, "host allocation failed");
     vmg_status st = build_plan(P, grids, n_grids, p, stream);
-    if (st == VMG_OK && p->tau_factor > 0.0 && !shifted_cycles(P))
-        st = fail(VMG_EINVAL, "tau_factor needs a grid with a coarser level (tau^h lives on it)");
     if (st == VMG_OK && (p->flags & VMG_AUTOTUNE)) {
         // a cycle schedule vmg_plan_tune_cycle cached for this plan's key; the
         // caller's explicit nu1/nu2 and inner_cycles take precedence
@@ -911,7 +916,6 @@ vmg_status vmg_levels_create(vmg_levels** out, const vmg_grid* grids, const vmg_
     for (int i = 0; i < n_grids; ++i) L->members[depth[i]].push_back(i);
     vmg_params pr = *p;
     for (int d = 0; d <= max_depth; ++d) {
-        if (d > 0) pr.tau_factor = 0.0;            // the truncation-error rule applies to the domain grid only
         std::vector<vmg_grid> sub;
         for (int i : L->members[d]) sub.push_back(grids[i]);
         vmg_plan* plan = nullptr;

@@ -897,6 +897,41 @@ __global__ void __launch_bounds__(NT) k_fas_batch(const Geom* __restrict__ gs, c
     f[gi] = L - rd[gi];
 }
 
+// Truncation-error estimate on the next coarser level of every grid (Sec. III.C):
+// with phi^H = R phi^h and rd = R d^h just formed by k_rr_batch (d^h = L^h phi^h
+// - f^h on Dirichlet grids), tau^h = L^H(R phi^h) - R L^h(phi^h) = L^H(phi^H) -
+// rd - R f^h.  Block partials of tau and tau^2 (grid k's blocks are contiguous).
+__global__ void __launch_bounds__(NT) k_tau_batch(const Geom* __restrict__ gs, const Geom* __restrict__ gfs,
+                                                  const int2* __restrict__ items, Coef c,
+                                                  const double* __restrict__ phi, const double* __restrict__ delta,
+                                                  const double* __restrict__ rd, const double* __restrict__ f_fine,
+                                                  double* partials) {
+    double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
+    const int2 w = items[blockIdx.x];
+    const Geom g = gs[w.x];
+    const int64_t e = (int64_t)w.y + threadIdx.x;
+    if (e < g.ncell) {
+        const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+        int I, J, K;
+        decode(g, e, I, J, K);
+        double Q, pc, fv;
+        bool gd;
+        const double L = cell_residual<1>(g, c, phi, delta, nullptr, 0.0, I, J, K, inv_h2, inv_h4, Q, gd, pc, fv);
+        double tau = L - rd[cell_index(g, I, J, K)];
+        if (f_fine) {
+            const Geom gf = gfs[w.x];
+            double rf = 0.0;
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                rf += f_fine[cell_index(gf, 2 * I + (m & 1), 2 * J + ((m >> 1) & 1), 2 * K + (m >> 2))];
+            tau -= 0.125 * rf;
+        }
+        acc[R_D1] = tau;
+        acc[R_D2] = tau * tau;
+    }
+    block_store_partials(acc, partials);
+}
+
 __global__ void __launch_bounds__(NT) k_prolong_batch(const Geom* __restrict__ gfs, const Geom* __restrict__ gcs,
                                                       const int2* __restrict__ items, double* __restrict__ phif,
                                                       const double* __restrict__ phic,
@@ -951,9 +986,11 @@ __global__ void __launch_bounds__(NT) k_norm_batch(const Geom* __restrict__ gs, 
 }
 
 // one block per grid: sum its blocks' partials [first[k], first[k+1]) in a fixed order
+// tau = 0: the residual norms of the grids; tau = 1: out[k].tau_rms only, the RMS of
+// the estimate (no mean removed: a Dirichlet grid has no free constant)
 __global__ void __launch_bounds__(NT) k_finalize_batch(const double* __restrict__ partials,
                                                        const int* __restrict__ first,
-                                                       const Geom* __restrict__ gs, NormOut* out) {
+                                                       const Geom* __restrict__ gs, NormOut* out, int tau) {
     __shared__ double red[NT / 64][R_NSLOT];
     const int k = blockIdx.x;
     double acc[R_NSLOT];
@@ -976,6 +1013,10 @@ __global__ void __launch_bounds__(NT) k_finalize_batch(const double* __restrict_
         for (int m = 0; m < NT / 64; ++m) tot[q] += red[m][q];
     }
     const double N = (double)gs[k].ncell;
+    if (tau) {
+        out[k].tau_rms = sqrt(fmax(tot[R_D2], 0.0) / N);
+        return;
+    }
     out[k].rms = sqrt(fmax(tot[R_D2], 0.0) / N);
     out[k].cbar = 0.0;
     out[k].mean_phi = tot[R_PHI] / N;
@@ -1417,6 +1458,16 @@ hipError_t launch_fas_batch(const Geom* gs, const int2* items, int nitems, const
     return hipGetLastError();
 }
 
+hipError_t launch_tau_batch(const Geom* gs, const Geom* gfs, const int2* items, int nitems, const Coef& c,
+                            const double* phi, const double* delta, const double* rd, const double* f_fine,
+                            double* partials, const int* first, int ngrids, NormOut* out, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tau_batch, dim3(nitems), dim3(NT), 0, s, gs, gfs, items, c, phi, delta, rd, f_fine,
+                       partials);
+    hipLaunchKernelGGL(k_finalize_batch, dim3(ngrids), dim3(NT), 0, s, partials, first, gs, out, 1);
+    return hipGetLastError();
+}
+
 hipError_t launch_prolong_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, double* phif,
                                 const double* phic, const double* oldc, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
@@ -1429,13 +1480,13 @@ hipError_t launch_norm_batch(const Geom* gs, const int2* items, int nitems, cons
                              NormOut* out, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_norm_batch, dim3(nitems), dim3(NT), 0, s, gs, items, c, phi, delta, f, partials);
-    hipLaunchKernelGGL(k_finalize_batch, dim3(ngrids), dim3(NT), 0, s, partials, first, gs, out);
+    hipLaunchKernelGGL(k_finalize_batch, dim3(ngrids), dim3(NT), 0, s, partials, first, gs, out, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize_batch(const double* partials, const int* first, const Geom* gs, int ngrids,
                                  NormOut* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize_batch, dim3(ngrids), dim3(NT), 0, s, partials, first, gs, out);
+    hipLaunchKernelGGL(k_finalize_batch, dim3(ngrids), dim3(NT), 0, s, partials, first, gs, out, 0);
     return hipGetLastError();
 }
 

@@ -184,6 +184,23 @@ static hipError_t cast_pass(Plan* P, GridState& G, bool update) {
     return level_mark(P, 0, false);
 }
 
+// Truncation-error estimate tau^h = L^H(R phi) - R L^h(phi) of the current FP64
+// phi (Sec. III.C) into the grid's NormOut, for plans that stop on it: the FP64
+// head passes of a cycle (restriction of phi and d, coarse right-hand side with
+// its tau sums) over level 1, whose FP64 buffers the mixed path leaves unused.
+static hipError_t tau_pass(Plan* P, GridState& G) {
+    LevelBuf& L = G.lev[0];
+    LevelBuf& C = G.lev[1];
+    int nb = 0, nbc = 0;
+    hipError_t e = launch_residual_restrict(L.g, C.g, P->coef, L.phi[L.cur], L.delta, level0_f(P, G), L.sc,
+                                            C.phi[0], C.phiold, C.rd, P->partials, &nb, P->stream);
+    if (e != hipSuccess) return e;
+    if ((e = launch_fas_rhs(C.g, P->coef, C.phi[0], C.delta, C.rd, C.f, P->partials_b, &nbc, P->stream,
+                            level0_f(P, G), &L.g)) != hipSuccess)
+        return e;
+    return launch_finalize(P->partials_b, nbc, C.g.ncell, C.g.dir ? 0 : 1, 1, C.sc, G.norm_dev, P->stream);
+}
+
 static hipError_t norms_to_host(Plan* P) {
     for (size_t gi = 0; gi < P->grids.size(); ++gi) {
         hipError_t e = hipMemcpyAsync(&P->host_norm[gi], P->grids[gi].norm_dev, sizeof(NormOut),
@@ -212,6 +229,7 @@ hipError_t enqueue_outer(Plan* P) {
         for (int c = 0; c < P->inner; ++c)
             if ((e = inner_vcycle(P, G, 0, zero_e && c == 0, c == 0)) != hipSuccess) return e;
         if ((e = cast_pass(P, G, true)) != hipSuccess) return e;
+        if (P->params.tau_factor > 0.0 && (e = tau_pass(P, G)) != hipSuccess) return e;
     }
     return norms_to_host(P);
 }

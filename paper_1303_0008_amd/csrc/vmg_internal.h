@@ -270,6 +270,12 @@ hipError_t launch_fas_batch(const Geom* gs, const int2* items, int nitems, const
                             const double* delta, const double* rd, double* f, hipStream_t s);
 hipError_t launch_prolong_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, double* phif,
                                 const double* phic, const double* oldc, hipStream_t s);
+// tau^h of every grid on level 1 (items: level-1 cells; first: each grid's block
+// range in them) into out[k].tau_rms; phi, delta, rd are the level-1 pools after
+// launch_rr_batch and the ghost refresh, f_fine the finest level's f (or null)
+hipError_t launch_tau_batch(const Geom* gs, const Geom* gfs, const int2* items, int nitems, const Coef& c,
+                            const double* phi, const double* delta, const double* rd, const double* f_fine,
+                            double* partials, const int* first, int ngrids, NormOut* out, hipStream_t s);
 hipError_t launch_norm_batch(const Geom* gs, const int2* items, int nitems, const Coef& c, const double* phi,
                              const double* delta, const double* f, double* partials, const int* first, int ngrids,
                              NormOut* out, hipStream_t s);

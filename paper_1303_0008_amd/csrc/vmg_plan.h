@@ -134,6 +134,7 @@ struct Plan {
     int2* d_gitems = nullptr;        // 256-value blocks of every grid's ghosts
     int bngitems = 0;
     int* d_first = nullptr;          // first norm block of each grid (+ end)
+    int* d_first1 = nullptr;         // the same for level 1 (tau^h), when every grid has it
     NormOut* d_norms = nullptr;
 };
 

@@ -1,11 +1,13 @@
 """The truncation-error stopping rule of Sec. III.C (|d^h| <= f |tau^h|, f <= 1/3)
-on the FP64 path, against the oracle's own estimate tau^h = L^H(R phi) -
-R L^h(phi) evaluated at the phi the GPU returns.
+against the oracle's own estimate tau^h = L^H(R phi) - R L^h(phi) evaluated at
+the phi the GPU returns: the periodic grid on the FP64 and mixed paths, and
+batches of Dirichlet grids (every grid stops on its own estimate, the coarse
+operator reading the restricted boundary values).
 
 The GPU forms tau^h as f^H - R f^h (+ cbar, a constant removed on periodic
-grids) inside the coarse right-hand-side pass; the oracle from its definition.
-Both RMS values must agree to 1e-9 relative (rounding of two different
-formulas at FP64, on values of size ~|L phi|)."""
+grids) from the passes that form the coarse right-hand side; the oracle from
+its definition.  Both RMS values must agree to 1e-9 relative (rounding of two
+different formulas at FP64, on values of size ~|L phi|)."""
 import numpy as np
 import pytest
 
@@ -37,20 +39,22 @@ def say(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("shape,alpha,seed", [((32, 32, 32), 0.1, 701), ((48, 32, 40), 0.2, 702)])
-def test_tau_stopping_rule(torch_cuda, V, oracle_mod, shape, alpha, seed):
+@pytest.mark.parametrize("shape,alpha,seed,prec", [((32, 32, 32), 0.1, 701, "fp64"), ((48, 32, 40), 0.2, 702, "fp64"),
+                                                   ((32, 32, 32), 0.1, 703, "mixed")])
+def test_tau_stopping_rule(torch_cuda, V, oracle_mod, shape, alpha, seed, prec):
     torch = torch_cuda
-    say("tau stop", shape, alpha)
+    pr = V.FP64 if prec == "fp64" else V.MIXED
+    say("tau stop", shape, alpha, prec)
     delta = I.lognormal(shape, seed, sigma=1.0)
     n2, n1, n0 = delta.shape
     d_t = dev(torch, delta)
     factor = 1.0 / 3.0
     # reference: the same solve to a tight tolerance only
     phi_full = torch.zeros_like(d_t)
-    with V.Plan([V.make_grid((n0, n1, n2))], V.make_params(alpha, 1.5, 1e-12, 80)) as p:
+    with V.Plan([V.make_grid((n0, n1, n2))], V.make_params(alpha, 1.5, 1e-12, 80, pr)) as p:
         r_full = p.solve(d_t, phi_full, allow_noconv=True)[0]
     phi_t = torch.zeros_like(d_t)
-    with V.Plan([V.make_grid((n0, n1, n2))], V.make_params(alpha, 1.5, 1e-12, 80, tau_factor=factor)) as p:
+    with V.Plan([V.make_grid((n0, n1, n2))], V.make_params(alpha, 1.5, 1e-12, 80, pr, tau_factor=factor)) as p:
         r = p.solve(d_t, phi_t)[0]
     say("  tau stop", r, "full", r_full["cycles"], r_full["rms"])
     assert r["status"] == V.VMG_OK and r["tau_rms"] > 0.0
@@ -67,10 +71,69 @@ def test_tau_stopping_rule(torch_cuda, V, oracle_mod, shape, alpha, seed):
     assert err <= 0.1 * r["tau_rms"]
 
 
+def _dirichlet_batch(V, oracle_mod, sizes, h, seed, amp=2e-5):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    grids, deltas, ghosts = [], [], []
+    off = goff = 0
+    for i, n in enumerate(sizes):
+        d = I.lognormal(n, seed * 100 + i, sigma=1.5)
+        g = amp * rng.standard_normal(oracle_mod.ghost_count(n))
+        grids.append(V.make_grid(n, h, V.DIRICHLET, off, goff))
+        deltas.append(d)
+        ghosts.append(g)
+        off += d.size
+        goff += g.size
+    return grids, deltas, ghosts
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_tau_stopping_rule_dirichlet_batch(torch_cuda, V, oracle_mod, prec):
+    """Uneven Dirichlet grids in one batched plan: the solve stops once every grid
+    meets |d| <= f |tau| (the tolerance is out of reach), and each grid's tau RMS
+    is the oracle's estimate at the returned phi with that grid's ghosts."""
+    torch = torch_cuda
+    pr = V.FP64 if prec == "fp64" else V.MIXED
+    sizes = [(16, 16, 16), (24, 24, 24), (8, 12, 16), (32, 32, 32)]
+    h = 1.0 / 512
+    grids, deltas, ghosts = _dirichlet_batch(V, oracle_mod, sizes, h, 31)
+    say("tau stop dirichlet", prec)
+    dt = dev(torch, np.concatenate([d.ravel() for d in deltas]))
+    gt = dev(torch, np.concatenate(ghosts))
+    factor = 1.0 / 3.0
+    phi_full = torch.zeros_like(dt)
+    with V.Plan(grids, V.make_params(0.1, 1.5, 1e-15, 60, pr)) as p:
+        r_full = p.solve(dt, phi_full, ghost=gt, allow_noconv=True)
+    phi_t = torch.zeros_like(dt)
+    with V.Plan(grids, V.make_params(0.1, 1.5, 1e-15, 60, pr, tau_factor=factor)) as p:
+        res = p.solve(dt, phi_t, ghost=gt)
+        hist = p.history(0)
+    out = phi_t.cpu().numpy()
+    full = phi_full.cpu().numpy()
+    say("  cycles", res[0]["cycles"], "full", r_full[0]["cycles"])
+    assert res[0]["cycles"] < r_full[0]["cycles"]
+    assert hist[0]["tau_rms"] == 0.0 and hist[-1]["tau_rms"] == res[0]["tau_rms"]
+    off = 0
+    for i, n in enumerate(sizes):
+        m = n[0] * n[1] * n[2]
+        r = res[i]
+        phi = out[off:off + m].reshape(n[2], n[1], n[0])
+        _, tau_rms = oracle_mod.truncation_error(deltas[i], phi, 0.1, 1.5, h=h, ghost=ghosts[i])
+        say("  ", n, r["rms"], r["tau_rms"], tau_rms)
+        assert r["status"] == V.VMG_OK and r["tau_rms"] > 0.0
+        assert r["rms"] <= factor * r["tau_rms"]
+        assert abs(r["tau_rms"] - tau_rms) <= 1e-9 * tau_rms
+        # off the converged solution by less than tau's share: |J^-1| ~ L^2 / (3 pi^2)
+        # on a Dirichlet box of side L, and |d| <= |tau| / 3
+        err = np.abs(out[off:off + m] - full[off:off + m]).max()
+        assert err <= 0.1 * r["tau_rms"] * (max(n) * h) ** 2
+        off += m
+
+
 def test_tau_factor_rejected_where_not_supported(torch_cuda, V):
     with pytest.raises(V.VmgError):
-        V.Plan([V.make_grid(16)], V.make_params(0.1, 1.5, 1e-8, 10, V.MIXED, tau_factor=0.3))
-    with pytest.raises(V.VmgError):
         V.Plan([V.make_grid(16)], V.make_params(0.1, 1.5, 1e-8, 10, tau_factor=-1.0))
-    with pytest.raises(V.VmgError):                      # the estimate is defined on periodic grids only
-        V.Plan([V.make_grid(16, 1 / 64, V.DIRICHLET)], V.make_params(0.1, 1.5, 1e-8, 10, tau_factor=0.3))
+    with pytest.raises(V.VmgError):                      # tau^h lives on a coarser level: 6^3 has none
+        V.Plan([V.make_grid(6)], V.make_params(0.1, 1.5, 1e-8, 10, V.MIXED, tau_factor=0.3))
+    with pytest.raises(V.VmgError):                      # an odd Dirichlet grid in the batch has none
+        V.Plan([V.make_grid(16, 1 / 64, V.DIRICHLET), V.make_grid(5, 1 / 64, V.DIRICHLET, 4096, 2000)],
+               V.make_params(0.1, 1.5, 1e-8, 10, tau_factor=0.3))
