@@ -2,10 +2,12 @@
 //
 //  * Sweep schedules, at plan creation (VMG_AUTOTUNE): for every level that
 //    runs the fused sweep, time the real smoother kernel on the plan's own
-//    buffers (HIP events on the plan's stream) for tile heights {8,4,16,12} x
-//    z chunks ({16,8,32} on the finest level, {16,8,4,2} below, since short
-//    chunks spread small grids over the chip) x both pipeline shapes, and keep
-//    the fastest.
+//    buffers (HIP events on the plan's stream), two sweeps at a time, for tile
+//    heights {8,4,16,12} x z chunks ({16,8,32,64} on the finest level,
+//    {16,8,4,2} below, since short chunks spread small grids over the chip) x
+//    both pipeline shapes, plus, on the coarser levels of a periodic plan, the
+//    brick schedule (two sweeps per launch without the z march), and keep the
+//    fastest.
 //  * The cycle schedule, on request (vmg_plan_tune_cycle): time complete
 //    solves of a given input (from the caller's initial guess) to the plan's
 //    tolerance for candidate nu1/nu2,
@@ -131,11 +133,20 @@ hipError_t apply(Plan* P, int l, const SmoothCfg& c) {
     return hipSuccess;
 }
 
-// One sweep of level l (every grid of the plan).
-hipError_t sweep_level(Plan* P, int l) {
-    if (P->batched) return batch_smooth_level(P, l);
+// n pre-sweeps of level l (every grid of the plan), then, with post, the coarse
+// correction's prolongation and n post-sweeps, as a V-cycle issues them.
+hipError_t sweep_level(Plan* P, int l, int n, bool post = false) {
+    if (P->batched) {
+        for (int s = 0; s < (post ? 2 * n : n); ++s) {
+            hipError_t e = batch_smooth_level(P, l);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     for (auto& G : P->grids) {
-        hipError_t e = P->mixed ? smooth_corr_level(P, G, l) : smooth_level_public(P, G, l);
+        hipError_t e = P->mixed ? smooth_corr_level_n(P, G, l, n) : smooth_level_public(P, G, l, n);
+        if (e == hipSuccess && post && l + 1 < (int)G.lev.size())
+            e = P->mixed ? post_smooth_corr(P, G, l, n) : post_smooth(P, G, l, n);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -191,20 +202,26 @@ vmg_status autotune(Plan* P) {
                 else
                     for (int b = 0; b < 4; ++b) cands.push_back(SmoothCfg{tys[a], zcoarse[b], pipe});
             }
+        // coarser periodic levels may also run their sweeps in pairs on bricks
+        if (l > 0 && !P->batched) cands.push_back(SmoothCfg{8, 8, PIPE_BRICK});
         double best_us = 1e300;
+        // the finest level: plain sweeps; below it, a V(2,2) cycle's smoothing (two
+        // sweeps, the coarse correction, two sweeps) per repetition
+        const bool post = l > 0;
+        const int per_rep = post ? 4 : 2;
         for (const SmoothCfg& c : cands) {
             const int warm = 2, reps = 6;
             bool ok = apply(P, l, c) == hipSuccess;
-            for (int r = 0; r < warm && ok; ++r) ok = sweep_level(P, l) == hipSuccess;
+            for (int r = 0; r < warm && ok; ++r) ok = sweep_level(P, l, 2, post) == hipSuccess;
             ok = ok && hipEventRecord(e0, P->stream) == hipSuccess;
-            for (int r = 0; r < reps && ok; ++r) ok = sweep_level(P, l) == hipSuccess;
+            for (int r = 0; r < reps && ok; ++r) ok = sweep_level(P, l, 2, post) == hipSuccess;
             ok = ok && hipEventRecord(e1, P->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
             float ms = 0.0f;
             if (!ok || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
                 st = fail(VMG_EHIP, "autotune timing failed");
                 break;
             }
-            const double us = 1e3 * ms / reps;
+            const double us = 1e3 * ms / (per_rep * reps);
             P->tune_log.push_back({l, c, us});
             if (us < best_us) {
                 best_us = us;

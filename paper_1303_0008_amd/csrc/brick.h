@@ -530,4 +530,183 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
     }
 }
 
+// ---------------------------------------------------------------------------
+// Several sweeps of a small periodic level in one launch, without the z march
+// (the march's pipeline fill dominates there).  A block owns a BB^3 brick and
+// runs S red-black sweeps (S = 1 or 2) of it: it stages u^0 on a ring of 2S
+// cells around the brick (periodic wrap) and the sources on a ring of 2S - 1;
+// phase p = 2 s + colour (sweep s, red then black) updates the cells of that
+// colour within ring 2S - 1 - p of the brick, so each phase finds its
+// neighbourhood complete from the previous phases and no block reads another
+// block's output (the rings are recomputed, as in the march).  A phase forms its
+// updates in registers and writes them in place after a barrier: the red phase
+// reads u^0 only (same-colour edge neighbours included), the black phase the
+// state with that sweep's reds updated, so the sweeps are those of the march.
+// With PRO the staged state first gets the prolonged coarse correction, with
+// the folded march's interpolation order (z, then y, then x).
+//
+// Policy interface (besides Cell, Src, Corr, add_corr and gc of the march):
+//   k.load_cell(i), k.load_src(i), k.store_cell(i, v)   element i of the level
+//   k.load_corr(i)                  u^H - u^H_old at element i of the coarse level
+//   k.update_nb(v, centre, src)     the updated cell from its 18 neighbours
+// ---------------------------------------------------------------------------
+constexpr int BB = 8;
+constexpr int BRICK_THREADS = 512;
+constexpr int BRICK_WAVES = 4;   // waves per SIMD: two blocks per CU (LDS <= 80 KB each)
+constexpr int brick_side(int s) { return BB + 4 * s; }          // staged region, per axis
+constexpr int brick_cwin(int s) { return brick_side(s) / 2 + 2; }   // coarse window, per axis
+
+__device__ __forceinline__ int wrap_idx(int i, int n) {
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+template <int S, bool PRO, typename K>
+__device__ __forceinline__ void brick_sweeps(const K& k, const Geom& g, int bx0, int by0, int bz0) {
+    using Cell = typename K::Cell;
+    using Src = typename K::Src;
+    using Corr = typename K::Corr;
+    constexpr int NTH = BRICK_THREADS;
+    constexpr int R = 2 * S;                   // staged ring
+    constexpr int RW = brick_side(S), RW2 = RW * RW, NU = RW2 * RW;
+    constexpr int RS = RW - 2, NS = RS * RS * RS;   // sources on ring 2S - 1
+    constexpr int CW = brick_cwin(S), NCW = CW * CW * CW;
+    constexpr int NLU = (NU + NTH - 1) / NTH, NLS = (NS + NTH - 1) / NTH;
+    constexpr int NQ = (NS / 2 + NTH - 1) / NTH;   // widest phase: one colour of ring 2S - 1
+    static_assert(!PRO || NCW * sizeof(Corr) <= NU * sizeof(Cell), "the coarse window lives in U's space");
+    __shared__ Cell U[NU];
+    __shared__ Src SR[NS];
+    // the coarse window is read before U is written: it borrows U's space
+    Corr* CWB = reinterpret_cast<Corr*>(U);
+    const int tid = threadIdx.x;
+
+    // ---- staging: u^0 (+ prolonged correction) on ring 2S, sources on ring 2S - 1
+    Cell u0[NLU];
+#pragma unroll
+    for (int q = 0; q < NLU; ++q) {
+        const int e = tid + q * NTH;
+        if (e < NU) {
+            const int x = e % RW, y = (e / RW) % RW, z = e / RW2;
+            u0[q] = k.load_cell(cell_index(g, wrap_idx(bx0 - R + x, g.n0), wrap_idx(by0 - R + y, g.n1),
+                                           wrap_idx(bz0 - R + z, g.n2)));
+        }
+    }
+    // every load is issued before the first LDS write (registers, then LDS)
+    Src s0[NLS];
+#pragma unroll
+    for (int q = 0; q < NLS; ++q) {
+        const int e = tid + q * NTH;
+        if (e < NS) {
+            const int x = e % RS, y = (e / RS) % RS, z = e / (RS * RS);
+            s0[q] = k.load_src(cell_index(g, wrap_idx(bx0 - R + 1 + x, g.n0), wrap_idx(by0 - R + 1 + y, g.n1),
+                                          wrap_idx(bz0 - R + 1 + z, g.n2)));
+        }
+    }
+    constexpr int NLC = PRO ? (NCW + NTH - 1) / NTH : 1;
+    Corr c0[NLC];
+    if (PRO) {
+        // coarse window: coarse cells (bx0 - R) / 2 - 1 + [0, CW) per axis (bx0 - R is even)
+        const int cx0 = (bx0 - R) / 2 - 1, cy0 = (by0 - R) / 2 - 1, cz0 = (bz0 - R) / 2 - 1;
+#pragma unroll
+        for (int q = 0; q < NLC; ++q) {
+            const int e = tid + q * NTH;
+            if (e < NCW) {
+                const int x = e % CW, y = (e / CW) % CW, z = e / (CW * CW);
+                c0[q] = k.load_corr(cell_index(k.gc, wrap_idx(cx0 + x, k.gc.n0), wrap_idx(cy0 + y, k.gc.n1),
+                                               wrap_idx(cz0 + z, k.gc.n2)));
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NLS; ++q) {
+        const int e = tid + q * NTH;
+        if (e < NS) SR[e] = s0[q];
+    }
+    if (PRO) {
+#pragma unroll
+        for (int q = 0; q < NLC; ++q) {
+            const int e = tid + q * NTH;
+            if (e < NCW) CWB[e] = c0[q];
+        }
+        __syncthreads();
+        const Corr a = Corr(0.75), b = Corr(0.25);
+#pragma unroll
+        for (int q = 0; q < NLU; ++q) {
+            const int e = tid + q * NTH;
+            if (e < NU) {
+                const int x = e % RW, y = (e / RW) % RW, z = e / RW2;
+                // fine cell x of the region lies in coarse window cell x/2 + 1; its
+                // farther coarse neighbour is on the side of its parity
+                const int ix = (x >> 1) + 1, iy = (y >> 1) + 1, iz = (z >> 1) + 1;
+                const int sx = (x & 1) ? 1 : -1, sy = (y & 1) ? CW : -CW, sz = (z & 1) ? CW * CW : -CW * CW;
+                const Corr* C0 = CWB + iz * CW * CW;
+                const Corr* C1 = C0 + sz;
+                const int o0 = iy * CW + ix, o1 = o0 + sx;
+                const Corr z00 = a * C0[o0] + b * C1[o0];
+                const Corr z01 = a * C0[o0 + sy] + b * C1[o0 + sy];
+                const Corr z10 = a * C0[o1] + b * C1[o1];
+                const Corr z11 = a * C0[o1 + sy] + b * C1[o1 + sy];
+                const Corr e0 = a * z00 + b * z01;
+                const Corr e1 = a * z10 + b * z11;
+                u0[q] = k.add_corr(u0[q], a * e0 + b * e1);
+            }
+        }
+        __syncthreads();   // every read of the window is done before U overwrites it
+    }
+#pragma unroll
+    for (int q = 0; q < NLU; ++q) {
+        const int e = tid + q * NTH;
+        if (e < NU) U[e] = u0[q];
+    }
+    __syncthreads();
+
+    // ---- the 2S colour phases on shrinking rings
+    const int par0 = (bx0 + by0 + bz0) & 1;   // colour of region cell (0,0,0) is par0 (R even)
+#pragma unroll
+    for (int p = 0; p < 2 * S; ++p) {
+        const int colour = p & 1, ring = 2 * S - 1 - p;
+        const int lo = R - ring, side = BB + 2 * ring, half = side / 2;
+        const int count = half * side * side;
+        Cell res[NQ];
+        int at[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int e = tid + q * NTH;
+            at[q] = -1;
+            if (e < count) {
+                const int hx = e % half, r = e / half;
+                const int y = lo + r % side, z = lo + r / side;
+                const int x = lo + 2 * hx + ((colour + par0 + y + z + lo) & 1);
+                const int c = (z * RW + y) * RW + x;
+                NbT<Cell> v;
+                v.xm = U[c - 1];                 v.xp = U[c + 1];
+                v.ym = U[c - RW];                v.yp = U[c + RW];
+                v.zm = U[c - RW2];               v.zp = U[c + RW2];
+                v.xmym = U[c - RW - 1];          v.xpym = U[c - RW + 1];
+                v.xmyp = U[c + RW - 1];          v.xpyp = U[c + RW + 1];
+                v.xmzm = U[c - RW2 - 1];         v.xpzm = U[c - RW2 + 1];
+                v.xmzp = U[c + RW2 - 1];         v.xpzp = U[c + RW2 + 1];
+                v.ymzm = U[c - RW2 - RW];        v.ypzm = U[c - RW2 + RW];
+                v.ymzp = U[c + RW2 - RW];        v.ypzp = U[c + RW2 + RW];
+                const Src sv = SR[((z - 1) * RS + (y - 1)) * RS + (x - 1)];
+                res[q] = k.update_nb(v, U[c], sv);
+                at[q] = c;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (at[q] >= 0) U[at[q]] = res[q];
+        __syncthreads();
+    }
+
+    // ---- the brick (its part inside the level) goes out
+    for (int e = tid; e < BB * BB * BB; e += NTH) {
+        const int x = e % BB, y = (e / BB) % BB, z = e / (BB * BB);
+        const int gx = bx0 + x, gy = by0 + y, gz = bz0 + z;
+        if (gx < g.n0 && gy < g.n1 && gz < g.n2)
+            k.store_cell(cell_index(g, gx, gy, gz), U[((z + R) * RW + (y + R)) * RW + (x + R)]);
+    }
+}
+
 }  // namespace vmg

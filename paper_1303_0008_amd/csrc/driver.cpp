@@ -241,18 +241,37 @@ static hipError_t collect_levels(Plan* P) {
     return hipSuccess;
 }
 
-static hipError_t smooth_level(Plan* P, GridState& G, int l, const ProlongIn* pro = nullptr) {
+// `count` sweeps of level l, the first from phi + the prolonged coarse correction
+// when `pro` is given: one launch per sweep, or per two on the brick schedule
+static hipError_t smooth_level_n(Plan* P, GridState& G, int l, int count, const ProlongIn* pro = nullptr) {
     LevelBuf& L = G.lev[l];
     const SmoothCfg cfg = level_schedule(P, l, L.g);
-    hipError_t e = launch_smooth(L.g, P->coef, L.phi[L.cur], L.phi[L.cur ^ 1], L.delta,
-                                 level_f(P, G, l), L.sc, cfg, P->stream, pro);
-    L.cur ^= 1;
-    P->cell_updates += L.g.ncell;
-    if (l == 0) P->finest_sweeps += 1;
-    return e;
+    const int per = cfg.pipe == PIPE_BRICK ? 2 : 1;
+    for (int s = 0; s < count;) {
+        const int n = std::min(per, count - s);
+        hipError_t e = launch_smooth(L.g, P->coef, L.phi[L.cur], L.phi[L.cur ^ 1], L.delta, level_f(P, G, l), L.sc,
+                                     cfg, P->stream, s == 0 ? pro : nullptr, n);
+        L.cur ^= 1;
+        P->cell_updates += n * L.g.ncell;
+        if (l == 0) P->finest_sweeps += n;
+        if (e != hipSuccess) return e;
+        s += n;
+    }
+    return hipSuccess;
 }
 
-hipError_t smooth_level_public(Plan* P, GridState& G, int l) { return smooth_level(P, G, l); }
+static hipError_t smooth_level(Plan* P, GridState& G, int l, const ProlongIn* pro = nullptr) {
+    return smooth_level_n(P, G, l, 1, pro);
+}
+
+hipError_t smooth_level_public(Plan* P, GridState& G, int l, int count) { return smooth_level_n(P, G, l, count); }
+
+bool fold_prolong_here(const Plan* P, const Geom& g, const Geom& gc, const SmoothCfg& cfg) {
+    if (!P->fold_prolong) return false;
+    if (cfg.pipe == PIPE_BRICK) return can_fold_prolong(g, gc, 2);
+    const int zc = cfg.zc > 0 ? cfg.zc : 16;
+    return can_fold_prolong(g, gc, zc) && fold_prolong_pays(g, zc);
+}
 
 // The finest level runs the plan's schedule; a coarser level its tuned one, else
 // the plan's schedule shortened by level_cfg.
@@ -309,8 +328,7 @@ static hipError_t vcycle_head(Plan* P, GridState& G, int l, NormOut* norm) {
     if ((e = level_mark(P, l, true)) != hipSuccess) return e;
     const int nu1 = pre_sweeps(P, l);
     if (l == 0 && (e = sweep_mark(P, true, nu1)) != hipSuccess) return e;
-    for (int s = 0; s < nu1; ++s)
-        if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
+    if ((e = smooth_level_n(P, G, l, nu1)) != hipSuccess) return e;
     if (l == 0 && (e = sweep_mark(P, false, nu1)) != hipSuccess) return e;
     LevelBuf& C = G.lev[l + 1];
     C.cur = 0;
@@ -331,28 +349,29 @@ static hipError_t vcycle_head(Plan* P, GridState& G, int l, NormOut* norm) {
     return level_mark(P, l, false);
 }
 
-static hipError_t vcycle_tail(Plan* P, GridState& G, int l) {
+// phi^h += P(phi^H - phi^H_old), then nu2 sweeps of level l: on periodic grids
+// the prolongation is folded into the first sweep where that pays (on the
+// finest level that sweep is not timed with the plain ones)
+hipError_t post_smooth(Plan* P, GridState& G, int l, int nu2) {
     LevelBuf& L = G.lev[l];
     LevelBuf& C = G.lev[l + 1];
     hipError_t e;
+    const int s0 = nu2 > 0 && fold_prolong_here(P, L.g, C.g, level_schedule(P, l, L.g)) ? 1 : 0;
+    const ProlongIn pro{C.g, C.phi[C.cur], C.phiold};
+    if (!s0 && (e = launch_prolong(L.g, C.g, L.phi[L.cur], C.phi[C.cur], C.phiold, P->stream)) != hipSuccess)
+        return e;
+    if (l > 0) return smooth_level_n(P, G, l, nu2, s0 ? &pro : nullptr);
+    if (s0 && (e = smooth_level(P, G, l, &pro)) != hipSuccess) return e;
+    if ((e = sweep_mark(P, true, nu2 - s0)) != hipSuccess) return e;
+    if ((e = smooth_level_n(P, G, l, nu2 - s0)) != hipSuccess) return e;
+    return sweep_mark(P, false, nu2 - s0);
+}
+
+static hipError_t vcycle_tail(Plan* P, GridState& G, int l) {
+    hipError_t e;
     if ((e = vcycle(P, G, l + 1)) != hipSuccess) return e;
     if ((e = level_mark(P, l, true)) != hipSuccess) return e;
-    // phi^h += P(phi^H - phi^H_old): on periodic grids folded into the first
-    // post-sweep (which is then not timed with the plain sweeps)
-    const SmoothCfg cfg = level_schedule(P, l, L.g);
-    const int zc = cfg.zc > 0 ? cfg.zc : 16;
-    const int nu2 = post_sweeps(P, l);
-    const int s0 = P->fold_prolong && nu2 > 0 && can_fold_prolong(L.g, C.g, zc) && fold_prolong_pays(L.g, zc) ? 1 : 0;
-    if (s0) {
-        const ProlongIn pro{C.g, C.phi[C.cur], C.phiold};
-        if ((e = smooth_level(P, G, l, &pro)) != hipSuccess) return e;
-    } else if ((e = launch_prolong(L.g, C.g, L.phi[L.cur], C.phi[C.cur], C.phiold, P->stream)) != hipSuccess) {
-        return e;
-    }
-    if (l == 0 && (e = sweep_mark(P, true, nu2 - s0)) != hipSuccess) return e;
-    for (int s = s0; s < nu2; ++s)
-        if ((e = smooth_level(P, G, l)) != hipSuccess) return e;
-    if (l == 0 && (e = sweep_mark(P, false, nu2 - s0)) != hipSuccess) return e;
+    if ((e = post_smooth(P, G, l, post_sweeps(P, l))) != hipSuccess) return e;
     return level_mark(P, l, false);
 }
 
@@ -1158,9 +1177,11 @@ vmg_status vmg_plan_set_schedule(vmg_plan* plan, int32_t level, int32_t tile_y, 
     if (tile_y != 4 && tile_y != 8 && tile_y != 12 && tile_y != 16)
         return fail(VMG_EINVAL, "tile_y must be 4, 8, 12 or 16");
     if (z_chunk < 2 || z_chunk > 1024 || (z_chunk & 1)) return fail(VMG_EINVAL, "z_chunk must be even, in [2, 1024]");
-    if (pipe != 0 && pipe != 1) return fail(VMG_EINVAL, "pipe must be 0 or 1");
+    if (pipe != 0 && pipe != 1 && pipe != PIPE_BRICK) return fail(VMG_EINVAL, "pipe must be 0, 1 or 2");
     if (level < 0 || level >= swept_level_count(P))
         return fail(VMG_EINVAL, "level " + std::to_string(level) + " has no fused sweep in this plan");
+    if (pipe == PIPE_BRICK && (level == 0 || P->batched))
+        return fail(VMG_EINVAL, "pipe 2 (bricks) runs on the coarser levels of a periodic plan only");
     const SmoothCfg c{tile_y, z_chunk, pipe};
     if (level == 0) P->cfg = c;
     if (P->batched) {

@@ -98,11 +98,7 @@ struct SmoothK {
         return buf_ld_f64(C.u, bo) - buf_ld_f64(C.o, bo);
     }
     __device__ double add_corr(double u, double v) const { return u + v; }
-    template <int W>
-    __device__ double update(const double* Pm, const double* Pc, const double* Pp, int co, int o,
-                             const Src& s) const {
-        Nb v;
-        nb_split<W>(Pm, Pc, Pp, co, o, v);
+    __device__ double update_nb(const Nb& v, double, const Src& s) const {
         double S;
         bool gd;
         const double Q = nl_root(v, s.dl, c, inv_h4, S, gd);
@@ -110,6 +106,23 @@ struct SmoothK {
         const double base = HAS_F ? fma(-h2_6, s.f, cb_6) : cb_6;
         return fma(S, 1.0 / 6.0, fma(-h2_6, Q, base));
     }
+    template <int W>
+    __device__ double update(const double* Pm, const double* Pc, const double* Pp, int co, int o,
+                             const Src& s) const {
+        Nb v;
+        nb_split<W>(Pm, Pc, Pp, co, o, v);
+        return update_nb(v, Pc[o], s);
+    }
+    // element access of the multi-sweep brick (brick_sweeps)
+    __device__ double load_cell(int64_t i) const { return pin[i]; }
+    __device__ Src load_src(int64_t i) const {
+        Src s;
+        s.dl = delta[i];
+        s.f = HAS_F ? f[i] : 0.0;
+        return s;
+    }
+    __device__ void store_cell(int64_t i, double v) const { pout[i] = v; }
+    __device__ double load_corr(int64_t i) const { return uc[i] - oc[i]; }
 };
 
 // PRO: the sweep starts from pin + P(uc - oc), the coarse correction prolonged
@@ -130,6 +143,22 @@ __global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER, PRO)
 // Persistent sweep over a (grid, tile x, tile y, z chunk) work list: every
 // Dirichlet grid of a batch at one level in one launch.  `proto` carries the
 // pooled level buffers and coefficients; geoms[w.x] locates grid w.x in them.
+
+// S sweeps (1 or 2) of a small periodic level with a FAS source, one BB^3 brick
+// per block (brick_sweeps); PRO adds the prolonged coarse correction first.  The
+// two-sweep prolonging variant keeps one block per CU: at two its registers
+// spill (measured slower).
+template <int S, bool PRO>
+__global__ void __launch_bounds__(BRICK_THREADS, (S == 2 && PRO) ? 2 : BRICK_WAVES) k_smooth_brick(SmoothArgs a) {
+    const int nbx = (a.g.n0 + BB - 1) / BB, nby = (a.g.n1 + BB - 1) / BB;
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby, bz = b / nby;
+    const SmoothK<true> k(a, a.g, true);
+    brick_sweeps<S, PRO>(k, a.g, bx * BB, by * BB, bz * BB);
+}
+
 template <int TY, bool HAS_F, bool DEFER>
 __global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER)) k_smooth_batch(SmoothArgs proto, const Geom* __restrict__ geoms,
                                                      const int4* __restrict__ items, int nitems) {
@@ -1166,10 +1195,30 @@ static hipError_t smooth_launch(const SmoothArgs& a, bool defer, hipStream_t s) 
 
 hipError_t launch_smooth(const Geom& g, const Coef& c, const double* pin, double* pout,
                          const double* delta, const double* f, const LevelScalars* sc,
-                         SmoothCfg cfg, hipStream_t s, const ProlongIn* pro) {
+                         SmoothCfg cfg, hipStream_t s, const ProlongIn* pro, int nsweeps) {
     SmoothArgs a;
     std::memset(&a, 0, sizeof(a));
     a.g = g; a.c = c; a.pin = pin; a.pout = pout; a.delta = delta; a.f = f; a.sc = sc;
+    if (cfg.pipe == PIPE_BRICK) {
+        // periodic coarse levels (with their FAS source), one or two sweeps
+        if (g.dir || !f || nsweeps < 1 || nsweeps > 2) return hipErrorInvalidValue;
+        if (pro) {
+            if (!can_fold_prolong(g, pro->gc, 2)) return hipErrorInvalidValue;
+            a.gc = pro->gc;
+            a.uc = pro->uc;
+            a.oc = pro->oc;
+        }
+        const dim3 nb(((g.n0 + BB - 1) / BB) * ((g.n1 + BB - 1) / BB) * ((g.n2 + BB - 1) / BB));
+        if (nsweeps == 2) {
+            if (pro) hipLaunchKernelGGL((k_smooth_brick<2, true>), nb, dim3(BRICK_THREADS), 0, s, a);
+            else hipLaunchKernelGGL((k_smooth_brick<2, false>), nb, dim3(BRICK_THREADS), 0, s, a);
+        } else {
+            if (pro) hipLaunchKernelGGL((k_smooth_brick<1, true>), nb, dim3(BRICK_THREADS), 0, s, a);
+            else hipLaunchKernelGGL((k_smooth_brick<1, false>), nb, dim3(BRICK_THREADS), 0, s, a);
+        }
+        return hipGetLastError();
+    }
+    if (nsweeps != 1) return hipErrorInvalidValue;
     a.zc = cfg.zc > 0 ? cfg.zc : 16;
     if (pro) {
         if (!can_fold_prolong(g, pro->gc, a.zc)) return hipErrorInvalidValue;

@@ -106,6 +106,14 @@ struct CorrK {
                              const Src& s) const {
         NbT<float2> v;
         nb_split<W>(Pm, Pc, Pp, co, o, v);
+        return update_nb(v, Pc[o], s);
+    }
+    // element access of the multi-sweep brick (brick_sweeps)
+    __device__ float2 load_cell(int64_t i) const { return make_float2(ZERO_E ? 0.0f : ein[i], pt[i]); }
+    __device__ Src load_src(int64_t i) const { return Src{t0[i], r[i]}; }
+    __device__ void store_cell(int64_t i, float2 v) const { eout[i] = v.x; }
+    __device__ float load_corr(int64_t i) const { return uc[i] - oc[i]; }
+    __device__ float2 update_nb(const NbT<float2>& v, float2 centre, const Src& s) const {
         NbT<float> ve, vp;
 #define VMG_SPLIT(m) ve.m = v.m.x; vp.m = v.m.y;
         VMG_SPLIT(xm) VMG_SPLIT(xp) VMG_SPLIT(ym) VMG_SPLIT(yp) VMG_SPLIT(zm) VMG_SPLIT(zp)
@@ -117,7 +125,7 @@ struct CorrK {
         const float dq = dq_corr(ve, vp, c.a_ih4, Se);
         const float dQ = dQ_of(dq, s.t0, c);
         // (Se - h^2 (dQ + r - cbar)) / 6
-        return make_float2(fmaf(Se, 1.0f / 6.0f, fmaf(-h2_6, dQ, fmaf(-h2_6, s.r, cb_6))), Pc[o].y);
+        return make_float2(fmaf(Se, 1.0f / 6.0f, fmaf(-h2_6, dQ, fmaf(-h2_6, s.r, cb_6))), centre.y);
     }
 };
 
@@ -134,6 +142,19 @@ __global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER, PRO)
     if (z0 >= a.g.n2) return;
     const CorrK<ZERO_E> k(a, DIR == 0);
     fused_sweep<TY, DIR, sweep_threads(TY), DEFER, PRO>(k, a.g, tx * TX, ty * TY, z0, min(z0 + a.zc, a.g.n2));
+}
+
+// S sweeps (1 or 2) of the correction on a small periodic level, one BB^3 brick
+// per block (brick_sweeps); PRO adds the prolonged coarse correction first
+template <int S, bool ZERO_E, bool PRO>
+__global__ void __launch_bounds__(BRICK_THREADS, BRICK_WAVES) k_smooth_corr_brick(CorrArgs a) {
+    const int nbx = (a.g.n0 + BB - 1) / BB, nby = (a.g.n1 + BB - 1) / BB;
+    int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby, bz = b / nby;
+    const CorrK<ZERO_E> k(a, true);
+    brick_sweeps<S, PRO>(k, a.g, bx * BB, by * BB, bz * BB);
 }
 
 // persistent sweep over a (grid, tile x, tile y, z chunk) work list (Dirichlet batches)
@@ -1058,10 +1079,33 @@ static hipError_t corr_launch(const CorrArgs& a, bool zero_in, bool defer, hipSt
 
 hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, float* eout,
                               const float* pt, const float* t0, const float* r, const LevelScalars* sc,
-                              SmoothCfg cfg, hipStream_t s, bool zero_in, const ProlongInF* pro) {
+                              SmoothCfg cfg, hipStream_t s, bool zero_in, const ProlongInF* pro, int nsweeps) {
     CorrArgs a;
     std::memset(&a, 0, sizeof(a));
     a.g = g; a.c = c; a.ein = ein; a.eout = eout; a.pt = pt; a.t0 = t0; a.r = r; a.sc = sc;
+    if (cfg.pipe == PIPE_BRICK) {
+        // periodic levels, one or two sweeps
+        if (g.dir || nsweeps < 1 || nsweeps > 2) return hipErrorInvalidValue;
+        if (pro) {
+            if (zero_in || !can_fold_prolong(g, pro->gc, 2)) return hipErrorInvalidValue;
+            a.gc = pro->gc;
+            a.uc = pro->uc;
+            a.oc = pro->oc;
+        }
+        const dim3 nb(((g.n0 + BB - 1) / BB) * ((g.n1 + BB - 1) / BB) * ((g.n2 + BB - 1) / BB));
+        const dim3 nt(BRICK_THREADS);
+#define VMG_CORR_BRICK(S)                                                                                  \
+    do {                                                                                                   \
+        if (pro) hipLaunchKernelGGL((k_smooth_corr_brick<S, false, true>), nb, nt, 0, s, a);               \
+        else if (zero_in) hipLaunchKernelGGL((k_smooth_corr_brick<S, true, false>), nb, nt, 0, s, a);      \
+        else hipLaunchKernelGGL((k_smooth_corr_brick<S, false, false>), nb, nt, 0, s, a);                  \
+    } while (0)
+        if (nsweeps == 2) VMG_CORR_BRICK(2);
+        else VMG_CORR_BRICK(1);
+#undef VMG_CORR_BRICK
+        return hipGetLastError();
+    }
+    if (nsweeps != 1) return hipErrorInvalidValue;
     a.zc = cfg.zc > 0 ? cfg.zc : 16;
     if (pro) {
         if (zero_in || !can_fold_prolong(g, pro->gc, a.zc)) return hipErrorInvalidValue;

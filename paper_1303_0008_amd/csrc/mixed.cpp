@@ -3,6 +3,7 @@
 // and norms stay FP64; smoothing, restriction and prolongation are FP32).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 
 #include "vmg_internal.h"
@@ -55,16 +56,46 @@ hipError_t mixed_prepare(Plan* P) {
     return hipSuccess;
 }
 
-hipError_t smooth_corr_level(Plan* P, GridState& G, int l, bool zero_in, const ProlongInF* pro) {
+// `count` correction sweeps of level l (one launch per sweep, or per two on the
+// brick schedule); zero_in and pro apply to the first
+hipError_t smooth_corr_level_n(Plan* P, GridState& G, int l, int count, bool zero_in, const ProlongInF* pro) {
     LevelBuf& L = G.lev[l];
     const CoefF cf = make_coef_f(P->coef, L.g.h);
     const SmoothCfg cfg = level_schedule(P, l, L.g);
-    hipError_t e = launch_smooth_corr(L.g, cf, L.e[L.ecur], L.e[L.ecur ^ 1], L.pt, L.t0, L.r, L.scf, cfg,
-                                      P->stream, zero_in, pro);
-    L.ecur ^= 1;
-    P->cell_updates += L.g.ncell;
-    if (l == 0) P->finest_sweeps += 1;
-    return e;
+    const int per = cfg.pipe == PIPE_BRICK ? 2 : 1;
+    for (int s = 0; s < count;) {
+        const int n = std::min(per, count - s);
+        hipError_t e = launch_smooth_corr(L.g, cf, L.e[L.ecur], L.e[L.ecur ^ 1], L.pt, L.t0, L.r, L.scf, cfg,
+                                          P->stream, zero_in && s == 0, s == 0 ? pro : nullptr, n);
+        L.ecur ^= 1;
+        P->cell_updates += n * L.g.ncell;
+        if (l == 0) P->finest_sweeps += n;
+        if (e != hipSuccess) return e;
+        s += n;
+    }
+    return hipSuccess;
+}
+
+hipError_t smooth_corr_level(Plan* P, GridState& G, int l, bool zero_in, const ProlongInF* pro) {
+    return smooth_corr_level_n(P, G, l, 1, zero_in, pro);
+}
+
+// e^h += P(e^H - e^H_old), then nu2 correction sweeps of level l: on periodic
+// grids the prolongation is folded into the first sweep where that pays (on the
+// finest level that sweep is not timed with the plain ones)
+hipError_t post_smooth_corr(Plan* P, GridState& G, int l, int nu2) {
+    LevelBuf& L = G.lev[l];
+    LevelBuf& C = G.lev[l + 1];
+    hipError_t e;
+    const int s0 = nu2 > 0 && fold_prolong_here(P, L.g, C.g, level_schedule(P, l, L.g)) ? 1 : 0;
+    const ProlongInF pro{C.g, C.e[C.ecur], C.eold};
+    if (!s0 && (e = launch_prolong_corr(L.g, C.g, L.e[L.ecur], C.e[C.ecur], C.eold, P->stream)) != hipSuccess)
+        return e;
+    if (l > 0) return smooth_corr_level_n(P, G, l, nu2, false, s0 ? &pro : nullptr);
+    if (s0 && (e = smooth_corr_level(P, G, l, false, &pro)) != hipSuccess) return e;
+    if ((e = sweep_mark(P, true, nu2 - s0)) != hipSuccess) return e;
+    if ((e = smooth_corr_level_n(P, G, l, nu2 - s0, false, nullptr)) != hipSuccess) return e;
+    return sweep_mark(P, false, nu2 - s0);
 }
 
 // The periodic coarse tail of the inner cycle: levels l..last in one launch.
@@ -116,11 +147,15 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e, bool f
     // the sweep that reads no correction (zero_e) is another kernel: it is not timed
     const int nu1 = pre_sweeps(P, l);
     const int t1 = zero_e ? nu1 - 1 : nu1;
-    for (int s = 0; s < nu1; ++s) {
-        if (l == 0 && s == nu1 - t1 && (e = sweep_mark(P, true, t1)) != hipSuccess) return e;
-        if ((e = smooth_corr_level(P, G, l, zero_e && s == 0)) != hipSuccess) return e;
+    if (l > 0) {
+        if ((e = smooth_corr_level_n(P, G, l, nu1, zero_e)) != hipSuccess) return e;
+    } else {
+        for (int s = 0; s < nu1; ++s) {
+            if (s == nu1 - t1 && (e = sweep_mark(P, true, t1)) != hipSuccess) return e;
+            if ((e = smooth_corr_level(P, G, l, zero_e && s == 0)) != hipSuccess) return e;
+        }
+        if (t1 > 0 && (e = sweep_mark(P, false, t1)) != hipSuccess) return e;
     }
-    if (l == 0 && t1 > 0 && (e = sweep_mark(P, false, t1)) != hipSuccess) return e;
     LevelBuf& C = G.lev[l + 1];
     const CoefF cc = make_coef_f(P->coef, C.g.h);
     C.ecur = 0;
@@ -144,22 +179,7 @@ static hipError_t inner_vcycle(Plan* P, GridState& G, int l, bool zero_e, bool f
     if ((e = level_mark(P, l, false)) != hipSuccess) return e;
     if ((e = inner_vcycle(P, G, l + 1, false, fresh_base)) != hipSuccess) return e;
     if ((e = level_mark(P, l, true)) != hipSuccess) return e;
-    // e^h += P(e^H - e^H_old): on periodic grids folded into the first
-    // post-sweep (which is then not timed with the plain sweeps)
-    const SmoothCfg cfg = level_schedule(P, l, L.g);
-    const int zc = cfg.zc > 0 ? cfg.zc : 16;
-    const int nu2 = post_sweeps(P, l);
-    const int s0 = P->fold_prolong && nu2 > 0 && can_fold_prolong(L.g, C.g, zc) && fold_prolong_pays(L.g, zc) ? 1 : 0;
-    if (s0) {
-        const ProlongInF pro{C.g, C.e[C.ecur], C.eold};
-        if ((e = smooth_corr_level(P, G, l, false, &pro)) != hipSuccess) return e;
-    } else if ((e = launch_prolong_corr(L.g, C.g, L.e[L.ecur], C.e[C.ecur], C.eold, P->stream)) != hipSuccess) {
-        return e;
-    }
-    if (l == 0 && (e = sweep_mark(P, true, nu2 - s0)) != hipSuccess) return e;
-    for (int s = s0; s < nu2; ++s)
-        if ((e = smooth_corr_level(P, G, l)) != hipSuccess) return e;
-    if (l == 0 && (e = sweep_mark(P, false, nu2 - s0)) != hipSuccess) return e;
+    if ((e = post_smooth_corr(P, G, l, post_sweeps(P, l))) != hipSuccess) return e;
     return level_mark(P, l, false);
 }
 

@@ -65,8 +65,11 @@ struct SmoothCfg {
     int ty;      // 4, 8, 12 or 16
     int zc;      // z planes per block
     int pipe = 1;   // 0: black one plane behind red, two barriers per plane step;
-                    // 1: black two planes behind, one barrier (four-plane rings)
+                    // 1: black two planes behind, one barrier (four-plane rings);
+                    // PIPE_BRICK: no z march, up to two sweeps per launch on 8^3
+                    // bricks (periodic levels below the finest; ty, zc unused)
 };
+constexpr int PIPE_BRICK = 2;
 
 // Blocks a tiled pass should at least launch: four per compute unit.
 constexpr int64_t MIN_TILED_BLOCKS = 1024;
@@ -148,9 +151,10 @@ inline bool can_fold_prolong(const Geom& g, const Geom& gc, int zc) {
 // planes corrected), and on levels of at most 64^3 cells the saved launch
 // outweighs it.  A 128^3 level swept in chunks of 4 loses.
 inline bool fold_prolong_pays(const Geom& g, int zc) { return zc >= 8 || g.ncell <= (int64_t)1 << 18; }
+// nsweeps: sweeps of this launch (2 only with the brick schedule)
 hipError_t launch_smooth(const Geom& g, const Coef& c, const double* pin, double* pout,
                          const double* delta, const double* f, const LevelScalars* sc,
-                         SmoothCfg cfg, hipStream_t s, const ProlongIn* pro = nullptr);
+                         SmoothCfg cfg, hipStream_t s, const ProlongIn* pro = nullptr, int nsweeps = 1);
 hipError_t launch_residual_restrict(const Geom& gf, const Geom& gc, const Coef& c,
                                     const double* phi, const double* delta, const double* f,
                                     const LevelScalars* sc, double* phic, double* phiold_c,
@@ -229,7 +233,7 @@ hipError_t launch_mass_assign(const double* pos, int64_t np, int n0, int n1, int
 hipError_t launch_smooth_corr(const Geom& g, const CoefF& c, const float* ein, float* eout,
                               const float* pt, const float* t0, const float* r, const LevelScalars* sc,
                               SmoothCfg cfg, hipStream_t s, bool zero_in = false,
-                              const ProlongInF* pro = nullptr);
+                              const ProlongInF* pro = nullptr, int nsweeps = 1);
 // ptc (may be null): receives the restricted base state phi~ of the coarse level
 hipError_t launch_rr_corr(const Geom& gf, const Geom& gc, const CoefF& c, const float* e, const float* pt,
                           const float* t0, const float* r, const LevelScalars* sc, float* ec, float* eold_c,

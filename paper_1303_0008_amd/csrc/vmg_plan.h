@@ -154,6 +154,11 @@ hipError_t enqueue_outer(Plan* P);          // one mixed-precision outer iterati
 hipError_t mixed_initial_pass(Plan* P);     // cast pass of the initial guess (+ norms to host)
 hipError_t mixed_prepare(Plan* P);          // per-solve set-up of the FP32 ghost shells
 hipError_t smooth_corr_level(Plan* P, GridState& G, int l, bool zero_in = false, const ProlongInF* pro = nullptr);
+hipError_t smooth_corr_level_n(Plan* P, GridState& G, int l, int count, bool zero_in = false,
+                               const ProlongInF* pro = nullptr);
+// coarse-correction prolongation + nu2 post-sweeps of level l (FP64 / correction)
+hipError_t post_smooth(Plan* P, GridState& G, int l, int nu2);
+hipError_t post_smooth_corr(Plan* P, GridState& G, int l, int nu2);
 vmg_status build_batch(Plan* P);
 vmg_status autotune(Plan* P);
 // levels of a plan that run the fused sweep (the levels a schedule applies to)
@@ -170,7 +175,11 @@ vmg_status tune_cycle(Plan* P, const double* delta, const double* ghost, const d
                       vmg_cycle* best, double* best_ms);
 vmg_status solve(Plan* P, const double* delta, const double* ghost, const double* source, double* phi,
                  vmg_result* out);
-hipError_t smooth_level_public(Plan* P, GridState& G, int l);
+// `count` FP64 sweeps of level l (in pairs on the brick schedule)
+hipError_t smooth_level_public(Plan* P, GridState& G, int l, int count);
+// whether the first post-sweep of level l (schedule cfg) takes the prolongation
+// from coarse level gc
+bool fold_prolong_here(const Plan* P, const Geom& g, const Geom& gc, const SmoothCfg& cfg);
 // schedule of the fused sweep on level l of a single-grid (periodic) plan
 SmoothCfg level_schedule(const Plan* P, int l, const Geom& g);
 // first level handled by the periodic coarse tail (FP64 plans), or -1

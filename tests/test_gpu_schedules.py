@@ -125,12 +125,42 @@ def test_schedules_give_the_same_iterate(torch_cuda, V, oracle_mod):
         assert np.abs(o - outs[0]).max() <= 1e-12 * np.abs(outs[0]).max()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_brick_schedule_vs_march_and_oracle(torch_cuda, V, oracle_mod, prec):
+    """The brick schedule (pipe 2: up to two sweeps per launch on 8^3 bricks, no z
+    march) on every coarser level runs the march's red-black sweeps: with pre- and
+    post-sweep counts that leave a one-sweep launch and a folded prolongation with
+    one or two sweeps, a few cycles give the march's iterate to rounding (printed:
+    bitwise or not); solved to the rounding floor it meets the oracle.  The ragged
+    case's levels end in partial bricks."""
+    p = V.FP64 if prec == "fp64" else V.MIXED
+    bar = 1e-10 if p == V.FP64 else 1e-8
+    for name in CASES:
+        delta, ref = case_ref(oracle_mod, name)
+        march = {lev: (4, 2, 1) for lev in range(1, 8)}
+        brick = {lev: (8, 8, 2) for lev in range(1, 8)}
+        for nu1, nu2 in ((2, 2), (3, 1), (1, 3)):
+            cyc = dict(nu1=nu1, nu2=nu2) if p == V.FP64 else dict(nu1=nu1, nu2=nu2, inner_cycles=2)
+            a, ia = solve_with(torch_cuda, V, delta, CASES[name]["alpha"], p, march, tol=1e-30, max_cycles=3,
+                               cycle=cyc)
+            b, ib = solve_with(torch_cuda, V, delta, CASES[name]["alpha"], p, brick, tol=1e-30, max_cycles=3,
+                               cycle=cyc)
+            d = float(np.abs(a - b).max() / np.abs(a).max())
+            say(f"{prec} {name} V({nu1},{nu2}) brick vs march: {d:.2e} bitwise {bool(np.array_equal(a, b))}")
+            assert ia["cycles"] == ib["cycles"] == 3
+            assert d <= (1e-12 if p == V.FP64 else 1e-6)
+        phi, info = solve_with(torch_cuda, V, delta, CASES[name]["alpha"], p, brick)
+        e = relerr(phi, ref)
+        say(f"{prec} {name} brick to the floor: err {e:.2e} cycles {info['cycles']} rms {info['rms']:.2e}")
+        assert e <= bar
+
+
 def test_set_schedule_rejects_bad_arguments(torch_cuda, V):
     with V.Plan([V.make_grid(32)], V.make_params(0.1, 1.5, 1e-8)) as p:
         n = p.level_count()
         assert n >= 1
         for lev, ty, zc, pipe in ((n, 8, 16, 1), (-1, 8, 16, 1), (0, 6, 16, 1), (0, 8, 3, 1), (0, 8, 0, 1),
-                                  (0, 8, 2048, 1), (0, 8, 16, 2), (0, 8, 16, -1)):
+                                  (0, 8, 2048, 1), (0, 8, 16, 2), (0, 8, 16, 3), (0, 8, 16, -1)):
             with pytest.raises(V.VmgError) as ei:
                 p.set_schedule(lev, ty, zc, pipe)
             assert ei.value.status == V.VMG_EINVAL
