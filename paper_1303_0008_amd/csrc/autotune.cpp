@@ -84,7 +84,10 @@ void load_file_cache() {
             c.ty = (int)v[0];
             c.zc = (int)v[1];
             c.pipe = v.size() == 4 ? (int)v[2] : 0;
-            g_tune_cache[key] = c;
+            // only schedules vmg_plan_set_schedule would accept (others are re-tuned)
+            const bool ok = (c.ty == 4 || c.ty == 8 || c.ty == 12 || c.ty == 16) && c.zc >= 2 && c.zc <= 1024 &&
+                            (c.zc & 1) == 0 && c.pipe >= 0 && c.pipe <= PIPE_BRICK;
+            if (ok) g_tune_cache[key] = c;
         }
     }
     std::fclose(f);
@@ -187,7 +190,8 @@ vmg_status autotune(Plan* P) {
     for (int l = 0; l < nlev && st == VMG_OK; ++l) {
         const std::string key = tune_key(P, l);
         SmoothCfg best;
-        if (cached(key, best)) {
+        // the brick schedule runs on the coarser levels of periodic plans only
+        if (cached(key, best) && (best.pipe != PIPE_BRICK || (l > 0 && !P->batched))) {
             P->tuned_from_cache = true;
             if (apply(P, l, best) != hipSuccess) st = fail(VMG_EHIP, "autotune: work list upload failed");
             continue;
