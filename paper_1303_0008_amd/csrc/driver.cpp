@@ -497,6 +497,9 @@ static vmg_status capture_graph(Plan* P, int src, int parity) {
     P->tev_used = 0;
     P->graph_updates[src][parity] = P->cell_updates - cu;
     P->graph_finest[src][parity] = P->finest_sweeps - fs;
+    // where the iteration leaves the finest phi: each launch on it flips the
+    // ping-pong buffers (the mixed path's update pass once per iteration)
+    P->graph_flip[src][parity] = finest_parity(P) != parity;
     P->cell_updates = cu;
     P->finest_sweeps = fs;
     for (size_t gi = 0; gi < P->grids.size(); ++gi) P->grids[gi].lev[0].cur = saved[gi];
@@ -580,11 +583,8 @@ static vmg_status run_cycle(Plan* P) {
     if (P->time_sweeps) CKH(collect_sweeps(P, P->graph_tev[src][parity]));
     P->cell_updates += P->graph_updates[src][parity];
     P->finest_sweeps += P->graph_finest[src][parity];
-    // the replayed iteration leaves the finest phi in the other buffer when it
-    // did an odd number of FP64 sweeps, and always on the periodic mixed path
-    // (its update pass writes phi + e to the second buffer); the batched mixed
-    // path updates in place
-    const bool flip = P->mixed ? !P->batched : ((P->nu1 + P->nu2) & 1) != 0;
+    // the replayed iteration leaves the finest phi where the captured one did
+    const bool flip = P->graph_flip[src][parity];
     if (flip) {
         if (P->batched)
             batch_flip_parity(P);

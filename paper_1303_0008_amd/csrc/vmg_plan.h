@@ -98,6 +98,7 @@ struct Plan {
     bool graph_ok[2][2] = {{false, false}, {false, false}};
     int64_t graph_updates[2][2] = {{0, 0}, {0, 0}};   // cell updates / finest sweeps of one replay
     int64_t graph_finest[2][2] = {{0, 0}, {0, 0}};
+    bool graph_flip[2][2] = {{false, false}, {false, false}};   // replay moves the finest phi
     int64_t cell_updates = 0, finest_sweeps = 0;
     std::vector<void*> allocs;
     // finest-sweep timing (vmg_plan_time_sweeps): event pairs around every
