@@ -3,7 +3,10 @@
 This module only *generates inputs*: it holds none of the solver's
 arithmetic (no stencil, no nonlinear root, no multigrid).  Both the CPU
 oracle's tests and the GPU path draw their inputs from here, so the two
-sides see byte-identical fields.
+sides see byte-identical fields.  Its cloud-in-cell deposit builds the
+Zel'dovich density the way the workload recipe states; the mass assignment
+the library offers (and the oracle's, pinned by moment and lattice tests of
+its own) is a separate implementation.
 
 Layout of every 3D field: a C-contiguous numpy array of shape
 ``(n2, n1, n0)`` -- z slowest, x fastest -- i.e. cell ``(i, j, k)`` sits at

@@ -903,7 +903,9 @@ def test_mass_assign_cic_matches_the_input_recipe_deposit(oracle_mod):
     """The input recipe's own cloud-in-cell deposit (a separate array-at-a-time
     implementation that makes the zeldovich256 density) and the oracle's
     particle-by-particle one agree on the same Zel'dovich particles, on a
-    cubic and a non-cubic grid."""
+    cubic and a non-cubic grid.  A consistency check between two deposits of
+    this repository, not a pin: the moment and lattice tests above pin the
+    oracle's weights to the scheme's definition."""
     pos = I.zeldovich_particles(32, I.BASE_SEED + 81, 1.2)
     for shape in ((32, 32, 32), (24, 40, 16)):
         rho = I.cic_deposit(shape, pos[:, 0], pos[:, 1], pos[:, 2])
