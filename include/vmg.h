@@ -423,7 +423,8 @@ vmg_status vmg_plan_set_cycle(vmg_plan *plan, const vmg_cycle *cycle);
  * trial starts, and receives the last trial's solution) to the plan's
  * tolerance for candidate schedules, by coordinate
  * search: nu1/nu2 over (1,1) .. (3,3), then the sweeps below the finest level
- * (as the finest, (1,1), (1,2), (2,1)), then inner cycles 1..3 (mixed), then
+ * (as the finest, (1,1), (1,2), (2,1)), then inner cycles 1..6 and nu1/nu2
+ * once more (mixed), then
  * coarsest sweeps {2, 4, 8, 16}, then the coarse tail on/off (periodic) or the
  * persistent launch size {512, 1024, 2048} (Dirichlet).  A candidate that does
  * not reach the tolerance within max_cycles is discarded.  The fastest

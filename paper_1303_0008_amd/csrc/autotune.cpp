@@ -326,12 +326,21 @@ vmg_status tune_cycle(Plan* P, const double* delta, const double* ghost, const d
         c.coarse_nu2 = cnus[i][1];
         if (c.coarse_nu1 != best.coarse_nu1 || c.coarse_nu2 != best.coarse_nu2) st = consider(c);
     }
-    if (P->mixed)
-        for (int k = 1; k <= 3 && st == VMG_OK; ++k) {
+    if (P->mixed) {
+        // inner cycles per outer step trade outer passes against inner work: more
+        // of them can save a whole outer step; then the sweep counts once more
+        for (int k = 1; k <= 6 && st == VMG_OK; ++k) {
             vmg_cycle c = best;
             c.inner_cycles = k;
             if (k != best.inner_cycles) st = consider(c);
         }
+        for (int i = 0; i < 7 && st == VMG_OK; ++i) {
+            vmg_cycle c = best;
+            c.nu1 = nus[i][0];
+            c.nu2 = nus[i][1];
+            if (c.nu1 != best.nu1 || c.nu2 != best.nu2) st = consider(c);
+        }
+    }
     const int coarse[4] = {2, 4, 8, 16};
     for (int i = 0; i < 4 && st == VMG_OK; ++i) {
         vmg_cycle c = best;
