@@ -263,7 +263,7 @@ def test_cycle_tuner(torch_cuda, V, oracle_mod, prec):
         say(f"{prec} tuned cycle {best} ({ms:.3f} ms)")
         assert pl.cycle() == best and ms > 0
         assert 1 <= best["nu1"] + best["nu2"] and best["coarse_sweeps"] in (2, 4, 8, 16)
-        assert (best["inner_cycles"] in (1, 2, 3)) if p == V.MIXED else best["inner_cycles"] == 0
+        assert (1 <= best["inner_cycles"] <= 6) if p == V.MIXED else best["inner_cycles"] == 0
         phi = torch.zeros_like(d_t)
         info = pl.solve(d_t, phi)[0]
     e = relerr(phi.cpu().numpy(), ref)
