@@ -233,3 +233,31 @@ def test_levels_deep_and_trivial_trees(torch_cuda, V, oracle_mod):
     with V.Plan([V.make_grid(32)], p) as plan:
         plan.solve(d, phi2)
     assert torch.equal(phi1, phi2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_levels_truncation_error_rule(torch_cuda, V, oracle_mod, prec):
+    """The truncation-error stopping rule on every grid of the tree (Sec. III.C: the
+    estimate applies on every level): with an unreachable tolerance each grid's
+    solve stops once |d| <= |tau| / 3, and each grid's tau RMS is the oracle's
+    estimate at the returned phi (with the ghost values the refinement was given;
+    mean removed on the periodic domain grid only) to 1e-9."""
+    levels = build_tree()
+    factor = 1.0 / 3.0
+    p = V.make_params(ALPHA, KAPPA, 1e-15, 100, V.FP64 if prec == "fp64" else V.MIXED, flags=V.GRAPH,
+                      tau_factor=factor)
+    res, got, ghost = gpu_tree(torch_cuda, V, levels, p)
+    goff = 0
+    for i, (r, g, phi) in enumerate(zip(res, levels, got)):
+        n = g["delta"].shape[::-1]
+        gh = None
+        if g["parent"] >= 0:
+            m = V.ghost_count(n)
+            gh = ghost[goff:goff + m]
+            goff += m
+        _, tau = oracle_mod.truncation_error(g["delta"], phi, ALPHA, KAPPA, h=g["h"], ghost=gh)
+        print(prec, i, phi.shape, "rms", r["rms"], "tau", r["tau_rms"], "oracle tau", tau, "cycles", r["cycles"],
+              flush=True)
+        assert r["status"] == V.VMG_OK and r["tau_rms"] > 0.0
+        assert r["rms"] <= factor * r["tau_rms"]
+        assert abs(r["tau_rms"] - tau) <= 1e-9 * tau
