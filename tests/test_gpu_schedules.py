@@ -155,6 +155,24 @@ def test_brick_schedule_vs_march_and_oracle(torch_cuda, V, oracle_mod, prec):
         assert e <= bar
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_brick_schedule_on_narrow_levels(torch_cuda, V, prec):
+    """A 16 x 16 x 32 grid: its first coarse level (8 x 8 x 16) is narrower than the
+    bricks' staged region (16 cells with two sweeps), which wraps round the level
+    twice in x and y; the brick schedule still gives the march's iterate bit for
+    bit."""
+    p = V.FP64 if prec == "fp64" else V.MIXED
+    delta = I.lognormal((32, 16, 16), 611, sigma=1.0)
+    outs = []
+    for sched in ({1: (4, 2, 1)}, {1: (8, 8, 2)}):
+        phi, info = solve_with(torch_cuda, V, delta, 0.1, p, sched, tol=1e-30, max_cycles=3,
+                               cycle=dict(nu1=2, nu2=2) if p == V.FP64 else dict(nu1=2, nu2=2, inner_cycles=2))
+        assert info["cycles"] == 3
+        outs.append(phi)
+    say(f"{prec} narrow levels brick vs march bitwise {bool(np.array_equal(outs[0], outs[1]))}")
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_set_schedule_rejects_bad_arguments(torch_cuda, V):
     with V.Plan([V.make_grid(32)], V.make_params(0.1, 1.5, 1e-8)) as p:
         n = p.level_count()
