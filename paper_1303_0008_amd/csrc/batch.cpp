@@ -138,7 +138,7 @@ vmg_status build_batch(Plan* P) {
         }
         // geometry and work lists
         std::vector<Geom> geom, geom_fine, geomC;
-        std::vector<int2> cells, fcells, store, gh;
+        std::vector<int2> cells, store, gh;
         B.cells_A = B.cells_C = 0;
         for (int k = 0; k < nm; ++k) {
             GridState& G = P->grids[B.members[k]];
@@ -154,19 +154,17 @@ vmg_status build_batch(Plan* P) {
             if (l > 0) {
                 const Geom& gf = G.lev[l - 1].g;
                 geom_fine.push_back(gf);
-                cell_items(fcells, k, gf.ncell);
                 cell_items(store, k, g.nstore);
                 cell_items(gh, k, ghost_count(g.n0, g.n1, g.n2));
             }
         }
         B.ncells = (int)cells.size();
-        B.nfcells = (int)fcells.size();
         B.nstore_items = (int)store.size();
         B.nghost_items = (int)gh.size();
         B.nC = (int)geomC.size();
         if (upload(P, &B.d_geom, geom) != hipSuccess || upload(P, &B.d_geom_fine, geom_fine) != hipSuccess ||
             upload(P, &B.d_geomC, geomC) != hipSuccess || upload(P, &B.d_cells, cells) != hipSuccess ||
-            upload(P, &B.d_fcells, fcells) != hipSuccess || upload(P, &B.d_store, store) != hipSuccess ||
+            upload(P, &B.d_store, store) != hipSuccess ||
             upload(P, &B.d_ghosts, gh) != hipSuccess)
             return fail(VMG_EHIP, "upload of batch work lists failed");
     }
@@ -256,7 +254,7 @@ static hipError_t bcycle(Plan* P, int l) {
     CKE(launch_ghost_refresh_batch(C.d_geom, C.d_ghosts, C.nghost_items, C.phi[0], C.phiold, s));
     CKE(launch_fas_batch(C.d_geom, C.d_cells, C.ncells, P->coef, C.phi[0], C.delta, C.rd, C.f, s));
     CKE(bcycle(P, l + 1));
-    CKE(launch_prolong_batch(C.d_geom_fine, C.d_geom, C.d_fcells, C.nfcells, B.phi[B.cur], C.phi[C.cur],
+    CKE(launch_prolong_batch(C.d_geom_fine, C.d_geom, C.d_cells, C.ncells, B.phi[B.cur], C.phi[C.cur],
                              C.phiold, s));
     if (l == 0) CKE(sweep_mark(P, true, post_sweeps(P, l)));
     for (int q = 0; q < post_sweeps(P, l); ++q) CKE(bsmooth(P, l));
@@ -326,7 +324,7 @@ static hipError_t bcycle_corr(Plan* P, int l) {
     CKE(launch_ghost_refresh_batch_f(C.d_geom, C.d_ghosts, C.nghost_items, C.e[0], C.eold, s));
     CKE(launch_fas_corr_batch(C.d_geom, C.d_cells, C.ncells, cf, C.e[0], C.pt, C.t0, C.rdf, C.r, s));
     CKE(bcycle_corr(P, l + 1));
-    CKE(launch_prolong_corr_batch(C.d_geom_fine, C.d_geom, C.d_fcells, C.nfcells, B.e[B.ecur], C.e[C.ecur],
+    CKE(launch_prolong_corr_batch(C.d_geom_fine, C.d_geom, C.d_cells, C.ncells, B.e[B.ecur], C.e[C.ecur],
                                   C.eold, s));
     if (l == 0) CKE(sweep_mark(P, true, post_sweeps(P, l)));
     for (int q = 0; q < post_sweeps(P, l); ++q) CKE(bsmooth_corr(P, l));

@@ -192,6 +192,17 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 }
 
 __device__ __forceinline__ void decode(const Geom& g, int64_t e, int& i, int& j, int& k) {
+    if (g.ncell <= 0x7fffffff) {
+        // 32-bit division: a few instructions against the long software
+        // sequence of a 64-bit one (every grid below 2^31 cells)
+        const unsigned u = (unsigned)e, n0 = (unsigned)g.n0, n1 = (unsigned)g.n1;
+        const unsigned r = u / n0;
+        i = (int)(u - r * n0);
+        const unsigned kk = r / n1;
+        j = (int)(r - kk * n1);
+        k = (int)kk;
+        return;
+    }
     i = (int)(e % g.n0);
     const int64_t r = e / g.n0;
     j = (int)(r % g.n1);
@@ -269,6 +280,85 @@ __device__ __forceinline__ int mirror(int i, int n, int& sign) {
     if (i < 0) { sign = -sign; return 0; }
     if (i >= n) { sign = -sign; return n - 1; }
     return i;
+}
+
+// Trilinear prolongation of a Dirichlet grid's coarse correction uc - oc onto the
+// 8 children (2I+a, 2J+b, 2K+c) of coarse cell (I, J, K), added to uf: the 3^3
+// coarse neighbourhood is read once (mirrored, with a sign flip, one cell outside
+// the grid) and each child sums its 8 nearest coarse values with weights 3/4 and
+// 1/4 per axis, in the same order as a child taken on its own.
+template <typename T>
+__device__ __forceinline__ void prolong_children(const Geom& gf, const Geom& gc, T* __restrict__ uf,
+                                                 const T* __restrict__ uc, const T* __restrict__ oc, int I, int J,
+                                                 int K) {
+    int ix[3], jy[3], kz[3], sx[3], sy[3], sz[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        sx[d] = sy[d] = sz[d] = 1;
+        ix[d] = mirror(I + d - 1, gc.n0, sx[d]);
+        jy[d] = mirror(J + d - 1, gc.n1, sy[d]);
+        kz[d] = mirror(K + d - 1, gc.n2, sz[d]);
+    }
+    T dl[3][3][3];
+#pragma unroll
+    for (int z = 0; z < 3; ++z)
+#pragma unroll
+        for (int y = 0; y < 3; ++y) {
+            const int64_t row = gc.off0 + (int64_t)jy[y] * gc.sy + (int64_t)kz[z] * gc.sz;
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+                const int64_t ci = row + ix[x];
+                const T sgn = (T)(sx[x] * sy[y] * sz[z]);
+                dl[z][y][x] = sgn * (uc[ci] - oc[ci]);
+            }
+        }
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) {
+        const int a = ch & 1, b = (ch >> 1) & 1, c = ch >> 2;
+        T acc = (T)0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int x = 1 + ((q & 1) ? (a ? 1 : -1) : 0);
+            const int y = 1 + ((q & 2) ? (b ? 1 : -1) : 0);
+            const int z = 1 + ((q & 4) ? (c ? 1 : -1) : 0);
+            const T wq = (T)(((q & 1) ? 0.25 : 0.75) * ((q & 2) ? 0.25 : 0.75) * ((q & 4) ? 0.25 : 0.75));
+            acc += wq * dl[z][y][x];
+        }
+        uf[cell_index(gf, 2 * I + a, 2 * J + b, 2 * K + c)] += acc;
+    }
+}
+
+// The 4^3 block of a padded (Dirichlet) fine grid around the children of coarse
+// cell (I, J, K), corners left out: b[z][y][x] = u at fine cell (2I-1+x, 2J-1+y,
+// 2K-1+z).  The 18-point stencils of the 8 children read exactly these 56 values.
+template <typename T>
+__device__ __forceinline__ void load_child_box(const Geom& g, const T* __restrict__ u, int I, int J, int K,
+                                               T (&b)[4][4][4]) {
+    const int64_t o = cell_index(g, 2 * I - 1, 2 * J - 1, 2 * K - 1);
+#pragma unroll
+    for (int z = 0; z < 4; ++z)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int64_t row = o + (int64_t)y * g.sy + (int64_t)z * g.sz;
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                const bool corner = (x == 0 || x == 3) && (y == 0 || y == 3) && (z == 0 || z == 3);
+                b[z][y][x] = corner ? (T)0 : u[row + x];
+            }
+        }
+}
+
+// stencil of child (a, b, c) out of a child box; returns the centre value
+template <typename T>
+__device__ __forceinline__ T box_nb(const T (&u)[4][4][4], int a, int b, int c, NbT<T>& v) {
+    const int x = 1 + a, y = 1 + b, z = 1 + c;
+    v.xm = u[z][y][x - 1]; v.xp = u[z][y][x + 1];
+    v.ym = u[z][y - 1][x]; v.yp = u[z][y + 1][x];
+    v.zm = u[z - 1][y][x]; v.zp = u[z + 1][y][x];
+    v.xpyp = u[z][y + 1][x + 1]; v.xmym = u[z][y - 1][x - 1]; v.xpym = u[z][y - 1][x + 1]; v.xmyp = u[z][y + 1][x - 1];
+    v.xpzp = u[z + 1][y][x + 1]; v.xmzm = u[z - 1][y][x - 1]; v.xpzm = u[z - 1][y][x + 1]; v.xmzp = u[z + 1][y][x - 1];
+    v.ypzp = u[z + 1][y + 1][x]; v.ymzm = u[z - 1][y - 1][x]; v.ypzm = u[z - 1][y + 1][x]; v.ymzp = u[z + 1][y - 1][x];
+    return u[z][y][x];
 }
 
 __device__ __forceinline__ int64_t ghost_count_dev(int n0, int n1, int n2) {

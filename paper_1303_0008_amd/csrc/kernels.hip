@@ -886,6 +886,7 @@ __global__ void __launch_bounds__(NT) k_rr_batch(const Geom* __restrict__ gfs, c
                                                  const double* __restrict__ phi, const double* __restrict__ delta,
                                                  const double* __restrict__ f, double* phic, double* phiold_c,
                                                  double* rd_c) {
+    // one thread per coarse cell: the children's stencils come out of one 4^3 box
     const int2 w = items[blockIdx.x];
     const Geom gf = gfs[w.x], gc = gcs[w.x];
     const int64_t e = (int64_t)w.y + threadIdx.x;
@@ -893,13 +894,20 @@ __global__ void __launch_bounds__(NT) k_rr_batch(const Geom* __restrict__ gfs, c
     const double inv_h2 = 1.0 / (gf.h * gf.h), inv_h4 = inv_h2 * inv_h2;
     int I, J, K;
     decode(gc, e, I, J, K);
+    double u[4][4][4];
+    load_child_box(gf, phi, I, J, K, u);
     double sphi = 0.0, sd = 0.0;
 #pragma unroll
     for (int ch = 0; ch < 8; ++ch) {
-        const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
-        double Q, pc, fv;
+        const int a = ch & 1, b = (ch >> 1) & 1, z = ch >> 2;
+        Nb v;
+        const double pc = box_nb(u, a, b, z, v);
+        const int64_t gi = cell_index(gf, 2 * I + a, 2 * J + b, 2 * K + z);
+        double S;
         bool gd;
-        sd += cell_residual<1>(gf, c, phi, delta, f, 0.0, i, j, k, inv_h2, inv_h4, Q, gd, pc, fv);
+        const double Q = nl_root(v, delta[gi], c, inv_h4, S, gd);
+        const double fv = f ? f[gi] : 0.0;
+        sd += (S - 6.0 * pc) * inv_h2 - Q - fv;
         sphi += pc;
     }
     const int64_t co = cell_index(gc, I, J, K);
@@ -961,6 +969,8 @@ __global__ void __launch_bounds__(NT) k_tau_batch(const Geom* __restrict__ gs, c
     block_store_partials(acc, partials);
 }
 
+// items: 256-cell blocks of the coarse level; each thread adds the prolonged
+// correction to the 8 children of its coarse cell
 __global__ void __launch_bounds__(NT) k_prolong_batch(const Geom* __restrict__ gfs, const Geom* __restrict__ gcs,
                                                       const int2* __restrict__ items, double* __restrict__ phif,
                                                       const double* __restrict__ phic,
@@ -968,23 +978,10 @@ __global__ void __launch_bounds__(NT) k_prolong_batch(const Geom* __restrict__ g
     const int2 w = items[blockIdx.x];
     const Geom gf = gfs[w.x], gc = gcs[w.x];
     const int64_t e = (int64_t)w.y + threadIdx.x;
-    if (e >= gf.ncell) return;
-    int i, j, k;
-    decode(gf, e, i, j, k);
-    const int I = i >> 1, J = j >> 1, K = k >> 1;
-    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
-    double acc = 0.0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        int sign = 1;
-        const int ii = mirror(I + ((q & 1) ? si : 0), gc.n0, sign);
-        const int jj = mirror(J + ((q & 2) ? sj : 0), gc.n1, sign);
-        const int kk = mirror(K + ((q & 4) ? sk : 0), gc.n2, sign);
-        const double wq = ((q & 1) ? 0.25 : 0.75) * ((q & 2) ? 0.25 : 0.75) * ((q & 4) ? 0.25 : 0.75);
-        const int64_t ci = cell_index(gc, ii, jj, kk);
-        acc += wq * sign * (phic[ci] - oldc[ci]);
-    }
-    phif[cell_index(gf, i, j, k)] += acc;
+    if (e >= gc.ncell) return;
+    int I, J, K;
+    decode(gc, e, I, J, K);
+    prolong_children(gf, gc, phif, phic, oldc, I, J, K);
 }
 
 // residual norm partials per block (grid k's blocks are contiguous)

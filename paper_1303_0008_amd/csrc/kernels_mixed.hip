@@ -920,6 +920,7 @@ __global__ void __launch_bounds__(NT) k_rr_corr_batch(const Geom* __restrict__ g
                                                       const float* __restrict__ e, const float* __restrict__ pt,
                                                       const float* __restrict__ t0, const float* __restrict__ r,
                                                       float* ec, float* eold_c, float* rd_c) {
+    // one thread per coarse cell: the children's stencils come out of two 4^3 boxes
     const int2 w = items[blockIdx.x];
     const Geom gf = gfs[w.x], gc = gcs[w.x];
     const int64_t q = (int64_t)w.y + threadIdx.x;
@@ -928,12 +929,21 @@ __global__ void __launch_bounds__(NT) k_rr_corr_batch(const Geom* __restrict__ g
     const float inv_h2 = 1.0f / c.h2;
     int I, J, K;
     decode(gc, q, I, J, K);
+    float ub[4][4][4], pb[4][4][4];
+    load_child_box(gf, e, I, J, K, ub);
+    load_child_box(gf, pt, I, J, K, pb);
     float se = 0.0f, sd = 0.0f;
 #pragma unroll
     for (int ch = 0; ch < 8; ++ch) {
-        const int i = 2 * I + (ch & 1), j = 2 * J + ((ch >> 1) & 1), k = 2 * K + (ch >> 2);
-        float dQ, ev, rv;
-        sd += corr_residual<1>(gf, c, e, pt, t0, r, 0.0f, i, j, k, inv_h2, dQ, ev, rv);
+        const int a = ch & 1, b = (ch >> 1) & 1, z = ch >> 2;
+        NbT<float> ve, vp;
+        const float ev = box_nb(ub, a, b, z, ve);
+        box_nb(pb, a, b, z, vp);
+        const int64_t gi = cell_index(gf, 2 * I + a, 2 * J + b, 2 * K + z);
+        float Se;
+        const float dq = dq_corr(ve, vp, c.a_ih4, Se);
+        const float dQ = dQ_of(dq, t0[gi], c);
+        sd += (Se - 6.0f * ev) * inv_h2 - dQ - (r ? r[gi] : 0.0f);
         se += ev;
     }
     const int64_t co = cell_index(gc, I, J, K);
@@ -959,6 +969,8 @@ __global__ void __launch_bounds__(NT) k_fas_corr_batch(const Geom* __restrict__ 
     r[gi] = L - rd[gi];
 }
 
+// items: 256-cell blocks of the coarse level; each thread adds the prolonged
+// correction to the 8 children of its coarse cell
 __global__ void __launch_bounds__(NT) k_prolong_corr_batch(const Geom* __restrict__ gfs, const Geom* __restrict__ gcs,
                                                            const int2* __restrict__ items, float* __restrict__ ef,
                                                            const float* __restrict__ ecs,
@@ -966,23 +978,10 @@ __global__ void __launch_bounds__(NT) k_prolong_corr_batch(const Geom* __restric
     const int2 w = items[blockIdx.x];
     const Geom gf = gfs[w.x], gc = gcs[w.x];
     const int64_t q = (int64_t)w.y + threadIdx.x;
-    if (q >= gf.ncell) return;
-    int i, j, k;
-    decode(gf, q, i, j, k);
-    const int I = i >> 1, J = j >> 1, K = k >> 1;
-    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
-    float acc = 0.0f;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        int sign = 1;
-        const int ii = mirror(I + ((m & 1) ? si : 0), gc.n0, sign);
-        const int jj = mirror(J + ((m & 2) ? sj : 0), gc.n1, sign);
-        const int kk = mirror(K + ((m & 4) ? sk : 0), gc.n2, sign);
-        const float wq = ((m & 1) ? 0.25f : 0.75f) * ((m & 2) ? 0.25f : 0.75f) * ((m & 4) ? 0.25f : 0.75f);
-        const int64_t ci = cell_index(gc, ii, jj, kk);
-        acc += wq * (float)sign * (ecs[ci] - oldc[ci]);
-    }
-    ef[cell_index(gf, i, j, k)] += acc;
+    if (q >= gc.ncell) return;
+    int I, J, K;
+    decode(gc, q, I, J, K);
+    prolong_children(gf, gc, ef, ecs, oldc, I, J, K);
 }
 
 __global__ void __launch_bounds__(NT) k_cast_batch(const Geom* __restrict__ gs, const int2* __restrict__ items,

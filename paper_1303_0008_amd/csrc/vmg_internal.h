@@ -272,6 +272,7 @@ hipError_t launch_rr_batch(const Geom* gfs, const Geom* gcs, const int2* items, 
                            double* phiold_c, double* rd_c, hipStream_t s);
 hipError_t launch_fas_batch(const Geom* gs, const int2* items, int nitems, const Coef& c, const double* phi,
                             const double* delta, const double* rd, double* f, hipStream_t s);
+// items: the coarse level's cells (each thread updates the 8 children of one)
 hipError_t launch_prolong_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, double* phif,
                                 const double* phic, const double* oldc, hipStream_t s);
 // tau^h of every grid on level 1 (items: level-1 cells; first: each grid's block
@@ -312,6 +313,7 @@ hipError_t launch_rr_corr_batch(const Geom* gfs, const Geom* gcs, const int2* it
                                 float* eold_c, float* rd_c, hipStream_t s);
 hipError_t launch_fas_corr_batch(const Geom* gs, const int2* items, int nitems, const CoefF& c, const float* e,
                                  const float* pt, const float* t0, const float* rd, float* r, hipStream_t s);
+// items: the coarse level's cells
 hipError_t launch_prolong_corr_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, float* ef,
                                      const float* ec, const float* eold_c, hipStream_t s);
 hipError_t launch_coarse_corr_batch(const Geom* gs, int ngrids, const CoefF& c, float* e0, float* e1,

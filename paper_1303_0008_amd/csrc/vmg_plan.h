@@ -60,8 +60,6 @@ struct BatchLevel {
     int nsitems = 0;
     int2* d_cells = nullptr;         // 256-cell blocks of every member at this level
     int ncells = 0;
-    int2* d_fcells = nullptr;        // 256-cell blocks of the finer level of every member (levels >= 1)
-    int nfcells = 0;
     int2* d_store = nullptr;         // 256-element blocks of each member's padded storage (levels >= 1)
     int nstore_items = 0;
     SmoothCfg cfg{8, 16};            // schedule of the persistent smoother on this level
