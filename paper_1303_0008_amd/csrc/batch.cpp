@@ -30,7 +30,7 @@ static hipError_t upload(Plan* P, T** dst, const std::vector<T>& v) {
 }
 
 static void cell_items(std::vector<int2>& out, int k, int64_t n) {
-    for (int64_t s = 0; s < n; s += 256) out.push_back(make_int2(k, (int)s));
+    for (int64_t s = 0; s < n; s += ITEM_CELLS) out.push_back(make_int2(k, (int)s));
 }
 
 // Work list of the persistent smoother on level l for schedule cfg (the grids of
@@ -181,7 +181,7 @@ vmg_status build_batch(Plan* P) {
         const Geom& g = G.lev[0].g;
         cell_items(gitems, (int)k, ghost_count(g.n0, g.n1, g.n2));
         first.push_back(blk);
-        blk += (int)((g.ncell + 255) / 256);
+        blk += (int)((g.ncell + ITEM_CELLS - 1) / ITEM_CELLS);
     }
     first.push_back(blk);
     // level-1 block ranges, for the truncation-error estimate
@@ -190,7 +190,7 @@ vmg_status build_batch(Plan* P) {
         int b1 = 0;
         for (size_t k = 0; k < B0.members.size(); ++k) {
             first1.push_back(b1);
-            b1 += (int)((P->grids[B0.members[k]].lev[1].g.ncell + 255) / 256);
+            b1 += (int)((P->grids[B0.members[k]].lev[1].g.ncell + ITEM_CELLS - 1) / ITEM_CELLS);
         }
         first1.push_back(b1);
     }

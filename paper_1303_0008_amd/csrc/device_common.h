@@ -258,6 +258,22 @@ __device__ __forceinline__ void block_store_partials(double (&acc)[R_NSLOT], dou
     }
 }
 
+// Per-item passes of the batched plans run one wave per item of ITEM_CELLS cells,
+// each lane taking ITEM_CELLS / 64 of them, so that the cross-lane sums of the
+// partials are paid once per item rather than once per 64 cells.
+constexpr int ITEM_LANES = 64;
+static_assert(ITEM_CELLS == NT, "the one-thread-per-cell item passes run NT threads per item");
+
+// Sum R_NSLOT per-lane accumulators over a one-wave block and store them in
+// partials[blockIdx.x * R_NSLOT + k].
+__device__ __forceinline__ void wave_store_partials(double (&acc)[R_NSLOT], double* partials) {
+#pragma unroll
+    for (int k = 0; k < R_NSLOT; ++k) {
+        const double s = wave_sum(acc[k]);
+        if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * R_NSLOT + k] = s;
+    }
+}
+
 // residual d = L(phi) + cbar - f at one cell; also returns Q and the guard flag
 template <int DIR>
 __device__ __forceinline__ double cell_residual(const Geom& g, const Coef& c, const double* phi,

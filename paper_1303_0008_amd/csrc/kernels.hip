@@ -938,17 +938,20 @@ __global__ void __launch_bounds__(NT) k_fas_batch(const Geom* __restrict__ gs, c
 // with phi^H = R phi^h and rd = R d^h just formed by k_rr_batch (d^h = L^h phi^h
 // - f^h on Dirichlet grids), tau^h = L^H(R phi^h) - R L^h(phi^h) = L^H(phi^H) -
 // rd - R f^h.  Block partials of tau and tau^2 (grid k's blocks are contiguous).
-__global__ void __launch_bounds__(NT) k_tau_batch(const Geom* __restrict__ gs, const Geom* __restrict__ gfs,
-                                                  const int2* __restrict__ items, Coef c,
-                                                  const double* __restrict__ phi, const double* __restrict__ delta,
-                                                  const double* __restrict__ rd, const double* __restrict__ f_fine,
-                                                  double* partials) {
+__global__ void __launch_bounds__(ITEM_LANES) k_tau_batch(const Geom* __restrict__ gs, const Geom* __restrict__ gfs,
+                                                          const int2* __restrict__ items, Coef c,
+                                                          const double* __restrict__ phi,
+                                                          const double* __restrict__ delta,
+                                                          const double* __restrict__ rd,
+                                                          const double* __restrict__ f_fine, double* partials) {
     double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
     const int2 w = items[blockIdx.x];
     const Geom g = gs[w.x];
-    const int64_t e = (int64_t)w.y + threadIdx.x;
-    if (e < g.ncell) {
-        const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+    const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+#pragma unroll
+    for (int m = 0; m < ITEM_CELLS / ITEM_LANES; ++m) {
+        const int64_t e = (int64_t)w.y + threadIdx.x + m * ITEM_LANES;
+        if (e >= g.ncell) break;
         int I, J, K;
         decode(g, e, I, J, K);
         double Q, pc, fv;
@@ -959,14 +962,14 @@ __global__ void __launch_bounds__(NT) k_tau_batch(const Geom* __restrict__ gs, c
             const Geom gf = gfs[w.x];
             double rf = 0.0;
 #pragma unroll
-            for (int m = 0; m < 8; ++m)
-                rf += f_fine[cell_index(gf, 2 * I + (m & 1), 2 * J + ((m >> 1) & 1), 2 * K + (m >> 2))];
+            for (int q = 0; q < 8; ++q)
+                rf += f_fine[cell_index(gf, 2 * I + (q & 1), 2 * J + ((q >> 1) & 1), 2 * K + (q >> 2))];
             tau -= 0.125 * rf;
         }
-        acc[R_D1] = tau;
-        acc[R_D2] = tau * tau;
+        acc[R_D1] += tau;
+        acc[R_D2] += tau * tau;
     }
-    block_store_partials(acc, partials);
+    wave_store_partials(acc, partials);
 }
 
 // items: 256-cell blocks of the coarse level; each thread adds the prolonged
@@ -985,30 +988,33 @@ __global__ void __launch_bounds__(NT) k_prolong_batch(const Geom* __restrict__ g
 }
 
 // residual norm partials per block (grid k's blocks are contiguous)
-__global__ void __launch_bounds__(NT) k_norm_batch(const Geom* __restrict__ gs, const int2* __restrict__ items,
-                                                   Coef c, const double* __restrict__ phi,
-                                                   const double* __restrict__ delta, const double* __restrict__ f,
-                                                   double* partials) {
+__global__ void __launch_bounds__(ITEM_LANES) k_norm_batch(const Geom* __restrict__ gs,
+                                                           const int2* __restrict__ items, Coef c,
+                                                           const double* __restrict__ phi,
+                                                           const double* __restrict__ delta,
+                                                           const double* __restrict__ f, double* partials) {
     double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
     const int2 w = items[blockIdx.x];
     const Geom g = gs[w.x];
-    const int64_t e = (int64_t)w.y + threadIdx.x;
-    if (e < g.ncell) {
-        const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+    const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+#pragma unroll
+    for (int m = 0; m < ITEM_CELLS / ITEM_LANES; ++m) {
+        const int64_t e = (int64_t)w.y + threadIdx.x + m * ITEM_LANES;
+        if (e >= g.ncell) break;
         int i, j, k;
         decode(g, e, i, j, k);
         double Q, pc, fv;
         bool gd;
         const double d = cell_residual<1>(g, c, phi, delta, f, 0.0, i, j, k, inv_h2, inv_h4, Q, gd, pc, fv);
-        acc[R_D2] = d * d;
-        acc[R_D1] = d;
-        acc[R_Q] = Q;
-        acc[R_F] = fv;
-        acc[R_PHI] = pc;
-        acc[R_GUARD] = gd ? 1.0 : 0.0;
-        acc[R_NONFIN] = isfinite(d) ? 0.0 : 1.0;
+        acc[R_D2] += d * d;
+        acc[R_D1] += d;
+        acc[R_Q] += Q;
+        acc[R_F] += fv;
+        acc[R_PHI] += pc;
+        acc[R_GUARD] += gd ? 1.0 : 0.0;
+        acc[R_NONFIN] += isfinite(d) ? 0.0 : 1.0;
     }
-    block_store_partials(acc, partials);
+    wave_store_partials(acc, partials);
 }
 
 // one block per grid: sum its blocks' partials [first[k], first[k+1]) in a fixed order
@@ -1508,7 +1514,7 @@ hipError_t launch_tau_batch(const Geom* gs, const Geom* gfs, const int2* items, 
                             const double* phi, const double* delta, const double* rd, const double* f_fine,
                             double* partials, const int* first, int ngrids, NormOut* out, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tau_batch, dim3(nitems), dim3(NT), 0, s, gs, gfs, items, c, phi, delta, rd, f_fine,
+    hipLaunchKernelGGL(k_tau_batch, dim3(nitems), dim3(ITEM_LANES), 0, s, gs, gfs, items, c, phi, delta, rd, f_fine,
                        partials);
     hipLaunchKernelGGL(k_finalize_batch, dim3(ngrids), dim3(NT), 0, s, partials, first, gs, out, 1);
     return hipGetLastError();
@@ -1525,7 +1531,7 @@ hipError_t launch_norm_batch(const Geom* gs, const int2* items, int nitems, cons
                              const double* delta, const double* f, double* partials, const int* first, int ngrids,
                              NormOut* out, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_norm_batch, dim3(nitems), dim3(NT), 0, s, gs, items, c, phi, delta, f, partials);
+    hipLaunchKernelGGL(k_norm_batch, dim3(nitems), dim3(ITEM_LANES), 0, s, gs, items, c, phi, delta, f, partials);
     hipLaunchKernelGGL(k_finalize_batch, dim3(ngrids), dim3(NT), 0, s, partials, first, gs, out, 0);
     return hipGetLastError();
 }

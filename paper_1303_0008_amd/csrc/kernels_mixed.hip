@@ -984,16 +984,20 @@ __global__ void __launch_bounds__(NT) k_prolong_corr_batch(const Geom* __restric
     prolong_children(gf, gc, ef, ecs, oldc, I, J, K);
 }
 
-__global__ void __launch_bounds__(NT) k_cast_batch(const Geom* __restrict__ gs, const int2* __restrict__ items,
-                                                   Coef c, const double* __restrict__ phi,
-                                                   const double* __restrict__ delta, const double* __restrict__ f,
-                                                   float* pt, float* t0, float* r, double* partials) {
+__global__ void __launch_bounds__(ITEM_LANES) k_cast_batch(const Geom* __restrict__ gs,
+                                                           const int2* __restrict__ items, Coef c,
+                                                           const double* __restrict__ phi,
+                                                           const double* __restrict__ delta,
+                                                           const double* __restrict__ f, float* pt, float* t0,
+                                                           float* r, double* partials) {
     double acc[R_NSLOT] = {0, 0, 0, 0, 0, 0, 0};
     const int2 w = items[blockIdx.x];
     const Geom g = gs[w.x];
-    const int64_t q = (int64_t)w.y + threadIdx.x;
-    if (q < g.ncell) {
-        const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+    const double inv_h2 = 1.0 / (g.h * g.h), inv_h4 = inv_h2 * inv_h2;
+#pragma unroll
+    for (int m = 0; m < ITEM_CELLS / ITEM_LANES; ++m) {
+        const int64_t q = (int64_t)w.y + threadIdx.x + m * ITEM_LANES;
+        if (q >= g.ncell) break;
         int i, j, k;
         decode(g, q, i, j, k);
         Nb v;
@@ -1009,15 +1013,15 @@ __global__ void __launch_bounds__(NT) k_cast_batch(const Geom* __restrict__ gs, 
         pt[gi] = (float)pc;
         t0[gi] = (float)(D0 >= 0.0 ? sqrt(D0) : -sqrt(-D0));
         r[gi] = (float)(-d);
-        acc[R_D2] = d * d;
-        acc[R_D1] = d;
-        acc[R_Q] = Q;
-        acc[R_F] = fv;
-        acc[R_PHI] = pc;
-        acc[R_GUARD] = gd ? 1.0 : 0.0;
-        acc[R_NONFIN] = isfinite(d) ? 0.0 : 1.0;
+        acc[R_D2] += d * d;
+        acc[R_D1] += d;
+        acc[R_Q] += Q;
+        acc[R_F] += fv;
+        acc[R_PHI] += pc;
+        acc[R_GUARD] += gd ? 1.0 : 0.0;
+        acc[R_NONFIN] += isfinite(d) ? 0.0 : 1.0;
     }
-    block_store_partials(acc, partials);
+    wave_store_partials(acc, partials);
 }
 
 __global__ void k_base_restrict_batch(const Geom* __restrict__ gfs, const Geom* __restrict__ gcs,
@@ -1319,7 +1323,7 @@ hipError_t launch_cast_batch(const Geom* gs, const int2* items, int nitems, cons
                              const double* delta, const double* f, float* pt, float* t0, float* r,
                              double* partials, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cast_batch, dim3(nitems), dim3(NT), 0, s, gs, items, c, phi, delta, f, pt, t0, r, partials);
+    hipLaunchKernelGGL(k_cast_batch, dim3(nitems), dim3(ITEM_LANES), 0, s, gs, items, c, phi, delta, f, pt, t0, r, partials);
     return hipGetLastError();
 }
 

@@ -5,6 +5,10 @@
 
 namespace vmg {
 
+// cells per work item of the batched (Dirichlet) passes: items are (grid, first
+// cell) pairs over ITEM_CELLS consecutive cells of one grid
+constexpr int ITEM_CELLS = 256;
+
 // One level of one grid as the kernels see it.  Periodic levels are stored
 // unpadded (n0*n1*n2, x fastest) and wrap their indices; Dirichlet levels are
 // stored with a one-cell shell ((n0+2)*(n1+2)*(n2+2)) that holds the ghosts.
