@@ -381,26 +381,35 @@ __device__ __forceinline__ int64_t ghost_count_dev(int n0, int n1, int n2) {
     return 2 * ((int64_t)n1 * n2 + (int64_t)n0 * n2 + (int64_t)n0 * n1) + 4 * ((int64_t)n0 + n1 + n2);
 }
 
-// Decode a compact ghost index into cell coordinates (i, j, k) in [-1, n].
-__device__ __forceinline__ void ghost_coords(int n0, int n1, int n2, int64_t q, int& i, int& j, int& k) {
-    const int64_t fx = (int64_t)n1 * n2, fy = (int64_t)n0 * n2, fz = (int64_t)n0 * n1;
-    if (q < 2 * fx) { const int s = (int)(q / fx); const int64_t r = q % fx;
-        i = s ? n0 : -1; j = (int)(r % n1); k = (int)(r / n1); return; }
+// Decode a compact ghost index into cell coordinates (i, j, k) in [-1, n]
+// (integer type I: 32-bit when the shell has fewer than 2^31 values).
+template <typename I>
+__device__ __forceinline__ void ghost_coords_t(I n0, I n1, I n2, I q, int& i, int& j, int& k) {
+    const I fx = n1 * n2, fy = n0 * n2, fz = n0 * n1;
+    if (q < 2 * fx) { const int s = (int)(q / fx); const I r = q - (I)s * fx;
+        i = s ? (int)n0 : -1; j = (int)(r % n1); k = (int)(r / n1); return; }
     q -= 2 * fx;
-    if (q < 2 * fy) { const int s = (int)(q / fy); const int64_t r = q % fy;
-        j = s ? n1 : -1; i = (int)(r % n0); k = (int)(r / n0); return; }
+    if (q < 2 * fy) { const int s = (int)(q / fy); const I r = q - (I)s * fy;
+        j = s ? (int)n1 : -1; i = (int)(r % n0); k = (int)(r / n0); return; }
     q -= 2 * fy;
-    if (q < 2 * fz) { const int s = (int)(q / fz); const int64_t r = q % fz;
-        k = s ? n2 : -1; i = (int)(r % n0); j = (int)(r / n0); return; }
+    if (q < 2 * fz) { const int s = (int)(q / fz); const I r = q - (I)s * fz;
+        k = s ? (int)n2 : -1; i = (int)(r % n0); j = (int)(r / n0); return; }
     q -= 2 * fz;
-    if (q < 4 * (int64_t)n0) { const int e = (int)(q / n0);
-        i = (int)(q % n0); j = (e & 1) ? n1 : -1; k = (e & 2) ? n2 : -1; return; }
-    q -= 4 * (int64_t)n0;
-    if (q < 4 * (int64_t)n1) { const int e = (int)(q / n1);
-        j = (int)(q % n1); i = (e & 1) ? n0 : -1; k = (e & 2) ? n2 : -1; return; }
-    q -= 4 * (int64_t)n1;
+    if (q < 4 * n0) { const int e = (int)(q / n0);
+        i = (int)(q - (I)e * n0); j = (e & 1) ? (int)n1 : -1; k = (e & 2) ? (int)n2 : -1; return; }
+    q -= 4 * n0;
+    if (q < 4 * n1) { const int e = (int)(q / n1);
+        j = (int)(q - (I)e * n1); i = (e & 1) ? (int)n0 : -1; k = (e & 2) ? (int)n2 : -1; return; }
+    q -= 4 * n1;
     const int e = (int)(q / n2);
-    k = (int)(q % n2); i = (e & 1) ? n0 : -1; j = (e & 2) ? n1 : -1;
+    k = (int)(q - (I)e * n2); i = (e & 1) ? (int)n0 : -1; j = (e & 2) ? (int)n1 : -1;
+}
+
+__device__ __forceinline__ void ghost_coords(int n0, int n1, int n2, int64_t q, int& i, int& j, int& k) {
+    if (ghost_count_dev(n0, n1, n2) <= 0x7fffffff)
+        ghost_coords_t<unsigned>((unsigned)n0, (unsigned)n1, (unsigned)n2, (unsigned)q, i, j, k);
+    else
+        ghost_coords_t<int64_t>(n0, n1, n2, q, i, j, k);
 }
 
 // Coarse Dirichlet ghost refresh: ghost = reference + (-1)^k (u - ref) at the mirrored
