@@ -251,7 +251,6 @@ static hipError_t bcycle(Plan* P, int l) {
     C.cur = 0;
     CKE(launch_rr_batch(C.d_geom_fine, C.d_geom, C.d_cells, C.ncells, P->coef, B.phi[B.cur], B.delta, bf(P, l),
                         C.phi[0], C.phiold, C.rd, s));
-    CKE(launch_ghost_refresh_batch(C.d_geom, C.d_ghosts, C.nghost_items, C.phi[0], C.phiold, s));
     CKE(launch_fas_batch(C.d_geom, C.d_cells, C.ncells, P->coef, C.phi[0], C.delta, C.rd, C.f, s));
     CKE(bcycle(P, l + 1));
     CKE(launch_prolong_batch(C.d_geom_fine, C.d_geom, C.d_cells, C.ncells, B.phi[B.cur], C.phi[C.cur],
@@ -275,7 +274,6 @@ static hipError_t btau(Plan* P, const double* phi) {
     hipStream_t s = P->stream;
     CKE(launch_rr_batch(C.d_geom_fine, C.d_geom, C.d_cells, C.ncells, P->coef, phi, B.delta, bf(P, 0), C.phi[0],
                         C.phiold, C.rd, s));
-    CKE(launch_ghost_refresh_batch(C.d_geom, C.d_ghosts, C.nghost_items, C.phi[0], C.phiold, s));
     return launch_tau_batch(C.d_geom, C.d_geom_fine, C.d_cells, C.ncells, P->coef, C.phi[0], C.delta, C.rd,
                             bf(P, 0), P->partials, P->d_first1, (int)C.members.size(), P->d_norms, s);
 }
@@ -321,7 +319,6 @@ static hipError_t bcycle_corr(Plan* P, int l) {
     C.ecur = 0;
     CKE(launch_rr_corr_batch(C.d_geom_fine, C.d_geom, C.d_cells, C.ncells, cf, B.e[B.ecur], B.pt, B.t0, B.r,
                              C.e[0], C.eold, C.rdf, s));
-    CKE(launch_ghost_refresh_batch_f(C.d_geom, C.d_ghosts, C.nghost_items, C.e[0], C.eold, s));
     CKE(launch_fas_corr_batch(C.d_geom, C.d_cells, C.ncells, cf, C.e[0], C.pt, C.t0, C.rdf, C.r, s));
     CKE(bcycle_corr(P, l + 1));
     CKE(launch_prolong_corr_batch(C.d_geom_fine, C.d_geom, C.d_cells, C.ncells, B.e[B.ecur], C.e[C.ecur],

@@ -344,6 +344,31 @@ __device__ __forceinline__ void prolong_children(const Geom& gf, const Geom& gc,
     }
 }
 
+// Right after a restriction, u = ref on every interior cell of a coarse
+// Dirichlet level, so its refreshed ghost shell (ref + (-1)^k (u - ref) at the
+// mirrored cell) is ref's.  The thread of interior cell (I, J, K) copies the
+// face and edge ghosts whose mirrored cell it is: each ghost has one writer.
+template <typename T>
+__device__ __forceinline__ void copy_ghosts_near(const Geom& g, T* __restrict__ u, const T* __restrict__ ref, int I,
+                                                 int J, int K) {
+    if (I > 0 && I < g.n0 - 1 && J > 0 && J < g.n1 - 1 && K > 0 && K < g.n2 - 1) return;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int out = (dx != 0) + (dy != 0) + (dz != 0);
+                if (out == 0 || out == 3) continue;   // the cell itself; corners are not stored
+                const int x = I + dx, y = J + dy, z = K + dz;
+                if ((dx != 0 && x >= 0 && x < g.n0) || (dy != 0 && y >= 0 && y < g.n1) ||
+                    (dz != 0 && z >= 0 && z < g.n2))
+                    continue;                         // a step that stays inside: not a ghost of this cell
+                const int64_t gi = cell_index(g, x, y, z);
+                u[gi] = ref[gi];
+            }
+}
+
 // The 4^3 block of a padded (Dirichlet) fine grid around the children of coarse
 // cell (I, J, K), corners left out: b[z][y][x] = u at fine cell (2I-1+x, 2J-1+y,
 // 2K-1+z).  The 18-point stencils of the 8 children read exactly these 56 values.

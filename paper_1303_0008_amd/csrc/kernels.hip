@@ -886,7 +886,8 @@ __global__ void __launch_bounds__(NT) k_rr_batch(const Geom* __restrict__ gfs, c
                                                  const double* __restrict__ phi, const double* __restrict__ delta,
                                                  const double* __restrict__ f, double* phic, double* phiold_c,
                                                  double* rd_c) {
-    // one thread per coarse cell: the children's stencils come out of one 4^3 box
+    // one thread per coarse cell: the children's stencils come out of one 4^3 box;
+    // the coarse ghost shell of phic is refreshed here too
     const int2 w = items[blockIdx.x];
     const Geom gf = gfs[w.x], gc = gcs[w.x];
     const int64_t e = (int64_t)w.y + threadIdx.x;
@@ -914,6 +915,7 @@ __global__ void __launch_bounds__(NT) k_rr_batch(const Geom* __restrict__ gfs, c
     phic[co] = 0.125 * sphi;
     phiold_c[co] = 0.125 * sphi;
     rd_c[co] = 0.125 * sd;
+    copy_ghosts_near(gc, phic, phiold_c, I, J, K);
 }
 
 __global__ void __launch_bounds__(NT) k_fas_batch(const Geom* __restrict__ gs, const int2* __restrict__ items,

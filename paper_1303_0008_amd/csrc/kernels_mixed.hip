@@ -920,7 +920,8 @@ __global__ void __launch_bounds__(NT) k_rr_corr_batch(const Geom* __restrict__ g
                                                       const float* __restrict__ e, const float* __restrict__ pt,
                                                       const float* __restrict__ t0, const float* __restrict__ r,
                                                       float* ec, float* eold_c, float* rd_c) {
-    // one thread per coarse cell: the children's stencils come out of two 4^3 boxes
+    // one thread per coarse cell: the children's stencils come out of two 4^3 boxes;
+    // the coarse ghost shell of ec is refreshed here too
     const int2 w = items[blockIdx.x];
     const Geom gf = gfs[w.x], gc = gcs[w.x];
     const int64_t q = (int64_t)w.y + threadIdx.x;
@@ -950,6 +951,7 @@ __global__ void __launch_bounds__(NT) k_rr_corr_batch(const Geom* __restrict__ g
     ec[co] = 0.125f * se;
     eold_c[co] = 0.125f * se;
     rd_c[co] = 0.125f * sd;
+    copy_ghosts_near(gc, ec, eold_c, I, J, K);
 }
 
 __global__ void __launch_bounds__(NT) k_fas_corr_batch(const Geom* __restrict__ gs, const int2* __restrict__ items,

@@ -271,6 +271,7 @@ struct SmoothArgs;
 hipError_t launch_smooth_batch_args(const Coef& c, const double* pin, double* pout, const double* delta,
                                     const double* f, SmoothCfg cfg, const Geom* geoms, const int4* items,
                                     int nitems, int max_blocks, hipStream_t s);
+// items: the coarse level's cells; also sets the coarse ghost shell of phic to phiold_c's
 hipError_t launch_rr_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, const Coef& c,
                            const double* phi, const double* delta, const double* f, double* phic,
                            double* phiold_c, double* rd_c, hipStream_t s);
@@ -312,6 +313,7 @@ hipError_t launch_check_finite_batch(const Geom* gs, const int64_t* uoff, const 
 hipError_t launch_smooth_corr_batch(const CoefF& c, const float* ein, float* eout, const float* pt, const float* t0,
                                     const float* r, SmoothCfg cfg, const Geom* geoms, const int4* items, int nitems,
                                     int max_blocks, hipStream_t s);
+// items: the coarse level's cells; also sets the coarse ghost shell of ec to eold_c's
 hipError_t launch_rr_corr_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, const CoefF& c,
                                 const float* e, const float* pt, const float* t0, const float* r, float* ec,
                                 float* eold_c, float* rd_c, hipStream_t s);
