@@ -385,7 +385,8 @@ vmg_status vmg_plan_stats(const vmg_plan *plan, int64_t *cell_updates, int64_t *
  * z-chunk of the finest level's fused sweep (chosen by the autotuner with
  * VMG_AUTOTUNE, which times every swept level's smoother for tile heights
  * {4,8,12,16} x z chunks x pipeline shapes, plus the brick schedule on the
- * coarser levels of a periodic plan, at plan creation, and installs a
+ * coarser levels of a periodic plan and on every level of a Dirichlet batch,
+ * at plan creation, and installs a
  * cached cycle schedule of vmg_plan_tune_cycle; Sec. V of the paper notes the
  * code needed more tuning), pre/post sweeps and coarsest-level sweeps.
  * Errors: VMG_EINVAL. */
@@ -450,15 +451,17 @@ int32_t vmg_plan_level_count(const vmg_plan *plan);
  * 64 x tile_y cells marching z_chunk planes, with pipeline shape `pipe`: 0 =
  * the black phase one plane behind the red phase (two barriers per plane
  * step, three-plane LDS rings), 1 = two planes behind (one barrier, four-plane
- * rings); or, with pipe 2 on a coarser level of a periodic plan, the brick
- * schedule: no z march, up to two sweeps per launch on 8^3 bricks whose rings
- * are recomputed by every block (tile_y and z_chunk are then only validated).
+ * rings); or, with pipe 2, the brick schedule: no z march, 8^3 bricks whose
+ * rings are recomputed by every block, up to two sweeps per launch on a
+ * coarser level of a periodic plan, one sweep per launch (the ghost shell as
+ * the boundary) on any level of a Dirichlet batch (tile_y and z_chunk are then
+ * only validated).
  * The schedule changes only the blocking of the same red-black update, not the
  * result's definition.  With VMG_GRAPH the iteration graphs are recorded again
  * (allocates).  Errors: VMG_EINVAL (null plan, level outside [0,
  * vmg_plan_level_count), tile_y not in {4, 8, 12, 16}, z_chunk odd or outside
- * [2, 1024], pipe not 0, 1 or 2, pipe 2 on the finest level or on a Dirichlet
- * batch), VMG_EHIP. */
+ * [2, 1024], pipe not 0, 1 or 2, pipe 2 on the finest level of a periodic
+ * plan), VMG_EHIP. */
 vmg_status vmg_plan_set_schedule(vmg_plan *plan, int32_t level, int32_t tile_y, int32_t z_chunk, int32_t pipe);
 
 /* The sweep schedule a level runs (host pointers, each may be NULL).

@@ -5,9 +5,9 @@
 //    buffers (HIP events on the plan's stream), two sweeps at a time, for tile
 //    heights {8,4,16,12} x z chunks ({16,8,32,64} on the finest level,
 //    {16,8,4,2} below, since short chunks spread small grids over the chip) x
-//    both pipeline shapes, plus, on the coarser levels of a periodic plan, the
-//    brick schedule (two sweeps per launch without the z march), and keep the
-//    fastest.
+//    both pipeline shapes, plus the brick schedule (without the z march: two
+//    sweeps per launch on the coarser levels of a periodic plan, one on every
+//    level of a Dirichlet batch), and keep the fastest.
 //  * The cycle schedule, on request (vmg_plan_tune_cycle): time complete
 //    solves of a given input (from the caller's initial guess) to the plan's
 //    tolerance for candidate nu1/nu2,
@@ -190,8 +190,9 @@ vmg_status autotune(Plan* P) {
     for (int l = 0; l < nlev && st == VMG_OK; ++l) {
         const std::string key = tune_key(P, l);
         SmoothCfg best;
-        // the brick schedule runs on the coarser levels of periodic plans only
-        if (cached(key, best) && (best.pipe != PIPE_BRICK || (l > 0 && !P->batched))) {
+        // the brick schedule runs on the coarser levels of periodic plans and on
+        // every level of Dirichlet batches
+        if (cached(key, best) && (best.pipe != PIPE_BRICK || l > 0 || P->batched)) {
             P->tuned_from_cache = true;
             if (apply(P, l, best) != hipSuccess) st = fail(VMG_EHIP, "autotune: work list upload failed");
             continue;
@@ -206,8 +207,9 @@ vmg_status autotune(Plan* P) {
                 else
                     for (int b = 0; b < 4; ++b) cands.push_back(SmoothCfg{tys[a], zcoarse[b], pipe});
             }
-        // coarser periodic levels may also run their sweeps in pairs on bricks
-        if (l > 0 && !P->batched) cands.push_back(SmoothCfg{8, 8, PIPE_BRICK});
+        // coarser periodic levels may also run their sweeps in pairs on bricks, and
+        // Dirichlet batches one at a time on every level
+        if (l > 0 || P->batched) cands.push_back(SmoothCfg{8, 8, PIPE_BRICK});
         double best_us = 1e300;
         // the finest level: plain sweeps; below it, a V(2,2) cycle's smoothing (two
         // sweeps, the coarse correction, two sweeps) per repetition

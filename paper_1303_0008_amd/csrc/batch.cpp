@@ -42,6 +42,14 @@ hipError_t batch_set_level_cfg(Plan* P, int l, SmoothCfg cfg) {
     for (size_t k = 0; k < B.members.size(); ++k) {
         if (B.coarsest[k]) continue;
         const Geom& g = P->grids[B.members[k]].lev[l].g;
+        if (cfg.pipe == PIPE_BRICK) {   // (grid, brick x, brick y, brick z)
+            const int bx = (g.n0 + BB_SIDE - 1) / BB_SIDE, by = (g.n1 + BB_SIDE - 1) / BB_SIDE;
+            const int bz = (g.n2 + BB_SIDE - 1) / BB_SIDE;
+            for (int z = 0; z < bz; ++z)
+                for (int y = 0; y < by; ++y)
+                    for (int x = 0; x < bx; ++x) items.push_back(make_int4((int)k, x, y, z));
+            continue;
+        }
         const int tx = (g.n0 + TX - 1) / TX, ty = (g.n1 + cfg.ty - 1) / cfg.ty;
         const int tz = (g.n2 + cfg.zc - 1) / cfg.zc;
         for (int c = 0; c < tz; ++c)

@@ -544,13 +544,17 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
 // state with that sweep's reds updated, so the sweeps are those of the march.
 // With PRO the staged state first gets the prolonged coarse correction, with
 // the folded march's interpolation order (z, then y, then x).
+// DIR = 1: a padded Dirichlet level (one sweep, S = 1): the region is staged
+// from the stored cells and ghost shell (what lies beyond the shell is never a
+// neighbour of an interior cell and stages as zero), and only interior cells
+// are updated: the ghosts are the sweep's boundary values.
 //
 // Policy interface (besides Cell, Src, Corr, add_corr and gc of the march):
 //   k.load_cell(i), k.load_src(i), k.store_cell(i, v)   element i of the level
 //   k.load_corr(i)                  u^H - u^H_old at element i of the coarse level
 //   k.update_nb(v, centre, src)     the updated cell from its 18 neighbours
 // ---------------------------------------------------------------------------
-constexpr int BB = 8;
+constexpr int BB = BB_SIDE;
 constexpr int BRICK_THREADS = 512;
 constexpr int BRICK_WAVES = 4;   // waves per SIMD: two blocks per CU (LDS <= 80 KB each)
 constexpr int brick_side(int s) { return BB + 4 * s; }          // staged region, per axis
@@ -561,7 +565,12 @@ __device__ __forceinline__ int wrap_idx(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
-template <int S, bool PRO, typename K>
+// whether padded element (x, y, z) of a Dirichlet level is stored (ghost shell included)
+__device__ __forceinline__ bool in_shell(const Geom& g, int x, int y, int z) {
+    return x >= -1 && x <= g.n0 && y >= -1 && y <= g.n1 && z >= -1 && z <= g.n2;
+}
+
+template <int S, bool PRO, int DIR = 0, typename K>
 __device__ __forceinline__ void brick_sweeps(const K& k, const Geom& g, int bx0, int by0, int bz0) {
     using Cell = typename K::Cell;
     using Src = typename K::Src;
@@ -574,6 +583,7 @@ __device__ __forceinline__ void brick_sweeps(const K& k, const Geom& g, int bx0,
     constexpr int NLU = (NU + NTH - 1) / NTH, NLS = (NS + NTH - 1) / NTH;
     constexpr int NQ = (NS / 2 + NTH - 1) / NTH;   // widest phase: one colour of ring 2S - 1
     static_assert(!PRO || NCW * sizeof(Corr) <= NU * sizeof(Cell), "the coarse window lives in U's space");
+    static_assert(!DIR || (S == 1 && !PRO), "Dirichlet levels: one sweep, no folded prolongation");
     __shared__ Cell U[NU];
     __shared__ Src SR[NS];
     // the coarse window is read before U is written: it borrows U's space
@@ -587,8 +597,13 @@ __device__ __forceinline__ void brick_sweeps(const K& k, const Geom& g, int bx0,
         const int e = tid + q * NTH;
         if (e < NU) {
             const int x = e % RW, y = (e / RW) % RW, z = e / RW2;
-            u0[q] = k.load_cell(cell_index(g, wrap_idx(bx0 - R + x, g.n0), wrap_idx(by0 - R + y, g.n1),
-                                           wrap_idx(bz0 - R + z, g.n2)));
+            if (DIR) {
+                const int gx = bx0 - R + x, gy = by0 - R + y, gz = bz0 - R + z;
+                u0[q] = in_shell(g, gx, gy, gz) ? k.load_cell(cell_index(g, gx, gy, gz)) : Cell{};
+            } else {
+                u0[q] = k.load_cell(cell_index(g, wrap_idx(bx0 - R + x, g.n0), wrap_idx(by0 - R + y, g.n1),
+                                               wrap_idx(bz0 - R + z, g.n2)));
+            }
         }
     }
     // every load is issued before the first LDS write (registers, then LDS)
@@ -598,8 +613,13 @@ __device__ __forceinline__ void brick_sweeps(const K& k, const Geom& g, int bx0,
         const int e = tid + q * NTH;
         if (e < NS) {
             const int x = e % RS, y = (e / RS) % RS, z = e / (RS * RS);
-            s0[q] = k.load_src(cell_index(g, wrap_idx(bx0 - R + 1 + x, g.n0), wrap_idx(by0 - R + 1 + y, g.n1),
-                                          wrap_idx(bz0 - R + 1 + z, g.n2)));
+            if (DIR) {
+                const int gx = bx0 - R + 1 + x, gy = by0 - R + 1 + y, gz = bz0 - R + 1 + z;
+                s0[q] = in_shell(g, gx, gy, gz) ? k.load_src(cell_index(g, gx, gy, gz)) : Src{};
+            } else {
+                s0[q] = k.load_src(cell_index(g, wrap_idx(bx0 - R + 1 + x, g.n0), wrap_idx(by0 - R + 1 + y, g.n1),
+                                              wrap_idx(bz0 - R + 1 + z, g.n2)));
+            }
         }
     }
     constexpr int NLC = PRO ? (NCW + NTH - 1) / NTH : 1;
@@ -677,6 +697,10 @@ __device__ __forceinline__ void brick_sweeps(const K& k, const Geom& g, int bx0,
                 const int hx = e % half, r = e / half;
                 const int y = lo + r % side, z = lo + r / side;
                 const int x = lo + 2 * hx + ((colour + par0 + y + z + lo) & 1);
+                if (DIR) {
+                    const int gx = bx0 - R + x, gy = by0 - R + y, gz = bz0 - R + z;
+                    if (gx < 0 || gx >= g.n0 || gy < 0 || gy >= g.n1 || gz < 0 || gz >= g.n2) continue;
+                }
                 const int c = (z * RW + y) * RW + x;
                 NbT<Cell> v;
                 v.xm = U[c - 1];                 v.xp = U[c + 1];

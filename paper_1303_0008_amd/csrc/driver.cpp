@@ -1180,8 +1180,9 @@ vmg_status vmg_plan_set_schedule(vmg_plan* plan, int32_t level, int32_t tile_y, 
     if (pipe != 0 && pipe != 1 && pipe != PIPE_BRICK) return fail(VMG_EINVAL, "pipe must be 0, 1 or 2");
     if (level < 0 || level >= swept_level_count(P))
         return fail(VMG_EINVAL, "level " + std::to_string(level) + " has no fused sweep in this plan");
-    if (pipe == PIPE_BRICK && (level == 0 || P->batched))
-        return fail(VMG_EINVAL, "pipe 2 (bricks) runs on the coarser levels of a periodic plan only");
+    if (pipe == PIPE_BRICK && level == 0 && !P->batched)
+        return fail(VMG_EINVAL, "pipe 2 (bricks) runs on the coarser levels of a periodic plan or on any level of "
+                                "a Dirichlet batch");
     const SmoothCfg c{tile_y, z_chunk, pipe};
     if (level == 0) P->cfg = c;
     if (P->batched) {

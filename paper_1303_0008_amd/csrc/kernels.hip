@@ -159,6 +159,24 @@ __global__ void __launch_bounds__(BRICK_THREADS, (S == 2 && PRO) ? 2 : BRICK_WAV
     brick_sweeps<S, PRO>(k, a.g, bx * BB, by * BB, bz * BB);
 }
 
+// One sweep of every Dirichlet grid of a batch at one level on BB^3 bricks:
+// items[it] = (grid, brick x, brick y, brick z) of a persistent work list; the
+// ghost shell is the boundary (brick_sweeps, DIR = 1).
+template <bool HAS_F>
+__global__ void __launch_bounds__(BRICK_THREADS, BRICK_WAVES) k_smooth_brick_batch(SmoothArgs proto,
+                                                                                   const Geom* __restrict__ geoms,
+                                                                                   const int4* __restrict__ items,
+                                                                                   int nitems) {
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int4 w = items[it];
+        SmoothArgs a = proto;
+        a.g = geoms[w.x];
+        const SmoothK<HAS_F> k(a, a.g, false);
+        brick_sweeps<1, false, 1>(k, a.g, w.y * BB, w.z * BB, w.w * BB);
+        __syncthreads();   // the next item's staging overwrites the LDS
+    }
+}
+
 template <int TY, bool HAS_F, bool DEFER>
 __global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER)) k_smooth_batch(SmoothArgs proto, const Geom* __restrict__ geoms,
                                                      const int4* __restrict__ items, int nitems) {
@@ -1478,6 +1496,11 @@ hipError_t launch_smooth_batch(const SmoothArgs& proto, const Geom* geoms, const
                                SmoothCfg cfg, int max_blocks, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     const int nb = std::min(nitems, max_blocks);
+    if (cfg.pipe == PIPE_BRICK) {
+        if (proto.f) hipLaunchKernelGGL((k_smooth_brick_batch<true>), dim3(nb), dim3(BRICK_THREADS), 0, s, proto, geoms, items, nitems);
+        else hipLaunchKernelGGL((k_smooth_brick_batch<false>), dim3(nb), dim3(BRICK_THREADS), 0, s, proto, geoms, items, nitems);
+        return hipGetLastError();
+    }
     const bool d = cfg.pipe != 0;
     if (cfg.ty == 4) smooth_batch_ty<4>(proto, geoms, items, nitems, nb, d, s);
     else if (cfg.ty == 16) smooth_batch_ty<16>(proto, geoms, items, nitems, nb, d, s);

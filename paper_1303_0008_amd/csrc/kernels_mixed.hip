@@ -173,6 +173,24 @@ __global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER)) k_s
     }
 }
 
+// one sweep of every grid of a Dirichlet batch at one level on BB^3 bricks
+// (items: grid, brick x, brick y, brick z)
+__global__ void __launch_bounds__(BRICK_THREADS, BRICK_WAVES) k_smooth_corr_brick_batch(CorrArgs proto,
+                                                                                        const Geom* __restrict__ geoms,
+                                                                                        const int4* __restrict__ items,
+                                                                                        int nitems) {
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int4 w = items[it];
+        CorrArgs a = proto;
+        a.g = geoms[w.x];
+        a.c.a_ih4 = proto.c.alpha / (float)(a.g.h * a.g.h * a.g.h * a.g.h);
+        a.c.h2 = (float)(a.g.h * a.g.h);
+        const CorrK<false> k(a, false);
+        brick_sweeps<1, false, 1>(k, a.g, w.y * BB, w.z * BB, w.w * BB);
+        __syncthreads();   // the next item's staging overwrites the LDS
+    }
+}
+
 // ---------------------------------------------------------------------------
 // inner residual + restriction, inner FAS rhs, prolongation (FP32 data, FP64 sums)
 // ---------------------------------------------------------------------------
@@ -1276,6 +1294,10 @@ hipError_t launch_smooth_corr_batch(const CoefF& c, const float* ein, float* eou
     a.c = c; a.ein = ein; a.eout = eout; a.pt = pt; a.t0 = t0; a.r = r; a.sc = nullptr;
     a.zc = cfg.zc > 0 ? cfg.zc : 16;
     const dim3 nb(std::min(nitems, max_blocks));
+    if (cfg.pipe == PIPE_BRICK) {
+        hipLaunchKernelGGL(k_smooth_corr_brick_batch, nb, dim3(BRICK_THREADS), 0, s, a, geoms, items, nitems);
+        return hipGetLastError();
+    }
     const bool d = cfg.pipe != 0;
 #define VMG_CORR_BATCH(T)                                                                                   \
     do {                                                                                                   \

@@ -70,10 +70,12 @@ struct SmoothCfg {
     int zc;      // z planes per block
     int pipe = 1;   // 0: black one plane behind red, two barriers per plane step;
                     // 1: black two planes behind, one barrier (four-plane rings);
-                    // PIPE_BRICK: no z march, up to two sweeps per launch on 8^3
-                    // bricks (periodic levels below the finest; ty, zc unused)
+                    // PIPE_BRICK: no z march, BB_SIDE^3 bricks (ty, zc unused): up
+                    // to two sweeps per launch on periodic levels below the finest,
+                    // one on any level of a Dirichlet batch
 };
 constexpr int PIPE_BRICK = 2;
+constexpr int BB_SIDE = 8;   // brick side of PIPE_BRICK
 
 // Blocks a tiled pass should at least launch: four per compute unit.
 constexpr int64_t MIN_TILED_BLOCKS = 1024;

@@ -434,8 +434,8 @@ def plan_level_count(handle):
 
 def plan_set_schedule(handle, level, tile_y, z_chunk, pipe=1):
     """vmg_plan_set_schedule: install a sweep schedule on one level: tile height, z chunk and
-    pipe 0/1 (the z march with three- or four-plane rings) or 2 (coarser periodic levels: up
-    to two sweeps per launch on 8^3 bricks)."""
+    pipe 0/1 (the z march with three- or four-plane rings) or 2 (8^3 bricks: up to two sweeps
+    per launch on coarser periodic levels, one on any level of a Dirichlet batch)."""
     _check(load().vmg_plan_set_schedule(ctypes.c_void_p(handle), int(level), int(tile_y), int(z_chunk), int(pipe)))
 
 

@@ -186,6 +186,40 @@ def test_patches96_gpu_pipeline(torch_cuda, V):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_brick_schedule_equals_march(torch_cuda, V, oracle_mod, prec):
+    """The brick schedule on a Dirichlet batch (pipe 2: one sweep per launch on
+    8^3 bricks, the ghost shell as the boundary, no z march) gives the march's
+    iterate bit for bit after three cycles, on every level at once and on the
+    coarser levels only.  Sizes that are no multiple of 8 end in partial bricks;
+    the 5^3 and 3 x 7 x 5 grids are their own coarsest level."""
+    torch = torch_cuda
+    sizes = [(16, 16, 16), (24, 24, 24), (8, 12, 16), (32, 32, 32), (5, 5, 5), (12, 20, 28), (3, 7, 5)]
+    h = 1.0 / 512
+    grids, deltas, ghosts = _batch(V, oracle_mod, sizes, h, 37)
+    dt = dev(torch, np.concatenate([d.ravel() for d in deltas]))
+    gt = dev(torch, np.concatenate(ghosts))
+    pr = V.FP64 if prec == "fp64" else V.MIXED
+    cyc = dict(nu1=2, nu2=1) if pr == V.FP64 else dict(nu1=2, nu2=1, inner_cycles=2)
+    outs = []
+    for label, first in (("march", None), ("bricks", 0), ("bricks below the finest", 1)):
+        phi = torch.zeros_like(dt)
+        with V.Plan(grids, V.make_params(0.1, 1.5, 1e-30, 3, pr)) as plan:
+            plan.set_cycle(**cyc)
+            for lev in range(plan.level_count()):
+                if first is None or lev < first:
+                    plan.set_schedule(lev, 8, 4, 1)
+                else:
+                    plan.set_schedule(lev, 8, 8, 2)
+                    assert plan.schedule(lev)[2] == 2
+            res = plan.solve(dt, phi, ghost=gt, allow_noconv=True)
+        assert all(r["cycles"] == 3 for r in res)
+        outs.append(phi.cpu().numpy())
+        say(f"{prec} batch {label}: rms {max(r['rms'] for r in res):.2e}, "
+            f"bitwise equal to the march {bool(np.array_equal(outs[0], outs[-1]))}")
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_batch_cycle_tuner_and_schedules(torch_cuda, V, oracle_mod, prec):
     """Dirichlet batch: the cycle tuner (including the persistent launch size)
     and every pipeline shape of the persistent smoother give the oracle's
@@ -218,7 +252,7 @@ def test_batch_cycle_tuner_and_schedules(torch_cuda, V, oracle_mod, prec):
         say(f"{prec} batch tuned cycle {best} ({ms:.3f} ms)")
         assert best["batch_blocks"] in (512, 1024, 2048) and best["coarse_tail"] == 0
         check(plan, "tuned cycle")
-        for pipe in (0, 1):
+        for pipe in (0, 1, 2):
             for lev in range(plan.level_count()):
                 plan.set_schedule(lev, 12 if lev == 0 else 4, 6 if lev == 0 else 2, pipe)
             check(plan, f"pipe {pipe}")
