@@ -233,12 +233,16 @@ static const double* bf(const Plan* P, int l) {
 // ---------------------------------------------------------------------------
 static hipError_t bsmooth(Plan* P, int l) {
     BatchLevel& B = P->blev[l];
+    // below the finest level the ghosts follow the interior: the brick schedule
+    // refreshes them as it writes, the march leaves that to a separate pass
+    const bool fold = l > 0 && B.cfg.pipe == PIPE_BRICK;
     CKE(launch_smooth_batch_args(P->coef, B.phi[B.cur], B.phi[B.cur ^ 1], B.delta, bf(P, l), B.cfg, B.d_geom,
-                                 B.d_sitems, B.nsitems, P->batch_blocks, P->stream));
+                                 B.d_sitems, B.nsitems, P->batch_blocks, P->stream, fold ? B.phiold : nullptr));
     B.cur ^= 1;
     P->cell_updates += B.cells_A;
     if (l == 0) P->finest_sweeps += 1;
-    else CKE(launch_ghost_refresh_batch(B.d_geom, B.d_ghosts, B.nghost_items, B.phi[B.cur], B.phiold, P->stream));
+    else if (!fold)
+        CKE(launch_ghost_refresh_batch(B.d_geom, B.d_ghosts, B.nghost_items, B.phi[B.cur], B.phiold, P->stream));
     return hipSuccess;
 }
 
@@ -301,12 +305,14 @@ static hipError_t bnorms(Plan* P) {
 static hipError_t bsmooth_corr(Plan* P, int l) {
     BatchLevel& B = P->blev[l];
     const CoefF cf = make_coef_f(P->coef, 1.0);   // per-grid h is applied inside the kernels
+    const bool fold = l > 0 && B.cfg.pipe == PIPE_BRICK;   // as in bsmooth
     CKE(launch_smooth_corr_batch(cf, B.e[B.ecur], B.e[B.ecur ^ 1], B.pt, B.t0, B.r, B.cfg, B.d_geom, B.d_sitems,
-                                 B.nsitems, P->batch_blocks, P->stream));
+                                 B.nsitems, P->batch_blocks, P->stream, fold ? B.eold : nullptr));
     B.ecur ^= 1;
     P->cell_updates += B.cells_A;
     if (l == 0) P->finest_sweeps += 1;
-    else CKE(launch_ghost_refresh_batch_f(B.d_geom, B.d_ghosts, B.nghost_items, B.e[B.ecur], B.eold, P->stream));
+    else if (!fold)
+        CKE(launch_ghost_refresh_batch_f(B.d_geom, B.d_ghosts, B.nghost_items, B.e[B.ecur], B.eold, P->stream));
     return hipSuccess;
 }
 

@@ -547,7 +547,9 @@ __device__ __forceinline__ void fused_sweep(const K& k, const Geom& g, const int
 // DIR = 1: a padded Dirichlet level (one sweep, S = 1): the region is staged
 // from the stored cells and ghost shell (what lies beyond the shell is never a
 // neighbour of an interior cell and stages as zero), and only interior cells
-// are updated: the ghosts are the sweep's boundary values.
+// are updated: the ghosts are the sweep's boundary values.  With GHOSTS the
+// output's ghost shell is refreshed as the brick goes out (coarse levels, whose
+// ghosts follow the interior: k.store_ghost).
 //
 // Policy interface (besides Cell, Src, Corr, add_corr and gc of the march):
 //   k.load_cell(i), k.load_src(i), k.store_cell(i, v)   element i of the level
@@ -570,7 +572,30 @@ __device__ __forceinline__ bool in_shell(const Geom& g, int x, int y, int z) {
     return x >= -1 && x <= g.n0 && y >= -1 && y <= g.n1 && z >= -1 && z <= g.n2;
 }
 
-template <int S, bool PRO, int DIR = 0, typename K>
+// Refresh the face and edge ghosts of the output whose mirrored interior cell is
+// (x, y, z) (element ii), from its new value v: each ghost has one such cell,
+// and the sign flips once per mirrored axis.
+template <typename K, typename Cell>
+__device__ __forceinline__ void brick_store_ghosts(const K& k, const Geom& g, int x, int y, int z, int64_t ii,
+                                                   const Cell& v) {
+    if (x > 0 && x < g.n0 - 1 && y > 0 && y < g.n1 - 1 && z > 0 && z < g.n2 - 1) return;
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int out = (dx != 0) + (dy != 0) + (dz != 0);
+                if (out == 0 || out == 3) continue;   // the cell itself; corners are not stored
+                const int gx = x + dx, gy = y + dy, gz = z + dz;
+                if ((dx != 0 && gx >= 0 && gx < g.n0) || (dy != 0 && gy >= 0 && gy < g.n1) ||
+                    (dz != 0 && gz >= 0 && gz < g.n2))
+                    continue;                         // a step that stays inside: not a ghost of this cell
+                k.store_ghost(cell_index(g, gx, gy, gz), ii, out == 1 ? -1 : 1, v);
+            }
+}
+
+template <int S, bool PRO, int DIR = 0, bool GHOSTS = false, typename K>
 __device__ __forceinline__ void brick_sweeps(const K& k, const Geom& g, int bx0, int by0, int bz0) {
     using Cell = typename K::Cell;
     using Src = typename K::Src;
@@ -584,6 +609,7 @@ __device__ __forceinline__ void brick_sweeps(const K& k, const Geom& g, int bx0,
     constexpr int NQ = (NS / 2 + NTH - 1) / NTH;   // widest phase: one colour of ring 2S - 1
     static_assert(!PRO || NCW * sizeof(Corr) <= NU * sizeof(Cell), "the coarse window lives in U's space");
     static_assert(!DIR || (S == 1 && !PRO), "Dirichlet levels: one sweep, no folded prolongation");
+    static_assert(!GHOSTS || DIR, "only Dirichlet levels have a ghost shell");
     __shared__ Cell U[NU];
     __shared__ Src SR[NS];
     // the coarse window is read before U is written: it borrows U's space
@@ -728,8 +754,12 @@ __device__ __forceinline__ void brick_sweeps(const K& k, const Geom& g, int bx0,
     for (int e = tid; e < BB * BB * BB; e += NTH) {
         const int x = e % BB, y = (e / BB) % BB, z = e / (BB * BB);
         const int gx = bx0 + x, gy = by0 + y, gz = bz0 + z;
-        if (gx < g.n0 && gy < g.n1 && gz < g.n2)
-            k.store_cell(cell_index(g, gx, gy, gz), U[((z + R) * RW + (y + R)) * RW + (x + R)]);
+        if (gx < g.n0 && gy < g.n1 && gz < g.n2) {
+            const Cell v = U[((z + R) * RW + (y + R)) * RW + (x + R)];
+            const int64_t ii = cell_index(g, gx, gy, gz);
+            k.store_cell(ii, v);
+            if (GHOSTS) brick_store_ghosts(k, g, gx, gy, gz, ii, v);
+        }
     }
 }
 

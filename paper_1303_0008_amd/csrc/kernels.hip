@@ -33,6 +33,9 @@ struct SmoothArgs {
     const double* uc;     // null: no prolongation
     const double* oc;
     int zc, tiles_x, tiles_y;
+    // Dirichlet bricks below the finest level: reference of the ghost refresh
+    // (null: the ghost shell of pout is left to a separate refresh)
+    const double* gref;
 };
 
 // FP64 smoother policy of the fused sweep: cells hold phi, sources are delta
@@ -57,9 +60,10 @@ struct SmoothK {
     Geom gc;                     // folded prolongation: coarse level and its phi^H, phi^H_old
     const double* __restrict__ uc;
     const double* __restrict__ oc;
+    const double* __restrict__ gref;
 
     __device__ SmoothK(const SmoothArgs& a, const Geom& g, bool periodic)
-        : pin(a.pin), pout(a.pout), delta(a.delta), f(a.f), c(a.c), gc(a.gc), uc(a.uc), oc(a.oc) {
+        : pin(a.pin), pout(a.pout), delta(a.delta), f(a.f), c(a.c), gc(a.gc), uc(a.uc), oc(a.oc), gref(a.gref) {
         const double h2 = g.h * g.h;
         inv_h4 = 1.0 / (h2 * h2);
         h2_6 = h2 * (1.0 / 6.0);
@@ -123,6 +127,10 @@ struct SmoothK {
     }
     __device__ void store_cell(int64_t i, double v) const { pout[i] = v; }
     __device__ double load_corr(int64_t i) const { return uc[i] - oc[i]; }
+    // ghost gi mirrored at interior element ii (sign s) after that cell became v
+    __device__ void store_ghost(int64_t gi, int64_t ii, int s, double v) const {
+        pout[gi] = gref[gi] + (double)s * (v - gref[ii]);
+    }
 };
 
 // PRO: the sweep starts from pin + P(uc - oc), the coarse correction prolonged
@@ -162,7 +170,7 @@ __global__ void __launch_bounds__(BRICK_THREADS, (S == 2 && PRO) ? 2 : BRICK_WAV
 // One sweep of every Dirichlet grid of a batch at one level on BB^3 bricks:
 // items[it] = (grid, brick x, brick y, brick z) of a persistent work list; the
 // ghost shell is the boundary (brick_sweeps, DIR = 1).
-template <bool HAS_F>
+template <bool HAS_F, bool GHOSTS>
 __global__ void __launch_bounds__(BRICK_THREADS, BRICK_WAVES) k_smooth_brick_batch(SmoothArgs proto,
                                                                                    const Geom* __restrict__ geoms,
                                                                                    const int4* __restrict__ items,
@@ -172,7 +180,7 @@ __global__ void __launch_bounds__(BRICK_THREADS, BRICK_WAVES) k_smooth_brick_bat
         SmoothArgs a = proto;
         a.g = geoms[w.x];
         const SmoothK<HAS_F> k(a, a.g, false);
-        brick_sweeps<1, false, 1>(k, a.g, w.y * BB, w.z * BB, w.w * BB);
+        brick_sweeps<1, false, 1, GHOSTS>(k, a.g, w.y * BB, w.z * BB, w.w * BB);
         __syncthreads();   // the next item's staging overwrites the LDS
     }
 }
@@ -1497,10 +1505,14 @@ hipError_t launch_smooth_batch(const SmoothArgs& proto, const Geom* geoms, const
     if (nitems <= 0) return hipSuccess;
     const int nb = std::min(nitems, max_blocks);
     if (cfg.pipe == PIPE_BRICK) {
-        if (proto.f) hipLaunchKernelGGL((k_smooth_brick_batch<true>), dim3(nb), dim3(BRICK_THREADS), 0, s, proto, geoms, items, nitems);
-        else hipLaunchKernelGGL((k_smooth_brick_batch<false>), dim3(nb), dim3(BRICK_THREADS), 0, s, proto, geoms, items, nitems);
+        const dim3 g(nb), t(BRICK_THREADS);
+        if (proto.f && proto.gref) hipLaunchKernelGGL((k_smooth_brick_batch<true, true>), g, t, 0, s, proto, geoms, items, nitems);
+        else if (proto.f) hipLaunchKernelGGL((k_smooth_brick_batch<true, false>), g, t, 0, s, proto, geoms, items, nitems);
+        else if (proto.gref) hipLaunchKernelGGL((k_smooth_brick_batch<false, true>), g, t, 0, s, proto, geoms, items, nitems);
+        else hipLaunchKernelGGL((k_smooth_brick_batch<false, false>), g, t, 0, s, proto, geoms, items, nitems);
         return hipGetLastError();
     }
+    if (proto.gref) return hipErrorInvalidValue;   // the march leaves the ghosts to a separate refresh
     const bool d = cfg.pipe != 0;
     if (cfg.ty == 4) smooth_batch_ty<4>(proto, geoms, items, nitems, nb, d, s);
     else if (cfg.ty == 16) smooth_batch_ty<16>(proto, geoms, items, nitems, nb, d, s);
@@ -1511,10 +1523,10 @@ hipError_t launch_smooth_batch(const SmoothArgs& proto, const Geom* geoms, const
 
 hipError_t launch_smooth_batch_args(const Coef& c, const double* pin, double* pout, const double* delta,
                                     const double* f, SmoothCfg cfg, const Geom* geoms, const int4* items,
-                                    int nitems, int max_blocks, hipStream_t s) {
+                                    int nitems, int max_blocks, hipStream_t s, const double* gref) {
     SmoothArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.c = c; a.pin = pin; a.pout = pout; a.delta = delta; a.f = f; a.sc = nullptr;
+    a.c = c; a.pin = pin; a.pout = pout; a.delta = delta; a.f = f; a.sc = nullptr; a.gref = gref;
     a.zc = cfg.zc > 0 ? cfg.zc : 16;
     return launch_smooth_batch(a, geoms, items, nitems, cfg, max_blocks, s);
 }

@@ -39,6 +39,9 @@ struct CorrArgs {
     const float* uc;          // null: no prolongation
     const float* oc;
     int zc, tiles_x, tiles_y;
+    // Dirichlet bricks below the finest level: reference of the ghost refresh
+    // (null: the ghost shell of eout is left to a separate refresh)
+    const float* gref;
 };
 
 // FP32 correction policy of the fused sweep (brick.h): a cell holds (e, phi~),
@@ -62,9 +65,11 @@ struct CorrK {
     Geom gc;            // folded prolongation: coarse level and its e^H, e^H_old
     const float* __restrict__ uc;
     const float* __restrict__ oc;
+    const float* __restrict__ gref;
 
     __device__ CorrK(const CorrArgs& a, bool periodic)
-        : ein(a.ein), eout(a.eout), pt(a.pt), t0(a.t0), r(a.r), c(a.c), gc(a.gc), uc(a.uc), oc(a.oc) {
+        : ein(a.ein), eout(a.eout), pt(a.pt), t0(a.t0), r(a.r), c(a.c), gc(a.gc), uc(a.uc), oc(a.oc),
+          gref(a.gref) {
         h2_6 = c.h2 * (1.0f / 6.0f);
         cb_6 = periodic ? h2_6 * (float)a.sc->cbar : 0.0f;
     }
@@ -113,6 +118,10 @@ struct CorrK {
     __device__ Src load_src(int64_t i) const { return Src{t0[i], r[i]}; }
     __device__ void store_cell(int64_t i, float2 v) const { eout[i] = v.x; }
     __device__ float load_corr(int64_t i) const { return uc[i] - oc[i]; }
+    // ghost gi mirrored at interior element ii (sign s) after that cell became v
+    __device__ void store_ghost(int64_t gi, int64_t ii, int s, float2 v) const {
+        eout[gi] = gref[gi] + (float)s * (v.x - gref[ii]);
+    }
     __device__ float2 update_nb(const NbT<float2>& v, float2 centre, const Src& s) const {
         NbT<float> ve, vp;
 #define VMG_SPLIT(m) ve.m = v.m.x; vp.m = v.m.y;
@@ -175,6 +184,7 @@ __global__ void __launch_bounds__(sweep_threads(TY), sweep_waves(TY, DEFER)) k_s
 
 // one sweep of every grid of a Dirichlet batch at one level on BB^3 bricks
 // (items: grid, brick x, brick y, brick z)
+template <bool GHOSTS>
 __global__ void __launch_bounds__(BRICK_THREADS, BRICK_WAVES) k_smooth_corr_brick_batch(CorrArgs proto,
                                                                                         const Geom* __restrict__ geoms,
                                                                                         const int4* __restrict__ items,
@@ -186,7 +196,7 @@ __global__ void __launch_bounds__(BRICK_THREADS, BRICK_WAVES) k_smooth_corr_bric
         a.c.a_ih4 = proto.c.alpha / (float)(a.g.h * a.g.h * a.g.h * a.g.h);
         a.c.h2 = (float)(a.g.h * a.g.h);
         const CorrK<false> k(a, false);
-        brick_sweeps<1, false, 1>(k, a.g, w.y * BB, w.z * BB, w.w * BB);
+        brick_sweeps<1, false, 1, GHOSTS>(k, a.g, w.y * BB, w.z * BB, w.w * BB);
         __syncthreads();   // the next item's staging overwrites the LDS
     }
 }
@@ -1287,7 +1297,7 @@ hipError_t launch_cast_all(const double* src, float* dst, int64_t n, hipStream_t
 // ---- batched launchers (Dirichlet batches) -------------------------------------
 hipError_t launch_smooth_corr_batch(const CoefF& c, const float* ein, float* eout, const float* pt, const float* t0,
                                     const float* r, SmoothCfg cfg, const Geom* geoms, const int4* items, int nitems,
-                                    int max_blocks, hipStream_t s) {
+                                    int max_blocks, hipStream_t s, const float* gref) {
     if (nitems <= 0) return hipSuccess;
     CorrArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -1295,9 +1305,12 @@ hipError_t launch_smooth_corr_batch(const CoefF& c, const float* ein, float* eou
     a.zc = cfg.zc > 0 ? cfg.zc : 16;
     const dim3 nb(std::min(nitems, max_blocks));
     if (cfg.pipe == PIPE_BRICK) {
-        hipLaunchKernelGGL(k_smooth_corr_brick_batch, nb, dim3(BRICK_THREADS), 0, s, a, geoms, items, nitems);
+        a.gref = gref;
+        if (gref) hipLaunchKernelGGL((k_smooth_corr_brick_batch<true>), nb, dim3(BRICK_THREADS), 0, s, a, geoms, items, nitems);
+        else hipLaunchKernelGGL((k_smooth_corr_brick_batch<false>), nb, dim3(BRICK_THREADS), 0, s, a, geoms, items, nitems);
         return hipGetLastError();
     }
+    if (gref) return hipErrorInvalidValue;   // the march leaves the ghosts to a separate refresh
     const bool d = cfg.pipe != 0;
 #define VMG_CORR_BATCH(T)                                                                                   \
     do {                                                                                                   \

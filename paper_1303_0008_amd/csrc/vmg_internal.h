@@ -270,9 +270,11 @@ hipError_t launch_cast_all(const double* src, float* dst, int64_t n, hipStream_t
 
 // ---- batched Dirichlet launchers (one launch per level for every grid) ------
 struct SmoothArgs;
+// one sweep of every grid of a batched level; gref (brick schedule only, levels
+// below the finest): refresh pout's ghost shell against this reference as well
 hipError_t launch_smooth_batch_args(const Coef& c, const double* pin, double* pout, const double* delta,
                                     const double* f, SmoothCfg cfg, const Geom* geoms, const int4* items,
-                                    int nitems, int max_blocks, hipStream_t s);
+                                    int nitems, int max_blocks, hipStream_t s, const double* gref = nullptr);
 // items: the coarse level's cells; also sets the coarse ghost shell of phic to phiold_c's
 hipError_t launch_rr_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, const Coef& c,
                            const double* phi, const double* delta, const double* f, double* phic,
@@ -314,7 +316,7 @@ hipError_t launch_check_finite_batch(const Geom* gs, const int64_t* uoff, const 
                                      const double* src, double* partials, hipStream_t s);
 hipError_t launch_smooth_corr_batch(const CoefF& c, const float* ein, float* eout, const float* pt, const float* t0,
                                     const float* r, SmoothCfg cfg, const Geom* geoms, const int4* items, int nitems,
-                                    int max_blocks, hipStream_t s);
+                                    int max_blocks, hipStream_t s, const float* gref = nullptr);
 // items: the coarse level's cells; also sets the coarse ghost shell of ec to eold_c's
 hipError_t launch_rr_corr_batch(const Geom* gfs, const Geom* gcs, const int2* items, int nitems, const CoefF& c,
                                 const float* e, const float* pt, const float* t0, const float* r, float* ec,
