@@ -272,15 +272,14 @@ def time_tau_rule(torch, V, delta, w, stream, steps):
             "tau_rms": r["tau_rms"]}
 
 
-def time_levels(torch, V, delta_np, w, steps):
-    """vmg_levels_solve on the workload's domain grid with 8 first-level 64^3
-    refinements at h = 1/512 centred on the 8 densest cells at least 40 cells
-    apart (so the refinements do not overlap) and a 64^3 second level at
-    h = 1/1024 in the middle of each (mixed precision, tol as the workload).
-    Each refinement's density is the cloud-in-cell assignment of the
-    workload's particles onto it (vmg_mass_assign_region), the recipe of the
-    domain grid at the finer spacing.  Wall time per vmg_levels_solve on a plan
-    created beforehand; the assignment of all 16 refinements is timed apart."""
+def levels_inputs(torch, V, delta_np, w):
+    """Grids, nests and densities of the multilevel workload: the domain grid with 8
+    first-level 64^3 refinements at h = 1/512 centred on the 8 densest cells at
+    least 40 cells apart (so the refinements do not overlap) and a 64^3 second
+    level at h = 1/1024 in the middle of each.  Each refinement's density is the
+    cloud-in-cell assignment of the workload's particles onto it
+    (vmg_mass_assign_region), the recipe of the domain grid at the finer spacing;
+    assign_all() (re)computes those densities in d."""
     import numpy as np
     from paper_1303_0008_amd import inputs as I
     n = w["n"]
@@ -296,7 +295,7 @@ def time_levels(torch, V, delta_np, w, steps):
     pos = torch.from_numpy(pos_np).to("cuda")
     grids = [V.make_grid(n)]
     nests = [V.make_nest(-1)]
-    regions = []                       # (offset, h, corner) of each refinement
+    regions = []                       # (offset, h, corner, origin) of each refinement
     off, goff = delta_np.size, 0
     corners = {}
     for lev, h in ((1, 1.0 / (2 * n)), (2, 1.0 / (4 * n))):
@@ -308,7 +307,7 @@ def time_levels(torch, V, delta_np, w, steps):
             corners[len(grids)] = corner
             grids.append(V.make_grid(64, h, V.DIRICHLET, off, goff))
             nests.append(V.make_nest(parent, origin))
-            regions.append((off, h, corner))
+            regions.append((off, h, corner, origin))
             off += 64 ** 3
             goff += V.ghost_count(64)
     d = torch.empty(off, dtype=torch.float64, device="cuda")
@@ -316,18 +315,52 @@ def time_levels(torch, V, delta_np, w, steps):
     work = torch.empty(V.mass_assign_workspace(pos_np.shape[0], 64), dtype=torch.uint8, device="cuda")
 
     def assign_all():
-        for o, h, corner in regions:
+        for o, h, corner, _ in regions:
             V.mass_assign_region(pos, 64, h, corner, pos_np.shape[0] * h ** 3, V.ASSIGN_CIC,
                                  delta=d[o:o + 64 ** 3].view(64, 64, 64), workspace=work)
 
+    return grids, nests, d, goff, regions, assign_all
+
+
+def levels_refinement_inputs(torch, V, delta_np, w):
+    """The 8 first-level refinements of the multilevel workload as one Dirichlet
+    batch, with boundary values and initial guess interpolated from the domain
+    grid's FP64 solution (what vmg_levels_solve hands them): the input of the
+    cycle tuner for the refinement plans."""
+    n = w["n"]
+    grids, nests, d, goff, regions, assign_all = levels_inputs(torch, V, delta_np, w)
+    assign_all()
+    parent_phi, _ = V.solve_field(d[:n ** 3].view(n, n, n), w["alpha"], w["kappa"], tol=1e-10, max_cycles=60)
+    first = [r for r in regions if abs(r[1] - 1.0 / (2 * n)) < 1e-15]
+    sub, origins = [], []
+    for k, (o, h, _, origin) in enumerate(first):
+        sub.append(V.make_grid(64, h, V.DIRICHLET, k * 64 ** 3, k * V.ghost_count(64)))
+        origins.append(origin)
+    dt = torch.cat([d[o:o + 64 ** 3] for o, _, _, _ in first])
+    ghost = torch.zeros(len(first) * V.ghost_count(64), dtype=torch.float64, device="cuda")
+    V.fill_ghosts(parent_phi, 1.0 / n, sub, origins, ghost)
+    guess = torch.zeros_like(dt)
+    V.fill_interior(parent_phi, 1.0 / n, sub, origins, guess)
+    torch.cuda.synchronize()
+    return sub, dt, ghost, guess
+
+
+def time_levels(torch, V, delta_np, w, steps):
+    """vmg_levels_solve on the multilevel workload (levels_inputs), mixed
+    precision, tol as the workload, tuned schedules (VMG_AUTOTUNE: the domain grid
+    and the refinement batches take their cached sweep and cycle schedules).  Wall
+    time per vmg_levels_solve on a plan created beforehand; the assignment of all
+    16 refinement densities is timed apart."""
+    grids, nests, d, goff, regions, assign_all = levels_inputs(torch, V, delta_np, w)
     assign_all()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     assign_all()
     torch.cuda.synchronize()
     assign_ms = 1e3 * (time.perf_counter() - t0)
+    off = d.numel()
     ghost = torch.zeros(goff, dtype=torch.float64, device="cuda")
-    params = V.make_params(w["alpha"], w["kappa"], w["tol"], 100, V.MIXED, flags=V.GRAPH)
+    params = V.make_params(w["alpha"], w["kappa"], w["tol"], 100, V.MIXED, flags=V.GRAPH | V.AUTOTUNE)
     phis = [torch.zeros_like(d) for _ in range(steps + 1)]
     with V.LevelsPlan(grids, nests, params) as L:
         L.solve(d, ghost, phis[0])
@@ -338,11 +371,13 @@ def time_levels(torch, V, delta_np, w, steps):
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t0) / steps
     log(f"levels: {ms:.2f} ms per multilevel solve ({len(grids)} grids, {off} cells), "
-        f"max rms {max(r['rms'] for r in res):.2e}; refinement densities assigned in {assign_ms:.2f} ms")
+        f"max rms {max(r['rms'] for r in res):.2e}, cycles {[r['cycles'] for r in res][:2]}...; "
+        f"refinement densities assigned in {assign_ms:.2f} ms")
     return {"ms_per_solve": ms, "grids": len(grids), "cells": off, "max_rms": max(r["rms"] for r in res),
             "cycles": [r["cycles"] for r in res], "refinement_assign_ms": assign_ms,
-            "note": "vmg_levels_solve on a plan created beforehand, from phi = 0, mixed precision; refinement "
-                    "densities by cloud-in-cell region assignment of the workload's particles"}
+            "note": "vmg_levels_solve on a plan created beforehand (tuned schedules), from phi = 0, mixed "
+                    "precision; refinement densities by cloud-in-cell region assignment of the workload's "
+                    "particles"}
 
 
 def oracle_cycle_updates(n, nu=4, ncoarse=60):
@@ -531,6 +566,10 @@ def retune(torch, V, I, stream, path):
     grids, dt_p, ghost, guess = patches96_inputs(torch, V, I)
     for prec in (V.FP64, V.MIXED):
         jobs.append(("patches96", grids, dict(I.WORKLOADS["patches96"]), prec, dt_p, ghost, guess))
+    # the refinement batches of the multilevel solve (both depths share the key)
+    wz = dict(I.WORKLOADS["zeldovich256"])
+    sub, dt_r, ghost_r, guess_r = levels_refinement_inputs(torch, V, I.workload_delta("zeldovich256"), wz)
+    jobs.append(("levels refinements", sub, wz, V.MIXED, dt_r, ghost_r, guess_r))
     for name, grids, w, prec, d, gh, g0 in jobs:
         params = V.make_params(w["alpha"], w["kappa"], w["tol"], 100, prec, flags=V.GRAPH | V.AUTOTUNE)
         with V.Plan(grids, params, stream=stream) as plan:
