@@ -81,14 +81,14 @@ def load_traffic(name, kernel):
 
 
 def time_solves(torch, V, delta, w, prec, steps, warmup, flags, stream, tau_factor=0.0, grids=None, ghost=None,
-                phi0=None, time_sweeps=False):
+                phi0=None, time_sweeps=False, max_cycles=100):
     """Solve the same input `steps` times after `warmup` untimed solves; wall time
     over the timed solves (bracketed by device synchronisation).  With
     time_sweeps, the library times every finest-level sweep of the timed solves
     with HIP events on the plan's stream.  Returns (plan, infos, cell updates,
     seconds, last phi, (summed sweep us, sweep launches))."""
     grids = grids or [V.make_grid(w["n"])]
-    params = V.make_params(w["alpha"], w["kappa"], w["tol"], 100, prec, flags=flags, tau_factor=tau_factor)
+    params = V.make_params(w["alpha"], w["kappa"], w["tol"], max_cycles, prec, flags=flags, tau_factor=tau_factor)
     plan = V.Plan(grids, params, stream=stream)
     # every solve starts from its own resident copy of the initial guess
     phis = [torch.zeros_like(delta) if phi0 is None else phi0.clone() for _ in range(steps + warmup)]
@@ -516,26 +516,21 @@ def other_configs(torch, V, I, stream, steps):
     for name, alpha in (("lognormal512a", 0.2), ("lognormal512b", -0.2)):
         w = dict(I.WORKLOADS[name])
         for pn, prec, bpc in (("mixed", V.MIXED, 20), ("fp64", V.FP64, 24)):
-            if name == "lognormal512b":
-                params = V.make_params(w["alpha"], w["kappa"], w["tol"], 30, prec, flags=flags)
-                phi = torch.zeros_like(d512)
-                with torch.cuda.stream(stream):
-                    with V.Plan([V.make_grid(512)], params, stream=stream) as plan:
-                        torch.cuda.synchronize()
-                        t0 = time.perf_counter()
-                        r = plan.solve(d512, phi, allow_noconv=True)[0]
-                        torch.cuda.synchronize()
-                        ms = 1e3 * (time.perf_counter() - t0)
-                res[f"{name}_{pn}"] = {"status": V.STATUS_NAMES[r["status"]], "rms": r["rms"], "cycles": r["cycles"],
-                                       "n_guarded": r["n_guarded"], "ms": ms, "max_cycles": 30}
-                log(f"{name} {pn}: {V.STATUS_NAMES[r['status']]}, rms {r['rms']:.2e} after {r['cycles']} "
-                    f"iterations ({ms:.0f} ms), {r['n_guarded']} guarded cells")
-                del phi
+            # the guarded configuration (alpha < 0) under-relaxes its kink cells and
+            # takes several times the iterations of the other
+            mc = 100 if alpha > 0 else 250
+            try:
+                plan, infos, upd, dt, _, _ = time_solves(torch, V, d512, w, prec, max(2, steps // 4), 1, flags, stream,
+                                                         max_cycles=mc)
+            except V.VmgError as e:   # reported, not fatal: the other lines still print
+                res[f"{name}_{pn}"] = {"status": "error", "error": str(e), "max_cycles": mc}
+                log(f"{name} {pn}: {e}")
+                torch.cuda.synchronize()
                 continue
-            plan, infos, upd, dt, _, _ = time_solves(torch, V, d512, w, prec, max(2, steps // 4), 1, flags, stream)
             plan.close()
             torch.cuda.empty_cache()
-            plan, _, _, _, _, sw = time_solves(torch, V, d512, w, prec, 2, 0, flags, stream, time_sweeps=True)
+            plan, _, _, _, _, sw = time_solves(torch, V, d512, w, prec, 2, 0, flags, stream, time_sweeps=True,
+                                               max_cycles=mc)
             ty, zc, pipe = plan.schedule(0)
             plan.close()
             kern = finest_kernel(pn, ty, pipe)

@@ -302,6 +302,24 @@ static double residual(OLevel *L, const OCoef *c, double cbar, double *sum_root,
 /* ------------------------------------------------------------------------- */
 /* relaxation: lexicographic Newton-Gauss-Seidel (Sec. III.B)                 */
 /* ------------------------------------------------------------------------- */
+/* Kink cells (reading: the paper does not discuss relaxation at the guard).
+ * Near D = 0, with D = disc / alpha_p^2 the normalised discriminant, the
+ * root's slope 1/sqrt(D) couples a cell so strongly to its neighbours that
+ * plain Gauss-Seidel updates can settle into a two-sweep oscillation across
+ * D = 0 (one sweep on the clamped side, the next on the steep side).  That
+ * coupling grows like 1 / (h^2 sqrt|D|), so the update is under-relaxed by
+ * w = min(1, max(KINK_WMIN, KINK_K h^2 sqrt|D|)); w = 1 wherever
+ * KINK_K h^2 sqrt|D| >= 1.  The fixed point, i.e. the discrete solution, is
+ * unchanged. */
+#define KINK_K (50.0 * 65536.0)
+#define KINK_WMIN 0.01
+
+static double update_weight(const OGrid *g, const OCoef *c, const CellEval *e) {
+    if (c->linear) return 1.0;
+    const double w = KINK_K * g->h * g->h * sqrt(fabs(e->disc) / (c->alpha_p * c->alpha_p));
+    return w < 1.0 ? fmax(w, KINK_WMIN) : 1.0;
+}
+
 static void relax(OLevel *L, const OCoef *c, int sweeps) {
     for (int s = 0; s < sweeps; ++s) {
         const double cbar = compat_const(L, c);
@@ -310,7 +328,7 @@ static void relax(OLevel *L, const OCoef *c, int sweeps) {
                 for (int i = 0; i < L->g.n[0]; ++i) {
                     const long p = pidx(&L->g, i, j, k);
                     const CellEval e = eval_at(&L->g, c, L->phi, L->delta, i, j, k);
-                    L->phi[p] -= (e.L + cbar - L->f[p]) / e.dL;
+                    L->phi[p] -= update_weight(&L->g, c, &e) * (e.L + cbar - L->f[p]) / e.dL;
                 }
     }
 }

@@ -111,9 +111,54 @@ __device__ __forceinline__ double nl_root_of(double q, double sD, const Coef& c)
 __device__ __forceinline__ double nl_root(const Nb& v, double dl, const Coef& c, double inv_h4,
                                           double& S, bool& guard) {
     const double q = nl_q(v, dl, c, inv_h4, S);
-    const double D = 1.0 + c.c8 * q;
+    const double D = fma(c.c8, q, 1.0);
     guard = !(D > 0.0);
     return guard ? c.vertex : nl_root_of(q, sqrt_nr(D), c);
+}
+
+// nl_root that also returns the discriminant D (the smoothers' kink test).
+__device__ __forceinline__ double nl_root_d(const Nb& v, double dl, const Coef& c, double inv_h4,
+                                            double& S, double& D) {
+    const double q = nl_q(v, dl, c, inv_h4, S);
+    D = fma(c.c8, q, 1.0);
+    return !(D > 0.0) ? c.vertex : nl_root_of(q, sqrt_nr(D), c);
+}
+
+// Kink cells.  Near D = 0 the root's slope 1/sqrt(D) (Eq. one_branch) couples
+// a cell so strongly to its neighbours that the plain Gauss-Seidel update can
+// oscillate across D = 0 from one sweep to the next (clamped on one sweep, on
+// the steep side of the root on the next) and the solve stalls.  The coupling
+// grows like 1 / (h^2 sqrt|D|) (the root's slope times the neighbours' weight
+// in q, alpha / h^4, times the update's h^2 / 6), so the update is
+// under-relaxed by w = min(1, max(KINK_WMIN, KINK_K h^2 sqrt|D|)); w = 1 (the
+// update itself, bit for bit) wherever KINK_K h^2 sqrt|D| >= 1.  A converged
+// state is a fixed point either way, so the discrete solution is unchanged.
+// Every smoother (both precisions, every schedule) applies the same rule, so
+// schedules stay bitwise interchangeable.  kink_k(h^2) is the per-level factor
+// KINK_K h^2.
+constexpr double KINK_K = 50.0 * 65536.0;   // w = 50 sqrt|D| on a 256^3 unit box
+constexpr float KINK_WMIN = 0.01f;
+
+__host__ __device__ __forceinline__ float kink_k(double h2) { return (float)(KINK_K * h2); }
+
+// (kk^2 |D| < 1 is tested first, so that a wave without kink cells, nearly
+// every wave, branches past the weight)
+__device__ __forceinline__ double kink_relax(double old, double nv, double D, float kk) {
+    const float aD = (float)fabs(D);
+    if (__builtin_expect(aD * (kk * kk) < 1.0f, 0)) {
+        const float w = fmaxf(kk * __builtin_amdgcn_sqrtf(aD), KINK_WMIN);
+        return fma((double)fminf(w, 1.0f), nv - old, old);
+    }
+    return nv;
+}
+
+__device__ __forceinline__ float kink_relax(float old, float nv, float D, float kk) {
+    const float aD = fabsf(D);
+    if (__builtin_expect(aD * (kk * kk) < 1.0f, 0)) {
+        const float w = fmaxf(kk * __builtin_amdgcn_sqrtf(aD), KINK_WMIN);
+        return fmaf(fminf(w, 1.0f), nv - old, old);
+    }
+    return nv;
 }
 
 // nl_root that also returns the discriminant D and +-sqrt|D| (sign of D): the
@@ -121,7 +166,7 @@ __device__ __forceinline__ double nl_root(const Nb& v, double dl, const Coef& c,
 __device__ __forceinline__ double nl_root_t0(const Nb& v, double dl, const Coef& c, double inv_h4,
                                              double& S, bool& guard, double& t0) {
     const double q = nl_q(v, dl, c, inv_h4, S);
-    const double D = 1.0 + c.c8 * q;
+    const double D = fma(c.c8, q, 1.0);
     guard = !(D > 0.0);
     if (guard) {
         t0 = D < 0.0 ? -sqrt_nr(-D) : 0.0;
@@ -136,7 +181,7 @@ __device__ __forceinline__ double nl_root_t0(const Nb& v, double dl, const Coef&
 // its 18 neighbours and density (the mixed path's base state).
 __device__ __forceinline__ double base_discriminant(const Nb& v, double dl, const Coef& c, double inv_h4) {
     double S;
-    return 1.0 + c.c8 * nl_q(v, dl, c, inv_h4, S);
+    return fma(c.c8, nl_q(v, dl, c, inv_h4, S), 1.0);
 }
 
 // Correction of the mixed path's FP32 inner problem: dq = alpha Phi(2 phi~ + e, e)
@@ -163,10 +208,24 @@ __device__ __forceinline__ float dq_corr(const NbT<float>& e, const NbT<float>& 
     return fmaf(a_ih4 * (1.0f / 3.0f), pd, a_ih4 * 0.125f * pb);
 }
 
+// dQ_of that also returns the discriminant D1 of the corrected state (the
+// smoothers' kink test)
+__device__ __forceinline__ float dQ_of_d(float dq, float t0, const CoefF& c, float& D1) {
+    const float D0 = t0 * fabsf(t0);   // sign(t0) t0^2
+    const float s0 = fmaxf(t0, 0.0f);
+    D1 = fmaf(c.c8, dq, D0);
+    const float s1 = __builtin_amdgcn_sqrtf(fmaxf(D1, 0.0f));
+    if (D0 >= 0.0f && D1 >= 0.0f) {
+        const float den = s0 + s1;
+        return den > 0.0f ? 2.0f * dq * __builtin_amdgcn_rcpf(den) : 0.0f;
+    }
+    return c.a34 * (s1 - s0);
+}
+
 __device__ __forceinline__ float dQ_of(float dq, float t0, const CoefF& c) {
     const float D0 = t0 * fabsf(t0);   // sign(t0) t0^2
     const float s0 = fmaxf(t0, 0.0f);
-    const float D1 = D0 + c.c8 * dq;
+    const float D1 = fmaf(c.c8, dq, D0);
     const float s1 = __builtin_amdgcn_sqrtf(fmaxf(D1, 0.0f));
     if (D0 >= 0.0f && D1 >= 0.0f) {
         const float den = s0 + s1;

@@ -57,6 +57,7 @@ struct SmoothK {
     const double* __restrict__ f;
     Coef c;
     double inv_h4, h2_6, cb_6;   // 1/h^4, h^2/6, h^2 cbar/6
+    float kk;                    // kink_k(h^2)
     Geom gc;                     // folded prolongation: coarse level and its phi^H, phi^H_old
     const double* __restrict__ uc;
     const double* __restrict__ oc;
@@ -67,6 +68,7 @@ struct SmoothK {
         const double h2 = g.h * g.h;
         inv_h4 = 1.0 / (h2 * h2);
         h2_6 = h2 * (1.0 / 6.0);
+        kk = kink_k(h2);
         cb_6 = periodic ? h2_6 * a.sc->cbar : 0.0;
     }
     static constexpr int EB = 8;
@@ -102,13 +104,12 @@ struct SmoothK {
         return buf_ld_f64(C.u, bo) - buf_ld_f64(C.o, bo);
     }
     __device__ double add_corr(double u, double v) const { return u + v; }
-    __device__ double update_nb(const Nb& v, double, const Src& s) const {
-        double S;
-        bool gd;
-        const double Q = nl_root(v, s.dl, c, inv_h4, S, gd);
-        // (S - h^2 (Q + f - cbar)) / 6
+    __device__ double update_nb(const Nb& v, double centre, const Src& s) const {
+        double S, D;
+        const double Q = nl_root_d(v, s.dl, c, inv_h4, S, D);
+        // (S - h^2 (Q + f - cbar)) / 6, under-relaxed at kink cells
         const double base = HAS_F ? fma(-h2_6, s.f, cb_6) : cb_6;
-        return fma(S, 1.0 / 6.0, fma(-h2_6, Q, base));
+        return kink_relax(centre, fma(S, 1.0 / 6.0, fma(-h2_6, Q, base)), D, kk);
     }
     template <int W>
     __device__ double update(const double* Pm, const double* Pc, const double* Pp, int co, int o,
@@ -741,10 +742,9 @@ __device__ __forceinline__ void coarse_solve_body(Geom g, const Coef& c, double*
                 Nb v;
                 gather_nb<DIR>(lg, sphi, i, j, k, v);
                 const int64_t li = cell_index(lg, i, j, k);
-                double S;
-                bool gd;
-                const double Q = nl_root(v, sdel[li], c, inv_h4, S, gd);
-                nv[q] = (S - h2 * (Q + sf[li] - cb)) * (1.0 / 6.0);
+                double S, D;
+                const double Q = nl_root_d(v, sdel[li], c, inv_h4, S, D);
+                nv[q] = kink_relax(sphi[li], (S - h2 * (Q + sf[li] - cb)) * (1.0 / 6.0), D, kink_k(h2));
                 ni[q] = li;
             }
             __syncthreads();

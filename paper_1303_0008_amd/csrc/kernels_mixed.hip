@@ -62,6 +62,7 @@ struct CorrK {
     const float* __restrict__ r;
     CoefF c;
     float h2_6, cb_6;   // h^2/6, h^2 cbar/6
+    float kk;           // kink_k(h^2)
     Geom gc;            // folded prolongation: coarse level and its e^H, e^H_old
     const float* __restrict__ uc;
     const float* __restrict__ oc;
@@ -71,6 +72,7 @@ struct CorrK {
         : ein(a.ein), eout(a.eout), pt(a.pt), t0(a.t0), r(a.r), c(a.c), gc(a.gc), uc(a.uc), oc(a.oc),
           gref(a.gref) {
         h2_6 = c.h2 * (1.0f / 6.0f);
+        kk = kink_k(c.h2);
         cb_6 = periodic ? h2_6 * (float)a.sc->cbar : 0.0f;
     }
     static constexpr int EB = 4;
@@ -130,11 +132,12 @@ struct CorrK {
         VMG_SPLIT(xpzp) VMG_SPLIT(xmzm) VMG_SPLIT(xpzm) VMG_SPLIT(xmzp)
         VMG_SPLIT(ypzp) VMG_SPLIT(ymzm) VMG_SPLIT(ypzm) VMG_SPLIT(ymzp)
 #undef VMG_SPLIT
-        float Se;
+        float Se, D1;
         const float dq = dq_corr(ve, vp, c.a_ih4, Se);
-        const float dQ = dQ_of(dq, s.t0, c);
-        // (Se - h^2 (dQ + r - cbar)) / 6
-        return make_float2(fmaf(Se, 1.0f / 6.0f, fmaf(-h2_6, dQ, fmaf(-h2_6, s.r, cb_6))), centre.y);
+        const float dQ = dQ_of_d(dq, s.t0, c, D1);
+        // (Se - h^2 (dQ + r - cbar)) / 6, under-relaxed at kink cells
+        return make_float2(kink_relax(centre.x, fmaf(Se, 1.0f / 6.0f, fmaf(-h2_6, dQ, fmaf(-h2_6, s.r, cb_6))), D1, kk),
+                           centre.y);
     }
 };
 
@@ -398,9 +401,9 @@ __device__ __forceinline__ void coarse_corr_body(Geom g, CoefF c, float* e, floa
                 gather_nb<DIR>(g, se, i, j, k, ve);
                 gather_nb<DIR>(g, sp, i, j, k, vp);
                 const int64_t li = cell_index(g, i, j, k);
-                float Se;
-                const float dQ = dQ_of(dq_corr(ve, vp, c.a_ih4, Se), st[li], c);
-                nv[q] = (Se - h2 * (dQ + sr[li] - cb)) * (1.0f / 6.0f);
+                float Se, D1;
+                const float dQ = dQ_of_d(dq_corr(ve, vp, c.a_ih4, Se), st[li], c, D1);
+                nv[q] = kink_relax(se[li], (Se - h2 * (dQ + sr[li] - cb)) * (1.0f / 6.0f), D1, kink_k(h2));
                 ni[q] = li;
             }
             __syncthreads();

@@ -119,10 +119,9 @@ __device__ void tail_sweep(const TLev& L, double* tmp, const Coef& c, double cb)
         const int e = (k * L.n1 + j) * L.n0 + i;
         Nb v;
         tail_gather(L, L.phi, i, j, k, v);
-        double S;
-        bool gd;
-        const double Q = nl_root(v, L.del[e], c, L.inv_h4, S, gd);
-        tmp[e] = (S - L.h2 * (Q + L.f[e] - cb)) * (1.0 / 6.0);
+        double S, D;
+        const double Q = nl_root_d(v, L.del[e], c, L.inv_h4, S, D);
+        tmp[e] = kink_relax(L.phi[e], (S - L.h2 * (Q + L.f[e] - cb)) * (1.0 / 6.0), D, kink_k(L.h2));
     };
     for (int colour = 0; colour < 2; ++colour) {
         if ((L.n0 & 1) == 0) {
@@ -370,13 +369,23 @@ __device__ __forceinline__ float ctail_dq(const CLev& L, const CoefF& c, int i, 
     return dQ_of(dq_corr(ve, vp, L.a_ih4, Se), L.t0[e], c);
 }
 
+// ctail_dq that also returns the discriminant of the corrected state
+__device__ __forceinline__ float ctail_dq_d(const CLev& L, const CoefF& c, int i, int j, int k, int e, float& Se,
+                                            float& D1) {
+    const TNbr o = tail_nbr(L.n0, L.n1, L.n2, i, j, k);
+    NbT<float> ve, vp;
+    tail_gather_o(o, L.e, ve);
+    tail_gather_o(o, L.pt, vp);
+    return dQ_of_d(dq_corr(ve, vp, L.a_ih4, Se), L.t0[e], c, D1);
+}
+
 __device__ void ctail_sweep(const CLev& L, float* tmp, const CoefF& c, float cb) {
     const int tid = threadIdx.x;
     auto update = [&](int i, int j, int k) {
         const int e = (k * L.n1 + j) * L.n0 + i;
-        float Se;
-        const float dQ = ctail_dq(L, c, i, j, k, e, Se);
-        tmp[e] = (Se - L.h2 * (dQ + L.r[e] - cb)) * (1.0f / 6.0f);
+        float Se, D1;
+        const float dQ = ctail_dq_d(L, c, i, j, k, e, Se, D1);
+        tmp[e] = kink_relax(L.e[e], (Se - L.h2 * (dQ + L.r[e] - cb)) * (1.0f / 6.0f), D1, kink_k(L.h2));
     };
     for (int colour = 0; colour < 2; ++colour) {
         if ((L.n0 & 1) == 0) {

@@ -6,17 +6,22 @@ out of reach on the CPU).
 * alpha = 0.2: the solve reaches the tolerance; the GPU's residual field of
   the returned phi equals the oracle's cell by cell (within rounding), and its
   RMS and cbar agree with the reported ones; FP64 and mixed agree.
-* alpha = -0.2 (about 9 % of the cells take the discriminant guard): this
-  configuration does NOT meet its tolerance.  A discrete solution exists (a
-  Newton solve with one-sided derivatives converges on a cut-out around the
-  cells that keep the residual), but at these densities (max delta ~2200) the
-  closed-form Gauss-Seidel update oscillates with period 2 at ~160 cells next to
-  the guard boundary, where its sensitivity to a neighbour, ~1/sqrt(D), exceeds
-  one; the oracle's own Gauss-Seidel started from the stalled state does not
-  lower the residual either.  What is tested is the error path: the solver
-  reports VMG_ENOCONV with a finite state whose residual, cbar and guard count
-  the oracle confirms.  (The element-wise parity of the alpha = 0.2 run against
-  the oracle's solution is in test_gpu_config_errors.py.)
+* alpha = -0.2 (about 9 % of the cells take the discriminant guard, max delta
+  ~2200): a few hundred cells sit within 1e-4 of the guard boundary D = 0,
+  where the root's slope 1/sqrt(D) makes the plain Gauss-Seidel update
+  oscillate across D = 0 with period two; the smoothers under-relax those
+  cells by min(1, 50 (256 h)^2 sqrt|D|) (Eq. one_branch; a converged state is
+  a fixed point either way), and both precisions reach the tolerance.  Here
+  the discrete system is not uniquely solvable: at a kink cell the clamped
+  root and the steep branch can both close the equations, and the FP64 and
+  mixed solves settle on solutions that differ around a few such cells (by
+  1.3e-7 at one cell, 5e-5 of |phi|_inf, with the same difference when both
+  are driven to 1e-10).  So what is checked is what is unique: each returned
+  phi solves the oracle's discrete equations (its residual field, computed by
+  the oracle cell by cell, equals the GPU's and meets the tolerance; cbar and
+  the guard count agree), and the two solutions differ only locally.
+  (The element-wise parity of the alpha = 0.2 run against the oracle's
+  solution is in test_gpu_config_errors.py.)
 """
 import numpy as np
 import pytest
@@ -87,26 +92,47 @@ def test_lognormal512a_mixed(torch_cuda, V, oracle_mod):
     assert info["n_guarded"] == rm["n_guarded"] == 0
 
 
-def test_lognormal512b_unmet_tolerance_reports_noconv(torch_cuda, V, oracle_mod):
-    torch = torch_cuda
-    w = I.WORKLOADS["lognormal512b"]
-    say("lognormal512b: generate")
-    delta = I.workload_delta("lognormal512b")
-    d_t = torch.from_numpy(delta).to("cuda")
-    phi, r = _solve(torch, V, d_t, w, V.MIXED, 30)
-    say("  mixed", r)
-    assert r["status"] == V.VMG_ENOCONV
-    assert np.isfinite(r["rms"]) and w["tol"] < r["rms"] < 1e-3
-    assert 0.05 * delta.size < r["n_guarded"] < 0.15 * delta.size
-    ph = phi.cpu().numpy()
-    del phi
+def _check_solution(torch, V, oracle_mod, delta, d_t, ph, w, r, label):
+    """The oracle's residual field of ph equals the GPU's and meets the tolerance."""
     assert np.all(np.isfinite(ph))
-    say("  residual field of the returned phi: GPU vs oracle, cell by cell")
+    say(f"  residual field of the {label} phi: GPU vs oracle, cell by cell")
     phi_t = torch.from_numpy(ph).to("cuda")
     err, bound, dmax, rg, info = residual_fields(V, torch, oracle_mod, delta, d_t, phi_t, w["alpha"], w["kappa"])
     del phi_t
     say(f"  max |d_gpu - d_oracle| = {err:.2e} (bound {bound:.2e}, max |d| {dmax:.2e}); oracle {info}")
     assert err <= bound
+    assert info["rms"] <= w["tol"]
     assert abs(info["rms"] - r["rms"]) <= 1e-3 * r["rms"]
     assert abs(info["cbar"] - r["compat_c"]) <= 1e-9 * max(1.0, abs(info["cbar"]))
     assert abs(info["n_guarded"] - r["n_guarded"]) <= 1e-4 * r["n_guarded"]
+
+
+def test_lognormal512b_guarded_converges(torch_cuda, V, oracle_mod):
+    torch = torch_cuda
+    w = I.WORKLOADS["lognormal512b"]
+    say("lognormal512b: generate")
+    delta = I.workload_delta("lognormal512b")
+    d_t = torch.from_numpy(delta).to("cuda")
+    phi_m, rm = _solve(torch, V, d_t, w, V.MIXED, 160)
+    say("  mixed", rm)
+    assert rm["status"] == V.VMG_OK and rm["rms"] <= w["tol"]
+    assert 0.05 * delta.size < rm["n_guarded"] < 0.15 * delta.size
+    phi_d, rd = _solve(torch, V, d_t, w, V.FP64, 200)
+    say("  fp64", rd)
+    assert rd["status"] == V.VMG_OK and rd["rms"] <= w["tol"]
+    pm = phi_m.cpu().numpy()
+    pd = phi_d.cpu().numpy()
+    del phi_m, phi_d
+    # two solutions of a system that is not unique at its kink cells: they may
+    # differ near a few cells, but the difference stays local and mean-free
+    diff = np.abs(pm - pd)
+    smooth = 0.1 * (rm["rms"] + rd["rms"])   # what the residuals allow a unique solution
+    far = int((diff > 10 * smooth).sum())
+    say("  max |phi_mixed - phi_fp64| = %.3e (|phi|_inf %.3e); %d cells beyond %.1e" % (
+        diff.max(), np.abs(pd).max(), far, 10 * smooth))
+    assert far <= 1e-5 * delta.size
+    assert diff.max() <= 1e-3 * np.abs(pd).max()
+    del diff
+    _check_solution(torch, V, oracle_mod, delta, d_t, pd, w, rd, "FP64")
+    del pd
+    _check_solution(torch, V, oracle_mod, delta, d_t, pm, w, rm, "mixed")
