@@ -152,6 +152,17 @@ __device__ __forceinline__ double kink_relax(double old, double nv, double D, fl
     return nv;
 }
 
+// kink_relax with the old value read from LDS inside the rare branch
+__device__ __forceinline__ double kink_relax_at(const double* pold, double nv, double D, float kk) {
+    const float aD = (float)fabs(D);
+    if (__builtin_expect(aD * (kk * kk) < 1.0f, 0)) {
+        const double old = *(const volatile double*)pold;
+        const float w = fmaxf(kk * __builtin_amdgcn_sqrtf(aD), KINK_WMIN);
+        return fma((double)fminf(w, 1.0f), nv - old, old);
+    }
+    return nv;
+}
+
 __device__ __forceinline__ float kink_relax(float old, float nv, float D, float kk) {
     const float aD = fabsf(D);
     if (__builtin_expect(aD * (kk * kk) < 1.0f, 0)) {

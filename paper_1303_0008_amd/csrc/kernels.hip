@@ -111,12 +111,16 @@ struct SmoothK {
         const double base = HAS_F ? fma(-h2_6, s.f, cb_6) : cb_6;
         return kink_relax(centre, fma(S, 1.0 / 6.0, fma(-h2_6, Q, base)), D, kk);
     }
+    // the march reads the centre from LDS only for a kink cell (kink_relax_at)
     template <int W>
     __device__ double update(const double* Pm, const double* Pc, const double* Pp, int co, int o,
                              const Src& s) const {
         Nb v;
         nb_split<W>(Pm, Pc, Pp, co, o, v);
-        return update_nb(v, Pc[o], s);
+        double S, D;
+        const double Q = nl_root_d(v, s.dl, c, inv_h4, S, D);
+        const double base = HAS_F ? fma(-h2_6, s.f, cb_6) : cb_6;
+        return kink_relax_at(Pc + o, fma(S, 1.0 / 6.0, fma(-h2_6, Q, base)), D, kk);
     }
     // element access of the multi-sweep brick (brick_sweeps)
     __device__ double load_cell(int64_t i) const { return pin[i]; }

@@ -108,6 +108,7 @@ struct CorrK {
         return buf_ld_f32(C.u, bo) - buf_ld_f32(C.o, bo);
     }
     __device__ float2 add_corr(float2 u, float v) const { return make_float2(u.x + v, u.y); }
+    // (the centre's phi~ travels with the red-updated cell: the black phase reads it)
     template <int W>
     __device__ float2 update(const float2* Pm, const float2* Pc, const float2* Pp, int co, int o,
                              const Src& s) const {
@@ -125,6 +126,12 @@ struct CorrK {
         eout[gi] = gref[gi] + (float)s * (v.x - gref[ii]);
     }
     __device__ float2 update_nb(const NbT<float2>& v, float2 centre, const Src& s) const {
+        float e, D1;
+        corr_new(v, s, e, D1);
+        return make_float2(kink_relax(centre.x, e, D1, kk), centre.y);
+    }
+    // the plain update of e and the discriminant D1 of the corrected state
+    __device__ void corr_new(const NbT<float2>& v, const Src& s, float& e, float& D1) const {
         NbT<float> ve, vp;
 #define VMG_SPLIT(m) ve.m = v.m.x; vp.m = v.m.y;
         VMG_SPLIT(xm) VMG_SPLIT(xp) VMG_SPLIT(ym) VMG_SPLIT(yp) VMG_SPLIT(zm) VMG_SPLIT(zp)
@@ -132,12 +139,11 @@ struct CorrK {
         VMG_SPLIT(xpzp) VMG_SPLIT(xmzm) VMG_SPLIT(xpzm) VMG_SPLIT(xmzp)
         VMG_SPLIT(ypzp) VMG_SPLIT(ymzm) VMG_SPLIT(ypzm) VMG_SPLIT(ymzp)
 #undef VMG_SPLIT
-        float Se, D1;
+        float Se;
         const float dq = dq_corr(ve, vp, c.a_ih4, Se);
         const float dQ = dQ_of_d(dq, s.t0, c, D1);
-        // (Se - h^2 (dQ + r - cbar)) / 6, under-relaxed at kink cells
-        return make_float2(kink_relax(centre.x, fmaf(Se, 1.0f / 6.0f, fmaf(-h2_6, dQ, fmaf(-h2_6, s.r, cb_6))), D1, kk),
-                           centre.y);
+        // (Se - h^2 (dQ + r - cbar)) / 6
+        e = fmaf(Se, 1.0f / 6.0f, fmaf(-h2_6, dQ, fmaf(-h2_6, s.r, cb_6)));
     }
 };
 
