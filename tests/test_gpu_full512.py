@@ -136,3 +136,23 @@ def test_lognormal512b_guarded_converges(torch_cuda, V, oracle_mod):
     _check_solution(torch, V, oracle_mod, delta, d_t, pd, w, rd, "FP64")
     del pd
     _check_solution(torch, V, oracle_mod, delta, d_t, pm, w, rm, "mixed")
+
+
+def test_lognormal256b_guarded_converges(torch_cuda, V, oracle_mod):
+    """The alpha = -0.2 recipe at 256^3 (max delta ~800, 9 % of the cells
+    guarded), which also stalled with the plain update (4e-6): both precisions
+    reach the tolerance through the kink weight, and each returned phi solves
+    the oracle's discrete equations cell by cell."""
+    torch = torch_cuda
+    w = dict(I.WORKLOADS["lognormal512b"], n=256)
+    say("lognormal256b: generate")
+    delta = I.workload_delta("lognormal512b", n=256)
+    d_t = torch.from_numpy(delta).to("cuda")
+    for prec, label in ((V.FP64, "FP64"), (V.MIXED, "mixed")):
+        phi, r = _solve(torch, V, d_t, w, prec, 120)
+        say(f"  {label}", r)
+        assert r["status"] == V.VMG_OK and r["rms"] <= w["tol"]
+        assert 0.05 * delta.size < r["n_guarded"] < 0.15 * delta.size
+        ph = phi.cpu().numpy()
+        del phi
+        _check_solution(torch, V, oracle_mod, delta, d_t, ph, w, r, label)

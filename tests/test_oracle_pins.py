@@ -911,3 +911,41 @@ def test_mass_assign_cic_matches_the_input_recipe_deposit(oracle_mod):
         rho = I.cic_deposit(shape, pos[:, 0], pos[:, 1], pos[:, 2])
         d = oracle_mod.mass_assign(pos, shape, "cic")
         assert np.abs((d + 1.0) - rho).max() <= 1e-12 * max(1.0, rho.max())
+
+
+# ---------------------------------------------------------------------------
+# kink cells: the relaxation under-relaxes a cell next to the guard boundary
+# ---------------------------------------------------------------------------
+KINK_K = 50.0 * 256 ** 2     # weight min(1, max(0.01, K h^2 sqrt|D|))
+
+
+@pytest.mark.parametrize("target", [1e-9, -1e-9, 2.5e-11, 1e-6])
+def test_kink_cell_update_is_under_relaxed(oracle_mod, target):
+    """The first cell of a lexicographic sweep is updated from the initial state,
+    so its change is the plain Newton-Gauss-Seidel step -d/(dL/dphi) of
+    Sec. III.B times the kink weight.  The cell's density is chosen so that its
+    normalised discriminant D = 1 + (8/3) alpha^2 Sigma_ijk (Eq. one_branch,
+    w = 1/3) equals the target; the weight is then 0.405 (|D| = 1e-9), the floor
+    0.01 (2.5e-11) or 1 (1e-6) on a 16^3 grid."""
+    n, alpha, kappa = 16, -0.2, 1.5
+    h = 1.0 / n
+    rng = np.random.Generator(np.random.PCG64(5))
+    phi = 1e-3 * rng.standard_normal((n, n, n))
+    delta = I.lognormal(n, 7, sigma=0.5)
+    delta[0, 0, 0] = 0.0
+    s_geo = oracle_mod.cell_operator(delta, phi, alpha, kappa, (0, 0, 0))[2]
+    # Sigma_ijk = s_geo + (kappa / alpha) delta at the cell
+    delta[0, 0, 0] = ((target - 1.0) * 3.0 / (8.0 * alpha ** 2) - s_geo) * alpha / kappa
+    L, dL, sig, root = oracle_mod.cell_operator(delta, phi, alpha, kappa, (0, 0, 0))
+    D = 1.0 + 8.0 / 3.0 * alpha ** 2 * sig
+    assert abs(D - target) <= 1e-12
+    _, info = oracle_mod.residual(delta, phi, alpha, kappa, want_field=False)
+    plain = -(L + info["cbar"]) / dL
+    w = min(1.0, max(0.01, KINK_K * h * h * np.sqrt(abs(D))))
+    new = oracle_mod.relax(delta, phi, alpha, kappa, 1)
+    step = new[0, 0, 0] - phi[0, 0, 0]
+    assert abs(step - w * plain) <= 1e-6 * abs(plain) + 1e-18
+    if abs(target) < 1e-8:
+        assert w < 0.5 and abs(step) < 0.5 * abs(plain)
+    else:
+        assert w == 1.0
