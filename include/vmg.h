@@ -35,6 +35,10 @@
  * nonlinear Gauss-Seidel sweeps, residual with 8-child-average restriction,
  * coarse right-hand side f^H = L^H(R phi^h) - R d^h, cell-centred trilinear
  * prolongation of phi^H - R phi^h, direct relaxation on the coarsest level.
+ * A cell whose D lies next to the guard boundary has its update scaled by
+ * min(1, max(0.01, 50 (256 h)^2 sqrt|D|)) (the root's slope 1/sqrt(D) would
+ * otherwise make its update oscillate across D = 0); elsewhere the update is
+ * the plain one, and a converged phi is the same either way.
  *
  * Memory conventions.  Every array pointer is a DEVICE pointer (hipMalloc /
  * torch.cuda memory) to FP64 data, x fastest: cell (i,j,k) of a grid is
